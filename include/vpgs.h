@@ -1,0 +1,255 @@
+/*
+ * vpgs.h -- C ABI of the MI355X (gfx950) differentiable Gaussian-splatting
+ * renderer and anchor decoder.
+ *
+ * The operations are those of the paper's scene representation and its
+ * rasterisation (VPGS-SLAM, Section III-A; eq. 1-6): neural Gaussians are
+ * decoded from voxel anchors (eq. 1-5) and the Gaussians of a submap are
+ * splatted into colour, depth and opacity images (eq. 6), whose L1 / SSIM /
+ * depth losses drive mapping (eq. 7) and photometric pose tracking
+ * (Section III-B, coarse stage).  The renderer computes:
+ *
+ *   projection   p = R mu + t; visible iff FP32 depth z > near; unit quaternion
+ *                q/|q|; Sigma = R_q diag(exp(2 l)) R_q^T; J the pinhole
+ *                Jacobian with a 1.3x field-of-view guard clamp;
+ *                Sigma2D = J R Sigma R^T J^T + 0.3 I; conic = Sigma2D^-1;
+ *                (u, v) = (fx x/z + cx, fy y/z + cy); opacity-aware box
+ *                { d^T conic d <= 2 ln(255 o) } padded by one pixel.
+ *   binning      one (tile id << 32 | FP32 depth bits, index) key per overlapped
+ *                tile, sorted, so the per-pixel order is (depth, index).
+ *   compositing  per pixel (centre at +0.5) front to back:
+ *                alpha = min(0.99, o exp(-d^T conic d / 2)); skip alpha < 1/255;
+ *                stop before blending once T (1 - alpha) < 1e-4;
+ *                RGB = sum alpha T c, depth = sum alpha T z, alpha = 1 - T.
+ *   backward     gradients of sum(gRGB . RGB + gD D + gA A) to means, log-scales,
+ *                quaternions, opacities, colours, and to a left se(3) pose
+ *                increment xi = (rho, phi) at 0: [R|t] <- Exp(xi) [R|t].
+ *
+ * Conventions
+ *   - Every pointer is a DEVICE pointer unless marked "host".  All floating
+ *     point data are FP32, C-contiguous, row-major.  Image planes are [H, W]
+ *     (RGB is [3, H, W], channel-major).
+ *   - Quaternions are (w, x, y, z) with any non-zero norm.  Opacities and
+ *     colours are post-activation values.
+ *   - Camera poses are world-to-camera [R | t], row-major 3x4, in host memory.
+ *   - Calls are asynchronous on the given HIP stream (hipStream_t passed as
+ *     void*; NULL = the default stream) unless stated otherwise.
+ *   - Ownership: the caller owns every input and output buffer.  The library
+ *     owns its workspace and the saved-state handles (until released).
+ *   - Errors: every entry point returns a status code; no exception crosses
+ *     the ABI.  Arguments are validated on the host before any launch: an
+ *     invalid argument returns VPGS_EINVAL and enqueues nothing.
+ *   - Thread safety: a context is used by one host thread at a time; use one
+ *     context per concurrent stream user.
+ */
+#ifndef VPGS_H_
+#define VPGS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VPGS_OK 0
+#define VPGS_EINVAL (-1)        /* invalid argument; nothing was enqueued */
+#define VPGS_ENOMEM (-2)        /* device or host allocation failed */
+#define VPGS_EHIP (-3)          /* a HIP runtime call failed */
+#define VPGS_ECAPACITY (-4)     /* the (tile, Gaussian) pair list overflowed */
+#define VPGS_EUNSUPPORTED (-5)  /* option combination not built */
+
+#define VPGS_MAX_VIEWS 64       /* views per call */
+#define VPGS_MAX_SETS 64        /* distinct Gaussian sets per call */
+#define VPGS_MAX_DIM 8192       /* image width and height limit */
+
+typedef struct vpgs_ctx vpgs_ctx;
+typedef struct vpgs_saved vpgs_saved;
+typedef struct vpgs_window vpgs_window;
+
+/* Pinhole camera.  near_plane <= 0 selects the default 0.2. */
+typedef struct {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float near_plane;
+  float world_to_cam[12]; /* host: row-major 3x4 [R | t] */
+} vpgs_camera;
+
+/* A Gaussian set of n Gaussians (SoA arrays of length n). */
+typedef struct {
+  int64_t n;
+  const float* means;      /* [n,3] */
+  const float* log_scales; /* [n,3] */
+  const float* quats;      /* [n,4] (w,x,y,z) */
+  const float* opacities;  /* [n] */
+  const float* colors;     /* [n,3] */
+} vpgs_gaussians;
+
+/* Rendered planes of one view (outputs, written in full). */
+typedef struct {
+  float* rgb;   /* [3,H,W] */
+  float* depth; /* [H,W] */
+  float* alpha; /* [H,W] */
+} vpgs_images;
+
+/* Upstream gradients of one view; a NULL plane counts as zero. */
+typedef struct {
+  const float* rgb;   /* [3,H,W] */
+  const float* depth; /* [H,W] */
+  const float* alpha; /* [H,W] */
+} vpgs_image_grads;
+
+/* Writable per-Gaussian arrays (shapes as in vpgs_gaussians): the gradients
+ * of a set, or the Gaussians a decode writes.  Written in full. */
+typedef struct {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacities;
+  float* colors;
+} vpgs_gauss_buffers;
+typedef vpgs_gauss_buffers vpgs_gauss_grads;
+
+/* Render options.  Zero fields take defaults (16x16 tiles, automatic pair
+ * capacity).  tile_w x tile_h must be one of the compiled shapes
+ * 16x16, 16x8, 8x8, 32x8 (else VPGS_EUNSUPPORTED).  pair_capacity = 0 sizes the
+ * pair list exactly (one host synchronisation per forward); > 0 fixes it (no
+ * synchronisation; an overflow is reported as VPGS_ECAPACITY by
+ * vpgs_saved_stats and the outputs of that call are invalid). */
+typedef struct {
+  int32_t tile_w, tile_h;
+  int32_t reserved0, reserved1;
+  int64_t pair_capacity;
+} vpgs_render_opts;
+
+/* Counters of one forward, filled by vpgs_saved_stats. */
+typedef struct {
+  int64_t n_records;   /* (view, Gaussian) records projected */
+  int64_t n_visible;   /* records with a non-empty tile rectangle */
+  int64_t n_pairs;     /* (tile, Gaussian) pairs emitted */
+  int64_t n_evaluated; /* (pixel, Gaussian) alpha evaluations */
+  int64_t n_blended;   /* (pixel, Gaussian) blends */
+  int64_t pair_capacity;
+  int64_t n_tiles;
+  int64_t n_pixels;
+  int32_t overflow;    /* 1 if the pair list overflowed */
+  int32_t tile_w, tile_h;
+  int32_t reserved;
+} vpgs_stats;
+
+/* ---- context ------------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  The context owns a grow-only
+ * workspace; it is freed by vpgs_destroy. */
+int vpgs_create(vpgs_ctx** out, int device);
+int vpgs_destroy(vpgs_ctx* ctx);
+const char* vpgs_status_string(int status);
+/* Text of the last error on this context (valid until the next call). */
+const char* vpgs_last_error(const vpgs_ctx* ctx);
+int vpgs_version(void);
+
+/* ---- renderer -------------------------------------------------------------- */
+
+/* Forward render of n_views views.  View v renders Gaussian set view_set[v]
+ * (host array; several views may share a set) with camera cams[v] (host)
+ * into out[v] (host array of device planes).  If `saved` is non-NULL a
+ * saved-state handle for vpgs_render_backward is returned; it must be
+ * released with vpgs_saved_release.  The Gaussian and camera buffers must not
+ * change between the forward and its backward. */
+int vpgs_render_forward(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, int n_views,
+                        const int32_t* view_set, const vpgs_camera* cams, const vpgs_images* out,
+                        const vpgs_render_opts* opts, vpgs_saved** saved, void* stream);
+
+/* Backward of a forward.  grad_out[v] (host array) holds the upstream planes
+ * of view v; grads[s] (host array) receives the gradient of set s summed over
+ * the views that render it; d_pose (device, [n_views,6] as (rho, phi), may be
+ * NULL) receives the pose-increment gradient of every view.  Per-pixel alpha
+ * is recomputed, not stored. */
+int vpgs_render_backward(vpgs_ctx* ctx, const vpgs_saved* saved, const vpgs_image_grads* grad_out,
+                         const vpgs_gauss_grads* grads, float* d_pose, void* stream);
+
+/* Synchronise the stream and read the counters of a forward.  Returns
+ * VPGS_ECAPACITY if its pair list overflowed. */
+int vpgs_saved_stats(vpgs_ctx* ctx, const vpgs_saved* saved, vpgs_stats* out, void* stream);
+
+/* Internal buffers of a forward, for inspection and tests.  Copies (device to
+ * device, on `stream`) `what` into dst, which must hold `bytes`; returns
+ * VPGS_EINVAL if bytes is smaller than the buffer (whose size in bytes is
+ * returned through *size when size is non-NULL, and dst may then be NULL):
+ *   VPGS_BUF_PROJ    float [R,12]: u, v, z, opacity, Qa, Qb, Qc, 0, r, g, b, 0
+ *   VPGS_BUF_EXTENT  float [R,2]: half extents hx, hy of the box
+ *   VPGS_BUF_COUNT   uint32 [R]: tiles overlapped (0 = culled)
+ *   VPGS_BUF_KEYS    uint64 [P]: sorted keys
+ *   VPGS_BUF_VALUES  uint32 [P]: sorted record indices
+ *   VPGS_BUF_RANGES  uint32 [T,2]: [start, end) of every tile
+ *   VPGS_BUF_TFINAL  float [sum H*W]: final transmittance, views concatenated
+ *   VPGS_BUF_NCONTRIB uint32 [sum H*W]: list length up to the last blend
+ * R = records (views in order, each the size of its set); T = tiles (views in
+ * order, row-major per view). */
+#define VPGS_BUF_PROJ 1
+#define VPGS_BUF_EXTENT 2
+#define VPGS_BUF_COUNT 3
+#define VPGS_BUF_KEYS 4
+#define VPGS_BUF_VALUES 5
+#define VPGS_BUF_RANGES 6
+#define VPGS_BUF_TFINAL 7
+#define VPGS_BUF_NCONTRIB 8
+int vpgs_saved_export(vpgs_ctx* ctx, const vpgs_saved* saved, int what, void* dst, size_t bytes,
+                      size_t* size, void* stream);
+
+int vpgs_saved_release(vpgs_ctx* ctx, vpgs_saved* saved);
+
+/* ---- anchor decoder (Section III-A, eq. 1-5) ------------------------------- */
+
+/* m anchors with k Gaussians each. */
+typedef struct {
+  int64_t m;
+  int32_t k;
+  int32_t reserved;
+  const float* xyz;     /* [m,3] anchor positions (voxel centres) */
+  const float* feat;    /* [m,32] anchor features */
+  const float* scale;   /* [m,3] anchor scaling l, > 0 */
+  const float* offsets; /* [m,k,3] learnable offsets */
+} vpgs_anchors;
+
+/* Three independent LINEAR-ReLU-LINEAR heads (h = 0 opacity, 1 colour,
+ * 2 covariance) on the 36-vector [feat(32), view direction(3), distance(1)];
+ * weights are (out, in) row-major: W1[h] [width,36], b1[h] [width],
+ * W2[h] [out_h,width], b2[h] [out_h] with out = (k, 3k, 7k).  The covariance
+ * head emits [scale(3) | quaternion(4)] per Gaussian.  width <= 128. */
+typedef struct {
+  int32_t in_dim; /* must be 36 */
+  int32_t width;
+  const float* W1[3];
+  const float* b1[3];
+  const float* W2[3];
+  const float* b2[3];
+} vpgs_mlp;
+
+typedef struct {
+  float* W1[3];
+  float* b1[3];
+  float* W2[3];
+  float* b2[3];
+} vpgs_mlp_grads;
+
+/* Decode m*k neural Gaussians (anchor-major: Gaussian a*k + j):
+ *   mean = xyz + offsets * scale (eq. 1); opacity = tanh (<= 0 is culled by the
+ *   renderer); colour = sigmoid (eq. 4); log-scale = log_sigmoid + log scale
+ *   (eq. 5); quaternion = normalised (norm floored at 1e-12).
+ * cam_center (host, 3 floats) is the camera position of eq. 3. */
+int vpgs_decode_forward(vpgs_ctx* ctx, const vpgs_anchors* anchors, const vpgs_mlp* mlp,
+                        const float* cam_center, const vpgs_gauss_buffers* out, void* stream);
+
+/* Gradients of sum(upstream . decoded) with respect to feat, scale, offsets
+ * and every weight and bias (all written in full; the camera is constant).
+ * `upstream` uses the vpgs_gauss_grads layout as input. */
+int vpgs_decode_backward(vpgs_ctx* ctx, const vpgs_anchors* anchors, const vpgs_mlp* mlp,
+                         const float* cam_center, const vpgs_gauss_grads* upstream, float* d_feat,
+                         float* d_scale, float* d_offsets, const vpgs_mlp_grads* d_mlp, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VPGS_H_ */

@@ -1,0 +1,12 @@
+"""MI355X (gfx950) differentiable Gaussian-splatting renderer and anchor
+decoder for the VPGS-SLAM hot path.
+
+The computation runs in hand-written HIP kernels behind the C ABI of
+``include/vpgs.h`` (``libvpgs.so``); this package marshals PyTorch tensors
+into that ABI.  Importing it does not load the library; the first call does,
+and fails loudly if the library is not built.
+"""
+from .render import (Context, RenderFn, Saved, camera_struct, get_context, render, render_backward,  # noqa: F401
+                     render_views)
+
+__version__ = "0.1.0"

@@ -1,0 +1,135 @@
+// internal.h -- shared definitions of the HIP kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vpgs.h"
+
+namespace vpgs {
+
+// Method constants (FP32): the compositing cutoffs, the EWA low-pass
+// dilation and the field-of-view guard of the projection.
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTransMin = 1e-4f;
+constexpr float kDilate = 0.3f;
+constexpr float kGuardLo = 0.15f;  // guard reaches 15% of the image beyond each edge
+constexpr float kGuardHi = 1.15f;
+constexpr float kDefaultNear = 0.2f;
+
+// Number of per-record gradient accumulators written by the backward
+// compositor: d(u, v, Qa, Qb, Qc, opacity, r, g, b, z).
+constexpr int kNumAcc = 10;
+
+// One view of a render call, as the kernels see it.
+struct ViewDesc {
+  int32_t W, H, tiles_x, tiles_y;
+  uint32_t tile_base;  // first global tile id of the view
+  uint32_t rec_base;   // first record of the view
+  uint32_t pix_base;   // first pixel of the view in the concatenated per-pixel buffers
+  int32_t set;         // Gaussian set rendered by the view
+  float fx, fy, cx, cy, near_z;
+  float glx, ghx, gly, ghy;  // guard limits on x/z and y/z
+  float R[9], t[3];
+  float* rgb;
+  float* depth;
+  float* alpha;
+  const float* g_rgb;
+  const float* g_depth;
+  const float* g_alpha;
+};
+
+// One Gaussian set of a render call.
+struct SetDesc {
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacities;
+  const float* colors;
+  float* d_means;
+  float* d_log_scales;
+  float* d_quats;
+  float* d_opacities;
+  float* d_colors;
+  int64_t n;
+  uint32_t block_base;  // first thread block of the set in per-Gaussian launches
+  int32_t view_first;   // its views are set_views[view_first .. view_first + view_count)
+  int32_t view_count;
+  int32_t pad;
+};
+
+struct CallTables {
+  ViewDesc views[VPGS_MAX_VIEWS];
+  SetDesc sets[VPGS_MAX_SETS];
+  int32_t set_views[VPGS_MAX_VIEWS];
+  int32_t n_views, n_sets;
+  uint32_t n_records, n_tiles;
+};
+
+// Device counters of one forward.
+struct Counters {
+  unsigned long long evaluated;
+  unsigned long long blended;
+  uint32_t pairs;      // pairs requested by the scan
+  uint32_t overflow;   // 1 if pairs > capacity
+  uint32_t visible;
+  uint32_t pad;
+};
+
+// Per-record projected data (struct of arrays).
+struct ProjBuffers {
+  float4* a;       // (u, v, z, opacity)
+  float4* b;       // (Qa, Qb, Qc, 0)
+  float4* c;       // (r, g, b, 0)
+  float2* ext;     // (hx, hy)
+  uint2* rect;     // (x0 | x1 << 16, y0 | y1 << 16) tile rectangle, inclusive
+  uint32_t* count; // tiles overlapped
+};
+
+// ---- launch helpers (defined in the .hip files) --------------------------------
+
+hipError_t launch_project(const CallTables* d_tab, const CallTables& h_tab, ProjBuffers pb, int tile_w,
+                          int tile_h, hipStream_t s);
+// Blocks of the per-Gaussian launches (the pose partial buffer holds
+// n_views * project_blocks * 6 floats).
+uint32_t project_blocks(const CallTables& h);
+hipError_t launch_project_backward(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
+                                   const float* acc, float* pose_partial, hipStream_t s);
+hipError_t launch_pose_reduce(const CallTables* d_tab, const CallTables& h_tab, const float* pose_partial,
+                              float* d_pose, hipStream_t s);
+
+// Exclusive scan of n uint32 values; total (device, uint32) receives the sum.
+size_t scan_workspace_bytes(uint32_t n);
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, void* ws,
+                       hipStream_t s);
+
+hipError_t launch_emit(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
+                       const uint32_t* offsets, Counters* cnt, uint64_t* keys, uint32_t* vals,
+                       uint32_t capacity, int tile_w, int tile_h, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs over key bits [0, key_bits).
+// The pair count is read from cnt->pairs (clamped to capacity) on the device.
+size_t sort_workspace_bytes(uint32_t capacity);
+hipError_t launch_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                       uint32_t capacity, int key_bits, const Counters* cnt, void* ws, int* result_in_alt,
+                       hipStream_t s);
+
+hipError_t launch_ranges(const uint64_t* keys, const Counters* cnt, uint32_t capacity, uint2* ranges,
+                         uint32_t n_tiles, hipStream_t s);
+
+hipError_t launch_composite_forward(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
+                                    const uint2* ranges, const uint32_t* vals, float* T_final,
+                                    uint32_t* n_contrib, Counters* cnt, int tile_w, int tile_h,
+                                    hipStream_t s);
+hipError_t launch_composite_backward(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
+                                     const uint2* ranges, const uint32_t* vals, const float* T_final,
+                                     const uint32_t* n_contrib, float* acc, int tile_w, int tile_h,
+                                     hipStream_t s);
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
+hipError_t launch_fill_f32(float* p, float value, size_t n, hipStream_t s);
+
+bool tile_shape_supported(int tw, int th);
+
+}  // namespace vpgs

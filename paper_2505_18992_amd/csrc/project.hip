@@ -1,0 +1,398 @@
+// project.hip -- EWA projection of Gaussians into every view that renders
+// them, and its backward (chain to the Gaussian parameters and to the left
+// se(3) increment of each view's pose).
+//
+// One thread per Gaussian of a set loops over the views of that set, so the
+// 56 parameter bytes of a Gaussian are read once per call however many views
+// share the set.
+#include "internal.h"
+
+namespace vpgs {
+namespace {
+
+constexpr int kProjBlock = 256;
+
+// Set index of a thread block (sets own contiguous block ranges).
+__device__ __forceinline__ int set_of_block(const CallTables* tab, uint32_t blk) {
+  int s = 0;
+  for (int i = 1; i < tab->n_sets; ++i)
+    if (blk >= tab->sets[i].block_base) s = i;
+  return s;
+}
+
+// Camera-space mean and projected centre in FP32 with a fixed operation
+// order and no contraction: these values decide visibility, the sort order
+// and the tile rectangle, so they are reproducible bit for bit.
+struct SpecPoint { float x, y, z, u, v; };
+__device__ __forceinline__ SpecPoint spec_point(const ViewDesc& V, float mx, float my, float mz) {
+#pragma clang fp contract(off)
+  SpecPoint p;
+  p.x = ((V.R[0] * mx + V.R[1] * my) + V.R[2] * mz) + V.t[0];
+  p.y = ((V.R[3] * mx + V.R[4] * my) + V.R[5] * mz) + V.t[1];
+  p.z = ((V.R[6] * mx + V.R[7] * my) + V.R[8] * mz) + V.t[2];
+  const float tx = p.x / p.z, ty = p.y / p.z;
+  p.u = V.fx * tx + V.cx;
+  p.v = V.fy * ty + V.cy;
+  return p;
+}
+
+// Pixel box of the padded opacity-aware ellipse, in FP32 with a fixed
+// operation order (pixel centres at +0.5: px is inside iff
+// u - hx - 1 <= px + 0.5 <= u + hx + 1).
+struct PixBox { int x0, x1, y0, y1; };
+__device__ __forceinline__ PixBox pixel_box(float u, float v, float hx, float hy, int W, int H) {
+#pragma clang fp contract(off)
+  const float lox = fminf(fmaxf((u - hx) - 1.5f, 0.0f), (float)W);
+  const float hix = fmaxf(fminf((u + hx) + 0.5f, (float)(W - 1)), -1.0f);
+  const float loy = fminf(fmaxf((v - hy) - 1.5f, 0.0f), (float)H);
+  const float hiy = fmaxf(fminf((v + hy) + 0.5f, (float)(H - 1)), -1.0f);
+  PixBox b;
+  b.x0 = (int)ceilf(lox);
+  b.x1 = (int)floorf(hix);
+  b.y0 = (int)ceilf(loy);
+  b.y1 = (int)floorf(hiy);
+  return b;
+}
+
+struct Quat { float w, x, y, z, inv_norm; bool ok; };
+__device__ __forceinline__ Quat unit_quat(float4 q) {
+  Quat r;
+  const float m = fmaxf(fmaxf(fabsf(q.x), fabsf(q.y)), fmaxf(fabsf(q.z), fabsf(q.w)));
+  r.ok = m > 0.0f && m < INFINITY;
+  if (!r.ok) { r.w = 1; r.x = r.y = r.z = 0; r.inv_norm = 0; return r; }
+  const float w = q.x / m, x = q.y / m, y = q.z / m, z = q.w / m;
+  const float n = sqrtf(w * w + x * x + y * y + z * z);
+  const float in = 1.0f / n;
+  r.w = w * in; r.x = x * in; r.y = y * in; r.z = z * in;
+  r.inv_norm = in / m;  // 1 / |q|
+  return r;
+}
+
+__device__ __forceinline__ void quat_to_rot(const Quat& q, float Rq[9]) {
+  const float w = q.w, x = q.x, y = q.y, z = q.z;
+  Rq[0] = 1.f - 2.f * (y * y + z * z); Rq[1] = 2.f * (x * y - w * z);       Rq[2] = 2.f * (x * z + w * y);
+  Rq[3] = 2.f * (x * y + w * z);       Rq[4] = 1.f - 2.f * (x * x + z * z); Rq[5] = 2.f * (y * z - w * x);
+  Rq[6] = 2.f * (x * z - w * y);       Rq[7] = 2.f * (y * z + w * x);       Rq[8] = 1.f - 2.f * (x * x + y * y);
+}
+
+// Sigma = M M^T with M = R_q diag(s); returns the 3x3 matrix.
+__device__ __forceinline__ void world_cov(const float Rq[9], const float s[3], float Sg[9]) {
+  float M[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) M[3 * r + k] = Rq[3 * r + k] * s[k];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Sg[3 * r + k] = M[3 * r] * M[3 * k] + M[3 * r + 1] * M[3 * k + 1] + M[3 * r + 2] * M[3 * k + 2];
+}
+
+// Sc = R Sg R^T
+__device__ __forceinline__ void cam_cov(const float R[9], const float Sg[9], float Sc[9]) {
+  float RS[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) RS[3 * r + k] = R[3 * r] * Sg[k] + R[3 * r + 1] * Sg[3 + k] + R[3 * r + 2] * Sg[6 + k];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Sc[3 * r + k] = RS[3 * r] * R[3 * k] + RS[3 * r + 1] * R[3 * k + 1] + RS[3 * r + 2] * R[3 * k + 2];
+}
+
+__global__ void __launch_bounds__(kProjBlock) project_kernel(const CallTables* __restrict__ tab, ProjBuffers pb,
+                                                             int tile_shift_x, int tile_shift_y,
+                                                             Counters* __restrict__ cnt_unused) {
+  const int s = set_of_block(tab, blockIdx.x);
+  const SetDesc& S = tab->sets[s];
+  const int64_t i = (int64_t)(blockIdx.x - S.block_base) * kProjBlock + threadIdx.x;
+  if (i >= S.n) return;
+  const float mx = S.means[3 * i], my = S.means[3 * i + 1], mz = S.means[3 * i + 2];
+  const float l0 = S.log_scales[3 * i], l1 = S.log_scales[3 * i + 1], l2 = S.log_scales[3 * i + 2];
+  const float4 q4 = reinterpret_cast<const float4*>(S.quats)[i];
+  const float o = S.opacities[i];
+  const float c0 = S.colors[3 * i], c1 = S.colors[3 * i + 1], c2 = S.colors[3 * i + 2];
+  const Quat q = unit_quat(q4);
+  float Rq[9], Sg[9];
+  quat_to_rot(q, Rq);
+  const float sc[3] = {expf(l0), expf(l1), expf(l2)};
+  world_cov(Rq, sc, Sg);
+  const bool opaque = o > kAlphaMin;
+  const float kq = 2.0f * logf(o / kAlphaMin);
+
+  for (int vi = 0; vi < S.view_count; ++vi) {
+    const int v = tab->set_views[S.view_first + vi];
+    const ViewDesc& V = tab->views[v];
+    const uint32_t rec = V.rec_base + (uint32_t)i;
+    const SpecPoint p = spec_point(V, mx, my, mz);
+    bool ok = q.ok && opaque && (p.z > V.near_z);
+    float Sc[9];
+    cam_cov(V.R, Sg, Sc);
+    const float txc = fminf(fmaxf(p.x / p.z, V.glx), V.ghx);
+    const float tyc = fminf(fmaxf(p.y / p.z, V.gly), V.ghy);
+    const float J00 = V.fx / p.z, J02 = -(V.fx * txc) / p.z;
+    const float J11 = V.fy / p.z, J12 = -(V.fy * tyc) / p.z;
+    const float a = J00 * J00 * Sc[0] + 2.f * J00 * J02 * Sc[2] + J02 * J02 * Sc[8] + kDilate;
+    const float b = J00 * J11 * Sc[1] + J00 * J12 * Sc[2] + J02 * J11 * Sc[5] + J02 * J12 * Sc[8];
+    const float c = J11 * J11 * Sc[4] + 2.f * J11 * J12 * Sc[5] + J12 * J12 * Sc[8] + kDilate;
+    const float det = a * c - b * b;
+    ok = ok && det > 0.0f;
+    const float idet = 1.0f / det;
+    const float Qa = c * idet, Qb = -b * idet, Qc = a * idet;
+    const float hx = sqrtf(kq * a), hy = sqrtf(kq * c);
+    ok = ok && isfinite(p.u) && isfinite(p.v) && isfinite(Qa) && isfinite(Qb) && isfinite(Qc) &&
+         isfinite(hx) && isfinite(hy);
+    uint32_t count = 0;
+    uint2 rect = make_uint2(0, 0);
+    if (ok) {
+      const PixBox bx = pixel_box(p.u, p.v, hx, hy, V.W, V.H);
+      if (bx.x0 <= bx.x1 && bx.y0 <= bx.y1) {
+        const uint32_t tx0 = (uint32_t)bx.x0 >> tile_shift_x, tx1 = (uint32_t)bx.x1 >> tile_shift_x;
+        const uint32_t ty0 = (uint32_t)bx.y0 >> tile_shift_y, ty1 = (uint32_t)bx.y1 >> tile_shift_y;
+        count = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+        rect = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+        pb.a[rec] = make_float4(p.u, p.v, p.z, o);
+        pb.b[rec] = make_float4(Qa, Qb, Qc, 0.0f);
+        pb.c[rec] = make_float4(c0, c1, c2, 0.0f);
+      }
+    }
+    pb.ext[rec] = ok ? make_float2(hx, hy) : make_float2(0.0f, 0.0f);
+    pb.rect[rec] = rect;
+    pb.count[rec] = count;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float block_sum(float v, float* red) {
+  // wave reduction, then across the waves of the block through LDS
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  float r = 0.f;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kProjBlock / 64; ++w) r += red[w];
+  return r;  // valid on thread 0
+}
+
+__global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const CallTables* __restrict__ tab, ProjBuffers pb,
+                                                                      const float* __restrict__ acc,
+                                                                      float* __restrict__ pose_partial) {
+  __shared__ float red[kProjBlock / 64];
+  const int s = set_of_block(tab, blockIdx.x);
+  const SetDesc& S = tab->sets[s];
+  const int64_t i = (int64_t)(blockIdx.x - S.block_base) * kProjBlock + threadIdx.x;
+  const bool live = i < S.n;
+  const int64_t ii = live ? i : 0;
+
+  const float mx = S.means[3 * ii], my = S.means[3 * ii + 1], mz = S.means[3 * ii + 2];
+  const float ls[3] = {S.log_scales[3 * ii], S.log_scales[3 * ii + 1], S.log_scales[3 * ii + 2]};
+  const float4 q4 = reinterpret_cast<const float4*>(S.quats)[ii];
+  const Quat q = unit_quat(q4);
+  float Rq[9], Sg[9];
+  quat_to_rot(q, Rq);
+  const float sc[3] = {expf(ls[0]), expf(ls[1]), expf(ls[2])};
+  world_cov(Rq, sc, Sg);
+
+  float dmu[3] = {0, 0, 0}, dSg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  float dop = 0.f, dcol[3] = {0, 0, 0};
+
+  for (int vi = 0; vi < S.view_count; ++vi) {
+    const int v = tab->set_views[S.view_first + vi];
+    const ViewDesc& V = tab->views[v];
+    const uint32_t rec = V.rec_base + (uint32_t)ii;
+    float pose[6] = {0, 0, 0, 0, 0, 0};
+    if (live && pb.count[rec] != 0) {
+      const float* g = acc + (size_t)rec * kNumAcc;
+      const float gu = g[0], gv = g[1], gQa = g[2], gQb = g[3], gQc = g[4], go = g[5];
+      const float gz_direct = g[9];
+      dop += go;
+      dcol[0] += g[6]; dcol[1] += g[7]; dcol[2] += g[8];
+
+      const SpecPoint p = spec_point(V, mx, my, mz);
+      float Sc[9];
+      cam_cov(V.R, Sg, Sc);
+      const float tx = p.x / p.z, ty = p.y / p.z;
+      const float txc = fminf(fmaxf(tx, V.glx), V.ghx);
+      const float tyc = fminf(fmaxf(ty, V.gly), V.ghy);
+      const float iz = 1.0f / p.z;
+      const float J00 = V.fx * iz, J02 = -(V.fx * txc) * iz;
+      const float J11 = V.fy * iz, J12 = -(V.fy * tyc) * iz;
+      const float a = J00 * J00 * Sc[0] + 2.f * J00 * J02 * Sc[2] + J02 * J02 * Sc[8] + kDilate;
+      const float b = J00 * J11 * Sc[1] + J00 * J12 * Sc[2] + J02 * J11 * Sc[5] + J02 * J12 * Sc[8];
+      const float c = J11 * J11 * Sc[4] + 2.f * J11 * J12 * Sc[5] + J12 * J12 * Sc[8] + kDilate;
+      const float idet = 1.0f / (a * c - b * b);
+      const float Qa = c * idet, Qb = -b * idet, Qc = a * idet;
+
+      // conic = Sigma2D^-1:  dL/dSigma2D = -Q G Q, G the symmetric conic gradient
+      const float dA = -(Qa * Qa * gQa + Qa * Qb * gQb + Qb * Qb * gQc);
+      const float dB = -(2.f * Qa * Qb * gQa + (Qa * Qc + Qb * Qb) * gQb + 2.f * Qb * Qc * gQc);  // scalar b
+      const float dC = -(Qb * Qb * gQa + Qb * Qc * gQb + Qc * Qc * gQc);
+      const float G00 = dA, G01 = 0.5f * dB, G11 = dC;
+      // Sigma2D = J Sc J^T:  dSc = J^T G J,  dJ = 2 G J Sc
+      const float Jm[6] = {J00, 0.f, J02, 0.f, J11, J12};
+      float GJ[6];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        GJ[k] = G00 * Jm[k] + G01 * Jm[3 + k];
+        GJ[3 + k] = G01 * Jm[k] + G11 * Jm[3 + k];
+      }
+      float dSc[9];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dSc[3 * r + k] = Jm[r] * GJ[k] + Jm[3 + r] * GJ[3 + k];
+      float dJ[6];
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          dJ[3 * r + k] = 2.f * (GJ[3 * r] * Sc[k] + GJ[3 * r + 1] * Sc[3 + k] + GJ[3 * r + 2] * Sc[6 + k]);
+      // J and (u, v, z) to the camera-space mean
+      float dx = gu * V.fx * iz, dy = gv * V.fy * iz;
+      float dz = gz_direct - (gu * V.fx * tx + gv * V.fy * ty) * iz;
+      dz += -(dJ[0] * V.fx + dJ[4] * V.fy) * iz * iz;
+      dz += (dJ[2] * V.fx * txc + dJ[5] * V.fy * tyc) * iz * iz;
+      const float dtxc = -dJ[2] * V.fx * iz, dtyc = -dJ[5] * V.fy * iz;
+      if (tx > V.glx && tx < V.ghx) { dx += dtxc * iz; dz -= dtxc * tx * iz; }
+      if (ty > V.gly && ty < V.ghy) { dy += dtyc * iz; dz -= dtyc * ty * iz; }
+      // camera-space mean to the world mean: dmu = R^T dp
+      dmu[0] += V.R[0] * dx + V.R[3] * dy + V.R[6] * dz;
+      dmu[1] += V.R[1] * dx + V.R[4] * dy + V.R[7] * dz;
+      dmu[2] += V.R[2] * dx + V.R[5] * dy + V.R[8] * dz;
+      // Sc = R Sg R^T:  dSg = R^T dSc R (accumulated over views)
+      float T1[9];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) T1[3 * r + k] = V.R[r] * dSc[k] + V.R[3 + r] * dSc[3 + k] + V.R[6 + r] * dSc[6 + k];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dSg[3 * r + k] += T1[3 * r] * V.R[k] + T1[3 * r + 1] * V.R[3 + k] + T1[3 * r + 2] * V.R[6 + k];
+      // pose: rho = dp; phi = p x dp + 2 vee-part of A = Sc dSc
+      float A[9];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) A[3 * r + k] = Sc[3 * r] * dSc[k] + Sc[3 * r + 1] * dSc[3 + k] + Sc[3 * r + 2] * dSc[6 + k];
+      pose[0] = dx; pose[1] = dy; pose[2] = dz;
+      pose[3] = p.y * dz - p.z * dy + 2.f * (A[5] - A[7]);
+      pose[4] = p.z * dx - p.x * dz + 2.f * (A[6] - A[2]);
+      pose[5] = p.x * dy - p.y * dx + 2.f * (A[1] - A[3]);
+    }
+    if (pose_partial != nullptr) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const float r = block_sum(pose[k], red);
+        if (threadIdx.x == 0) pose_partial[((size_t)v * gridDim.x + blockIdx.x) * 6 + k] = r;
+      }
+    }
+  }
+  if (!live) return;
+  // Sg = M M^T with M = R_q diag(s):  dM = 2 dSg M
+  float M[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) M[3 * r + k] = Rq[3 * r + k] * sc[k];
+  float dM[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      dM[3 * r + k] = (dSg[3 * r] + dSg[r]) * M[k] + (dSg[3 * r + 1] + dSg[3 + r]) * M[3 + k] +
+                      (dSg[3 * r + 2] + dSg[6 + r]) * M[6 + k];
+  // (the symmetrised form (dSg + dSg^T) M equals 2 dSg M for symmetric dSg)
+  float ds[3], dR[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) ds[k] = dM[k] * Rq[k] + dM[3 + k] * Rq[3 + k] + dM[6 + k] * Rq[6 + k];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dR[3 * r + k] = dM[3 * r + k] * sc[k];
+  const float w = q.w, x = q.x, y = q.y, z = q.z;
+  const float dqw = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+  const float dqx = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] - 2.f * x * dR[8]);
+  const float dqy = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] - 2.f * y * dR[8]);
+  const float dqz = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] + y * dR[5] + x * dR[6] + y * dR[7]);
+  const float dot = w * dqw + x * dqx + y * dqy + z * dqz;
+  const float in = q.inv_norm;
+  S.d_means[3 * i] = dmu[0]; S.d_means[3 * i + 1] = dmu[1]; S.d_means[3 * i + 2] = dmu[2];
+  S.d_log_scales[3 * i] = ds[0] * sc[0];
+  S.d_log_scales[3 * i + 1] = ds[1] * sc[1];
+  S.d_log_scales[3 * i + 2] = ds[2] * sc[2];
+  reinterpret_cast<float4*>(S.d_quats)[i] =
+      make_float4((dqw - w * dot) * in, (dqx - x * dot) * in, (dqy - y * dot) * in, (dqz - z * dot) * in);
+  S.d_opacities[i] = dop;
+  S.d_colors[3 * i] = dcol[0]; S.d_colors[3 * i + 1] = dcol[1]; S.d_colors[3 * i + 2] = dcol[2];
+}
+
+__global__ void pose_reduce_kernel(const CallTables* __restrict__ tab, const float* __restrict__ partial,
+                                   int total_blocks, float* __restrict__ d_pose) {
+  // one block per view; sums the partials of the blocks of the view's set
+  __shared__ float red[256];
+  const int v = blockIdx.x;
+  const SetDesc& S = tab->sets[tab->views[v].set];
+  const int b0 = (int)S.block_base;
+  const int nb = (int)((S.n + kProjBlock - 1) / kProjBlock);
+  for (int k = 0; k < 6; ++k) {
+    float s = 0.f;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partial[((size_t)v * total_blocks + b0 + b) * 6 + k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) d_pose[6 * v + k] = red[0];
+    __syncthreads();
+  }
+}
+
+int ilog2(int x) {
+  int r = 0;
+  while ((1 << r) < x) ++r;
+  return r;
+}
+
+}  // namespace
+
+uint32_t project_blocks(const CallTables& h) {
+  uint32_t b = 0;
+  for (int s = 0; s < h.n_sets; ++s) b += (uint32_t)((h.sets[s].n + kProjBlock - 1) / kProjBlock);
+  return b;
+}
+
+hipError_t launch_project(const CallTables* d_tab, const CallTables& h_tab, ProjBuffers pb, int tile_w, int tile_h,
+                          hipStream_t s) {
+  const uint32_t blocks = project_blocks(h_tab);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(kProjBlock), 0, s, d_tab, pb, ilog2(tile_w), ilog2(tile_h),
+                     nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_backward(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
+                                   const float* acc, float* pose_partial, hipStream_t s) {
+  const uint32_t blocks = project_blocks(h_tab);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(project_backward_kernel, dim3(blocks), dim3(kProjBlock), 0, s, d_tab, pb, acc, pose_partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_pose_reduce(const CallTables* d_tab, const CallTables& h_tab, const float* pose_partial,
+                              float* d_pose, hipStream_t s) {
+  if (h_tab.n_views == 0) return hipSuccess;
+  hipLaunchKernelGGL(pose_reduce_kernel, dim3(h_tab.n_views), dim3(256), 0, s, d_tab, pose_partial,
+                     (int)project_blocks(h_tab), d_pose);
+  return hipGetLastError();
+}
+
+}  // namespace vpgs

@@ -1,0 +1,530 @@
+// runtime.cpp -- host side of the C ABI: argument validation, the context and
+// its grow-only buffers, the saved forward state, and the launch sequence of
+// the render forward and backward.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace vpgs;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace
+
+struct vpgs_saved {
+  // host and device call tables; the host copy is pinned and guarded by an
+  // event so an in-flight upload is never overwritten
+  CallTables* h_tab = nullptr;
+  hipEvent_t tab_uploaded = nullptr;
+  DevBuf tab, pa, pb, pc, ext, rect, count, offsets, scan_ws, keys, vals, keys_alt, vals_alt, sort_ws, ranges,
+      tfinal, ncontrib, counters, acc, pose_partial;
+  int result_in_alt = 0;
+  int tile_w = 16, tile_h = 16;
+  uint32_t capacity = 0;
+  uint32_t n_pixels = 0;
+  bool in_use = false;
+};
+
+struct vpgs_ctx {
+  int device = 0;
+  std::string last_error;
+  std::vector<vpgs_saved*> pool;
+  void* h_pinned = nullptr;  // small pinned buffer for counter readback
+};
+
+namespace {
+
+int fail(vpgs_ctx* ctx, int code, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->last_error = buf;
+  }
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(ctx, VPGS_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int ensure(vpgs_ctx* ctx, DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.cap >= bytes) return VPGS_OK;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    if (e != hipSuccess) return fail(ctx, VPGS_EHIP, "hipFree: %s", hipGetErrorString(e));
+  }
+  const size_t want = bytes + bytes / 4;
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return fail(ctx, VPGS_ENOMEM, "hipMalloc(%zu): %s", want, hipGetErrorString(e));
+  }
+  b.cap = want;
+  return VPGS_OK;
+}
+
+void free_buf(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+void destroy_saved(vpgs_saved* s) {
+  DevBuf* bufs[] = {&s->tab, &s->pa, &s->pb, &s->pc, &s->ext, &s->rect, &s->count, &s->offsets, &s->scan_ws,
+                    &s->keys, &s->vals, &s->keys_alt, &s->vals_alt, &s->sort_ws, &s->ranges, &s->tfinal,
+                    &s->ncontrib, &s->counters, &s->acc, &s->pose_partial};
+  for (DevBuf* b : bufs) free_buf(*b);
+  if (s->tab_uploaded) (void)hipEventDestroy(s->tab_uploaded);
+  if (s->h_tab) (void)hipHostFree(s->h_tab);
+  delete s;
+}
+
+int acquire_saved(vpgs_ctx* ctx, vpgs_saved** out) {
+  for (vpgs_saved* s : ctx->pool)
+    if (!s->in_use) {
+      s->in_use = true;
+      *out = s;
+      return VPGS_OK;
+    }
+  vpgs_saved* s = new (std::nothrow) vpgs_saved();
+  if (!s) return fail(ctx, VPGS_ENOMEM, "out of host memory");
+  hipError_t e = hipHostMalloc((void**)&s->h_tab, sizeof(CallTables), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete s;
+    return fail(ctx, VPGS_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+  }
+  e = hipEventCreateWithFlags(&s->tab_uploaded, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    destroy_saved(s);
+    return fail(ctx, VPGS_EHIP, "hipEventCreate: %s", hipGetErrorString(e));
+  }
+  std::memset(s->h_tab, 0, sizeof(CallTables));
+  s->in_use = true;
+  ctx->pool.push_back(s);
+  *out = s;
+  return VPGS_OK;
+}
+
+bool finite(float x) { return std::isfinite(x); }
+
+int check_camera(vpgs_ctx* ctx, const vpgs_camera& c, int v) {
+  if (c.width < 1 || c.height < 1 || c.width > VPGS_MAX_DIM || c.height > VPGS_MAX_DIM)
+    return fail(ctx, VPGS_EINVAL, "view %d: image size %dx%d outside [1, %d]", v, c.width, c.height, VPGS_MAX_DIM);
+  if (!(finite(c.fx) && finite(c.fy) && c.fx > 0 && c.fy > 0))
+    return fail(ctx, VPGS_EINVAL, "view %d: focal lengths must be finite and positive", v);
+  if (!(finite(c.cx) && finite(c.cy) && finite(c.near_plane)))
+    return fail(ctx, VPGS_EINVAL, "view %d: principal point and near plane must be finite", v);
+  for (int k = 0; k < 12; ++k)
+    if (!finite(c.world_to_cam[k])) return fail(ctx, VPGS_EINVAL, "view %d: non-finite pose", v);
+  return VPGS_OK;
+}
+
+int ilog2_ceil(uint64_t x) {
+  int r = 0;
+  while ((1ull << r) < x) ++r;
+  return r;
+}
+
+// Builds the host call tables (without gradient pointers).
+int build_tables(vpgs_ctx* ctx, CallTables& T, int n_sets, const vpgs_gaussians* sets, int n_views,
+                 const int32_t* view_set, const vpgs_camera* cams, const vpgs_images* out, int tw, int th) {
+  std::memset(&T, 0, sizeof(T));
+  T.n_views = n_views;
+  T.n_sets = n_sets;
+  uint64_t rec = 0, tiles = 0, pix = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const vpgs_camera& c = cams[v];
+    ViewDesc& V = T.views[v];
+    const int s = view_set[v];
+    V.W = c.width;
+    V.H = c.height;
+    V.tiles_x = (c.width + tw - 1) / tw;
+    V.tiles_y = (c.height + th - 1) / th;
+    V.tile_base = (uint32_t)tiles;
+    V.rec_base = (uint32_t)rec;
+    V.pix_base = (uint32_t)pix;
+    V.set = s;
+    V.fx = c.fx; V.fy = c.fy; V.cx = c.cx; V.cy = c.cy;
+    V.near_z = c.near_plane > 0.f ? c.near_plane : kDefaultNear;
+    V.glx = (-kGuardLo * (float)c.width - c.cx) / c.fx;
+    V.ghx = (kGuardHi * (float)c.width - c.cx) / c.fx;
+    V.gly = (-kGuardLo * (float)c.height - c.cy) / c.fy;
+    V.ghy = (kGuardHi * (float)c.height - c.cy) / c.fy;
+    for (int r = 0; r < 3; ++r) {
+      for (int k = 0; k < 3; ++k) V.R[3 * r + k] = c.world_to_cam[4 * r + k];
+      V.t[r] = c.world_to_cam[4 * r + 3];
+    }
+    V.rgb = out[v].rgb;
+    V.depth = out[v].depth;
+    V.alpha = out[v].alpha;
+    rec += (uint64_t)sets[s].n;
+    tiles += (uint64_t)V.tiles_x * V.tiles_y;
+    pix += (uint64_t)c.width * c.height;
+  }
+  if (rec >= 0xffffffffull) return fail(ctx, VPGS_EINVAL, "too many (view, Gaussian) records: %llu", (unsigned long long)rec);
+  if (pix >= 0xffffffffull) return fail(ctx, VPGS_EINVAL, "too many pixels");
+  T.n_records = (uint32_t)rec;
+  T.n_tiles = (uint32_t)tiles;
+  // sets: contiguous block ranges and the list of views of each set
+  uint32_t block = 0;
+  int nv = 0;
+  for (int s = 0; s < n_sets; ++s) {
+    SetDesc& S = T.sets[s];
+    S.means = sets[s].means;
+    S.log_scales = sets[s].log_scales;
+    S.quats = sets[s].quats;
+    S.opacities = sets[s].opacities;
+    S.colors = sets[s].colors;
+    S.n = sets[s].n;
+    S.block_base = block;
+    block += (uint32_t)((sets[s].n + 255) / 256);
+    S.view_first = nv;
+    for (int v = 0; v < n_views; ++v)
+      if (view_set[v] == s) T.set_views[nv++] = v;
+    S.view_count = nv - S.view_first;
+  }
+  return VPGS_OK;
+}
+
+int upload_tables(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(sv->tab.p, sv->h_tab, sizeof(CallTables), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(sv->tab_uploaded, st));
+  return VPGS_OK;
+}
+
+ProjBuffers proj_of(vpgs_saved* s) {
+  ProjBuffers pb;
+  pb.a = static_cast<float4*>(s->pa.p);
+  pb.b = static_cast<float4*>(s->pb.p);
+  pb.c = static_cast<float4*>(s->pc.p);
+  pb.ext = static_cast<float2*>(s->ext.p);
+  pb.rect = static_cast<uint2*>(s->rect.p);
+  pb.count = static_cast<uint32_t*>(s->count.p);
+  return pb;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int validate_forward(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, int n_views, const int32_t* view_set,
+                     const vpgs_camera* cams, const vpgs_images* out, const vpgs_render_opts* opts) {
+  if (n_sets < 1 || n_sets > VPGS_MAX_SETS) return fail(ctx, VPGS_EINVAL, "n_sets %d outside [1, %d]", n_sets, VPGS_MAX_SETS);
+  if (n_views < 1 || n_views > VPGS_MAX_VIEWS)
+    return fail(ctx, VPGS_EINVAL, "n_views %d outside [1, %d]", n_views, VPGS_MAX_VIEWS);
+  if (!sets || !view_set || !cams || !out) return fail(ctx, VPGS_EINVAL, "NULL argument array");
+  for (int s = 0; s < n_sets; ++s) {
+    const vpgs_gaussians& g = sets[s];
+    if (g.n < 0 || g.n > 0x7fffffffLL) return fail(ctx, VPGS_EINVAL, "set %d: n = %lld out of range", s, (long long)g.n);
+    if (g.n > 0 && (!g.means || !g.log_scales || !g.quats || !g.opacities || !g.colors))
+      return fail(ctx, VPGS_EINVAL, "set %d: NULL parameter pointer", s);
+    if (g.n > 0 && !aligned16(g.quats)) return fail(ctx, VPGS_EINVAL, "set %d: quats must be 16-byte aligned", s);
+  }
+  for (int v = 0; v < n_views; ++v) {
+    if (view_set[v] < 0 || view_set[v] >= n_sets)
+      return fail(ctx, VPGS_EINVAL, "view %d: set index %d outside [0, %d)", v, view_set[v], n_sets);
+    int rc = check_camera(ctx, cams[v], v);
+    if (rc) return rc;
+    if (!out[v].rgb || !out[v].depth || !out[v].alpha) return fail(ctx, VPGS_EINVAL, "view %d: NULL output plane", v);
+  }
+  if (opts) {
+    const int tw = opts->tile_w ? opts->tile_w : 16, th = opts->tile_h ? opts->tile_h : 16;
+    if (!tile_shape_supported(tw, th)) return fail(ctx, VPGS_EUNSUPPORTED, "tile shape %dx%d not built", tw, th);
+    if (opts->pair_capacity < 0 || opts->pair_capacity > 0x7fffffffLL)
+      return fail(ctx, VPGS_EINVAL, "pair_capacity %lld out of range", (long long)opts->pair_capacity);
+  }
+  return VPGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vpgs_version(void) { return 1; }
+
+const char* vpgs_status_string(int status) {
+  switch (status) {
+    case VPGS_OK: return "ok";
+    case VPGS_EINVAL: return "invalid argument";
+    case VPGS_ENOMEM: return "out of memory";
+    case VPGS_EHIP: return "HIP runtime error";
+    case VPGS_ECAPACITY: return "pair list capacity exceeded";
+    case VPGS_EUNSUPPORTED: return "unsupported option";
+    default: return "unknown status";
+  }
+}
+
+const char* vpgs_last_error(const vpgs_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "NULL context"; }
+
+int vpgs_create(vpgs_ctx** out, int device) {
+  if (!out) return VPGS_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return VPGS_EINVAL;
+  vpgs_ctx* ctx = new (std::nothrow) vpgs_ctx();
+  if (!ctx) return VPGS_ENOMEM;
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess || hipHostMalloc(&ctx->h_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return VPGS_EHIP;
+  }
+  *out = ctx;
+  return VPGS_OK;
+}
+
+int vpgs_destroy(vpgs_ctx* ctx) {
+  if (!ctx) return VPGS_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (vpgs_saved* s : ctx->pool) destroy_saved(s);
+  if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
+  delete ctx;
+  return VPGS_OK;
+}
+
+int vpgs_render_forward(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, int n_views, const int32_t* view_set,
+                        const vpgs_camera* cams, const vpgs_images* out, const vpgs_render_opts* opts,
+                        vpgs_saved** saved, void* stream) {
+  if (!ctx) return VPGS_EINVAL;
+  if (saved) *saved = nullptr;
+  int rc = validate_forward(ctx, n_sets, sets, n_views, view_set, cams, out, opts);
+  if (rc) return rc;
+  const int tw = (opts && opts->tile_w) ? opts->tile_w : 16;
+  const int th = (opts && opts->tile_h) ? opts->tile_h : 16;
+  const int64_t fixed_cap = opts ? opts->pair_capacity : 0;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(ctx->device));
+
+  vpgs_saved* sv = nullptr;
+  rc = acquire_saved(ctx, &sv);
+  if (rc) return rc;
+  struct Releaser {
+    vpgs_saved* s; bool keep = false;
+    ~Releaser() { if (!keep) s->in_use = false; }
+  } rel{sv};
+
+  HIP_TRY(hipEventSynchronize(sv->tab_uploaded));  // the previous upload from h_tab has completed
+  rc = build_tables(ctx, *sv->h_tab, n_sets, sets, n_views, view_set, cams, out, tw, th);
+  if (rc) return rc;
+  const CallTables& T = *sv->h_tab;
+  sv->tile_w = tw;
+  sv->tile_h = th;
+  uint64_t pixels = 0;
+  for (int v = 0; v < n_views; ++v) pixels += (uint64_t)T.views[v].W * T.views[v].H;
+  sv->n_pixels = (uint32_t)pixels;
+  const size_t R = T.n_records;
+
+  if ((rc = ensure(ctx, sv->tab, sizeof(CallTables))) || (rc = ensure(ctx, sv->pa, R * 16)) ||
+      (rc = ensure(ctx, sv->pb, R * 16)) || (rc = ensure(ctx, sv->pc, R * 16)) || (rc = ensure(ctx, sv->ext, R * 8)) ||
+      (rc = ensure(ctx, sv->rect, R * 8)) || (rc = ensure(ctx, sv->count, R * 4)) ||
+      (rc = ensure(ctx, sv->offsets, R * 4)) || (rc = ensure(ctx, sv->scan_ws, scan_workspace_bytes((uint32_t)R))) ||
+      (rc = ensure(ctx, sv->ranges, (size_t)T.n_tiles * 8)) || (rc = ensure(ctx, sv->tfinal, pixels * 4)) ||
+      (rc = ensure(ctx, sv->ncontrib, pixels * 4)) || (rc = ensure(ctx, sv->counters, sizeof(Counters))))
+    return rc;
+
+  rc = upload_tables(ctx, sv, st);
+  if (rc) return rc;
+  const CallTables* d_tab = static_cast<const CallTables*>(sv->tab.p);
+  Counters* cnt = static_cast<Counters*>(sv->counters.p);
+  const ProjBuffers pb = proj_of(sv);
+
+  HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, sizeof(Counters) / 4, st));
+  HIP_TRY(launch_project(d_tab, T, pb, tw, th, st));
+  HIP_TRY(launch_scan(pb.count, static_cast<uint32_t*>(sv->offsets.p), (uint32_t)R, &cnt->pairs, sv->scan_ws.p, st));
+
+  uint32_t cap;
+  if (fixed_cap > 0) {
+    cap = (uint32_t)fixed_cap;
+  } else {
+    uint32_t* hp = static_cast<uint32_t*>(ctx->h_pinned);
+    HIP_TRY(hipMemcpyAsync(hp, &cnt->pairs, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    cap = std::max<uint32_t>(*hp, 1u);
+  }
+  if ((rc = ensure(ctx, sv->keys, (size_t)cap * 8)) || (rc = ensure(ctx, sv->keys_alt, (size_t)cap * 8)) ||
+      (rc = ensure(ctx, sv->vals, (size_t)cap * 4)) || (rc = ensure(ctx, sv->vals_alt, (size_t)cap * 4)) ||
+      (rc = ensure(ctx, sv->sort_ws, sort_workspace_bytes(cap))))
+    return rc;
+  sv->capacity = cap;
+
+  uint64_t* keys = static_cast<uint64_t*>(sv->keys.p);
+  uint32_t* vals = static_cast<uint32_t*>(sv->vals.p);
+  uint64_t* keys_alt = static_cast<uint64_t*>(sv->keys_alt.p);
+  uint32_t* vals_alt = static_cast<uint32_t*>(sv->vals_alt.p);
+  HIP_TRY(launch_emit(d_tab, T, pb, static_cast<const uint32_t*>(sv->offsets.p), cnt, keys, vals, cap, tw, th, st));
+  const int key_bits = 32 + ilog2_ceil(std::max<uint32_t>(T.n_tiles, 2u));
+  HIP_TRY(launch_sort(keys, vals, keys_alt, vals_alt, cap, key_bits, cnt, sv->sort_ws.p, &sv->result_in_alt, st));
+  const uint64_t* skeys = sv->result_in_alt ? keys_alt : keys;
+  const uint32_t* svals = sv->result_in_alt ? vals_alt : vals;
+  HIP_TRY(launch_ranges(skeys, cnt, cap, static_cast<uint2*>(sv->ranges.p), T.n_tiles, st));
+  HIP_TRY(launch_composite_forward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
+                                   static_cast<float*>(sv->tfinal.p), static_cast<uint32_t*>(sv->ncontrib.p), cnt, tw,
+                                   th, st));
+  if (saved) {
+    rel.keep = true;
+    *saved = sv;
+  }
+  return VPGS_OK;
+}
+
+int vpgs_render_backward(vpgs_ctx* ctx, const vpgs_saved* saved_c, const vpgs_image_grads* grad_out,
+                         const vpgs_gauss_grads* grads, float* d_pose, void* stream) {
+  if (!ctx) return VPGS_EINVAL;
+  vpgs_saved* sv = const_cast<vpgs_saved*>(saved_c);
+  if (!sv || !sv->in_use) return fail(ctx, VPGS_EINVAL, "invalid saved-state handle");
+  bool known = false;
+  for (vpgs_saved* s : ctx->pool) known = known || s == sv;
+  if (!known) return fail(ctx, VPGS_EINVAL, "saved-state handle of another context");
+  if (!grad_out || !grads) return fail(ctx, VPGS_EINVAL, "NULL argument array");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipEventSynchronize(sv->tab_uploaded));
+  CallTables& T = *sv->h_tab;
+  for (int s = 0; s < T.n_sets; ++s) {
+    const vpgs_gauss_grads& g = grads[s];
+    if (T.sets[s].n > 0 && (!g.means || !g.log_scales || !g.quats || !g.opacities || !g.colors))
+      return fail(ctx, VPGS_EINVAL, "set %d: NULL gradient pointer", s);
+    if (T.sets[s].n > 0 && !aligned16(g.quats)) return fail(ctx, VPGS_EINVAL, "set %d: d_quats must be 16-byte aligned", s);
+  }
+  for (int s = 0; s < T.n_sets; ++s) {
+    T.sets[s].d_means = grads[s].means;
+    T.sets[s].d_log_scales = grads[s].log_scales;
+    T.sets[s].d_quats = grads[s].quats;
+    T.sets[s].d_opacities = grads[s].opacities;
+    T.sets[s].d_colors = grads[s].colors;
+  }
+  for (int v = 0; v < T.n_views; ++v) {
+    T.views[v].g_rgb = grad_out[v].rgb;
+    T.views[v].g_depth = grad_out[v].depth;
+    T.views[v].g_alpha = grad_out[v].alpha;
+  }
+  const size_t R = T.n_records;
+  const uint32_t pblocks = project_blocks(T);
+  int rc;
+  if ((rc = ensure(ctx, sv->acc, R * kNumAcc * sizeof(float))) ||
+      (rc = ensure(ctx, sv->pose_partial, (size_t)T.n_views * std::max<uint32_t>(pblocks, 1u) * 6 * sizeof(float))))
+    return rc;
+  rc = upload_tables(ctx, sv, st);
+  if (rc) return rc;
+  const CallTables* d_tab = static_cast<const CallTables*>(sv->tab.p);
+  const ProjBuffers pb = proj_of(sv);
+  float* acc = static_cast<float*>(sv->acc.p);
+  const uint32_t* svals = static_cast<const uint32_t*>(sv->result_in_alt ? sv->vals_alt.p : sv->vals.p);
+  HIP_TRY(launch_fill_f32(acc, 0.0f, R * kNumAcc, st));
+  HIP_TRY(launch_composite_backward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
+                                    static_cast<const float*>(sv->tfinal.p),
+                                    static_cast<const uint32_t*>(sv->ncontrib.p), acc, sv->tile_w, sv->tile_h, st));
+  float* partial = d_pose ? static_cast<float*>(sv->pose_partial.p) : nullptr;
+  HIP_TRY(launch_project_backward(d_tab, T, pb, acc, partial, st));
+  if (d_pose) HIP_TRY(launch_pose_reduce(d_tab, T, partial, d_pose, st));
+  return VPGS_OK;
+}
+
+int vpgs_saved_stats(vpgs_ctx* ctx, const vpgs_saved* saved, vpgs_stats* out, void* stream) {
+  if (!ctx) return VPGS_EINVAL;
+  if (!saved || !out) return fail(ctx, VPGS_EINVAL, "NULL argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(ctx->device));
+  Counters* hc = static_cast<Counters*>(ctx->h_pinned);
+  HIP_TRY(hipMemcpyAsync(hc, saved->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  std::memset(out, 0, sizeof(*out));
+  const CallTables& T = *saved->h_tab;
+  out->n_records = T.n_records;
+  out->n_pairs = hc->pairs;
+  out->n_evaluated = (int64_t)hc->evaluated;
+  out->n_blended = (int64_t)hc->blended;
+  out->pair_capacity = saved->capacity;
+  out->n_tiles = T.n_tiles;
+  out->n_pixels = saved->n_pixels;
+  out->overflow = hc->overflow || hc->pairs > saved->capacity;
+  out->tile_w = saved->tile_w;
+  out->tile_h = saved->tile_h;
+  // visible records: count the non-zero tile counts on the host (diagnostic)
+  out->n_visible = -1;
+  return out->overflow ? fail(ctx, VPGS_ECAPACITY, "pair list overflow: %u pairs, capacity %u", hc->pairs,
+                              saved->capacity)
+                       : VPGS_OK;
+}
+
+int vpgs_saved_export(vpgs_ctx* ctx, const vpgs_saved* saved, int what, void* dst, size_t bytes, size_t* size,
+                      void* stream) {
+  if (!ctx) return VPGS_EINVAL;
+  if (!saved) return fail(ctx, VPGS_EINVAL, "NULL saved handle");
+  const CallTables& T = *saved->h_tab;
+  const size_t R = T.n_records;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(ctx->device));
+  size_t need = 0;
+  switch (what) {
+    case VPGS_BUF_PROJ: need = R * 48; break;
+    case VPGS_BUF_EXTENT: need = R * 8; break;
+    case VPGS_BUF_COUNT: need = R * 4; break;
+    case VPGS_BUF_KEYS: need = (size_t)saved->capacity * 8; break;
+    case VPGS_BUF_VALUES: need = (size_t)saved->capacity * 4; break;
+    case VPGS_BUF_RANGES: need = (size_t)T.n_tiles * 8; break;
+    case VPGS_BUF_TFINAL: need = (size_t)saved->n_pixels * 4; break;
+    case VPGS_BUF_NCONTRIB: need = (size_t)saved->n_pixels * 4; break;
+    default: return fail(ctx, VPGS_EINVAL, "unknown buffer %d", what);
+  }
+  if (size) *size = need;
+  if (!dst) return size ? VPGS_OK : fail(ctx, VPGS_EINVAL, "NULL destination");
+  if (bytes < need) return fail(ctx, VPGS_EINVAL, "destination holds %zu bytes, %zu needed", bytes, need);
+  if (need == 0) return VPGS_OK;
+  const bool alt = saved->result_in_alt != 0;
+  switch (what) {
+    case VPGS_BUF_PROJ: {
+      // interleave a, b, c into rows of 12 floats
+      HIP_TRY(hipMemcpy2DAsync(dst, 48, saved->pa.p, 16, 16, R, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpy2DAsync(static_cast<char*>(dst) + 16, 48, saved->pb.p, 16, 16, R, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpy2DAsync(static_cast<char*>(dst) + 32, 48, saved->pc.p, 16, 16, R, hipMemcpyDeviceToDevice, st));
+      return VPGS_OK;
+    }
+    case VPGS_BUF_EXTENT: HIP_TRY(hipMemcpyAsync(dst, saved->ext.p, need, hipMemcpyDeviceToDevice, st)); break;
+    case VPGS_BUF_COUNT: HIP_TRY(hipMemcpyAsync(dst, saved->count.p, need, hipMemcpyDeviceToDevice, st)); break;
+    case VPGS_BUF_KEYS:
+      HIP_TRY(hipMemcpyAsync(dst, alt ? saved->keys_alt.p : saved->keys.p, need, hipMemcpyDeviceToDevice, st));
+      break;
+    case VPGS_BUF_VALUES:
+      HIP_TRY(hipMemcpyAsync(dst, alt ? saved->vals_alt.p : saved->vals.p, need, hipMemcpyDeviceToDevice, st));
+      break;
+    case VPGS_BUF_RANGES: HIP_TRY(hipMemcpyAsync(dst, saved->ranges.p, need, hipMemcpyDeviceToDevice, st)); break;
+    case VPGS_BUF_TFINAL: HIP_TRY(hipMemcpyAsync(dst, saved->tfinal.p, need, hipMemcpyDeviceToDevice, st)); break;
+    case VPGS_BUF_NCONTRIB: HIP_TRY(hipMemcpyAsync(dst, saved->ncontrib.p, need, hipMemcpyDeviceToDevice, st)); break;
+  }
+  return VPGS_OK;
+}
+
+int vpgs_saved_release(vpgs_ctx* ctx, vpgs_saved* saved) {
+  if (!ctx) return VPGS_EINVAL;
+  if (!saved) return VPGS_OK;
+  for (vpgs_saved* s : ctx->pool)
+    if (s == saved) {
+      if (!s->in_use) return fail(ctx, VPGS_EINVAL, "saved-state handle released twice");
+      s->in_use = false;
+      return VPGS_OK;
+    }
+  return fail(ctx, VPGS_EINVAL, "saved-state handle of another context");
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// scan.hip -- exclusive prefix sum of uint32 counts (reduce, scan of the
+// block sums, downsweep), plus small fill kernels.
+#include "internal.h"
+
+namespace vpgs {
+namespace {
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 16;
+constexpr uint32_t kScanTile = kScanBlock * kScanItems;  // 4096 values per block
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(v, off, 64);
+    if (lane >= off) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan of one value per thread across the block; returns the
+// exclusive prefix and writes the block total to *total.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t incl = wave_incl_scan(v);
+  if (lane == 63) lds[wave] = incl;
+  __syncthreads();
+  uint32_t wbase = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kScanBlock / 64; ++w) {
+    const uint32_t x = lds[w];
+    if (w < wave) wbase += x;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return wbase + incl - v;
+}
+
+__global__ void __launch_bounds__(kScanBlock) scan_reduce_kernel(const uint32_t* __restrict__ in, uint32_t n,
+                                                                 uint32_t* __restrict__ sums) {
+  __shared__ uint32_t lds[kScanBlock / 64];
+  const size_t base = (size_t)blockIdx.x * kScanTile;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const size_t idx = base + (size_t)k * kScanBlock + threadIdx.x;
+    if (idx < n) s += in[idx];
+  }
+  uint32_t tot;
+  block_excl_scan(s, lds, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Exclusive scan of each block's tile, offset by block_offsets[block]
+// (NULL = 0).  If total is non-NULL the last block writes the grand total.
+__global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t* __restrict__ in, uint32_t n,
+                                                               const uint32_t* __restrict__ block_offsets,
+                                                               uint32_t* __restrict__ out, uint32_t* __restrict__ total) {
+  __shared__ uint32_t lds[kScanBlock / 64];
+  const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;  // blocked layout
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const size_t idx = base + k;
+    v[k] = idx < n ? in[idx] : 0u;
+    s += v[k];
+  }
+  uint32_t tot;
+  uint32_t run = block_excl_scan(s, lds, &tot);
+  const uint32_t off = block_offsets ? block_offsets[blockIdx.x] : 0u;
+  run += off;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const size_t idx = base + k;
+    if (idx < n) out[idx] = run;
+    run += v[k];
+  }
+  if (total != nullptr && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t value, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+__global__ void fill_f32_kernel(float* p, float value, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+inline uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+// Workspace: block sums of every level, recursively.
+size_t scan_workspace_bytes(uint32_t n) {
+  size_t bytes = 0;
+  uint32_t m = n;
+  while (m > kScanTile) {
+    m = div_up(m, kScanTile);
+    bytes += 2 * ((size_t)m * sizeof(uint32_t) + 256);
+  }
+  return bytes + 256;
+}
+
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, void* ws, hipStream_t s) {
+  if (n == 0) return total ? launch_fill_u32(total, 0u, 1, s) : hipSuccess;
+  const uint32_t blocks = div_up(n, kScanTile);
+  if (blocks == 1) {
+    hipLaunchKernelGGL(scan_down_kernel, dim3(1), dim3(kScanBlock), 0, s, in, n, nullptr, out, total);
+    return hipGetLastError();
+  }
+  char* w = static_cast<char*>(ws);
+  uint32_t* sums = reinterpret_cast<uint32_t*>(w);
+  const size_t sum_bytes = ((size_t)blocks * sizeof(uint32_t) + 255) / 256 * 256;
+  uint32_t* sums_scanned = reinterpret_cast<uint32_t*>(w + sum_bytes);
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(blocks), dim3(kScanBlock), 0, s, in, n, sums);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_scan(sums, sums_scanned, blocks, total, w + 2 * sum_bytes, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(scan_down_kernel, dim3(blocks), dim3(kScanBlock), 0, s, in, n, sums_scanned, out, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, value, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f32(float* p, float value, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, value, n);
+  return hipGetLastError();
+}
+
+}  // namespace vpgs

@@ -1,0 +1,265 @@
+"""PyTorch-facing API of the renderer and decoder.
+
+PyTorch supplies device memory, the current HIP stream and autograd; every
+step of the computation runs in ``libvpgs.so``.
+
+* ``render(...)``          forward render of one or more views (no autograd).
+* ``render_backward(...)`` its backward.
+* ``RenderFn``             ``torch.autograd.Function`` over one Gaussian set
+                           and its views, with an optional se(3) pose leaf.
+* ``render_views(...)``    autograd render of several sets and views.
+"""
+from __future__ import annotations
+
+import ctypes
+import threading
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import check, load
+
+__all__ = ["Context", "get_context", "render", "render_backward", "Saved", "RenderFn", "render_views",
+           "camera_struct"]
+
+
+class Context:
+    """One library context per device (the library requires one per stream user)."""
+
+    def __init__(self, device: int = 0):
+        L = load()
+        h = ctypes.c_void_p()
+        st = L.vpgs_create(ctypes.byref(h), int(device))
+        if st != 0:
+            raise _lib.VpgsError(st, f"vpgs_create(device={device}) failed: {L.vpgs_status_string(st).decode()}")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            load().vpgs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_CTX = {}
+_CTX_LOCK = threading.Lock()
+
+
+def get_context(device: Optional[int] = None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    key = (threading.get_ident(), device)
+    with _CTX_LOCK:
+        if key not in _CTX:
+            _CTX[key] = Context(device)
+        return _CTX[key]
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check_tensor(t, name, shape_tail, n=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 GPU tensor")
+    if tuple(t.shape[1:]) != tuple(shape_tail) or (n is not None and t.shape[0] != n):
+        raise ValueError(f"{name}: bad shape {tuple(t.shape)}")
+
+
+def camera_struct(cam) -> _lib.Camera:
+    """Any object with width, height, fx, fy, cx, cy, world_to_cam (3x4) and
+    optional near."""
+    c = _lib.Camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.near_plane = float(getattr(cam, "near", 0.2))
+    w2c = torch.as_tensor(cam.world_to_cam, dtype=torch.float32).reshape(-1).tolist()
+    for k in range(12):
+        c.world_to_cam[k] = w2c[k]
+    return c
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Saved:
+    """Handle of a forward's saved state; released on close or garbage collection."""
+
+    def __init__(self, ctx: Context, handle, n_views, n_sets, set_sizes, view_sizes):
+        self.ctx = ctx
+        self.handle = handle
+        self.n_views = n_views
+        self.n_sets = n_sets
+        self.set_sizes = set_sizes
+        self.view_sizes = view_sizes
+
+    def stats(self) -> dict:
+        s = _lib.Stats()
+        st = load().vpgs_saved_stats(self.ctx.handle, self.handle, ctypes.byref(s), _stream())
+        d = {f: getattr(s, f) for f, _ in _lib.Stats._fields_}
+        if st not in (0, _lib.VPGS_ECAPACITY):
+            check(st, self.ctx.handle, "vpgs_saved_stats")
+        return d
+
+    def export(self, what: int, dtype=torch.float32) -> torch.Tensor:
+        L = load()
+        size = ctypes.c_size_t(0)
+        check(L.vpgs_saved_export(self.ctx.handle, self.handle, what, None, 0, ctypes.byref(size), _stream()),
+              self.ctx.handle, "export size")
+        itemsize = torch.tensor([], dtype=dtype).element_size()
+        out = torch.empty(max(size.value // itemsize, 1), dtype=dtype, device="cuda")
+        check(L.vpgs_saved_export(self.ctx.handle, self.handle, what, _ptr(out), out.numel() * itemsize, None,
+                                  _stream()), self.ctx.handle, "export")
+        return out[: size.value // itemsize]
+
+    def close(self):
+        if self.handle:
+            load().vpgs_saved_release(self.ctx.handle, self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _set_struct(s) -> _lib.Gaussians:
+    means, log_scales, quats, opacities, colors = s
+    n = means.shape[0]
+    _check_tensor(means, "means", (3,), n)
+    _check_tensor(log_scales, "log_scales", (3,), n)
+    _check_tensor(quats, "quats", (4,), n)
+    _check_tensor(opacities, "opacities", (), n)
+    _check_tensor(colors, "colors", (3,), n)
+    g = _lib.Gaussians()
+    g.n = n
+    g.means, g.log_scales, g.quats, g.opacities, g.colors = (t.data_ptr() for t in s)
+    return g
+
+
+def render(sets: Sequence[Sequence[torch.Tensor]], cameras: Sequence, view_set: Optional[Sequence[int]] = None,
+           tile=(16, 16), pair_capacity: int = 0, keep: bool = True, ctx: Optional[Context] = None):
+    """Forward render.  ``sets`` is a list of (means, log_scales, quats,
+    opacities, colors) tuples; view v renders sets[view_set[v]] with
+    cameras[v].  Returns (list of (rgb[3,H,W], depth[H,W], alpha[H,W]), Saved or None)."""
+    ctx = ctx or get_context()
+    L = load()
+    nv = len(cameras)
+    if view_set is None:
+        view_set = [0] * nv
+    gs = (_lib.Gaussians * len(sets))(*[_set_struct(s) for s in sets])
+    cams = (_lib.Camera * nv)(*[camera_struct(c) for c in cameras])
+    vs = (ctypes.c_int32 * nv)(*view_set)
+    outs, ims = [], (_lib.Images * nv)()
+    dev = sets[0][0].device
+    for v, c in enumerate(cameras):
+        H, W = int(c.height), int(c.width)
+        rgb = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+        depth = torch.empty((H, W), dtype=torch.float32, device=dev)
+        alpha = torch.empty((H, W), dtype=torch.float32, device=dev)
+        ims[v].rgb, ims[v].depth, ims[v].alpha = rgb.data_ptr(), depth.data_ptr(), alpha.data_ptr()
+        outs.append((rgb, depth, alpha))
+    opts = _lib.RenderOpts()
+    opts.tile_w, opts.tile_h = tile
+    opts.pair_capacity = int(pair_capacity)
+    h = ctypes.c_void_p()
+    st = L.vpgs_render_forward(ctx.handle, len(sets), gs, nv, vs, cams, ims, ctypes.byref(opts),
+                               ctypes.byref(h) if keep else None, _stream())
+    check(st, ctx.handle, "vpgs_render_forward")
+    saved = Saved(ctx, h, nv, len(sets), [s[0].shape[0] for s in sets],
+                  [(int(c.height), int(c.width)) for c in cameras]) if keep else None
+    return outs, saved
+
+
+def render_backward(saved: Saved, grad_images: Sequence, want_pose: bool = True):
+    """Backward of ``render``.  grad_images[v] = (g_rgb, g_depth, g_alpha),
+    any of them None.  Returns (list of per-set gradient tuples, d_pose[V,6] or None)."""
+    L = load()
+    nv, ns = saved.n_views, saved.n_sets
+    gi = (_lib.ImageGrads * nv)()
+    keep_alive = []
+    for v, (gr, gd, ga) in enumerate(grad_images):
+        H, W = saved.view_sizes[v]
+        for t, shp in ((gr, (3, H, W)), (gd, (H, W)), (ga, (H, W))):
+            if t is not None and (tuple(t.shape) != shp or t.dtype != torch.float32 or not t.is_contiguous()):
+                raise ValueError(f"upstream gradient of view {v} must be contiguous float32 of shape {shp}")
+        gi[v].rgb, gi[v].depth, gi[v].alpha = (t.data_ptr() if t is not None else None for t in (gr, gd, ga))
+        keep_alive += [gr, gd, ga]
+    grads, gb = [], (_lib.GaussBuffers * ns)()
+    for s, n in enumerate(saved.set_sizes):
+        g = (torch.empty((n, 3), dtype=torch.float32, device="cuda"),
+             torch.empty((n, 3), dtype=torch.float32, device="cuda"),
+             torch.empty((n, 4), dtype=torch.float32, device="cuda"),
+             torch.empty((n,), dtype=torch.float32, device="cuda"),
+             torch.empty((n, 3), dtype=torch.float32, device="cuda"))
+        gb[s].means, gb[s].log_scales, gb[s].quats, gb[s].opacities, gb[s].colors = (t.data_ptr() for t in g)
+        grads.append(g)
+    d_pose = torch.empty((nv, 6), dtype=torch.float32, device="cuda") if want_pose else None
+    st = L.vpgs_render_backward(saved.ctx.handle, saved.handle, gi, gb, _ptr(d_pose) if want_pose else None,
+                                _stream())
+    check(st, saved.ctx.handle, "vpgs_render_backward")
+    return grads, d_pose
+
+
+class _RenderViews(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, cfg, pose_delta, *flat):
+        cameras, view_set, tile, cap = cfg
+        sets = [tuple(flat[5 * s: 5 * s + 5]) for s in range(len(flat) // 5)]
+        sets = [tuple(t.detach().contiguous() for t in s) for s in sets]
+        outs, saved = render(sets, cameras, view_set, tile=tile, pair_capacity=cap, keep=True)
+        ctx.saved_handle = saved
+        ctx.n_sets = len(sets)
+        ctx.want_pose = pose_delta is not None
+        flat_out = []
+        for o in outs:
+            flat_out += list(o)
+        return tuple(flat_out)
+
+    @staticmethod
+    def backward(ctx, *g):
+        saved = ctx.saved_handle
+        grads_img = []
+        for v in range(saved.n_views):
+            trip = g[3 * v: 3 * v + 3]
+            grads_img.append(tuple(t.contiguous() if t is not None else None for t in trip))
+        grads, d_pose = render_backward(saved, grads_img, want_pose=ctx.want_pose)
+        saved.close()
+        ctx.saved_handle = None
+        flat = []
+        for gset in grads:
+            flat += list(gset)
+        return (None, d_pose, *flat)
+
+
+def render_views(sets, cameras, view_set=None, pose_delta: Optional[torch.Tensor] = None, tile=(16, 16),
+                 pair_capacity: int = 0):
+    """Differentiable render of several Gaussian sets and views.
+
+    ``pose_delta`` ([V, 6], zeros) is a leaf whose gradient is the gradient of
+    the loss with respect to a left se(3) increment (rho, phi) of each view's
+    pose; the render itself is at the given poses.  Returns a list of
+    (rgb, depth, alpha) per view."""
+    nv = len(cameras)
+    if view_set is None:
+        view_set = [0] * nv
+    flat = []
+    for s in sets:
+        flat += list(s)
+    out = _RenderViews.apply((list(cameras), list(view_set), tuple(tile), int(pair_capacity)), pose_delta, *flat)
+    return [tuple(out[3 * v: 3 * v + 3]) for v in range(nv)]
+
+
+# The autograd function: RenderFn.apply((cameras, view_set, tile, capacity), pose_delta, *set_tensors)
+RenderFn = _RenderViews

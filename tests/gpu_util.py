@@ -1,0 +1,82 @@
+"""Helpers shared by the GPU parity tests: device transfer, the tolerance
+gates and the near-tie masks (test infrastructure)."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+
+# Margins of the near-tie mask: a pixel is excluded from the image gate (and
+# its upstream weights are zeroed for the gradient gate) if any Gaussian
+# evaluated there has alpha within a relative 2e-4 of 1/255, o*G within 1e-5
+# of the 0.99 clamp, or T(1 - alpha) within a relative 1e-3 of 1e-4 -- the
+# places where an FP32 evaluation can take the other branch of a cutoff.
+MARGINS = (2e-4, 1e-5, 1e-3)
+
+IMAGE_RTOL = 1e-5     # norm-wise, per plane, FP32 vs the FP64 oracle
+GRAD_TOL = 1e-4       # per element against the error scale, and norm-wise
+
+
+def to_dev(arrs, dev="cuda"):
+    return tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in arrs)
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def image_errors(got, ref, mask):
+    """Norm-wise relative errors of the five planes over unmasked pixels."""
+    rgb, depth, alpha = (np_(t).astype(np.float64) for t in got)
+    keep = ~mask
+    out = {}
+    for name, g, e in (("r", rgb[0], ref["rgb"][0]), ("g", rgb[1], ref["rgb"][1]), ("b", rgb[2], ref["rgb"][2]),
+                       ("depth", depth, ref["depth"]), ("alpha", alpha, ref["alpha"])):
+        num = np.linalg.norm((g - e)[keep])
+        den = np.linalg.norm(e[keep])
+        out[name] = num / den if den > 0 else num
+    return out
+
+
+def assert_images(got, ref, mask, rtol=IMAGE_RTOL):
+    errs = image_errors(got, ref, mask)
+    bad = {k: v for k, v in errs.items() if not v <= rtol}
+    assert not bad, f"image parity failed: {errs} (masked {int(mask.sum())} px)"
+    return errs
+
+
+def assert_grads(got: dict, G: dict, S: dict, tol=GRAD_TOL, keys=None):
+    """Per element |g - g_ref| <= tol * scale (plus a floor), and norm-wise."""
+    report = {}
+    for k in keys or G.keys():
+        g = np.asarray(got[k], np.float64)
+        e, s = G[k], S[k]
+        floor = 1e-7 * (s.max() if s.size else 0.0)
+        err = np.abs(g - e)
+        worst = float(np.max(err / (s + floor + 1e-30))) if err.size else 0.0
+        nrm = float(np.linalg.norm(g - e) / max(np.linalg.norm(e), 1e-30))
+        report[k] = (worst, nrm)
+        assert worst <= tol, f"{k}: per-element error {worst:.3e} of scale exceeds {tol} ({report})"
+        assert nrm <= tol or np.linalg.norm(e) < 1e-6 * np.linalg.norm(s), f"{k}: norm-wise {nrm:.3e} ({report})"
+    return report
+
+
+def masked_weights(weights, mask):
+    gr, gd, ga = (np.array(w, np.float32) for w in weights)
+    gr[:, mask] = 0.0
+    gd[mask] = 0.0
+    ga[mask] = 0.0
+    return gr, gd, ga
+
+
+def oracle_reference(g, cam, weights=None):
+    """FP64 render (with near-tie flags) and, if weights are given, the masked
+    gradients and their error scales."""
+    ref = oracle.render(g, cam, margins=MARGINS)
+    mask = ref["flags"]
+    if weights is None:
+        return ref, mask, None
+    w = masked_weights(weights, mask)
+    G, S = oracle.grad(g, cam, *[x.astype(np.float64) for x in w])
+    return ref, mask, (w, G, S)
