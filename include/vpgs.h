@@ -199,6 +199,20 @@ int vpgs_saved_export(vpgs_ctx* ctx, const vpgs_saved* saved, int what, void* ds
 
 int vpgs_saved_release(vpgs_ctx* ctx, vpgs_saved* saved);
 
+/* ---- stage timing (diagnostics) ------------------------------------------ */
+
+/* When enabled, every launch sequence of the context records a pair of HIP
+ * events on its stream around each stage (projection, scan, emission, sort,
+ * ranges, forward compositing, backward compositing, projection backward,
+ * pose reduction, fills, decode forward, decode backward).  vpgs_profile_read
+ * synchronises on the recorded events and returns, for stage index `stage`
+ * (0 <= stage < VPGS_NUM_STAGES), its name, the number of recorded launches
+ * and their summed duration in milliseconds since the last enable.  Disabled
+ * by default; enabling resets the totals. */
+#define VPGS_NUM_STAGES 12
+int vpgs_profile_enable(vpgs_ctx* ctx, int on);
+int vpgs_profile_read(vpgs_ctx* ctx, int stage, const char** name, int64_t* calls, double* total_ms);
+
 /* ---- anchor decoder (Section III-A, eq. 1-5) ------------------------------- */
 
 /* m anchors with k Gaussians each. */

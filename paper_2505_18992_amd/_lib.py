@@ -22,6 +22,7 @@ VPGS_ECAPACITY = -4
 VPGS_EUNSUPPORTED = -5
 MAX_VIEWS = 64
 MAX_SETS = 64
+NUM_STAGES = 12
 
 BUF_PROJ, BUF_EXTENT, BUF_COUNT, BUF_KEYS, BUF_VALUES, BUF_RANGES, BUF_TFINAL, BUF_NCONTRIB = range(1, 9)
 
@@ -93,6 +94,9 @@ SIGNATURES = {
     "vpgs_saved_export": (ctypes.c_int, [c_void_p, c_void_p, ctypes.c_int, c_void_p, ctypes.c_size_t,
                                          ctypes.POINTER(ctypes.c_size_t), c_void_p]),
     "vpgs_saved_release": (ctypes.c_int, [c_void_p, c_void_p]),
+    "vpgs_profile_enable": (ctypes.c_int, [c_void_p, ctypes.c_int]),
+    "vpgs_profile_read": (ctypes.c_int, [c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     "vpgs_decode_forward": (ctypes.c_int, [c_void_p, ctypes.POINTER(Anchors), ctypes.POINTER(Mlp),
                                            ctypes.POINTER(ctypes.c_float), ctypes.POINTER(GaussBuffers), c_void_p]),
     "vpgs_decode_backward": (ctypes.c_int, [c_void_p, ctypes.POINTER(Anchors), ctypes.POINTER(Mlp),

@@ -39,11 +39,24 @@ struct vpgs_saved {
   bool in_use = false;
 };
 
+const char* const kStageNames[VPGS_NUM_STAGES] = {
+    "project", "scan", "emit", "sort", "ranges", "composite_forward", "composite_backward",
+    "project_backward", "pose_reduce", "fill", "decode_forward", "decode_backward"};
+enum Stage { ST_PROJECT, ST_SCAN, ST_EMIT, ST_SORT, ST_RANGES, ST_FWD, ST_BWD, ST_PROJ_BWD, ST_POSE, ST_FILL,
+             ST_DEC_FWD, ST_DEC_BWD };
+
 struct vpgs_ctx {
   int device = 0;
   std::string last_error;
   std::vector<vpgs_saved*> pool;
   void* h_pinned = nullptr;  // small pinned buffer for counter readback
+  // stage timing
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_free;
+  struct Pending { int stage; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  double stage_ms[VPGS_NUM_STAGES] = {};
+  int64_t stage_calls[VPGS_NUM_STAGES] = {};
 };
 
 namespace {
@@ -59,6 +72,38 @@ int fail(vpgs_ctx* ctx, int code, const char* fmt, ...) {
   }
   return code;
 }
+
+hipEvent_t take_event(vpgs_ctx* ctx) {
+  if (!ctx->ev_free.empty()) {
+    hipEvent_t e = ctx->ev_free.back();
+    ctx->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records an event pair around one stage when profiling is on.
+struct StageTimer {
+  vpgs_ctx* ctx;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  StageTimer(vpgs_ctx* c, int s, hipStream_t stream) : ctx(c), stage(s), st(stream) {
+    if (ctx->profiling) {
+      a = take_event(ctx);
+      if (a) (void)hipEventRecord(a, st);
+    }
+  }
+  ~StageTimer() {
+    if (!a) return;
+    hipEvent_t b = take_event(ctx);
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+    ctx->pending.push_back({stage, a, b});
+  }
+};
 
 #define HIP_TRY(expr)                                                                      \
   do {                                                                                     \
@@ -292,10 +337,48 @@ int vpgs_create(vpgs_ctx** out, int device) {
   return VPGS_OK;
 }
 
+int vpgs_profile_enable(vpgs_ctx* ctx, int on) {
+  if (!ctx) return VPGS_EINVAL;
+  for (auto& p : ctx->pending) {
+    (void)hipEventSynchronize(p.b);
+    ctx->ev_free.push_back(p.a);
+    ctx->ev_free.push_back(p.b);
+  }
+  ctx->pending.clear();
+  for (int i = 0; i < VPGS_NUM_STAGES; ++i) {
+    ctx->stage_ms[i] = 0.0;
+    ctx->stage_calls[i] = 0;
+  }
+  ctx->profiling = on != 0;
+  return VPGS_OK;
+}
+
+int vpgs_profile_read(vpgs_ctx* ctx, int stage, const char** name, int64_t* calls, double* total_ms) {
+  if (!ctx) return VPGS_EINVAL;
+  if (stage < 0 || stage >= VPGS_NUM_STAGES) return fail(ctx, VPGS_EINVAL, "stage %d out of range", stage);
+  for (auto& p : ctx->pending) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(p.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.a, p.b);
+    if (e != hipSuccess) return fail(ctx, VPGS_EHIP, "event timing: %s", hipGetErrorString(e));
+    ctx->stage_ms[p.stage] += ms;
+    ctx->stage_calls[p.stage] += 1;
+    ctx->ev_free.push_back(p.a);
+    ctx->ev_free.push_back(p.b);
+  }
+  ctx->pending.clear();
+  if (name) *name = kStageNames[stage];
+  if (calls) *calls = ctx->stage_calls[stage];
+  if (total_ms) *total_ms = ctx->stage_ms[stage];
+  return VPGS_OK;
+}
+
 int vpgs_destroy(vpgs_ctx* ctx) {
   if (!ctx) return VPGS_EINVAL;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  for (auto& p : ctx->pending) { ctx->ev_free.push_back(p.a); ctx->ev_free.push_back(p.b); }
+  for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
   for (vpgs_saved* s : ctx->pool) destroy_saved(s);
   if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
   delete ctx;
@@ -348,9 +431,18 @@ int vpgs_render_forward(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, i
   Counters* cnt = static_cast<Counters*>(sv->counters.p);
   const ProjBuffers pb = proj_of(sv);
 
-  HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, sizeof(Counters) / 4, st));
-  HIP_TRY(launch_project(d_tab, T, pb, tw, th, st));
-  HIP_TRY(launch_scan(pb.count, static_cast<uint32_t*>(sv->offsets.p), (uint32_t)R, &cnt->pairs, sv->scan_ws.p, st));
+  {
+    StageTimer t(ctx, ST_FILL, st);
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, sizeof(Counters) / 4, st));
+  }
+  {
+    StageTimer t(ctx, ST_PROJECT, st);
+    HIP_TRY(launch_project(d_tab, T, pb, tw, th, st));
+  }
+  {
+    StageTimer t(ctx, ST_SCAN, st);
+    HIP_TRY(launch_scan(pb.count, static_cast<uint32_t*>(sv->offsets.p), (uint32_t)R, &cnt->pairs, sv->scan_ws.p, st));
+  }
 
   uint32_t cap;
   if (fixed_cap > 0) {
@@ -371,15 +463,27 @@ int vpgs_render_forward(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, i
   uint32_t* vals = static_cast<uint32_t*>(sv->vals.p);
   uint64_t* keys_alt = static_cast<uint64_t*>(sv->keys_alt.p);
   uint32_t* vals_alt = static_cast<uint32_t*>(sv->vals_alt.p);
-  HIP_TRY(launch_emit(d_tab, T, pb, static_cast<const uint32_t*>(sv->offsets.p), cnt, keys, vals, cap, tw, th, st));
+  {
+    StageTimer t(ctx, ST_EMIT, st);
+    HIP_TRY(launch_emit(d_tab, T, pb, static_cast<const uint32_t*>(sv->offsets.p), cnt, keys, vals, cap, tw, th, st));
+  }
   const int key_bits = 32 + ilog2_ceil(std::max<uint32_t>(T.n_tiles, 2u));
-  HIP_TRY(launch_sort(keys, vals, keys_alt, vals_alt, cap, key_bits, cnt, sv->sort_ws.p, &sv->result_in_alt, st));
+  {
+    StageTimer t(ctx, ST_SORT, st);
+    HIP_TRY(launch_sort(keys, vals, keys_alt, vals_alt, cap, key_bits, cnt, sv->sort_ws.p, &sv->result_in_alt, st));
+  }
   const uint64_t* skeys = sv->result_in_alt ? keys_alt : keys;
   const uint32_t* svals = sv->result_in_alt ? vals_alt : vals;
-  HIP_TRY(launch_ranges(skeys, cnt, cap, static_cast<uint2*>(sv->ranges.p), T.n_tiles, st));
-  HIP_TRY(launch_composite_forward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
-                                   static_cast<float*>(sv->tfinal.p), static_cast<uint32_t*>(sv->ncontrib.p), cnt, tw,
-                                   th, st));
+  {
+    StageTimer t(ctx, ST_RANGES, st);
+    HIP_TRY(launch_ranges(skeys, cnt, cap, static_cast<uint2*>(sv->ranges.p), T.n_tiles, st));
+  }
+  {
+    StageTimer t(ctx, ST_FWD, st);
+    HIP_TRY(launch_composite_forward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
+                                     static_cast<float*>(sv->tfinal.p), static_cast<uint32_t*>(sv->ncontrib.p), cnt,
+                                     tw, th, st));
+  }
   if (saved) {
     rel.keep = true;
     *saved = sv;
@@ -430,13 +534,25 @@ int vpgs_render_backward(vpgs_ctx* ctx, const vpgs_saved* saved_c, const vpgs_im
   const ProjBuffers pb = proj_of(sv);
   float* acc = static_cast<float*>(sv->acc.p);
   const uint32_t* svals = static_cast<const uint32_t*>(sv->result_in_alt ? sv->vals_alt.p : sv->vals.p);
-  HIP_TRY(launch_fill_f32(acc, 0.0f, R * kNumAcc, st));
-  HIP_TRY(launch_composite_backward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
-                                    static_cast<const float*>(sv->tfinal.p),
-                                    static_cast<const uint32_t*>(sv->ncontrib.p), acc, sv->tile_w, sv->tile_h, st));
+  {
+    StageTimer t(ctx, ST_FILL, st);
+    HIP_TRY(launch_fill_f32(acc, 0.0f, R * kNumAcc, st));
+  }
+  {
+    StageTimer t(ctx, ST_BWD, st);
+    HIP_TRY(launch_composite_backward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
+                                      static_cast<const float*>(sv->tfinal.p),
+                                      static_cast<const uint32_t*>(sv->ncontrib.p), acc, sv->tile_w, sv->tile_h, st));
+  }
   float* partial = d_pose ? static_cast<float*>(sv->pose_partial.p) : nullptr;
-  HIP_TRY(launch_project_backward(d_tab, T, pb, acc, partial, st));
-  if (d_pose) HIP_TRY(launch_pose_reduce(d_tab, T, partial, d_pose, st));
+  {
+    StageTimer t(ctx, ST_PROJ_BWD, st);
+    HIP_TRY(launch_project_backward(d_tab, T, pb, acc, partial, st));
+  }
+  if (d_pose) {
+    StageTimer t(ctx, ST_POSE, st);
+    HIP_TRY(launch_pose_reduce(d_tab, T, partial, d_pose, st));
+  }
   return VPGS_OK;
 }
 

@@ -41,6 +41,21 @@ class Context:
             load().vpgs_destroy(self.handle)
             self.handle = None
 
+    def profile(self, on: bool = True):
+        """Enable (and reset) or disable per-stage HIP-event timing."""
+        check(load().vpgs_profile_enable(self.handle, int(on)), self.handle, "vpgs_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{stage name: (launch sequences recorded, total milliseconds)}."""
+        L = load()
+        out = {}
+        for i in range(_lib.NUM_STAGES):
+            name, calls, ms = ctypes.c_char_p(), ctypes.c_int64(), ctypes.c_double()
+            check(L.vpgs_profile_read(self.handle, i, ctypes.byref(name), ctypes.byref(calls), ctypes.byref(ms)),
+                  self.handle, "vpgs_profile_read")
+            out[name.value.decode()] = (calls.value, ms.value)
+        return out
+
     def __del__(self):
         try:
             self.close()
