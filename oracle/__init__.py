@@ -42,7 +42,7 @@ def lib():
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     _D, _D, _D, _D, _I32, _I32, _U8]
         L.oracle_grad.argtypes = [c_int, c_int, _D, _D, i64, _D, _D, _D, _D, _D, _D, _D, _D, _U8,
-                                  _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D]
+                                  _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D]
         L.oracle_binning.argtypes = [i64, _U8, _F, _F, _F, _F, _U32, c_int, c_int, c_int, c_int,
                                      ctypes.c_uint32, ctypes.c_uint32, i64, _U64, _U32, _U32]
         L.oracle_binning.restype = i64
@@ -108,11 +108,16 @@ def render(g, cam, brute_force: bool = False, margins=(1e-4, 1e-4, 1e-4)):
     return dict(rgb=rgb, depth=depth, alpha=alpha, T_final=T, n_blend=nb, n_eval=ne, flags=fl.astype(bool))
 
 
-def grad(g, cam, g_rgb, g_depth, g_alpha, skip: Optional[np.ndarray] = None):
+def grad(g, cam, g_rgb, g_depth, g_alpha, skip: Optional[np.ndarray] = None, quantities: bool = False):
     """FP64 gradient of sum(g_rgb*RGB + g_depth*D + g_alpha*A).
 
     Returns (grads, scales): dicts with means, log_scales, quats, opacities,
-    colors and pose (rho, phi) -- the gradient and its error scale."""
+    colors and pose (rho, phi) -- the gradient and its summation error scale.
+    scales also holds "<name>_fp32": a first-order bound on how far a float32
+    evaluation of the same forward moves the gradient (rounding of the
+    projected centres, propagated through the transmittance).  With
+    quantities=True grads also holds "quantity": [n, 10] gradients with
+    respect to (u, v, Qa, Qb, Qc, opacity, r, g, b, z) of every Gaussian."""
     W, H = cam.width, cam.height
     n = g.n
     intr, w2c = _cam_arrays(cam)
@@ -121,12 +126,20 @@ def grad(g, cam, g_rgb, g_depth, g_alpha, skip: Optional[np.ndarray] = None):
     sk = None if skip is None else np.ascontiguousarray(skip, dtype=np.uint8)
     outs = [np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((n, 4)), np.zeros(n), np.zeros((n, 3)), np.zeros(6)]
     scl = [np.zeros_like(a) for a in outs]
+    bnd = [np.zeros_like(a) for a in outs]
+    qg = np.zeros((n, 10)) if quantities else None
     lib().oracle_grad(W, H, _p(intr, _D), _p(w2c, _D), n, _p(m, _D), _p(l, _D), _p(q, _D), _p(o, _D),
                       _p(c, _D), _p(gr, _D), _p(gd, _D), _p(ga, _D),
                       None if sk is None else _p(sk, _U8),
-                      *[_p(a, _D) for a in outs], *[_p(a, _D) for a in scl])
+                      *[_p(a, _D) for a in outs], *[_p(a, _D) for a in scl],
+                      None if qg is None else _p(qg, _D), *[_p(a, _D) for a in bnd])
     keys = ["means", "log_scales", "quats", "opacities", "colors", "pose"]
-    return dict(zip(keys, outs)), dict(zip(keys, scl))
+    G = dict(zip(keys, outs))
+    if quantities:
+        G["quantity"] = qg
+    S = dict(zip(keys, scl))
+    S.update({k + "_fp32": b for k, b in zip(keys, bnd)})
+    return G, S
 
 
 def binning(valid, u, v, hx, hy, zbits, W, H, tw, th, tile_base=0, index_base=0, cap=None):

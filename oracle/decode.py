@@ -22,7 +22,7 @@ from __future__ import annotations
 
 import torch
 
-__all__ = ["decode_forward", "decode_backward"]
+__all__ = ["decode_forward", "decode_backward", "relu_near_ties"]
 
 
 def _t(a):
@@ -71,3 +71,21 @@ def decode_backward(xyz, feat, scale, offsets, W1, b1, W2, b2, cam_center, upstr
     return dict(feat=n(feat), scale=n(scale), offsets=n(offsets),
                 W1=[n(w) for w in W1], b1=[n(b) for b in b1],
                 W2=[n(w) for w in W2], b2=[n(b) for b in b2])
+
+
+def relu_near_ties(xyz, feat, scale, offsets, W1, b1, W2, b2, cam_center, margin=1e-5):
+    """Anchors with a hidden pre-activation within ``margin`` (relative to the
+    sum of the magnitudes of its terms) of zero: there a float32 evaluation
+    may take the other side of the ReLU, whose derivative jumps."""
+    xyz, feat = _t(xyz), _t(feat)
+    xc = _t(cam_center).reshape(1, 3)
+    diff = xyz - xc
+    delta = torch.linalg.norm(diff, dim=1, keepdim=True)
+    h = torch.cat([feat, diff / delta, delta], dim=1)
+    flag = torch.zeros(h.shape[0], dtype=torch.bool)
+    for j in range(3):
+        W, b = _t(W1[j]), _t(b1[j])
+        pre = h @ W.T + b
+        mag = h.abs() @ W.abs().T + b.abs()
+        flag |= (pre.abs() <= margin * mag).any(dim=1)
+    return flag.numpy()

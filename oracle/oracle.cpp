@@ -344,20 +344,29 @@ PixOut composite_pixel(const std::vector<Prim>& pr, const std::vector<int32_t>& 
   PixOut r;
   r.C[0] = r.C[1] = r.C[2] = 0.0; r.D = 0.0; r.T = 1.0; r.nb = 0; r.ne = 0; r.flag = 0; r.last = -1;
   const double cxp = px + 0.5, cyp = py + 0.5;
-  double T = 1.0;
+  // A float32 evaluation carries the projected centre to within a few units
+  // in the last place of |u|, |v|; that moves sigma by |d sigma/d u| du and
+  // alpha by the same relative amount.  The flag margins add this term, and
+  // the transmittance margin accumulates the relative errors of (1 - alpha).
+  const double ulp_pos = std::ldexp(1.0, -22);
+  double T = 1.0, eT = 0.0;
   for (size_t k = 0; k < cand.size(); ++k) {
     const Prim& p = pr[cand[k]];
     if (p.near_guard) r.flag = 1;
     const double dx = p.u - cxp, dy = p.v - cyp;
     const double sigma = 0.5 * (p.Qa * dx * dx + p.Qc * dy * dy) + p.Qb * dx * dy;
     const double raw = p.o * std::exp(-sigma);
-    if (std::fabs(raw - kAlphaMax) <= m.clamp) r.flag = 1;
+    const double drel = std::fabs(p.Qa * dx + p.Qb * dy) * std::fabs(p.u) * ulp_pos +
+                        std::fabs(p.Qb * dx + p.Qc * dy) * std::fabs(p.v) * ulp_pos +
+                        (1.0 + sigma) * 16.0 * std::ldexp(1.0, -24);  // exp and conic rounding
+    if (std::fabs(raw - kAlphaMax) <= m.clamp + raw * drel) r.flag = 1;
     const double alpha = std::min(kAlphaMax, raw);
     r.ne++;
-    if (std::fabs(alpha - kAlphaMin) <= m.alpha * kAlphaMin) r.flag = 1;
+    if (std::fabs(alpha - kAlphaMin) <= (m.alpha + drel) * kAlphaMin) r.flag = 1;
     if (alpha < kAlphaMin) continue;
     const double Tn = T * (1.0 - alpha);
-    if (std::fabs(Tn - kTmin) <= m.trans * kTmin) r.flag = 1;
+    eT += alpha * drel / (1.0 - alpha);
+    if (std::fabs(Tn - kTmin) <= (m.trans + eT) * kTmin) r.flag = 1;
     if (Tn < kTmin) break;
     const double w = alpha * T;
     for (int ch = 0; ch < 3; ++ch) r.C[ch] += w * p.col[ch];
@@ -379,7 +388,7 @@ enum { QU = 0, QV, QA, QB, QC, QO, QR, QG, QBL, QZ, NQ };
 // runs the F11 recurrence over the suffix starting at k.
 void pixel_quantity_grads(const std::vector<Prim>& pr, const std::vector<int32_t>& bl,
                           const std::vector<double>& bl_T, size_t k, int px, int py,
-                          Dual<NQ> out[5] /* R, G, B, D, A */) {
+                          Dual<NQ> out[5] /* R, G, B, D, A */, Dual<NQ>* alpha_k) {
   typedef Dual<NQ> D;
   const double cxp = px + 0.5, cyp = py + 0.5;
   const Prim& g = pr[bl[k]];
@@ -397,6 +406,7 @@ void pixel_quantity_grads(const std::vector<Prim>& pr, const std::vector<int32_t
       D sigma = 0.5 * (q[QA] * dx * dx + q[QC] * dy * dy) + q[QB] * dx * dy;
       D raw = q[QO] * exp(-sigma);
       alpha = raw.v < kAlphaMax ? raw : D(kAlphaMax);
+      if (alpha_k) *alpha_k = alpha;
       cc[0] = q[QR]; cc[1] = q[QG]; cc[2] = q[QBL]; z = q[QZ];
     } else {
       const double dx = p.u - cxp, dy = p.v - cyp;
@@ -475,26 +485,32 @@ int oracle_render(int W, int H, const double* intr, const double* w2c, int64_t n
 
 // FP64 gradient of L = sum_p g_rgb . RGB + g_d D + g_a A for one view.
 // skip[p] = 1 drops pixel p from the loss.  Outputs are written (not
-// accumulated).  s_* are the error scales: sum over pixels and quantities of
-// |g . d(output)/d(quantity)| |d(quantity)/d(parameter)|.
+// accumulated).  s_* are the error scales: sums over pixels and quantities of
+// |contribution to d L / d(quantity)| |d(quantity)/d(parameter)|, where the
+// contribution through alpha_i counts the magnitudes of the two terms of
+// d L / d alpha_i = T_i f_i - S_i / (1 - alpha_i) (f = g . (c, z, 1), S the
+// weighted sum of f behind i): a floating-point evaluation of that difference
+// errs relative to those magnitudes, not to their (possibly cancelling) sum.
 int oracle_grad(int W, int H, const double* intr, const double* w2c, int64_t n,
                 const double* means, const double* ls, const double* quats, const double* opac,
                 const double* cols, const double* g_rgb, const double* g_depth, const double* g_alpha,
                 const uint8_t* skip, double* d_means, double* d_ls, double* d_quats, double* d_opac,
                 double* d_cols, double* d_pose, double* s_means, double* s_ls, double* s_quats,
-                double* s_opac, double* s_cols, double* s_pose) {
+                double* s_opac, double* s_cols, double* s_pose, double* q_grad, double* b_means,
+                double* b_ls, double* b_quats, double* b_opac, double* b_cols, double* b_pose) {
   const Cam cam = make_cam(W, H, intr, w2c);
   const Inputs in{n, means, ls, quats, opac, cols};
   std::vector<Prim> pr = project_all(cam, in, 1);
   Buckets b = make_buckets(cam, pr);
   const Margins m{0.0, 0.0, 0.0};
   const size_t HW = (size_t)W * H;
-  std::vector<double> G((size_t)n * NQ, 0.0), Gabs((size_t)n * NQ, 0.0);
+  std::vector<double> G((size_t)n * NQ, 0.0), Gabs((size_t)n * NQ, 0.0), Gfp((size_t)n * NQ, 0.0);
+  const double ulp_pos = std::ldexp(1.0, -22);
 #pragma omp parallel
   {
     std::vector<int32_t> cand, bl;
-    std::vector<double> bla, blT;
-    Dual<NQ> outs[5];
+    std::vector<double> bla, blT, fbar, drel, eTb;
+    Dual<NQ> outs[5], alpha_k;
 #pragma omp for schedule(dynamic, 1)
     for (int py = 0; py < H; ++py)
       for (int px = 0; px < W; ++px) {
@@ -505,26 +521,59 @@ int oracle_grad(int W, int H, const double* intr, const double* w2c, int64_t n,
         pixel_candidates(b, pr, px, py, cand);
         bl.clear(); bla.clear(); blT.clear();
         composite_pixel(pr, cand, px, py, m, &bl, &bla, &blT);
-        for (size_t k = 0; k < bl.size(); ++k) {
-          pixel_quantity_grads(pr, bl, blT, k, px, py, outs);
+        // magnitude of f for every blended Gaussian, and the suffix sums
+        fbar.assign(bl.size(), 0.0);
+        for (size_t j = 0; j < bl.size(); ++j) {
+          const Prim& p = pr[bl[j]];
+          fbar[j] = std::fabs(gw[0]) * std::fabs(p.col[0]) + std::fabs(gw[1]) * std::fabs(p.col[1]) +
+                    std::fabs(gw[2]) * std::fabs(p.col[2]) + std::fabs(gw[3]) * std::fabs(p.z) + std::fabs(gw[4]);
+        }
+        // first-order float32 propagation: relative error of each blended
+        // alpha from the rounding of the projected centre, and the relative
+        // error it leaves in the transmittance of everything behind it
+        drel.assign(bl.size(), 0.0);
+        eTb.assign(bl.size(), 0.0);
+        double eT = 0.0;
+        for (size_t j = 0; j < bl.size(); ++j) {
+          const Prim& p = pr[bl[j]];
+          const double dx = p.u - (px + 0.5), dy = p.v - (py + 0.5);
+          const double sigma = 0.5 * (p.Qa * dx * dx + p.Qc * dy * dy) + p.Qb * dx * dy;
+          drel[j] = std::fabs(p.Qa * dx + p.Qb * dy) * std::fabs(p.u) * ulp_pos +
+                    std::fabs(p.Qb * dx + p.Qc * dy) * std::fabs(p.v) * ulp_pos +
+                    (1.0 + sigma) * 16.0 * std::ldexp(1.0, -24);  // exp and conic rounding
+          eTb[j] = eT;
+          eT += bla[j] * drel[j] / (1.0 - bla[j]) + 2.0 * std::ldexp(1.0, -24);
+        }
+        double behind = 0.0;  // sum over blended j > k of alpha_j T_j fbar_j
+        for (size_t kk = bl.size(); kk-- > 0;) {
+          const size_t k = kk;
+          pixel_quantity_grads(pr, bl, blT, k, px, py, outs, &alpha_k);
           const int32_t gi = bl[k];
+          const double mag = blT[k] * fbar[k] + behind / (1.0 - bla[k]);
           for (int qn = 0; qn < NQ; ++qn) {
             double acc = 0.0;
             for (int o = 0; o < 5; ++o) acc += gw[o] * outs[o].d[qn];
+            const double scale = qn <= QO ? mag * std::fabs(alpha_k.d[qn]) : std::fabs(acc);
+            const double fp = qn <= QO ? scale * (eT + drel[k]) : scale * (eTb[k] + drel[k]);
 #pragma omp atomic
             G[(size_t)gi * NQ + qn] += acc;
 #pragma omp atomic
-            Gabs[(size_t)gi * NQ + qn] += std::fabs(acc);
+            Gabs[(size_t)gi * NQ + qn] += scale;
+#pragma omp atomic
+            Gfp[(size_t)gi * NQ + qn] += fp;
           }
+          behind += bla[k] * blT[k] * fbar[k];
         }
       }
   }
+  if (q_grad)  // d L / d(u, v, Qa, Qb, Qc, o, r, g, b, z) of every Gaussian
+    for (size_t i = 0; i < G.size(); ++i) q_grad[i] = G[i];
   // chain through the projection: 14 parameter duals + 6 pose duals
   typedef Dual<20> D20;
-  double pose[6] = {0, 0, 0, 0, 0, 0}, spose[6] = {0, 0, 0, 0, 0, 0};
+  double pose[6] = {0, 0, 0, 0, 0, 0}, spose[6] = {0, 0, 0, 0, 0, 0}, bpose[6] = {0, 0, 0, 0, 0, 0};
 #pragma omp parallel
   {
-    double lpose[6] = {0, 0, 0, 0, 0, 0}, lspose[6] = {0, 0, 0, 0, 0, 0};
+    double lpose[6] = {0, 0, 0, 0, 0, 0}, lspose[6] = {0, 0, 0, 0, 0, 0}, lbpose[6] = {0, 0, 0, 0, 0, 0};
 #pragma omp for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
       double* dm = d_means + 3 * i; double* dl = d_ls + 3 * i; double* dq = d_quats + 4 * i;
@@ -534,8 +583,14 @@ int oracle_grad(int W, int H, const double* intr, const double* w2c, int64_t n,
       for (int k = 0; k < 3; ++k) dm[k] = dl[k] = dc[k] = sm[k] = sl[k] = sc[k] = 0.0;
       for (int k = 0; k < 4; ++k) dq[k] = sq[k] = 0.0;
       d_opac[i] = s_opac[i] = 0.0;
+      double* bm = b_means + 3 * i; double* bl_ = b_ls + 3 * i; double* bq = b_quats + 4 * i;
+      double* bc = b_cols + 3 * i;
+      for (int k = 0; k < 3; ++k) bm[k] = bl_[k] = bc[k] = 0.0;
+      for (int k = 0; k < 4; ++k) bq[k] = 0.0;
+      b_opac[i] = 0.0;
       const double* Gi = &G[(size_t)i * NQ];
       const double* Ai = &Gabs[(size_t)i * NQ];
+      const double* Fi = &Gfp[(size_t)i * NQ];
       bool any = false;
       for (int qn = 0; qn < NQ; ++qn) any = any || Ai[qn] != 0.0;
       if (!any) continue;
@@ -569,12 +624,20 @@ int oracle_grad(int W, int H, const double* intr, const double* w2c, int64_t n,
       qd[QU] = P.u; qd[QV] = P.v; qd[QA] = P.Qa; qd[QB] = P.Qb; qd[QC] = P.Qc; qd[QZ] = P.z;
       qd[QO] = D20(opac[i]); qd[QO].d[10] = 1.0;
       for (int k = 0; k < 3; ++k) { qd[QR + k] = D20(cols[3 * i + k]); qd[QR + k].d[11 + k] = 1.0; }
-      double dv[20], sv[20];
+      double dv[20], sv[20], bv[20];
       for (int j = 0; j < 20; ++j) {
-        double acc = 0.0, sacc = 0.0;
-        for (int qn = 0; qn < NQ; ++qn) { acc += Gi[qn] * qd[qn].d[j]; sacc += Ai[qn] * std::fabs(qd[qn].d[j]); }
-        dv[j] = acc; sv[j] = sacc;
+        double acc = 0.0, sacc = 0.0, bacc = 0.0;
+        for (int qn = 0; qn < NQ; ++qn) {
+          acc += Gi[qn] * qd[qn].d[j];
+          sacc += Ai[qn] * std::fabs(qd[qn].d[j]);
+          bacc += Fi[qn] * std::fabs(qd[qn].d[j]);
+        }
+        dv[j] = acc; sv[j] = sacc; bv[j] = bacc;
       }
+      for (int k = 0; k < 3; ++k) { bm[k] = bv[k]; bl_[k] = bv[3 + k]; bc[k] = bv[11 + k]; }
+      for (int k = 0; k < 4; ++k) bq[k] = bv[6 + k];
+      b_opac[i] = bv[10];
+      for (int k = 0; k < 6; ++k) lbpose[k] += bv[14 + k];
       for (int k = 0; k < 3; ++k) { dm[k] = dv[k]; sm[k] = sv[k]; dl[k] = dv[3 + k]; sl[k] = sv[3 + k]; }
       for (int k = 0; k < 4; ++k) { dq[k] = dv[6 + k]; sq[k] = sv[6 + k]; }
       d_opac[i] = dv[10]; s_opac[i] = sv[10];
@@ -582,9 +645,9 @@ int oracle_grad(int W, int H, const double* intr, const double* w2c, int64_t n,
       for (int k = 0; k < 6; ++k) { lpose[k] += dv[14 + k]; lspose[k] += sv[14 + k]; }
     }
 #pragma omp critical
-    for (int k = 0; k < 6; ++k) { pose[k] += lpose[k]; spose[k] += lspose[k]; }
+    for (int k = 0; k < 6; ++k) { pose[k] += lpose[k]; spose[k] += lspose[k]; bpose[k] += lbpose[k]; }
   }
-  for (int k = 0; k < 6; ++k) { d_pose[k] = pose[k]; s_pose[k] = spose[k]; }
+  for (int k = 0; k < 6; ++k) { d_pose[k] = pose[k]; s_pose[k] = spose[k]; b_pose[k] = bpose[k]; }
   return 0;
 }
 

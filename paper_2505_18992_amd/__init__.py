@@ -6,7 +6,7 @@ The computation runs in hand-written HIP kernels behind the C ABI of
 into that ABI.  Importing it does not load the library; the first call does,
 and fails loudly if the library is not built.
 """
-from .render import (Context, RenderFn, Saved, camera_struct, get_context, render, render_backward,  # noqa: F401
-                     render_views)
+from .render import (Context, DecodeFn, RenderFn, Saved, camera_struct, decode, decode_backward,  # noqa: F401
+                     decode_forward, get_context, render, render_backward, render_views)
 
 __version__ = "0.1.0"

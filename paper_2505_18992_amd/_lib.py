@@ -24,7 +24,7 @@ MAX_VIEWS = 64
 MAX_SETS = 64
 NUM_STAGES = 12
 
-BUF_PROJ, BUF_EXTENT, BUF_COUNT, BUF_KEYS, BUF_VALUES, BUF_RANGES, BUF_TFINAL, BUF_NCONTRIB = range(1, 9)
+BUF_PROJ, BUF_EXTENT, BUF_COUNT, BUF_KEYS, BUF_VALUES, BUF_RANGES, BUF_TFINAL, BUF_NCONTRIB, BUF_GRADACC = range(1, 10)
 
 
 class Camera(ctypes.Structure):

@@ -12,54 +12,15 @@
 #include <string>
 #include <vector>
 
-#include "internal.h"
+#include "runtime.h"
 
 using namespace vpgs;
 
-namespace {
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t cap = 0;
-};
-
-}  // namespace
-
-struct vpgs_saved {
-  // host and device call tables; the host copy is pinned and guarded by an
-  // event so an in-flight upload is never overwritten
-  CallTables* h_tab = nullptr;
-  hipEvent_t tab_uploaded = nullptr;
-  DevBuf tab, pa, pb, pc, ext, rect, count, offsets, scan_ws, keys, vals, keys_alt, vals_alt, sort_ws, ranges,
-      tfinal, ncontrib, counters, acc, pose_partial;
-  int result_in_alt = 0;
-  int tile_w = 16, tile_h = 16;
-  uint32_t capacity = 0;
-  uint32_t n_pixels = 0;
-  bool in_use = false;
-};
+namespace vpgs {
 
 const char* const kStageNames[VPGS_NUM_STAGES] = {
     "project", "scan", "emit", "sort", "ranges", "composite_forward", "composite_backward",
     "project_backward", "pose_reduce", "fill", "decode_forward", "decode_backward"};
-enum Stage { ST_PROJECT, ST_SCAN, ST_EMIT, ST_SORT, ST_RANGES, ST_FWD, ST_BWD, ST_PROJ_BWD, ST_POSE, ST_FILL,
-             ST_DEC_FWD, ST_DEC_BWD };
-
-struct vpgs_ctx {
-  int device = 0;
-  std::string last_error;
-  std::vector<vpgs_saved*> pool;
-  void* h_pinned = nullptr;  // small pinned buffer for counter readback
-  // stage timing
-  bool profiling = false;
-  std::vector<hipEvent_t> ev_free;
-  struct Pending { int stage; hipEvent_t a, b; };
-  std::vector<Pending> pending;
-  double stage_ms[VPGS_NUM_STAGES] = {};
-  int64_t stage_calls[VPGS_NUM_STAGES] = {};
-};
-
-namespace {
 
 int fail(vpgs_ctx* ctx, int code, const char* fmt, ...) {
   if (ctx) {
@@ -84,32 +45,20 @@ hipEvent_t take_event(vpgs_ctx* ctx) {
   return e;
 }
 
-// Records an event pair around one stage when profiling is on.
-struct StageTimer {
-  vpgs_ctx* ctx;
-  int stage;
-  hipStream_t st;
-  hipEvent_t a = nullptr;
-  StageTimer(vpgs_ctx* c, int s, hipStream_t stream) : ctx(c), stage(s), st(stream) {
-    if (ctx->profiling) {
-      a = take_event(ctx);
-      if (a) (void)hipEventRecord(a, st);
-    }
+StageTimer::StageTimer(vpgs_ctx* c, int s, hipStream_t stream) : ctx(c), stage(s), st(stream) {
+  if (ctx->profiling) {
+    a = take_event(ctx);
+    if (a) (void)hipEventRecord(a, st);
   }
-  ~StageTimer() {
-    if (!a) return;
-    hipEvent_t b = take_event(ctx);
-    if (!b) return;
-    (void)hipEventRecord(b, st);
-    ctx->pending.push_back({stage, a, b});
-  }
-};
+}
 
-#define HIP_TRY(expr)                                                                      \
-  do {                                                                                     \
-    hipError_t e_ = (expr);                                                                \
-    if (e_ != hipSuccess) return fail(ctx, VPGS_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
+StageTimer::~StageTimer() {
+  if (!a) return;
+  hipEvent_t b = take_event(ctx);
+  if (!b) return;
+  (void)hipEventRecord(b, st);
+  ctx->pending.push_back({stage, a, b});
+}
 
 int ensure(vpgs_ctx* ctx, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
@@ -135,6 +84,10 @@ void free_buf(DevBuf& b) {
   b.p = nullptr;
   b.cap = 0;
 }
+
+}  // namespace vpgs
+
+namespace {
 
 void destroy_saved(vpgs_saved* s) {
   DevBuf* bufs[] = {&s->tab, &s->pa, &s->pb, &s->pc, &s->ext, &s->rect, &s->count, &s->offsets, &s->scan_ws,
@@ -380,6 +333,8 @@ int vpgs_destroy(vpgs_ctx* ctx) {
   for (auto& p : ctx->pending) { ctx->ev_free.push_back(p.a); ctx->ev_free.push_back(p.b); }
   for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
   for (vpgs_saved* s : ctx->pool) destroy_saved(s);
+  free_buf(ctx->dec_ws);
+  free_buf(ctx->dec_partial);
   if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
   delete ctx;
   return VPGS_OK;
@@ -601,6 +556,7 @@ int vpgs_saved_export(vpgs_ctx* ctx, const vpgs_saved* saved, int what, void* ds
     case VPGS_BUF_RANGES: need = (size_t)T.n_tiles * 8; break;
     case VPGS_BUF_TFINAL: need = (size_t)saved->n_pixels * 4; break;
     case VPGS_BUF_NCONTRIB: need = (size_t)saved->n_pixels * 4; break;
+    case VPGS_BUF_GRADACC: need = saved->acc.p ? R * kNumAcc * 4 : 0; break;
     default: return fail(ctx, VPGS_EINVAL, "unknown buffer %d", what);
   }
   if (size) *size = need;
@@ -627,6 +583,7 @@ int vpgs_saved_export(vpgs_ctx* ctx, const vpgs_saved* saved, int what, void* ds
     case VPGS_BUF_RANGES: HIP_TRY(hipMemcpyAsync(dst, saved->ranges.p, need, hipMemcpyDeviceToDevice, st)); break;
     case VPGS_BUF_TFINAL: HIP_TRY(hipMemcpyAsync(dst, saved->tfinal.p, need, hipMemcpyDeviceToDevice, st)); break;
     case VPGS_BUF_NCONTRIB: HIP_TRY(hipMemcpyAsync(dst, saved->ncontrib.p, need, hipMemcpyDeviceToDevice, st)); break;
+    case VPGS_BUF_GRADACC: HIP_TRY(hipMemcpyAsync(dst, saved->acc.p, need, hipMemcpyDeviceToDevice, st)); break;
   }
   return VPGS_OK;
 }

@@ -1,0 +1,81 @@
+// runtime.h -- host-side state shared by the C ABI translation units: the
+// context, the saved forward state, grow-only device buffers, error
+// reporting and stage timing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace vpgs {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+enum Stage { ST_PROJECT, ST_SCAN, ST_EMIT, ST_SORT, ST_RANGES, ST_FWD, ST_BWD, ST_PROJ_BWD, ST_POSE, ST_FILL,
+             ST_DEC_FWD, ST_DEC_BWD };
+extern const char* const kStageNames[VPGS_NUM_STAGES];
+
+}  // namespace vpgs
+
+struct vpgs_saved {
+  // host and device call tables; the host copy is pinned and guarded by an
+  // event so an in-flight upload is never overwritten
+  vpgs::CallTables* h_tab = nullptr;
+  hipEvent_t tab_uploaded = nullptr;
+  vpgs::DevBuf tab, pa, pb, pc, ext, rect, count, offsets, scan_ws, keys, vals, keys_alt, vals_alt, sort_ws, ranges,
+      tfinal, ncontrib, counters, acc, pose_partial;
+  int result_in_alt = 0;
+  int tile_w = 16, tile_h = 16;
+  uint32_t capacity = 0;
+  uint32_t n_pixels = 0;
+  bool in_use = false;
+};
+
+struct vpgs_ctx {
+  int device = 0;
+  std::string last_error;
+  std::vector<vpgs_saved*> pool;
+  void* h_pinned = nullptr;  // small pinned buffer for counter readback
+  // decode workspace
+  vpgs::DevBuf dec_ws, dec_partial;
+  // stage timing
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_free;
+  struct Pending { int stage; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  double stage_ms[VPGS_NUM_STAGES] = {};
+  int64_t stage_calls[VPGS_NUM_STAGES] = {};
+};
+
+namespace vpgs {
+
+// Records the message as the context's last error and returns code.
+int fail(vpgs_ctx* ctx, int code, const char* fmt, ...);
+// Grows b to at least `bytes` (hipFree + hipMalloc; contents are not kept).
+int ensure(vpgs_ctx* ctx, DevBuf& b, size_t bytes);
+void free_buf(DevBuf& b);
+
+// Records a HIP event pair around one stage when profiling is on.
+struct StageTimer {
+  vpgs_ctx* ctx;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  StageTimer(vpgs_ctx* c, int s, hipStream_t stream);
+  ~StageTimer();
+};
+
+}  // namespace vpgs
+
+#define HIP_TRY(expr)                                                                              \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess) return vpgs::fail(ctx, VPGS_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)

@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import check, load
 
 __all__ = ["Context", "get_context", "render", "render_backward", "Saved", "RenderFn", "render_views",
-           "camera_struct"]
+           "camera_struct", "decode_forward", "decode_backward", "DecodeFn", "decode"]
 
 
 class Context:
@@ -110,8 +110,10 @@ def _stream():
 class Saved:
     """Handle of a forward's saved state; released on close or garbage collection."""
 
-    def __init__(self, ctx: Context, handle, n_views, n_sets, set_sizes, view_sizes):
+    def __init__(self, ctx: Context, handle, n_views, n_sets, set_sizes, view_sizes, keep_alive=()):
         self.ctx = ctx
+        # the library reads the Gaussian buffers again in the backward: hold them
+        self._keep_alive = tuple(keep_alive)
         self.handle = handle
         self.n_views = n_views
         self.n_sets = n_sets
@@ -141,6 +143,7 @@ class Saved:
         if self.handle:
             load().vpgs_saved_release(self.ctx.handle, self.handle)
             self.handle = None
+        self._keep_alive = ()
 
     def __del__(self):
         try:
@@ -193,7 +196,8 @@ def render(sets: Sequence[Sequence[torch.Tensor]], cameras: Sequence, view_set: 
                                ctypes.byref(h) if keep else None, _stream())
     check(st, ctx.handle, "vpgs_render_forward")
     saved = Saved(ctx, h, nv, len(sets), [s[0].shape[0] for s in sets],
-                  [(int(c.height), int(c.width)) for c in cameras]) if keep else None
+                  [(int(c.height), int(c.width)) for c in cameras],
+                  keep_alive=[t for s in sets for t in s]) if keep else None
     return outs, saved
 
 
@@ -278,3 +282,126 @@ def render_views(sets, cameras, view_set=None, pose_delta: Optional[torch.Tensor
 
 # The autograd function: RenderFn.apply((cameras, view_set, tile, capacity), pose_delta, *set_tensors)
 RenderFn = _RenderViews
+
+
+# ---------------------------------------------------------------------------
+# anchor decoder
+# ---------------------------------------------------------------------------
+
+def _anchors_struct(xyz, feat, scale, offsets) -> _lib.Anchors:
+    m, k = offsets.shape[0], offsets.shape[1]
+    _check_tensor(xyz, "xyz", (3,), m)
+    _check_tensor(feat, "feat", (32,), m)
+    _check_tensor(scale, "scale", (3,), m)
+    _check_tensor(offsets, "offsets", (k, 3), m)
+    a = _lib.Anchors()
+    a.m, a.k = m, k
+    a.xyz, a.feat, a.scale, a.offsets = xyz.data_ptr(), feat.data_ptr(), scale.data_ptr(), offsets.data_ptr()
+    return a
+
+
+def _mlp_struct(W1, b1, W2, b2) -> _lib.Mlp:
+    mlp = _lib.Mlp()
+    mlp.in_dim = int(W1[0].shape[1])
+    mlp.width = int(W1[0].shape[0])
+    for h in range(3):
+        for t, nm in ((W1[h], "W1"), (b1[h], "b1"), (W2[h], "W2"), (b2[h], "b2")):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{nm}[{h}] must be a contiguous float32 GPU tensor")
+        mlp.W1[h], mlp.b1[h], mlp.W2[h], mlp.b2[h] = (W1[h].data_ptr(), b1[h].data_ptr(), W2[h].data_ptr(),
+                                                      b2[h].data_ptr())
+    return mlp
+
+
+def _cam3(cam_center):
+    c = [float(x) for x in torch.as_tensor(cam_center).reshape(-1).tolist()]
+    return (ctypes.c_float * 3)(*c)
+
+
+def decode_forward(anchors, mlp, cam_center, ctx: Optional[Context] = None):
+    """Decode m*k neural Gaussians from anchors (xyz, feat, scale, offsets)
+    and decoder weights (W1, b1, W2, b2: lists of 3 tensors).  Returns
+    (means, log_scales, quats, opacities, colors)."""
+    ctx = ctx or get_context()
+    xyz, feat, scale, offsets = anchors
+    m, k = offsets.shape[0], offsets.shape[1]
+    n = m * k
+    dev = xyz.device
+    out = (torch.empty((n, 3), dtype=torch.float32, device=dev), torch.empty((n, 3), dtype=torch.float32, device=dev),
+           torch.empty((n, 4), dtype=torch.float32, device=dev), torch.empty((n,), dtype=torch.float32, device=dev),
+           torch.empty((n, 3), dtype=torch.float32, device=dev))
+    gb = _lib.GaussBuffers()
+    gb.means, gb.log_scales, gb.quats, gb.opacities, gb.colors = (t.data_ptr() for t in out)
+    a = _anchors_struct(xyz, feat, scale, offsets)
+    w = _mlp_struct(*mlp)
+    check(load().vpgs_decode_forward(ctx.handle, ctypes.byref(a), ctypes.byref(w), _cam3(cam_center),
+                                     ctypes.byref(gb), _stream()), ctx.handle, "vpgs_decode_forward")
+    return out
+
+
+def decode_backward(anchors, mlp, cam_center, upstream, ctx: Optional[Context] = None):
+    """Gradients of sum(upstream . decoded) w.r.t. feat, scale, offsets and the
+    weights.  Returns (d_feat, d_scale, d_offsets, (dW1, db1, dW2, db2))."""
+    ctx = ctx or get_context()
+    xyz, feat, scale, offsets = anchors
+    W1, b1, W2, b2 = mlp
+    up = tuple(t.contiguous() for t in upstream)
+    for t, shp in zip(up, ((3,), (3,), (4,), (), (3,))):
+        if t.dtype != torch.float32 or tuple(t.shape[1:]) != shp:
+            raise ValueError("upstream gradients must be float32 with the decoded shapes")
+    gb = _lib.GaussBuffers()
+    gb.means, gb.log_scales, gb.quats, gb.opacities, gb.colors = (t.data_ptr() for t in up)
+    d_feat, d_scale, d_off = torch.empty_like(feat), torch.empty_like(scale), torch.empty_like(offsets)
+    dW1 = [torch.empty_like(t) for t in W1]
+    db1 = [torch.empty_like(t) for t in b1]
+    dW2 = [torch.empty_like(t) for t in W2]
+    db2 = [torch.empty_like(t) for t in b2]
+    g = _lib.MlpGrads()
+    for h in range(3):
+        g.W1[h], g.b1[h], g.W2[h], g.b2[h] = dW1[h].data_ptr(), db1[h].data_ptr(), dW2[h].data_ptr(), db2[h].data_ptr()
+    a = _anchors_struct(xyz, feat, scale, offsets)
+    w = _mlp_struct(W1, b1, W2, b2)
+    check(load().vpgs_decode_backward(ctx.handle, ctypes.byref(a), ctypes.byref(w), _cam3(cam_center),
+                                      ctypes.byref(gb), _ptr(d_feat), _ptr(d_scale), _ptr(d_off), ctypes.byref(g),
+                                      _stream()), ctx.handle, "vpgs_decode_backward")
+    return d_feat, d_scale, d_off, (dW1, db1, dW2, db2)
+
+
+class DecodeFn(torch.autograd.Function):
+    """DecodeFn.apply(cam_center, xyz, feat, scale, offsets, W1_0, W1_1, W1_2,
+    b1_0.., W2_0.., b2_0..) -> (means, log_scales, quats, opacities, colors).
+    Gradients flow to feat, scale, offsets and the 12 weight tensors (the
+    anchor positions and the camera are constants of the decode)."""
+
+    @staticmethod
+    def forward(ctx, cam_center, xyz, feat, scale, offsets, *w):
+        W1, b1, W2, b2 = list(w[0:3]), list(w[3:6]), list(w[6:9]), list(w[9:12])
+        anchors = tuple(t.detach().contiguous() for t in (xyz, feat, scale, offsets))
+        mlp = tuple([t.detach().contiguous() for t in lst] for lst in (W1, b1, W2, b2))
+        ctx.save_for_backward(*anchors, *[t for lst in mlp for t in lst])
+        ctx.cam_center = cam_center
+        return decode_forward(anchors, mlp, cam_center)
+
+    @staticmethod
+    def backward(ctx, *g):
+        saved = ctx.saved_tensors
+        anchors = saved[:4]
+        mlp = (list(saved[4:7]), list(saved[7:10]), list(saved[10:13]), list(saved[13:16]))
+        up = []
+        for t, ref in zip(g, decode_forward_shapes(anchors)):
+            up.append(t if t is not None else torch.zeros(ref, dtype=torch.float32, device=anchors[0].device))
+        d_feat, d_scale, d_off, (dW1, db1, dW2, db2) = decode_backward(anchors, mlp, ctx.cam_center, up)
+        return (None, None, d_feat, d_scale, d_off, *dW1, *db1, *dW2, *db2)
+
+
+def decode_forward_shapes(anchors):
+    m, k = anchors[3].shape[0], anchors[3].shape[1]
+    n = m * k
+    return ((n, 3), (n, 3), (n, 4), (n,), (n, 3))
+
+
+def decode(anchors, mlp, cam_center):
+    """Differentiable decode: anchors = (xyz, feat, scale, offsets); mlp =
+    (W1, b1, W2, b2) lists of 3 tensors each."""
+    W1, b1, W2, b2 = mlp
+    return DecodeFn.apply(cam_center, *anchors, *W1, *b1, *W2, *b2)

@@ -1,0 +1,140 @@
+"""GPU parity of the anchor decode (Section III-A, eq. 1-5) and of
+decode -> render -> backward -> decode-backward against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+from gpu_util import MARGINS, assert_grads, masked_weights, np_, to_dev
+from oracle import decode as odec
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _case(seed, m, k, width):
+    rng = np.random.default_rng(seed)
+    a = scenes.make_anchors(rng, m, k)
+    d = scenes.make_decoder(rng, width, k)
+    cam = np.array([6.0, 4.0, 2.0]) + rng.normal(0, 1.0, 3)
+    return a, d, cam.astype(np.float32)
+
+
+def _dev_inputs(a, d):
+    anchors = to_dev((a.xyz, a.feat, a.scale, a.offsets))
+    mlp = tuple([torch.from_numpy(x).cuda() for x in lst] for lst in (d.W1, d.b1, d.W2, d.b2))
+    return anchors, mlp
+
+
+def _untie(up, a, d, cam):
+    """Zero the upstream rows of anchors whose ReLU decision is a near tie
+    (both sides then produce exactly zero for them)."""
+    flags = odec.relu_near_ties(a.xyz, a.feat, a.scale, a.offsets, d.W1, d.b1, d.W2, d.b2, cam.astype(np.float64))
+    rows = np.repeat(flags, a.k)
+    out = []
+    for u in up:
+        u = np.array(u, np.float32, copy=True)
+        u[rows] = 0.0
+        out.append(u)
+    return out, int(flags.sum())
+
+
+@pytest.mark.parametrize("m,k,width", [(3000, 10, 64), (1000, 10, 32), (777, 3, 50), (1, 16, 128)])
+def test_decode_forward_parity(m, k, width):
+    from paper_2505_18992_amd import decode_forward
+    print(f"case decode forward m={m} k={k} width={width}", flush=True)
+    a, d, cam = _case(m + k, m, k, width)
+    anchors, mlp = _dev_inputs(a, d)
+    got = [np_(t) for t in decode_forward(anchors, mlp, cam)]
+    exp = [t.numpy() for t in odec.decode_forward(a.xyz, a.feat, a.scale, a.offsets, d.W1, d.b1, d.W2, d.b2,
+                                                  cam.astype(np.float64))]
+    for name, g, e in zip(["means", "log_scales", "quats", "opacities", "colors"], got, exp):
+        # a normalised quaternion's components err relative to the unit norm
+        np.testing.assert_allclose(g, e, rtol=1e-5, atol=1e-5 if name == "quats" else 1e-6, err_msg=name)
+
+
+@pytest.mark.parametrize("m,k,width", [(3000, 10, 64), (1000, 10, 32), (1, 16, 128)])
+def test_decode_backward_parity(m, k, width):
+    from paper_2505_18992_amd import decode_backward
+    print(f"case decode backward m={m} k={k} width={width}", flush=True)
+    a, d, cam = _case(7 * m + k, m, k, width)
+    anchors, mlp = _dev_inputs(a, d)
+    rng = np.random.default_rng(5)
+    n = m * k
+    up = [rng.standard_normal((n, 3)).astype(np.float32), rng.standard_normal((n, 3)).astype(np.float32),
+          rng.standard_normal((n, 4)).astype(np.float32), rng.standard_normal(n).astype(np.float32),
+          rng.standard_normal((n, 3)).astype(np.float32)]
+    up, n_ties = _untie(up, a, d, cam)
+    print("relu near-tie anchors", n_ties, flush=True)
+    d_feat, d_scale, d_off, (dW1, db1, dW2, db2) = decode_backward(anchors, mlp, cam, to_dev(up))
+    G = odec.decode_backward(a.xyz, a.feat, a.scale, a.offsets, d.W1, d.b1, d.W2, d.b2, cam.astype(np.float64), up)
+    pairs = [("feat", d_feat, G["feat"]), ("scale", d_scale, G["scale"]), ("offsets", d_off, G["offsets"])]
+    for h in range(3):
+        pairs += [(f"W1[{h}]", dW1[h], G["W1"][h]), (f"b1[{h}]", db1[h], G["b1"][h]),
+                  (f"W2[{h}]", dW2[h], G["W2"][h]), (f"b2[{h}]", db2[h], G["b2"][h])]
+    for name, g, e in pairs:
+        g = np_(g).astype(np.float64)
+        nrm = np.linalg.norm(g - e) / max(np.linalg.norm(e), 1e-30)
+        assert nrm <= 1e-5, (name, nrm)
+        # per element against the tensor's largest magnitude (sums of many signed terms)
+        assert np.max(np.abs(g - e)) <= 1e-4 * np.abs(e).max() + 1e-7, (name, np.max(np.abs(g - e)))
+
+
+def test_decode_autograd_matches_backward():
+    from paper_2505_18992_amd import decode, decode_backward
+    a, d, cam = _case(3, 500, 10, 64)
+    anchors, mlp = _dev_inputs(a, d)
+    feat = anchors[1].clone().requires_grad_(True)
+    W = [[t.clone().requires_grad_(True) for t in lst] for lst in mlp]
+    outs = decode((anchors[0], feat, anchors[2], anchors[3]), W, cam)
+    rng = np.random.default_rng(1)
+    ws = [torch.from_numpy(rng.standard_normal(tuple(o.shape)).astype(np.float32)).cuda() for o in outs]
+    loss = sum((o * w).sum() for o, w in zip(outs, ws))
+    loss.backward()
+    d_feat, _, _, (dW1, _, dW2, _) = decode_backward(anchors, mlp, cam, ws)
+    assert torch.allclose(feat.grad, d_feat, rtol=1e-6, atol=1e-7)
+    assert torch.allclose(W[0][2].grad, dW1[2], rtol=1e-6, atol=1e-7)
+    assert torch.allclose(W[2][1].grad, dW2[1], rtol=1e-6, atol=1e-7)
+
+
+def test_decode_render_backward_end_to_end():
+    """decode -> render -> backward -> decode backward (the mapping step of
+    the anchor representation) against the oracle's FP64 chain."""
+    from paper_2505_18992_amd import decode_backward, decode_forward, render, render_backward
+    sc = scenes.make_c3(m=4000, img=(320, 180))
+    a, d, cam = sc.anchors, sc.decoder, sc.cameras[0]
+    R = cam.world_to_cam[:, :3].astype(np.float64)
+    centre = (-R.T @ cam.world_to_cam[:, 3].astype(np.float64)).astype(np.float32)
+    print("case c3-4k end-to-end", flush=True)
+    anchors, mlp = _dev_inputs(a, d)
+    gs = decode_forward(anchors, mlp, centre)
+    outs, saved = render([gs], [cam])
+    # oracle chain on its own FP64 decode
+    o_out = [t.numpy() for t in odec.decode_forward(a.xyz, a.feat, a.scale, a.offsets, d.W1, d.b1, d.W2, d.b2,
+                                                    centre.astype(np.float64))]
+    og = scenes.GaussianSet(*o_out)
+    ref = oracle.render(og, cam, margins=MARGINS)
+    mask = ref["flags"]
+    w = masked_weights(sc.weights[0], mask)
+    G, S = oracle.grad(og, cam, *[x.astype(np.float64) for x in w])
+    grads, _ = render_backward(saved, [to_dev(w)], want_pose=False)
+    saved.close()
+    got = dict(zip(["means", "log_scales", "quats", "opacities", "colors"], [np_(t) for t in grads[0]]))
+    # the decoded Gaussians differ from the oracle's by FP32 rounding, so the
+    # render-level gradients are compared at the render gate
+    assert_grads(got, G, S, keys=["means", "log_scales", "quats", "opacities", "colors"], tol=2e-4)
+    up_gpu, _ = _untie([np_(t) for t in grads[0]], a, d, centre)
+    up_ora, _ = _untie([G[k] for k in ("means", "log_scales", "quats", "opacities", "colors")], a, d, centre)
+    d_feat, d_scale, d_off, (dW1, db1, dW2, db2) = decode_backward(anchors, mlp, centre, to_dev(up_gpu))
+    GD = odec.decode_backward(a.xyz, a.feat, a.scale, a.offsets, d.W1, d.b1, d.W2, d.b2, centre.astype(np.float64),
+                              [x.astype(np.float64) for x in up_ora])
+    for name, g, e in (("feat", d_feat, GD["feat"]), ("W2[2]", dW2[2], GD["W2"][2]), ("W1[0]", dW1[0], GD["W1"][0])):
+        g = np_(g).astype(np.float64)
+        nrm = np.linalg.norm(g - e) / max(np.linalg.norm(e), 1e-30)
+        assert nrm <= 1e-3, (name, nrm)
