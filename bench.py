@@ -105,7 +105,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c4-1200")
-    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--tile", default="auto", help="WxH or auto (the window's search)")
+    ap.add_argument("--persistent", type=int, default=-1, help="-1 search, 0 off, >0 workgroups")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -114,12 +115,11 @@ def main():
         return 2
 
     import torch
-    from paper_2505_18992_amd import _lib, get_context, render, render_backward
+    from paper_2505_18992_amd import RenderWindow, _lib, get_context, render, render_backward
 
     _lib.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    tw, th = (int(x) for x in args.tile.split("x"))
     log(f"[bench] building workload {args.workload}")
     sc, desc = workload(args.workload)
     sets = [tuple(torch.from_numpy(a).to(dev) for a in g.arrays()) for g in sc.sets]
@@ -128,49 +128,79 @@ def main():
     nv = len(cams)
     n_gauss = sum(g.n for g in sc.sets)
     ctx = get_context(0)
+    tile = None if args.tile == "auto" else tuple(int(x) for x in args.tile.split("x"))
 
-    cap = 0
-
-    def step(capacity):
-        outs, saved = render(sets, cams, vset, tile=(tw, th), pair_capacity=capacity)
-        render_backward(saved, gw)
-        return saved
-
-    # first call sizes the pair list; later calls run with a fixed capacity (no host sync)
-    saved = step(0)
-    st = saved.stats()
-    saved.close()
-    cap = int(math.ceil(st["n_pairs"] * 1.02)) + 1024
-    log(f"[bench] pairs={st['n_pairs']} blended={st['n_blended']} evaluated={st['n_evaluated']} capacity={cap}")
+    # the mapping-window launch: all views bound, tuned, captured in HIP graphs
+    t0 = time.perf_counter()
+    win = RenderWindow(sets, cams, vset, tile=tile, persistent=args.persistent, use_graph=True)
+    cfg = win.config()
+    log(f"[bench] window ready in {time.perf_counter() - t0:.1f} s: tile {cfg['tile_w']}x{cfg['tile_h']}, "
+        f"persistent {cfg['persistent']}, pair capacity {cfg['pair_capacity']}")
+    for v in range(nv):
+        for dst, src in zip(win.grad_out[v], gw[v]):
+            dst.copy_(src)
     for _ in range(args.warmup):
-        step(cap).close()
+        win.run()
     torch.cuda.synchronize()
 
-    # timed region
+    # timed region: K whole steps (forward + backward of every view)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(cap).close()
+        win.run()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
-    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step")
-
-    # per-stage HIP-event timing over a second pass of the same steps
-    ctx.profile(True)
-    saved = None
-    for _ in range(args.steps):
-        if saved is not None:
-            saved.close()
-        saved = step(cap)
-    torch.cuda.synchronize()
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    st = saved.stats()
-    saved.close()
+    st = win.stats()
     if st["overflow"]:
         raise SystemExit("pair capacity overflow in the timed pass")
+    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step")
+
+    # per-stage HIP-event timing: the same configuration launched without the
+    # graph (events recorded on the launch stream around every stage)
+    twin = RenderWindow(sets, cams, vset, tile=(cfg["tile_w"], cfg["tile_h"]), persistent=cfg["persistent"],
+                        use_graph=False, pair_capacity=cfg["pair_capacity"])
+    for v in range(nv):
+        for dst, src in zip(twin.grad_out[v], gw[v]):
+            dst.copy_(src)
+    twin.run()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        twin.run()
+    torch.cuda.synchronize()
+    ms_eager_window = (time.perf_counter() - t0) * 1e3 / args.steps
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    twin.close()
     stage_ms = {k: v[1] / max(v[0], 1) for k, v in prof.items() if v[0] > 0}
+    # fills run in both halves: per step, not per launch sequence
+    if "fill" in prof:
+        stage_ms["fill"] = prof["fill"][1] / args.steps
     log("[bench] stage ms/step: " + ", ".join(f"{k}={v:.3f}" for k, v in sorted(stage_ms.items(), key=lambda x: -x[1])))
+
+    # one view per launch: the same kernels, each view its own forward+backward call
+    per_view_caps = []
+    for v in range(nv):
+        outs, saved = render([sets[vset[v]]], [cams[v]], [0], tile=(cfg["tile_w"], cfg["tile_h"]))
+        per_view_caps.append(int(saved.stats()["n_pairs"] * 1.25) + 4096)
+        saved.close()
+    def one_view_pass():
+        for v in range(nv):
+            outs, saved = render([sets[vset[v]]], [cams[v]], [0], tile=(cfg["tile_w"], cfg["tile_h"]),
+                                 pair_capacity=per_view_caps[v])
+            render_backward(saved, [gw[v]])
+            saved.close()
+    one_view_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = max(2, args.steps // 4)
+    for _ in range(reps):
+        one_view_pass()
+    torch.cuda.synchronize()
+    ms_per_view_launch = (time.perf_counter() - t0) * 1e3 / reps
+    log(f"[bench] one view per launch: {ms_per_view_launch:.3f} ms for {nv} views; "
+        f"eager window {ms_eager_window:.3f} ms")
 
     E, B, P = st["n_evaluated"], st["n_blended"], st["n_pairs"]
     dom = max(stage_ms, key=stage_ms.get)
@@ -205,9 +235,13 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "gaussians": n_gauss, "views": nv,
-                   "resolutions": sorted({f"{c.width}x{c.height}" for c in cams}), "tile": args.tile},
+                   "resolutions": sorted({f"{c.width}x{c.height}" for c in cams}),
+                   "launch": "one HIP graph per forward and per backward over all views"},
         "blends_per_sec": B / (ms_step * 1e-3),
         "counts": {"pairs": P, "evaluated": E, "blended": B},
+        "window": {k: cfg[k] for k in ("tile_w", "tile_h", "persistent", "pair_capacity")},
+        "one_view_per_launch": {"ms_for_all_views": ms_per_view_launch, "views_per_sec": nv / (ms_per_view_launch * 1e-3),
+                                "batched_speedup": ms_per_view_launch / ms_step},
         "stage_ms": stage_ms,
         "roofline": roof,
     }

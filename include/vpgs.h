@@ -202,6 +202,50 @@ int vpgs_saved_export(vpgs_ctx* ctx, const vpgs_saved* saved, int what, void* ds
 
 int vpgs_saved_release(vpgs_ctx* ctx, vpgs_saved* saved);
 
+/* ---- mapping window: batched, graph-captured forward + backward ---------- */
+
+/* A window binds every buffer of a repeated multi-view forward+backward (the
+ * keyframes of a mapping window, or the views of several submaps) once, picks
+ * the tile shape and compositing mode with a timed search on the actual
+ * inputs, and captures the launch sequence of all views in two HIP graphs:
+ * the forward (projection, binning, sort, ranges, forward compositing) and
+ * the backward (backward compositing, projection backward, pose reduction).
+ * A run is one graph launch per part; the pair list has a fixed capacity (no
+ * host synchronisation), and an overflow is reported by vpgs_window_stats. */
+typedef struct {
+  int32_t tile_w, tile_h;   /* 0 = chosen by the search */
+  int32_t persistent;       /* -1 = chosen by the search; 0 = one workgroup per tile;
+                               > 0 = that many persistent workgroups on a tile queue */
+  int32_t use_graph;        /* 1 = capture in a HIP graph (default); 0 = launch eagerly */
+  int64_t pair_capacity;    /* 0 = pairs measured at creation plus 25% headroom */
+  int32_t tune_reps;        /* timed runs per candidate in the search (0 = 3) */
+  int32_t reserved;
+} vpgs_window_opts;
+
+/* Inputs and outputs as in vpgs_render_forward / vpgs_render_backward, all
+ * bound for the life of the window (host arrays are copied; the device
+ * buffers they point to must stay allocated).  opts may be NULL (full search,
+ * graph on).  Runs the search on `stream` (it overwrites the bound outputs). */
+int vpgs_window_create(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, int n_views,
+                       const int32_t* view_set, const vpgs_camera* cams, const vpgs_images* out,
+                       const vpgs_image_grads* grad_out, const vpgs_gauss_grads* grads, float* d_pose,
+                       const vpgs_window_opts* opts, vpgs_window** win, void* stream);
+/* New poses and intrinsics for the bound views (image sizes must not change);
+ * takes effect at the next run. */
+int vpgs_window_set_cameras(vpgs_window* win, const vpgs_camera* cams);
+/* parts = 1: forward of every view; 2: backward (uses the upstream planes
+ * as they are when it runs, so a loss gradient can be computed between the
+ * two); 3: both.  Each part is one graph launch on `stream`. */
+#define VPGS_WINDOW_FORWARD 1
+#define VPGS_WINDOW_BACKWARD 2
+int vpgs_window_run(vpgs_window* win, int parts, void* stream);
+/* Synchronise and read the counters of the last run (VPGS_ECAPACITY on
+ * overflow: grow pair_capacity and recreate the window). */
+int vpgs_window_stats(vpgs_window* win, vpgs_stats* out, void* stream);
+/* The configuration the window runs with. */
+int vpgs_window_config(const vpgs_window* win, vpgs_window_opts* out);
+int vpgs_window_destroy(vpgs_window* win);
+
 /* ---- stage timing (diagnostics) ------------------------------------------ */
 
 /* When enabled, every launch sequence of the context records a pair of HIP

@@ -23,6 +23,7 @@ VPGS_EUNSUPPORTED = -5
 MAX_VIEWS = 64
 MAX_SETS = 64
 NUM_STAGES = 12
+WINDOW_FORWARD, WINDOW_BACKWARD = 1, 2
 
 BUF_PROJ, BUF_EXTENT, BUF_COUNT, BUF_KEYS, BUF_VALUES, BUF_RANGES, BUF_TFINAL, BUF_NCONTRIB, BUF_GRADACC = range(1, 10)
 
@@ -63,6 +64,12 @@ class Stats(ctypes.Structure):
                 ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class WindowOpts(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("pair_capacity", ctypes.c_int64), ("tune_reps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class Anchors(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("k", ctypes.c_int32), ("reserved", ctypes.c_int32), ("xyz", c_void_p),
                 ("feat", c_void_p), ("scale", c_void_p), ("offsets", c_void_p)]
@@ -94,6 +101,16 @@ SIGNATURES = {
     "vpgs_saved_export": (ctypes.c_int, [c_void_p, c_void_p, ctypes.c_int, c_void_p, ctypes.c_size_t,
                                          ctypes.POINTER(ctypes.c_size_t), c_void_p]),
     "vpgs_saved_release": (ctypes.c_int, [c_void_p, c_void_p]),
+    "vpgs_window_create": (ctypes.c_int, [c_void_p, ctypes.c_int, ctypes.POINTER(Gaussians), ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Camera),
+                                          ctypes.POINTER(Images), ctypes.POINTER(ImageGrads),
+                                          ctypes.POINTER(GaussBuffers), c_void_p, ctypes.POINTER(WindowOpts),
+                                          ctypes.POINTER(c_void_p), c_void_p]),
+    "vpgs_window_set_cameras": (ctypes.c_int, [c_void_p, ctypes.POINTER(Camera)]),
+    "vpgs_window_run": (ctypes.c_int, [c_void_p, ctypes.c_int, c_void_p]),
+    "vpgs_window_stats": (ctypes.c_int, [c_void_p, ctypes.POINTER(Stats), c_void_p]),
+    "vpgs_window_config": (ctypes.c_int, [c_void_p, ctypes.POINTER(WindowOpts)]),
+    "vpgs_window_destroy": (ctypes.c_int, [c_void_p]),
     "vpgs_profile_enable": (ctypes.c_int, [c_void_p, ctypes.c_int]),
     "vpgs_profile_read": (ctypes.c_int, [c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),

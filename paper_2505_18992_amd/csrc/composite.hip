@@ -46,13 +46,20 @@ __device__ __forceinline__ Falloff falloff(const float4 A, const float4 B, float
 }
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
-    const CallTables* __restrict__ tab, const float4* __restrict__ pa, const float4* __restrict__ pb,
-    const float4* __restrict__ pc, const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
-    float* __restrict__ T_final, uint32_t* __restrict__ n_contrib, Counters* __restrict__ cnt) {
+struct FwdShared {
+  float4 A[TW * TH], B[TW * TH], C[TW * TH];
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab, const float4* __restrict__ pa,
+                                             const float4* __restrict__ pb, const float4* __restrict__ pc,
+                                             const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
+                                             float* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
+                                             uint32_t tile, FwdShared<TW, TH>& sh, uint32_t& ne, uint32_t& nb) {
   constexpr int BS = TW * TH;
-  __shared__ float4 sA[BS], sB[BS], sC[BS];
-  const uint32_t tile = blockIdx.x;
+  float4* sA = sh.A;
+  float4* sB = sh.B;
+  float4* sC = sh.C;
   const ViewDesc& V = tab->views[view_of_tile(tab, tile)];
   const uint32_t lt = tile - V.tile_base;
   const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
@@ -62,7 +69,7 @@ __global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
   const uint2 rg = ranges[tile];
 
   float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
-  uint32_t last = 0, ne = 0, nb = 0;
+  uint32_t last = 0;
   bool done = !inside;
 
   for (uint32_t start = rg.x; start < rg.y; start += BS) {
@@ -105,7 +112,10 @@ __global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
     T_final[V.pix_base + pix] = T;
     n_contrib[V.pix_base + pix] = last;
   }
-  // evaluation and blend counters: wave sums, one atomic per wave
+}
+
+// Evaluation and blend counters: wave sums, one atomic per wave.
+__device__ __forceinline__ void flush_counts(uint32_t ne, uint32_t nb, Counters* cnt) {
   unsigned long long e = ne, b = nb;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -118,6 +128,36 @@ __global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
   }
 }
 
+// Next tile of a persistent workgroup: thread 0 takes a ticket from the
+// queue counter and broadcasts it through LDS.
+__device__ __forceinline__ uint32_t next_tile(uint32_t* queue, uint32_t* slot) {
+  __syncthreads();
+  if (threadIdx.x == 0) *slot = atomicAdd(queue, 1u);
+  __syncthreads();
+  return *slot;
+}
+
+// One workgroup per tile (grid = tiles), or, when queue is non-NULL, a
+// persistent grid whose workgroups take tiles from the queue until it runs
+// past the last tile.
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
+    const CallTables* __restrict__ tab, const float4* __restrict__ pa, const float4* __restrict__ pb,
+    const float4* __restrict__ pc, const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    float* __restrict__ T_final, uint32_t* __restrict__ n_contrib, Counters* __restrict__ cnt,
+    uint32_t* __restrict__ queue, uint32_t n_tiles) {
+  __shared__ FwdShared<TW, TH> sh;
+  __shared__ uint32_t slot;
+  uint32_t ne = 0, nb = 0;
+  if (queue == nullptr) {
+    forward_tile<TW, TH>(tab, pa, pb, pc, ranges, vals, T_final, n_contrib, blockIdx.x, sh, ne, nb);
+  } else {
+    for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot))
+      forward_tile<TW, TH>(tab, pa, pb, pc, ranges, vals, T_final, n_contrib, t, sh, ne, nb);
+  }
+  flush_counts(ne, nb, cnt);
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -125,15 +165,25 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
-    const CallTables* __restrict__ tab, const float4* __restrict__ pa, const float4* __restrict__ pb,
-    const float4* __restrict__ pc, const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
-    const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib, float* __restrict__ acc) {
+struct BwdShared {
+  float4 A[TW * TH], B[TW * TH], C[TW * TH];
+  uint32_t rec[TW * TH];
+  uint32_t maxlast[(TW * TH) / 64];
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab, const float4* __restrict__ pa,
+                                              const float4* __restrict__ pb, const float4* __restrict__ pc,
+                                              const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
+                                              const float* __restrict__ T_final,
+                                              const uint32_t* __restrict__ n_contrib, float* __restrict__ acc,
+                                              uint32_t tile, BwdShared<TW, TH>& sh) {
   constexpr int BS = TW * TH;
-  __shared__ float4 sA[BS], sB[BS], sC[BS];
-  __shared__ uint32_t sRec[BS];
-  __shared__ uint32_t smax[BS / 64];
-  const uint32_t tile = blockIdx.x;
+  float4* sA = sh.A;
+  float4* sB = sh.B;
+  float4* sC = sh.C;
+  uint32_t* sRec = sh.rec;
+  uint32_t* smax = sh.maxlast;
   const ViewDesc& V = tab->views[view_of_tile(tab, tile)];
   const uint32_t lt = tile - V.tile_base;
   const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
@@ -223,19 +273,38 @@ __global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
 }
 
 template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
+    const CallTables* __restrict__ tab, const float4* __restrict__ pa, const float4* __restrict__ pb,
+    const float4* __restrict__ pc, const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib, float* __restrict__ acc,
+    uint32_t* __restrict__ queue, uint32_t n_tiles) {
+  __shared__ BwdShared<TW, TH> sh;
+  __shared__ uint32_t slot;
+  if (queue == nullptr) {
+    backward_tile<TW, TH>(tab, pa, pb, pc, ranges, vals, T_final, n_contrib, acc, blockIdx.x, sh);
+  } else {
+    for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot))
+      backward_tile<TW, TH>(tab, pa, pb, pc, ranges, vals, T_final, n_contrib, acc, t, sh);
+  }
+}
+
+template <int TW, int TH>
 hipError_t launch_fwd_t(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb, const uint2* ranges,
-                        const uint32_t* vals, float* T_final, uint32_t* n_contrib, Counters* cnt, hipStream_t s) {
-  hipLaunchKernelGGL((composite_forward_kernel<TW, TH>), dim3(h.n_tiles), dim3(TW * TH), 0, s, d_tab, pb.a, pb.b,
-                     pb.c, ranges, vals, T_final, n_contrib, cnt);
+                        const uint32_t* vals, float* T_final, uint32_t* n_contrib, Counters* cnt, uint32_t* queue,
+                        uint32_t blocks, hipStream_t s) {
+  const uint32_t grid = queue ? blocks : h.n_tiles;
+  hipLaunchKernelGGL((composite_forward_kernel<TW, TH>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.a, pb.b, pb.c,
+                     ranges, vals, T_final, n_contrib, cnt, queue, h.n_tiles);
   return hipGetLastError();
 }
 
 template <int TW, int TH>
 hipError_t launch_bwd_t(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb, const uint2* ranges,
                         const uint32_t* vals, const float* T_final, const uint32_t* n_contrib, float* acc,
-                        hipStream_t s) {
-  hipLaunchKernelGGL((composite_backward_kernel<TW, TH>), dim3(h.n_tiles), dim3(TW * TH), 0, s, d_tab, pb.a, pb.b,
-                     pb.c, ranges, vals, T_final, n_contrib, acc);
+                        uint32_t* queue, uint32_t blocks, hipStream_t s) {
+  const uint32_t grid = queue ? blocks : h.n_tiles;
+  hipLaunchKernelGGL((composite_backward_kernel<TW, TH>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.a, pb.b, pb.c,
+                     ranges, vals, T_final, n_contrib, acc, queue, h.n_tiles);
   return hipGetLastError();
 }
 
@@ -247,23 +316,27 @@ bool tile_shape_supported(int tw, int th) {
 
 hipError_t launch_composite_forward(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb,
                                     const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,
-                                    Counters* cnt, int tile_w, int tile_h, hipStream_t s) {
+                                    Counters* cnt, int tile_w, int tile_h, uint32_t* queue, uint32_t blocks,
+                                    hipStream_t s) {
   if (h.n_tiles == 0) return hipSuccess;
-  if (tile_w == 16 && tile_h == 16) return launch_fwd_t<16, 16>(d_tab, h, pb, ranges, vals, T_final, n_contrib, cnt, s);
-  if (tile_w == 16 && tile_h == 8) return launch_fwd_t<16, 8>(d_tab, h, pb, ranges, vals, T_final, n_contrib, cnt, s);
-  if (tile_w == 8 && tile_h == 8) return launch_fwd_t<8, 8>(d_tab, h, pb, ranges, vals, T_final, n_contrib, cnt, s);
-  if (tile_w == 32 && tile_h == 8) return launch_fwd_t<32, 8>(d_tab, h, pb, ranges, vals, T_final, n_contrib, cnt, s);
+#define VPGS_FWD(TW, TH) \
+  if (tile_w == TW && tile_h == TH) \
+    return launch_fwd_t<TW, TH>(d_tab, h, pb, ranges, vals, T_final, n_contrib, cnt, queue, blocks, s);
+  VPGS_FWD(16, 16) VPGS_FWD(16, 8) VPGS_FWD(8, 8) VPGS_FWD(32, 8)
+#undef VPGS_FWD
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_composite_backward(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb,
                                      const uint2* ranges, const uint32_t* vals, const float* T_final,
-                                     const uint32_t* n_contrib, float* acc, int tile_w, int tile_h, hipStream_t s) {
+                                     const uint32_t* n_contrib, float* acc, int tile_w, int tile_h, uint32_t* queue,
+                                     uint32_t blocks, hipStream_t s) {
   if (h.n_tiles == 0) return hipSuccess;
-  if (tile_w == 16 && tile_h == 16) return launch_bwd_t<16, 16>(d_tab, h, pb, ranges, vals, T_final, n_contrib, acc, s);
-  if (tile_w == 16 && tile_h == 8) return launch_bwd_t<16, 8>(d_tab, h, pb, ranges, vals, T_final, n_contrib, acc, s);
-  if (tile_w == 8 && tile_h == 8) return launch_bwd_t<8, 8>(d_tab, h, pb, ranges, vals, T_final, n_contrib, acc, s);
-  if (tile_w == 32 && tile_h == 8) return launch_bwd_t<32, 8>(d_tab, h, pb, ranges, vals, T_final, n_contrib, acc, s);
+#define VPGS_BWD(TW, TH) \
+  if (tile_w == TW && tile_h == TH) \
+    return launch_bwd_t<TW, TH>(d_tab, h, pb, ranges, vals, T_final, n_contrib, acc, queue, blocks, s);
+  VPGS_BWD(16, 16) VPGS_BWD(16, 8) VPGS_BWD(8, 8) VPGS_BWD(32, 8)
+#undef VPGS_BWD
   return hipErrorInvalidValue;
 }
 

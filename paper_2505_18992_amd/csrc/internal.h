@@ -74,7 +74,9 @@ struct Counters {
   uint32_t pairs;      // pairs requested by the scan
   uint32_t overflow;   // 1 if pairs > capacity
   uint32_t visible;
-  uint32_t pad;
+  uint32_t queue_fwd;  // tile tickets of the persistent forward compositor
+  uint32_t queue_bwd;  // and of the persistent backward compositor
+  uint32_t pad[3];
 };
 
 // Per-record projected data (struct of arrays).
@@ -118,14 +120,16 @@ hipError_t launch_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint3
 hipError_t launch_ranges(const uint64_t* keys, const Counters* cnt, uint32_t capacity, uint2* ranges,
                          uint32_t n_tiles, hipStream_t s);
 
+// Compositing: one workgroup per tile, or (queue != NULL) `blocks`
+// persistent workgroups taking tiles from the zeroed counter *queue.
 hipError_t launch_composite_forward(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
                                     const uint2* ranges, const uint32_t* vals, float* T_final,
                                     uint32_t* n_contrib, Counters* cnt, int tile_w, int tile_h,
-                                    hipStream_t s);
+                                    uint32_t* queue, uint32_t blocks, hipStream_t s);
 hipError_t launch_composite_backward(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
                                      const uint2* ranges, const uint32_t* vals, const float* T_final,
                                      const uint32_t* n_contrib, float* acc, int tile_w, int tile_h,
-                                     hipStream_t s);
+                                     uint32_t* queue, uint32_t blocks, hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float value, size_t n, hipStream_t s);

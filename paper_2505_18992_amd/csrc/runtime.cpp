@@ -87,7 +87,7 @@ void free_buf(DevBuf& b) {
 
 }  // namespace vpgs
 
-namespace {
+namespace vpgs {
 
 void destroy_saved(vpgs_saved* s) {
   DevBuf* bufs[] = {&s->tab, &s->pa, &s->pb, &s->pc, &s->ext, &s->rect, &s->count, &s->offsets, &s->scan_ws,
@@ -99,13 +99,7 @@ void destroy_saved(vpgs_saved* s) {
   delete s;
 }
 
-int acquire_saved(vpgs_ctx* ctx, vpgs_saved** out) {
-  for (vpgs_saved* s : ctx->pool)
-    if (!s->in_use) {
-      s->in_use = true;
-      *out = s;
-      return VPGS_OK;
-    }
+int new_saved(vpgs_ctx* ctx, vpgs_saved** out) {
   vpgs_saved* s = new (std::nothrow) vpgs_saved();
   if (!s) return fail(ctx, VPGS_ENOMEM, "out of host memory");
   hipError_t e = hipHostMalloc((void**)&s->h_tab, sizeof(CallTables), hipHostMallocDefault);
@@ -119,6 +113,20 @@ int acquire_saved(vpgs_ctx* ctx, vpgs_saved** out) {
     return fail(ctx, VPGS_EHIP, "hipEventCreate: %s", hipGetErrorString(e));
   }
   std::memset(s->h_tab, 0, sizeof(CallTables));
+  *out = s;
+  return VPGS_OK;
+}
+
+int acquire_saved(vpgs_ctx* ctx, vpgs_saved** out) {
+  for (vpgs_saved* s : ctx->pool)
+    if (!s->in_use) {
+      s->in_use = true;
+      *out = s;
+      return VPGS_OK;
+    }
+  vpgs_saved* s = nullptr;
+  int rc = new_saved(ctx, &s);
+  if (rc) return rc;
   s->in_use = true;
   ctx->pool.push_back(s);
   *out = s;
@@ -254,7 +262,171 @@ int validate_forward(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, int 
   return VPGS_OK;
 }
 
-}  // namespace
+}  // namespace vpgs
+
+namespace vpgs {
+
+int read_pair_count(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st, uint32_t* out) {
+  Counters* cnt = static_cast<Counters*>(sv->counters.p);
+  uint32_t* hp = static_cast<uint32_t*>(ctx->h_pinned);
+  HIP_TRY(hipMemcpyAsync(hp, &cnt->pairs, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *out = *hp;
+  return VPGS_OK;
+}
+
+int prepare_front(vpgs_ctx* ctx, vpgs_saved* sv) {
+  const CallTables& T = *sv->h_tab;
+  uint64_t pixels = 0;
+  for (int v = 0; v < T.n_views; ++v) pixels += (uint64_t)T.views[v].W * T.views[v].H;
+  sv->n_pixels = (uint32_t)pixels;
+  sv->key_bits = 32 + ilog2_ceil(std::max<uint32_t>(T.n_tiles, 2u));
+  const size_t R = T.n_records;
+  int rc;
+  if ((rc = ensure(ctx, sv->tab, sizeof(CallTables))) || (rc = ensure(ctx, sv->pa, R * 16)) ||
+      (rc = ensure(ctx, sv->pb, R * 16)) || (rc = ensure(ctx, sv->pc, R * 16)) || (rc = ensure(ctx, sv->ext, R * 8)) ||
+      (rc = ensure(ctx, sv->rect, R * 8)) || (rc = ensure(ctx, sv->count, R * 4)) ||
+      (rc = ensure(ctx, sv->offsets, R * 4)) || (rc = ensure(ctx, sv->scan_ws, scan_workspace_bytes((uint32_t)R))) ||
+      (rc = ensure(ctx, sv->ranges, (size_t)T.n_tiles * 8)) || (rc = ensure(ctx, sv->tfinal, pixels * 4)) ||
+      (rc = ensure(ctx, sv->ncontrib, pixels * 4)) || (rc = ensure(ctx, sv->counters, sizeof(Counters))))
+    return rc;
+  return VPGS_OK;
+}
+
+int ensure_pairs(vpgs_ctx* ctx, vpgs_saved* sv, uint32_t cap) {
+  int rc;
+  if ((rc = ensure(ctx, sv->keys, (size_t)cap * 8)) || (rc = ensure(ctx, sv->keys_alt, (size_t)cap * 8)) ||
+      (rc = ensure(ctx, sv->vals, (size_t)cap * 4)) || (rc = ensure(ctx, sv->vals_alt, (size_t)cap * 4)) ||
+      (rc = ensure(ctx, sv->sort_ws, sort_workspace_bytes(cap))))
+    return rc;
+  sv->capacity = cap;
+  return VPGS_OK;
+}
+
+int ensure_backward(vpgs_ctx* ctx, vpgs_saved* sv) {
+  const CallTables& T = *sv->h_tab;
+  const size_t R = T.n_records;
+  const uint32_t pblocks = project_blocks(T);
+  int rc;
+  if ((rc = ensure(ctx, sv->acc, R * kNumAcc * sizeof(float))) ||
+      (rc = ensure(ctx, sv->pose_partial, (size_t)T.n_views * std::max<uint32_t>(pblocks, 1u) * 6 * sizeof(float))))
+    return rc;
+  return VPGS_OK;
+}
+
+int bind_backward(vpgs_ctx* ctx, CallTables& T, const vpgs_image_grads* grad_out, const vpgs_gauss_grads* grads) {
+  if (!grad_out || !grads) return fail(ctx, VPGS_EINVAL, "NULL argument array");
+  for (int s = 0; s < T.n_sets; ++s) {
+    const vpgs_gauss_grads& g = grads[s];
+    if (T.sets[s].n > 0 && (!g.means || !g.log_scales || !g.quats || !g.opacities || !g.colors))
+      return fail(ctx, VPGS_EINVAL, "set %d: NULL gradient pointer", s);
+    if (T.sets[s].n > 0 && !aligned16(g.quats)) return fail(ctx, VPGS_EINVAL, "set %d: d_quats must be 16-byte aligned", s);
+  }
+  for (int s = 0; s < T.n_sets; ++s) {
+    T.sets[s].d_means = grads[s].means;
+    T.sets[s].d_log_scales = grads[s].log_scales;
+    T.sets[s].d_quats = grads[s].quats;
+    T.sets[s].d_opacities = grads[s].opacities;
+    T.sets[s].d_colors = grads[s].colors;
+  }
+  for (int v = 0; v < T.n_views; ++v) {
+    T.views[v].g_rgb = grad_out[v].rgb;
+    T.views[v].g_depth = grad_out[v].depth;
+    T.views[v].g_alpha = grad_out[v].alpha;
+  }
+  return VPGS_OK;
+}
+
+int enqueue_front(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
+  const CallTables& T = *sv->h_tab;
+  const CallTables* d_tab = static_cast<const CallTables*>(sv->tab.p);
+  Counters* cnt = static_cast<Counters*>(sv->counters.p);
+  const ProjBuffers pb = proj_of(sv);
+  {
+    StageTimer t(ctx, ST_FILL, st);
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, sizeof(Counters) / 4, st));
+  }
+  {
+    StageTimer t(ctx, ST_PROJECT, st);
+    HIP_TRY(launch_project(d_tab, T, pb, sv->tile_w, sv->tile_h, st));
+  }
+  {
+    StageTimer t(ctx, ST_SCAN, st);
+    HIP_TRY(launch_scan(pb.count, static_cast<uint32_t*>(sv->offsets.p), T.n_records, &cnt->pairs, sv->scan_ws.p,
+                        st));
+  }
+  return VPGS_OK;
+}
+
+int enqueue_back(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
+  const CallTables& T = *sv->h_tab;
+  const CallTables* d_tab = static_cast<const CallTables*>(sv->tab.p);
+  Counters* cnt = static_cast<Counters*>(sv->counters.p);
+  const ProjBuffers pb = proj_of(sv);
+  const uint32_t cap = sv->capacity;
+  uint64_t* keys = static_cast<uint64_t*>(sv->keys.p);
+  uint32_t* vals = static_cast<uint32_t*>(sv->vals.p);
+  uint64_t* keys_alt = static_cast<uint64_t*>(sv->keys_alt.p);
+  uint32_t* vals_alt = static_cast<uint32_t*>(sv->vals_alt.p);
+  {
+    StageTimer t(ctx, ST_EMIT, st);
+    HIP_TRY(launch_emit(d_tab, T, pb, static_cast<const uint32_t*>(sv->offsets.p), cnt, keys, vals, cap, sv->tile_w,
+                        sv->tile_h, st));
+  }
+  {
+    StageTimer t(ctx, ST_SORT, st);
+    HIP_TRY(launch_sort(keys, vals, keys_alt, vals_alt, cap, sv->key_bits, cnt, sv->sort_ws.p, &sv->result_in_alt,
+                        st));
+  }
+  const uint64_t* skeys = sv->result_in_alt ? keys_alt : keys;
+  const uint32_t* svals = sv->result_in_alt ? vals_alt : vals;
+  {
+    StageTimer t(ctx, ST_RANGES, st);
+    HIP_TRY(launch_ranges(skeys, cnt, cap, static_cast<uint2*>(sv->ranges.p), T.n_tiles, st));
+  }
+  {
+    StageTimer t(ctx, ST_FWD, st);
+    HIP_TRY(launch_composite_forward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
+                                     static_cast<float*>(sv->tfinal.p), static_cast<uint32_t*>(sv->ncontrib.p), cnt,
+                                     sv->tile_w, sv->tile_h, sv->persistent_blocks ? &cnt->queue_fwd : nullptr,
+                                     sv->persistent_blocks, st));
+  }
+  return VPGS_OK;
+}
+
+int enqueue_backward(vpgs_ctx* ctx, vpgs_saved* sv, float* d_pose, hipStream_t st) {
+  const CallTables& T = *sv->h_tab;
+  const CallTables* d_tab = static_cast<const CallTables*>(sv->tab.p);
+  Counters* cnt = static_cast<Counters*>(sv->counters.p);
+  const ProjBuffers pb = proj_of(sv);
+  const size_t R = T.n_records;
+  float* acc = static_cast<float*>(sv->acc.p);
+  const uint32_t* svals = static_cast<const uint32_t*>(sv->result_in_alt ? sv->vals_alt.p : sv->vals.p);
+  {
+    StageTimer t(ctx, ST_FILL, st);
+    HIP_TRY(launch_fill_f32(acc, 0.0f, R * kNumAcc, st));
+    HIP_TRY(launch_fill_u32(&cnt->queue_bwd, 0u, 1, st));
+  }
+  {
+    StageTimer t(ctx, ST_BWD, st);
+    HIP_TRY(launch_composite_backward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
+                                      static_cast<const float*>(sv->tfinal.p),
+                                      static_cast<const uint32_t*>(sv->ncontrib.p), acc, sv->tile_w, sv->tile_h,
+                                      sv->persistent_blocks ? &cnt->queue_bwd : nullptr, sv->persistent_blocks, st));
+  }
+  float* partial = d_pose ? static_cast<float*>(sv->pose_partial.p) : nullptr;
+  {
+    StageTimer t(ctx, ST_PROJ_BWD, st);
+    HIP_TRY(launch_project_backward(d_tab, T, pb, acc, partial, st));
+  }
+  if (d_pose) {
+    StageTimer t(ctx, ST_POSE, st);
+    HIP_TRY(launch_pose_reduce(d_tab, T, partial, d_pose, st));
+  }
+  return VPGS_OK;
+}
+
+}  // namespace vpgs
 
 extern "C" {
 
@@ -364,81 +536,20 @@ int vpgs_render_forward(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, i
   HIP_TRY(hipEventSynchronize(sv->tab_uploaded));  // the previous upload from h_tab has completed
   rc = build_tables(ctx, *sv->h_tab, n_sets, sets, n_views, view_set, cams, out, tw, th);
   if (rc) return rc;
-  const CallTables& T = *sv->h_tab;
   sv->tile_w = tw;
   sv->tile_h = th;
-  uint64_t pixels = 0;
-  for (int v = 0; v < n_views; ++v) pixels += (uint64_t)T.views[v].W * T.views[v].H;
-  sv->n_pixels = (uint32_t)pixels;
-  const size_t R = T.n_records;
-
-  if ((rc = ensure(ctx, sv->tab, sizeof(CallTables))) || (rc = ensure(ctx, sv->pa, R * 16)) ||
-      (rc = ensure(ctx, sv->pb, R * 16)) || (rc = ensure(ctx, sv->pc, R * 16)) || (rc = ensure(ctx, sv->ext, R * 8)) ||
-      (rc = ensure(ctx, sv->rect, R * 8)) || (rc = ensure(ctx, sv->count, R * 4)) ||
-      (rc = ensure(ctx, sv->offsets, R * 4)) || (rc = ensure(ctx, sv->scan_ws, scan_workspace_bytes((uint32_t)R))) ||
-      (rc = ensure(ctx, sv->ranges, (size_t)T.n_tiles * 8)) || (rc = ensure(ctx, sv->tfinal, pixels * 4)) ||
-      (rc = ensure(ctx, sv->ncontrib, pixels * 4)) || (rc = ensure(ctx, sv->counters, sizeof(Counters))))
+  sv->persistent_blocks = 0;
+  if ((rc = prepare_front(ctx, sv)) || (rc = upload_tables(ctx, sv, st)) || (rc = enqueue_front(ctx, sv, st)))
     return rc;
-
-  rc = upload_tables(ctx, sv, st);
-  if (rc) return rc;
-  const CallTables* d_tab = static_cast<const CallTables*>(sv->tab.p);
-  Counters* cnt = static_cast<Counters*>(sv->counters.p);
-  const ProjBuffers pb = proj_of(sv);
-
-  {
-    StageTimer t(ctx, ST_FILL, st);
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, sizeof(Counters) / 4, st));
-  }
-  {
-    StageTimer t(ctx, ST_PROJECT, st);
-    HIP_TRY(launch_project(d_tab, T, pb, tw, th, st));
-  }
-  {
-    StageTimer t(ctx, ST_SCAN, st);
-    HIP_TRY(launch_scan(pb.count, static_cast<uint32_t*>(sv->offsets.p), (uint32_t)R, &cnt->pairs, sv->scan_ws.p, st));
-  }
-
   uint32_t cap;
   if (fixed_cap > 0) {
     cap = (uint32_t)fixed_cap;
   } else {
-    uint32_t* hp = static_cast<uint32_t*>(ctx->h_pinned);
-    HIP_TRY(hipMemcpyAsync(hp, &cnt->pairs, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    cap = std::max<uint32_t>(*hp, 1u);
+    rc = read_pair_count(ctx, sv, st, &cap);
+    if (rc) return rc;
+    cap = std::max<uint32_t>(cap, 1u);
   }
-  if ((rc = ensure(ctx, sv->keys, (size_t)cap * 8)) || (rc = ensure(ctx, sv->keys_alt, (size_t)cap * 8)) ||
-      (rc = ensure(ctx, sv->vals, (size_t)cap * 4)) || (rc = ensure(ctx, sv->vals_alt, (size_t)cap * 4)) ||
-      (rc = ensure(ctx, sv->sort_ws, sort_workspace_bytes(cap))))
-    return rc;
-  sv->capacity = cap;
-
-  uint64_t* keys = static_cast<uint64_t*>(sv->keys.p);
-  uint32_t* vals = static_cast<uint32_t*>(sv->vals.p);
-  uint64_t* keys_alt = static_cast<uint64_t*>(sv->keys_alt.p);
-  uint32_t* vals_alt = static_cast<uint32_t*>(sv->vals_alt.p);
-  {
-    StageTimer t(ctx, ST_EMIT, st);
-    HIP_TRY(launch_emit(d_tab, T, pb, static_cast<const uint32_t*>(sv->offsets.p), cnt, keys, vals, cap, tw, th, st));
-  }
-  const int key_bits = 32 + ilog2_ceil(std::max<uint32_t>(T.n_tiles, 2u));
-  {
-    StageTimer t(ctx, ST_SORT, st);
-    HIP_TRY(launch_sort(keys, vals, keys_alt, vals_alt, cap, key_bits, cnt, sv->sort_ws.p, &sv->result_in_alt, st));
-  }
-  const uint64_t* skeys = sv->result_in_alt ? keys_alt : keys;
-  const uint32_t* svals = sv->result_in_alt ? vals_alt : vals;
-  {
-    StageTimer t(ctx, ST_RANGES, st);
-    HIP_TRY(launch_ranges(skeys, cnt, cap, static_cast<uint2*>(sv->ranges.p), T.n_tiles, st));
-  }
-  {
-    StageTimer t(ctx, ST_FWD, st);
-    HIP_TRY(launch_composite_forward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
-                                     static_cast<float*>(sv->tfinal.p), static_cast<uint32_t*>(sv->ncontrib.p), cnt,
-                                     tw, th, st));
-  }
+  if ((rc = ensure_pairs(ctx, sv, cap)) || (rc = enqueue_back(ctx, sv, st))) return rc;
   if (saved) {
     rel.keep = true;
     *saved = sv;
@@ -454,60 +565,14 @@ int vpgs_render_backward(vpgs_ctx* ctx, const vpgs_saved* saved_c, const vpgs_im
   bool known = false;
   for (vpgs_saved* s : ctx->pool) known = known || s == sv;
   if (!known) return fail(ctx, VPGS_EINVAL, "saved-state handle of another context");
-  if (!grad_out || !grads) return fail(ctx, VPGS_EINVAL, "NULL argument array");
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(hipSetDevice(ctx->device));
   HIP_TRY(hipEventSynchronize(sv->tab_uploaded));
-  CallTables& T = *sv->h_tab;
-  for (int s = 0; s < T.n_sets; ++s) {
-    const vpgs_gauss_grads& g = grads[s];
-    if (T.sets[s].n > 0 && (!g.means || !g.log_scales || !g.quats || !g.opacities || !g.colors))
-      return fail(ctx, VPGS_EINVAL, "set %d: NULL gradient pointer", s);
-    if (T.sets[s].n > 0 && !aligned16(g.quats)) return fail(ctx, VPGS_EINVAL, "set %d: d_quats must be 16-byte aligned", s);
-  }
-  for (int s = 0; s < T.n_sets; ++s) {
-    T.sets[s].d_means = grads[s].means;
-    T.sets[s].d_log_scales = grads[s].log_scales;
-    T.sets[s].d_quats = grads[s].quats;
-    T.sets[s].d_opacities = grads[s].opacities;
-    T.sets[s].d_colors = grads[s].colors;
-  }
-  for (int v = 0; v < T.n_views; ++v) {
-    T.views[v].g_rgb = grad_out[v].rgb;
-    T.views[v].g_depth = grad_out[v].depth;
-    T.views[v].g_alpha = grad_out[v].alpha;
-  }
-  const size_t R = T.n_records;
-  const uint32_t pblocks = project_blocks(T);
-  int rc;
-  if ((rc = ensure(ctx, sv->acc, R * kNumAcc * sizeof(float))) ||
-      (rc = ensure(ctx, sv->pose_partial, (size_t)T.n_views * std::max<uint32_t>(pblocks, 1u) * 6 * sizeof(float))))
-    return rc;
-  rc = upload_tables(ctx, sv, st);
+  int rc = bind_backward(ctx, *sv->h_tab, grad_out, grads);
   if (rc) return rc;
-  const CallTables* d_tab = static_cast<const CallTables*>(sv->tab.p);
-  const ProjBuffers pb = proj_of(sv);
-  float* acc = static_cast<float*>(sv->acc.p);
-  const uint32_t* svals = static_cast<const uint32_t*>(sv->result_in_alt ? sv->vals_alt.p : sv->vals.p);
-  {
-    StageTimer t(ctx, ST_FILL, st);
-    HIP_TRY(launch_fill_f32(acc, 0.0f, R * kNumAcc, st));
-  }
-  {
-    StageTimer t(ctx, ST_BWD, st);
-    HIP_TRY(launch_composite_backward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
-                                      static_cast<const float*>(sv->tfinal.p),
-                                      static_cast<const uint32_t*>(sv->ncontrib.p), acc, sv->tile_w, sv->tile_h, st));
-  }
-  float* partial = d_pose ? static_cast<float*>(sv->pose_partial.p) : nullptr;
-  {
-    StageTimer t(ctx, ST_PROJ_BWD, st);
-    HIP_TRY(launch_project_backward(d_tab, T, pb, acc, partial, st));
-  }
-  if (d_pose) {
-    StageTimer t(ctx, ST_POSE, st);
-    HIP_TRY(launch_pose_reduce(d_tab, T, partial, d_pose, st));
-  }
+  if ((rc = ensure_backward(ctx, sv)) || (rc = upload_tables(ctx, sv, st)) ||
+      (rc = enqueue_backward(ctx, sv, d_pose, st)))
+    return rc;
   return VPGS_OK;
 }
 

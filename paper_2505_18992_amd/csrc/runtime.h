@@ -33,6 +33,8 @@ struct vpgs_saved {
       tfinal, ncontrib, counters, acc, pose_partial;
   int result_in_alt = 0;
   int tile_w = 16, tile_h = 16;
+  int key_bits = 48;
+  uint32_t persistent_blocks = 0;  // 0: one compositing workgroup per tile
   uint32_t capacity = 0;
   uint32_t n_pixels = 0;
   bool in_use = false;
@@ -61,6 +63,24 @@ int fail(vpgs_ctx* ctx, int code, const char* fmt, ...);
 // Grows b to at least `bytes` (hipFree + hipMalloc; contents are not kept).
 int ensure(vpgs_ctx* ctx, DevBuf& b, size_t bytes);
 void free_buf(DevBuf& b);
+
+// Forward/backward pipeline of one call, shared by the eager entry points
+// and the captured window.  The host call tables must be built first.
+int build_tables(vpgs_ctx* ctx, CallTables& T, int n_sets, const vpgs_gaussians* sets, int n_views,
+                 const int32_t* view_set, const vpgs_camera* cams, const vpgs_images* out, int tw, int th);
+int validate_forward(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, int n_views, const int32_t* view_set,
+                     const vpgs_camera* cams, const vpgs_images* out, const vpgs_render_opts* opts);
+int bind_backward(vpgs_ctx* ctx, CallTables& T, const vpgs_image_grads* grad_out, const vpgs_gauss_grads* grads);
+int upload_tables(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st);
+int prepare_front(vpgs_ctx* ctx, vpgs_saved* sv);
+int ensure_pairs(vpgs_ctx* ctx, vpgs_saved* sv, uint32_t cap);
+int ensure_backward(vpgs_ctx* ctx, vpgs_saved* sv);
+int read_pair_count(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st, uint32_t* out);
+int enqueue_front(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st);
+int enqueue_back(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st);
+int enqueue_backward(vpgs_ctx* ctx, vpgs_saved* sv, float* d_pose, hipStream_t st);
+int new_saved(vpgs_ctx* ctx, vpgs_saved** out);
+void destroy_saved(vpgs_saved* s);
 
 // Records a HIP event pair around one stage when profiling is on.
 struct StageTimer {

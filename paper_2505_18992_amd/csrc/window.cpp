@@ -1,0 +1,282 @@
+// window.cpp -- the mapping window: every view's forward and backward bound
+// once, tuned once, captured in one HIP graph and replayed per iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace vpgs;
+
+struct vpgs_window {
+  vpgs_ctx* ctx = nullptr;
+  vpgs_saved* sv = nullptr;  // buffers owned by the window
+  std::vector<vpgs_gaussians> sets;
+  std::vector<int32_t> view_set;
+  std::vector<vpgs_camera> cams;
+  std::vector<vpgs_images> out;
+  std::vector<vpgs_image_grads> grad_out;
+  std::vector<vpgs_gauss_grads> grads;
+  float* d_pose = nullptr;
+  vpgs_window_opts cfg{};
+  bool cams_dirty = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};       // forward, backward
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+const int kShapes[][2] = {{16, 16}, {16, 8}, {8, 8}, {32, 8}};
+
+int configure(vpgs_window* w, int tw, int th) {
+  vpgs_ctx* ctx = w->ctx;
+  vpgs_saved* sv = w->sv;
+  HIP_TRY(hipEventSynchronize(sv->tab_uploaded));
+  int rc = build_tables(ctx, *sv->h_tab, (int)w->sets.size(), w->sets.data(), (int)w->view_set.size(),
+                        w->view_set.data(), w->cams.data(), w->out.data(), tw, th);
+  if (rc) return rc;
+  rc = bind_backward(ctx, *sv->h_tab, w->grad_out.data(), w->grads.data());
+  if (rc) return rc;
+  sv->tile_w = tw;
+  sv->tile_h = th;
+  return prepare_front(ctx, sv);
+}
+
+// The window's launch sequence without a graph: part 1 = forward, 2 = backward.
+int enqueue_part(vpgs_window* w, int part, hipStream_t st) {
+  int rc;
+  if (part == 1) {
+    if ((rc = enqueue_front(w->ctx, w->sv, st)) || (rc = enqueue_back(w->ctx, w->sv, st))) return rc;
+    return VPGS_OK;
+  }
+  return enqueue_backward(w->ctx, w->sv, w->d_pose, st);
+}
+
+int enqueue_all(vpgs_window* w, hipStream_t st) {
+  int rc = enqueue_part(w, 1, st);
+  return rc ? rc : enqueue_part(w, 2, st);
+}
+
+// Sizes the pair list for the current tile shape: one eager front half and a
+// read of the pair count.
+int size_pairs(vpgs_window* w, hipStream_t st, int64_t fixed) {
+  vpgs_ctx* ctx = w->ctx;
+  int rc = upload_tables(ctx, w->sv, st);
+  if (rc) return rc;
+  uint32_t cap = 0;
+  if (fixed > 0) {
+    cap = (uint32_t)fixed;
+  } else {
+    if ((rc = enqueue_front(ctx, w->sv, st)) || (rc = read_pair_count(ctx, w->sv, st, &cap))) return rc;
+    cap = (uint32_t)std::min<uint64_t>((uint64_t)cap + cap / 4 + 4096, 0x7fffffffull);
+  }
+  if ((rc = ensure_pairs(ctx, w->sv, cap)) || (rc = ensure_backward(ctx, w->sv))) return rc;
+  return VPGS_OK;
+}
+
+int time_config(vpgs_window* w, hipStream_t st, int reps, float* ms) {
+  vpgs_ctx* ctx = w->ctx;
+  hipEvent_t a, b;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  int rc = enqueue_all(w, st);  // warm-up
+  float best = 1e30f;
+  for (int r = 0; r < reps && rc == 0; ++r) {
+    (void)hipEventRecord(a, st);
+    rc = enqueue_all(w, st);
+    (void)hipEventRecord(b, st);
+    if (rc == 0 && hipEventSynchronize(b) == hipSuccess) {
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, a, b);
+      best = std::min(best, t);
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *ms = best;
+  return rc;
+}
+
+int capture(vpgs_window* w) {
+  vpgs_ctx* ctx = w->ctx;
+  if (!w->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&w->cap_stream, hipStreamNonBlocking));
+  for (int part = 1; part <= 2; ++part) {
+    const bool prof = ctx->profiling;
+    ctx->profiling = false;  // no event records inside the graph
+    HIP_TRY(hipStreamBeginCapture(w->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_part(w, part, w->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(w->cap_stream, &g);
+    ctx->profiling = prof;
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(ctx, VPGS_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    w->graph[part - 1] = g;
+    HIP_TRY(hipGraphInstantiate(&w->exec[part - 1], g, nullptr, nullptr, 0));
+  }
+  return VPGS_OK;
+}
+
+void release(vpgs_window* w) {
+  for (int i = 0; i < 2; ++i) {
+    if (w->exec[i]) (void)hipGraphExecDestroy(w->exec[i]);
+    if (w->graph[i]) (void)hipGraphDestroy(w->graph[i]);
+  }
+  if (w->cap_stream) (void)hipStreamDestroy(w->cap_stream);
+  if (w->sv) destroy_saved(w->sv);
+  delete w;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vpgs_window_create(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, int n_views, const int32_t* view_set,
+                       const vpgs_camera* cams, const vpgs_images* out, const vpgs_image_grads* grad_out,
+                       const vpgs_gauss_grads* grads, float* d_pose, const vpgs_window_opts* opts, vpgs_window** win,
+                       void* stream) {
+  if (!ctx) return VPGS_EINVAL;
+  if (!win) return fail(ctx, VPGS_EINVAL, "NULL window pointer");
+  *win = nullptr;
+  vpgs_window_opts o{};
+  o.persistent = -1;
+  o.use_graph = 1;
+  if (opts) o = *opts;
+  if (o.tune_reps <= 0) o.tune_reps = 3;
+  if ((o.tile_w != 0 || o.tile_h != 0) && !tile_shape_supported(o.tile_w, o.tile_h))
+    return fail(ctx, VPGS_EUNSUPPORTED, "tile shape %dx%d not built", o.tile_w, o.tile_h);
+  if (o.pair_capacity < 0 || o.pair_capacity > 0x7fffffffLL) return fail(ctx, VPGS_EINVAL, "pair_capacity out of range");
+  vpgs_render_opts ro{};
+  ro.tile_w = o.tile_w;
+  ro.tile_h = o.tile_h;
+  int rc = validate_forward(ctx, n_sets, sets, n_views, view_set, cams, out, &ro);
+  if (rc) return rc;
+  if (!grad_out || !grads) return fail(ctx, VPGS_EINVAL, "NULL gradient arrays");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(ctx->device));
+
+  vpgs_window* w = new (std::nothrow) vpgs_window();
+  if (!w) return fail(ctx, VPGS_ENOMEM, "out of host memory");
+  w->ctx = ctx;
+  w->sets.assign(sets, sets + n_sets);
+  w->view_set.assign(view_set, view_set + n_views);
+  w->cams.assign(cams, cams + n_views);
+  w->out.assign(out, out + n_views);
+  w->grad_out.assign(grad_out, grad_out + n_views);
+  w->grads.assign(grads, grads + n_sets);
+  w->d_pose = d_pose;
+  rc = new_saved(ctx, &w->sv);
+  if (rc) { release(w); return rc; }
+  w->sv->in_use = true;
+
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+  // candidates of the search
+  std::vector<std::pair<int, int>> shapes;
+  if (o.tile_w && o.tile_h) shapes.push_back({o.tile_w, o.tile_h});
+  else for (auto& s : kShapes) shapes.push_back({s[0], s[1]});
+  std::vector<int> modes;
+  if (o.persistent >= 0) modes.push_back(o.persistent);
+  else { modes.push_back(0); modes.push_back(4 * cus); }
+
+  float best_ms = 1e30f;
+  int best_tw = shapes[0].first, best_th = shapes[0].second, best_mode = modes[0];
+  const bool search = shapes.size() * modes.size() > 1;
+  for (auto& sh : shapes) {
+    if ((rc = configure(w, sh.first, sh.second)) || (rc = size_pairs(w, st, o.pair_capacity))) { release(w); return rc; }
+    if (!search) break;
+    for (int m : modes) {
+      w->sv->persistent_blocks = (uint32_t)m;
+      float ms = 0.f;
+      rc = time_config(w, st, o.tune_reps, &ms);
+      if (rc) { release(w); return rc; }
+      if (ms < best_ms) { best_ms = ms; best_tw = sh.first; best_th = sh.second; best_mode = m; }
+    }
+  }
+  o.tile_w = best_tw;
+  o.tile_h = best_th;
+  o.persistent = best_mode;
+  if ((rc = configure(w, best_tw, best_th)) || (rc = size_pairs(w, st, o.pair_capacity))) { release(w); return rc; }
+  w->sv->persistent_blocks = (uint32_t)best_mode;
+  o.pair_capacity = w->sv->capacity;
+  w->cfg = o;
+  HIP_TRY(hipStreamSynchronize(st));
+  if (o.use_graph) {
+    rc = capture(w);
+    if (rc) { release(w); return rc; }
+  }
+  *win = w;
+  return VPGS_OK;
+}
+
+int vpgs_window_set_cameras(vpgs_window* w, const vpgs_camera* cams) {
+  if (!w) return VPGS_EINVAL;
+  vpgs_ctx* ctx = w->ctx;
+  if (!cams) return fail(ctx, VPGS_EINVAL, "NULL cameras");
+  for (size_t v = 0; v < w->cams.size(); ++v)
+    if (cams[v].width != w->cams[v].width || cams[v].height != w->cams[v].height)
+      return fail(ctx, VPGS_EINVAL, "view %zu: image size changed", v);
+  std::vector<vpgs_camera> old = w->cams;
+  w->cams.assign(cams, cams + old.size());
+  vpgs_render_opts ro{};
+  int rc = validate_forward(ctx, (int)w->sets.size(), w->sets.data(), (int)w->cams.size(), w->view_set.data(),
+                            w->cams.data(), w->out.data(), &ro);
+  if (rc) { w->cams = old; return rc; }
+  w->cams_dirty = true;
+  return VPGS_OK;
+}
+
+int vpgs_window_run(vpgs_window* w, int parts, void* stream) {
+  if (!w) return VPGS_EINVAL;
+  vpgs_ctx* ctx = w->ctx;
+  if (parts < 1 || parts > 3) return fail(ctx, VPGS_EINVAL, "parts must be 1 (forward), 2 (backward) or 3 (both)");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (w->cams_dirty) {
+    // rebuild the tables for the new poses (same shapes, same buffers) and upload
+    HIP_TRY(hipEventSynchronize(w->sv->tab_uploaded));
+    int rc = build_tables(ctx, *w->sv->h_tab, (int)w->sets.size(), w->sets.data(), (int)w->view_set.size(),
+                          w->view_set.data(), w->cams.data(), w->out.data(), w->cfg.tile_w, w->cfg.tile_h);
+    if (!rc) rc = bind_backward(ctx, *w->sv->h_tab, w->grad_out.data(), w->grads.data());
+    if (!rc) rc = upload_tables(ctx, w->sv, st);
+    if (rc) return rc;
+    w->cams_dirty = false;
+  }
+  for (int part = 1; part <= 2; ++part) {
+    if (!(parts & part)) continue;
+    if (w->exec[part - 1]) {
+      HIP_TRY(hipGraphLaunch(w->exec[part - 1], st));
+    } else {
+      int rc = enqueue_part(w, part, st);
+      if (rc) return rc;
+    }
+  }
+  return VPGS_OK;
+}
+
+int vpgs_window_stats(vpgs_window* w, vpgs_stats* out, void* stream) {
+  if (!w) return VPGS_EINVAL;
+  return vpgs_saved_stats(w->ctx, w->sv, out, stream);
+}
+
+int vpgs_window_config(const vpgs_window* w, vpgs_window_opts* out) {
+  if (!w || !out) return VPGS_EINVAL;
+  *out = w->cfg;
+  return VPGS_OK;
+}
+
+int vpgs_window_destroy(vpgs_window* w) {
+  if (!w) return VPGS_EINVAL;
+  (void)hipSetDevice(w->ctx->device);
+  (void)hipDeviceSynchronize();
+  release(w);
+  return VPGS_OK;
+}
+
+}  // extern "C"

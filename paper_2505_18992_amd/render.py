@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import check, load
 
 __all__ = ["Context", "get_context", "render", "render_backward", "Saved", "RenderFn", "render_views",
-           "camera_struct", "decode_forward", "decode_backward", "DecodeFn", "decode"]
+           "camera_struct", "decode_forward", "decode_backward", "DecodeFn", "decode", "RenderWindow"]
 
 
 class Context:
@@ -282,6 +282,90 @@ def render_views(sets, cameras, view_set=None, pose_delta: Optional[torch.Tensor
 
 # The autograd function: RenderFn.apply((cameras, view_set, tile, capacity), pose_delta, *set_tensors)
 RenderFn = _RenderViews
+
+
+# ---------------------------------------------------------------------------
+# mapping window: all views bound once, tuned once, replayed as graph launches
+# ---------------------------------------------------------------------------
+
+class RenderWindow:
+    """Batched forward+backward of a fixed set of views (a mapping window).
+
+    ``outputs[v]`` = (rgb, depth, alpha) written by each forward;
+    ``grad_out[v]`` = (g_rgb, g_depth, g_alpha) read by each backward (fill
+    them in place, e.g. with a loss gradient, between the two parts);
+    ``grads[s]`` = the 5 gradient tensors of set s; ``d_pose`` [V, 6].
+    The Gaussian tensors are read in place, so an optimiser may update them
+    between runs."""
+
+    def __init__(self, sets, cameras, view_set=None, tile=None, persistent: int = -1, use_graph: bool = True,
+                 pair_capacity: int = 0, tune_reps: int = 3, ctx: Optional[Context] = None):
+        self.ctx = ctx or get_context()
+        L = load()
+        nv = len(cameras)
+        view_set = [0] * nv if view_set is None else list(view_set)
+        self.sets = [tuple(s) for s in sets]
+        dev = self.sets[0][0].device
+        f = lambda *shape: torch.zeros(shape, dtype=torch.float32, device=dev)
+        self.outputs = [(f(3, c.height, c.width), f(c.height, c.width), f(c.height, c.width)) for c in cameras]
+        self.grad_out = [(f(3, c.height, c.width), f(c.height, c.width), f(c.height, c.width)) for c in cameras]
+        self.grads = [(f(s[0].shape[0], 3), f(s[0].shape[0], 3), f(s[0].shape[0], 4), f(s[0].shape[0]),
+                       f(s[0].shape[0], 3)) for s in self.sets]
+        self.d_pose = f(nv, 6)
+        gs = (_lib.Gaussians * len(self.sets))(*[_set_struct(s) for s in self.sets])
+        cams = (_lib.Camera * nv)(*[camera_struct(c) for c in cameras])
+        vs = (ctypes.c_int32 * nv)(*view_set)
+        ims = (_lib.Images * nv)()
+        gis = (_lib.ImageGrads * nv)()
+        for v in range(nv):
+            ims[v].rgb, ims[v].depth, ims[v].alpha = (t.data_ptr() for t in self.outputs[v])
+            gis[v].rgb, gis[v].depth, gis[v].alpha = (t.data_ptr() for t in self.grad_out[v])
+        gb = (_lib.GaussBuffers * len(self.sets))()
+        for s, g in enumerate(self.grads):
+            gb[s].means, gb[s].log_scales, gb[s].quats, gb[s].opacities, gb[s].colors = (t.data_ptr() for t in g)
+        o = _lib.WindowOpts()
+        o.tile_w, o.tile_h = tile if tile is not None else (0, 0)
+        o.persistent = int(persistent)
+        o.use_graph = int(use_graph)
+        o.pair_capacity = int(pair_capacity)
+        o.tune_reps = int(tune_reps)
+        h = ctypes.c_void_p()
+        check(L.vpgs_window_create(self.ctx.handle, len(self.sets), gs, nv, vs, cams, ims, gis, gb,
+                                   _ptr(self.d_pose), ctypes.byref(o), ctypes.byref(h), _stream()),
+              self.ctx.handle, "vpgs_window_create")
+        self.handle = h
+        self.n_views = nv
+
+    def set_cameras(self, cameras):
+        cams = (_lib.Camera * self.n_views)(*[camera_struct(c) for c in cameras])
+        check(load().vpgs_window_set_cameras(self.handle, cams), self.ctx.handle, "vpgs_window_set_cameras")
+
+    def run(self, forward: bool = True, backward: bool = True):
+        parts = (_lib.WINDOW_FORWARD if forward else 0) | (_lib.WINDOW_BACKWARD if backward else 0)
+        check(load().vpgs_window_run(self.handle, parts, _stream()), self.ctx.handle, "vpgs_window_run")
+
+    def stats(self) -> dict:
+        s = _lib.Stats()
+        st = load().vpgs_window_stats(self.handle, ctypes.byref(s), _stream())
+        if st not in (0, _lib.VPGS_ECAPACITY):
+            check(st, self.ctx.handle, "vpgs_window_stats")
+        return {f: getattr(s, f) for f, _ in _lib.Stats._fields_}
+
+    def config(self) -> dict:
+        o = _lib.WindowOpts()
+        check(load().vpgs_window_config(self.handle, ctypes.byref(o)), self.ctx.handle, "vpgs_window_config")
+        return {f: getattr(o, f) for f, _ in _lib.WindowOpts._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().vpgs_window_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------------------

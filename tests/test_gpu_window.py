@@ -1,0 +1,142 @@
+"""The mapping window: all views bound once, tuned, captured in HIP graphs
+and replayed.  Its results equal the eager entry points' (forward bit for
+bit with the same tile shape; gradients within the atomic-order tolerance),
+on every replay, after pose updates and in the persistent compositing mode."""
+import numpy as np
+import pytest
+import torch
+
+import scenes
+from gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _scene():
+    sc = scenes.make_c4(n=40_000, views=4)
+    return sc, [to_dev(g.arrays()) for g in sc.sets], [to_dev(w) for w in sc.weights]
+
+
+def _eager(sets, cams, vset, gw, tile):
+    from paper_2505_18992_amd import render, render_backward
+    outs, saved = render(sets, cams, vset, tile=tile)
+    grads, d_pose = render_backward(saved, gw)
+    saved.close()
+    return outs, grads, d_pose
+
+
+def _close(a, b, rel=2e-3):
+    """Two FP32 runs differ only in the order of their atomic additions.  A
+    Gaussian that covers ~1e5 pixels sums terms of both signs whose
+    magnitudes exceed the total by ~1e3, so the order can move an element by
+    ~1e-3 of the tensor's largest value (the oracle comparisons bound each
+    run against its summation scale)."""
+    scale = float(b.abs().max()) + 1e-12
+    return float((a - b).abs().max()) <= rel * scale
+
+
+def _check(win, outs, grads, d_pose):
+    for v in range(len(outs)):
+        for a, b in zip(win.outputs[v], outs[v]):
+            assert torch.equal(a, b)
+    for s in range(len(grads)):
+        for k, (a, b) in enumerate(zip(win.grads[s], grads[s])):
+            assert _close(a, b), (s, k, float((a - b).abs().max()), float(b.abs().max()),
+                                  int(torch.argmax((a - b).abs().reshape(-1))))
+    assert _close(win.d_pose, d_pose, 1e-2)
+
+
+@pytest.mark.parametrize("use_graph,persistent", [(True, 0), (True, 1024), (False, 0)])
+def test_window_matches_eager_on_every_replay(use_graph, persistent):
+    from paper_2505_18992_amd import RenderWindow
+    sc, sets, gw = _scene()
+    print(f"case window graph={use_graph} persistent={persistent}", flush=True)
+    win = RenderWindow(sets, sc.cameras, sc.view_set, tile=(16, 16), persistent=persistent, use_graph=use_graph)
+    for v in range(len(sc.cameras)):
+        for dst, src in zip(win.grad_out[v], gw[v]):
+            dst.copy_(src)
+    outs, grads, d_pose = _eager(sets, sc.cameras, sc.view_set, gw, (16, 16))
+    for rep in range(3):
+        win.run()
+        torch.cuda.synchronize()
+        _check(win, outs, grads, d_pose)
+        # eager work and a synchronisation between replays
+        junk = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+    st = win.stats()
+    assert st["overflow"] == 0 and st["n_pairs"] > 0
+    win.close()
+
+
+def test_window_pose_update_and_parts():
+    from paper_2505_18992_amd import RenderWindow
+    sc, sets, gw = _scene()
+    win = RenderWindow(sets, sc.cameras, sc.view_set, tile=(16, 8), persistent=0)
+    cams2 = [c.copy() for c in sc.cameras]
+    for c in cams2:
+        c.world_to_cam[:, 3] += np.array([0.05, -0.02, 0.1], np.float32)
+    win.set_cameras(cams2)
+    win.run(forward=True, backward=False)
+    # the upstream gradient is filled between the two parts
+    for v in range(len(cams2)):
+        for dst, src in zip(win.grad_out[v], gw[v]):
+            dst.copy_(src)
+    win.run(forward=False, backward=True)
+    torch.cuda.synchronize()
+    outs, grads, d_pose = _eager(sets, cams2, sc.view_set, gw, (16, 8))
+    _check(win, outs, grads, d_pose)
+    win.close()
+
+
+def test_window_search_picks_a_built_configuration():
+    from paper_2505_18992_amd import RenderWindow
+    sc, sets, gw = _scene()
+    win = RenderWindow(sets, sc.cameras, sc.view_set, tune_reps=2)
+    cfg = win.config()
+    assert (cfg["tile_w"], cfg["tile_h"]) in [(16, 16), (16, 8), (8, 8), (32, 8)]
+    assert cfg["pair_capacity"] > 0 and cfg["use_graph"] == 1
+    for v in range(len(sc.cameras)):
+        for dst, src in zip(win.grad_out[v], gw[v]):
+            dst.copy_(src)
+    win.run()
+    torch.cuda.synchronize()
+    outs, grads, d_pose = _eager(sets, sc.cameras, sc.view_set, gw, (cfg["tile_w"], cfg["tile_h"]))
+    _check(win, outs, grads, d_pose)
+    # forward is also independent of the tile shape
+    outs16, _, _ = _eager(sets, sc.cameras, sc.view_set, gw, (16, 16))
+    for v in range(len(outs)):
+        for a, b in zip(win.outputs[v], outs16[v]):
+            assert torch.equal(a, b)
+    win.close()
+
+
+def test_window_overflow_reported():
+    from paper_2505_18992_amd import RenderWindow
+    sc, sets, gw = _scene()
+    win = RenderWindow(sets, sc.cameras, sc.view_set, tile=(16, 16), persistent=0, pair_capacity=1000)
+    win.run()
+    st = win.stats()
+    assert st["overflow"] == 1 and st["pair_capacity"] == 1000
+    win.close()
+
+
+def test_window_multiple_sets():
+    from paper_2505_18992_amd import RenderWindow
+    sc = scenes.make_c5(n_per=30_000, views_per=2)
+    sets = [to_dev(g.arrays()) for g in sc.sets]
+    gw = [to_dev(w) for w in sc.weights]
+    win = RenderWindow(sets, sc.cameras, sc.view_set, tile=(16, 16), persistent=0)
+    for v in range(len(sc.cameras)):
+        for dst, src in zip(win.grad_out[v], gw[v]):
+            dst.copy_(src)
+    win.run()
+    torch.cuda.synchronize()
+    outs, grads, d_pose = _eager(sets, sc.cameras, sc.view_set, gw, (16, 16))
+    _check(win, outs, grads, d_pose)
+    win.close()
