@@ -28,26 +28,34 @@ __device__ __forceinline__ int view_of_tile(const CallTables* tab, uint32_t tile
   return lo;
 }
 
-// Gaussian falloff at a pixel centre.  Shared verbatim by the forward and the
-// backward (no contraction beyond the explicit fmaf), so the backward
-// recomputes bit-identical alpha values.
-struct Falloff { float dx, dy, G, raw, alpha; };
-__device__ __forceinline__ Falloff falloff(const float4 A, const float4 B, float pxc, float pyc) {
+// Per-Gaussian constants staged in LDS for the per-pixel loops: the conic
+// pre-scaled so that alpha = min(0.99, 2^e) with
+//   e = -log2(e) (Qa dx^2 + 2 Qb dx dy + Qc dy^2) / 2 + log2(o),
+// i.e. o exp(-sigma) with the constant factors and the opacity folded in.
+// Forward and backward stage and evaluate it with the same instructions, so
+// the backward recomputes bit-identical alpha values.
+constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
+constexpr float kNegLog2e = -1.44269504088896340736f;
+__device__ __forceinline__ float4 stage_exponent(const float4 A, const float4 B) {
+  return make_float4(B.x * kNegHalfLog2e, B.y * kNegLog2e, B.z * kNegHalfLog2e, __log2f(A.w));
+}
+
+struct Falloff { float dx, dy, raw, alpha; };
+__device__ __forceinline__ Falloff falloff(const float4 A, const float4 E, float pxc, float pyc) {
 #pragma clang fp contract(off)
   Falloff f;
   f.dx = A.x - pxc;
   f.dy = A.y - pyc;
-  const float quad = fmaf(B.z * f.dy, f.dy, (B.x * f.dx) * f.dx);   // Qa dx^2 + Qc dy^2
-  const float sigma = fmaf(B.y * f.dx, f.dy, 0.5f * quad);         // + Qb dx dy
-  f.G = __expf(-sigma);
-  f.raw = A.w * f.G;
+  const float t = fmaf(E.x, f.dx, E.y * f.dy);          // Qa' dx + Qb' dy
+  const float e = fmaf(t, f.dx, fmaf(E.z * f.dy, f.dy, E.w));
+  f.raw = __builtin_amdgcn_exp2f(e);
   f.alpha = fminf(kAlphaMax, f.raw);
   return f;
 }
 
 template <int TW, int TH>
 struct FwdShared {
-  float4 A[TW * TH], B[TW * TH], C[TW * TH];
+  float4 A[TW * TH], E[TW * TH], C[TW * TH];
 };
 
 template <int TW, int TH>
@@ -57,9 +65,6 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
                                              float* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
                                              uint32_t tile, FwdShared<TW, TH>& sh, uint32_t& ne, uint32_t& nb) {
   constexpr int BS = TW * TH;
-  float4* sA = sh.A;
-  float4* sB = sh.B;
-  float4* sC = sh.C;
   const ViewDesc& V = tab->views[view_of_tile(tab, tile)];
   const uint32_t lt = tile - V.tile_base;
   const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
@@ -77,28 +82,35 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
     const uint32_t idx = start + threadIdx.x;
     if (idx < rg.y) {
       const uint32_t rec = vals[idx];
-      sA[threadIdx.x] = pa[rec];
-      sB[threadIdx.x] = pb[rec];
-      sC[threadIdx.x] = pc[rec];
+      const float4 A = pa[rec];
+      sh.A[threadIdx.x] = A;
+      sh.E[threadIdx.x] = stage_exponent(A, pb[rec]);
+      sh.C[threadIdx.x] = pc[rec];
     }
     __syncthreads();
     const int nbat = (int)min((uint32_t)BS, rg.y - start);
-    for (int j = 0; j < nbat && !done; ++j) {
-      const float4 A = sA[j];
-      const Falloff f = falloff(A, sB[j], pxc, pyc);
-      ++ne;
-      if (f.alpha < kAlphaMin) continue;
-      const float Tn = T * (1.0f - f.alpha);
-      if (Tn < kTransMin) { done = true; break; }
-      const float w = f.alpha * T;
-      const float4 c = sC[j];
-      C0 = fmaf(w, c.x, C0);
-      C1 = fmaf(w, c.y, C1);
-      C2 = fmaf(w, c.z, C2);
-      D = fmaf(w, A.z, D);
-      T = Tn;
-      last = start + (uint32_t)j + 1u - rg.x;
-      ++nb;
+    if (__ballot(!done) != 0ull) {
+      const uint32_t base = start - rg.x + 1u;
+      for (int j = 0; j < nbat; ++j) {
+        const float4 A = sh.A[j];
+        const Falloff f = falloff(A, sh.E[j], pxc, pyc);
+        const float4 c = sh.C[j];
+        ne += done ? 0u : 1u;
+        const bool ok = !done && f.alpha >= kAlphaMin;
+        const float Tn = T * (1.0f - f.alpha);
+        const bool stop = ok && Tn < kTransMin;
+        const bool blend = ok && !stop;
+        const float w = blend ? f.alpha * T : 0.0f;
+        C0 = fmaf(w, c.x, C0);
+        C1 = fmaf(w, c.y, C1);
+        C2 = fmaf(w, c.z, C2);
+        D = fmaf(w, A.z, D);
+        T = blend ? Tn : T;
+        last = blend ? base + (uint32_t)j : last;
+        nb += blend ? 1u : 0u;
+        done = done || stop;
+        if ((j & 7) == 7 && __ballot(!done) == 0ull) break;
+      }
     }
   }
   if (inside) {
@@ -158,15 +170,53 @@ __global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
   flush_counts(ne, nb, cnt);
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
+// ---------------------------------------------------------------------------
+// wavefront reduce-scatter of the 10 per-Gaussian gradient values
+// ---------------------------------------------------------------------------
+// Recursive halving over 16 slots (10 used): each step pairs a lane with one
+// that differs in one "keep" bit (2, 3, 4, 5 in turn), keeps half of its
+// slots and adds the partner's copy of them; the last two steps sum the
+// remaining lanes of each quad.  Lane L ends with the wave total of slot
+// 8*b2 + 4*b3 + 2*b4 + b5 (b = bits of L).  The pairings are lane xor 7
+// (DPP row half-mirror), xor 8 (DPP row rotate by 8), xor 16 (swizzle),
+// xor 32 (permute), xor 1 and xor 2 (DPP quad permutations).  All lanes of
+// the wavefront must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float swz16(float v) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+}
+
+__device__ __forceinline__ float wave_reduce_scatter10(const float g[kNumAcc], int lane) {
+  const bool b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1, b4 = (lane >> 4) & 1, b5 = (lane >> 5) & 1;
+  float h[8];
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  for (int i = 0; i < 8; ++i) {  // slots i and 8 + i (slots >= 10 are zero)
+    const float lo = g[i];
+    const float hi = (8 + i < kNumAcc) ? g[8 + i] : 0.0f;
+    h[i] = (b2 ? hi : lo) + dpp<0x141>(b2 ? lo : hi);
+  }
+  float q[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) q[i] = (b3 ? h[4 + i] : h[i]) + dpp<0x128>(b3 ? h[i] : h[4 + i]);
+  float r[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) r[i] = (b4 ? q[2 + i] : q[i]) + swz16(b4 ? q[i] : q[2 + i]);
+  float t = (b5 ? r[1] : r[0]) + __shfl_xor(b5 ? r[0] : r[1], 32, 64);
+  t += dpp<0xB1>(t);  // quad_perm [1,0,3,2]
+  t += dpp<0x4E>(t);  // quad_perm [2,3,0,1]
+  return t;
+}
+
+__device__ __forceinline__ int scatter_slot(int lane) {
+  return (((lane >> 2) & 1) << 3) | (((lane >> 3) & 1) << 2) | (((lane >> 4) & 1) << 1) | ((lane >> 5) & 1);
 }
 
 template <int TW, int TH>
 struct BwdShared {
-  float4 A[TW * TH], B[TW * TH], C[TW * TH];
+  float4 A[TW * TH], E[TW * TH], B[TW * TH], C[TW * TH];
   uint32_t rec[TW * TH];
   uint32_t maxlast[(TW * TH) / 64];
 };
@@ -179,11 +229,6 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
                                               const uint32_t* __restrict__ n_contrib, float* __restrict__ acc,
                                               uint32_t tile, BwdShared<TW, TH>& sh) {
   constexpr int BS = TW * TH;
-  float4* sA = sh.A;
-  float4* sB = sh.B;
-  float4* sC = sh.C;
-  uint32_t* sRec = sh.rec;
-  uint32_t* smax = sh.maxlast;
   const ViewDesc& V = tab->views[view_of_tile(tab, tile)];
   const uint32_t lt = tile - V.tile_base;
   const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
@@ -192,6 +237,8 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
   const uint2 rg = ranges[tile];
   const int lane = threadIdx.x & 63;
+  const int slot_id = scatter_slot(lane);
+  const bool writer = (lane & 3) == 0 && slot_id < kNumAcc;
 
   const size_t HW = (size_t)V.W * V.H;
   const size_t pix = inside ? (size_t)py * V.W + px : 0;
@@ -203,15 +250,16 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
     if (V.g_depth) gD = V.g_depth[pix];
     if (V.g_alpha) gA = V.g_alpha[pix];
   }
-  // the walk starts after the last entry any pixel of the tile blended
-  uint32_t m = last;
+  // the walk starts after the last entry any pixel of the tile blended; a
+  // wavefront skips the entries after its own last one
+  uint32_t wave_last = last;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
-  if (lane == 0) smax[threadIdx.x >> 6] = m;
+  for (int off = 32; off > 0; off >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, off, 64));
+  if (lane == 0) sh.maxlast[threadIdx.x >> 6] = wave_last;
   __syncthreads();
   uint32_t max_last = 0;
 #pragma unroll
-  for (int w = 0; w < BS / 64; ++w) max_last = max(max_last, smax[w]);
+  for (int w = 0; w < BS / 64; ++w) max_last = max(max_last, sh.maxlast[w]);
 
   float S = 0.f;  // sum over blended entries behind the current one of alpha T f
   for (int end = (int)max_last; end > 0; end -= BS) {
@@ -221,53 +269,47 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
       const int j = begin + (int)threadIdx.x;
       if (j < end) {
         const uint32_t rec = vals[rg.x + (uint32_t)j];
-        sRec[threadIdx.x] = rec;
-        sA[threadIdx.x] = pa[rec];
-        sB[threadIdx.x] = pb[rec];
-        sC[threadIdx.x] = pc[rec];
+        const float4 A = pa[rec];
+        const float4 B = pb[rec];
+        sh.rec[threadIdx.x] = rec;
+        sh.A[threadIdx.x] = A;
+        sh.E[threadIdx.x] = stage_exponent(A, B);
+        sh.B[threadIdx.x] = make_float4(B.x, B.y, B.z, 1.0f / A.w);
+        sh.C[threadIdx.x] = pc[rec];
       }
     }
     __syncthreads();
-    for (int j = end - 1; j >= begin; --j) {
-      const int slot = j - begin;
+    const int jtop = min(end, (int)wave_last) - 1;
+    for (int j = jtop; j >= begin; --j) {
+      const int sl = j - begin;
+      const float4 A = sh.A[sl];
+      const Falloff f = falloff(A, sh.E[sl], pxc, pyc);
+      const bool valid = (uint32_t)j < last && f.alpha >= kAlphaMin;
+      if (__ballot(valid) == 0ull) continue;
+      const float4 B = sh.B[sl];
+      const float4 c = sh.C[sl];
+      const float r1m = __builtin_amdgcn_rcpf(1.0f - f.alpha);
+      const float Tj = valid ? T * r1m : T;
+      const float fj = gC0 * c.x + gC1 * c.y + gC2 * c.z + gD * A.z + gA;
+      const float dLda = Tj * fj - S * r1m;
+      const float w = valid ? f.alpha * Tj : 0.0f;
+      S = fmaf(w, fj, S);
+      T = Tj;
+      const bool unclamped = valid && f.raw < kAlphaMax;
+      const float ds = unclamped ? -dLda * f.raw : 0.0f;  // dL/dsigma = dL/dalpha * (-alpha)
       float g[kNumAcc];
-#pragma unroll
-      for (int k = 0; k < kNumAcc; ++k) g[k] = 0.f;
-      bool has = false;
-      if ((uint32_t)j < last) {
-        const float4 A = sA[slot], B = sB[slot];
-        const Falloff f = falloff(A, B, pxc, pyc);
-        if (f.alpha >= kAlphaMin) {
-          has = true;
-          T = T / (1.0f - f.alpha);
-          const float4 c = sC[slot];
-          const float fj = gC0 * c.x + gC1 * c.y + gC2 * c.z + gD * A.z + gA;
-          const float dLda = T * fj - S / (1.0f - f.alpha);
-          const float w = f.alpha * T;
-          S = fmaf(w, fj, S);
-          g[6] = w * gC0;
-          g[7] = w * gC1;
-          g[8] = w * gC2;
-          g[9] = w * gD;
-          if (f.raw < kAlphaMax) {
-            const float ds = -dLda * f.alpha;  // dL/dsigma
-            g[0] = ds * (B.x * f.dx + B.y * f.dy);
-            g[1] = ds * (B.y * f.dx + B.z * f.dy);
-            g[2] = ds * 0.5f * f.dx * f.dx;
-            g[3] = ds * f.dx * f.dy;
-            g[4] = ds * 0.5f * f.dy * f.dy;
-            g[5] = dLda * f.G;
-          }
-        }
-      }
-      if (__ballot(has) != 0ull) {
-#pragma unroll
-        for (int k = 0; k < kNumAcc; ++k) g[k] = wave_sum(g[k]);
-        float mine = g[0];
-#pragma unroll
-        for (int k = 1; k < kNumAcc; ++k) mine = lane == k ? g[k] : mine;
-        if (lane < kNumAcc) unsafeAtomicAdd(acc + (size_t)sRec[slot] * kNumAcc + lane, mine);
-      }
+      g[0] = ds * (B.x * f.dx + B.y * f.dy);
+      g[1] = ds * (B.y * f.dx + B.z * f.dy);
+      g[2] = ds * 0.5f * f.dx * f.dx;
+      g[3] = ds * f.dx * f.dy;
+      g[4] = ds * 0.5f * f.dy * f.dy;
+      g[5] = unclamped ? dLda * f.raw * B.w : 0.0f;  // dalpha/do = exp(-sigma) = raw / o
+      g[6] = w * gC0;
+      g[7] = w * gC1;
+      g[8] = w * gC2;
+      g[9] = w * gD;
+      const float mine = wave_reduce_scatter10(g, lane);
+      if (writer) unsafeAtomicAdd(acc + (size_t)sh.rec[sl] * kNumAcc + slot_id, mine);
     }
   }
 }
