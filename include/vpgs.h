@@ -251,12 +251,13 @@ int vpgs_window_destroy(vpgs_window* win);
 /* When enabled, every launch sequence of the context records a pair of HIP
  * events on its stream around each stage (projection, scan, emission, sort,
  * ranges, forward compositing, backward compositing, projection backward,
- * pose reduction, fills, decode forward, decode backward).  vpgs_profile_read
+ * pose reduction, fills, decode forward, decode backward, depth ordering of
+ * the visible records).  vpgs_profile_read
  * synchronises on the recorded events and returns, for stage index `stage`
  * (0 <= stage < VPGS_NUM_STAGES), its name, the number of recorded launches
  * and their summed duration in milliseconds since the last enable.  Disabled
  * by default; enabling resets the totals. */
-#define VPGS_NUM_STAGES 12
+#define VPGS_NUM_STAGES 13
 int vpgs_profile_enable(vpgs_ctx* ctx, int on);
 int vpgs_profile_read(vpgs_ctx* ctx, int stage, const char** name, int64_t* calls, double* total_ms);
 

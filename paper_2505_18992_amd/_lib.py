@@ -22,7 +22,7 @@ VPGS_ECAPACITY = -4
 VPGS_EUNSUPPORTED = -5
 MAX_VIEWS = 64
 MAX_SETS = 64
-NUM_STAGES = 12
+NUM_STAGES = 13
 WINDOW_FORWARD, WINDOW_BACKWARD = 1, 2
 
 BUF_PROJ, BUF_EXTENT, BUF_COUNT, BUF_KEYS, BUF_VALUES, BUF_RANGES, BUF_TFINAL, BUF_NCONTRIB, BUF_GRADACC = range(1, 10)

@@ -101,24 +101,47 @@ hipError_t launch_project_backward(const CallTables* d_tab, const CallTables& h_
 hipError_t launch_pose_reduce(const CallTables* d_tab, const CallTables& h_tab, const float* pose_partial,
                               float* d_pose, hipStream_t s);
 
-// Exclusive scan of n uint32 values; total (device, uint32) receives the sum.
+// Exclusive scan of n uint32 values (or, with flags, of value != 0); total
+// (device, uint32) receives the sum.
 size_t scan_workspace_bytes(uint32_t n);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, void* ws,
-                       hipStream_t s);
+                       hipStream_t s, bool flags = false);
 
+// Depth order of the visible records: compaction (record order), stable
+// sort by FP32 depth bits, tile counts gathered in that order and their
+// exclusive scan (pair offsets; the total goes to *pair_off_total).
+struct DepthOrder {
+  uint32_t* keys;
+  uint32_t* vals;
+  uint32_t* keys_alt;
+  uint32_t* vals_alt;
+  uint32_t* counts;
+  uint32_t* pair_off;
+  uint32_t* pair_off_total;
+  void* scan_ws;
+  int* sorted_in_alt;  // host: 1 if the sorted records are in vals_alt
+};
+hipError_t launch_depth_order(const CallTables& h_tab, const ProjBuffers pb, const uint32_t* vis_off,
+                              const uint32_t* n_visible, DepthOrder d, void* sort_ws, hipStream_t s);
+
+// One (tile id, record) pair per overlapped tile, in depth order.
 hipError_t launch_emit(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
-                       const uint32_t* offsets, Counters* cnt, uint64_t* keys, uint32_t* vals,
-                       uint32_t capacity, int tile_w, int tile_h, hipStream_t s);
+                       const uint32_t* sorted_rec, const uint32_t* pair_off, const uint32_t* n_visible,
+                       Counters* cnt, uint32_t* keys, uint32_t* vals, uint32_t capacity, hipStream_t s);
 
-// Stable LSD radix sort of (key, value) pairs over key bits [0, key_bits).
+// Stable LSD radix sort of (tile id, record) pairs over key bits [0, key_bits).
 // The pair count is read from cnt->pairs (clamped to capacity) on the device.
 size_t sort_workspace_bytes(uint32_t capacity);
-hipError_t launch_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+hipError_t launch_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                        uint32_t capacity, int key_bits, const Counters* cnt, void* ws, int* result_in_alt,
                        hipStream_t s);
 
-hipError_t launch_ranges(const uint64_t* keys, const Counters* cnt, uint32_t capacity, uint2* ranges,
+hipError_t launch_ranges(const uint32_t* tiles, const Counters* cnt, uint32_t capacity, uint2* ranges,
                          uint32_t n_tiles, hipStream_t s);
+
+// Sorted keys in the exported 64-bit form (tile id << 32 | depth bits).
+hipError_t launch_key64(const uint32_t* tiles, const uint32_t* recs, const ProjBuffers pb, const Counters* cnt,
+                        uint32_t capacity, uint64_t* out, hipStream_t s);
 
 // Compositing: one workgroup per tile, or (queue != NULL) `blocks`
 // persistent workgroups taking tiles from the zeroed counter *queue.

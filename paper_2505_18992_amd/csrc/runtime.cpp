@@ -20,7 +20,7 @@ namespace vpgs {
 
 const char* const kStageNames[VPGS_NUM_STAGES] = {
     "project", "scan", "emit", "sort", "ranges", "composite_forward", "composite_backward",
-    "project_backward", "pose_reduce", "fill", "decode_forward", "decode_backward"};
+    "project_backward", "pose_reduce", "fill", "decode_forward", "decode_backward", "depth_order"};
 
 int fail(vpgs_ctx* ctx, int code, const char* fmt, ...) {
   if (ctx) {
@@ -92,7 +92,8 @@ namespace vpgs {
 void destroy_saved(vpgs_saved* s) {
   DevBuf* bufs[] = {&s->tab, &s->pa, &s->pb, &s->pc, &s->ext, &s->rect, &s->count, &s->offsets, &s->scan_ws,
                     &s->keys, &s->vals, &s->keys_alt, &s->vals_alt, &s->sort_ws, &s->ranges, &s->tfinal,
-                    &s->ncontrib, &s->counters, &s->acc, &s->pose_partial};
+                    &s->ncontrib, &s->counters, &s->acc, &s->pose_partial, &s->dk, &s->dk_alt, &s->dv,
+                    &s->dv_alt, &s->dcount, &s->dpoff, &s->key64};
   for (DevBuf* b : bufs) free_buf(*b);
   if (s->tab_uploaded) (void)hipEventDestroy(s->tab_uploaded);
   if (s->h_tab) (void)hipHostFree(s->h_tab);
@@ -280,9 +281,13 @@ int prepare_front(vpgs_ctx* ctx, vpgs_saved* sv) {
   uint64_t pixels = 0;
   for (int v = 0; v < T.n_views; ++v) pixels += (uint64_t)T.views[v].W * T.views[v].H;
   sv->n_pixels = (uint32_t)pixels;
-  sv->key_bits = 32 + ilog2_ceil(std::max<uint32_t>(T.n_tiles, 2u));
+  sv->key_bits = ilog2_ceil(std::max<uint32_t>(T.n_tiles, 2u));
   const size_t R = T.n_records;
   int rc;
+  if ((rc = ensure(ctx, sv->dk, R * 4)) || (rc = ensure(ctx, sv->dk_alt, R * 4)) || (rc = ensure(ctx, sv->dv, R * 4)) ||
+      (rc = ensure(ctx, sv->dv_alt, R * 4)) || (rc = ensure(ctx, sv->dcount, R * 4)) ||
+      (rc = ensure(ctx, sv->dpoff, R * 4)) || (rc = ensure(ctx, sv->sort_ws, sort_workspace_bytes((uint32_t)R))))
+    return rc;
   if ((rc = ensure(ctx, sv->tab, sizeof(CallTables))) || (rc = ensure(ctx, sv->pa, R * 16)) ||
       (rc = ensure(ctx, sv->pb, R * 16)) || (rc = ensure(ctx, sv->pc, R * 16)) || (rc = ensure(ctx, sv->ext, R * 8)) ||
       (rc = ensure(ctx, sv->rect, R * 8)) || (rc = ensure(ctx, sv->count, R * 4)) ||
@@ -295,9 +300,10 @@ int prepare_front(vpgs_ctx* ctx, vpgs_saved* sv) {
 
 int ensure_pairs(vpgs_ctx* ctx, vpgs_saved* sv, uint32_t cap) {
   int rc;
-  if ((rc = ensure(ctx, sv->keys, (size_t)cap * 8)) || (rc = ensure(ctx, sv->keys_alt, (size_t)cap * 8)) ||
+  if ((rc = ensure(ctx, sv->keys, (size_t)cap * 4)) || (rc = ensure(ctx, sv->keys_alt, (size_t)cap * 4)) ||
       (rc = ensure(ctx, sv->vals, (size_t)cap * 4)) || (rc = ensure(ctx, sv->vals_alt, (size_t)cap * 4)) ||
-      (rc = ensure(ctx, sv->sort_ws, sort_workspace_bytes(cap))))
+      (rc = ensure(ctx, sv->sort_ws,
+                   sort_workspace_bytes(std::max<uint32_t>(cap, sv->h_tab->n_records)))))
     return rc;
   sv->capacity = cap;
   return VPGS_OK;
@@ -351,9 +357,25 @@ int enqueue_front(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
     HIP_TRY(launch_project(d_tab, T, pb, sv->tile_w, sv->tile_h, st));
   }
   {
+    // visible records (count != 0): compaction offsets and their number
     StageTimer t(ctx, ST_SCAN, st);
-    HIP_TRY(launch_scan(pb.count, static_cast<uint32_t*>(sv->offsets.p), T.n_records, &cnt->pairs, sv->scan_ws.p,
-                        st));
+    HIP_TRY(launch_scan(pb.count, static_cast<uint32_t*>(sv->offsets.p), T.n_records, &cnt->visible, sv->scan_ws.p,
+                        st, true));
+  }
+  {
+    StageTimer t(ctx, ST_DEPTH, st);
+    DepthOrder d;
+    d.keys = static_cast<uint32_t*>(sv->dk.p);
+    d.vals = static_cast<uint32_t*>(sv->dv.p);
+    d.keys_alt = static_cast<uint32_t*>(sv->dk_alt.p);
+    d.vals_alt = static_cast<uint32_t*>(sv->dv_alt.p);
+    d.counts = static_cast<uint32_t*>(sv->dcount.p);
+    d.pair_off = static_cast<uint32_t*>(sv->dpoff.p);
+    d.pair_off_total = &cnt->pairs;
+    d.scan_ws = sv->scan_ws.p;
+    d.sorted_in_alt = &sv->depth_in_alt;
+    HIP_TRY(launch_depth_order(T, pb, static_cast<const uint32_t*>(sv->offsets.p), &cnt->visible, d, sv->sort_ws.p,
+                               st));
   }
   return VPGS_OK;
 }
@@ -364,21 +386,22 @@ int enqueue_back(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
   Counters* cnt = static_cast<Counters*>(sv->counters.p);
   const ProjBuffers pb = proj_of(sv);
   const uint32_t cap = sv->capacity;
-  uint64_t* keys = static_cast<uint64_t*>(sv->keys.p);
+  uint32_t* keys = static_cast<uint32_t*>(sv->keys.p);
   uint32_t* vals = static_cast<uint32_t*>(sv->vals.p);
-  uint64_t* keys_alt = static_cast<uint64_t*>(sv->keys_alt.p);
+  uint32_t* keys_alt = static_cast<uint32_t*>(sv->keys_alt.p);
   uint32_t* vals_alt = static_cast<uint32_t*>(sv->vals_alt.p);
   {
     StageTimer t(ctx, ST_EMIT, st);
-    HIP_TRY(launch_emit(d_tab, T, pb, static_cast<const uint32_t*>(sv->offsets.p), cnt, keys, vals, cap, sv->tile_w,
-                        sv->tile_h, st));
+    const uint32_t* sorted_rec = static_cast<const uint32_t*>(sv->depth_in_alt ? sv->dv_alt.p : sv->dv.p);
+    HIP_TRY(launch_emit(d_tab, T, pb, sorted_rec, static_cast<const uint32_t*>(sv->dpoff.p), &cnt->visible, cnt, keys,
+                        vals, cap, st));
   }
   {
     StageTimer t(ctx, ST_SORT, st);
     HIP_TRY(launch_sort(keys, vals, keys_alt, vals_alt, cap, sv->key_bits, cnt, sv->sort_ws.p, &sv->result_in_alt,
                         st));
   }
-  const uint64_t* skeys = sv->result_in_alt ? keys_alt : keys;
+  const uint32_t* skeys = sv->result_in_alt ? keys_alt : keys;
   const uint32_t* svals = sv->result_in_alt ? vals_alt : vals;
   {
     StageTimer t(ctx, ST_RANGES, st);
@@ -596,8 +619,7 @@ int vpgs_saved_stats(vpgs_ctx* ctx, const vpgs_saved* saved, vpgs_stats* out, vo
   out->overflow = hc->overflow || hc->pairs > saved->capacity;
   out->tile_w = saved->tile_w;
   out->tile_h = saved->tile_h;
-  // visible records: count the non-zero tile counts on the host (diagnostic)
-  out->n_visible = -1;
+  out->n_visible = hc->visible;
   return out->overflow ? fail(ctx, VPGS_ECAPACITY, "pair list overflow: %u pairs, capacity %u", hc->pairs,
                               saved->capacity)
                        : VPGS_OK;
@@ -639,9 +661,17 @@ int vpgs_saved_export(vpgs_ctx* ctx, const vpgs_saved* saved, int what, void* ds
     }
     case VPGS_BUF_EXTENT: HIP_TRY(hipMemcpyAsync(dst, saved->ext.p, need, hipMemcpyDeviceToDevice, st)); break;
     case VPGS_BUF_COUNT: HIP_TRY(hipMemcpyAsync(dst, saved->count.p, need, hipMemcpyDeviceToDevice, st)); break;
-    case VPGS_BUF_KEYS:
-      HIP_TRY(hipMemcpyAsync(dst, alt ? saved->keys_alt.p : saved->keys.p, need, hipMemcpyDeviceToDevice, st));
+    case VPGS_BUF_KEYS: {
+      vpgs_saved* sv = const_cast<vpgs_saved*>(saved);
+      int rc = ensure(ctx, sv->key64, need);
+      if (rc) return rc;
+      HIP_TRY(launch_key64(static_cast<const uint32_t*>(alt ? saved->keys_alt.p : saved->keys.p),
+                           static_cast<const uint32_t*>(alt ? saved->vals_alt.p : saved->vals.p),
+                           proj_of(sv), static_cast<const Counters*>(saved->counters.p), saved->capacity,
+                           static_cast<uint64_t*>(sv->key64.p), st));
+      HIP_TRY(hipMemcpyAsync(dst, sv->key64.p, need, hipMemcpyDeviceToDevice, st));
       break;
+    }
     case VPGS_BUF_VALUES:
       HIP_TRY(hipMemcpyAsync(dst, alt ? saved->vals_alt.p : saved->vals.p, need, hipMemcpyDeviceToDevice, st));
       break;

@@ -19,7 +19,7 @@ struct DevBuf {
 };
 
 enum Stage { ST_PROJECT, ST_SCAN, ST_EMIT, ST_SORT, ST_RANGES, ST_FWD, ST_BWD, ST_PROJ_BWD, ST_POSE, ST_FILL,
-             ST_DEC_FWD, ST_DEC_BWD };
+             ST_DEC_FWD, ST_DEC_BWD, ST_DEPTH };
 extern const char* const kStageNames[VPGS_NUM_STAGES];
 
 }  // namespace vpgs
@@ -30,10 +30,11 @@ struct vpgs_saved {
   vpgs::CallTables* h_tab = nullptr;
   hipEvent_t tab_uploaded = nullptr;
   vpgs::DevBuf tab, pa, pb, pc, ext, rect, count, offsets, scan_ws, keys, vals, keys_alt, vals_alt, sort_ws, ranges,
-      tfinal, ncontrib, counters, acc, pose_partial;
+      tfinal, ncontrib, counters, acc, pose_partial, dk, dk_alt, dv, dv_alt, dcount, dpoff, key64;
   int result_in_alt = 0;
+  int depth_in_alt = 0;
   int tile_w = 16, tile_h = 16;
-  int key_bits = 48;
+  int key_bits = 16;  // tile-id bits sorted
   uint32_t persistent_blocks = 0;  // 0: one compositing workgroup per tile
   uint32_t capacity = 0;
   uint32_t n_pixels = 0;

@@ -38,15 +38,18 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds, u
   return wbase + incl - v;
 }
 
+// flags != 0: scan the indicator (value != 0) instead of the values.
+__device__ __forceinline__ uint32_t scan_value(uint32_t x, int flags) { return flags ? (x != 0u) : x; }
+
 __global__ void __launch_bounds__(kScanBlock) scan_reduce_kernel(const uint32_t* __restrict__ in, uint32_t n,
-                                                                 uint32_t* __restrict__ sums) {
+                                                                 uint32_t* __restrict__ sums, int flags) {
   __shared__ uint32_t lds[kScanBlock / 64];
   const size_t base = (size_t)blockIdx.x * kScanTile;
   uint32_t s = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const size_t idx = base + (size_t)k * kScanBlock + threadIdx.x;
-    if (idx < n) s += in[idx];
+    if (idx < n) s += scan_value(in[idx], flags);
   }
   uint32_t tot;
   block_excl_scan(s, lds, &tot);
@@ -57,7 +60,8 @@ __global__ void __launch_bounds__(kScanBlock) scan_reduce_kernel(const uint32_t*
 // (NULL = 0).  If total is non-NULL the last block writes the grand total.
 __global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t* __restrict__ in, uint32_t n,
                                                                const uint32_t* __restrict__ block_offsets,
-                                                               uint32_t* __restrict__ out, uint32_t* __restrict__ total) {
+                                                               uint32_t* __restrict__ out, uint32_t* __restrict__ total,
+                                                               int flags) {
   __shared__ uint32_t lds[kScanBlock / 64];
   const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;  // blocked layout
   uint32_t v[kScanItems];
@@ -65,7 +69,7 @@ __global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t* _
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const size_t idx = base + k;
-    v[k] = idx < n ? in[idx] : 0u;
+    v[k] = idx < n ? scan_value(in[idx], flags) : 0u;
     s += v[k];
   }
   uint32_t tot;
@@ -105,23 +109,25 @@ size_t scan_workspace_bytes(uint32_t n) {
   return bytes + 256;
 }
 
-hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, void* ws, hipStream_t s) {
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, void* ws, hipStream_t s,
+                       bool flags) {
+  const int fl = flags ? 1 : 0;
   if (n == 0) return total ? launch_fill_u32(total, 0u, 1, s) : hipSuccess;
   const uint32_t blocks = div_up(n, kScanTile);
   if (blocks == 1) {
-    hipLaunchKernelGGL(scan_down_kernel, dim3(1), dim3(kScanBlock), 0, s, in, n, nullptr, out, total);
+    hipLaunchKernelGGL(scan_down_kernel, dim3(1), dim3(kScanBlock), 0, s, in, n, nullptr, out, total, fl);
     return hipGetLastError();
   }
   char* w = static_cast<char*>(ws);
   uint32_t* sums = reinterpret_cast<uint32_t*>(w);
   const size_t sum_bytes = ((size_t)blocks * sizeof(uint32_t) + 255) / 256 * 256;
   uint32_t* sums_scanned = reinterpret_cast<uint32_t*>(w + sum_bytes);
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3(blocks), dim3(kScanBlock), 0, s, in, n, sums);
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(blocks), dim3(kScanBlock), 0, s, in, n, sums, fl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = launch_scan(sums, sums_scanned, blocks, total, w + 2 * sum_bytes, s);
+  e = launch_scan(sums, sums_scanned, blocks, total, w + 2 * sum_bytes, s, false);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(scan_down_kernel, dim3(blocks), dim3(kScanBlock), 0, s, in, n, sums_scanned, out, nullptr);
+  hipLaunchKernelGGL(scan_down_kernel, dim3(blocks), dim3(kScanBlock), 0, s, in, n, sums_scanned, out, nullptr, fl);
   return hipGetLastError();
 }
 

@@ -1,17 +1,33 @@
-// sort.hip -- tile binning: key emission, a stable LSD radix sort of
-// (tile id << 32 | depth bits, record index) pairs, and per-tile ranges.
+// sort.hip -- tile binning.
 //
-// The pair count lives on the device (written by the count scan), so no host
-// round trip is needed between projection and compositing; every kernel
-// clamps it to the allocated capacity.
+// The per-tile order is (tile, FP32 depth bits, record index).  Instead of
+// one wide sort of every (tile, Gaussian) pair, binning runs in two narrow
+// stable sorts:
+//   1. visible records are compacted in record order and stably sorted by
+//      their 32-bit depth bits (so ties keep record order);
+//   2. pairs are emitted in that depth order, one 32-bit tile id per
+//      overlapped tile, and stably sorted by tile id.
+// Stability makes the result the (tile, depth, index) order.  The depth sort
+// touches each visible record once instead of every pair, and the tile sort
+// needs only ceil(log2(tiles) / 8) passes.
+//
+// Counts (visible records, pairs) stay on the device; every kernel clamps
+// them to the allocated capacity, so no host round trip is needed.
 #include "internal.h"
 
 namespace vpgs {
 namespace {
 
-// ---------------------------------------------------------------------------
-// key emission
-// ---------------------------------------------------------------------------
+constexpr int kSortBlock = 256;
+constexpr int kWaves = kSortBlock / 64;
+constexpr int kRounds = 16;                              // 64-key rounds per wave
+constexpr uint32_t kSortTile = kSortBlock * kRounds;     // 4096 keys per workgroup
+constexpr int kRadix = 256;
+
+__device__ __forceinline__ uint32_t clamped(const uint32_t* n, uint32_t capacity) {
+  const uint32_t v = *n;
+  return v < capacity ? v : capacity;
+}
 
 __device__ __forceinline__ int view_of_record(const CallTables* tab, uint32_t rec) {
   int lo = 0, hi = tab->n_views - 1;
@@ -22,48 +38,86 @@ __device__ __forceinline__ int view_of_record(const CallTables* tab, uint32_t re
   return lo;
 }
 
-__global__ void __launch_bounds__(256) emit_kernel(const CallTables* __restrict__ tab, const uint2* __restrict__ rect,
-                                                   const uint32_t* __restrict__ count, const float4* __restrict__ pa,
-                                                   const uint32_t* __restrict__ offsets, Counters* __restrict__ cnt,
-                                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                   uint32_t n_records, uint32_t capacity) {
+// ---------------------------------------------------------------------------
+// visible-record compaction (record order) with the depth key
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) compact_kernel(const uint32_t* __restrict__ count, const float4* __restrict__ pa,
+                                                      const uint32_t* __restrict__ vis_off, uint32_t n_records,
+                                                      uint32_t* __restrict__ dkeys, uint32_t* __restrict__ dvals) {
   const uint32_t rec = blockIdx.x * blockDim.x + threadIdx.x;
-  if (rec >= n_records) return;
-  const uint32_t c = count[rec];
-  if (c == 0) return;
-  const ViewDesc& V = tab->views[view_of_record(tab, rec)];
-  const uint2 r = rect[rec];
-  const uint32_t tx0 = r.x & 0xffffu, tx1 = r.x >> 16, ty0 = r.y & 0xffffu, ty1 = r.y >> 16;
-  const uint32_t zbits = __float_as_uint(pa[rec].z);
-  uint32_t off = offsets[rec];
-  if (off + c > capacity || off + c < off) cnt->overflow = 1u;
-  for (uint32_t ty = ty0; ty <= ty1; ++ty)
-    for (uint32_t tx = tx0; tx <= tx1; ++tx) {
-      if (off < capacity) {
-        const uint64_t tile = (uint64_t)(V.tile_base + ty * (uint32_t)V.tiles_x + tx);
-        keys[off] = (tile << 32) | zbits;
-        vals[off] = rec;
-      }
-      ++off;
+  if (rec >= n_records || count[rec] == 0u) return;
+  const uint32_t pos = vis_off[rec];
+  dkeys[pos] = __float_as_uint(reinterpret_cast<const float*>(pa)[4 * (size_t)rec + 2]);
+  dvals[pos] = rec;
+}
+
+// Tile counts in depth order, zero past the last visible record.
+__global__ void __launch_bounds__(256) gather_counts_kernel(const uint32_t* __restrict__ sorted_rec,
+                                                            const uint32_t* __restrict__ count,
+                                                            const uint32_t* __restrict__ n_visible, uint32_t n_records,
+                                                            uint32_t* __restrict__ out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_records) return;
+  out[i] = i < clamped(n_visible, n_records) ? count[sorted_rec[i]] : 0u;
+}
+
+// ---------------------------------------------------------------------------
+// pair emission in depth order
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void emit_range(uint32_t k0, uint32_t k1, uint32_t stride, uint32_t off, uint32_t rec,
+                                           uint32_t tile0, uint32_t w, uint32_t tiles_x, uint32_t capacity,
+                                           uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  for (uint32_t k = k0; k < k1; k += stride) {
+    const uint32_t p = off + k;
+    if (p < capacity) {
+      keys[p] = tile0 + (k / w) * tiles_x + (k % w);
+      vals[p] = rec;
     }
+  }
+}
+
+constexpr uint32_t kSmallFootprint = 8;  // records with more tiles are emitted by the whole wavefront
+
+__global__ void __launch_bounds__(256) emit_kernel(const CallTables* __restrict__ tab, const uint2* __restrict__ rect,
+                                                   const uint32_t* __restrict__ count,
+                                                   const uint32_t* __restrict__ sorted_rec,
+                                                   const uint32_t* __restrict__ pair_off,
+                                                   const uint32_t* __restrict__ n_visible, Counters* __restrict__ cnt,
+                                                   uint32_t n_records, uint32_t capacity, uint32_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ vals) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nv = clamped(n_visible, n_records);
+  const int lane = threadIdx.x & 63;
+  uint32_t rec = 0, c = 0, off = 0, tile0 = 0, w = 1, tiles_x = 1;
+  if (i < nv) {
+    rec = sorted_rec[i];
+    c = count[rec];
+    off = pair_off[i];
+    const ViewDesc& V = tab->views[view_of_record(tab, rec)];
+    const uint2 r = rect[rec];
+    const uint32_t tx0 = r.x & 0xffffu, tx1 = r.x >> 16, ty0 = r.y & 0xffffu;
+    tiles_x = (uint32_t)V.tiles_x;
+    w = tx1 - tx0 + 1u;
+    tile0 = V.tile_base + ty0 * tiles_x + tx0;
+    if (off + c > capacity || off + c < off) cnt->overflow = 1u;
+  }
+  if (c <= kSmallFootprint) emit_range(0, c, 1, off, rec, tile0, w, tiles_x, capacity, keys, vals);
+  // large footprints: the wavefront emits them one at a time, lanes over tiles
+  uint64_t big = __ballot(c > kSmallFootprint);
+  while (big != 0ull) {
+    const int src = __ffsll((unsigned long long)big) - 1;
+    big &= big - 1ull;
+    const uint32_t bc = __shfl(c, src, 64), boff = __shfl(off, src, 64), brec = __shfl(rec, src, 64);
+    const uint32_t bt0 = __shfl(tile0, src, 64), bw = __shfl(w, src, 64), btx = __shfl(tiles_x, src, 64);
+    emit_range((uint32_t)lane, bc, 64, boff, brec, bt0, bw, btx, capacity, keys, vals);
+  }
 }
 
 // ---------------------------------------------------------------------------
-// radix sort: 8-bit digits, 4096 pairs per block (4 waves x 1024 contiguous)
+// stable LSD radix sort, 8-bit digits, 4096 keys per workgroup
 // ---------------------------------------------------------------------------
 
-constexpr int kSortBlock = 256;
-constexpr int kWaves = kSortBlock / 64;
-constexpr int kRounds = 16;                              // 64-key rounds per wave
-constexpr uint32_t kSortTile = kSortBlock * kRounds;     // 4096
-constexpr int kRadix = 256;
-
-__device__ __forceinline__ uint32_t pair_count(const Counters* cnt, uint32_t capacity) {
-  const uint32_t p = cnt->pairs;
-  return p < capacity ? p : capacity;
-}
-
-// Lanes of the wave holding the same 8-bit digit (among the active lanes).
+// Lanes of the wavefront holding the same 8-bit digit (among active lanes).
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {
   uint64_t peers = active;
 #pragma unroll
@@ -79,14 +133,14 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-__global__ void __launch_bounds__(kSortBlock) radix_hist_kernel(const uint64_t* __restrict__ keys,
-                                                                const Counters* __restrict__ cnt, uint32_t capacity,
-                                                                int shift, uint32_t* __restrict__ hist) {
+template <class K>
+__global__ void __launch_bounds__(kSortBlock) radix_hist_kernel(const K* __restrict__ keys, const uint32_t* __restrict__ n_ptr,
+                                                                uint32_t capacity, int shift, uint32_t* __restrict__ hist) {
   __shared__ uint32_t wcnt[kWaves][kRadix];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int d = threadIdx.x; d < kWaves * kRadix; d += kSortBlock) (&wcnt[0][0])[d] = 0;
   __syncthreads();
-  const uint32_t n = pair_count(cnt, capacity);
+  const uint32_t n = clamped(n_ptr, capacity);
   const uint32_t base = blockIdx.x * kSortTile + wave * (kSortTile / kWaves);
   if (blockIdx.x * kSortTile < n) {
     for (int r = 0; r < kRounds; ++r) {
@@ -107,32 +161,33 @@ __global__ void __launch_bounds__(kSortBlock) radix_hist_kernel(const uint64_t* 
   hist[(size_t)d * gridDim.x + blockIdx.x] = s;
 }
 
-__global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const uint64_t* __restrict__ keys_in,
+template <class K>
+__global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __restrict__ keys_in,
                                                                    const uint32_t* __restrict__ vals_in,
-                                                                   uint64_t* __restrict__ keys_out,
-                                                                   uint32_t* __restrict__ vals_out,
-                                                                   const Counters* __restrict__ cnt, uint32_t capacity,
+                                                                   K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+                                                                   const uint32_t* __restrict__ n_ptr, uint32_t capacity,
                                                                    int shift, const uint32_t* __restrict__ hist_scan) {
   __shared__ uint32_t wcnt[kWaves][kRadix];   // per-wave digit counts, then per-wave prefixes
   __shared__ uint32_t dstart[kRadix];         // block-local first position of each digit
   __shared__ uint32_t gbase[kRadix];          // global first position of each digit for this block
-  __shared__ uint64_t skeys[kSortTile];
+  __shared__ uint32_t wsum[kWaves];
+  __shared__ K skeys[kSortTile];
   __shared__ uint32_t svals[kSortTile];
-  const uint32_t n = pair_count(cnt, capacity);
+  const uint32_t n = clamped(n_ptr, capacity);
   if (blockIdx.x * kSortTile >= n) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int d = threadIdx.x; d < kWaves * kRadix; d += kSortBlock) (&wcnt[0][0])[d] = 0;
   __syncthreads();
 
   const uint32_t base = blockIdx.x * kSortTile + wave * (kSortTile / kWaves);
-  uint64_t k[kRounds];
+  K k[kRounds];
   uint32_t v[kRounds];
   uint32_t loc[kRounds];
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t idx = base + r * 64 + lane;
     const bool ok = idx < n;
-    k[r] = ok ? keys_in[idx] : 0ull;
+    k[r] = ok ? keys_in[idx] : (K)0;
     v[r] = ok ? vals_in[idx] : 0u;
     const uint32_t d = (uint32_t)(k[r] >> shift) & 0xffu;
     const uint64_t active = __ballot(ok);
@@ -143,7 +198,7 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const uint64_
   }
   __syncthreads();
   {
-    // per-digit: prefix over waves, block total; then exclusive scan over digits
+    // per digit: prefix over waves and block total, then a scan over digits
     const int d = threadIdx.x;
     uint32_t run = 0;
 #pragma unroll
@@ -152,14 +207,12 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const uint64_
       wcnt[w][d] = run;
       run += c;
     }
-    // block-wide exclusive scan of run over the 256 digits
     uint32_t incl = run;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
       const uint32_t t = __shfl_up(incl, off, 64);
       if (lane >= off) incl += t;
     }
-    __shared__ uint32_t wsum[kWaves];
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
     uint32_t wb = 0;
@@ -181,7 +234,7 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const uint64_
   __syncthreads();
   const uint32_t tile_n = min(kSortTile, n - blockIdx.x * kSortTile);
   for (uint32_t p = threadIdx.x; p < tile_n; p += kSortBlock) {
-    const uint64_t key = skeys[p];
+    const K key = skeys[p];
     const uint32_t d = (uint32_t)(key >> shift) & 0xffu;
     const uint32_t g = gbase[d] + (p - dstart[d]);
     keys_out[g] = key;
@@ -189,44 +242,17 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const uint64_
   }
 }
 
-// ---------------------------------------------------------------------------
-// ranges
-// ---------------------------------------------------------------------------
-
-__global__ void ranges_kernel(const uint64_t* __restrict__ keys, const Counters* __restrict__ cnt, uint32_t capacity,
-                              uint2* __restrict__ ranges, uint32_t n_tiles) {
-  const uint32_t n = pair_count(cnt, capacity);
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  const uint32_t t = (uint32_t)(keys[k] >> 32);
-  if (t >= n_tiles) return;
-  if (k == 0 || (uint32_t)(keys[k - 1] >> 32) != t) ranges[t].x = k;
-  if (k == n - 1 || (uint32_t)(keys[k + 1] >> 32) != t) ranges[t].y = k + 1;
-}
-
 inline uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
-}  // namespace
-
-hipError_t launch_emit(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb, const uint32_t* offsets,
-                       Counters* cnt, uint64_t* keys, uint32_t* vals, uint32_t capacity, int tile_w, int tile_h,
-                       hipStream_t s) {
-  (void)tile_w; (void)tile_h;
-  if (h_tab.n_records == 0) return hipSuccess;
-  hipLaunchKernelGGL(emit_kernel, dim3(div_up(h_tab.n_records, 256)), dim3(256), 0, s, d_tab, pb.rect, pb.count, pb.a,
-                     offsets, cnt, keys, vals, h_tab.n_records, capacity);
-  return hipGetLastError();
-}
-
-size_t sort_workspace_bytes(uint32_t capacity) {
+size_t radix_ws_bytes(uint32_t capacity) {
   const uint32_t blocks = div_up(capacity > 0 ? capacity : 1, kSortTile);
-  const size_t hist = (size_t)blocks * kRadix * sizeof(uint32_t);
-  const size_t h = (hist + 255) / 256 * 256;
+  const size_t h = ((size_t)blocks * kRadix * sizeof(uint32_t) + 255) / 256 * 256;
   return 2 * h + scan_workspace_bytes(blocks * kRadix) + 256;
 }
 
-hipError_t launch_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, uint32_t capacity,
-                       int key_bits, const Counters* cnt, void* ws, int* result_in_alt, hipStream_t s) {
+template <class K>
+hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, uint32_t capacity, int key_bits,
+                      const uint32_t* n_ptr, void* ws, int* result_in_alt, hipStream_t s) {
   *result_in_alt = 0;
   if (capacity == 0) return hipSuccess;
   const uint32_t blocks = div_up(capacity, kSortTile);
@@ -234,20 +260,20 @@ hipError_t launch_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint3
   uint32_t* hist = static_cast<uint32_t*>(ws);
   uint32_t* hist_scan = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + hist_bytes);
   void* scan_ws = static_cast<char*>(ws) + 2 * hist_bytes;
-  uint64_t* kin = keys; uint32_t* vin = vals;
-  uint64_t* kout = keys_alt; uint32_t* vout = vals_alt;
+  K* kin = keys; uint32_t* vin = vals;
+  K* kout = keys_alt; uint32_t* vout = vals_alt;
   int alt = 0;
   for (int shift = 0; shift < key_bits; shift += 8) {
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(blocks), dim3(kSortBlock), 0, s, kin, cnt, capacity, shift, hist);
+    hipLaunchKernelGGL(radix_hist_kernel<K>, dim3(blocks), dim3(kSortBlock), 0, s, kin, n_ptr, capacity, shift, hist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_scan(hist, hist_scan, blocks * kRadix, nullptr, scan_ws, s);
+    e = launch_scan(hist, hist_scan, blocks * kRadix, nullptr, scan_ws, s, false);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3(blocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout, cnt, capacity,
-                       shift, hist_scan);
+    hipLaunchKernelGGL(radix_scatter_kernel<K>, dim3(blocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout, n_ptr,
+                       capacity, shift, hist_scan);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    uint64_t* tk = kin; kin = kout; kout = tk;
+    K* tk = kin; kin = kout; kout = tk;
     uint32_t* tv = vin; vin = vout; vout = tv;
     alt ^= 1;
   }
@@ -255,11 +281,83 @@ hipError_t launch_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint3
   return hipSuccess;
 }
 
-hipError_t launch_ranges(const uint64_t* keys, const Counters* cnt, uint32_t capacity, uint2* ranges, uint32_t n_tiles,
-                         hipStream_t s) {
+// ---------------------------------------------------------------------------
+// ranges and key export
+// ---------------------------------------------------------------------------
+__global__ void ranges_kernel(const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ n_ptr,
+                              uint32_t capacity, uint2* __restrict__ ranges, uint32_t n_tiles) {
+  const uint32_t n = clamped(n_ptr, capacity);
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t t = tiles[k];
+  if (t >= n_tiles) return;
+  if (k == 0 || tiles[k - 1] != t) ranges[t].x = k;
+  if (k == n - 1 || tiles[k + 1] != t) ranges[t].y = k + 1;
+}
+
+__global__ void key64_kernel(const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ recs,
+                             const float4* __restrict__ pa, const uint32_t* __restrict__ n_ptr, uint32_t capacity,
+                             uint64_t* __restrict__ out) {
+  const uint32_t n = clamped(n_ptr, capacity);
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= capacity) return;
+  out[k] = k < n ? ((uint64_t)tiles[k] << 32) |
+                       __float_as_uint(reinterpret_cast<const float*>(pa)[4 * (size_t)recs[k] + 2])
+                 : 0ull;
+}
+
+}  // namespace
+
+size_t sort_workspace_bytes(uint32_t capacity) { return radix_ws_bytes(capacity); }
+
+hipError_t launch_depth_order(const CallTables& h, const ProjBuffers pb, const uint32_t* vis_off,
+                              const uint32_t* n_visible, DepthOrder d, void* ws, hipStream_t s) {
+  const uint32_t R = h.n_records;
+  if (R == 0) return launch_fill_u32(d.pair_off_total, 0u, 1, s);
+  hipLaunchKernelGGL(compact_kernel, dim3(div_up(R, 256)), dim3(256), 0, s, pb.count, pb.a, vis_off, R, d.keys,
+                     d.vals);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int alt = 0;
+  e = radix_sort<uint32_t>(d.keys, d.vals, d.keys_alt, d.vals_alt, R, 32, n_visible, ws, &alt, s);
+  if (e != hipSuccess) return e;
+  const uint32_t* sorted = alt ? d.vals_alt : d.vals;
+  *d.sorted_in_alt = alt;
+  hipLaunchKernelGGL(gather_counts_kernel, dim3(div_up(R, 256)), dim3(256), 0, s, sorted, pb.count, n_visible, R,
+                     d.counts);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_scan(d.counts, d.pair_off, R, d.pair_off_total, d.scan_ws, s, false);
+}
+
+hipError_t launch_emit(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb, const uint32_t* sorted_rec,
+                       const uint32_t* pair_off, const uint32_t* n_visible, Counters* cnt, uint32_t* keys,
+                       uint32_t* vals, uint32_t capacity, hipStream_t s) {
+  if (h.n_records == 0) return hipSuccess;
+  hipLaunchKernelGGL(emit_kernel, dim3(div_up(h.n_records, 256)), dim3(256), 0, s, d_tab, pb.rect, pb.count,
+                     sorted_rec, pair_off, n_visible, cnt, h.n_records, capacity, keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, uint32_t capacity,
+                       int key_bits, const Counters* cnt, void* ws, int* result_in_alt, hipStream_t s) {
+  return radix_sort<uint32_t>(keys, vals, keys_alt, vals_alt, capacity, key_bits, &cnt->pairs, ws, result_in_alt, s);
+}
+
+hipError_t launch_ranges(const uint32_t* tiles, const Counters* cnt, uint32_t capacity, uint2* ranges,
+                         uint32_t n_tiles, hipStream_t s) {
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * (size_t)n_tiles, s);
   if (e != hipSuccess || capacity == 0) return e;
-  hipLaunchKernelGGL(ranges_kernel, dim3(div_up(capacity, 256)), dim3(256), 0, s, keys, cnt, capacity, ranges, n_tiles);
+  hipLaunchKernelGGL(ranges_kernel, dim3(div_up(capacity, 256)), dim3(256), 0, s, tiles, &cnt->pairs, capacity, ranges,
+                     n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_key64(const uint32_t* tiles, const uint32_t* recs, const ProjBuffers pb, const Counters* cnt,
+                        uint32_t capacity, uint64_t* out, hipStream_t s) {
+  if (capacity == 0) return hipSuccess;
+  hipLaunchKernelGGL(key64_kernel, dim3(div_up(capacity, 256)), dim3(256), 0, s, tiles, recs, pb.a, &cnt->pairs,
+                     capacity, out);
   return hipGetLastError();
 }
 
