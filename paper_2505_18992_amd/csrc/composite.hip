@@ -1,7 +1,8 @@
 // composite.hip -- per-tile front-to-back alpha compositing and its
 // backward.
 //
-// One workgroup per (view, tile); one thread per pixel.  Each tile walks its
+// One workgroup per (view, tile); one thread per pixel, each wavefront an
+// 8x8 quadrant of the tile.  Each tile walks its
 // depth-sorted slice of the pair list in batches staged in LDS (every pixel
 // of the tile reads the same Gaussian, so LDS reads broadcast).  A pixel
 // stops at the first Gaussian that would take its transmittance under 1e-4;
@@ -53,25 +54,89 @@ __device__ __forceinline__ Falloff falloff(const float4 A, const float4 E, float
   return f;
 }
 
+// Hit lists are padded to a multiple of kGroup entries with a sentinel slot
+// (index BS, staged once per workgroup) whose exponent is -inf, so alpha is 0
+// there and nothing is blended; the per-pixel loops then run whole groups
+// without per-entry bounds tests, and the forward checks for early
+// termination between groups.
+constexpr int kGroup = 8;
+constexpr float kNegInf = -__builtin_inff();
+
 template <int TW, int TH>
 struct FwdShared {
-  float4 A[TW * TH], E[TW * TH], C[TW * TH];
+  float4 A[TW * TH + 1], E[TW * TH + 1], C[TW * TH + 1], X[TW * TH];
+  uint16_t hits[(TW * TH) / 64][TW * TH + kGroup];  // per wavefront: staged entries that meet its quadrant
 };
+
+// Each wavefront owns an 8x8 quadrant of its tile (lane -> (lane % 8,
+// lane / 8)); a Gaussian whose padded box misses the quadrant cannot reach
+// alpha >= 1/255 there, so the wavefront leaves it out of its hit list.
+template <int TW, int TH>
+struct Quadrant {
+  int px, py;            // this thread's pixel
+  float x0, x1, y0, y1;  // pixel-centre bounds of the wavefront's quadrant
+  __device__ __forceinline__ Quadrant(int tx, int ty) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int qx = wave % (TW / 8), qy = wave / (TW / 8);
+    const int bx = tx * TW + qx * 8, by = ty * TH + qy * 8;
+    px = bx + (lane & 7);
+    py = by + (lane >> 3);
+    x0 = (float)bx + 0.5f;
+    x1 = x0 + 7.0f;
+    y0 = (float)by + 0.5f;
+    y1 = y0 + 7.0f;
+  }
+  __device__ __forceinline__ bool meets(const float4 box) const {
+    return !(box.y < x0 || box.x > x1 || box.w < y0 || box.z > y1);
+  }
+};
+
+// Compacts the staged entries [0, n) whose padded box meets the wavefront's
+// quadrant into list[] -- in staging order, or in reverse order if DESC --
+// pads it with the sentinel index BS to a multiple of kGroup and returns the
+// number of hits (the same in every lane).  Lane l tests entries l, l + 64,
+// ...; a ballot and a lane-prefix count give each hit its slot.  All lanes
+// of the wavefront must be active; the list is read after the next
+// workgroup barrier.
+template <int BS, bool DESC, int TW, int TH>
+__device__ __forceinline__ int wave_hits(const float4* X, int n, const Quadrant<TW, TH>& q, uint16_t* list) {
+  const int lane = threadIdx.x & 63;
+  int count = 0;
+#pragma unroll
+  for (int k = 0; k < BS / 64; ++k) {
+    const int e = DESC ? n - 1 - (k * 64 + lane) : k * 64 + lane;
+    const bool hit = (DESC ? e >= 0 : e < n) && q.meets(X[e]);
+    const uint64_t m = __ballot(hit);
+    const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if (hit) list[count + below] = (uint16_t)e;
+    count += __popcll(m);
+  }
+  if (lane < ((count + kGroup - 1) & ~(kGroup - 1)) - count) list[count + lane] = (uint16_t)BS;
+  return count;
+}
+
+// Padded box of the opacity-aware ellipse: [u - hx - 1, u + hx + 1] x [v - hy - 1, v + hy + 1].
+__device__ __forceinline__ float4 stage_box(const float4 A, const float2 h) {
+  return make_float4(A.x - h.x - 1.0f, A.x + h.x + 1.0f, A.y - h.y - 1.0f, A.y + h.y + 1.0f);
+}
 
 template <int TW, int TH>
 __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab, const float4* __restrict__ pa,
                                              const float4* __restrict__ pb, const float4* __restrict__ pc,
-                                             const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
-                                             float* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
-                                             uint32_t tile, FwdShared<TW, TH>& sh, uint32_t& ne, uint32_t& nb) {
+                                             const float2* __restrict__ ext, const uint2* __restrict__ ranges,
+                                             const uint32_t* __restrict__ vals, float* __restrict__ T_final,
+                                             uint32_t* __restrict__ n_contrib, uint32_t tile, FwdShared<TW, TH>& sh,
+                                             uint32_t& ne, uint32_t& nb) {
   constexpr int BS = TW * TH;
   const ViewDesc& V = tab->views[view_of_tile(tab, tile)];
   const uint32_t lt = tile - V.tile_base;
   const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
-  const int px = tx * TW + (int)(threadIdx.x % TW), py = ty * TH + (int)(threadIdx.x / TW);
+  const Quadrant<TW, TH> q(tx, ty);
+  const int px = q.px, py = q.py;
   const bool inside = px < V.W && py < V.H;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
   const uint2 rg = ranges[tile];
+  uint16_t* hits = sh.hits[threadIdx.x >> 6];
 
   float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
   uint32_t last = 0;
@@ -86,16 +151,20 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
       sh.A[threadIdx.x] = A;
       sh.E[threadIdx.x] = stage_exponent(A, pb[rec]);
       sh.C[threadIdx.x] = pc[rec];
+      sh.X[threadIdx.x] = stage_box(A, ext[rec]);
     }
     __syncthreads();
-    const int nbat = (int)min((uint32_t)BS, rg.y - start);
-    if (__ballot(!done) != 0ull) {
-      const uint32_t base = start - rg.x + 1u;
-      for (int j = 0; j < nbat; ++j) {
+    const int nhit = wave_hits<BS, false>(sh.X, (int)min((uint32_t)BS, rg.y - start), q, hits);
+    __syncthreads();
+    const uint32_t base = start - rg.x + 1u;
+    for (int g = 0; g < nhit && __ballot(!done) != 0ull; g += kGroup) {
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) {
+        const int j = hits[g + u];
         const float4 A = sh.A[j];
         const Falloff f = falloff(A, sh.E[j], pxc, pyc);
         const float4 c = sh.C[j];
-        ne += done ? 0u : 1u;
+        ne += (g + u < nhit && !done) ? 1u : 0u;
         const bool ok = !done && f.alpha >= kAlphaMin;
         const float Tn = T * (1.0f - f.alpha);
         const bool stop = ok && Tn < kTransMin;
@@ -109,7 +178,6 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
         last = blend ? base + (uint32_t)j : last;
         nb += blend ? 1u : 0u;
         done = done || stop;
-        if ((j & 7) == 7 && __ballot(!done) == 0ull) break;
       }
     }
   }
@@ -155,17 +223,22 @@ __device__ __forceinline__ uint32_t next_tile(uint32_t* queue, uint32_t* slot) {
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
     const CallTables* __restrict__ tab, const float4* __restrict__ pa, const float4* __restrict__ pb,
-    const float4* __restrict__ pc, const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
-    float* __restrict__ T_final, uint32_t* __restrict__ n_contrib, Counters* __restrict__ cnt,
-    uint32_t* __restrict__ queue, uint32_t n_tiles) {
+    const float4* __restrict__ pc, const float2* __restrict__ ext, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ vals, float* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
+    Counters* __restrict__ cnt, uint32_t* __restrict__ queue, uint32_t n_tiles) {
   __shared__ FwdShared<TW, TH> sh;
   __shared__ uint32_t slot;
   uint32_t ne = 0, nb = 0;
+  if (threadIdx.x == 0) {  // the sentinel slot (read after the first staging barrier)
+    sh.A[TW * TH] = make_float4(0.f, 0.f, 0.f, 0.f);
+    sh.E[TW * TH] = make_float4(0.f, 0.f, 0.f, kNegInf);
+    sh.C[TW * TH] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   if (queue == nullptr) {
-    forward_tile<TW, TH>(tab, pa, pb, pc, ranges, vals, T_final, n_contrib, blockIdx.x, sh, ne, nb);
+    forward_tile<TW, TH>(tab, pa, pb, pc, ext, ranges, vals, T_final, n_contrib, blockIdx.x, sh, ne, nb);
   } else {
     for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot))
-      forward_tile<TW, TH>(tab, pa, pb, pc, ranges, vals, T_final, n_contrib, t, sh, ne, nb);
+      forward_tile<TW, TH>(tab, pa, pb, pc, ext, ranges, vals, T_final, n_contrib, t, sh, ne, nb);
   }
   flush_counts(ne, nb, cnt);
 }
@@ -216,23 +289,25 @@ __device__ __forceinline__ int scatter_slot(int lane) {
 
 template <int TW, int TH>
 struct BwdShared {
-  float4 A[TW * TH], E[TW * TH], B[TW * TH], C[TW * TH];
+  float4 A[TW * TH + 1], E[TW * TH + 1], B[TW * TH + 1], C[TW * TH + 1], X[TW * TH];
   uint32_t rec[TW * TH];
+  uint16_t hits[(TW * TH) / 64][TW * TH + kGroup];  // per wavefront, descending
   uint32_t maxlast[(TW * TH) / 64];
 };
 
 template <int TW, int TH>
 __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab, const float4* __restrict__ pa,
                                               const float4* __restrict__ pb, const float4* __restrict__ pc,
-                                              const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
-                                              const float* __restrict__ T_final,
+                                              const float2* __restrict__ ext, const uint2* __restrict__ ranges,
+                                              const uint32_t* __restrict__ vals, const float* __restrict__ T_final,
                                               const uint32_t* __restrict__ n_contrib, float* __restrict__ acc,
                                               uint32_t tile, BwdShared<TW, TH>& sh) {
   constexpr int BS = TW * TH;
   const ViewDesc& V = tab->views[view_of_tile(tab, tile)];
   const uint32_t lt = tile - V.tile_base;
   const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
-  const int px = tx * TW + (int)(threadIdx.x % TW), py = ty * TH + (int)(threadIdx.x / TW);
+  const Quadrant<TW, TH> q(tx, ty);
+  const int px = q.px, py = q.py;
   const bool inside = px < V.W && py < V.H;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
   const uint2 rg = ranges[tile];
@@ -276,12 +351,17 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
         sh.E[threadIdx.x] = stage_exponent(A, B);
         sh.B[threadIdx.x] = make_float4(B.x, B.y, B.z, 1.0f / A.w);
         sh.C[threadIdx.x] = pc[rec];
+        sh.X[threadIdx.x] = stage_box(A, ext[rec]);
       }
     }
     __syncthreads();
-    const int jtop = min(end, (int)wave_last) - 1;
-    for (int j = jtop; j >= begin; --j) {
-      const int sl = j - begin;
+    // entries of this wavefront: those before its own last blended one
+    uint16_t* hits = sh.hits[threadIdx.x >> 6];
+    const int nhit = wave_hits<BS, true>(sh.X, min(end, (int)wave_last) - begin, q, hits);
+    __syncthreads();
+    for (int i = 0; i < nhit; ++i) {
+      const int sl = hits[i];
+      const int j = begin + sl;
       const float4 A = sh.A[sl];
       const Falloff f = falloff(A, sh.E[sl], pxc, pyc);
       const bool valid = (uint32_t)j < last && f.alpha >= kAlphaMin;
@@ -319,14 +399,18 @@ __global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
     const CallTables* __restrict__ tab, const float4* __restrict__ pa, const float4* __restrict__ pb,
     const float4* __restrict__ pc, const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib, float* __restrict__ acc,
-    uint32_t* __restrict__ queue, uint32_t n_tiles) {
+    const float2* __restrict__ ext, uint32_t* __restrict__ queue, uint32_t n_tiles) {
   __shared__ BwdShared<TW, TH> sh;
   __shared__ uint32_t slot;
+  if (threadIdx.x == 0) {  // the sentinel slot (read after the first staging barrier)
+    sh.A[TW * TH] = make_float4(0.f, 0.f, 0.f, 0.f);
+    sh.E[TW * TH] = make_float4(0.f, 0.f, 0.f, kNegInf);
+  }
   if (queue == nullptr) {
-    backward_tile<TW, TH>(tab, pa, pb, pc, ranges, vals, T_final, n_contrib, acc, blockIdx.x, sh);
+    backward_tile<TW, TH>(tab, pa, pb, pc, ext, ranges, vals, T_final, n_contrib, acc, blockIdx.x, sh);
   } else {
     for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot))
-      backward_tile<TW, TH>(tab, pa, pb, pc, ranges, vals, T_final, n_contrib, acc, t, sh);
+      backward_tile<TW, TH>(tab, pa, pb, pc, ext, ranges, vals, T_final, n_contrib, acc, t, sh);
   }
 }
 
@@ -336,7 +420,7 @@ hipError_t launch_fwd_t(const CallTables* d_tab, const CallTables& h, const Proj
                         uint32_t blocks, hipStream_t s) {
   const uint32_t grid = queue ? blocks : h.n_tiles;
   hipLaunchKernelGGL((composite_forward_kernel<TW, TH>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.a, pb.b, pb.c,
-                     ranges, vals, T_final, n_contrib, cnt, queue, h.n_tiles);
+                     pb.ext, ranges, vals, T_final, n_contrib, cnt, queue, h.n_tiles);
   return hipGetLastError();
 }
 
@@ -346,7 +430,7 @@ hipError_t launch_bwd_t(const CallTables* d_tab, const CallTables& h, const Proj
                         uint32_t* queue, uint32_t blocks, hipStream_t s) {
   const uint32_t grid = queue ? blocks : h.n_tiles;
   hipLaunchKernelGGL((composite_backward_kernel<TW, TH>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.a, pb.b, pb.c,
-                     ranges, vals, T_final, n_contrib, acc, queue, h.n_tiles);
+                     ranges, vals, T_final, n_contrib, acc, pb.ext, queue, h.n_tiles);
   return hipGetLastError();
 }
 

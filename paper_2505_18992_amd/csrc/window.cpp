@@ -183,7 +183,7 @@ int vpgs_window_create(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, in
   else for (auto& s : kShapes) shapes.push_back({s[0], s[1]});
   std::vector<int> modes;
   if (o.persistent >= 0) modes.push_back(o.persistent);
-  else { modes.push_back(0); modes.push_back(4 * cus); }
+  else { modes.push_back(0); modes.push_back(4 * cus); modes.push_back(8 * cus); }
 
   float best_ms = 1e30f;
   int best_tw = shapes[0].first, best_th = shapes[0].second, best_mode = modes[0];
