@@ -246,45 +246,57 @@ __global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
 // ---------------------------------------------------------------------------
 // wavefront reduce-scatter of the 10 per-Gaussian gradient values
 // ---------------------------------------------------------------------------
-// Recursive halving over 16 slots (10 used): each step pairs a lane with one
-// that differs in one "keep" bit (2, 3, 4, 5 in turn), keeps half of its
-// slots and adds the partner's copy of them; the last two steps sum the
-// remaining lanes of each quad.  Lane L ends with the wave total of slot
-// 8*b2 + 4*b3 + 2*b4 + b5 (b = bits of L).  The pairings are lane xor 7
-// (DPP row half-mirror), xor 8 (DPP row rotate by 8), xor 16 (swizzle),
-// xor 32 (permute), xor 1 and xor 2 (DPP quad permutations).  All lanes of
-// the wavefront must be active.
+// Recursive halving of the 10 values: each step pairs a lane with the one
+// that differs in one lane-index bit, keeps half of its values and adds the
+// partner's copy of them; a value without a pair is summed in both lanes.
+//   bit 5: g[i] with g[5 + i] (v_permlane32_swap exchanges the upper half of
+//          one register with the lower half of another, so one swap and one
+//          add do a whole pair)                            10 -> 5 values
+//   bit 4: (h0, h3) and (h1, h4) by v_permlane16_swap, h2 in both  5 -> 3
+//   bit 3: (a, b) by DPP row rotate 8 (lane xor 8), c in both     3 -> 2
+//   bit 2: (x, c) by DPP row half-mirror (lane xor 7)             2 -> 1
+//   bits 0-1: sums over the quad (DPP quad permutations).
+// Lane L ends with the wave total of slot 5 b5 + (b2 ? 2 : 3 b4 + b3) (b =
+// bits of L), 25 VALU operations in all.  All lanes of the wavefront must be
+// active.
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
-__device__ __forceinline__ float swz16(float v) {
-  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+__device__ __forceinline__ float pair_sum32(float lo, float hi) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float pair_sum16(float lo, float hi) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
 __device__ __forceinline__ float wave_reduce_scatter10(const float g[kNumAcc], int lane) {
-  const bool b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1, b4 = (lane >> 4) & 1, b5 = (lane >> 5) & 1;
-  float h[8];
+  const bool b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+  float h[5];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {  // slots i and 8 + i (slots >= 10 are zero)
-    const float lo = g[i];
-    const float hi = (8 + i < kNumAcc) ? g[8 + i] : 0.0f;
-    h[i] = (b2 ? hi : lo) + dpp<0x141>(b2 ? lo : hi);
-  }
-  float q[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) q[i] = (b3 ? h[4 + i] : h[i]) + dpp<0x128>(b3 ? h[i] : h[4 + i]);
-  float r[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) r[i] = (b4 ? q[2 + i] : q[i]) + swz16(b4 ? q[i] : q[2 + i]);
-  float t = (b5 ? r[1] : r[0]) + __shfl_xor(b5 ? r[0] : r[1], 32, 64);
+  for (int i = 0; i < 5; ++i) h[i] = pair_sum32(g[i], g[5 + i]);
+  const float a = pair_sum16(h[0], h[3]);
+  const float b = pair_sum16(h[1], h[4]);
+  float c = pair_sum16(h[2], h[2]);
+  const float x = (b3 ? b : a) + dpp<0x128>(b3 ? a : b);  // row_ror:8
+  c += dpp<0x128>(c);
+  float t = (b2 ? c : x) + dpp<0x141>(b2 ? x : c);        // row_half_mirror
   t += dpp<0xB1>(t);  // quad_perm [1,0,3,2]
   t += dpp<0x4E>(t);  // quad_perm [2,3,0,1]
   return t;
 }
 
 __device__ __forceinline__ int scatter_slot(int lane) {
-  return (((lane >> 2) & 1) << 3) | (((lane >> 3) & 1) << 2) | (((lane >> 4) & 1) << 1) | ((lane >> 5) & 1);
+  const int b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1, b4 = (lane >> 4) & 1, b5 = (lane >> 5) & 1;
+  return 5 * b5 + (b2 ? 2 : 3 * b4 + b3);
+}
+
+// One lane per slot: the first lane of a quad, and for slot 5 b5 + 2 (held
+// by every lane with b2 set) only the one with b3 = b4 = 0.
+__device__ __forceinline__ bool scatter_writer(int lane) {
+  return (lane & 3) == 0 && (((lane >> 2) & 1) == 0 || ((lane >> 3) & 3) == 0);
 }
 
 template <int TW, int TH>
@@ -313,7 +325,7 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
   const uint2 rg = ranges[tile];
   const int lane = threadIdx.x & 63;
   const int slot_id = scatter_slot(lane);
-  const bool writer = (lane & 3) == 0 && slot_id < kNumAcc;
+  const bool writer = scatter_writer(lane);
 
   const size_t HW = (size_t)V.W * V.H;
   const size_t pix = inside ? (size_t)py * V.W + px : 0;
