@@ -60,17 +60,18 @@ __device__ __forceinline__ Falloff falloff(const float4 A, const float4 E, float
 // without per-entry bounds tests, and the forward checks for early
 // termination between groups.
 constexpr int kGroup = 8;
+constexpr float kLog2AlphaMin = -7.99435343685885793769f;  // log2(1/255)
 constexpr float kNegInf = -__builtin_inff();
 
 template <int TW, int TH>
 struct FwdShared {
-  float4 A[TW * TH + 1], E[TW * TH + 1], C[TW * TH + 1], X[TW * TH];
-  uint16_t hits[(TW * TH) / 64][TW * TH + kGroup];  // per wavefront: staged entries that meet its quadrant
+  float4 A[TW * TH + 1], E[TW * TH + 1], C[TW * TH + 1];
+  uint16_t hits[(TW * TH) / 64][TW * TH + kGroup];  // per wavefront: staged entries that reach its quadrant
 };
 
 // Each wavefront owns an 8x8 quadrant of its tile (lane -> (lane % 8,
-// lane / 8)); a Gaussian whose padded box misses the quadrant cannot reach
-// alpha >= 1/255 there, so the wavefront leaves it out of its hit list.
+// lane / 8)) and keeps in its hit list only the Gaussians that can reach
+// alpha >= 1/255 at one of the quadrant's pixel centres.
 template <int TW, int TH>
 struct Quadrant {
   int px, py;            // this thread's pixel
@@ -86,26 +87,51 @@ struct Quadrant {
     y0 = (float)by + 0.5f;
     y1 = y0 + 7.0f;
   }
-  __device__ __forceinline__ bool meets(const float4 box) const {
-    return !(box.y < x0 || box.x > x1 || box.w < y0 || box.z > y1);
+  // Whether the staged Gaussian (A, E) can reach alpha >= 1/255 at a pixel
+  // centre of the quadrant.  Its exponent is e(d) = E.w - f(d) with
+  // f(d) = a dx^2 + b dx dy + c dy^2 (a = -E.x, b = -E.y, c = -E.z, d = mean
+  // - pixel centre), a positive-definite form, so alpha >= 1/255 somewhere
+  // in the quadrant iff E.w - min f >= log2(1/255) over the rectangle of
+  // pixel centres.  The minimum is 0 if d = 0 lies inside, else it is on an
+  // edge, where f is a 1-D quadratic minimised at its clamped vertex.  The
+  // margin covers the float32 rounding of f here and in the per-pixel
+  // evaluation (a few ulps of the largest |term| over the rectangle), so
+  // every pixel whose float32 alpha passes the cutoff is kept: the test only
+  // removes work.
+  __device__ __forceinline__ bool reaches(const float4 A, const float4 E) const {
+    const float a = -E.x, b = -E.y, c = -E.z;
+    const float dx0 = A.x - x1, dx1 = A.x - x0, dy0 = A.y - y1, dy1 = A.y - y0;
+    const float ra = __builtin_amdgcn_rcpf(2.0f * a), rc = __builtin_amdgcn_rcpf(2.0f * c);
+    auto f = [&](float dx, float dy) { return fmaf(fmaf(b, dy, a * dx), dx, c * dy * dy); };
+    const float e0 = f(dx0, fminf(fmaxf(-b * dx0 * rc, dy0), dy1));
+    const float e1 = f(dx1, fminf(fmaxf(-b * dx1 * rc, dy0), dy1));
+    const float e2 = f(fminf(fmaxf(-b * dy0 * ra, dx0), dx1), dy0);
+    const float e3 = f(fminf(fmaxf(-b * dy1 * ra, dx0), dx1), dy1);
+    const bool inside = dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f;
+    const float fmin = inside ? 0.0f : fminf(fminf(e0, e1), fminf(e2, e3));
+    const float mx = fmaxf(dx0 * dx0, dx1 * dx1), my = fmaxf(dy0 * dy0, dy1 * dy1);
+    const float fabs_max = fmaf(a, mx, fmaf(fabsf(b), sqrtf(mx * my), c * my));
+    const float margin = fmaf(16.0f * 1.1920929e-7f, fabs_max + fabsf(E.w), 1e-6f);
+    return E.w - fmin >= kLog2AlphaMin - margin;
   }
 };
 
-// Compacts the staged entries [0, n) whose padded box meets the wavefront's
-// quadrant into list[] -- in staging order, or in reverse order if DESC --
+// Compacts the staged entries [0, n) that reach the wavefront's quadrant
+// into list[] -- in staging order, or in reverse order if DESC --
 // pads it with the sentinel index BS to a multiple of kGroup and returns the
 // number of hits (the same in every lane).  Lane l tests entries l, l + 64,
 // ...; a ballot and a lane-prefix count give each hit its slot.  All lanes
 // of the wavefront must be active; the list is read after the next
 // workgroup barrier.
 template <int BS, bool DESC, int TW, int TH>
-__device__ __forceinline__ int wave_hits(const float4* X, int n, const Quadrant<TW, TH>& q, uint16_t* list) {
+__device__ __forceinline__ int wave_hits(const float4* A, const float4* E, int n, const Quadrant<TW, TH>& q,
+                                         uint16_t* list) {
   const int lane = threadIdx.x & 63;
   int count = 0;
 #pragma unroll
   for (int k = 0; k < BS / 64; ++k) {
     const int e = DESC ? n - 1 - (k * 64 + lane) : k * 64 + lane;
-    const bool hit = (DESC ? e >= 0 : e < n) && q.meets(X[e]);
+    const bool hit = (DESC ? e >= 0 : e < n) && q.reaches(A[e], E[e]);
     const uint64_t m = __ballot(hit);
     const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
     if (hit) list[count + below] = (uint16_t)e;
@@ -115,15 +141,10 @@ __device__ __forceinline__ int wave_hits(const float4* X, int n, const Quadrant<
   return count;
 }
 
-// Padded box of the opacity-aware ellipse: [u - hx - 1, u + hx + 1] x [v - hy - 1, v + hy + 1].
-__device__ __forceinline__ float4 stage_box(const float4 A, const float2 h) {
-  return make_float4(A.x - h.x - 1.0f, A.x + h.x + 1.0f, A.y - h.y - 1.0f, A.y + h.y + 1.0f);
-}
-
 template <int TW, int TH>
 __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab, const float4* __restrict__ pa,
                                              const float4* __restrict__ pb, const float4* __restrict__ pc,
-                                             const float2* __restrict__ ext, const uint2* __restrict__ ranges,
+                                             const uint2* __restrict__ ranges,
                                              const uint32_t* __restrict__ vals, float* __restrict__ T_final,
                                              uint32_t* __restrict__ n_contrib, uint32_t tile, FwdShared<TW, TH>& sh,
                                              uint32_t& ne, uint32_t& nb) {
@@ -151,10 +172,9 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
       sh.A[threadIdx.x] = A;
       sh.E[threadIdx.x] = stage_exponent(A, pb[rec]);
       sh.C[threadIdx.x] = pc[rec];
-      sh.X[threadIdx.x] = stage_box(A, ext[rec]);
     }
     __syncthreads();
-    const int nhit = wave_hits<BS, false>(sh.X, (int)min((uint32_t)BS, rg.y - start), q, hits);
+    const int nhit = wave_hits<BS, false>(sh.A, sh.E, (int)min((uint32_t)BS, rg.y - start), q, hits);
     __syncthreads();
     const uint32_t base = start - rg.x + 1u;
     for (int g = 0; g < nhit && __ballot(!done) != 0ull; g += kGroup) {
@@ -223,7 +243,7 @@ __device__ __forceinline__ uint32_t next_tile(uint32_t* queue, uint32_t* slot) {
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
     const CallTables* __restrict__ tab, const float4* __restrict__ pa, const float4* __restrict__ pb,
-    const float4* __restrict__ pc, const float2* __restrict__ ext, const uint2* __restrict__ ranges,
+    const float4* __restrict__ pc, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals, float* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
     Counters* __restrict__ cnt, uint32_t* __restrict__ queue, uint32_t n_tiles) {
   __shared__ FwdShared<TW, TH> sh;
@@ -235,10 +255,10 @@ __global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
     sh.C[TW * TH] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   if (queue == nullptr) {
-    forward_tile<TW, TH>(tab, pa, pb, pc, ext, ranges, vals, T_final, n_contrib, blockIdx.x, sh, ne, nb);
+    forward_tile<TW, TH>(tab, pa, pb, pc, ranges, vals, T_final, n_contrib, blockIdx.x, sh, ne, nb);
   } else {
     for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot))
-      forward_tile<TW, TH>(tab, pa, pb, pc, ext, ranges, vals, T_final, n_contrib, t, sh, ne, nb);
+      forward_tile<TW, TH>(tab, pa, pb, pc, ranges, vals, T_final, n_contrib, t, sh, ne, nb);
   }
   flush_counts(ne, nb, cnt);
 }
@@ -301,7 +321,7 @@ __device__ __forceinline__ bool scatter_writer(int lane) {
 
 template <int TW, int TH>
 struct BwdShared {
-  float4 A[TW * TH + 1], E[TW * TH + 1], B[TW * TH + 1], C[TW * TH + 1], X[TW * TH];
+  float4 A[TW * TH + 1], E[TW * TH + 1], B[TW * TH + 1], C[TW * TH + 1];
   uint32_t rec[TW * TH];
   uint16_t hits[(TW * TH) / 64][TW * TH + kGroup];  // per wavefront, descending
   uint32_t maxlast[(TW * TH) / 64];
@@ -310,7 +330,7 @@ struct BwdShared {
 template <int TW, int TH>
 __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab, const float4* __restrict__ pa,
                                               const float4* __restrict__ pb, const float4* __restrict__ pc,
-                                              const float2* __restrict__ ext, const uint2* __restrict__ ranges,
+                                              const uint2* __restrict__ ranges,
                                               const uint32_t* __restrict__ vals, const float* __restrict__ T_final,
                                               const uint32_t* __restrict__ n_contrib, float* __restrict__ acc,
                                               uint32_t tile, BwdShared<TW, TH>& sh) {
@@ -363,13 +383,12 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
         sh.E[threadIdx.x] = stage_exponent(A, B);
         sh.B[threadIdx.x] = make_float4(B.x, B.y, B.z, 1.0f / A.w);
         sh.C[threadIdx.x] = pc[rec];
-        sh.X[threadIdx.x] = stage_box(A, ext[rec]);
-      }
+        }
     }
     __syncthreads();
     // entries of this wavefront: those before its own last blended one
     uint16_t* hits = sh.hits[threadIdx.x >> 6];
-    const int nhit = wave_hits<BS, true>(sh.X, min(end, (int)wave_last) - begin, q, hits);
+    const int nhit = wave_hits<BS, true>(sh.A, sh.E, min(end, (int)wave_last) - begin, q, hits);
     __syncthreads();
     for (int i = 0; i < nhit; ++i) {
       const int sl = hits[i];
@@ -411,7 +430,7 @@ __global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
     const CallTables* __restrict__ tab, const float4* __restrict__ pa, const float4* __restrict__ pb,
     const float4* __restrict__ pc, const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib, float* __restrict__ acc,
-    const float2* __restrict__ ext, uint32_t* __restrict__ queue, uint32_t n_tiles) {
+    uint32_t* __restrict__ queue, uint32_t n_tiles) {
   __shared__ BwdShared<TW, TH> sh;
   __shared__ uint32_t slot;
   if (threadIdx.x == 0) {  // the sentinel slot (read after the first staging barrier)
@@ -419,10 +438,10 @@ __global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
     sh.E[TW * TH] = make_float4(0.f, 0.f, 0.f, kNegInf);
   }
   if (queue == nullptr) {
-    backward_tile<TW, TH>(tab, pa, pb, pc, ext, ranges, vals, T_final, n_contrib, acc, blockIdx.x, sh);
+    backward_tile<TW, TH>(tab, pa, pb, pc, ranges, vals, T_final, n_contrib, acc, blockIdx.x, sh);
   } else {
     for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot))
-      backward_tile<TW, TH>(tab, pa, pb, pc, ext, ranges, vals, T_final, n_contrib, acc, t, sh);
+      backward_tile<TW, TH>(tab, pa, pb, pc, ranges, vals, T_final, n_contrib, acc, t, sh);
   }
 }
 
@@ -432,7 +451,7 @@ hipError_t launch_fwd_t(const CallTables* d_tab, const CallTables& h, const Proj
                         uint32_t blocks, hipStream_t s) {
   const uint32_t grid = queue ? blocks : h.n_tiles;
   hipLaunchKernelGGL((composite_forward_kernel<TW, TH>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.a, pb.b, pb.c,
-                     pb.ext, ranges, vals, T_final, n_contrib, cnt, queue, h.n_tiles);
+                     ranges, vals, T_final, n_contrib, cnt, queue, h.n_tiles);
   return hipGetLastError();
 }
 
@@ -442,7 +461,7 @@ hipError_t launch_bwd_t(const CallTables* d_tab, const CallTables& h, const Proj
                         uint32_t* queue, uint32_t blocks, hipStream_t s) {
   const uint32_t grid = queue ? blocks : h.n_tiles;
   hipLaunchKernelGGL((composite_backward_kernel<TW, TH>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.a, pb.b, pb.c,
-                     ranges, vals, T_final, n_contrib, acc, pb.ext, queue, h.n_tiles);
+                     ranges, vals, T_final, n_contrib, acc, queue, h.n_tiles);
   return hipGetLastError();
 }
 
