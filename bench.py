@@ -105,9 +105,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c4-1200")
-    ap.add_argument("--tile", default="auto", help="WxH or auto (the window's search)")
-    ap.add_argument("--persistent", type=int, default=-1, help="-1 search, 0 off, >0 workgroups")
+    ap.add_argument("--tile", default="16x16", help="WxH, or auto for the window's search over shapes")
+    ap.add_argument("--persistent", type=int, default=1024,
+                    help="persistent compositing workgroups: 0 one per tile, -1 search")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-one-view", action="store_true",
+                    help="skip the one-view-per-launch comparison (profiling runs: it launches the same kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -180,27 +183,29 @@ def main():
     log("[bench] stage ms/step: " + ", ".join(f"{k}={v:.3f}" for k, v in sorted(stage_ms.items(), key=lambda x: -x[1])))
 
     # one view per launch: the same kernels, each view its own forward+backward call
+    ms_per_view_launch = None
     per_view_caps = []
-    for v in range(nv):
-        outs, saved = render([sets[vset[v]]], [cams[v]], [0], tile=(cfg["tile_w"], cfg["tile_h"]))
-        per_view_caps.append(int(saved.stats()["n_pairs"] * 1.25) + 4096)
-        saved.close()
     def one_view_pass():
         for v in range(nv):
             outs, saved = render([sets[vset[v]]], [cams[v]], [0], tile=(cfg["tile_w"], cfg["tile_h"]),
                                  pair_capacity=per_view_caps[v])
             render_backward(saved, [gw[v]])
             saved.close()
-    one_view_pass()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = max(2, args.steps // 4)
-    for _ in range(reps):
+    if not args.no_one_view:
+        for v in range(nv):
+            outs, saved = render([sets[vset[v]]], [cams[v]], [0], tile=(cfg["tile_w"], cfg["tile_h"]))
+            per_view_caps.append(int(saved.stats()["n_pairs"] * 1.25) + 4096)
+            saved.close()
         one_view_pass()
-    torch.cuda.synchronize()
-    ms_per_view_launch = (time.perf_counter() - t0) * 1e3 / reps
-    log(f"[bench] one view per launch: {ms_per_view_launch:.3f} ms for {nv} views; "
-        f"eager window {ms_eager_window:.3f} ms")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = max(2, args.steps // 4)
+        for _ in range(reps):
+            one_view_pass()
+        torch.cuda.synchronize()
+        ms_per_view_launch = (time.perf_counter() - t0) * 1e3 / reps
+        log(f"[bench] one view per launch: {ms_per_view_launch:.3f} ms for {nv} views; "
+            f"eager window {ms_eager_window:.3f} ms")
 
     E, B, P = st["n_evaluated"], st["n_blended"], st["n_pairs"]
     dom = max(stage_ms, key=stage_ms.get)
@@ -240,8 +245,9 @@ def main():
         "blends_per_sec": B / (ms_step * 1e-3),
         "counts": {"pairs": P, "evaluated": E, "blended": B},
         "window": {k: cfg[k] for k in ("tile_w", "tile_h", "persistent", "pair_capacity")},
-        "one_view_per_launch": {"ms_for_all_views": ms_per_view_launch, "views_per_sec": nv / (ms_per_view_launch * 1e-3),
-                                "batched_speedup": ms_per_view_launch / ms_step},
+        "one_view_per_launch": None if ms_per_view_launch is None else
+        {"ms_for_all_views": ms_per_view_launch, "views_per_sec": nv / (ms_per_view_launch * 1e-3),
+         "batched_speedup": ms_per_view_launch / ms_step},
         "stage_ms": stage_ms,
         "roofline": roof,
     }

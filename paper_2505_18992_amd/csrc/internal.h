@@ -102,14 +102,21 @@ hipError_t launch_pose_reduce(const CallTables* d_tab, const CallTables& h_tab, 
                               float* d_pose, hipStream_t s);
 
 // Exclusive scan of n uint32 values (or, with flags, of value != 0); total
-// (device, uint32) receives the sum.
+// (device, uint32) receives the sum.  With n_dev the length is the device
+// count min(*n_dev, n): later values count as zero and are not written.
 size_t scan_workspace_bytes(uint32_t n);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, void* ws,
-                       hipStream_t s, bool flags = false);
+                       hipStream_t s, bool flags = false, const uint32_t* n_dev = nullptr);
 
-// Depth order of the visible records: compaction (record order), stable
-// sort by FP32 depth bits, tile counts gathered in that order and their
-// exclusive scan (pair offsets; the total goes to *pair_off_total).
+// Stream compaction of the visible records (count != 0) in record order:
+// keys = FP32 depth bits, vals = record index; *total = their number.
+hipError_t launch_compact_visible(const uint32_t* count, const float4* pa, uint32_t n, uint32_t* keys,
+                                  uint32_t* vals, uint32_t* total, void* ws, hipStream_t s);
+
+// Depth order of the compacted visible records: stable sort by FP32 depth
+// bits, their tile counts gathered in that order (by the last sort pass) and
+// the exclusive scan of those (pair offsets; the total goes to
+// *pair_off_total).
 struct DepthOrder {
   uint32_t* keys;
   uint32_t* vals;
@@ -121,8 +128,8 @@ struct DepthOrder {
   void* scan_ws;
   int* sorted_in_alt;  // host: 1 if the sorted records are in vals_alt
 };
-hipError_t launch_depth_order(const CallTables& h_tab, const ProjBuffers pb, const uint32_t* vis_off,
-                              const uint32_t* n_visible, DepthOrder d, void* sort_ws, hipStream_t s);
+hipError_t launch_depth_order(const CallTables& h_tab, const ProjBuffers pb, const uint32_t* n_visible, DepthOrder d,
+                              void* sort_ws, hipStream_t s);
 
 // One (tile id, record) pair per overlapped tile, in depth order.
 hipError_t launch_emit(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,

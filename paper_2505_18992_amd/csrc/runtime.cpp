@@ -90,7 +90,7 @@ void free_buf(DevBuf& b) {
 namespace vpgs {
 
 void destroy_saved(vpgs_saved* s) {
-  DevBuf* bufs[] = {&s->tab, &s->pa, &s->pb, &s->pc, &s->ext, &s->rect, &s->count, &s->offsets, &s->scan_ws,
+  DevBuf* bufs[] = {&s->tab, &s->pa, &s->pb, &s->pc, &s->ext, &s->rect, &s->count, &s->scan_ws,
                     &s->keys, &s->vals, &s->keys_alt, &s->vals_alt, &s->sort_ws, &s->ranges, &s->tfinal,
                     &s->ncontrib, &s->counters, &s->acc, &s->pose_partial, &s->dk, &s->dk_alt, &s->dv,
                     &s->dv_alt, &s->dcount, &s->dpoff, &s->key64};
@@ -291,7 +291,7 @@ int prepare_front(vpgs_ctx* ctx, vpgs_saved* sv) {
   if ((rc = ensure(ctx, sv->tab, sizeof(CallTables))) || (rc = ensure(ctx, sv->pa, R * 16)) ||
       (rc = ensure(ctx, sv->pb, R * 16)) || (rc = ensure(ctx, sv->pc, R * 16)) || (rc = ensure(ctx, sv->ext, R * 8)) ||
       (rc = ensure(ctx, sv->rect, R * 8)) || (rc = ensure(ctx, sv->count, R * 4)) ||
-      (rc = ensure(ctx, sv->offsets, R * 4)) || (rc = ensure(ctx, sv->scan_ws, scan_workspace_bytes((uint32_t)R))) ||
+      (rc = ensure(ctx, sv->scan_ws, scan_workspace_bytes((uint32_t)R))) ||
       (rc = ensure(ctx, sv->ranges, (size_t)T.n_tiles * 8)) || (rc = ensure(ctx, sv->tfinal, pixels * 4)) ||
       (rc = ensure(ctx, sv->ncontrib, pixels * 4)) || (rc = ensure(ctx, sv->counters, sizeof(Counters))))
     return rc;
@@ -357,10 +357,10 @@ int enqueue_front(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
     HIP_TRY(launch_project(d_tab, T, pb, sv->tile_w, sv->tile_h, st));
   }
   {
-    // visible records (count != 0): compaction offsets and their number
+    // visible records (count != 0), compacted in record order with their depth keys
     StageTimer t(ctx, ST_SCAN, st);
-    HIP_TRY(launch_scan(pb.count, static_cast<uint32_t*>(sv->offsets.p), T.n_records, &cnt->visible, sv->scan_ws.p,
-                        st, true));
+    HIP_TRY(launch_compact_visible(pb.count, pb.a, T.n_records, static_cast<uint32_t*>(sv->dk.p),
+                                   static_cast<uint32_t*>(sv->dv.p), &cnt->visible, sv->scan_ws.p, st));
   }
   {
     StageTimer t(ctx, ST_DEPTH, st);
@@ -374,8 +374,7 @@ int enqueue_front(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
     d.pair_off_total = &cnt->pairs;
     d.scan_ws = sv->scan_ws.p;
     d.sorted_in_alt = &sv->depth_in_alt;
-    HIP_TRY(launch_depth_order(T, pb, static_cast<const uint32_t*>(sv->offsets.p), &cnt->visible, d, sv->sort_ws.p,
-                               st));
+    HIP_TRY(launch_depth_order(T, pb, &cnt->visible, d, sv->sort_ws.p, st));
   }
   return VPGS_OK;
 }

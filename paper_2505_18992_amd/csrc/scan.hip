@@ -1,5 +1,10 @@
 // scan.hip -- exclusive prefix sum of uint32 counts (reduce, scan of the
-// block sums, downsweep), plus small fill kernels.
+// block sums, downsweep), the same scan fused with stream compaction of the
+// visible records, and small fill kernels.
+//
+// A scan may take its length from a device counter (n_dev, clamped to the
+// allocated n): values at or past it count as zero and their outputs are not
+// written, so no host round trip is needed.
 #include "internal.h"
 
 namespace vpgs {
@@ -41,9 +46,17 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds, u
 // flags != 0: scan the indicator (value != 0) instead of the values.
 __device__ __forceinline__ uint32_t scan_value(uint32_t x, int flags) { return flags ? (x != 0u) : x; }
 
-__global__ void __launch_bounds__(kScanBlock) scan_reduce_kernel(const uint32_t* __restrict__ in, uint32_t n,
+__device__ __forceinline__ uint32_t scan_length(uint32_t n, const uint32_t* n_dev) {
+  if (n_dev == nullptr) return n;
+  const uint32_t m = *n_dev;
+  return m < n ? m : n;
+}
+
+__global__ void __launch_bounds__(kScanBlock) scan_reduce_kernel(const uint32_t* __restrict__ in, uint32_t n_alloc,
+                                                                 const uint32_t* __restrict__ n_dev,
                                                                  uint32_t* __restrict__ sums, int flags) {
   __shared__ uint32_t lds[kScanBlock / 64];
+  const uint32_t n = scan_length(n_alloc, n_dev);
   const size_t base = (size_t)blockIdx.x * kScanTile;
   uint32_t s = 0;
 #pragma unroll
@@ -58,11 +71,13 @@ __global__ void __launch_bounds__(kScanBlock) scan_reduce_kernel(const uint32_t*
 
 // Exclusive scan of each block's tile, offset by block_offsets[block]
 // (NULL = 0).  If total is non-NULL the last block writes the grand total.
-__global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t* __restrict__ in, uint32_t n,
+__global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t* __restrict__ in, uint32_t n_alloc,
+                                                               const uint32_t* __restrict__ n_dev,
                                                                const uint32_t* __restrict__ block_offsets,
                                                                uint32_t* __restrict__ out, uint32_t* __restrict__ total,
                                                                int flags) {
   __shared__ uint32_t lds[kScanBlock / 64];
+  const uint32_t n = scan_length(n_alloc, n_dev);
   const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;  // blocked layout
   uint32_t v[kScanItems];
   uint32_t s = 0;
@@ -80,6 +95,42 @@ __global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t* _
   for (int k = 0; k < kScanItems; ++k) {
     const size_t idx = base + k;
     if (idx < n) out[idx] = run;
+    run += v[k];
+  }
+  if (total != nullptr && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
+}
+
+// Down-sweep of the indicator scan (count != 0) that scatters instead of
+// storing offsets: visible record r goes to position (number of visible
+// records before r), with key = bits of its FP32 depth (pa[r].z) and value r.
+// Record order is kept, so equal depths stay in index order.
+__global__ void __launch_bounds__(kScanBlock) compact_down_kernel(const uint32_t* __restrict__ count, uint32_t n,
+                                                                  const uint32_t* __restrict__ block_offsets,
+                                                                  const float4* __restrict__ pa,
+                                                                  uint32_t* __restrict__ keys,
+                                                                  uint32_t* __restrict__ vals,
+                                                                  uint32_t* __restrict__ total) {
+  __shared__ uint32_t lds[kScanBlock / 64];
+  const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const size_t idx = base + k;
+    v[k] = (idx < n && count[idx] != 0u) ? 1u : 0u;
+    s += v[k];
+  }
+  uint32_t tot;
+  uint32_t run = block_excl_scan(s, lds, &tot);
+  const uint32_t off = block_offsets ? block_offsets[blockIdx.x] : 0u;
+  run += off;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (v[k]) {
+      const size_t idx = base + k;
+      keys[run] = __float_as_uint(reinterpret_cast<const float*>(pa)[4 * idx + 2]);
+      vals[run] = (uint32_t)idx;
+    }
     run += v[k];
   }
   if (total != nullptr && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
@@ -110,24 +161,47 @@ size_t scan_workspace_bytes(uint32_t n) {
 }
 
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, void* ws, hipStream_t s,
-                       bool flags) {
+                       bool flags, const uint32_t* n_dev) {
   const int fl = flags ? 1 : 0;
   if (n == 0) return total ? launch_fill_u32(total, 0u, 1, s) : hipSuccess;
   const uint32_t blocks = div_up(n, kScanTile);
   if (blocks == 1) {
-    hipLaunchKernelGGL(scan_down_kernel, dim3(1), dim3(kScanBlock), 0, s, in, n, nullptr, out, total, fl);
+    hipLaunchKernelGGL(scan_down_kernel, dim3(1), dim3(kScanBlock), 0, s, in, n, n_dev, nullptr, out, total, fl);
     return hipGetLastError();
   }
   char* w = static_cast<char*>(ws);
   uint32_t* sums = reinterpret_cast<uint32_t*>(w);
   const size_t sum_bytes = ((size_t)blocks * sizeof(uint32_t) + 255) / 256 * 256;
   uint32_t* sums_scanned = reinterpret_cast<uint32_t*>(w + sum_bytes);
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3(blocks), dim3(kScanBlock), 0, s, in, n, sums, fl);
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(blocks), dim3(kScanBlock), 0, s, in, n, n_dev, sums, fl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = launch_scan(sums, sums_scanned, blocks, total, w + 2 * sum_bytes, s, false);
+  e = launch_scan(sums, sums_scanned, blocks, total, w + 2 * sum_bytes, s, false, nullptr);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(scan_down_kernel, dim3(blocks), dim3(kScanBlock), 0, s, in, n, sums_scanned, out, nullptr, fl);
+  hipLaunchKernelGGL(scan_down_kernel, dim3(blocks), dim3(kScanBlock), 0, s, in, n, n_dev, sums_scanned, out, nullptr,
+                     fl);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_visible(const uint32_t* count, const float4* pa, uint32_t n, uint32_t* keys, uint32_t* vals,
+                                  uint32_t* total, void* ws, hipStream_t s) {
+  if (n == 0) return total ? launch_fill_u32(total, 0u, 1, s) : hipSuccess;
+  const uint32_t blocks = div_up(n, kScanTile);
+  if (blocks == 1) {
+    hipLaunchKernelGGL(compact_down_kernel, dim3(1), dim3(kScanBlock), 0, s, count, n, nullptr, pa, keys, vals, total);
+    return hipGetLastError();
+  }
+  char* w = static_cast<char*>(ws);
+  uint32_t* sums = reinterpret_cast<uint32_t*>(w);
+  const size_t sum_bytes = ((size_t)blocks * sizeof(uint32_t) + 255) / 256 * 256;
+  uint32_t* sums_scanned = reinterpret_cast<uint32_t*>(w + sum_bytes);
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(blocks), dim3(kScanBlock), 0, s, count, n, nullptr, sums, 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_scan(sums, sums_scanned, blocks, total, w + 2 * sum_bytes, s, false, nullptr);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(compact_down_kernel, dim3(blocks), dim3(kScanBlock), 0, s, count, n, sums_scanned, pa, keys, vals,
+                     nullptr);
   return hipGetLastError();
 }
 

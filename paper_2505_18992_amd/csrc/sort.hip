@@ -13,6 +13,11 @@
 //
 // Counts (visible records, pairs) stay on the device; every kernel clamps
 // them to the allocated capacity, so no host round trip is needed.
+//
+// Each radix pass is three kernels: per-workgroup digit histograms, a scan
+// of every digit's row of histograms (one workgroup per digit), and the
+// scatter, which adds the digit's global base (a scan of the row totals it
+// redoes itself) to its row offset.
 #include "internal.h"
 
 namespace vpgs {
@@ -36,29 +41,6 @@ __device__ __forceinline__ int view_of_record(const CallTables* tab, uint32_t re
     if (tab->views[mid].rec_base <= rec) lo = mid; else hi = mid - 1;
   }
   return lo;
-}
-
-// ---------------------------------------------------------------------------
-// visible-record compaction (record order) with the depth key
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) compact_kernel(const uint32_t* __restrict__ count, const float4* __restrict__ pa,
-                                                      const uint32_t* __restrict__ vis_off, uint32_t n_records,
-                                                      uint32_t* __restrict__ dkeys, uint32_t* __restrict__ dvals) {
-  const uint32_t rec = blockIdx.x * blockDim.x + threadIdx.x;
-  if (rec >= n_records || count[rec] == 0u) return;
-  const uint32_t pos = vis_off[rec];
-  dkeys[pos] = __float_as_uint(reinterpret_cast<const float*>(pa)[4 * (size_t)rec + 2]);
-  dvals[pos] = rec;
-}
-
-// Tile counts in depth order, zero past the last visible record.
-__global__ void __launch_bounds__(256) gather_counts_kernel(const uint32_t* __restrict__ sorted_rec,
-                                                            const uint32_t* __restrict__ count,
-                                                            const uint32_t* __restrict__ n_visible, uint32_t n_records,
-                                                            uint32_t* __restrict__ out) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_records) return;
-  out[i] = i < clamped(n_visible, n_records) ? count[sorted_rec[i]] : 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -161,12 +143,56 @@ __global__ void __launch_bounds__(kSortBlock) radix_hist_kernel(const K* __restr
   hist[(size_t)d * gridDim.x + blockIdx.x] = s;
 }
 
+// Exclusive scan of one value per thread over the 256-thread workgroup.
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* wsum) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  uint32_t wb = 0;
+  for (int w = 0; w < wave; ++w) wb += wsum[w];
+  __syncthreads();
+  return wb + incl - v;
+}
+
+// One workgroup per digit d: exclusive scan of hist[d][0, blocks) in place
+// of hist_scan and the row total in row_total[d].  Thread t owns a
+// contiguous run of the row.
+__global__ void __launch_bounds__(kSortBlock) radix_offsets_kernel(const uint32_t* __restrict__ hist, uint32_t blocks,
+                                                                   uint32_t* __restrict__ hist_scan,
+                                                                   uint32_t* __restrict__ row_total) {
+  __shared__ uint32_t wsum[kWaves];
+  const uint32_t d = blockIdx.x;
+  const uint32_t per = (blocks + kSortBlock - 1) / kSortBlock;
+  const uint32_t b0 = threadIdx.x * per;
+  const uint32_t b1 = min(b0 + per, blocks);
+  const uint32_t* row = hist + (size_t)d * blocks;
+  uint32_t* out = hist_scan + (size_t)d * blocks;
+  uint32_t sum = 0;
+  for (uint32_t b = b0; b < b1; ++b) sum += row[b];
+  uint32_t run = block_excl_scan256(sum, wsum);
+  for (uint32_t b = b0; b < b1; ++b) {
+    const uint32_t c = row[b];
+    out[b] = run;
+    run += c;
+  }
+  if (threadIdx.x == kSortBlock - 1) row_total[d] = run;
+}
+
 template <class K>
 __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __restrict__ keys_in,
                                                                    const uint32_t* __restrict__ vals_in,
                                                                    K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
                                                                    const uint32_t* __restrict__ n_ptr, uint32_t capacity,
-                                                                   int shift, const uint32_t* __restrict__ hist_scan) {
+                                                                   int shift, const uint32_t* __restrict__ hist_scan,
+                                                                   const uint32_t* __restrict__ row_total,
+                                                                   const uint32_t* __restrict__ gather_src,
+                                                                   uint32_t* __restrict__ gather_dst) {
   __shared__ uint32_t wcnt[kWaves][kRadix];   // per-wave digit counts, then per-wave prefixes
   __shared__ uint32_t dstart[kRadix];         // block-local first position of each digit
   __shared__ uint32_t gbase[kRadix];          // global first position of each digit for this block
@@ -218,7 +244,10 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
     uint32_t wb = 0;
     for (int w = 0; w < wave; ++w) wb += wsum[w];
     dstart[d] = wb + incl - run;
-    gbase[d] = hist_scan[(size_t)d * gridDim.x + blockIdx.x];
+    __syncthreads();
+    // global base of digit d: the totals of the smaller digits
+    const uint32_t digit_base = block_excl_scan256(row_total[d], wsum);
+    gbase[d] = digit_base + hist_scan[(size_t)d * gridDim.x + blockIdx.x];
   }
   __syncthreads();
 #pragma unroll
@@ -237,8 +266,10 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
     const K key = skeys[p];
     const uint32_t d = (uint32_t)(key >> shift) & 0xffu;
     const uint32_t g = gbase[d] + (p - dstart[d]);
+    const uint32_t val = svals[p];
     keys_out[g] = key;
-    vals_out[g] = svals[p];
+    vals_out[g] = val;
+    if (gather_dst != nullptr) gather_dst[g] = gather_src[val];
   }
 }
 
@@ -247,30 +278,36 @@ inline uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 size_t radix_ws_bytes(uint32_t capacity) {
   const uint32_t blocks = div_up(capacity > 0 ? capacity : 1, kSortTile);
   const size_t h = ((size_t)blocks * kRadix * sizeof(uint32_t) + 255) / 256 * 256;
-  return 2 * h + scan_workspace_bytes(blocks * kRadix) + 256;
+  return 2 * h + kRadix * sizeof(uint32_t);
 }
 
+// gather_src/gather_dst (may be NULL): the last pass also writes
+// gather_dst[i] = gather_src[value i] for every sorted position i.
 template <class K>
 hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, uint32_t capacity, int key_bits,
-                      const uint32_t* n_ptr, void* ws, int* result_in_alt, hipStream_t s) {
+                      const uint32_t* n_ptr, void* ws, int* result_in_alt, hipStream_t s,
+                      const uint32_t* gather_src = nullptr, uint32_t* gather_dst = nullptr) {
   *result_in_alt = 0;
   if (capacity == 0) return hipSuccess;
   const uint32_t blocks = div_up(capacity, kSortTile);
   const size_t hist_bytes = ((size_t)blocks * kRadix * sizeof(uint32_t) + 255) / 256 * 256;
   uint32_t* hist = static_cast<uint32_t*>(ws);
   uint32_t* hist_scan = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + hist_bytes);
-  void* scan_ws = static_cast<char*>(ws) + 2 * hist_bytes;
+  uint32_t* row_total = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + 2 * hist_bytes);
   K* kin = keys; uint32_t* vin = vals;
   K* kout = keys_alt; uint32_t* vout = vals_alt;
   int alt = 0;
   for (int shift = 0; shift < key_bits; shift += 8) {
+    const bool last = shift + 8 >= key_bits;
     hipLaunchKernelGGL(radix_hist_kernel<K>, dim3(blocks), dim3(kSortBlock), 0, s, kin, n_ptr, capacity, shift, hist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_scan(hist, hist_scan, blocks * kRadix, nullptr, scan_ws, s, false);
+    hipLaunchKernelGGL(radix_offsets_kernel, dim3(kRadix), dim3(kSortBlock), 0, s, hist, blocks, hist_scan, row_total);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(radix_scatter_kernel<K>, dim3(blocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout, n_ptr,
-                       capacity, shift, hist_scan);
+                       capacity, shift, hist_scan, row_total, last ? gather_src : nullptr,
+                       last ? gather_dst : nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     K* tk = kin; kin = kout; kout = tk;
@@ -310,24 +347,16 @@ __global__ void key64_kernel(const uint32_t* __restrict__ tiles, const uint32_t*
 
 size_t sort_workspace_bytes(uint32_t capacity) { return radix_ws_bytes(capacity); }
 
-hipError_t launch_depth_order(const CallTables& h, const ProjBuffers pb, const uint32_t* vis_off,
-                              const uint32_t* n_visible, DepthOrder d, void* ws, hipStream_t s) {
+hipError_t launch_depth_order(const CallTables& h, const ProjBuffers pb, const uint32_t* n_visible, DepthOrder d,
+                              void* ws, hipStream_t s) {
   const uint32_t R = h.n_records;
   if (R == 0) return launch_fill_u32(d.pair_off_total, 0u, 1, s);
-  hipLaunchKernelGGL(compact_kernel, dim3(div_up(R, 256)), dim3(256), 0, s, pb.count, pb.a, vis_off, R, d.keys,
-                     d.vals);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   int alt = 0;
-  e = radix_sort<uint32_t>(d.keys, d.vals, d.keys_alt, d.vals_alt, R, 32, n_visible, ws, &alt, s);
+  hipError_t e = radix_sort<uint32_t>(d.keys, d.vals, d.keys_alt, d.vals_alt, R, 32, n_visible, ws, &alt, s, pb.count,
+                                      d.counts);
   if (e != hipSuccess) return e;
-  const uint32_t* sorted = alt ? d.vals_alt : d.vals;
   *d.sorted_in_alt = alt;
-  hipLaunchKernelGGL(gather_counts_kernel, dim3(div_up(R, 256)), dim3(256), 0, s, sorted, pb.count, n_visible, R,
-                     d.counts);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_scan(d.counts, d.pair_off, R, d.pair_off_total, d.scan_ws, s, false);
+  return launch_scan(d.counts, d.pair_off, R, d.pair_off_total, d.scan_ws, s, false, n_visible);
 }
 
 hipError_t launch_emit(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb, const uint32_t* sorted_rec,
