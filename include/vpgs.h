@@ -177,7 +177,8 @@ int vpgs_saved_stats(vpgs_ctx* ctx, const vpgs_saved* saved, vpgs_stats* out, vo
  * VPGS_EINVAL if bytes is smaller than the buffer (whose size in bytes is
  * returned through *size when size is non-NULL, and dst may then be NULL):
  *   VPGS_BUF_PROJ    float [R,12]: u, v, z, opacity, Qa, Qb, Qc, 0, r, g, b, 0
- *   VPGS_BUF_EXTENT  float [R,2]: half extents hx, hy of the box
+ *                    (rows of culled records, count 0, are unspecified)
+ *   VPGS_BUF_EXTENT  float [R,2]: half extents hx, hy of the box (0 if culled)
  *   VPGS_BUF_COUNT   uint32 [R]: tiles overlapped (0 = culled)
  *   VPGS_BUF_KEYS    uint64 [P]: sorted keys
  *   VPGS_BUF_VALUES  uint32 [P]: sorted record indices

@@ -142,8 +142,7 @@ __device__ __forceinline__ int wave_hits(const float4* A, const float4* E, int n
 }
 
 template <int TW, int TH>
-__device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab, const float4* __restrict__ pa,
-                                             const float4* __restrict__ pb, const float4* __restrict__ pc,
+__device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab, const float4* __restrict__ recs,
                                              const uint2* __restrict__ ranges,
                                              const uint32_t* __restrict__ vals, float* __restrict__ T_final,
                                              uint32_t* __restrict__ n_contrib, uint32_t tile, FwdShared<TW, TH>& sh,
@@ -167,11 +166,11 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
     if (__syncthreads_count(done) == BS) break;
     const uint32_t idx = start + threadIdx.x;
     if (idx < rg.y) {
-      const uint32_t rec = vals[idx];
-      const float4 A = pa[rec];
+      const float4* r = recs + rec_slot(vals[idx], 0);
+      const float4 A = r[0];
       sh.A[threadIdx.x] = A;
-      sh.E[threadIdx.x] = stage_exponent(A, pb[rec]);
-      sh.C[threadIdx.x] = pc[rec];
+      sh.E[threadIdx.x] = stage_exponent(A, r[1]);
+      sh.C[threadIdx.x] = r[2];
     }
     __syncthreads();
     const int nhit = wave_hits<BS, false>(sh.A, sh.E, (int)min((uint32_t)BS, rg.y - start), q, hits);
@@ -242,8 +241,7 @@ __device__ __forceinline__ uint32_t next_tile(uint32_t* queue, uint32_t* slot) {
 // past the last tile.
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
-    const CallTables* __restrict__ tab, const float4* __restrict__ pa, const float4* __restrict__ pb,
-    const float4* __restrict__ pc, const uint2* __restrict__ ranges,
+    const CallTables* __restrict__ tab, const float4* __restrict__ recs, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals, float* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
     Counters* __restrict__ cnt, uint32_t* __restrict__ queue, uint32_t n_tiles) {
   __shared__ FwdShared<TW, TH> sh;
@@ -255,10 +253,10 @@ __global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
     sh.C[TW * TH] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   if (queue == nullptr) {
-    forward_tile<TW, TH>(tab, pa, pb, pc, ranges, vals, T_final, n_contrib, blockIdx.x, sh, ne, nb);
+    forward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, blockIdx.x, sh, ne, nb);
   } else {
     for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot))
-      forward_tile<TW, TH>(tab, pa, pb, pc, ranges, vals, T_final, n_contrib, t, sh, ne, nb);
+      forward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, t, sh, ne, nb);
   }
   flush_counts(ne, nb, cnt);
 }
@@ -328,8 +326,7 @@ struct BwdShared {
 };
 
 template <int TW, int TH>
-__device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab, const float4* __restrict__ pa,
-                                              const float4* __restrict__ pb, const float4* __restrict__ pc,
+__device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab, const float4* __restrict__ recs,
                                               const uint2* __restrict__ ranges,
                                               const uint32_t* __restrict__ vals, const float* __restrict__ T_final,
                                               const uint32_t* __restrict__ n_contrib, float* __restrict__ acc,
@@ -376,13 +373,14 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
       const int j = begin + (int)threadIdx.x;
       if (j < end) {
         const uint32_t rec = vals[rg.x + (uint32_t)j];
-        const float4 A = pa[rec];
-        const float4 B = pb[rec];
+        const float4* r = recs + rec_slot(rec, 0);
+        const float4 A = r[0];
+        const float4 B = r[1];
         sh.rec[threadIdx.x] = rec;
         sh.A[threadIdx.x] = A;
         sh.E[threadIdx.x] = stage_exponent(A, B);
         sh.B[threadIdx.x] = make_float4(B.x, B.y, B.z, 1.0f / A.w);
-        sh.C[threadIdx.x] = pc[rec];
+        sh.C[threadIdx.x] = r[2];
         }
     }
     __syncthreads();
@@ -427,8 +425,8 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
 
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
-    const CallTables* __restrict__ tab, const float4* __restrict__ pa, const float4* __restrict__ pb,
-    const float4* __restrict__ pc, const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    const CallTables* __restrict__ tab, const float4* __restrict__ recs, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ vals,
     const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib, float* __restrict__ acc,
     uint32_t* __restrict__ queue, uint32_t n_tiles) {
   __shared__ BwdShared<TW, TH> sh;
@@ -438,10 +436,10 @@ __global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
     sh.E[TW * TH] = make_float4(0.f, 0.f, 0.f, kNegInf);
   }
   if (queue == nullptr) {
-    backward_tile<TW, TH>(tab, pa, pb, pc, ranges, vals, T_final, n_contrib, acc, blockIdx.x, sh);
+    backward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, acc, blockIdx.x, sh);
   } else {
     for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot))
-      backward_tile<TW, TH>(tab, pa, pb, pc, ranges, vals, T_final, n_contrib, acc, t, sh);
+      backward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, acc, t, sh);
   }
 }
 
@@ -450,7 +448,7 @@ hipError_t launch_fwd_t(const CallTables* d_tab, const CallTables& h, const Proj
                         const uint32_t* vals, float* T_final, uint32_t* n_contrib, Counters* cnt, uint32_t* queue,
                         uint32_t blocks, hipStream_t s) {
   const uint32_t grid = queue ? blocks : h.n_tiles;
-  hipLaunchKernelGGL((composite_forward_kernel<TW, TH>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.a, pb.b, pb.c,
+  hipLaunchKernelGGL((composite_forward_kernel<TW, TH>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.rec,
                      ranges, vals, T_final, n_contrib, cnt, queue, h.n_tiles);
   return hipGetLastError();
 }
@@ -460,7 +458,7 @@ hipError_t launch_bwd_t(const CallTables* d_tab, const CallTables& h, const Proj
                         const uint32_t* vals, const float* T_final, const uint32_t* n_contrib, float* acc,
                         uint32_t* queue, uint32_t blocks, hipStream_t s) {
   const uint32_t grid = queue ? blocks : h.n_tiles;
-  hipLaunchKernelGGL((composite_backward_kernel<TW, TH>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.a, pb.b, pb.c,
+  hipLaunchKernelGGL((composite_backward_kernel<TW, TH>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.rec,
                      ranges, vals, T_final, n_contrib, acc, queue, h.n_tiles);
   return hipGetLastError();
 }

@@ -80,14 +80,20 @@ struct Counters {
 };
 
 // Per-record projected data (struct of arrays).
+// Per-(view, Gaussian) projection record: four float4 (64 bytes, one
+// aligned line), written only for records that overlap a tile (count != 0):
+//   [0] (u, v, z, opacity)
+//   [1] (Qa, Qb, Qc, 0)            conic
+//   [2] (r, g, b, 0)
+//   [3] (hx, hy, bits(rect.x), bits(rect.y))  box half extents and the
+//       inclusive tile rectangle (x0 | x1 << 16, y0 | y1 << 16)
+// count is a separate array (scanned contiguously).
+constexpr int kRecSlots = 4;
 struct ProjBuffers {
-  float4* a;       // (u, v, z, opacity)
-  float4* b;       // (Qa, Qb, Qc, 0)
-  float4* c;       // (r, g, b, 0)
-  float2* ext;     // (hx, hy)
-  uint2* rect;     // (x0 | x1 << 16, y0 | y1 << 16) tile rectangle, inclusive
-  uint32_t* count; // tiles overlapped
+  float4* rec;      // [R * kRecSlots]
+  uint32_t* count;  // [R] tiles overlapped, 0 = culled
 };
+__host__ __device__ __forceinline__ size_t rec_slot(uint32_t r, int k) { return (size_t)r * kRecSlots + k; }
 
 // ---- launch helpers (defined in the .hip files) --------------------------------
 
@@ -108,9 +114,12 @@ size_t scan_workspace_bytes(uint32_t n);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, void* ws,
                        hipStream_t s, bool flags = false, const uint32_t* n_dev = nullptr);
 
+// (hx, hy) per record into out[R], zero where count == 0.
+hipError_t launch_export_extent(const ProjBuffers pb, uint32_t n, float2* out, hipStream_t s);
+
 // Stream compaction of the visible records (count != 0) in record order:
 // keys = FP32 depth bits, vals = record index; *total = their number.
-hipError_t launch_compact_visible(const uint32_t* count, const float4* pa, uint32_t n, uint32_t* keys,
+hipError_t launch_compact_visible(const uint32_t* count, const float4* recs, uint32_t n, uint32_t* keys,
                                   uint32_t* vals, uint32_t* total, void* ws, hipStream_t s);
 
 // Depth order of the compacted visible records: stable sort by FP32 depth

@@ -152,13 +152,13 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(const CallTables* _
         const uint32_t ty0 = (uint32_t)bx.y0 >> tile_shift_y, ty1 = (uint32_t)bx.y1 >> tile_shift_y;
         count = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
         rect = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
-        pb.a[rec] = make_float4(p.u, p.v, p.z, o);
-        pb.b[rec] = make_float4(Qa, Qb, Qc, 0.0f);
-        pb.c[rec] = make_float4(c0, c1, c2, 0.0f);
+        float4* out = pb.rec + rec_slot(rec, 0);
+        out[0] = make_float4(p.u, p.v, p.z, o);
+        out[1] = make_float4(Qa, Qb, Qc, 0.0f);
+        out[2] = make_float4(c0, c1, c2, 0.0f);
+        out[3] = make_float4(hx, hy, __uint_as_float(rect.x), __uint_as_float(rect.y));
       }
     }
-    pb.ext[rec] = ok ? make_float2(hx, hy) : make_float2(0.0f, 0.0f);
-    pb.rect[rec] = rect;
     pb.count[rec] = count;
   }
 }
@@ -368,6 +368,24 @@ uint32_t project_blocks(const CallTables& h) {
   uint32_t b = 0;
   for (int s = 0; s < h.n_sets; ++s) b += (uint32_t)((h.sets[s].n + kProjBlock - 1) / kProjBlock);
   return b;
+}
+
+// Half extents (hx, hy) of every record, zero for culled ones.
+__global__ void export_extent_kernel(ProjBuffers pb, uint32_t n, float2* __restrict__ out) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  float2 e = make_float2(0.0f, 0.0f);
+  if (pb.count[r] != 0) {
+    const float4 x = pb.rec[rec_slot(r, 3)];
+    e = make_float2(x.x, x.y);
+  }
+  out[r] = e;
+}
+
+hipError_t launch_export_extent(const ProjBuffers pb, uint32_t n, float2* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(export_extent_kernel, dim3((n + 255) / 256), dim3(256), 0, s, pb, n, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_project(const CallTables* d_tab, const CallTables& h_tab, ProjBuffers pb, int tile_w, int tile_h,

@@ -90,7 +90,7 @@ void free_buf(DevBuf& b) {
 namespace vpgs {
 
 void destroy_saved(vpgs_saved* s) {
-  DevBuf* bufs[] = {&s->tab, &s->pa, &s->pb, &s->pc, &s->ext, &s->rect, &s->count, &s->scan_ws,
+  DevBuf* bufs[] = {&s->tab, &s->rec, &s->count, &s->scan_ws,
                     &s->keys, &s->vals, &s->keys_alt, &s->vals_alt, &s->sort_ws, &s->ranges, &s->tfinal,
                     &s->ncontrib, &s->counters, &s->acc, &s->pose_partial, &s->dk, &s->dk_alt, &s->dv,
                     &s->dv_alt, &s->dcount, &s->dpoff, &s->key64};
@@ -223,11 +223,7 @@ int upload_tables(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
 
 ProjBuffers proj_of(vpgs_saved* s) {
   ProjBuffers pb;
-  pb.a = static_cast<float4*>(s->pa.p);
-  pb.b = static_cast<float4*>(s->pb.p);
-  pb.c = static_cast<float4*>(s->pc.p);
-  pb.ext = static_cast<float2*>(s->ext.p);
-  pb.rect = static_cast<uint2*>(s->rect.p);
+  pb.rec = static_cast<float4*>(s->rec.p);
   pb.count = static_cast<uint32_t*>(s->count.p);
   return pb;
 }
@@ -288,9 +284,8 @@ int prepare_front(vpgs_ctx* ctx, vpgs_saved* sv) {
       (rc = ensure(ctx, sv->dv_alt, R * 4)) || (rc = ensure(ctx, sv->dcount, R * 4)) ||
       (rc = ensure(ctx, sv->dpoff, R * 4)) || (rc = ensure(ctx, sv->sort_ws, sort_workspace_bytes((uint32_t)R))))
     return rc;
-  if ((rc = ensure(ctx, sv->tab, sizeof(CallTables))) || (rc = ensure(ctx, sv->pa, R * 16)) ||
-      (rc = ensure(ctx, sv->pb, R * 16)) || (rc = ensure(ctx, sv->pc, R * 16)) || (rc = ensure(ctx, sv->ext, R * 8)) ||
-      (rc = ensure(ctx, sv->rect, R * 8)) || (rc = ensure(ctx, sv->count, R * 4)) ||
+  if ((rc = ensure(ctx, sv->tab, sizeof(CallTables))) || (rc = ensure(ctx, sv->rec, R * kRecSlots * 16)) ||
+      (rc = ensure(ctx, sv->count, R * 4)) ||
       (rc = ensure(ctx, sv->scan_ws, scan_workspace_bytes((uint32_t)R))) ||
       (rc = ensure(ctx, sv->ranges, (size_t)T.n_tiles * 8)) || (rc = ensure(ctx, sv->tfinal, pixels * 4)) ||
       (rc = ensure(ctx, sv->ncontrib, pixels * 4)) || (rc = ensure(ctx, sv->counters, sizeof(Counters))))
@@ -359,7 +354,7 @@ int enqueue_front(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
   {
     // visible records (count != 0), compacted in record order with their depth keys
     StageTimer t(ctx, ST_SCAN, st);
-    HIP_TRY(launch_compact_visible(pb.count, pb.a, T.n_records, static_cast<uint32_t*>(sv->dk.p),
+    HIP_TRY(launch_compact_visible(pb.count, pb.rec, T.n_records, static_cast<uint32_t*>(sv->dk.p),
                                    static_cast<uint32_t*>(sv->dv.p), &cnt->visible, sv->scan_ws.p, st));
   }
   {
@@ -652,13 +647,13 @@ int vpgs_saved_export(vpgs_ctx* ctx, const vpgs_saved* saved, int what, void* ds
   const bool alt = saved->result_in_alt != 0;
   switch (what) {
     case VPGS_BUF_PROJ: {
-      // interleave a, b, c into rows of 12 floats
-      HIP_TRY(hipMemcpy2DAsync(dst, 48, saved->pa.p, 16, 16, R, hipMemcpyDeviceToDevice, st));
-      HIP_TRY(hipMemcpy2DAsync(static_cast<char*>(dst) + 16, 48, saved->pb.p, 16, 16, R, hipMemcpyDeviceToDevice, st));
-      HIP_TRY(hipMemcpy2DAsync(static_cast<char*>(dst) + 32, 48, saved->pc.p, 16, 16, R, hipMemcpyDeviceToDevice, st));
+      // the first three slots of every record as rows of 12 floats
+      HIP_TRY(hipMemcpy2DAsync(dst, 48, saved->rec.p, kRecSlots * 16, 48, R, hipMemcpyDeviceToDevice, st));
       return VPGS_OK;
     }
-    case VPGS_BUF_EXTENT: HIP_TRY(hipMemcpyAsync(dst, saved->ext.p, need, hipMemcpyDeviceToDevice, st)); break;
+    case VPGS_BUF_EXTENT:
+      HIP_TRY(launch_export_extent(proj_of(const_cast<vpgs_saved*>(saved)), (uint32_t)R, static_cast<float2*>(dst), st));
+      break;
     case VPGS_BUF_COUNT: HIP_TRY(hipMemcpyAsync(dst, saved->count.p, need, hipMemcpyDeviceToDevice, st)); break;
     case VPGS_BUF_KEYS: {
       vpgs_saved* sv = const_cast<vpgs_saved*>(saved);

@@ -102,11 +102,12 @@ __global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t* _
 
 // Down-sweep of the indicator scan (count != 0) that scatters instead of
 // storing offsets: visible record r goes to position (number of visible
-// records before r), with key = bits of its FP32 depth (pa[r].z) and value r.
+// records before r), with key = bits of its FP32 depth (slot 0 .z of its
+// projection record) and value r.
 // Record order is kept, so equal depths stay in index order.
 __global__ void __launch_bounds__(kScanBlock) compact_down_kernel(const uint32_t* __restrict__ count, uint32_t n,
                                                                   const uint32_t* __restrict__ block_offsets,
-                                                                  const float4* __restrict__ pa,
+                                                                  const float4* __restrict__ recs,
                                                                   uint32_t* __restrict__ keys,
                                                                   uint32_t* __restrict__ vals,
                                                                   uint32_t* __restrict__ total) {
@@ -128,7 +129,7 @@ __global__ void __launch_bounds__(kScanBlock) compact_down_kernel(const uint32_t
   for (int k = 0; k < kScanItems; ++k) {
     if (v[k]) {
       const size_t idx = base + k;
-      keys[run] = __float_as_uint(reinterpret_cast<const float*>(pa)[4 * idx + 2]);
+      keys[run] = __float_as_uint(recs[rec_slot((uint32_t)idx, 0)].z);
       vals[run] = (uint32_t)idx;
     }
     run += v[k];
@@ -183,12 +184,12 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_compact_visible(const uint32_t* count, const float4* pa, uint32_t n, uint32_t* keys, uint32_t* vals,
+hipError_t launch_compact_visible(const uint32_t* count, const float4* recs, uint32_t n, uint32_t* keys, uint32_t* vals,
                                   uint32_t* total, void* ws, hipStream_t s) {
   if (n == 0) return total ? launch_fill_u32(total, 0u, 1, s) : hipSuccess;
   const uint32_t blocks = div_up(n, kScanTile);
   if (blocks == 1) {
-    hipLaunchKernelGGL(compact_down_kernel, dim3(1), dim3(kScanBlock), 0, s, count, n, nullptr, pa, keys, vals, total);
+    hipLaunchKernelGGL(compact_down_kernel, dim3(1), dim3(kScanBlock), 0, s, count, n, nullptr, recs, keys, vals, total);
     return hipGetLastError();
   }
   char* w = static_cast<char*>(ws);
@@ -200,7 +201,7 @@ hipError_t launch_compact_visible(const uint32_t* count, const float4* pa, uint3
   if (e != hipSuccess) return e;
   e = launch_scan(sums, sums_scanned, blocks, total, w + 2 * sum_bytes, s, false, nullptr);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(compact_down_kernel, dim3(blocks), dim3(kScanBlock), 0, s, count, n, sums_scanned, pa, keys, vals,
+  hipLaunchKernelGGL(compact_down_kernel, dim3(blocks), dim3(kScanBlock), 0, s, count, n, sums_scanned, recs, keys, vals,
                      nullptr);
   return hipGetLastError();
 }

@@ -60,7 +60,7 @@ __device__ __forceinline__ void emit_range(uint32_t k0, uint32_t k1, uint32_t st
 
 constexpr uint32_t kSmallFootprint = 8;  // records with more tiles are emitted by the whole wavefront
 
-__global__ void __launch_bounds__(256) emit_kernel(const CallTables* __restrict__ tab, const uint2* __restrict__ rect,
+__global__ void __launch_bounds__(256) emit_kernel(const CallTables* __restrict__ tab, const float4* __restrict__ recs,
                                                    const uint32_t* __restrict__ count,
                                                    const uint32_t* __restrict__ sorted_rec,
                                                    const uint32_t* __restrict__ pair_off,
@@ -76,8 +76,9 @@ __global__ void __launch_bounds__(256) emit_kernel(const CallTables* __restrict_
     c = count[rec];
     off = pair_off[i];
     const ViewDesc& V = tab->views[view_of_record(tab, rec)];
-    const uint2 r = rect[rec];
-    const uint32_t tx0 = r.x & 0xffffu, tx1 = r.x >> 16, ty0 = r.y & 0xffffu;
+    const float4 x = recs[rec_slot(rec, 3)];
+    const uint32_t rx = __float_as_uint(x.z), ry = __float_as_uint(x.w);
+    const uint32_t tx0 = rx & 0xffffu, tx1 = rx >> 16, ty0 = ry & 0xffffu;
     tiles_x = (uint32_t)V.tiles_x;
     w = tx1 - tx0 + 1u;
     tile0 = V.tile_base + ty0 * tiles_x + tx0;
@@ -332,15 +333,13 @@ __global__ void ranges_kernel(const uint32_t* __restrict__ tiles, const uint32_t
   if (k == n - 1 || tiles[k + 1] != t) ranges[t].y = k + 1;
 }
 
-__global__ void key64_kernel(const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ recs,
-                             const float4* __restrict__ pa, const uint32_t* __restrict__ n_ptr, uint32_t capacity,
+__global__ void key64_kernel(const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ rec_of,
+                             const float4* __restrict__ recs, const uint32_t* __restrict__ n_ptr, uint32_t capacity,
                              uint64_t* __restrict__ out) {
   const uint32_t n = clamped(n_ptr, capacity);
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= capacity) return;
-  out[k] = k < n ? ((uint64_t)tiles[k] << 32) |
-                       __float_as_uint(reinterpret_cast<const float*>(pa)[4 * (size_t)recs[k] + 2])
-                 : 0ull;
+  out[k] = k < n ? ((uint64_t)tiles[k] << 32) | __float_as_uint(recs[rec_slot(rec_of[k], 0)].z) : 0ull;
 }
 
 }  // namespace
@@ -363,7 +362,7 @@ hipError_t launch_emit(const CallTables* d_tab, const CallTables& h, const ProjB
                        const uint32_t* pair_off, const uint32_t* n_visible, Counters* cnt, uint32_t* keys,
                        uint32_t* vals, uint32_t capacity, hipStream_t s) {
   if (h.n_records == 0) return hipSuccess;
-  hipLaunchKernelGGL(emit_kernel, dim3(div_up(h.n_records, 256)), dim3(256), 0, s, d_tab, pb.rect, pb.count,
+  hipLaunchKernelGGL(emit_kernel, dim3(div_up(h.n_records, 256)), dim3(256), 0, s, d_tab, pb.rec, pb.count,
                      sorted_rec, pair_off, n_visible, cnt, h.n_records, capacity, keys, vals);
   return hipGetLastError();
 }
@@ -385,7 +384,7 @@ hipError_t launch_ranges(const uint32_t* tiles, const Counters* cnt, uint32_t ca
 hipError_t launch_key64(const uint32_t* tiles, const uint32_t* recs, const ProjBuffers pb, const Counters* cnt,
                         uint32_t capacity, uint64_t* out, hipStream_t s) {
   if (capacity == 0) return hipSuccess;
-  hipLaunchKernelGGL(key64_kernel, dim3(div_up(capacity, 256)), dim3(256), 0, s, tiles, recs, pb.a, &cnt->pairs,
+  hipLaunchKernelGGL(key64_kernel, dim3(div_up(capacity, 256)), dim3(256), 0, s, tiles, recs, pb.rec, &cnt->pairs,
                      capacity, out);
   return hipGetLastError();
 }
