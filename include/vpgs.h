@@ -185,8 +185,6 @@ int vpgs_saved_stats(vpgs_ctx* ctx, const vpgs_saved* saved, vpgs_stats* out, vo
  *   VPGS_BUF_RANGES  uint32 [T,2]: [start, end) of every tile
  *   VPGS_BUF_TFINAL  float [sum H*W]: final transmittance, views concatenated
  *   VPGS_BUF_NCONTRIB uint32 [sum H*W]: list length up to the last blend
- *   VPGS_BUF_GRADACC float [R,10]: after a backward, the gradient with respect
- *                    to (u, v, Qa, Qb, Qc, opacity, r, g, b, z) of every record
  * R = records (views in order, each the size of its set); T = tiles (views in
  * order, row-major per view). */
 #define VPGS_BUF_PROJ 1
@@ -197,7 +195,6 @@ int vpgs_saved_stats(vpgs_ctx* ctx, const vpgs_saved* saved, vpgs_stats* out, vo
 #define VPGS_BUF_RANGES 6
 #define VPGS_BUF_TFINAL 7
 #define VPGS_BUF_NCONTRIB 8
-#define VPGS_BUF_GRADACC 9
 int vpgs_saved_export(vpgs_ctx* ctx, const vpgs_saved* saved, int what, void* dst, size_t bytes,
                       size_t* size, void* stream);
 

@@ -25,7 +25,7 @@ MAX_SETS = 64
 NUM_STAGES = 13
 WINDOW_FORWARD, WINDOW_BACKWARD = 1, 2
 
-BUF_PROJ, BUF_EXTENT, BUF_COUNT, BUF_KEYS, BUF_VALUES, BUF_RANGES, BUF_TFINAL, BUF_NCONTRIB, BUF_GRADACC = range(1, 10)
+BUF_PROJ, BUF_EXTENT, BUF_COUNT, BUF_KEYS, BUF_VALUES, BUF_RANGES, BUF_TFINAL, BUF_NCONTRIB = range(1, 9)
 
 
 class Camera(ctypes.Structure):

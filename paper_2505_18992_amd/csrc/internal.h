@@ -87,11 +87,13 @@ struct Counters {
 //   [2] (r, g, b, 0)
 //   [3] (hx, hy, bits(rect.x), bits(rect.y))  box half extents and the
 //       inclusive tile rectangle (x0 | x1 << 16, y0 | y1 << 16)
-// count is a separate array (scanned contiguously).
+// count and the depth key (IEEE bits of the FP32 z, written with the
+// record) are separate arrays, read contiguously by the scans.
 constexpr int kRecSlots = 4;
 struct ProjBuffers {
   float4* rec;      // [R * kRecSlots]
   uint32_t* count;  // [R] tiles overlapped, 0 = culled
+  uint32_t* zkey;   // [R] depth key of records with count != 0
 };
 __host__ __device__ __forceinline__ size_t rec_slot(uint32_t r, int k) { return (size_t)r * kRecSlots + k; }
 
@@ -102,8 +104,9 @@ hipError_t launch_project(const CallTables* d_tab, const CallTables& h_tab, Proj
 // Blocks of the per-Gaussian launches (the pose partial buffer holds
 // n_views * project_blocks * 6 floats).
 uint32_t project_blocks(const CallTables& h);
+// Reads each visible record's row of acc and leaves it zero.
 hipError_t launch_project_backward(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
-                                   const float* acc, float* pose_partial, hipStream_t s);
+                                   float* acc, float* pose_partial, hipStream_t s);
 hipError_t launch_pose_reduce(const CallTables* d_tab, const CallTables& h_tab, const float* pose_partial,
                               float* d_pose, hipStream_t s);
 
@@ -118,8 +121,8 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* 
 hipError_t launch_export_extent(const ProjBuffers pb, uint32_t n, float2* out, hipStream_t s);
 
 // Stream compaction of the visible records (count != 0) in record order:
-// keys = FP32 depth bits, vals = record index; *total = their number.
-hipError_t launch_compact_visible(const uint32_t* count, const float4* recs, uint32_t n, uint32_t* keys,
+// keys = depth keys, vals = record index; *total = their number.
+hipError_t launch_compact_visible(const uint32_t* count, const uint32_t* zkey, uint32_t n, uint32_t* keys,
                                   uint32_t* vals, uint32_t* total, void* ws, hipStream_t s);
 
 // Depth order of the compacted visible records: stable sort by FP32 depth

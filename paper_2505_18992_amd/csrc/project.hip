@@ -157,6 +157,7 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(const CallTables* _
         out[1] = make_float4(Qa, Qb, Qc, 0.0f);
         out[2] = make_float4(c0, c1, c2, 0.0f);
         out[3] = make_float4(hx, hy, __uint_as_float(rect.x), __uint_as_float(rect.y));
+        pb.zkey[rec] = __float_as_uint(p.z);
       }
     }
     pb.count[rec] = count;
@@ -182,7 +183,7 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
 }
 
 __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const CallTables* __restrict__ tab, ProjBuffers pb,
-                                                                      const float* __restrict__ acc,
+                                                                      float* __restrict__ acc,
                                                                       float* __restrict__ pose_partial) {
   __shared__ float red[kProjBlock / 64];
   const int s = set_of_block(tab, blockIdx.x);
@@ -209,11 +210,16 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
     const uint32_t rec = V.rec_base + (uint32_t)ii;
     float pose[6] = {0, 0, 0, 0, 0, 0};
     if (live && pb.count[rec] != 0) {
-      const float* g = acc + (size_t)rec * kNumAcc;
+      // read the record's accumulated gradient and leave its row zero for
+      // the next backward (rows of culled records are never touched)
+      float* g = acc + (size_t)rec * kNumAcc;
       const float gu = g[0], gv = g[1], gQa = g[2], gQb = g[3], gQc = g[4], go = g[5];
       const float gz_direct = g[9];
+      const float gc0 = g[6], gc1 = g[7], gc2 = g[8];
+#pragma unroll
+      for (int k = 0; k < kNumAcc; ++k) g[k] = 0.0f;
       dop += go;
-      dcol[0] += g[6]; dcol[1] += g[7]; dcol[2] += g[8];
+      dcol[0] += gc0; dcol[1] += gc1; dcol[2] += gc2;
 
       const SpecPoint p = spec_point(V, mx, my, mz);
       float Sc[9];
@@ -398,7 +404,7 @@ hipError_t launch_project(const CallTables* d_tab, const CallTables& h_tab, Proj
 }
 
 hipError_t launch_project_backward(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
-                                   const float* acc, float* pose_partial, hipStream_t s) {
+                                   float* acc, float* pose_partial, hipStream_t s) {
   const uint32_t blocks = project_blocks(h_tab);
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(project_backward_kernel, dim3(blocks), dim3(kProjBlock), 0, s, d_tab, pb, acc, pose_partial);

@@ -90,7 +90,7 @@ void free_buf(DevBuf& b) {
 namespace vpgs {
 
 void destroy_saved(vpgs_saved* s) {
-  DevBuf* bufs[] = {&s->tab, &s->rec, &s->count, &s->scan_ws,
+  DevBuf* bufs[] = {&s->tab, &s->rec, &s->count, &s->zkey, &s->scan_ws,
                     &s->keys, &s->vals, &s->keys_alt, &s->vals_alt, &s->sort_ws, &s->ranges, &s->tfinal,
                     &s->ncontrib, &s->counters, &s->acc, &s->pose_partial, &s->dk, &s->dk_alt, &s->dv,
                     &s->dv_alt, &s->dcount, &s->dpoff, &s->key64};
@@ -224,6 +224,7 @@ int upload_tables(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
 ProjBuffers proj_of(vpgs_saved* s) {
   ProjBuffers pb;
   pb.rec = static_cast<float4*>(s->rec.p);
+  pb.zkey = static_cast<uint32_t*>(s->zkey.p);
   pb.count = static_cast<uint32_t*>(s->count.p);
   return pb;
 }
@@ -285,7 +286,7 @@ int prepare_front(vpgs_ctx* ctx, vpgs_saved* sv) {
       (rc = ensure(ctx, sv->dpoff, R * 4)) || (rc = ensure(ctx, sv->sort_ws, sort_workspace_bytes((uint32_t)R))))
     return rc;
   if ((rc = ensure(ctx, sv->tab, sizeof(CallTables))) || (rc = ensure(ctx, sv->rec, R * kRecSlots * 16)) ||
-      (rc = ensure(ctx, sv->count, R * 4)) ||
+      (rc = ensure(ctx, sv->count, R * 4)) || (rc = ensure(ctx, sv->zkey, R * 4)) ||
       (rc = ensure(ctx, sv->scan_ws, scan_workspace_bytes((uint32_t)R))) ||
       (rc = ensure(ctx, sv->ranges, (size_t)T.n_tiles * 8)) || (rc = ensure(ctx, sv->tfinal, pixels * 4)) ||
       (rc = ensure(ctx, sv->ncontrib, pixels * 4)) || (rc = ensure(ctx, sv->counters, sizeof(Counters))))
@@ -304,14 +305,19 @@ int ensure_pairs(vpgs_ctx* ctx, vpgs_saved* sv, uint32_t cap) {
   return VPGS_OK;
 }
 
-int ensure_backward(vpgs_ctx* ctx, vpgs_saved* sv) {
+// The gradient accumulator is zero between backwards: it is cleared once
+// when (re)allocated, and the projection backward clears every row it reads
+// (the only rows the compositing backward adds to).
+int ensure_backward(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
   const CallTables& T = *sv->h_tab;
   const size_t R = T.n_records;
   const uint32_t pblocks = project_blocks(T);
+  const void* old_acc = sv->acc.p;
   int rc;
   if ((rc = ensure(ctx, sv->acc, R * kNumAcc * sizeof(float))) ||
       (rc = ensure(ctx, sv->pose_partial, (size_t)T.n_views * std::max<uint32_t>(pblocks, 1u) * 6 * sizeof(float))))
     return rc;
+  if (sv->acc.p != old_acc) HIP_TRY(launch_fill_f32(static_cast<float*>(sv->acc.p), 0.0f, sv->acc.cap / 4, st));
   return VPGS_OK;
 }
 
@@ -354,7 +360,7 @@ int enqueue_front(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
   {
     // visible records (count != 0), compacted in record order with their depth keys
     StageTimer t(ctx, ST_SCAN, st);
-    HIP_TRY(launch_compact_visible(pb.count, pb.rec, T.n_records, static_cast<uint32_t*>(sv->dk.p),
+    HIP_TRY(launch_compact_visible(pb.count, pb.zkey, T.n_records, static_cast<uint32_t*>(sv->dk.p),
                                    static_cast<uint32_t*>(sv->dv.p), &cnt->visible, sv->scan_ws.p, st));
   }
   {
@@ -416,12 +422,10 @@ int enqueue_backward(vpgs_ctx* ctx, vpgs_saved* sv, float* d_pose, hipStream_t s
   const CallTables* d_tab = static_cast<const CallTables*>(sv->tab.p);
   Counters* cnt = static_cast<Counters*>(sv->counters.p);
   const ProjBuffers pb = proj_of(sv);
-  const size_t R = T.n_records;
   float* acc = static_cast<float*>(sv->acc.p);
   const uint32_t* svals = static_cast<const uint32_t*>(sv->result_in_alt ? sv->vals_alt.p : sv->vals.p);
   {
     StageTimer t(ctx, ST_FILL, st);
-    HIP_TRY(launch_fill_f32(acc, 0.0f, R * kNumAcc, st));
     HIP_TRY(launch_fill_u32(&cnt->queue_bwd, 0u, 1, st));
   }
   {
@@ -587,7 +591,7 @@ int vpgs_render_backward(vpgs_ctx* ctx, const vpgs_saved* saved_c, const vpgs_im
   HIP_TRY(hipEventSynchronize(sv->tab_uploaded));
   int rc = bind_backward(ctx, *sv->h_tab, grad_out, grads);
   if (rc) return rc;
-  if ((rc = ensure_backward(ctx, sv)) || (rc = upload_tables(ctx, sv, st)) ||
+  if ((rc = ensure_backward(ctx, sv, st)) || (rc = upload_tables(ctx, sv, st)) ||
       (rc = enqueue_backward(ctx, sv, d_pose, st)))
     return rc;
   return VPGS_OK;
@@ -637,7 +641,6 @@ int vpgs_saved_export(vpgs_ctx* ctx, const vpgs_saved* saved, int what, void* ds
     case VPGS_BUF_RANGES: need = (size_t)T.n_tiles * 8; break;
     case VPGS_BUF_TFINAL: need = (size_t)saved->n_pixels * 4; break;
     case VPGS_BUF_NCONTRIB: need = (size_t)saved->n_pixels * 4; break;
-    case VPGS_BUF_GRADACC: need = saved->acc.p ? R * kNumAcc * 4 : 0; break;
     default: return fail(ctx, VPGS_EINVAL, "unknown buffer %d", what);
   }
   if (size) *size = need;
@@ -672,7 +675,6 @@ int vpgs_saved_export(vpgs_ctx* ctx, const vpgs_saved* saved, int what, void* ds
     case VPGS_BUF_RANGES: HIP_TRY(hipMemcpyAsync(dst, saved->ranges.p, need, hipMemcpyDeviceToDevice, st)); break;
     case VPGS_BUF_TFINAL: HIP_TRY(hipMemcpyAsync(dst, saved->tfinal.p, need, hipMemcpyDeviceToDevice, st)); break;
     case VPGS_BUF_NCONTRIB: HIP_TRY(hipMemcpyAsync(dst, saved->ncontrib.p, need, hipMemcpyDeviceToDevice, st)); break;
-    case VPGS_BUF_GRADACC: HIP_TRY(hipMemcpyAsync(dst, saved->acc.p, need, hipMemcpyDeviceToDevice, st)); break;
   }
   return VPGS_OK;
 }

@@ -29,7 +29,7 @@ struct vpgs_saved {
   // event so an in-flight upload is never overwritten
   vpgs::CallTables* h_tab = nullptr;
   hipEvent_t tab_uploaded = nullptr;
-  vpgs::DevBuf tab, rec, count, scan_ws, keys, vals, keys_alt, vals_alt, sort_ws, ranges,
+  vpgs::DevBuf tab, rec, count, zkey, scan_ws, keys, vals, keys_alt, vals_alt, sort_ws, ranges,
       tfinal, ncontrib, counters, acc, pose_partial, dk, dk_alt, dv, dv_alt, dcount, dpoff, key64;
   int result_in_alt = 0;
   int depth_in_alt = 0;
@@ -75,7 +75,7 @@ int bind_backward(vpgs_ctx* ctx, CallTables& T, const vpgs_image_grads* grad_out
 int upload_tables(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st);
 int prepare_front(vpgs_ctx* ctx, vpgs_saved* sv);
 int ensure_pairs(vpgs_ctx* ctx, vpgs_saved* sv, uint32_t cap);
-int ensure_backward(vpgs_ctx* ctx, vpgs_saved* sv);
+int ensure_backward(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st);
 int read_pair_count(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st, uint32_t* out);
 int enqueue_front(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st);
 int enqueue_back(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st);

@@ -69,6 +69,37 @@ __global__ void __launch_bounds__(kScanBlock) scan_reduce_kernel(const uint32_t*
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
+// Down-sweeps.  Each wavefront owns kWaveItems consecutive values of its
+// block's tile and walks them in rounds of 64 (coalesced loads and stores):
+// its offset within the block comes from the other wavefronts' totals (one
+// barrier), each round is a wavefront scan carried by a running sum.
+constexpr int kWaveItems = kScanTile / (kScanBlock / 64);  // 1024
+constexpr int kWaveRounds = kWaveItems / 64;                // 16
+
+// Sum of one value per lane over the wavefront (every lane gets it).
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Exclusive prefix of this wavefront within its block from the wavefront
+// totals; the last wavefront's end is the block total.
+__device__ __forceinline__ uint32_t wave_offset(uint32_t wave_total, uint32_t* lds, uint32_t* block_total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) lds[wave] = wave_total;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kScanBlock / 64; ++w) {
+    const uint32_t x = lds[w];
+    if (w < wave) off += x;
+    tot += x;
+  }
+  *block_total = tot;
+  return off;
+}
+
 // Exclusive scan of each block's tile, offset by block_offsets[block]
 // (NULL = 0).  If total is non-NULL the last block writes the grand total.
 __global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t* __restrict__ in, uint32_t n_alloc,
@@ -78,61 +109,66 @@ __global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t* _
                                                                int flags) {
   __shared__ uint32_t lds[kScanBlock / 64];
   const uint32_t n = scan_length(n_alloc, n_dev);
-  const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;  // blocked layout
-  uint32_t v[kScanItems];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)wave * kWaveItems + lane;
+  uint32_t v[kWaveRounds];
   uint32_t s = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const size_t idx = base + k;
+  for (int k = 0; k < kWaveRounds; ++k) {
+    const size_t idx = base + (size_t)k * 64;
     v[k] = idx < n ? scan_value(in[idx], flags) : 0u;
     s += v[k];
   }
   uint32_t tot;
-  uint32_t run = block_excl_scan(s, lds, &tot);
   const uint32_t off = block_offsets ? block_offsets[blockIdx.x] : 0u;
-  run += off;
+  uint32_t run = off + wave_offset(wave_sum(s), lds, &tot);
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const size_t idx = base + k;
-    if (idx < n) out[idx] = run;
-    run += v[k];
+  for (int k = 0; k < kWaveRounds; ++k) {
+    const size_t idx = base + (size_t)k * 64;
+    const uint32_t incl = wave_incl_scan(v[k]);
+    if (idx < n) out[idx] = run + incl - v[k];
+    run += __shfl(incl, 63, 64);
   }
   if (total != nullptr && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
 }
 
 // Down-sweep of the indicator scan (count != 0) that scatters instead of
 // storing offsets: visible record r goes to position (number of visible
-// records before r), with key = bits of its FP32 depth (slot 0 .z of its
-// projection record) and value r.
-// Record order is kept, so equal depths stay in index order.
+// records before r), with key = its depth key and value r.  Record order is
+// kept, so equal depths stay in index order.
 __global__ void __launch_bounds__(kScanBlock) compact_down_kernel(const uint32_t* __restrict__ count, uint32_t n,
                                                                   const uint32_t* __restrict__ block_offsets,
-                                                                  const float4* __restrict__ recs,
+                                                                  const uint32_t* __restrict__ zkey,
                                                                   uint32_t* __restrict__ keys,
                                                                   uint32_t* __restrict__ vals,
                                                                   uint32_t* __restrict__ total) {
   __shared__ uint32_t lds[kScanBlock / 64];
-  const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)wave * kWaveItems + lane;
+  uint32_t flags = 0;  // bit k: this lane's value of round k is visible
   uint32_t s = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const size_t idx = base + k;
-    v[k] = (idx < n && count[idx] != 0u) ? 1u : 0u;
-    s += v[k];
+  for (int k = 0; k < kWaveRounds; ++k) {
+    const size_t idx = base + (size_t)k * 64;
+    const bool vis = idx < n && count[idx] != 0u;
+    flags |= (vis ? 1u : 0u) << k;
+    s += __popcll(__ballot(vis));
   }
   uint32_t tot;
-  uint32_t run = block_excl_scan(s, lds, &tot);
   const uint32_t off = block_offsets ? block_offsets[blockIdx.x] : 0u;
-  run += off;
+  uint32_t run = off + wave_offset(s, lds, &tot);
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    if (v[k]) {
-      const size_t idx = base + k;
-      keys[run] = __float_as_uint(recs[rec_slot((uint32_t)idx, 0)].z);
-      vals[run] = (uint32_t)idx;
+  for (int k = 0; k < kWaveRounds; ++k) {
+    const bool vis = (flags >> k) & 1u;
+    const uint64_t m = __ballot(vis);
+    if (vis) {
+      const size_t idx = base + (size_t)k * 64;
+      const uint32_t pos =
+          run + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      keys[pos] = zkey[idx];
+      vals[pos] = (uint32_t)idx;
     }
-    run += v[k];
+    run += __popcll(m);
   }
   if (total != nullptr && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
 }
@@ -184,12 +220,12 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_compact_visible(const uint32_t* count, const float4* recs, uint32_t n, uint32_t* keys, uint32_t* vals,
+hipError_t launch_compact_visible(const uint32_t* count, const uint32_t* zkey, uint32_t n, uint32_t* keys, uint32_t* vals,
                                   uint32_t* total, void* ws, hipStream_t s) {
   if (n == 0) return total ? launch_fill_u32(total, 0u, 1, s) : hipSuccess;
   const uint32_t blocks = div_up(n, kScanTile);
   if (blocks == 1) {
-    hipLaunchKernelGGL(compact_down_kernel, dim3(1), dim3(kScanBlock), 0, s, count, n, nullptr, recs, keys, vals, total);
+    hipLaunchKernelGGL(compact_down_kernel, dim3(1), dim3(kScanBlock), 0, s, count, n, nullptr, zkey, keys, vals, total);
     return hipGetLastError();
   }
   char* w = static_cast<char*>(ws);
@@ -201,7 +237,7 @@ hipError_t launch_compact_visible(const uint32_t* count, const float4* recs, uin
   if (e != hipSuccess) return e;
   e = launch_scan(sums, sums_scanned, blocks, total, w + 2 * sum_bytes, s, false, nullptr);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(compact_down_kernel, dim3(blocks), dim3(kScanBlock), 0, s, count, n, sums_scanned, recs, keys, vals,
+  hipLaunchKernelGGL(compact_down_kernel, dim3(blocks), dim3(kScanBlock), 0, s, count, n, sums_scanned, zkey, keys, vals,
                      nullptr);
   return hipGetLastError();
 }

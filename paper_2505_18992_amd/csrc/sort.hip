@@ -61,7 +61,6 @@ __device__ __forceinline__ void emit_range(uint32_t k0, uint32_t k1, uint32_t st
 constexpr uint32_t kSmallFootprint = 8;  // records with more tiles are emitted by the whole wavefront
 
 __global__ void __launch_bounds__(256) emit_kernel(const CallTables* __restrict__ tab, const float4* __restrict__ recs,
-                                                   const uint32_t* __restrict__ count,
                                                    const uint32_t* __restrict__ sorted_rec,
                                                    const uint32_t* __restrict__ pair_off,
                                                    const uint32_t* __restrict__ n_visible, Counters* __restrict__ cnt,
@@ -73,14 +72,14 @@ __global__ void __launch_bounds__(256) emit_kernel(const CallTables* __restrict_
   uint32_t rec = 0, c = 0, off = 0, tile0 = 0, w = 1, tiles_x = 1;
   if (i < nv) {
     rec = sorted_rec[i];
-    c = count[rec];
     off = pair_off[i];
     const ViewDesc& V = tab->views[view_of_record(tab, rec)];
     const float4 x = recs[rec_slot(rec, 3)];
     const uint32_t rx = __float_as_uint(x.z), ry = __float_as_uint(x.w);
-    const uint32_t tx0 = rx & 0xffffu, tx1 = rx >> 16, ty0 = ry & 0xffffu;
+    const uint32_t tx0 = rx & 0xffffu, tx1 = rx >> 16, ty0 = ry & 0xffffu, ty1 = ry >> 16;
     tiles_x = (uint32_t)V.tiles_x;
     w = tx1 - tx0 + 1u;
+    c = w * (ty1 - ty0 + 1u);  // the record's count
     tile0 = V.tile_base + ty0 * tiles_x + tx0;
     if (off + c > capacity || off + c < off) cnt->overflow = 1u;
   }
@@ -362,7 +361,7 @@ hipError_t launch_emit(const CallTables* d_tab, const CallTables& h, const ProjB
                        const uint32_t* pair_off, const uint32_t* n_visible, Counters* cnt, uint32_t* keys,
                        uint32_t* vals, uint32_t capacity, hipStream_t s) {
   if (h.n_records == 0) return hipSuccess;
-  hipLaunchKernelGGL(emit_kernel, dim3(div_up(h.n_records, 256)), dim3(256), 0, s, d_tab, pb.rec, pb.count,
+  hipLaunchKernelGGL(emit_kernel, dim3(div_up(h.n_records, 256)), dim3(256), 0, s, d_tab, pb.rec,
                      sorted_rec, pair_off, n_visible, cnt, h.n_records, capacity, keys, vals);
   return hipGetLastError();
 }

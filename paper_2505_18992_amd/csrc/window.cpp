@@ -74,7 +74,7 @@ int size_pairs(vpgs_window* w, hipStream_t st, int64_t fixed) {
     if ((rc = enqueue_front(ctx, w->sv, st)) || (rc = read_pair_count(ctx, w->sv, st, &cap))) return rc;
     cap = (uint32_t)std::min<uint64_t>((uint64_t)cap + cap / 4 + 4096, 0x7fffffffull);
   }
-  if ((rc = ensure_pairs(ctx, w->sv, cap)) || (rc = ensure_backward(ctx, w->sv))) return rc;
+  if ((rc = ensure_pairs(ctx, w->sv, cap)) || (rc = ensure_backward(ctx, w->sv, st))) return rc;
   return VPGS_OK;
 }
 
