@@ -319,7 +319,7 @@ __device__ __forceinline__ bool scatter_writer(int lane) {
 
 template <int TW, int TH>
 struct BwdShared {
-  float4 A[TW * TH + 1], E[TW * TH + 1], B[TW * TH + 1], C[TW * TH + 1];
+  float4 A[TW * TH + 1], E[TW * TH + 1], C[TW * TH + 1];  // C = (r, g, b, 1 / opacity)
   uint32_t rec[TW * TH];
   uint16_t hits[(TW * TH) / 64][TW * TH + kGroup];  // per wavefront, descending
   uint32_t maxlast[(TW * TH) / 64];
@@ -375,12 +375,11 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
         const uint32_t rec = vals[rg.x + (uint32_t)j];
         const float4* r = recs + rec_slot(rec, 0);
         const float4 A = r[0];
-        const float4 B = r[1];
+        const float4 c = r[2];
         sh.rec[threadIdx.x] = rec;
         sh.A[threadIdx.x] = A;
-        sh.E[threadIdx.x] = stage_exponent(A, B);
-        sh.B[threadIdx.x] = make_float4(B.x, B.y, B.z, 1.0f / A.w);
-        sh.C[threadIdx.x] = r[2];
+        sh.E[threadIdx.x] = stage_exponent(A, r[1]);
+        sh.C[threadIdx.x] = make_float4(c.x, c.y, c.z, 1.0f / A.w);
         }
     }
     __syncthreads();
@@ -395,24 +394,29 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
       const Falloff f = falloff(A, sh.E[sl], pxc, pyc);
       const bool valid = (uint32_t)j < last && f.alpha >= kAlphaMin;
       if (__ballot(valid) == 0ull) continue;
-      const float4 B = sh.B[sl];
       const float4 c = sh.C[sl];
       const float r1m = __builtin_amdgcn_rcpf(1.0f - f.alpha);
       const float Tj = valid ? T * r1m : T;
-      const float fj = gC0 * c.x + gC1 * c.y + gC2 * c.z + gD * A.z + gA;
+      const float fj = fmaf(gC0, c.x, fmaf(gC1, c.y, fmaf(gC2, c.z, fmaf(gD, A.z, gA))));
       const float dLda = Tj * fj - S * r1m;
       const float w = valid ? f.alpha * Tj : 0.0f;
       S = fmaf(w, fj, S);
       T = Tj;
-      const bool unclamped = valid && f.raw < kAlphaMax;
-      const float ds = unclamped ? -dLda * f.raw : 0.0f;  // dL/dsigma = dL/dalpha * (-alpha)
+      // s = dL/dalpha * alpha where alpha is not clamped (0 where it is):
+      // dL/dsigma = -s and dL/do = s / o.  The conic terms are accumulated
+      // as moments of s over the pixel offsets d = mean - pixel centre,
+      //   (sum s dx, sum s dy, sum s dx^2, sum s dx dy, sum s dy^2),
+      // which the projection backward turns into dL/du, dL/dv = -Q (M0, M1)
+      // and dL/d(Qa, Qb, Qc) = -(M2 / 2, M3, M4 / 2).
+      const float sg = (valid && f.raw < kAlphaMax) ? dLda * f.raw : 0.0f;
+      const float sx = sg * f.dx, sy = sg * f.dy;
       float g[kNumAcc];
-      g[0] = ds * (B.x * f.dx + B.y * f.dy);
-      g[1] = ds * (B.y * f.dx + B.z * f.dy);
-      g[2] = ds * 0.5f * f.dx * f.dx;
-      g[3] = ds * f.dx * f.dy;
-      g[4] = ds * 0.5f * f.dy * f.dy;
-      g[5] = unclamped ? dLda * f.raw * B.w : 0.0f;  // dalpha/do = exp(-sigma) = raw / o
+      g[0] = sx;
+      g[1] = sy;
+      g[2] = sx * f.dx;
+      g[3] = sx * f.dy;
+      g[4] = sy * f.dy;
+      g[5] = sg * c.w;
       g[6] = w * gC0;
       g[7] = w * gC1;
       g[8] = w * gC2;

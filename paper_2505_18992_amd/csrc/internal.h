@@ -19,7 +19,10 @@ constexpr float kGuardHi = 1.15f;
 constexpr float kDefaultNear = 0.2f;
 
 // Number of per-record gradient accumulators written by the backward
-// compositor: d(u, v, Qa, Qb, Qc, opacity, r, g, b, z).
+// compositor.  With s = dL/dalpha * alpha per pixel (0 where alpha is
+// clamped) and d = (u, v) - pixel centre they hold
+//   sum s dx, sum s dy, sum s dx^2, sum s dx dy, sum s dy^2,   (conic moments)
+//   dL/dopacity, dL/d(r, g, b), dL/dz.
 constexpr int kNumAcc = 10;
 
 // One view of a render call, as the kernels see it.

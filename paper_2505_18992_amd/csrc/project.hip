@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
       // read the record's accumulated gradient and leave its row zero for
       // the next backward (rows of culled records are never touched)
       float* g = acc + (size_t)rec * kNumAcc;
-      const float gu = g[0], gv = g[1], gQa = g[2], gQb = g[3], gQc = g[4], go = g[5];
+      const float m0 = g[0], m1 = g[1], m2 = g[2], m3 = g[3], m4 = g[4], go = g[5];
       const float gz_direct = g[9];
       const float gc0 = g[6], gc1 = g[7], gc2 = g[8];
 #pragma unroll
@@ -235,6 +235,11 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
       const float c = J11 * J11 * Sc[4] + 2.f * J11 * J12 * Sc[5] + J12 * J12 * Sc[8] + kDilate;
       const float idet = 1.0f / (a * c - b * b);
       const float Qa = c * idet, Qb = -b * idet, Qc = a * idet;
+      // the row holds moments of s = dL/dalpha * alpha over the pixel offsets
+      // d = (u, v) - pixel centre; dL/dsigma = -s with
+      // sigma = (Qa dx^2 + 2 Qb dx dy + Qc dy^2) / 2
+      const float gu = -(Qa * m0 + Qb * m1), gv = -(Qb * m0 + Qc * m1);
+      const float gQa = -0.5f * m2, gQb = -m3, gQc = -0.5f * m4;
 
       // conic = Sigma2D^-1:  dL/dSigma2D = -Q G Q, G the symmetric conic gradient
       const float dA = -(Qa * Qa * gQa + Qa * Qb * gQb + Qb * Qb * gQc);
