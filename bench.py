@@ -137,8 +137,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c4-1200")
-    ap.add_argument("--tile", default="16x16", help="WxH, or auto for the window's search over shapes")
-    ap.add_argument("--persistent", type=int, default=1024,
+    ap.add_argument("--tile", default="32x8", help="WxH, or auto for the window's search over shapes")
+    ap.add_argument("--persistent", type=int, default=0,
                     help="persistent compositing workgroups: 0 one per tile, -1 search")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-one-view", action="store_true",

@@ -222,8 +222,9 @@ __device__ __forceinline__ void flush_counts(uint32_t ne, uint32_t nb, Counters*
     b += __shfl_xor(b, off, 64);
   }
   if ((threadIdx.x & 63) == 0) {
-    atomicAdd(&cnt->evaluated, e);
-    atomicAdd(&cnt->blended, b);
+    const int slot = (int)(blockIdx.x % kCountSlots);
+    atomicAdd(&cnt->evaluated[slot], e);
+    atomicAdd(&cnt->blended[slot], b);
   }
 }
 

@@ -71,9 +71,13 @@ struct CallTables {
 };
 
 // Device counters of one forward.
+// The evaluation and blend counts are spread over kCountSlots slots (each
+// wavefront adds to the slot of its workgroup index) so that thousands of
+// workgroups do not serialise on one address; readers sum the slots.
+constexpr int kCountSlots = 64;
 struct Counters {
-  unsigned long long evaluated;
-  unsigned long long blended;
+  unsigned long long evaluated[kCountSlots];
+  unsigned long long blended[kCountSlots];
   uint32_t pairs;      // pairs requested by the scan
   uint32_t overflow;   // 1 if pairs > capacity
   uint32_t visible;
@@ -81,6 +85,7 @@ struct Counters {
   uint32_t queue_bwd;  // and of the persistent backward compositor
   uint32_t pad[3];
 };
+static_assert(sizeof(Counters) <= 4096, "the counters are read back through a 4 KiB pinned buffer");
 
 // Per-record projected data (struct of arrays).
 // Per-(view, Gaussian) projection record: four float4 (64 bytes, one

@@ -609,8 +609,13 @@ int vpgs_saved_stats(vpgs_ctx* ctx, const vpgs_saved* saved, vpgs_stats* out, vo
   const CallTables& T = *saved->h_tab;
   out->n_records = T.n_records;
   out->n_pairs = hc->pairs;
-  out->n_evaluated = (int64_t)hc->evaluated;
-  out->n_blended = (int64_t)hc->blended;
+  unsigned long long ev = 0, bl = 0;
+  for (int k = 0; k < kCountSlots; ++k) {
+    ev += hc->evaluated[k];
+    bl += hc->blended[k];
+  }
+  out->n_evaluated = (int64_t)ev;
+  out->n_blended = (int64_t)bl;
   out->pair_capacity = saved->capacity;
   out->n_tiles = T.n_tiles;
   out->n_pixels = saved->n_pixels;
