@@ -48,12 +48,12 @@ SORT_BYTES_PER_PAIR_PASS = 20.0  # 32-bit keys and values: histogram read 4 B, s
 # only for the kernel sources they were taken with; after any change to
 # those the traffic is reported as null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("composite_backward", 16, 16, 1024): {
-        "sources_sha256": "3090431fa60c3e7ffb14c5b722d191e4af30b8f0b825f84d30037ea26ce0447a",
-        "fetch_bytes": 1006371275, "write_bytes": 614622272},
-    ("composite_forward", 16, 16, 1024): {
-        "sources_sha256": "3090431fa60c3e7ffb14c5b722d191e4af30b8f0b825f84d30037ea26ce0447a",
-        "fetch_bytes": 753059526, "write_bytes": 186406704},
+    ("composite_backward", 32, 8, 0): {
+        "sources_sha256": "95a588fd6282fcc4c19281d6375bb524a17ffe01bfab071cabffd4b4e102fa8a",
+        "fetch_bytes": 1109627039, "write_bytes": 613763904},
+    ("composite_forward", 32, 8, 0): {
+        "sources_sha256": "95a588fd6282fcc4c19281d6375bb524a17ffe01bfab071cabffd4b4e102fa8a",
+        "fetch_bytes": 943182169, "write_bytes": 197206213},
 }
 TRAFFIC_SOURCES = ("paper_2505_18992_amd/csrc/composite.hip", "paper_2505_18992_amd/csrc/internal.h")
 
