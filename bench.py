@@ -131,6 +131,39 @@ def cpu_baseline(sc, budget_s=25.0):
             "blends_per_sec": blends / t_view, "seconds_measured": t_fwd + t_grad}
 
 
+LOSS_BYTES_PER_PIXEL = 52.0  # rendered colour+depth and target colour+depth read (32 B), 3+1+1 gradient planes written
+
+
+def time_mapping_loss(win, cams, steps):
+    """Mapping loss (eq. 7-8) of every view of the window against a
+    perturbed copy of its rendered frame: ms per call over all views and the
+    achieved rate of the algorithmic bytes (inputs read once, planes written
+    once)."""
+    import torch
+    from paper_2505_18992_amd import mapping_loss
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    ims, tgs = [], []
+    for rgb, depth, _ in win.outputs:
+        ims.append((rgb, depth))
+        noise = torch.randn(rgb.shape, generator=gen, device=rgb.device) * 0.05
+        tgs.append(((rgb + noise).clamp(0, 1).contiguous(), torch.where(depth > 0, depth * 1.02, depth).contiguous()))
+    terms, _ = mapping_loss(ims, tgs, cams)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        mapping_loss(ims, tgs, cams)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    pixels = sum(c.width * c.height for c in cams)
+    gbs = LOSS_BYTES_PER_PIXEL * pixels / (ms * 1e-3) / 1e9
+    log(f"[bench] mapping loss: {ms:.3f} ms for {len(cams)} views ({gbs:.0f} GB/s of algorithmic bytes)")
+    return {"ms_per_call": ms, "views": len(cams), "bytes_per_pixel": LOSS_BYTES_PER_PIXEL, "achieved_GBs": gbs,
+            "peak_GBs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS,
+            "loss_view0": [float(v) for v in terms[0].cpu().tolist()]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +272,10 @@ def main():
         log(f"[bench] one view per launch: {ms_per_view_launch:.3f} ms for {nv} views; "
             f"eager window {ms_eager_window:.3f} ms")
 
+    # the mapping loss of eq. 7-8 on the same views (rendered frames against
+    # perturbed copies of themselves), timed on its own
+    loss_stage = time_mapping_loss(win, cams, args.steps)
+
     E, B, P = st["n_evaluated"], st["n_blended"], st["n_pairs"]
     dom = max(stage_ms, key=stage_ms.get)
     t_dom = stage_ms[dom] * 1e-3
@@ -282,6 +319,7 @@ def main():
         {"ms_for_all_views": ms_per_view_launch, "views_per_sec": nv / (ms_per_view_launch * 1e-3),
          "batched_speedup": ms_per_view_launch / ms_step},
         "stage_ms": stage_ms,
+        "mapping_loss": loss_stage,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

@@ -250,12 +250,12 @@ int vpgs_window_destroy(vpgs_window* win);
  * events on its stream around each stage (projection, scan, emission, sort,
  * ranges, forward compositing, backward compositing, projection backward,
  * pose reduction, fills, decode forward, decode backward, depth ordering of
- * the visible records).  vpgs_profile_read
+ * the visible records, mapping loss, volume loss).  vpgs_profile_read
  * synchronises on the recorded events and returns, for stage index `stage`
  * (0 <= stage < VPGS_NUM_STAGES), its name, the number of recorded launches
  * and their summed duration in milliseconds since the last enable.  Disabled
  * by default; enabling resets the totals. */
-#define VPGS_NUM_STAGES 13
+#define VPGS_NUM_STAGES 15
 int vpgs_profile_enable(vpgs_ctx* ctx, int on);
 int vpgs_profile_read(vpgs_ctx* ctx, int stage, const char** name, int64_t* calls, double* total_ms);
 
@@ -307,6 +307,47 @@ int vpgs_decode_forward(vpgs_ctx* ctx, const vpgs_anchors* anchors, const vpgs_m
 int vpgs_decode_backward(vpgs_ctx* ctx, const vpgs_anchors* anchors, const vpgs_mlp* mlp,
                          const float* cam_center, const vpgs_gauss_grads* upstream, float* d_feat,
                          float* d_scale, float* d_offsets, const vpgs_mlp_grads* d_mlp, void* stream);
+
+/* ---- mapping loss (Section III-A, eq. 7-9) -------------------------------- */
+
+/* Target frame of one view: colour [3,H,W] and depth [H,W] (device); pixels
+ * whose target depth is <= 0 carry no depth. */
+typedef struct {
+  const float* rgb;
+  const float* depth;
+} vpgs_targets;
+
+typedef struct {
+  float lambda_ssim;  /* weight of the SSIM term inside L_SSIM (eq. 8); the paper uses 0.2 */
+  float lambda_depth; /* weight of the depth term in eq. 7 (not given in the paper; 1 is the default) */
+  int32_t reserved0, reserved1;
+} vpgs_loss_opts;
+
+/* Mapping loss of eq. 7-8 for n_views rendered views against their targets:
+ *   L_c    = mean |X - Y| over channels and pixels (X rendered, Y target colour)
+ *   L_SSIM = (1 - lambda_ssim) mean |X - Y| + lambda_ssim (1 - mean SSIM(X, Y))
+ *   L_d    = mean |D - T| over pixels with target depth T > 0 (0 if none)
+ *   L      = L_c + L_SSIM + lambda_depth L_d
+ * SSIM: 11x11 Gaussian window of sigma 1.5, zero-padded same-size filtering
+ * per channel, C1 = 0.01^2, C2 = 0.03^2, averaged over channels and pixels.
+ * Only cams[v].width/height are read.  rendered[v].rgb/.depth are read.
+ * Writes terms[4 v + k] (device floats: L_c, L_SSIM, L_d, L) and the gradient
+ * of sum_v L_v with respect to the rendered planes into grad[v].rgb and
+ * grad[v].depth (written in full; d|x|/dx is 0 at 0); grad[v].alpha, if
+ * non-NULL, is zeroed.  These planes are the upstream gradients the render
+ * backward takes.  opts NULL = (0.2, 1).  A workspace of 36 bytes per pixel of
+ * the largest view is kept in the context.  Asynchronous on `stream`. */
+int vpgs_mapping_loss(vpgs_ctx* ctx, int n_views, const vpgs_camera* cams, const vpgs_images* rendered,
+                      const vpgs_targets* targets, const vpgs_loss_opts* opts, float* terms,
+                      const vpgs_images* grad, void* stream);
+
+/* Volume regulariser of eq. 9 for n_sets Gaussian sets:
+ * loss[s] (device float) = lambda_vol * sum_i prod(exp(log_scales_i)), and its
+ * gradient lambda_vol * prod(exp(log_scales_i)) is ADDED to each of the three
+ * entries of grads[s].log_scales (run it after the render backward, which
+ * writes those gradients).  The paper uses lambda_vol = 0.001. */
+int vpgs_volume_loss(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, float lambda_vol, float* loss,
+                     const vpgs_gauss_grads* grads, void* stream);
 
 #ifdef __cplusplus
 }

@@ -26,7 +26,7 @@ import numpy as np
 import torch
 
 __all__ = ["WINDOW", "SIGMA", "C1", "C2", "window_1d", "ssim_map", "ssim_map_bruteforce", "view_loss",
-           "view_loss_grad", "volume_loss"]
+           "view_loss_grad", "view_grad_bounds", "volume_loss"]
 
 WINDOW = 11
 SIGMA = 1.5
@@ -132,3 +132,36 @@ def volume_loss(log_scales, lam_vol=0.001):
     val = lam_vol * float(prod.sum())
     grad = (lam_vol * prod)[:, None].expand(-1, 3).numpy().copy()
     return val, grad
+
+
+def view_grad_bounds(rgb, t_rgb, lam_ssim=0.2, lam_d=1.0):
+    """Error scales of the colour gradient (float64 [3,H,W] each), for
+    comparing a float32 evaluation:
+
+    * scale: the magnitude of its terms, |w| (G*|P1| + 2|X| G*|P2| + |Y| G*|P3|)
+      + the L1 weight, with P1..P3 the partials of the SSIM map with respect to
+      the local mean of X, E[X^2] and E[XY] and w = -lambda_ssim / N;
+    * fp32: the same filtered sum with each pixel's partials weighted by the
+      amplification of float32 rounding in its statistics,
+      (E[X^2] + mu_x^2 + E[Y^2] + mu_y^2 + 2|E[XY]| + 2|mu_x mu_y|) / min(B2, |A2|),
+      times 2^-24 (the variance-like terms are differences of filtered
+      squares, and A2, B2 are the denominators of the structure term)."""
+    x, y = _t(rgb), _t(t_rgb)
+    n = x.numel()
+    m1, m2 = _filter(x), _filter(y)
+    e11, e22, e12 = _filter(x * x), _filter(y * y), _filter(x * y)
+    A1 = 2 * m1 * m2 + C1
+    A2 = 2 * (e12 - m1 * m2) + C2
+    B1 = m1 * m1 + m2 * m2 + C1
+    B2 = (e11 - m1 * m1) + (e22 - m2 * m2) + C2
+    S = A1 * A2 / (B1 * B2)
+    P1 = 2 * S * (m2 / A1 - m2 / A2 - m1 / B1 + m1 / B2)
+    P2 = -S / B2
+    P3 = 2 * S / A2
+    w = lam_ssim / n
+    wl1 = (2.0 - lam_ssim) / n
+    scale = w * (_filter(P1.abs()) + 2 * x.abs() * _filter(P2.abs()) + y.abs() * _filter(P3.abs())) + wl1
+    kappa = (e11 + m1 * m1 + e22 + m2 * m2 + 2 * e12.abs() + 2 * (m1 * m2).abs()) / torch.minimum(B2, A2.abs())
+    fp32 = w * (_filter(P1.abs() * kappa) + 2 * x.abs() * _filter(P2.abs() * kappa) +
+                y.abs() * _filter(P3.abs() * kappa)) * 2.0 ** -24
+    return scale.numpy(), fp32.numpy()

@@ -22,7 +22,7 @@ VPGS_ECAPACITY = -4
 VPGS_EUNSUPPORTED = -5
 MAX_VIEWS = 64
 MAX_SETS = 64
-NUM_STAGES = 13
+NUM_STAGES = 15
 WINDOW_FORWARD, WINDOW_BACKWARD = 1, 2
 
 BUF_PROJ, BUF_EXTENT, BUF_COUNT, BUF_KEYS, BUF_VALUES, BUF_RANGES, BUF_TFINAL, BUF_NCONTRIB = range(1, 9)
@@ -84,6 +84,15 @@ class MlpGrads(ctypes.Structure):
     _fields_ = [("W1", c_void_p * 3), ("b1", c_void_p * 3), ("W2", c_void_p * 3), ("b2", c_void_p * 3)]
 
 
+class Targets(ctypes.Structure):
+    _fields_ = [("rgb", c_void_p), ("depth", c_void_p)]
+
+
+class LossOpts(ctypes.Structure):
+    _fields_ = [("lambda_ssim", ctypes.c_float), ("lambda_depth", ctypes.c_float), ("reserved0", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32)]
+
+
 # every entry point of include/vpgs.h, with its ctypes signature
 SIGNATURES = {
     "vpgs_create": (ctypes.c_int, [ctypes.POINTER(c_void_p), ctypes.c_int]),
@@ -119,6 +128,11 @@ SIGNATURES = {
     "vpgs_decode_backward": (ctypes.c_int, [c_void_p, ctypes.POINTER(Anchors), ctypes.POINTER(Mlp),
                                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(GaussBuffers), c_void_p,
                                             c_void_p, c_void_p, ctypes.POINTER(MlpGrads), c_void_p]),
+    "vpgs_mapping_loss": (ctypes.c_int, [c_void_p, ctypes.c_int, ctypes.POINTER(Camera), ctypes.POINTER(Images),
+                                         ctypes.POINTER(Targets), ctypes.POINTER(LossOpts), c_void_p,
+                                         ctypes.POINTER(Images), c_void_p]),
+    "vpgs_volume_loss": (ctypes.c_int, [c_void_p, ctypes.c_int, ctypes.POINTER(Gaussians), ctypes.c_float,
+                                        c_void_p, ctypes.POINTER(GaussBuffers), c_void_p]),
 }
 
 _LIB = None

@@ -1,0 +1,364 @@
+// loss.hip -- the mapping loss of eq. 7-9 and its gradient planes.
+//
+// Per view (rendered colour X, depth D; target colour Y, depth T):
+//   L_c    = mean |X - Y| over channels and pixels
+//   L_SSIM = (1 - ls) mean |X - Y| + ls (1 - mean SSIM(X, Y))     (eq. 8)
+//   L_d    = mean |D - T| over pixels with T > 0
+//   L      = L_c + L_SSIM + ld L_d                                  (eq. 7)
+// SSIM uses an 11x11 Gaussian window (sigma 1.5) with zero padding, C1 =
+// 0.01^2, C2 = 0.03^2.  The volume term of eq. 9 (ls, ld, lv the lambdas)
+// is a separate per-Gaussian kernel that adds lv prod(exp(l)) to the
+// log-scale gradients.
+//
+// SSIM at pixel p depends on the filtered statistics m1 = G*X, m2 = G*Y,
+// e11 = G*X^2, e22 = G*Y^2, e12 = G*XY.  With S_p the map value,
+//   dS_p/dX_q = G(p - q) (P1_p + 2 X_q P2_p + Y_q P3_p),
+//   P1 = dS/dm1, P2 = dS/de11, P3 = dS/de12 (the others held fixed),
+// so the gradient of mean S is (G*P1 + 2 X (G*P2) + Y (G*P3)) / N.  Two
+// stencil kernels per view: the first filters the five statistics and
+// writes S's partials (and block sums of the loss terms), the second
+// filters the partials and writes the gradient planes.  Both stage a
+// 32x16-pixel tile plus a 5-pixel halo in LDS and filter it separably.
+#include <algorithm>
+#include <cmath>
+
+#include "runtime.h"
+
+namespace vpgs {
+namespace {
+
+constexpr int kTileW = 32, kTileH = 16;
+constexpr int kRad = 5, kTaps = 2 * kRad + 1;
+constexpr int kHaloW = kTileW + 2 * kRad, kHaloH = kTileH + 2 * kRad;  // 42 x 26
+constexpr int kLossBlock = 256;
+constexpr float kC1 = 0.0001f, kC2 = 0.0009f;
+constexpr int kSumSlots = 64;   // block sums are spread over slots per view
+constexpr int kSums = 4;        // sum S, sum |X - Y|, sum valid |D - T|, valid count
+
+// Normalised Gaussian taps, sigma 1.5: exp(-(k - 5)^2 / 4.5) / their sum,
+// rounded to float.
+__constant__ float kGauss[kTaps] = {1.028380124e-03f, 7.598758209e-03f, 3.600077331e-02f, 1.093606874e-01f,
+                                    2.130055428e-01f, 2.660117149e-01f, 2.130055428e-01f, 1.093606874e-01f,
+                                    3.600077331e-02f, 7.598758209e-03f, 1.028380124e-03f};
+
+struct ViewArgs {
+  int W, H;
+  const float* x;   // rendered colour [3,H,W]
+  const float* d;   // rendered depth [H,W]
+  const float* y;   // target colour
+  const float* t;   // target depth
+  float* gx;        // colour gradient [3,H,W]
+  float* gd;        // depth gradient [H,W]
+  float* ga;        // alpha gradient [H,W] (zeroed) or NULL
+  float* P;         // partials workspace [3 channels][3][H,W]
+  double* sums;     // [kSums][kSumSlots] of this view
+};
+
+__device__ __forceinline__ float block_sum(float v, float* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float r = 0.f;
+#pragma unroll
+  for (int w = 0; w < kLossBlock / 64; ++w) r += red[w];
+  return r;  // every thread
+}
+
+// Loads the tile's halo window of plane `src` ([H,W]) into lds[kHaloH][kHaloW],
+// zero outside the image.
+__device__ __forceinline__ void load_halo(const float* __restrict__ src, int W, int H, int x0, int y0,
+                                          float (*lds)[kHaloW]) {
+  for (int k = threadIdx.x; k < kHaloH * kHaloW; k += kLossBlock) {
+    const int r = k / kHaloW, c = k - r * kHaloW;
+    const int gy = y0 - kRad + r, gx = x0 - kRad + c;
+    lds[r][c] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? src[(size_t)gy * W + gx] : 0.0f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// kernel 1: statistics, SSIM partials and the block sums
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kLossBlock) ssim_stats_kernel(ViewArgs a) {
+  __shared__ float sx[kHaloH][kHaloW], sy[kHaloH][kHaloW];
+  __shared__ float hs[5][kHaloH][kTileW];  // horizontal sums of x, y, x^2, y^2, xy
+  __shared__ float red[kLossBlock / 64];
+  const int c = blockIdx.z;
+  const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
+  const size_t HW = (size_t)a.W * a.H;
+  load_halo(a.x + c * HW, a.W, a.H, x0, y0, sx);
+  load_halo(a.y + c * HW, a.W, a.H, x0, y0, sy);
+  __syncthreads();
+  for (int k = threadIdx.x; k < kHaloH * kTileW; k += kLossBlock) {
+    const int r = k / kTileW, j = k - r * kTileW;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+      const float g = kGauss[t], xv = sx[r][j + t], yv = sy[r][j + t];
+      s0 = fmaf(g, xv, s0);
+      s1 = fmaf(g, yv, s1);
+      s2 = fmaf(g, xv * xv, s2);
+      s3 = fmaf(g, yv * yv, s3);
+      s4 = fmaf(g, xv * yv, s4);
+    }
+    hs[0][r][j] = s0; hs[1][r][j] = s1; hs[2][r][j] = s2; hs[3][r][j] = s3; hs[4][r][j] = s4;
+  }
+  __syncthreads();
+  float ssum = 0.f, l1sum = 0.f;
+  float* P = a.P + (size_t)c * 3 * HW;
+  for (int k = threadIdx.x; k < kTileH * kTileW; k += kLossBlock) {
+    const int i = k / kTileW, j = k - i * kTileW;
+    const int px = x0 + j, py = y0 + i;
+    if (px >= a.W || py >= a.H) continue;
+    float m1 = 0.f, m2 = 0.f, e11 = 0.f, e22 = 0.f, e12 = 0.f;
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+      const float g = kGauss[t];
+      m1 = fmaf(g, hs[0][i + t][j], m1);
+      m2 = fmaf(g, hs[1][i + t][j], m2);
+      e11 = fmaf(g, hs[2][i + t][j], e11);
+      e22 = fmaf(g, hs[3][i + t][j], e22);
+      e12 = fmaf(g, hs[4][i + t][j], e12);
+    }
+    const float A1 = 2.f * m1 * m2 + kC1, A2 = 2.f * (e12 - m1 * m2) + kC2;
+    const float B1 = m1 * m1 + m2 * m2 + kC1, B2 = (e11 - m1 * m1) + (e22 - m2 * m2) + kC2;
+    const float S = (A1 * A2) / (B1 * B2);
+    const size_t pix = (size_t)py * a.W + px;
+    P[pix] = 2.f * S * (m2 / A1 - m2 / A2 - m1 / B1 + m1 / B2);  // dS/dm1
+    P[HW + pix] = -S / B2;                                          // dS/de11
+    P[2 * HW + pix] = 2.f * S / A2;                                 // dS/de12
+    ssum += S;
+    l1sum += fabsf(sx[i + kRad][j + kRad] - sy[i + kRad][j + kRad]);
+  }
+  const int slot = (int)((blockIdx.y * gridDim.x + blockIdx.x) % kSumSlots);
+  ssum = block_sum(ssum, red);
+  l1sum = block_sum(l1sum, red);
+  if (threadIdx.x == 0) {
+    atomicAdd(&a.sums[0 * kSumSlots + slot], (double)ssum);
+    atomicAdd(&a.sums[1 * kSumSlots + slot], (double)l1sum);
+  }
+  if (c == 0) {  // depth terms once per pixel
+    float dsum = 0.f, nvalid = 0.f;
+    for (int k = threadIdx.x; k < kTileH * kTileW; k += kLossBlock) {
+      const int i = k / kTileW, j = k - i * kTileW;
+      const int px = x0 + j, py = y0 + i;
+      if (px >= a.W || py >= a.H) continue;
+      const size_t pix = (size_t)py * a.W + px;
+      const float tv = a.t[pix];
+      if (tv > 0.0f) {
+        dsum += fabsf(a.d[pix] - tv);
+        nvalid += 1.0f;
+      }
+    }
+    dsum = block_sum(dsum, red);
+    nvalid = block_sum(nvalid, red);
+    if (threadIdx.x == 0) {
+      atomicAdd(&a.sums[2 * kSumSlots + slot], (double)dsum);
+      atomicAdd(&a.sums[3 * kSumSlots + slot], (double)nvalid);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// kernel 2: gradient planes
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float sgnf(float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); }
+
+__global__ void __launch_bounds__(kLossBlock) ssim_grad_kernel(ViewArgs a, float w_ssim, float w_l1, float lam_d) {
+  __shared__ float sp[3][kHaloH][kHaloW];
+  __shared__ float hs[3][kHaloH][kTileW];
+  const int c = blockIdx.z;
+  const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
+  const size_t HW = (size_t)a.W * a.H;
+  const float* P = a.P + (size_t)c * 3 * HW;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) load_halo(P + q * HW, a.W, a.H, x0, y0, sp[q]);
+  __syncthreads();
+  for (int k = threadIdx.x; k < kHaloH * kTileW; k += kLossBlock) {
+    const int r = k / kTileW, j = k - r * kTileW;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+      const float g = kGauss[t];
+      s0 = fmaf(g, sp[0][r][j + t], s0);
+      s1 = fmaf(g, sp[1][r][j + t], s1);
+      s2 = fmaf(g, sp[2][r][j + t], s2);
+    }
+    hs[0][r][j] = s0; hs[1][r][j] = s1; hs[2][r][j] = s2;
+  }
+  __syncthreads();
+  // valid target-depth pixels of the view (from the first kernel's sums)
+  float nvalid = 0.f;
+  if (c == 0) {
+    double n = 0.0;
+    for (int s = 0; s < kSumSlots; ++s) n += a.sums[3 * kSumSlots + s];
+    nvalid = (float)n;
+  }
+  for (int k = threadIdx.x; k < kTileH * kTileW; k += kLossBlock) {
+    const int i = k / kTileW, j = k - i * kTileW;
+    const int px = x0 + j, py = y0 + i;
+    if (px >= a.W || py >= a.H) continue;
+    float q1 = 0.f, q2 = 0.f, q3 = 0.f;
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+      const float g = kGauss[t];
+      q1 = fmaf(g, hs[0][i + t][j], q1);
+      q2 = fmaf(g, hs[1][i + t][j], q2);
+      q3 = fmaf(g, hs[2][i + t][j], q3);
+    }
+    const size_t pix = (size_t)py * a.W + px;
+    const float xv = a.x[c * HW + pix], yv = a.y[c * HW + pix];
+    a.gx[c * HW + pix] = w_ssim * (q1 + 2.f * xv * q2 + yv * q3) + w_l1 * sgnf(xv - yv);
+    if (c == 0) {
+      const float tv = a.t[pix];
+      a.gd[pix] = (tv > 0.0f && nvalid > 0.f) ? lam_d * sgnf(a.d[pix] - tv) / nvalid : 0.0f;
+      if (a.ga) a.ga[pix] = 0.0f;
+    }
+  }
+}
+
+// Loss terms of one view from the block sums: L_c, L_SSIM, L_d, total.
+__global__ void loss_terms_kernel(const double* __restrict__ sums, int W, int H, float lam_ssim, float lam_d,
+                                  float* __restrict__ terms) {
+  if (threadIdx.x != 0) return;
+  double s[kSums] = {0, 0, 0, 0};
+  for (int q = 0; q < kSums; ++q)
+    for (int k = 0; k < kSumSlots; ++k) s[q] += sums[q * kSumSlots + k];
+  const double n = 3.0 * W * H;
+  const double l1 = s[1] / n, ssim = s[0] / n;
+  const double ld = s[3] > 0 ? s[2] / s[3] : 0.0;
+  const double l_ssim = (1.0 - lam_ssim) * l1 + lam_ssim * (1.0 - ssim);
+  terms[0] = (float)l1;
+  terms[1] = (float)l_ssim;
+  terms[2] = (float)ld;
+  terms[3] = (float)(l1 + l_ssim + lam_d * ld);
+}
+
+// Volume term of eq. 9: loss = lv sum_i prod(exp(l_i)); adds lv prod(exp(l_i))
+// to each of the three log-scale gradients of Gaussian i.
+__global__ void volume_kernel(const float* __restrict__ ls, int64_t n, float lam_vol, float* __restrict__ dls,
+                              double* __restrict__ acc) {
+  __shared__ float red[kLossBlock / 64];
+  const int64_t i = (int64_t)blockIdx.x * kLossBlock + threadIdx.x;
+  float v = 0.f;
+  if (i < n) {
+    v = lam_vol * expf(ls[3 * i] + ls[3 * i + 1] + ls[3 * i + 2]);
+    dls[3 * i] += v;
+    dls[3 * i + 1] += v;
+    dls[3 * i + 2] += v;
+  }
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) atomicAdd(&acc[blockIdx.x % kSumSlots], (double)v);
+}
+
+__global__ void volume_total_kernel(const double* __restrict__ acc, float* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int k = 0; k < kSumSlots; ++k) s += acc[k];
+  *out = (float)s;
+}
+
+__global__ void zero_f64_kernel(double* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+}  // namespace
+}  // namespace vpgs
+
+using namespace vpgs;
+
+int vpgs_mapping_loss(vpgs_ctx* ctx, int n_views, const vpgs_camera* cams, const vpgs_images* rendered,
+                      const vpgs_targets* targets, const vpgs_loss_opts* opts, float* terms, const vpgs_images* grad,
+                      void* stream) {
+  if (!ctx) return VPGS_EINVAL;
+  if (n_views < 0 || n_views > VPGS_MAX_VIEWS) return fail(ctx, VPGS_EINVAL, "n_views %d out of range", n_views);
+  if (n_views == 0) return VPGS_OK;
+  if (!cams || !rendered || !targets || !terms || !grad) return fail(ctx, VPGS_EINVAL, "NULL argument");
+  const float lam_ssim = opts ? opts->lambda_ssim : 0.2f;
+  const float lam_d = opts ? opts->lambda_depth : 1.0f;
+  if (!(lam_ssim >= 0.f && lam_ssim <= 1.f) || !(lam_d >= 0.f) || !std::isfinite(lam_d))
+    return fail(ctx, VPGS_EINVAL, "loss weights out of range");
+  size_t ws = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const int W = cams[v].width, H = cams[v].height;
+    if (W <= 0 || H <= 0 || W > VPGS_MAX_DIM || H > VPGS_MAX_DIM)
+      return fail(ctx, VPGS_EINVAL, "view %d: size %dx%d out of range", v, W, H);
+    if (!rendered[v].rgb || !rendered[v].depth || !targets[v].rgb || !targets[v].depth || !grad[v].rgb ||
+        !grad[v].depth)
+      return fail(ctx, VPGS_EINVAL, "view %d: NULL image plane", v);
+    ws = std::max(ws, (size_t)9 * W * H * sizeof(float));
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(ctx->device));
+  int rc;
+  const size_t sums_bytes = (size_t)n_views * kSums * kSumSlots * sizeof(double);
+  if ((rc = ensure(ctx, ctx->loss_ws, ws)) || (rc = ensure(ctx, ctx->loss_sums, sums_bytes))) return rc;
+  StageTimer timer(ctx, ST_LOSS, st);
+  const int nz = n_views * kSums * kSumSlots;
+  hipLaunchKernelGGL(zero_f64_kernel, dim3((nz + 255) / 256), dim3(256), 0, st,
+                     static_cast<double*>(ctx->loss_sums.p), nz);
+  HIP_TRY(hipGetLastError());
+  for (int v = 0; v < n_views; ++v) {
+    ViewArgs a;
+    a.W = cams[v].width;
+    a.H = cams[v].height;
+    a.x = rendered[v].rgb;
+    a.d = rendered[v].depth;
+    a.y = targets[v].rgb;
+    a.t = targets[v].depth;
+    a.gx = grad[v].rgb;
+    a.gd = grad[v].depth;
+    a.ga = grad[v].alpha;
+    a.P = static_cast<float*>(ctx->loss_ws.p);
+    a.sums = static_cast<double*>(ctx->loss_sums.p) + (size_t)v * kSums * kSumSlots;
+    const dim3 grid((a.W + kTileW - 1) / kTileW, (a.H + kTileH - 1) / kTileH, 3);
+    const double n = 3.0 * a.W * a.H;
+    const float w_ssim = (float)(-lam_ssim / n);
+    const float w_l1 = (float)((2.0 - lam_ssim) / n);  // L_c and the (1 - ls) L1 part of L_SSIM
+    hipLaunchKernelGGL(ssim_stats_kernel, grid, dim3(kLossBlock), 0, st, a);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(ssim_grad_kernel, grid, dim3(kLossBlock), 0, st, a, w_ssim, w_l1, lam_d);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(loss_terms_kernel, dim3(1), dim3(64), 0, st, a.sums, a.W, a.H, lam_ssim, lam_d, terms + 4 * v);
+    HIP_TRY(hipGetLastError());
+  }
+  return VPGS_OK;
+}
+
+int vpgs_volume_loss(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, float lambda_vol, float* loss,
+                     const vpgs_gauss_grads* grads, void* stream) {
+  if (!ctx) return VPGS_EINVAL;
+  if (n_sets < 0 || n_sets > VPGS_MAX_SETS) return fail(ctx, VPGS_EINVAL, "n_sets %d out of range", n_sets);
+  if (n_sets == 0) return VPGS_OK;
+  if (!sets || !loss || !grads) return fail(ctx, VPGS_EINVAL, "NULL argument");
+  if (!(lambda_vol >= 0.f) || !std::isfinite(lambda_vol)) return fail(ctx, VPGS_EINVAL, "lambda_vol out of range");
+  for (int s = 0; s < n_sets; ++s) {
+    if (sets[s].n < 0) return fail(ctx, VPGS_EINVAL, "set %d: negative size", s);
+    if (sets[s].n > 0 && (!sets[s].log_scales || !grads[s].log_scales))
+      return fail(ctx, VPGS_EINVAL, "set %d: NULL log-scales", s);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(ctx->device));
+  int rc;
+  if ((rc = ensure(ctx, ctx->loss_sums, (size_t)n_sets * kSumSlots * sizeof(double)))) return rc;
+  StageTimer timer(ctx, ST_VOLUME, st);
+  double* acc = static_cast<double*>(ctx->loss_sums.p);
+  const int nz = n_sets * kSumSlots;
+  hipLaunchKernelGGL(zero_f64_kernel, dim3((nz + 255) / 256), dim3(256), 0, st, acc, nz);
+  HIP_TRY(hipGetLastError());
+  for (int s = 0; s < n_sets; ++s) {
+    const int64_t n = sets[s].n;
+    if (n > 0) {
+      const int64_t blocks = (n + kLossBlock - 1) / kLossBlock;
+      if (blocks > 0x7fffffff) return fail(ctx, VPGS_EINVAL, "set %d too large", s);
+      hipLaunchKernelGGL(volume_kernel, dim3((unsigned)blocks), dim3(kLossBlock), 0, st, sets[s].log_scales, n,
+                         lambda_vol, grads[s].log_scales, acc + (size_t)s * kSumSlots);
+      HIP_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(volume_total_kernel, dim3(1), dim3(64), 0, st, acc + (size_t)s * kSumSlots, loss + s);
+    HIP_TRY(hipGetLastError());
+  }
+  return VPGS_OK;
+}

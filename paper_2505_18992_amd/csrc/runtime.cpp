@@ -20,7 +20,8 @@ namespace vpgs {
 
 const char* const kStageNames[VPGS_NUM_STAGES] = {
     "project", "scan", "emit", "sort", "ranges", "composite_forward", "composite_backward",
-    "project_backward", "pose_reduce", "fill", "decode_forward", "decode_backward", "depth_order"};
+    "project_backward", "pose_reduce", "fill", "decode_forward", "decode_backward", "depth_order",
+    "mapping_loss", "volume_loss"};
 
 int fail(vpgs_ctx* ctx, int code, const char* fmt, ...) {
   if (ctx) {
@@ -528,6 +529,8 @@ int vpgs_destroy(vpgs_ctx* ctx) {
   for (vpgs_saved* s : ctx->pool) destroy_saved(s);
   free_buf(ctx->dec_ws);
   free_buf(ctx->dec_partial);
+  free_buf(ctx->loss_ws);
+  free_buf(ctx->loss_sums);
   if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
   delete ctx;
   return VPGS_OK;

@@ -19,7 +19,7 @@ struct DevBuf {
 };
 
 enum Stage { ST_PROJECT, ST_SCAN, ST_EMIT, ST_SORT, ST_RANGES, ST_FWD, ST_BWD, ST_PROJ_BWD, ST_POSE, ST_FILL,
-             ST_DEC_FWD, ST_DEC_BWD, ST_DEPTH };
+             ST_DEC_FWD, ST_DEC_BWD, ST_DEPTH, ST_LOSS, ST_VOLUME };
 extern const char* const kStageNames[VPGS_NUM_STAGES];
 
 }  // namespace vpgs
@@ -48,6 +48,8 @@ struct vpgs_ctx {
   void* h_pinned = nullptr;  // small pinned buffer for counter readback
   // decode workspace
   vpgs::DevBuf dec_ws, dec_partial;
+  // mapping-loss workspace: SSIM partials of one view, block sums
+  vpgs::DevBuf loss_ws, loss_sums;
   // stage timing
   bool profiling = false;
   std::vector<hipEvent_t> ev_free;

@@ -21,7 +21,8 @@ from . import _lib
 from ._lib import check, load
 
 __all__ = ["Context", "get_context", "render", "render_backward", "Saved", "RenderFn", "render_views",
-           "camera_struct", "decode_forward", "decode_backward", "DecodeFn", "decode", "RenderWindow"]
+           "camera_struct", "decode_forward", "decode_backward", "DecodeFn", "decode", "RenderWindow",
+           "mapping_loss", "volume_loss"]
 
 
 class Context:
@@ -489,3 +490,71 @@ def decode(anchors, mlp, cam_center):
     (W1, b1, W2, b2) lists of 3 tensors each."""
     W1, b1, W2, b2 = mlp
     return DecodeFn.apply(cam_center, *anchors, *W1, *b1, *W2, *b2)
+
+
+# ---------------------------------------------------------------------------
+# mapping loss (eq. 7-9)
+# ---------------------------------------------------------------------------
+def mapping_loss(images: Sequence, targets: Sequence, cameras: Sequence, lambda_ssim: float = 0.2,
+                 lambda_depth: float = 1.0, ctx: Optional[Context] = None):
+    """Mapping loss of eq. 7-8 of every view and its gradient planes.
+
+    images: per view (rgb [3,H,W], depth [H,W], ...) as rendered; targets:
+    per view (rgb [3,H,W], depth [H,W]) with depth <= 0 = no target.  Returns
+    (terms [n_views, 4] = (L_c, L_SSIM, L_d, L) on the device, grads) with
+    grads[v] = (g_rgb, g_depth, g_alpha) -- the upstream planes of the render
+    backward for the summed loss (g_alpha is zero)."""
+    ctx = ctx or get_context()
+    nv = len(images)
+    if not (len(targets) == nv and len(cameras) == nv):
+        raise ValueError("images, targets and cameras must have one entry per view")
+    dev = images[0][0].device if nv else torch.device("cuda")
+    cams = (_lib.Camera * max(nv, 1))()
+    ims = (_lib.Images * max(nv, 1))()
+    tgs = (_lib.Targets * max(nv, 1))()
+    gbs = (_lib.Images * max(nv, 1))()
+    grads = []
+    for v in range(nv):
+        rgb, depth = images[v][0], images[v][1]
+        trgb, tdepth = targets[v][0], targets[v][1]
+        H, W = int(depth.shape[0]), int(depth.shape[1])
+        for t, shape, name in ((rgb, (3, H, W), "rgb"), (depth, (H, W), "depth"), (trgb, (3, H, W), "target rgb"),
+                               (tdepth, (H, W), "target depth")):
+            if tuple(t.shape) != shape or t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError(f"view {v}: {name} must be contiguous float32 {shape}")
+        cams[v] = camera_struct(cameras[v]) if not isinstance(cameras[v], _lib.Camera) else cameras[v]
+        if cams[v].width != W or cams[v].height != H:
+            raise ValueError(f"view {v}: camera size {cams[v].width}x{cams[v].height} differs from the image {W}x{H}")
+        ims[v].rgb, ims[v].depth, ims[v].alpha = rgb.data_ptr(), depth.data_ptr(), None
+        tgs[v].rgb, tgs[v].depth = trgb.data_ptr(), tdepth.data_ptr()
+        g = (torch.empty_like(rgb), torch.empty_like(depth), torch.empty_like(depth))
+        gbs[v].rgb, gbs[v].depth, gbs[v].alpha = (t.data_ptr() for t in g)
+        grads.append(g)
+    terms = torch.empty((max(nv, 1), 4), dtype=torch.float32, device=dev)
+    opts = _lib.LossOpts(float(lambda_ssim), float(lambda_depth), 0, 0)
+    check(load().vpgs_mapping_loss(ctx.handle, nv, cams, ims, tgs, ctypes.byref(opts), terms.data_ptr(), gbs,
+                                   _stream()), ctx.handle, "vpgs_mapping_loss")
+    return terms[:nv], grads
+
+
+def volume_loss(sets: Sequence, grads: Sequence, lambda_vol: float = 0.001, ctx: Optional[Context] = None):
+    """Volume term of eq. 9 per Gaussian set; adds its gradient into
+    grads[s][1] (the log-scale gradients).  Returns the per-set losses
+    (device tensor [n_sets])."""
+    ctx = ctx or get_context()
+    ns = len(sets)
+    if len(grads) != ns:
+        raise ValueError("one gradient tuple per set")
+    gs = (_lib.Gaussians * max(ns, 1))()
+    gb = (_lib.GaussBuffers * max(ns, 1))()
+    for s in range(ns):
+        gs[s] = _set_struct(sets[s])
+        dls = grads[s][1]
+        if tuple(dls.shape) != tuple(sets[s][1].shape) or dls.dtype != torch.float32 or not dls.is_contiguous():
+            raise ValueError(f"set {s}: log-scale gradient must match the log-scales")
+        gb[s].log_scales = dls.data_ptr()
+    dev = sets[0][0].device if ns else torch.device("cuda")
+    out = torch.empty((max(ns, 1),), dtype=torch.float32, device=dev)
+    check(load().vpgs_volume_loss(ctx.handle, ns, gs, float(lambda_vol), out.data_ptr(), gb, _stream()), ctx.handle,
+          "vpgs_volume_loss")
+    return out[:ns]
