@@ -336,7 +336,7 @@ typedef struct {
  * grad[v].depth (written in full; d|x|/dx is 0 at 0); grad[v].alpha, if
  * non-NULL, is zeroed.  These planes are the upstream gradients the render
  * backward takes.  opts NULL = (0.2, 1).  A workspace of 36 bytes per pixel of
- * the largest view is kept in the context.  Asynchronous on `stream`. */
+ * all views is kept in the context.  Asynchronous on `stream`. */
 int vpgs_mapping_loss(vpgs_ctx* ctx, int n_views, const vpgs_camera* cams, const vpgs_images* rendered,
                       const vpgs_targets* targets, const vpgs_loss_opts* opts, float* terms,
                       const vpgs_images* grad, void* stream);

@@ -18,7 +18,8 @@
 // stencil kernels per view: the first filters the five statistics and
 // writes S's partials (and block sums of the loss terms), the second
 // filters the partials and writes the gradient planes.  Both stage a
-// 32x16-pixel tile plus a 5-pixel halo in LDS and filter it separably.
+// 32x16-pixel tile plus a 5-pixel halo in LDS and filter it separably.  One
+// launch of each covers up to 16 views.
 #include <algorithm>
 #include <cmath>
 
@@ -41,6 +42,8 @@ __constant__ float kGauss[kTaps] = {1.028380124e-03f, 7.598758209e-03f, 3.600077
                                     2.130055428e-01f, 2.660117149e-01f, 2.130055428e-01f, 1.093606874e-01f,
                                     3.600077331e-02f, 7.598758209e-03f, 1.028380124e-03f};
 
+constexpr int kLossViews = 16;  // views per launch (their arguments travel by value)
+
 struct ViewArgs {
   int W, H;
   const float* x;   // rendered colour [3,H,W]
@@ -52,6 +55,13 @@ struct ViewArgs {
   float* ga;        // alpha gradient [H,W] (zeroed) or NULL
   float* P;         // partials workspace [3 channels][3][H,W]
   double* sums;     // [kSums][kSumSlots] of this view
+  int tiles_x, tiles_y;
+};
+
+// A launch covers up to kLossViews views: grid = (max tiles_x, max tiles_y,
+// 3 channels x views); workgroups past their view's tiles return.
+struct LossBatch {
+  ViewArgs v[kLossViews];
 };
 
 __device__ __forceinline__ float block_sum(float v, float* red) {
@@ -80,11 +90,19 @@ __device__ __forceinline__ void load_halo(const float* __restrict__ src, int W, 
 // ---------------------------------------------------------------------------
 // kernel 1: statistics, SSIM partials and the block sums
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kLossBlock) ssim_stats_kernel(ViewArgs a) {
+// With A1 = 2 m1 m2 + C1, A2 = 2 (e12 - m1 m2) + C2, B1 = m1^2 + m2^2 + C1,
+// B2 = (e11 - m1^2) + (e22 - m2^2) + C2 and S = A1 A2 / (B1 B2):
+//   dS/dm1  = 2 / (B1 B2) (m2 (A2 - A1) + A1 A2 m1 (1 / B2 - 1 / B1))
+//   dS/de11 = -A1 A2 / (B1 B2^2)
+//   dS/de12 = 2 A1 / (B1 B2)
+// (only B1 >= C1 and B2 >= C2 are divided by; A2 may vanish).
+__global__ void __launch_bounds__(kLossBlock) ssim_stats_kernel(LossBatch batch) {
   __shared__ float sx[kHaloH][kHaloW], sy[kHaloH][kHaloW];
   __shared__ float hs[5][kHaloH][kTileW];  // horizontal sums of x, y, x^2, y^2, xy
   __shared__ float red[kLossBlock / 64];
-  const int c = blockIdx.z;
+  const ViewArgs& a = batch.v[blockIdx.z / 3];
+  if ((int)blockIdx.x >= a.tiles_x || (int)blockIdx.y >= a.tiles_y) return;
+  const int c = blockIdx.z % 3;
   const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
   const size_t HW = (size_t)a.W * a.H;
   load_halo(a.x + c * HW, a.W, a.H, x0, y0, sx);
@@ -123,15 +141,17 @@ __global__ void __launch_bounds__(kLossBlock) ssim_stats_kernel(ViewArgs a) {
     }
     const float A1 = 2.f * m1 * m2 + kC1, A2 = 2.f * (e12 - m1 * m2) + kC2;
     const float B1 = m1 * m1 + m2 * m2 + kC1, B2 = (e11 - m1 * m1) + (e22 - m2 * m2) + kC2;
-    const float S = (A1 * A2) / (B1 * B2);
+    const float rB1 = 1.0f / B1, rB2 = 1.0f / B2;
+    const float rr = rB1 * rB2;
+    const float S = A1 * A2 * rr;
     const size_t pix = (size_t)py * a.W + px;
-    P[pix] = 2.f * S * (m2 / A1 - m2 / A2 - m1 / B1 + m1 / B2);  // dS/dm1
-    P[HW + pix] = -S / B2;                                          // dS/de11
-    P[2 * HW + pix] = 2.f * S / A2;                                 // dS/de12
+    P[pix] = 2.f * rr * (m2 * (A2 - A1) + A1 * A2 * m1 * (rB2 - rB1));  // dS/dm1
+    P[HW + pix] = -S * rB2;                                               // dS/de11
+    P[2 * HW + pix] = 2.f * A1 * rr;                                      // dS/de12
     ssum += S;
     l1sum += fabsf(sx[i + kRad][j + kRad] - sy[i + kRad][j + kRad]);
   }
-  const int slot = (int)((blockIdx.y * gridDim.x + blockIdx.x) % kSumSlots);
+  const int slot = (int)((blockIdx.y * a.tiles_x + blockIdx.x) % kSumSlots);
   ssum = block_sum(ssum, red);
   l1sum = block_sum(l1sum, red);
   if (threadIdx.x == 0) {
@@ -165,15 +185,26 @@ __global__ void __launch_bounds__(kLossBlock) ssim_stats_kernel(ViewArgs a) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float sgnf(float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); }
 
-__global__ void __launch_bounds__(kLossBlock) ssim_grad_kernel(ViewArgs a, float w_ssim, float w_l1, float lam_d) {
+__global__ void __launch_bounds__(kLossBlock) ssim_grad_kernel(LossBatch batch, float lam_ssim, float lam_d) {
   __shared__ float sp[3][kHaloH][kHaloW];
   __shared__ float hs[3][kHaloH][kTileW];
-  const int c = blockIdx.z;
+  __shared__ float s_nvalid;
+  const ViewArgs& a = batch.v[blockIdx.z / 3];
+  if ((int)blockIdx.x >= a.tiles_x || (int)blockIdx.y >= a.tiles_y) return;
+  const int c = blockIdx.z % 3;
+  const float n = 3.0f * (float)a.W * (float)a.H;
+  const float w_ssim = -lam_ssim / n;
+  const float w_l1 = (2.0f - lam_ssim) / n;  // L_c and the (1 - lambda_ssim) L1 part of L_SSIM
   const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
   const size_t HW = (size_t)a.W * a.H;
   const float* P = a.P + (size_t)c * 3 * HW;
 #pragma unroll
   for (int q = 0; q < 3; ++q) load_halo(P + q * HW, a.W, a.H, x0, y0, sp[q]);
+  if (c == 0 && threadIdx.x == 0) {  // valid target-depth pixels of the view (first kernel's sums)
+    double nv = 0.0;
+    for (int k = 0; k < kSumSlots; ++k) nv += a.sums[3 * kSumSlots + k];
+    s_nvalid = (float)nv;
+  }
   __syncthreads();
   for (int k = threadIdx.x; k < kHaloH * kTileW; k += kLossBlock) {
     const int r = k / kTileW, j = k - r * kTileW;
@@ -188,13 +219,7 @@ __global__ void __launch_bounds__(kLossBlock) ssim_grad_kernel(ViewArgs a, float
     hs[0][r][j] = s0; hs[1][r][j] = s1; hs[2][r][j] = s2;
   }
   __syncthreads();
-  // valid target-depth pixels of the view (from the first kernel's sums)
-  float nvalid = 0.f;
-  if (c == 0) {
-    double n = 0.0;
-    for (int s = 0; s < kSumSlots; ++s) n += a.sums[3 * kSumSlots + s];
-    nvalid = (float)n;
-  }
+  const float nvalid = c == 0 ? s_nvalid : 0.f;
   for (int k = threadIdx.x; k < kTileH * kTileW; k += kLossBlock) {
     const int i = k / kTileW, j = k - i * kTileW;
     const int px = x0 + j, py = y0 + i;
@@ -219,8 +244,11 @@ __global__ void __launch_bounds__(kLossBlock) ssim_grad_kernel(ViewArgs a, float
 }
 
 // Loss terms of one view from the block sums: L_c, L_SSIM, L_d, total.
-__global__ void loss_terms_kernel(const double* __restrict__ sums, int W, int H, float lam_ssim, float lam_d,
-                                  float* __restrict__ terms) {
+__global__ void loss_terms_kernel(LossBatch batch, float lam_ssim, float lam_d, float* __restrict__ terms) {
+  const ViewArgs& a = batch.v[blockIdx.x];
+  const double* sums = a.sums;
+  const int W = a.W, H = a.H;
+  terms += 4 * blockIdx.x;
   if (threadIdx.x != 0) return;
   double s[kSums] = {0, 0, 0, 0};
   for (int q = 0; q < kSums; ++q)
@@ -288,7 +316,7 @@ int vpgs_mapping_loss(vpgs_ctx* ctx, int n_views, const vpgs_camera* cams, const
     if (!rendered[v].rgb || !rendered[v].depth || !targets[v].rgb || !targets[v].depth || !grad[v].rgb ||
         !grad[v].depth)
       return fail(ctx, VPGS_EINVAL, "view %d: NULL image plane", v);
-    ws = std::max(ws, (size_t)9 * W * H * sizeof(float));
+    ws += (size_t)9 * W * H * sizeof(float);
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(hipSetDevice(ctx->device));
@@ -300,28 +328,37 @@ int vpgs_mapping_loss(vpgs_ctx* ctx, int n_views, const vpgs_camera* cams, const
   hipLaunchKernelGGL(zero_f64_kernel, dim3((nz + 255) / 256), dim3(256), 0, st,
                      static_cast<double*>(ctx->loss_sums.p), nz);
   HIP_TRY(hipGetLastError());
-  for (int v = 0; v < n_views; ++v) {
-    ViewArgs a;
-    a.W = cams[v].width;
-    a.H = cams[v].height;
-    a.x = rendered[v].rgb;
-    a.d = rendered[v].depth;
-    a.y = targets[v].rgb;
-    a.t = targets[v].depth;
-    a.gx = grad[v].rgb;
-    a.gd = grad[v].depth;
-    a.ga = grad[v].alpha;
-    a.P = static_cast<float*>(ctx->loss_ws.p);
-    a.sums = static_cast<double*>(ctx->loss_sums.p) + (size_t)v * kSums * kSumSlots;
-    const dim3 grid((a.W + kTileW - 1) / kTileW, (a.H + kTileH - 1) / kTileH, 3);
-    const double n = 3.0 * a.W * a.H;
-    const float w_ssim = (float)(-lam_ssim / n);
-    const float w_l1 = (float)((2.0 - lam_ssim) / n);  // L_c and the (1 - ls) L1 part of L_SSIM
-    hipLaunchKernelGGL(ssim_stats_kernel, grid, dim3(kLossBlock), 0, st, a);
+  size_t off = 0;  // each view's partials workspace
+  for (int v0 = 0; v0 < n_views; v0 += kLossViews) {
+    const int nb = std::min(kLossViews, n_views - v0);
+    LossBatch batch{};
+    int gx = 1, gy = 1;
+    for (int b = 0; b < nb; ++b) {
+      const int v = v0 + b;
+      ViewArgs& a = batch.v[b];
+      a.W = cams[v].width;
+      a.H = cams[v].height;
+      a.x = rendered[v].rgb;
+      a.d = rendered[v].depth;
+      a.y = targets[v].rgb;
+      a.t = targets[v].depth;
+      a.gx = grad[v].rgb;
+      a.gd = grad[v].depth;
+      a.ga = grad[v].alpha;
+      a.P = static_cast<float*>(ctx->loss_ws.p) + off;
+      off += (size_t)9 * a.W * a.H;
+      a.sums = static_cast<double*>(ctx->loss_sums.p) + (size_t)v * kSums * kSumSlots;
+      a.tiles_x = (a.W + kTileW - 1) / kTileW;
+      a.tiles_y = (a.H + kTileH - 1) / kTileH;
+      gx = std::max(gx, a.tiles_x);
+      gy = std::max(gy, a.tiles_y);
+    }
+    const dim3 grid(gx, gy, 3 * nb);
+    hipLaunchKernelGGL(ssim_stats_kernel, grid, dim3(kLossBlock), 0, st, batch);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(ssim_grad_kernel, grid, dim3(kLossBlock), 0, st, a, w_ssim, w_l1, lam_d);
+    hipLaunchKernelGGL(ssim_grad_kernel, grid, dim3(kLossBlock), 0, st, batch, lam_ssim, lam_d);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(loss_terms_kernel, dim3(1), dim3(64), 0, st, a.sums, a.W, a.H, lam_ssim, lam_d, terms + 4 * v);
+    hipLaunchKernelGGL(loss_terms_kernel, dim3(nb), dim3(64), 0, st, batch, lam_ssim, lam_d, terms + 4 * v0);
     HIP_TRY(hipGetLastError());
   }
   return VPGS_OK;
