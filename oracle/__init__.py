@@ -8,6 +8,10 @@ and shares no code with it.
   FP64 C++ reference in ``oracle.cpp`` (see its header for the definition).
 * ``decode``: the anchor -> neural-Gaussian decoder of Section III-A
   (eq. 1-5) in plain PyTorch CPU float64 with autograd (``decode.py``).
+* ``loss``: the mapping loss of eq. 7-9 (``loss.py``).
+* ``densify``: the submap-expansion statistics of Section III-A -- screen-space
+  gradient and opacity accumulators, anchor growth and pruning, expansion
+  candidates and samples (``densify.py``).
 """
 from __future__ import annotations
 
@@ -42,7 +46,8 @@ def lib():
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     _D, _D, _D, _D, _I32, _I32, _U8]
         L.oracle_grad.argtypes = [c_int, c_int, _D, _D, i64, _D, _D, _D, _D, _D, _D, _D, _D, _U8,
-                                  _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D]
+                                  _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D,
+                                  _D, _D]
         L.oracle_binning.argtypes = [i64, _U8, _F, _F, _F, _F, _U32, c_int, c_int, c_int, c_int,
                                      ctypes.c_uint32, ctypes.c_uint32, i64, _U64, _U32, _U32]
         L.oracle_binning.restype = i64
@@ -117,7 +122,8 @@ def grad(g, cam, g_rgb, g_depth, g_alpha, skip: Optional[np.ndarray] = None, qua
     evaluation of the same forward moves the gradient (rounding of the
     projected centres, propagated through the transmittance).  With
     quantities=True grads also holds "quantity": [n, 10] gradients with
-    respect to (u, v, Qa, Qb, Qc, opacity, r, g, b, z) of every Gaussian."""
+    respect to (u, v, Qa, Qb, Qc, opacity, r, g, b, z) of every Gaussian, and
+    scales the matching "quantity" and "quantity_fp32" arrays."""
     W, H = cam.width, cam.height
     n = g.n
     intr, w2c = _cam_arrays(cam)
@@ -128,17 +134,22 @@ def grad(g, cam, g_rgb, g_depth, g_alpha, skip: Optional[np.ndarray] = None, qua
     scl = [np.zeros_like(a) for a in outs]
     bnd = [np.zeros_like(a) for a in outs]
     qg = np.zeros((n, 10)) if quantities else None
+    qs = np.zeros((n, 10)) if quantities else None
+    qb = np.zeros((n, 10)) if quantities else None
     lib().oracle_grad(W, H, _p(intr, _D), _p(w2c, _D), n, _p(m, _D), _p(l, _D), _p(q, _D), _p(o, _D),
                       _p(c, _D), _p(gr, _D), _p(gd, _D), _p(ga, _D),
                       None if sk is None else _p(sk, _U8),
                       *[_p(a, _D) for a in outs], *[_p(a, _D) for a in scl],
-                      None if qg is None else _p(qg, _D), *[_p(a, _D) for a in bnd])
+                      None if qg is None else _p(qg, _D), *[_p(a, _D) for a in bnd],
+                      None if qs is None else _p(qs, _D), None if qb is None else _p(qb, _D))
     keys = ["means", "log_scales", "quats", "opacities", "colors", "pose"]
     G = dict(zip(keys, outs))
-    if quantities:
-        G["quantity"] = qg
     S = dict(zip(keys, scl))
     S.update({k + "_fp32": b for k, b in zip(keys, bnd)})
+    if quantities:
+        G["quantity"] = qg
+        S["quantity"] = qs
+        S["quantity_fp32"] = qb
     return G, S
 
 

@@ -497,7 +497,8 @@ int oracle_grad(int W, int H, const double* intr, const double* w2c, int64_t n,
                 const uint8_t* skip, double* d_means, double* d_ls, double* d_quats, double* d_opac,
                 double* d_cols, double* d_pose, double* s_means, double* s_ls, double* s_quats,
                 double* s_opac, double* s_cols, double* s_pose, double* q_grad, double* b_means,
-                double* b_ls, double* b_quats, double* b_opac, double* b_cols, double* b_pose) {
+                double* b_ls, double* b_quats, double* b_opac, double* b_cols, double* b_pose,
+                double* q_scale, double* q_bound) {
   const Cam cam = make_cam(W, H, intr, w2c);
   const Inputs in{n, means, ls, quats, opac, cols};
   std::vector<Prim> pr = project_all(cam, in, 1);
@@ -568,6 +569,8 @@ int oracle_grad(int W, int H, const double* intr, const double* w2c, int64_t n,
   }
   if (q_grad)  // d L / d(u, v, Qa, Qb, Qc, o, r, g, b, z) of every Gaussian
     for (size_t i = 0; i < G.size(); ++i) q_grad[i] = G[i];
+  if (q_scale)  // and their error scales and float32 bounds
+    for (size_t i = 0; i < G.size(); ++i) { q_scale[i] = Gabs[i]; q_bound[i] = Gfp[i]; }
   // chain through the projection: 14 parameter duals + 6 pose duals
   typedef Dual<20> D20;
   double pose[6] = {0, 0, 0, 0, 0, 0}, spose[6] = {0, 0, 0, 0, 0, 0}, bpose[6] = {0, 0, 0, 0, 0, 0};
