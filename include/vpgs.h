@@ -250,12 +250,13 @@ int vpgs_window_destroy(vpgs_window* win);
  * events on its stream around each stage (projection, scan, emission, sort,
  * ranges, forward compositing, backward compositing, projection backward,
  * pose reduction, fills, decode forward, decode backward, depth ordering of
- * the visible records, mapping loss, volume loss).  vpgs_profile_read
+ * the visible records, mapping loss, volume loss, anchor statistics,
+ * expansion sampling).  vpgs_profile_read
  * synchronises on the recorded events and returns, for stage index `stage`
  * (0 <= stage < VPGS_NUM_STAGES), its name, the number of recorded launches
  * and their summed duration in milliseconds since the last enable.  Disabled
  * by default; enabling resets the totals. */
-#define VPGS_NUM_STAGES 15
+#define VPGS_NUM_STAGES 17
 int vpgs_profile_enable(vpgs_ctx* ctx, int on);
 int vpgs_profile_read(vpgs_ctx* ctx, int stage, const char** name, int64_t* calls, double* total_ms);
 
@@ -348,6 +349,86 @@ int vpgs_mapping_loss(vpgs_ctx* ctx, int n_views, const vpgs_camera* cams, const
  * writes those gradients).  The paper uses lambda_vol = 0.001. */
 int vpgs_volume_loss(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, float lambda_vol, float* loss,
                      const vpgs_gauss_grads* grads, void* stream);
+
+/* ---- submap expansion statistics (Section III-A) ------------------------- */
+
+/* Anchors grow where the averaged gradient of the neural Gaussians of a voxel
+ * is large, and are pruned when the accumulated opacity of their neural
+ * Gaussians is small; new anchors are sampled where the map does not yet
+ * explain the frame (low accumulated alpha or a large depth discrepancy).
+ *
+ * Per-Gaussian accumulators of one set: [n,4] floats, 16-byte aligned, ADDED
+ * to by every backward that is given them (zero them to start an interval):
+ *   [0] sum of |dL/d(u, v)|, the norm of the gradient of the loss with
+ *       respect to the Gaussian's projected centre, over the views that render
+ *       it (those where it overlaps a tile: the forward's visibility);
+ *   [1] the number of those views;
+ *   [2] sum of max(opacity, 0) over the views whose frustum holds its centre:
+ *       FP32 camera depth z > near, 0 <= u < W and 0 <= v < H, the centre as
+ *       the projection computes it, whether or not the Gaussian is rendered;
+ *   [3] the number of those views.
+ * Counts are exact (integers held in floats, below 2^24).  grad_space 0
+ * measures the gradient in pixels; 1 in normalised device coordinates
+ * (x_ndc = 2 u / W - 1): the norm of (W/2 dL/du, H/2 dL/dv). */
+typedef struct {
+  float* const* accum; /* host array [n_sets]: device [n,4] buffer of set s, or NULL for none */
+  int32_t grad_space;  /* 0 = pixels, 1 = normalised device coordinates */
+  int32_t reserved;
+} vpgs_densify_accum;
+
+/* vpgs_render_backward, plus the accumulation above in the same pass (the
+ * projection backward reads each Gaussian's accumulators once and writes them
+ * once).  acc may be NULL (then it is vpgs_render_backward). */
+int vpgs_render_backward_accum(vpgs_ctx* ctx, const vpgs_saved* saved, const vpgs_image_grads* grad_out,
+                               const vpgs_gauss_grads* grads, float* d_pose, const vpgs_densify_accum* acc,
+                               void* stream);
+
+/* Binds accumulators to a window (host array copied; the buffers must stay
+ * allocated); every later backward run of the window adds to them.  NULL
+ * unbinds.  Takes effect at the next run (no re-capture). */
+int vpgs_window_set_accum(vpgs_window* win, const vpgs_densify_accum* acc);
+
+/* Anchor statistics from the accumulators of m*k decoded Gaussians
+ * (anchor-major, Gaussian a*k + j, as vpgs_decode_forward writes them).  With
+ * S_c the FP32 sum over j = 0..k-1, in that order, of accum[4 (a k + j) + c]:
+ *   stats[4a + 0] = S_0 / S_1, or 0 when S_1 = 0: the averaged gradient
+ *   stats[4a + 1] = S_1, stats[4a + 2] = S_2 (accumulated opacity), stats[4a + 3] = S_3
+ *   grow[a]  = 1 if stats[4a + 0] > tau_g, else 0
+ *   prune[a] = 1 if S_3 > 0 and S_2 < tau_o * S_3 (FP32 product), else 0
+ * accum and stats are device [m*k,4] / [m,4] floats, 16-byte aligned; grow and
+ * prune (device bytes [m]) may be NULL.  1 <= k <= 64. */
+int vpgs_anchor_stats(vpgs_ctx* ctx, int64_t m, int32_t k, const float* accum, float tau_g, float tau_o,
+                      float* stats, uint8_t* grow, uint8_t* prune, void* stream);
+
+typedef struct {
+  float alpha_threshold; /* candidate where the rendered alpha is below this ... */
+  float depth_threshold; /* ... or where |D - T| is above this */
+  int32_t n_samples;     /* samples drawn per view (>= 0) */
+  int32_t reserved;
+} vpgs_expand_opts;
+
+/* Outputs of one view (device).  mask may be NULL; the sample arrays are
+ * needed when n_samples > 0. */
+typedef struct {
+  uint8_t* mask;  /* [H,W]: 1 at candidate pixels, else 0 */
+  int32_t* pixel; /* [n_samples]: sampled pixel y*W + x, or -1 if the view has no candidate */
+  float* points;  /* [n_samples,3]: world points (0 if none) */
+  float* colors;  /* [n_samples,3]: target colour at the pixel (0 if none) */
+} vpgs_expand_out;
+
+/* Expansion sampling of n_views frames.  A pixel of view v is a candidate iff
+ * its target depth T > 0 and (rendered alpha A < alpha_threshold or
+ * |D - T| > depth_threshold), in FP32 (rendered[v].alpha and .depth, and
+ * targets[v].depth and .rgb are read).  counts[v] (device int32) receives the
+ * number c of candidates.  Sample i of view v takes the candidate of rank
+ * r = min((int)(u c), c - 1) in raster order, u = uniforms[v n_samples + i]
+ * in [0, 1) (device floats, FP32 product), and back-projects its pixel centre
+ * with the target depth: X = R^T (T ((x + 1/2 - cx)/fx, (y + 1/2 - cy)/fy, 1)
+ * - t), with [R | t] = cams[v].world_to_cam.  The workspace holds one byte
+ * per pixel when a mask is NULL, and 8 bytes per 1024 pixels. */
+int vpgs_expansion_sample(vpgs_ctx* ctx, int n_views, const vpgs_camera* cams, const vpgs_images* rendered,
+                          const vpgs_targets* targets, const vpgs_expand_opts* opts, const float* uniforms,
+                          int32_t* counts, const vpgs_expand_out* out, void* stream);
 
 #ifdef __cplusplus
 }

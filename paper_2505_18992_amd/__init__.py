@@ -6,8 +6,8 @@ The computation runs in hand-written HIP kernels behind the C ABI of
 into that ABI.  Importing it does not load the library; the first call does,
 and fails loudly if the library is not built.
 """
-from .render import (Context, DecodeFn, RenderFn, Saved, camera_struct, decode, decode_backward,  # noqa: F401
-                     decode_forward, get_context, mapping_loss, render, render_backward, render_views,
-                     RenderWindow, volume_loss)
+from .render import (Context, DecodeFn, RenderFn, Saved, anchor_stats, camera_struct, decode,  # noqa: F401
+                     decode_backward, decode_forward, expansion_sample, get_context, mapping_loss, render,
+                     render_backward, render_views, RenderWindow, volume_loss)
 
 __version__ = "0.1.0"

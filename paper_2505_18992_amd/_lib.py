@@ -22,7 +22,7 @@ VPGS_ECAPACITY = -4
 VPGS_EUNSUPPORTED = -5
 MAX_VIEWS = 64
 MAX_SETS = 64
-NUM_STAGES = 15
+NUM_STAGES = 17
 WINDOW_FORWARD, WINDOW_BACKWARD = 1, 2
 
 BUF_PROJ, BUF_EXTENT, BUF_COUNT, BUF_KEYS, BUF_VALUES, BUF_RANGES, BUF_TFINAL, BUF_NCONTRIB = range(1, 9)
@@ -93,6 +93,19 @@ class LossOpts(ctypes.Structure):
                 ("reserved1", ctypes.c_int32)]
 
 
+class DensifyAccum(ctypes.Structure):
+    _fields_ = [("accum", ctypes.POINTER(c_void_p)), ("grad_space", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class ExpandOpts(ctypes.Structure):
+    _fields_ = [("alpha_threshold", ctypes.c_float), ("depth_threshold", ctypes.c_float),
+                ("n_samples", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class ExpandOut(ctypes.Structure):
+    _fields_ = [("mask", c_void_p), ("pixel", c_void_p), ("points", c_void_p), ("colors", c_void_p)]
+
+
 # every entry point of include/vpgs.h, with its ctypes signature
 SIGNATURES = {
     "vpgs_create": (ctypes.c_int, [ctypes.POINTER(c_void_p), ctypes.c_int]),
@@ -133,6 +146,15 @@ SIGNATURES = {
                                          ctypes.POINTER(Images), c_void_p]),
     "vpgs_volume_loss": (ctypes.c_int, [c_void_p, ctypes.c_int, ctypes.POINTER(Gaussians), ctypes.c_float,
                                         c_void_p, ctypes.POINTER(GaussBuffers), c_void_p]),
+    "vpgs_render_backward_accum": (ctypes.c_int, [c_void_p, c_void_p, ctypes.POINTER(ImageGrads),
+                                                  ctypes.POINTER(GaussBuffers), c_void_p,
+                                                  ctypes.POINTER(DensifyAccum), c_void_p]),
+    "vpgs_window_set_accum": (ctypes.c_int, [c_void_p, ctypes.POINTER(DensifyAccum)]),
+    "vpgs_anchor_stats": (ctypes.c_int, [c_void_p, ctypes.c_int64, ctypes.c_int32, c_void_p, ctypes.c_float,
+                                         ctypes.c_float, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "vpgs_expansion_sample": (ctypes.c_int, [c_void_p, ctypes.c_int, ctypes.POINTER(Camera), ctypes.POINTER(Images),
+                                             ctypes.POINTER(Targets), ctypes.POINTER(ExpandOpts), c_void_p, c_void_p,
+                                             ctypes.POINTER(ExpandOut), c_void_p]),
 }
 
 _LIB = None

@@ -55,6 +55,7 @@ struct SetDesc {
   float* d_quats;
   float* d_opacities;
   float* d_colors;
+  float* accum;         // [n,4] expansion accumulators added to by the backward, or NULL
   int64_t n;
   uint32_t block_base;  // first thread block of the set in per-Gaussian launches
   int32_t view_first;   // its views are set_views[view_first .. view_first + view_count)
@@ -68,6 +69,8 @@ struct CallTables {
   int32_t set_views[VPGS_MAX_VIEWS];
   int32_t n_views, n_sets;
   uint32_t n_records, n_tiles;
+  int32_t accum_space;  // gradient of the accumulators: 0 pixels, 1 normalised device coordinates
+  int32_t pad;
 };
 
 // Device counters of one forward.

@@ -203,6 +203,11 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
 
   float dmu[3] = {0, 0, 0}, dSg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   float dop = 0.f, dcol[3] = {0, 0, 0};
+  // expansion accumulators: screen-space gradient norm and rendered views,
+  // opacity and views whose frustum holds the centre
+  const bool track = S.accum != nullptr;
+  const float o_acc = track ? fmaxf(S.opacities[ii], 0.0f) : 0.0f;
+  float a_grad = 0.f, a_ren = 0.f, a_op = 0.f, a_seen = 0.f;
 
   for (int vi = 0; vi < S.view_count; ++vi) {
     const int v = tab->set_views[S.view_first + vi];
@@ -240,6 +245,13 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
       // sigma = (Qa dx^2 + 2 Qb dx dy + Qc dy^2) / 2
       const float gu = -(Qa * m0 + Qb * m1), gv = -(Qb * m0 + Qc * m1);
       const float gQa = -0.5f * m2, gQb = -m3, gQc = -0.5f * m4;
+      if (track) {
+        const float su = tab->accum_space ? 0.5f * (float)V.W : 1.0f;
+        const float sv = tab->accum_space ? 0.5f * (float)V.H : 1.0f;
+        const float nu = gu * su, nv = gv * sv;
+        a_grad += sqrtf(nu * nu + nv * nv);
+        a_ren += 1.0f;
+      }
 
       // conic = Sigma2D^-1:  dL/dSigma2D = -Q G Q, G the symmetric conic gradient
       const float dA = -(Qa * Qa * gQa + Qa * Qb * gQb + Qb * Qb * gQc);
@@ -298,6 +310,13 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
       pose[4] = p.z * dx - p.x * dz + 2.f * (A[6] - A[2]);
       pose[5] = p.x * dy - p.y * dx + 2.f * (A[1] - A[3]);
     }
+    if (track && live) {
+      const SpecPoint p = spec_point(V, mx, my, mz);
+      if (p.z > V.near_z && p.u >= 0.0f && p.u < (float)V.W && p.v >= 0.0f && p.v < (float)V.H) {
+        a_op += o_acc;
+        a_seen += 1.0f;
+      }
+    }
     if (pose_partial != nullptr) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
@@ -343,6 +362,12 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
       make_float4((dqw - w * dot) * in, (dqx - x * dot) * in, (dqy - y * dot) * in, (dqz - z * dot) * in);
   S.d_opacities[i] = dop;
   S.d_colors[3 * i] = dcol[0]; S.d_colors[3 * i + 1] = dcol[1]; S.d_colors[3 * i + 2] = dcol[2];
+  if (track) {
+    float4* a = reinterpret_cast<float4*>(S.accum) + i;
+    float4 cur = *a;
+    cur.x += a_grad; cur.y += a_ren; cur.z += a_op; cur.w += a_seen;
+    *a = cur;
+  }
 }
 
 __global__ void pose_reduce_kernel(const CallTables* __restrict__ tab, const float* __restrict__ partial,

@@ -21,7 +21,7 @@ namespace vpgs {
 const char* const kStageNames[VPGS_NUM_STAGES] = {
     "project", "scan", "emit", "sort", "ranges", "composite_forward", "composite_backward",
     "project_backward", "pose_reduce", "fill", "decode_forward", "decode_backward", "depth_order",
-    "mapping_loss", "volume_loss"};
+    "mapping_loss", "volume_loss", "anchor_stats", "expansion"};
 
 int fail(vpgs_ctx* ctx, int code, const char* fmt, ...) {
   if (ctx) {
@@ -330,7 +330,9 @@ int bind_backward(vpgs_ctx* ctx, CallTables& T, const vpgs_image_grads* grad_out
       return fail(ctx, VPGS_EINVAL, "set %d: NULL gradient pointer", s);
     if (T.sets[s].n > 0 && !aligned16(g.quats)) return fail(ctx, VPGS_EINVAL, "set %d: d_quats must be 16-byte aligned", s);
   }
+  T.accum_space = 0;
   for (int s = 0; s < T.n_sets; ++s) {
+    T.sets[s].accum = nullptr;
     T.sets[s].d_means = grads[s].means;
     T.sets[s].d_log_scales = grads[s].log_scales;
     T.sets[s].d_quats = grads[s].quats;
@@ -342,6 +344,18 @@ int bind_backward(vpgs_ctx* ctx, CallTables& T, const vpgs_image_grads* grad_out
     T.views[v].g_depth = grad_out[v].depth;
     T.views[v].g_alpha = grad_out[v].alpha;
   }
+  return VPGS_OK;
+}
+
+int bind_accum(vpgs_ctx* ctx, CallTables& T, const vpgs_densify_accum* acc) {
+  if (!acc) return VPGS_OK;
+  if (acc->grad_space != 0 && acc->grad_space != 1) return fail(ctx, VPGS_EINVAL, "grad_space must be 0 or 1");
+  if (!acc->accum) return fail(ctx, VPGS_EINVAL, "NULL accumulator array");
+  for (int s = 0; s < T.n_sets; ++s)
+    if (acc->accum[s] && T.sets[s].n > 0 && !aligned16(acc->accum[s]))
+      return fail(ctx, VPGS_EINVAL, "set %d: accumulators must be 16-byte aligned", s);
+  T.accum_space = acc->grad_space;
+  for (int s = 0; s < T.n_sets; ++s) T.sets[s].accum = T.sets[s].n > 0 ? acc->accum[s] : nullptr;
   return VPGS_OK;
 }
 
@@ -531,6 +545,8 @@ int vpgs_destroy(vpgs_ctx* ctx) {
   free_buf(ctx->dec_partial);
   free_buf(ctx->loss_ws);
   free_buf(ctx->loss_sums);
+  free_buf(ctx->expand_mask);
+  free_buf(ctx->expand_blocks);
   if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
   delete ctx;
   return VPGS_OK;
@@ -583,6 +599,12 @@ int vpgs_render_forward(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, i
 
 int vpgs_render_backward(vpgs_ctx* ctx, const vpgs_saved* saved_c, const vpgs_image_grads* grad_out,
                          const vpgs_gauss_grads* grads, float* d_pose, void* stream) {
+  return vpgs_render_backward_accum(ctx, saved_c, grad_out, grads, d_pose, nullptr, stream);
+}
+
+int vpgs_render_backward_accum(vpgs_ctx* ctx, const vpgs_saved* saved_c, const vpgs_image_grads* grad_out,
+                               const vpgs_gauss_grads* grads, float* d_pose, const vpgs_densify_accum* acc,
+                               void* stream) {
   if (!ctx) return VPGS_EINVAL;
   vpgs_saved* sv = const_cast<vpgs_saved*>(saved_c);
   if (!sv || !sv->in_use) return fail(ctx, VPGS_EINVAL, "invalid saved-state handle");
@@ -593,6 +615,7 @@ int vpgs_render_backward(vpgs_ctx* ctx, const vpgs_saved* saved_c, const vpgs_im
   HIP_TRY(hipSetDevice(ctx->device));
   HIP_TRY(hipEventSynchronize(sv->tab_uploaded));
   int rc = bind_backward(ctx, *sv->h_tab, grad_out, grads);
+  if (!rc) rc = bind_accum(ctx, *sv->h_tab, acc);
   if (rc) return rc;
   if ((rc = ensure_backward(ctx, sv, st)) || (rc = upload_tables(ctx, sv, st)) ||
       (rc = enqueue_backward(ctx, sv, d_pose, st)))

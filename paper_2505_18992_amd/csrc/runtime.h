@@ -19,7 +19,7 @@ struct DevBuf {
 };
 
 enum Stage { ST_PROJECT, ST_SCAN, ST_EMIT, ST_SORT, ST_RANGES, ST_FWD, ST_BWD, ST_PROJ_BWD, ST_POSE, ST_FILL,
-             ST_DEC_FWD, ST_DEC_BWD, ST_DEPTH, ST_LOSS, ST_VOLUME };
+             ST_DEC_FWD, ST_DEC_BWD, ST_DEPTH, ST_LOSS, ST_VOLUME, ST_ANCHOR, ST_EXPAND };
 extern const char* const kStageNames[VPGS_NUM_STAGES];
 
 }  // namespace vpgs
@@ -50,6 +50,8 @@ struct vpgs_ctx {
   vpgs::DevBuf dec_ws, dec_partial;
   // mapping-loss workspace: SSIM partials of one view, block sums
   vpgs::DevBuf loss_ws, loss_sums;
+  // expansion sampling: candidate masks not given by the caller, block counts and offsets
+  vpgs::DevBuf expand_mask, expand_blocks;
   // stage timing
   bool profiling = false;
   std::vector<hipEvent_t> ev_free;
@@ -73,7 +75,10 @@ int build_tables(vpgs_ctx* ctx, CallTables& T, int n_sets, const vpgs_gaussians*
                  const int32_t* view_set, const vpgs_camera* cams, const vpgs_images* out, int tw, int th);
 int validate_forward(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, int n_views, const int32_t* view_set,
                      const vpgs_camera* cams, const vpgs_images* out, const vpgs_render_opts* opts);
+// Binds the gradient outputs (and unbinds any expansion accumulators).
 int bind_backward(vpgs_ctx* ctx, CallTables& T, const vpgs_image_grads* grad_out, const vpgs_gauss_grads* grads);
+// Binds expansion accumulators (acc may be NULL: none).
+int bind_accum(vpgs_ctx* ctx, CallTables& T, const vpgs_densify_accum* acc);
 int upload_tables(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st);
 int prepare_front(vpgs_ctx* ctx, vpgs_saved* sv);
 int ensure_pairs(vpgs_ctx* ctx, vpgs_saved* sv, uint32_t cap);

@@ -21,8 +21,10 @@ struct vpgs_window {
   std::vector<vpgs_image_grads> grad_out;
   std::vector<vpgs_gauss_grads> grads;
   float* d_pose = nullptr;
+  std::vector<float*> accum;  // expansion accumulators per set (empty: none bound)
+  vpgs_densify_accum acc_desc{};
   vpgs_window_opts cfg{};
-  bool cams_dirty = false;
+  bool tables_dirty = false;  // the tables need a rebuild before the next run
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph[2] = {nullptr, nullptr};       // forward, backward
   hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -32,6 +34,12 @@ namespace {
 
 const int kShapes[][2] = {{16, 16}, {16, 8}, {8, 8}, {32, 8}};
 
+const vpgs_densify_accum* accum_of(vpgs_window* w) {
+  if (w->accum.empty()) return nullptr;
+  w->acc_desc.accum = w->accum.data();
+  return &w->acc_desc;
+}
+
 int configure(vpgs_window* w, int tw, int th) {
   vpgs_ctx* ctx = w->ctx;
   vpgs_saved* sv = w->sv;
@@ -40,6 +48,7 @@ int configure(vpgs_window* w, int tw, int th) {
                         w->view_set.data(), w->cams.data(), w->out.data(), tw, th);
   if (rc) return rc;
   rc = bind_backward(ctx, *sv->h_tab, w->grad_out.data(), w->grads.data());
+  if (!rc) rc = bind_accum(ctx, *sv->h_tab, accum_of(w));
   if (rc) return rc;
   sv->tile_w = tw;
   sv->tile_h = th;
@@ -228,7 +237,25 @@ int vpgs_window_set_cameras(vpgs_window* w, const vpgs_camera* cams) {
   int rc = validate_forward(ctx, (int)w->sets.size(), w->sets.data(), (int)w->cams.size(), w->view_set.data(),
                             w->cams.data(), w->out.data(), &ro);
   if (rc) { w->cams = old; return rc; }
-  w->cams_dirty = true;
+  w->tables_dirty = true;
+  return VPGS_OK;
+}
+
+int vpgs_window_set_accum(vpgs_window* w, const vpgs_densify_accum* acc) {
+  if (!w) return VPGS_EINVAL;
+  vpgs_ctx* ctx = w->ctx;
+  if (!acc) {
+    w->accum.clear();
+  } else {
+    if (acc->grad_space != 0 && acc->grad_space != 1) return fail(ctx, VPGS_EINVAL, "grad_space must be 0 or 1");
+    if (!acc->accum) return fail(ctx, VPGS_EINVAL, "NULL accumulator array");
+    for (size_t s = 0; s < w->sets.size(); ++s)
+      if (acc->accum[s] && (reinterpret_cast<uintptr_t>(acc->accum[s]) & 15u) != 0)
+        return fail(ctx, VPGS_EINVAL, "set %zu: accumulators must be 16-byte aligned", s);
+    w->accum.assign(acc->accum, acc->accum + w->sets.size());
+    w->acc_desc = *acc;
+  }
+  w->tables_dirty = true;
   return VPGS_OK;
 }
 
@@ -238,15 +265,16 @@ int vpgs_window_run(vpgs_window* w, int parts, void* stream) {
   if (parts < 1 || parts > 3) return fail(ctx, VPGS_EINVAL, "parts must be 1 (forward), 2 (backward) or 3 (both)");
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(hipSetDevice(ctx->device));
-  if (w->cams_dirty) {
+  if (w->tables_dirty) {
     // rebuild the tables for the new poses (same shapes, same buffers) and upload
     HIP_TRY(hipEventSynchronize(w->sv->tab_uploaded));
     int rc = build_tables(ctx, *w->sv->h_tab, (int)w->sets.size(), w->sets.data(), (int)w->view_set.size(),
                           w->view_set.data(), w->cams.data(), w->out.data(), w->cfg.tile_w, w->cfg.tile_h);
     if (!rc) rc = bind_backward(ctx, *w->sv->h_tab, w->grad_out.data(), w->grads.data());
+    if (!rc) rc = bind_accum(ctx, *w->sv->h_tab, accum_of(w));
     if (!rc) rc = upload_tables(ctx, w->sv, st);
     if (rc) return rc;
-    w->cams_dirty = false;
+    w->tables_dirty = false;
   }
   for (int part = 1; part <= 2; ++part) {
     if (!(parts & part)) continue;

@@ -202,9 +202,31 @@ def render(sets: Sequence[Sequence[torch.Tensor]], cameras: Sequence, view_set: 
     return outs, saved
 
 
-def render_backward(saved: Saved, grad_images: Sequence, want_pose: bool = True):
+def _accum_struct(accum, set_sizes, grad_space: int):
+    """DensifyAccum over per-set [n,4] float32 tensors (None entries allowed);
+    returns (struct, keep-alive array)."""
+    if len(accum) != len(set_sizes):
+        raise ValueError("one accumulator (or None) per set")
+    arr = (ctypes.c_void_p * max(len(accum), 1))()
+    for s, (a, n) in enumerate(zip(accum, set_sizes)):
+        if a is None:
+            continue
+        if tuple(a.shape) != (n, 4) or a.dtype != torch.float32 or not a.is_contiguous():
+            raise ValueError(f"set {s}: accumulators must be contiguous float32 [{n}, 4]")
+        arr[s] = a.data_ptr()
+    return _lib.DensifyAccum(ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), int(grad_space), 0), arr
+
+
+def render_backward(saved: Saved, grad_images: Sequence, want_pose: bool = True, accum: Optional[Sequence] = None,
+                    grad_space: int = 0):
     """Backward of ``render``.  grad_images[v] = (g_rgb, g_depth, g_alpha),
-    any of them None.  Returns (list of per-set gradient tuples, d_pose[V,6] or None)."""
+    any of them None.  Returns (list of per-set gradient tuples, d_pose[V,6] or None).
+
+    accum: optional per-set [n,4] float32 expansion accumulators (or None per
+    set) that the same pass adds to: (sum of |dL/d(u,v)| and count over the
+    views that render each Gaussian, sum of max(opacity,0) and count over the
+    views whose frustum holds its centre); grad_space 1 measures the gradient
+    in normalised device coordinates."""
     L = load()
     nv, ns = saved.n_views, saved.n_sets
     gi = (_lib.ImageGrads * nv)()
@@ -226,9 +248,15 @@ def render_backward(saved: Saved, grad_images: Sequence, want_pose: bool = True)
         gb[s].means, gb[s].log_scales, gb[s].quats, gb[s].opacities, gb[s].colors = (t.data_ptr() for t in g)
         grads.append(g)
     d_pose = torch.empty((nv, 6), dtype=torch.float32, device="cuda") if want_pose else None
-    st = L.vpgs_render_backward(saved.ctx.handle, saved.handle, gi, gb, _ptr(d_pose) if want_pose else None,
-                                _stream())
-    check(st, saved.ctx.handle, "vpgs_render_backward")
+    if accum is None:
+        st = L.vpgs_render_backward(saved.ctx.handle, saved.handle, gi, gb, _ptr(d_pose) if want_pose else None,
+                                    _stream())
+        check(st, saved.ctx.handle, "vpgs_render_backward")
+    else:
+        acc, _keep = _accum_struct(accum, saved.set_sizes, grad_space)
+        st = L.vpgs_render_backward_accum(saved.ctx.handle, saved.handle, gi, gb,
+                                          _ptr(d_pose) if want_pose else None, ctypes.byref(acc), _stream())
+        check(st, saved.ctx.handle, "vpgs_render_backward_accum")
     return grads, d_pose
 
 
@@ -340,6 +368,18 @@ class RenderWindow:
     def set_cameras(self, cameras):
         cams = (_lib.Camera * self.n_views)(*[camera_struct(c) for c in cameras])
         check(load().vpgs_window_set_cameras(self.handle, cams), self.ctx.handle, "vpgs_window_set_cameras")
+
+    def set_accum(self, accum: Optional[Sequence], grad_space: int = 0):
+        """Binds per-set [n,4] expansion accumulators (see ``render_backward``)
+        that every later backward run adds to; None unbinds."""
+        L = load()
+        if accum is None:
+            check(L.vpgs_window_set_accum(self.handle, None), self.ctx.handle, "vpgs_window_set_accum")
+            self._accum = None
+            return
+        acc, keep = _accum_struct(accum, [s[0].shape[0] for s in self.sets], grad_space)
+        check(L.vpgs_window_set_accum(self.handle, ctypes.byref(acc)), self.ctx.handle, "vpgs_window_set_accum")
+        self._accum = list(accum)  # the window keeps the device pointers
 
     def run(self, forward: bool = True, backward: bool = True):
         parts = (_lib.WINDOW_FORWARD if forward else 0) | (_lib.WINDOW_BACKWARD if backward else 0)
@@ -558,3 +598,83 @@ def volume_loss(sets: Sequence, grads: Sequence, lambda_vol: float = 0.001, ctx:
     check(load().vpgs_volume_loss(ctx.handle, ns, gs, float(lambda_vol), out.data_ptr(), gb, _stream()), ctx.handle,
           "vpgs_volume_loss")
     return out[:ns]
+
+
+# ---------------------------------------------------------------------------
+# submap expansion statistics
+# ---------------------------------------------------------------------------
+
+def anchor_stats(accum: torch.Tensor, k: int, tau_g: float, tau_o: float, ctx: Optional[Context] = None):
+    """Per-anchor statistics from the [m*k, 4] accumulators of decoded
+    Gaussians (anchor-major): (stats [m,4] = (averaged gradient, rendered
+    views, accumulated opacity, frustum views), grow uint8 [m], prune uint8 [m])."""
+    ctx = ctx or get_context()
+    if accum.dim() != 2 or accum.shape[1] != 4 or accum.dtype != torch.float32 or not accum.is_contiguous():
+        raise ValueError("accumulators must be contiguous float32 [m*k, 4]")
+    if k < 1 or accum.shape[0] % k:
+        raise ValueError("the accumulator rows must be a multiple of k")
+    m = accum.shape[0] // k
+    stats = torch.empty((m, 4), dtype=torch.float32, device=accum.device)
+    grow = torch.empty((m,), dtype=torch.uint8, device=accum.device)
+    prune = torch.empty((m,), dtype=torch.uint8, device=accum.device)
+    check(load().vpgs_anchor_stats(ctx.handle, m, int(k), _ptr(accum), float(tau_g), float(tau_o), _ptr(stats),
+                                   _ptr(grow), _ptr(prune), _stream()), ctx.handle, "vpgs_anchor_stats")
+    return stats, grow, prune
+
+
+def expansion_sample(images: Sequence, targets: Sequence, cameras: Sequence, alpha_threshold: float,
+                     depth_threshold: float, uniforms: Optional[torch.Tensor] = None, want_mask: bool = True,
+                     ctx: Optional[Context] = None) -> dict:
+    """Expansion candidates and samples of every view (Section III-A).
+
+    images[v] = (rgb, depth, alpha) as rendered (depth and alpha are read);
+    targets[v] = (rgb [3,H,W], depth [H,W]); uniforms [n_views, M] float32
+    in [0, 1) or None (no samples).  Returns a dict with counts [V] int32,
+    masks (list of uint8 [H,W], or None), and for M > 0 pixels [V,M] int32,
+    points [V,M,3] and colors [V,M,3]."""
+    ctx = ctx or get_context()
+    nv = len(images)
+    if not (len(targets) == nv and len(cameras) == nv):
+        raise ValueError("images, targets and cameras must have one entry per view")
+    dev = images[0][1].device if nv else torch.device("cuda")
+    M = 0
+    if uniforms is not None:
+        if uniforms.dim() != 2 or uniforms.shape[0] != nv or uniforms.dtype != torch.float32 \
+                or not uniforms.is_contiguous():
+            raise ValueError("uniforms must be contiguous float32 [n_views, M]")
+        M = int(uniforms.shape[1])
+    cams = (_lib.Camera * max(nv, 1))()
+    ims = (_lib.Images * max(nv, 1))()
+    tgs = (_lib.Targets * max(nv, 1))()
+    outs = (_lib.ExpandOut * max(nv, 1))()
+    masks = []
+    pixels = torch.empty((nv, M), dtype=torch.int32, device=dev)
+    points = torch.empty((nv, M, 3), dtype=torch.float32, device=dev)
+    colors = torch.empty((nv, M, 3), dtype=torch.float32, device=dev)
+    for v in range(nv):
+        depth, alpha = images[v][1], images[v][2]
+        trgb, tdepth = targets[v][0], targets[v][1]
+        H, W = int(depth.shape[0]), int(depth.shape[1])
+        for t, shape, name in ((depth, (H, W), "depth"), (alpha, (H, W), "alpha"), (trgb, (3, H, W), "target rgb"),
+                               (tdepth, (H, W), "target depth")):
+            if tuple(t.shape) != shape or t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError(f"view {v}: {name} must be contiguous float32 {shape}")
+        cams[v] = camera_struct(cameras[v]) if not isinstance(cameras[v], _lib.Camera) else cameras[v]
+        if cams[v].width != W or cams[v].height != H:
+            raise ValueError(f"view {v}: camera size {cams[v].width}x{cams[v].height} differs from the image {W}x{H}")
+        ims[v].rgb, ims[v].depth, ims[v].alpha = None, depth.data_ptr(), alpha.data_ptr()
+        tgs[v].rgb, tgs[v].depth = trgb.data_ptr(), tdepth.data_ptr()
+        mk = torch.empty((H, W), dtype=torch.uint8, device=dev) if want_mask else None
+        masks.append(mk)
+        outs[v].mask = _ptr(mk)
+        if M > 0:
+            outs[v].pixel, outs[v].points, outs[v].colors = (pixels[v].data_ptr(), points[v].data_ptr(),
+                                                              colors[v].data_ptr())
+    counts = torch.empty((max(nv, 1),), dtype=torch.int32, device=dev)
+    opts = _lib.ExpandOpts(float(alpha_threshold), float(depth_threshold), M, 0)
+    check(load().vpgs_expansion_sample(ctx.handle, nv, cams, ims, tgs, ctypes.byref(opts), _ptr(uniforms),
+                                       counts.data_ptr(), outs, _stream()), ctx.handle, "vpgs_expansion_sample")
+    out = {"counts": counts[:nv], "masks": masks if want_mask else None}
+    if M > 0:
+        out.update(pixels=pixels, points=points, colors=colors)
+    return out

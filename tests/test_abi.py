@@ -58,6 +58,10 @@ def test_null_context_is_rejected_without_touching_the_device(lib):
     assert lib.vpgs_decode_backward(None, None, None, None, None, None, None, None, None, None) == _lib.VPGS_EINVAL
     assert lib.vpgs_saved_release(None, None) == _lib.VPGS_EINVAL
     assert lib.vpgs_destroy(None) == _lib.VPGS_EINVAL
+    assert lib.vpgs_render_backward_accum(None, None, None, None, None, None, None) == _lib.VPGS_EINVAL
+    assert lib.vpgs_window_set_accum(None, None) == _lib.VPGS_EINVAL
+    assert lib.vpgs_anchor_stats(None, 1, 1, None, 0.0, 0.0, None, None, None, None) == _lib.VPGS_EINVAL
+    assert lib.vpgs_expansion_sample(None, 1, None, None, None, None, None, None, None, None) == _lib.VPGS_EINVAL
     assert lib.vpgs_create(None, 0) == _lib.VPGS_EINVAL
     assert lib.vpgs_last_error(None) == b"NULL context"
 
