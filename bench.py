@@ -49,11 +49,11 @@ SORT_BYTES_PER_PAIR_PASS = 20.0  # 32-bit keys and values: histogram read 4 B, s
 # those the traffic is reported as null until it is measured again.
 MEASURED_TRAFFIC = {
     ("composite_backward", 32, 8, 0): {
-        "sources_sha256": "95a588fd6282fcc4c19281d6375bb524a17ffe01bfab071cabffd4b4e102fa8a",
-        "fetch_bytes": 1109627039, "write_bytes": 613763904},
+        "sources_sha256": "1768689087d12b1bef222375b0505bc6f15b3856c90cd6b97191d21433194723",
+        "fetch_bytes": 1109690287, "write_bytes": 613763904},
     ("composite_forward", 32, 8, 0): {
-        "sources_sha256": "95a588fd6282fcc4c19281d6375bb524a17ffe01bfab071cabffd4b4e102fa8a",
-        "fetch_bytes": 943182169, "write_bytes": 197206213},
+        "sources_sha256": "1768689087d12b1bef222375b0505bc6f15b3856c90cd6b97191d21433194723",
+        "fetch_bytes": 943196428, "write_bytes": 197190039},
 }
 TRAFFIC_SOURCES = ("paper_2505_18992_amd/csrc/composite.hip", "paper_2505_18992_amd/csrc/internal.h")
 
@@ -100,9 +100,12 @@ def workload(name):
     return sc, desc
 
 
+CPU_CROPS = 6  # seeded 128x128 gradient crops per view in the CPU baseline
+
+
 def cpu_baseline(sc):
     """Time the FP64 oracle on every view of the workload: the full forward
-    image, and the gradient over three seeded 128x128 crops scaled to the
+    image, and the gradient over six seeded 128x128 crops scaled to the
     whole view (about 10-15 s of host work at 16 threads)."""
     import oracle
     rng = np.random.default_rng(7)
@@ -115,7 +118,7 @@ def cpu_baseline(sc):
         t_fwd = time.perf_counter() - t0
         skip = np.ones((H, W), np.uint8)
         cw, ch = min(128, W), min(128, H)
-        for _ in range(3):
+        for _ in range(CPU_CROPS):
             x0 = int(rng.integers(0, W - cw + 1)); y0 = int(rng.integers(0, H - ch + 1))
             skip[y0:y0 + ch, x0:x0 + cw] = 0
         crop_px = int((skip == 0).sum())
@@ -131,7 +134,7 @@ def cpu_baseline(sc):
     nv = len(sc.cameras)
     return {"value": nv / t_total, "unit": "views/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"all {nv} views of the workload: FP64 forward on each full view ({t_fwd_total:.1f} s) and the "
-                      f"gradient on 3 seeded 128x128 crops per view ({crop_px_total} px, {t_grad_total:.1f} s), "
+                      f"gradient on {CPU_CROPS} seeded 128x128 crops per view ({crop_px_total} px, {t_grad_total:.1f} s), "
                       f"scaled by pixel count",
             "blends_per_sec": blends / t_total, "seconds_measured": t_fwd_total + t_grad_total}
 
@@ -167,6 +170,92 @@ def time_mapping_loss(win, cams, steps):
     return {"ms_per_call": ms, "views": len(cams), "bytes_per_pixel": LOSS_BYTES_PER_PIXEL, "achieved_GBs": gbs,
             "peak_GBs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS,
             "loss_view0": [float(v) for v in terms[0].cpu().tolist()]}
+
+
+ACCUM_BYTES_PER_GAUSSIAN = 36.0   # [n,4] accumulators read and written, opacity read
+ANCHOR_BYTES_PER_GAUSSIAN = 16.0  # accumulator rows read once
+ANCHOR_BYTES_PER_ANCHOR = 18.0    # statistics row and two flags written
+EXPAND_BYTES_PER_PIXEL = 13.0     # rendered alpha and depth and target depth read, mask byte written
+EXPAND_BYTES_PER_SAMPLE = 48.0    # uniform, target depth and colour read; pixel, point and colour written
+
+
+def _stage_ms(ctx, stage, fn, steps):
+    """Milliseconds per call of one library stage, from the HIP events the
+    library records on its launch stream around the stage's kernels (the
+    host-side argument marshalling of each call is outside them)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    calls, tot = ctx.profile_read()[stage]
+    ctx.profile(False)
+    return tot / max(calls, 1)
+
+
+def time_expansion(sets, gw, cams, vset, cfg, win, steps, k=10, n_samples=4096):
+    """Submap-expansion statistics on the workload: the accumulators in the
+    projection backward (its stage time with and without them), the anchor
+    reduction over the accumulators of the whole set taken as anchors of k
+    Gaussians, and the expansion sampler on the window's rendered frames
+    (target depth = rendered depth x 1.02, n_samples draws per view)."""
+    import torch
+    from paper_2505_18992_amd import RenderWindow, anchor_stats, expansion_sample, get_context
+    ctx = get_context(0)
+    ewin = RenderWindow(sets, cams, vset, tile=(cfg["tile_w"], cfg["tile_h"]), persistent=cfg["persistent"],
+                        use_graph=False, pair_capacity=cfg["pair_capacity"])
+    for v in range(len(cams)):
+        for dst, src in zip(ewin.grad_out[v], gw[v]):
+            dst.copy_(src)
+    ewin.run()
+    torch.cuda.synchronize()
+    acc = [torch.zeros((s[0].shape[0], 4), dtype=torch.float32, device=s[0].device) for s in sets]
+    pb = {}
+    for mode in ("plain", "accum"):
+        ewin.set_accum(acc if mode == "accum" else None)
+        ewin.run(forward=False, backward=True)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(steps):
+            ewin.run(forward=False, backward=True)
+        torch.cuda.synchronize()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        calls, tot = prof["project_backward"]
+        pb[mode] = tot / max(calls, 1)
+    ewin.close()
+    n = sum(s[0].shape[0] for s in sets)
+    extra = pb["accum"] - pb["plain"]
+    # anchor reduction over the first set's accumulators
+    a0 = acc[0][: (acc[0].shape[0] // k) * k]
+    m = a0.shape[0] // k
+    ms_anchor = _stage_ms(ctx, "anchor_stats", lambda: anchor_stats(a0, k, 1e-3, 0.05), steps)
+    gbs_anchor = (ANCHOR_BYTES_PER_GAUSSIAN * m * k + ANCHOR_BYTES_PER_ANCHOR * m) / (ms_anchor * 1e-3) / 1e9
+    # expansion sampler on the rendered frames
+    ims = [(None, d, a) for _, d, a in win.outputs]
+    tgs = [(rgb, torch.where(d > 0, d * 1.02, d).contiguous()) for rgb, d, _ in win.outputs]
+    gen = torch.Generator(device="cuda").manual_seed(12)
+    u = torch.rand((len(cams), n_samples), generator=gen, device="cuda")
+    res = expansion_sample(ims, tgs, cams, 0.5, 0.1, u)
+    counts = res["counts"].cpu().tolist()
+    ms_exp = _stage_ms(ctx, "expansion", lambda: expansion_sample(ims, tgs, cams, 0.5, 0.1, u), steps)
+    pixels = sum(c.width * c.height for c in cams)
+    gbs_exp = (EXPAND_BYTES_PER_PIXEL * pixels + EXPAND_BYTES_PER_SAMPLE * n_samples * len(cams)) / (ms_exp * 1e-3) / 1e9
+    log(f"[bench] expansion: project_backward {pb['plain']:.3f} -> {pb['accum']:.3f} ms with accumulators; "
+        f"anchor stats {ms_anchor:.4f} ms ({gbs_anchor:.0f} GB/s); sampler {ms_exp:.4f} ms ({gbs_exp:.0f} GB/s)")
+    return {
+        "accumulate": {"project_backward_ms": pb["plain"], "project_backward_ms_with_accum": pb["accum"],
+                       "extra_ms": extra, "gaussians": n, "bytes_per_gaussian": ACCUM_BYTES_PER_GAUSSIAN,
+                       "achieved_GBs_of_extra": ACCUM_BYTES_PER_GAUSSIAN * n / (extra * 1e-3) / 1e9
+                       if extra > 0 else None},
+        "anchor_stats": {"ms_per_call": ms_anchor, "anchors": m, "k": k, "achieved_GBs": gbs_anchor,
+                         "frac": gbs_anchor / HBM_PEAK_GBS},
+        "expansion_sample": {"ms_per_call": ms_exp, "views": len(cams), "pixels": pixels,
+                             "samples_per_view": n_samples, "candidates": counts, "achieved_GBs": gbs_exp,
+                             "frac": gbs_exp / HBM_PEAK_GBS},
+    }
 
 
 def main():
@@ -280,6 +369,8 @@ def main():
     # the mapping loss of eq. 7-8 on the same views (rendered frames against
     # perturbed copies of themselves), timed on its own
     loss_stage = time_mapping_loss(win, cams, args.steps)
+    # the submap-expansion statistics of Section III-A on the same workload
+    expansion = time_expansion(sets, gw, cams, vset, cfg, win, args.steps)
 
     E, B, P = st["n_evaluated"], st["n_blended"], st["n_pairs"]
     dom = max(stage_ms, key=stage_ms.get)
@@ -325,6 +416,7 @@ def main():
          "batched_speedup": ms_per_view_launch / ms_step},
         "stage_ms": stage_ms,
         "mapping_loss": loss_stage,
+        "expansion": expansion,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
