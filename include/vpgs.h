@@ -251,12 +251,12 @@ int vpgs_window_destroy(vpgs_window* win);
  * ranges, forward compositing, backward compositing, projection backward,
  * pose reduction, fills, decode forward, decode backward, depth ordering of
  * the visible records, mapping loss, volume loss, anchor statistics,
- * expansion sampling).  vpgs_profile_read
+ * expansion sampling, distillation loss).  vpgs_profile_read
  * synchronises on the recorded events and returns, for stage index `stage`
  * (0 <= stage < VPGS_NUM_STAGES), its name, the number of recorded launches
  * and their summed duration in milliseconds since the last enable.  Disabled
  * by default; enabling resets the totals. */
-#define VPGS_NUM_STAGES 17
+#define VPGS_NUM_STAGES 18
 int vpgs_profile_enable(vpgs_ctx* ctx, int on);
 int vpgs_profile_read(vpgs_ctx* ctx, int stage, const char** name, int64_t* calls, double* total_ms);
 
@@ -429,6 +429,24 @@ typedef struct {
 int vpgs_expansion_sample(vpgs_ctx* ctx, int n_views, const vpgs_camera* cams, const vpgs_images* rendered,
                           const vpgs_targets* targets, const vpgs_expand_opts* opts, const float* uniforms,
                           int32_t* counts, const vpgs_expand_out* out, void* stream);
+
+/* ---- submap fusion (Section III-C, eq. 14) -------------------------------- */
+
+/* Distillation loss between two submaps alpha and beta rendered at the poses
+ * of the m keyframes of their overlap (rend_a[k] from alpha, rend_b[k] from
+ * beta, both of cams[k]'s size; .rgb and .depth are read):
+ *   l_k = mean over channels and pixels of (C_a - C_b)^2
+ *       + mean over pixels of (D_a - D_b)^2,      L = (1/m) sum_k l_k.
+ * terms (device [m,2] floats: the colour and depth means of each keyframe)
+ * and loss (device float) may be NULL.  grad_a / grad_b (host arrays of
+ * device planes, or NULL for no gradient on that side) receive
+ * dL/dC_a = 2 (C_a - C_b) / (3 m H W) = -dL/dC_b and
+ * dL/dD_a = 2 (D_a - D_b) / (m H W) = -dL/dD_b (a NULL plane is skipped;
+ * .alpha planes, when given, are zeroed): the upstream planes of the render
+ * backward of both submaps.  1 <= m <= VPGS_MAX_VIEWS. */
+int vpgs_distill_loss(vpgs_ctx* ctx, int m, const vpgs_camera* cams, const vpgs_images* rend_a,
+                      const vpgs_images* rend_b, float* terms, float* loss, const vpgs_images* grad_a,
+                      const vpgs_images* grad_b, void* stream);
 
 #ifdef __cplusplus
 }

@@ -7,7 +7,7 @@ into that ABI.  Importing it does not load the library; the first call does,
 and fails loudly if the library is not built.
 """
 from .render import (Context, DecodeFn, RenderFn, Saved, anchor_stats, camera_struct, decode,  # noqa: F401
-                     decode_backward, decode_forward, expansion_sample, get_context, mapping_loss, render,
+                     decode_backward, decode_forward, distill_loss, expansion_sample, get_context, mapping_loss, render,
                      render_backward, render_views, RenderWindow, volume_loss)
 
 __version__ = "0.1.0"

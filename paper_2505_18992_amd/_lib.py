@@ -22,7 +22,7 @@ VPGS_ECAPACITY = -4
 VPGS_EUNSUPPORTED = -5
 MAX_VIEWS = 64
 MAX_SETS = 64
-NUM_STAGES = 17
+NUM_STAGES = 18
 WINDOW_FORWARD, WINDOW_BACKWARD = 1, 2
 
 BUF_PROJ, BUF_EXTENT, BUF_COUNT, BUF_KEYS, BUF_VALUES, BUF_RANGES, BUF_TFINAL, BUF_NCONTRIB = range(1, 9)
@@ -155,6 +155,9 @@ SIGNATURES = {
     "vpgs_expansion_sample": (ctypes.c_int, [c_void_p, ctypes.c_int, ctypes.POINTER(Camera), ctypes.POINTER(Images),
                                              ctypes.POINTER(Targets), ctypes.POINTER(ExpandOpts), c_void_p, c_void_p,
                                              ctypes.POINTER(ExpandOut), c_void_p]),
+    "vpgs_distill_loss": (ctypes.c_int, [c_void_p, ctypes.c_int, ctypes.POINTER(Camera), ctypes.POINTER(Images),
+                                         ctypes.POINTER(Images), c_void_p, c_void_p, ctypes.POINTER(Images),
+                                         ctypes.POINTER(Images), c_void_p]),
 }
 
 _LIB = None

@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(kExpandBlock) expand_scan_kernel(ExpandBatch B
 }
 
 // One wavefront per sample: the chunk holding the candidate of rank r by a
-// binary search over the offsets, then the position inside the chunk by a
+// 64-way search over the offsets, then the position inside the chunk by a
 // wavefront prefix count of 16 mask bytes per lane (raster order), and the
 // back-projection of that pixel centre with the target depth.
 __global__ void __launch_bounds__(kExpandBlock) expand_sample_kernel(ExpandBatch B) {
@@ -153,18 +153,36 @@ __global__ void __launch_bounds__(kExpandBlock) expand_sample_kernel(ExpandBatch
   uint32_t r = 0;  // u in [0, 1); anything else is clamped to the first or last rank
   if (prod >= (float)c) r = c - 1;
   else if (prod > 0.0f) r = min((uint32_t)prod, c - 1);
-  int lo = 0, hi = V.nb - 1;  // the last chunk whose offset is <= r
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (V.boff[mid] <= r) lo = mid; else hi = mid - 1;
+  // the last chunk whose offset is <= r, by a 64-way search: the lanes probe
+  // evenly spaced offsets of the remaining range and keep the last one that
+  // is <= r (boff[lo] <= r holds throughout, boff is non-decreasing)
+  int lo = 0, len = V.nb;
+  while (len > 1) {
+    const int step = (len + 63) >> 6;
+    const int idx = lo + lane * step;
+    const bool ok = idx < lo + len && V.boff[idx] <= r;
+    const int last = 63 - __clzll(__ballot(ok));
+    const int end = lo + len;
+    lo += last * step;
+    len = min(step, end - lo);
   }
   const uint32_t within = r - V.boff[lo];
   const int64_t HW = (int64_t)V.W * V.H;
   const int64_t p0 = (int64_t)lo * kExpandChunk + 16 * lane;
   uint32_t bits = 0;  // candidate flags of the lane's 16 pixels
+  if (p0 + 16 <= HW && (reinterpret_cast<uintptr_t>(V.mask + p0) & 15u) == 0) {
+    const uint4 w = *reinterpret_cast<const uint4*>(V.mask + p0);
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-  for (int q = 0; q < 16; ++q)
-    if (p0 + q < HW && V.mask[p0 + q]) bits |= 1u << q;
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if ((ws[j] >> (8 * b)) & 0xffu) bits |= 1u << (4 * j + b);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (p0 + q < HW && V.mask[p0 + q]) bits |= 1u << q;
+  }
   const uint32_t cnt = (uint32_t)__popc(bits);
   uint32_t incl = cnt;
 #pragma unroll

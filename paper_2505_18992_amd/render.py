@@ -678,3 +678,56 @@ def expansion_sample(images: Sequence, targets: Sequence, cameras: Sequence, alp
     if M > 0:
         out.update(pixels=pixels, points=points, colors=colors)
     return out
+
+
+# ---------------------------------------------------------------------------
+# submap fusion
+# ---------------------------------------------------------------------------
+
+def distill_loss(images_a: Sequence, images_b: Sequence, cameras: Sequence, grad_a: Optional[Sequence] = None,
+                 grad_b: Optional[Sequence] = None, want_grads: bool = True, ctx: Optional[Context] = None):
+    """Distillation loss of eq. 14 between two submaps rendered at the m
+    keyframes of their overlap: images_a[k] / images_b[k] = (rgb, depth, ...)
+    from submap alpha / beta.  Returns (loss [1], terms [m, 2], grads_a,
+    grads_b); grads are per keyframe (g_rgb, g_depth, g_alpha) written into
+    grad_a / grad_b when given (e.g. a window's upstream planes), else
+    allocated when want_grads (None otherwise)."""
+    ctx = ctx or get_context()
+    m = len(images_a)
+    if not (len(images_b) == m and len(cameras) == m):
+        raise ValueError("images_a, images_b and cameras must have one entry per keyframe")
+    dev = images_a[0][0].device if m else torch.device("cuda")
+    cams = (_lib.Camera * max(m, 1))()
+    ia = (_lib.Images * max(m, 1))()
+    ib = (_lib.Images * max(m, 1))()
+    ga = (_lib.Images * max(m, 1))()
+    gb = (_lib.Images * max(m, 1))()
+    outs = {"a": grad_a, "b": grad_b}
+    for side in ("a", "b"):
+        if outs[side] is None and want_grads:
+            outs[side] = [tuple(torch.empty_like(x) for x in (img[0], img[1], img[1]))
+                          for img in (images_a if side == "a" else images_b)]
+    for k in range(m):
+        for side, src in (("a", images_a[k]), ("b", images_b[k])):
+            rgb, depth = src[0], src[1]
+            H, W = int(depth.shape[0]), int(depth.shape[1])
+            for t, shape, name in ((rgb, (3, H, W), "rgb"), (depth, (H, W), "depth")):
+                if tuple(t.shape) != shape or t.dtype != torch.float32 or not t.is_contiguous():
+                    raise ValueError(f"keyframe {k} ({side}): {name} must be contiguous float32 {shape}")
+            dst = ia if side == "a" else ib
+            dst[k].rgb, dst[k].depth, dst[k].alpha = rgb.data_ptr(), depth.data_ptr(), None
+            g = outs[side]
+            if g is not None:
+                gg = ga if side == "a" else gb
+                gg[k].rgb, gg[k].depth, gg[k].alpha = (t.data_ptr() if t is not None else None for t in g[k])
+        cams[k] = camera_struct(cameras[k]) if not isinstance(cameras[k], _lib.Camera) else cameras[k]
+        if cams[k].width != int(images_a[k][1].shape[1]) or cams[k].height != int(images_a[k][1].shape[0]):
+            raise ValueError(f"keyframe {k}: camera size differs from the images")
+        if tuple(images_b[k][1].shape) != tuple(images_a[k][1].shape):
+            raise ValueError(f"keyframe {k}: the two renders differ in size")
+    terms = torch.empty((max(m, 1), 2), dtype=torch.float32, device=dev)
+    loss = torch.empty((1,), dtype=torch.float32, device=dev)
+    check(load().vpgs_distill_loss(ctx.handle, m, cams, ia, ib, terms.data_ptr(), loss.data_ptr(),
+                                   ga if outs["a"] is not None else None, gb if outs["b"] is not None else None,
+                                   _stream()), ctx.handle, "vpgs_distill_loss")
+    return loss, terms[:m], outs["a"], outs["b"]

@@ -62,6 +62,7 @@ def test_null_context_is_rejected_without_touching_the_device(lib):
     assert lib.vpgs_window_set_accum(None, None) == _lib.VPGS_EINVAL
     assert lib.vpgs_anchor_stats(None, 1, 1, None, 0.0, 0.0, None, None, None, None) == _lib.VPGS_EINVAL
     assert lib.vpgs_expansion_sample(None, 1, None, None, None, None, None, None, None, None) == _lib.VPGS_EINVAL
+    assert lib.vpgs_distill_loss(None, 1, None, None, None, None, None, None, None, None) == _lib.VPGS_EINVAL
     assert lib.vpgs_create(None, 0) == _lib.VPGS_EINVAL
     assert lib.vpgs_last_error(None) == b"NULL context"
 
