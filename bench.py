@@ -100,12 +100,12 @@ def workload(name):
     return sc, desc
 
 
-CPU_CROPS = 6  # seeded 128x128 gradient crops per view in the CPU baseline
+CPU_CROPS = 8  # seeded 128x128 gradient crops per view in the CPU baseline
 
 
 def cpu_baseline(sc):
     """Time the FP64 oracle on every view of the workload: the full forward
-    image, and the gradient over six seeded 128x128 crops scaled to the
+    image, and the gradient over eight seeded 128x128 crops scaled to the
     whole view (about 10-15 s of host work at 16 threads)."""
     import oracle
     rng = np.random.default_rng(7)
@@ -258,6 +258,73 @@ def time_expansion(sets, gw, cams, vset, cfg, win, steps, k=10, n_samples=4096):
     }
 
 
+DISTILL_BYTES_PER_PIXEL = 72.0  # both renders' colour+depth read (32 B), both sides' gradient planes written (40 B)
+
+
+def time_distillation(steps, m=4):
+    """One submap-fusion iteration of eq. 14 on the street workload: two
+    overlapping 1.5 M-Gaussian submaps rendered at m keyframes of their
+    overlap in one window (2m views, one graph per part), the distillation
+    loss writing both sides' upstream planes, and the backward."""
+    import torch
+    import scenes
+    from paper_2505_18992_amd import RenderWindow, distill_loss, get_context
+    ctx = get_context(0)
+    sc = scenes.make_c5(submaps=2, weights=False)
+    kf = [scenes.camera_look((52.0 + 16.0 * i / max(m - 1, 1), 1.0 - 2.0 * (i % 2), 1.7), 0.03 * (i % 3 - 1), 0.0,
+                             0.0, 1242, 375, 720.0, 720.0, 621.0, 187.5) for i in range(m)]
+    cams, vset = kf + kf, [0] * m + [1] * m
+    sets = [tuple(torch.from_numpy(a).cuda() for a in g.arrays()) for g in sc.sets]
+    win = RenderWindow(sets, cams, vset, tile=(32, 8), persistent=0)
+    ia, ib = win.outputs[:m], win.outputs[m:]
+
+    def iteration():
+        win.run(forward=True, backward=False)
+        distill_loss(ia, ib, kf, grad_a=win.grad_out[:m], grad_b=win.grad_out[m:])
+        win.run(forward=False, backward=True)
+    for _ in range(3):
+        iteration()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        iteration()
+    torch.cuda.synchronize()
+    ms_iter = (time.perf_counter() - t0) * 1e3 / steps
+    ms_loss = _stage_ms(ctx, "distillation",
+                        lambda: distill_loss(ia, ib, kf, grad_a=win.grad_out[:m], grad_b=win.grad_out[m:]), steps)
+    loss, _, _, _ = distill_loss(ia, ib, kf, grad_a=win.grad_out[:m], grad_b=win.grad_out[m:])
+    st = win.stats()
+    # stage times of the same iteration launched eagerly
+    twin = RenderWindow(sets, cams, vset, tile=(32, 8), persistent=0, use_graph=False,
+                        pair_capacity=win.config()["pair_capacity"])
+    tia, tib = twin.outputs[:m], twin.outputs[m:]
+
+    def eager_iteration():
+        twin.run(forward=True, backward=False)
+        distill_loss(tia, tib, kf, grad_a=twin.grad_out[:m], grad_b=twin.grad_out[m:])
+        twin.run(forward=False, backward=True)
+    eager_iteration()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(steps):
+        eager_iteration()
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    twin.close()
+    stage_ms = {k: v[1] / steps for k, v in prof.items() if v[0] > 0}
+    win.close()
+    pixels = m * 1242 * 375
+    gbs = DISTILL_BYTES_PER_PIXEL * pixels / (ms_loss * 1e-3) / 1e9
+    log(f"[bench] distillation: {ms_iter:.3f} ms per iteration ({2 * m} views of 2 x 1.5M-Gaussian submaps); "
+        f"loss kernel {ms_loss:.4f} ms ({gbs:.0f} GB/s)")
+    return {"ms_per_iteration": ms_iter, "keyframes": m, "views": 2 * m, "gaussians_per_submap": sc.sets[0].n,
+            "resolution": "1242x375", "blends": st["n_blended"], "evaluated": st["n_evaluated"],
+            "pairs": st["n_pairs"], "loss": float(loss[0]), "stage_ms": stage_ms,
+            "loss_kernel": {"ms_per_call": ms_loss, "bytes_per_pixel": DISTILL_BYTES_PER_PIXEL, "achieved_GBs": gbs,
+                            "frac": gbs / HBM_PEAK_GBS}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -371,6 +438,8 @@ def main():
     loss_stage = time_mapping_loss(win, cams, args.steps)
     # the submap-expansion statistics of Section III-A on the same workload
     expansion = time_expansion(sets, gw, cams, vset, cfg, win, args.steps)
+    # submap fusion (eq. 14) on two street submaps
+    distillation = time_distillation(args.steps)
 
     E, B, P = st["n_evaluated"], st["n_blended"], st["n_pairs"]
     dom = max(stage_ms, key=stage_ms.get)
@@ -417,6 +486,7 @@ def main():
         "stage_ms": stage_ms,
         "mapping_loss": loss_stage,
         "expansion": expansion,
+        "distillation": distillation,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
