@@ -162,17 +162,26 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
   uint32_t last = 0;
   bool done = !inside;
 
+  // batch i + 1 is loaded into registers while batch i is tested and
+  // composited, so a long list does not wait on each batch's loads
+  float4 pA = make_float4(0.f, 0.f, 0.f, 0.f), pR = pA, pC = pA;
+  if (rg.x + threadIdx.x < rg.y) {
+    const float4* r = recs + rec_slot(vals[rg.x + threadIdx.x], 0);
+    pA = r[0]; pR = r[1]; pC = r[2];
+  }
   for (uint32_t start = rg.x; start < rg.y; start += BS) {
     if (__syncthreads_count(done) == BS) break;
-    const uint32_t idx = start + threadIdx.x;
-    if (idx < rg.y) {
-      const float4* r = recs + rec_slot(vals[idx], 0);
-      const float4 A = r[0];
-      sh.A[threadIdx.x] = A;
-      sh.E[threadIdx.x] = stage_exponent(A, r[1]);
-      sh.C[threadIdx.x] = r[2];
+    if (start + threadIdx.x < rg.y) {
+      sh.A[threadIdx.x] = pA;
+      sh.E[threadIdx.x] = stage_exponent(pA, pR);
+      sh.C[threadIdx.x] = pC;
     }
     __syncthreads();
+    const uint32_t nidx = start + BS + threadIdx.x;
+    if (nidx < rg.y) {
+      const float4* r = recs + rec_slot(vals[nidx], 0);
+      pA = r[0]; pR = r[1]; pC = r[2];
+    }
     const int nhit = wave_hits<BS, false>(sh.A, sh.E, (int)min((uint32_t)BS, rg.y - start), q, hits);
     __syncthreads();
     const uint32_t base = start - rg.x + 1u;
@@ -244,7 +253,7 @@ template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
     const CallTables* __restrict__ tab, const float4* __restrict__ recs, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals, float* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
-    Counters* __restrict__ cnt, uint32_t* __restrict__ queue, uint32_t n_tiles) {
+    const uint32_t* __restrict__ order, Counters* __restrict__ cnt, uint32_t* __restrict__ queue, uint32_t n_tiles) {
   __shared__ FwdShared<TW, TH> sh;
   __shared__ uint32_t slot;
   uint32_t ne = 0, nb = 0;
@@ -254,10 +263,13 @@ __global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
     sh.C[TW * TH] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   if (queue == nullptr) {
-    forward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, blockIdx.x, sh, ne, nb);
+    const uint32_t tile = order[blockIdx.x];
+    if (tile < n_tiles) forward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, tile, sh, ne, nb);
   } else {
-    for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot))
-      forward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, t, sh, ne, nb);
+    for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot)) {
+      const uint32_t tile = order[t];
+      if (tile < n_tiles) forward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, tile, sh, ne, nb);
+    }
   }
   flush_counts(ne, nb, cnt);
 }
@@ -433,7 +445,7 @@ __global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
     const CallTables* __restrict__ tab, const float4* __restrict__ recs, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals,
     const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib, float* __restrict__ acc,
-    uint32_t* __restrict__ queue, uint32_t n_tiles) {
+    const uint32_t* __restrict__ order, uint32_t* __restrict__ queue, uint32_t n_tiles) {
   __shared__ BwdShared<TW, TH> sh;
   __shared__ uint32_t slot;
   if (threadIdx.x == 0) {  // the sentinel slot (read after the first staging barrier)
@@ -441,30 +453,33 @@ __global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
     sh.E[TW * TH] = make_float4(0.f, 0.f, 0.f, kNegInf);
   }
   if (queue == nullptr) {
-    backward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, acc, blockIdx.x, sh);
+    const uint32_t tile = order[blockIdx.x];
+    if (tile < n_tiles) backward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, acc, tile, sh);
   } else {
-    for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot))
-      backward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, acc, t, sh);
+    for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot)) {
+      const uint32_t tile = order[t];
+      if (tile < n_tiles) backward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, acc, tile, sh);
+    }
   }
 }
 
 template <int TW, int TH>
 hipError_t launch_fwd_t(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb, const uint2* ranges,
-                        const uint32_t* vals, float* T_final, uint32_t* n_contrib, Counters* cnt, uint32_t* queue,
-                        uint32_t blocks, hipStream_t s) {
+                        const uint32_t* vals, const uint32_t* order, float* T_final, uint32_t* n_contrib,
+                        Counters* cnt, uint32_t* queue, uint32_t blocks, hipStream_t s) {
   const uint32_t grid = queue ? blocks : h.n_tiles;
   hipLaunchKernelGGL((composite_forward_kernel<TW, TH>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.rec,
-                     ranges, vals, T_final, n_contrib, cnt, queue, h.n_tiles);
+                     ranges, vals, T_final, n_contrib, order, cnt, queue, h.n_tiles);
   return hipGetLastError();
 }
 
 template <int TW, int TH>
 hipError_t launch_bwd_t(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb, const uint2* ranges,
-                        const uint32_t* vals, const float* T_final, const uint32_t* n_contrib, float* acc,
-                        uint32_t* queue, uint32_t blocks, hipStream_t s) {
+                        const uint32_t* vals, const uint32_t* order, const float* T_final,
+                        const uint32_t* n_contrib, float* acc, uint32_t* queue, uint32_t blocks, hipStream_t s) {
   const uint32_t grid = queue ? blocks : h.n_tiles;
   hipLaunchKernelGGL((composite_backward_kernel<TW, TH>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.rec,
-                     ranges, vals, T_final, n_contrib, acc, queue, h.n_tiles);
+                     ranges, vals, T_final, n_contrib, acc, order, queue, h.n_tiles);
   return hipGetLastError();
 }
 
@@ -475,26 +490,26 @@ bool tile_shape_supported(int tw, int th) {
 }
 
 hipError_t launch_composite_forward(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb,
-                                    const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,
-                                    Counters* cnt, int tile_w, int tile_h, uint32_t* queue, uint32_t blocks,
-                                    hipStream_t s) {
+                                    const uint2* ranges, const uint32_t* vals, const uint32_t* order,
+                                    float* T_final, uint32_t* n_contrib, Counters* cnt, int tile_w, int tile_h,
+                                    uint32_t* queue, uint32_t blocks, hipStream_t s) {
   if (h.n_tiles == 0) return hipSuccess;
 #define VPGS_FWD(TW, TH) \
   if (tile_w == TW && tile_h == TH) \
-    return launch_fwd_t<TW, TH>(d_tab, h, pb, ranges, vals, T_final, n_contrib, cnt, queue, blocks, s);
+    return launch_fwd_t<TW, TH>(d_tab, h, pb, ranges, vals, order, T_final, n_contrib, cnt, queue, blocks, s);
   VPGS_FWD(16, 16) VPGS_FWD(16, 8) VPGS_FWD(8, 8) VPGS_FWD(32, 8)
 #undef VPGS_FWD
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_composite_backward(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb,
-                                     const uint2* ranges, const uint32_t* vals, const float* T_final,
-                                     const uint32_t* n_contrib, float* acc, int tile_w, int tile_h, uint32_t* queue,
-                                     uint32_t blocks, hipStream_t s) {
+                                     const uint2* ranges, const uint32_t* vals, const uint32_t* order,
+                                     const float* T_final, const uint32_t* n_contrib, float* acc, int tile_w,
+                                     int tile_h, uint32_t* queue, uint32_t blocks, hipStream_t s) {
   if (h.n_tiles == 0) return hipSuccess;
 #define VPGS_BWD(TW, TH) \
   if (tile_w == TW && tile_h == TH) \
-    return launch_bwd_t<TW, TH>(d_tab, h, pb, ranges, vals, T_final, n_contrib, acc, queue, blocks, s);
+    return launch_bwd_t<TW, TH>(d_tab, h, pb, ranges, vals, order, T_final, n_contrib, acc, queue, blocks, s);
   VPGS_BWD(16, 16) VPGS_BWD(16, 8) VPGS_BWD(8, 8) VPGS_BWD(32, 8)
 #undef VPGS_BWD
   return hipErrorInvalidValue;

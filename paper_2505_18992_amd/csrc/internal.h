@@ -78,6 +78,9 @@ struct CallTables {
 // wavefront adds to the slot of its workgroup index) so that thousands of
 // workgroups do not serialise on one address; readers sum the slots.
 constexpr int kCountSlots = 64;
+// Tiles are composited longest list first: their lengths fall into
+// kOrderBuckets classes (half-octaves), ordered by descending class.
+constexpr int kOrderBuckets = 66;
 struct Counters {
   unsigned long long evaluated[kCountSlots];
   unsigned long long blended[kCountSlots];
@@ -87,6 +90,8 @@ struct Counters {
   uint32_t queue_fwd;  // tile tickets of the persistent forward compositor
   uint32_t queue_bwd;  // and of the persistent backward compositor
   uint32_t pad[3];
+  uint32_t tile_hist[kOrderBuckets];    // tiles per list-length class (the compositing order)
+  uint32_t tile_cursor[kOrderBuckets];  // slots taken in each class
 };
 static_assert(sizeof(Counters) <= 4096, "the counters are read back through a 4 KiB pinned buffer");
 
@@ -168,21 +173,28 @@ hipError_t launch_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint3
 
 hipError_t launch_ranges(const uint32_t* tiles, const Counters* cnt, uint32_t capacity, uint2* ranges,
                          uint32_t n_tiles, hipStream_t s);
+// The compositing order of the tiles: order[i] is the tile the i-th
+// workgroup (or queue ticket) takes, by descending half-octave of the list
+// length, so that the longest lists start first (the order within a class is
+// unspecified; every tile appears once).  Uses the zeroed tile_hist and
+// tile_cursor of cnt.
+hipError_t launch_tile_order(const uint2* ranges, uint32_t n_tiles, Counters* cnt, uint32_t* order, hipStream_t s);
 
 // Sorted keys in the exported 64-bit form (tile id << 32 | depth bits).
 hipError_t launch_key64(const uint32_t* tiles, const uint32_t* recs, const ProjBuffers pb, const Counters* cnt,
                         uint32_t capacity, uint64_t* out, hipStream_t s);
 
 // Compositing: one workgroup per tile, or (queue != NULL) `blocks`
-// persistent workgroups taking tiles from the zeroed counter *queue.
+// persistent workgroups taking tiles from the zeroed counter *queue; the
+// i-th workgroup or ticket takes tile order[i].
 hipError_t launch_composite_forward(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
-                                    const uint2* ranges, const uint32_t* vals, float* T_final,
-                                    uint32_t* n_contrib, Counters* cnt, int tile_w, int tile_h,
+                                    const uint2* ranges, const uint32_t* vals, const uint32_t* order,
+                                    float* T_final, uint32_t* n_contrib, Counters* cnt, int tile_w, int tile_h,
                                     uint32_t* queue, uint32_t blocks, hipStream_t s);
 hipError_t launch_composite_backward(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
-                                     const uint2* ranges, const uint32_t* vals, const float* T_final,
-                                     const uint32_t* n_contrib, float* acc, int tile_w, int tile_h,
-                                     uint32_t* queue, uint32_t blocks, hipStream_t s);
+                                     const uint2* ranges, const uint32_t* vals, const uint32_t* order,
+                                     const float* T_final, const uint32_t* n_contrib, float* acc, int tile_w,
+                                     int tile_h, uint32_t* queue, uint32_t blocks, hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float value, size_t n, hipStream_t s);

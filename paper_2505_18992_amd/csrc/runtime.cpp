@@ -94,7 +94,7 @@ void destroy_saved(vpgs_saved* s) {
   DevBuf* bufs[] = {&s->tab, &s->rec, &s->count, &s->zkey, &s->scan_ws,
                     &s->keys, &s->vals, &s->keys_alt, &s->vals_alt, &s->sort_ws, &s->ranges, &s->tfinal,
                     &s->ncontrib, &s->counters, &s->acc, &s->pose_partial, &s->dk, &s->dk_alt, &s->dv,
-                    &s->dv_alt, &s->dcount, &s->dpoff, &s->key64};
+                    &s->dv_alt, &s->dcount, &s->dpoff, &s->key64, &s->order};
   for (DevBuf* b : bufs) free_buf(*b);
   if (s->tab_uploaded) (void)hipEventDestroy(s->tab_uploaded);
   if (s->h_tab) (void)hipHostFree(s->h_tab);
@@ -289,7 +289,8 @@ int prepare_front(vpgs_ctx* ctx, vpgs_saved* sv) {
   if ((rc = ensure(ctx, sv->tab, sizeof(CallTables))) || (rc = ensure(ctx, sv->rec, R * kRecSlots * 16)) ||
       (rc = ensure(ctx, sv->count, R * 4)) || (rc = ensure(ctx, sv->zkey, R * 4)) ||
       (rc = ensure(ctx, sv->scan_ws, scan_workspace_bytes((uint32_t)R))) ||
-      (rc = ensure(ctx, sv->ranges, (size_t)T.n_tiles * 8)) || (rc = ensure(ctx, sv->tfinal, pixels * 4)) ||
+      (rc = ensure(ctx, sv->ranges, (size_t)T.n_tiles * 8)) || (rc = ensure(ctx, sv->order, (size_t)T.n_tiles * 4)) ||
+      (rc = ensure(ctx, sv->tfinal, pixels * 4)) ||
       (rc = ensure(ctx, sv->ncontrib, pixels * 4)) || (rc = ensure(ctx, sv->counters, sizeof(Counters))))
     return rc;
   return VPGS_OK;
@@ -421,11 +422,13 @@ int enqueue_back(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
   {
     StageTimer t(ctx, ST_RANGES, st);
     HIP_TRY(launch_ranges(skeys, cnt, cap, static_cast<uint2*>(sv->ranges.p), T.n_tiles, st));
+    HIP_TRY(launch_tile_order(static_cast<const uint2*>(sv->ranges.p), T.n_tiles, cnt,
+                              static_cast<uint32_t*>(sv->order.p), st));
   }
   {
     StageTimer t(ctx, ST_FWD, st);
     HIP_TRY(launch_composite_forward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
-                                     static_cast<float*>(sv->tfinal.p), static_cast<uint32_t*>(sv->ncontrib.p), cnt,
+                                     static_cast<const uint32_t*>(sv->order.p), static_cast<float*>(sv->tfinal.p), static_cast<uint32_t*>(sv->ncontrib.p), cnt,
                                      sv->tile_w, sv->tile_h, sv->persistent_blocks ? &cnt->queue_fwd : nullptr,
                                      sv->persistent_blocks, st));
   }
@@ -446,7 +449,7 @@ int enqueue_backward(vpgs_ctx* ctx, vpgs_saved* sv, float* d_pose, hipStream_t s
   {
     StageTimer t(ctx, ST_BWD, st);
     HIP_TRY(launch_composite_backward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
-                                      static_cast<const float*>(sv->tfinal.p),
+                                      static_cast<const uint32_t*>(sv->order.p), static_cast<const float*>(sv->tfinal.p),
                                       static_cast<const uint32_t*>(sv->ncontrib.p), acc, sv->tile_w, sv->tile_h,
                                       sv->persistent_blocks ? &cnt->queue_bwd : nullptr, sv->persistent_blocks, st));
   }

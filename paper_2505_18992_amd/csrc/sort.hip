@@ -341,6 +341,60 @@ __global__ void key64_kernel(const uint32_t* __restrict__ tiles, const uint32_t*
   out[k] = k < n ? ((uint64_t)tiles[k] << 32) | __float_as_uint(recs[rec_slot(rec_of[k], 0)].z) : 0ull;
 }
 
+// Half-octave class of a list length: 0 for an empty list, else
+// 1 + 2 floor(log2 len) + the bit below the leading one.
+__device__ __forceinline__ int length_class(uint32_t len) {
+  if (len == 0) return 0;
+  const int lg = 31 - __clz((int)len);
+  const int sub = lg > 0 ? (int)((len >> (lg - 1)) & 1u) : 0;
+  return 1 + 2 * lg + sub;
+}
+
+__global__ void __launch_bounds__(256) tile_hist_kernel(const uint2* __restrict__ ranges, uint32_t n_tiles,
+                                                        Counters* __restrict__ cnt) {
+  __shared__ uint32_t h[kOrderBuckets];
+  for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) h[b] = 0;
+  __syncthreads();
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  if (t < n_tiles) {
+    const uint2 r = ranges[t];
+    atomicAdd(&h[length_class(r.y - r.x)], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x)
+    if (h[b]) atomicAdd(&cnt->tile_hist[b], h[b]);
+}
+
+// Each workgroup ranks its tiles within their classes in LDS, reserves a run
+// of slots per class with one global atomic, and writes its tiles there;
+// classes are laid out from the longest down.
+__global__ void __launch_bounds__(256) tile_order_kernel(const uint2* __restrict__ ranges, uint32_t n_tiles,
+                                                         Counters* __restrict__ cnt, uint32_t* __restrict__ order) {
+  __shared__ uint32_t first[kOrderBuckets], local[kOrderBuckets], base[kOrderBuckets];
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int b = kOrderBuckets - 1; b >= 0; --b) {
+      first[b] = acc;
+      acc += cnt->tile_hist[b];
+    }
+  }
+  for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) local[b] = 0;
+  __syncthreads();
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  int cls = 0;
+  uint32_t rank = 0;
+  if (t < n_tiles) {
+    const uint2 r = ranges[t];
+    cls = length_class(r.y - r.x);
+    rank = atomicAdd(&local[cls], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x)
+    base[b] = local[b] ? atomicAdd(&cnt->tile_cursor[b], local[b]) : 0u;
+  __syncthreads();
+  if (t < n_tiles) order[first[cls] + base[cls] + rank] = t;
+}
+
 }  // namespace
 
 size_t sort_workspace_bytes(uint32_t capacity) { return radix_ws_bytes(capacity); }
@@ -377,6 +431,14 @@ hipError_t launch_ranges(const uint32_t* tiles, const Counters* cnt, uint32_t ca
   if (e != hipSuccess || capacity == 0) return e;
   hipLaunchKernelGGL(ranges_kernel, dim3(div_up(capacity, 256)), dim3(256), 0, s, tiles, &cnt->pairs, capacity, ranges,
                      n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_order(const uint2* ranges, uint32_t n_tiles, Counters* cnt, uint32_t* order, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  const dim3 grid(div_up(n_tiles, 256));
+  hipLaunchKernelGGL(tile_hist_kernel, grid, dim3(256), 0, s, ranges, n_tiles, cnt);
+  hipLaunchKernelGGL(tile_order_kernel, grid, dim3(256), 0, s, ranges, n_tiles, cnt, order);
   return hipGetLastError();
 }
 
