@@ -20,6 +20,9 @@ paper's setting:
           mixed resolution on a 20 m path (the mapping window).
 * ``c5``  4 submaps x 1.5 M Gaussians along a 200 m street (ground and
           facades), 16 keyframes at 1242x375 (KITTI-like street frames).
+* ``street scan``  1.5 M map points on an 80 m street with boxes, one
+          64-beam LiDAR sweep in the sensor frame, the true and a perturbed
+          pose (the voxel-map registration of the fine tracking stage).
 
 Seeds are ``100 * config + purpose`` (1 scene, 2 poses, 3 loss weights)
 unless a caller overrides them.  Every array is float32, C-contiguous.
@@ -35,7 +38,7 @@ import numpy as np
 __all__ = [
     "Camera", "GaussianSet", "AnchorSet", "Decoder", "Scene",
     "camera_look", "random_gaussians", "upstream_weights",
-    "make_c1", "make_c2", "make_c3", "make_c4", "make_c5", "make_config",
+    "make_c1", "make_c2", "make_c3", "make_c4", "make_c5", "make_config", "StreetScan", "make_street_scan",
     "tiny_scene",
 ]
 
@@ -376,6 +379,112 @@ def make_c5(seed: Optional[int] = None, n_per: int = 1_500_000, submaps: int = 4
     if weights:
         sc.weights = upstream_weights(503 if seed is None else seed + 2, cams)
     return sc
+
+
+@dataclasses.dataclass
+class StreetScan:
+    """A voxel-map registration case: map points on a street's surfaces, one
+    LiDAR sweep of the same street in the sensor frame, the sensor's true
+    pose and a perturbed initial guess (sensor-to-world [R | t], float64)."""
+    map_points: np.ndarray  # (n, 3) float32, world frame
+    scan: np.ndarray        # (m, 3) float32, sensor frame
+    pose_gt: np.ndarray     # (3, 4)
+    pose_init: np.ndarray   # (3, 4)
+    voxel: float
+
+
+def _street_boxes(rng, length, half_width, count):
+    """Axis-aligned boxes standing on the ground: parked cars, poles, kiosks."""
+    kinds = np.array([[4.5, 1.8, 1.5], [0.3, 0.3, 4.0], [2.0, 2.0, 2.5]])
+    k = rng.integers(0, 3, count)
+    size = kinds[k] * rng.uniform(0.8, 1.2, (count, 3))
+    ctr = np.stack([rng.uniform(0.0, length, count), rng.uniform(-half_width + 1.5, half_width - 1.5, count),
+                    np.zeros(count)], axis=1)
+    lo = ctr - 0.5 * size * np.array([1, 1, 0])
+    hi = lo + size
+    return lo, hi
+
+
+def _street_surfaces(length, half_width, height, lo, hi):
+    """Rectangles (origin, e1, e2) of the ground, both facades and the
+    visible faces (top and four sides) of every box."""
+    rects = [(np.array([0.0, -half_width, 0.0]), np.array([length, 0, 0.]), np.array([0, 2 * half_width, 0.])),
+             (np.array([0.0, -half_width, 0.0]), np.array([length, 0, 0.]), np.array([0, 0, height])),
+             (np.array([0.0, half_width, 0.0]), np.array([length, 0, 0.]), np.array([0, 0, height]))]
+    for a, b in zip(lo, hi):
+        d = b - a
+        ex, ey, ez = np.array([d[0], 0, 0]), np.array([0, d[1], 0]), np.array([0, 0, d[2]])
+        rects += [(a + ez, ex, ey), (a, ex, ez), (a + ey, ex, ez), (a, ey, ez), (a + ex, ey, ez)]
+    return rects
+
+
+def _cast_street(origin, dirs, length, half_width, height, lo, hi, max_range):
+    """Ray parameter of the first hit of each unit direction with the
+    street (ground z = 0, facades y = +-half_width up to height, boxes),
+    restricted to 0 <= x <= length; inf for a miss."""
+    t_best = np.full(dirs.shape[0], np.inf)
+
+    def keep(t):
+        p = origin + t[:, None] * dirs
+        ok = (t > 0.1) & (t <= max_range) & (p[:, 0] >= 0) & (p[:, 0] <= length)
+        return np.where(ok, t, np.inf), p
+
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t, p = keep(-origin[2] / dirs[:, 2])
+        t = np.where(np.abs(p[:, 1]) <= half_width, t, np.inf)
+        t_best = np.minimum(t_best, t)
+        for side in (-half_width, half_width):
+            t, p = keep((side - origin[1]) / dirs[:, 1])
+            t = np.where((p[:, 2] >= 0) & (p[:, 2] <= height), t, np.inf)
+            t_best = np.minimum(t_best, t)
+        inv = 1.0 / dirs
+        for a, b in zip(lo, hi):  # slab test
+            t0 = (a - origin) * inv
+            t1 = (b - origin) * inv
+            tn = np.max(np.minimum(t0, t1), axis=1)
+            tf = np.min(np.maximum(t0, t1), axis=1)
+            hit = (tf >= tn) & (tn > 0.1) & (tn <= max_range)
+            t_best = np.where(hit & (tn < t_best), tn, t_best)
+    return t_best
+
+
+def make_street_scan(seed: Optional[int] = None, n_map: int = 1_500_000, beams: int = 64, azimuths: int = 2048,
+                     length: float = 80.0, voxel: float = 1.0, noise: float = 0.02,
+                     init_error=(0.5, 0.3, 0.05, 2.0)) -> StreetScan:
+    """Frame-to-map registration on a street (the outdoor fine-tracking case).
+
+    The map is n_map points drawn area-weighted on the ground (16 m wide),
+    two facades (15 m high) and 50 boxes (cars, poles, kiosks) of an 80 m
+    street, with normal noise 0.02 m: the means of a submap's Gaussians.
+    The scan is one sweep of a 64-beam LiDAR (elevations -24.8..+2 deg,
+    2048 azimuths, 80 m range, range noise 0.02 m) from a sensor 1.8 m above
+    the road at x in [30, 50], in the sensor frame.  The initial guess is the
+    true pose moved by init_error = (dx, dy, dz metres, yaw degrees).
+    """
+    rng = np.random.default_rng(601 if seed is None else seed)
+    half_width, height = 8.0, 15.0
+    lo, hi = _street_boxes(rng, length, half_width, 50)
+    pts = _sample_patches(rng, _street_surfaces(length, half_width, height, lo, hi), n_map)
+    pts += rng.normal(0.0, noise, pts.shape)
+    prng = np.random.default_rng(602 if seed is None else seed + 1)
+    pos = np.array([prng.uniform(30.0, 50.0), prng.uniform(-3.0, 3.0), 1.8])
+    yaw = prng.uniform(-0.3, 0.3)
+    R = _rot_axis(np.array([0.0, 0.0, 1.0]), yaw)
+    el = np.radians(np.linspace(-24.8, 2.0, beams))
+    az = np.linspace(-math.pi, math.pi, azimuths, endpoint=False)
+    E, A = np.meshgrid(el, az, indexing="ij")
+    d_sensor = np.stack([np.cos(E) * np.cos(A), np.cos(E) * np.sin(A), np.sin(E)], axis=-1).reshape(-1, 3)
+    d_world = d_sensor @ R.T
+    t = _cast_street(pos, d_world, length, half_width, height, lo, hi, 80.0)
+    hit = np.isfinite(t)
+    r = t[hit] + prng.normal(0.0, noise, int(hit.sum()))
+    scan = d_sensor[hit] * r[:, None]
+    gt = np.concatenate([R, pos[:, None]], axis=1)
+    dx, dy, dz, dyaw = init_error
+    Ri = _rot_axis(np.array([0.0, 0.0, 1.0]), yaw + math.radians(dyaw))
+    init = np.concatenate([Ri, (pos + np.array([dx, dy, dz]))[:, None]], axis=1)
+    f = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    return StreetScan(f(pts), f(scan), gt, init, voxel)
 
 
 def make_config(i: int, **kw) -> Scene:
