@@ -251,12 +251,13 @@ int vpgs_window_destroy(vpgs_window* win);
  * ranges, forward compositing, backward compositing, projection backward,
  * pose reduction, fills, decode forward, decode backward, depth ordering of
  * the visible records, mapping loss, volume loss, anchor statistics,
- * expansion sampling, distillation loss).  vpgs_profile_read
+ * expansion sampling, distillation loss, voxel map and downsampling,
+ * registration).  vpgs_profile_read
  * synchronises on the recorded events and returns, for stage index `stage`
  * (0 <= stage < VPGS_NUM_STAGES), its name, the number of recorded launches
  * and their summed duration in milliseconds since the last enable.  Disabled
  * by default; enabling resets the totals. */
-#define VPGS_NUM_STAGES 18
+#define VPGS_NUM_STAGES 20
 int vpgs_profile_enable(vpgs_ctx* ctx, int on);
 int vpgs_profile_read(vpgs_ctx* ctx, int stage, const char** name, int64_t* calls, double* total_ms);
 
@@ -447,6 +448,83 @@ int vpgs_expansion_sample(vpgs_ctx* ctx, int n_views, const vpgs_camera* cams, c
 int vpgs_distill_loss(vpgs_ctx* ctx, int m, const vpgs_camera* cams, const vpgs_images* rend_a,
                       const vpgs_images* rend_b, float* terms, float* loss, const vpgs_images* grad_a,
                       const vpgs_images* grad_b, void* stream);
+
+/* ---- voxel map and frame-to-map registration (Section III-B, eq. 10-12) --- */
+
+/* Voxels: point p lies in voxel floor(p / voxel), per axis, the division in
+ * FP32; coordinates must satisfy |p / voxel| < 2^20.  A voxel map holds, for
+ * every occupied voxel, its first max_per_voxel points by index (a copy, so
+ * the input may be freed once the stream has passed the build).  Lookups go
+ * through a hash table over the occupied voxels. */
+typedef struct vpgs_voxel_map vpgs_voxel_map;
+
+/* Builds the map of n points (device [n,3] floats, n < 2^31) asynchronously
+ * on `stream`.  Release with vpgs_voxel_map_destroy. */
+int vpgs_voxel_map_create(vpgs_ctx* ctx, const float* points, int64_t n, float voxel, int32_t max_per_voxel,
+                          vpgs_voxel_map** map, void* stream);
+/* Synchronises `stream` and reports the points given and the occupied voxels. */
+int vpgs_voxel_map_info(vpgs_voxel_map* map, int64_t* n_points, int64_t* n_voxels, void* stream);
+int vpgs_voxel_map_destroy(vpgs_voxel_map* map);
+
+/* Downsampling that keeps one original point per voxel: the first one by
+ * index.  out_idx (device int32 [n]) receives the kept indices in ascending
+ * order, *out_count (device int32) their number.  The fine tracking stage
+ * downsamples a scan twice (two voxel sizes). */
+int vpgs_voxel_downsample(vpgs_ctx* ctx, const float* points, int64_t n, float voxel, int32_t* out_idx,
+                          int32_t* out_count, void* stream);
+
+/* Correspondences of n source points (device [n,3]) under pose (host 3x4
+ * row-major [R | t], float64, rounded to FP32 for the transform): s = R p + t
+ * in FP32 as ((R00 p_x + R01 p_y) + R02 p_z) + t_x, with no fused products;
+ * the nearest stored point among the 27 voxels around the voxel of s, by
+ * FP32 squared distance ((dx dx + dy dy) + dz dz), ties to the lower index.
+ * nn[i] (device int32, may be NULL) = its original index if d^2 < tau^2
+ * (FP32), else -1; d2[i] (device float, may be NULL) = its d^2 (+inf when
+ * no neighbouring voxel has points). */
+int vpgs_icp_correspond(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* src, int64_t n, const double* pose,
+                        float tau, int32_t* nn, float* d2, void* stream);
+
+/* Gauss-Newton terms of the robust registration cost of eq. 11 at pose, over
+ * the correspondences above: with r = s - m, e^2 = |r|^2 and the
+ * Geman-McClure kernel of eq. 12, rho(e) = (e^2 / 2) / (kappa + e^2), kappa =
+ * sigma / 3, the weight w = rho'(e) / e = kappa / (kappa + e^2)^2 and
+ * J = [I, -[s]x] (left increment xi = (rho, phi)):
+ *   terms[0..20]  H = sum w J^T J, upper triangle row by row
+ *   terms[21..26] g = sum w J^T r
+ *   terms[27]     number of correspondences, terms[28] sum rho(e)
+ * terms: device, 29 doubles. */
+int vpgs_icp_linearize(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* src, int64_t n, const double* pose,
+                       float tau, float sigma, double* terms, void* stream);
+
+typedef struct {
+  float tau;              /* correspondence threshold (map units) */
+  float sigma;            /* kernel scale sigma_t of eq. 12 (kappa = sigma / 3) */
+  int32_t max_iterations; /* Gauss-Newton steps at most (>= 0) */
+  int32_t reserved;
+  double eps;             /* stop once |dx| < eps */
+} vpgs_icp_opts;
+
+typedef struct {
+  int32_t iterations;     /* steps taken */
+  int32_t converged;      /* 1 if the last step was below eps */
+  int32_t count;          /* correspondences of the last linearisation */
+  int32_t degenerate;     /* 1 if it stopped on fewer than 6 correspondences or a singular system */
+  float rho;              /* sum rho(e) of the last linearisation */
+  int32_t reserved;
+} vpgs_icp_result;
+
+/* Frame-to-map registration of a scan (device [n,3], sensor frame): the
+ * initial pose is prev_pose * pred_pose (eq. 10: the previous pose and the
+ * predicted relative motion, host 3x4 float64; pred_pose may be NULL), then
+ * Gauss-Newton steps H dx = -g (FP64 Cholesky on the device) with
+ * T <- Exp(dx) T (SE(3) exponential), until |dx| < eps or max_iterations, or a
+ * degenerate system.  The pose stays on the device between steps; the host
+ * checks the stop flag every four steps.  Synchronous: returns the final
+ * pose (pose_out, host 3x4 float64) and, if result is non-NULL, the
+ * counters. */
+int vpgs_icp_register(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* src, int64_t n,
+                      const double* prev_pose, const double* pred_pose, const vpgs_icp_opts* opts, double* pose_out,
+                      vpgs_icp_result* result, void* stream);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,7 @@ VPGS_ECAPACITY = -4
 VPGS_EUNSUPPORTED = -5
 MAX_VIEWS = 64
 MAX_SETS = 64
-NUM_STAGES = 18
+NUM_STAGES = 20
 WINDOW_FORWARD, WINDOW_BACKWARD = 1, 2
 
 BUF_PROJ, BUF_EXTENT, BUF_COUNT, BUF_KEYS, BUF_VALUES, BUF_RANGES, BUF_TFINAL, BUF_NCONTRIB = range(1, 9)
@@ -106,6 +106,16 @@ class ExpandOut(ctypes.Structure):
     _fields_ = [("mask", c_void_p), ("pixel", c_void_p), ("points", c_void_p), ("colors", c_void_p)]
 
 
+class IcpOpts(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_float), ("sigma", ctypes.c_float), ("max_iterations", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("eps", ctypes.c_double)]
+
+
+class IcpResult(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("count", ctypes.c_int32),
+                ("degenerate", ctypes.c_int32), ("rho", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
 # every entry point of include/vpgs.h, with its ctypes signature
 SIGNATURES = {
     "vpgs_create": (ctypes.c_int, [ctypes.POINTER(c_void_p), ctypes.c_int]),
@@ -158,6 +168,23 @@ SIGNATURES = {
     "vpgs_distill_loss": (ctypes.c_int, [c_void_p, ctypes.c_int, ctypes.POINTER(Camera), ctypes.POINTER(Images),
                                          ctypes.POINTER(Images), c_void_p, c_void_p, ctypes.POINTER(Images),
                                          ctypes.POINTER(Images), c_void_p]),
+    "vpgs_voxel_map_create": (ctypes.c_int, [c_void_p, c_void_p, ctypes.c_int64, ctypes.c_float, ctypes.c_int32,
+                                             ctypes.POINTER(c_void_p), c_void_p]),
+    "vpgs_voxel_map_info": (ctypes.c_int, [c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                           c_void_p]),
+    "vpgs_voxel_map_destroy": (ctypes.c_int, [c_void_p]),
+    "vpgs_voxel_downsample": (ctypes.c_int, [c_void_p, c_void_p, ctypes.c_int64, ctypes.c_float, c_void_p, c_void_p,
+                                             c_void_p]),
+    "vpgs_icp_correspond": (ctypes.c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_int64,
+                                           ctypes.POINTER(ctypes.c_double), ctypes.c_float, c_void_p, c_void_p,
+                                           c_void_p]),
+    "vpgs_icp_linearize": (ctypes.c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_int64,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_float, ctypes.c_float, c_void_p,
+                                          c_void_p]),
+    "vpgs_icp_register": (ctypes.c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(IcpOpts), ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(IcpResult), c_void_p]),
 }
 
 _LIB = None

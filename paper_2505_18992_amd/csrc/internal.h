@@ -171,6 +171,14 @@ hipError_t launch_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint3
                        uint32_t capacity, int key_bits, const Counters* cnt, void* ws, int* result_in_alt,
                        hipStream_t s);
 
+// Stable LSD radix sort of (key, value) over key bits [0, key_bits) for the
+// first min(*n_dev, capacity) entries; the result is in the alt buffers iff
+// *result_in_alt.  The last pass also writes gather_dst[i] =
+// gather_src[value of sorted entry i] when both are non-NULL.
+hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, uint32_t capacity,
+                             int key_bits, const uint32_t* n_dev, void* ws, int* result_in_alt, hipStream_t s,
+                             const uint32_t* gather_src, uint32_t* gather_dst);
+
 hipError_t launch_ranges(const uint32_t* tiles, const Counters* cnt, uint32_t capacity, uint2* ranges,
                          uint32_t n_tiles, hipStream_t s);
 // The compositing order of the tiles: order[i] is the tile the i-th

@@ -21,7 +21,7 @@ namespace vpgs {
 const char* const kStageNames[VPGS_NUM_STAGES] = {
     "project", "scan", "emit", "sort", "ranges", "composite_forward", "composite_backward",
     "project_backward", "pose_reduce", "fill", "decode_forward", "decode_backward", "depth_order",
-    "mapping_loss", "volume_loss", "anchor_stats", "expansion", "distillation"};
+    "mapping_loss", "volume_loss", "anchor_stats", "expansion", "distillation", "voxel_map", "icp"};
 
 int fail(vpgs_ctx* ctx, int code, const char* fmt, ...) {
   if (ctx) {
@@ -551,6 +551,8 @@ int vpgs_destroy(vpgs_ctx* ctx) {
   free_buf(ctx->expand_mask);
   free_buf(ctx->expand_blocks);
   free_buf(ctx->distill_ws);
+  free_buf(ctx->icp_build);
+  free_buf(ctx->icp_ws);
   if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
   delete ctx;
   return VPGS_OK;

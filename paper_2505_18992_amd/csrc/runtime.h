@@ -19,7 +19,8 @@ struct DevBuf {
 };
 
 enum Stage { ST_PROJECT, ST_SCAN, ST_EMIT, ST_SORT, ST_RANGES, ST_FWD, ST_BWD, ST_PROJ_BWD, ST_POSE, ST_FILL,
-             ST_DEC_FWD, ST_DEC_BWD, ST_DEPTH, ST_LOSS, ST_VOLUME, ST_ANCHOR, ST_EXPAND, ST_DISTILL };
+             ST_DEC_FWD, ST_DEC_BWD, ST_DEPTH, ST_LOSS, ST_VOLUME, ST_ANCHOR, ST_EXPAND, ST_DISTILL, ST_VOXEL,
+             ST_ICP };
 extern const char* const kStageNames[VPGS_NUM_STAGES];
 
 }  // namespace vpgs
@@ -54,6 +55,9 @@ struct vpgs_ctx {
   vpgs::DevBuf expand_mask, expand_blocks;
   // distillation loss: FP64 partial sums per keyframe
   vpgs::DevBuf distill_ws;
+  // registration: temporaries of voxel-map builds and downsampling; the
+  // per-iteration partial sums and state
+  vpgs::DevBuf icp_build, icp_ws;
   // stage timing
   bool profiling = false;
   std::vector<hipEvent_t> ev_free;

@@ -420,6 +420,13 @@ hipError_t launch_emit(const CallTables* d_tab, const CallTables& h, const ProjB
   return hipGetLastError();
 }
 
+hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, uint32_t capacity,
+                             int key_bits, const uint32_t* n_dev, void* ws, int* result_in_alt, hipStream_t s,
+                             const uint32_t* gather_src, uint32_t* gather_dst) {
+  return radix_sort<uint32_t>(keys, vals, keys_alt, vals_alt, capacity, key_bits, n_dev, ws, result_in_alt, s,
+                              gather_src, gather_dst);
+}
+
 hipError_t launch_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, uint32_t capacity,
                        int key_bits, const Counters* cnt, void* ws, int* result_in_alt, hipStream_t s) {
   return radix_sort<uint32_t>(keys, vals, keys_alt, vals_alt, capacity, key_bits, &cnt->pairs, ws, result_in_alt, s);
