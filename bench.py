@@ -325,6 +325,67 @@ def time_distillation(steps, m=4):
                             "frac": gbs / HBM_PEAK_GBS}}
 
 
+def time_registration(steps, voxel=1.0, cap=20, tau=3.0, sigma=1.0):
+    """Frame-to-map registration (eq. 10-12) on the street LiDAR case: the
+    voxel map of 1.5 M map points, then per frame the double downsampling of
+    the 131 k-point sweep (0.5 and 1.5 voxels) and the Gauss-Newton
+    registration from the perturbed pose; and the same registration on the
+    whole sweep (every point a source point)."""
+    import numpy as np
+    import torch
+    import scenes
+    from paper_2505_18992_amd import VoxelMap, get_context, icp_register, voxel_downsample
+    ctx = get_context(0)
+    sc = scenes.make_street_scan()
+    pts = torch.from_numpy(sc.map_points).cuda()
+    scan = torch.from_numpy(sc.scan).cuda()
+    VoxelMap(pts, voxel, cap).close()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    vm = VoxelMap(pts, voxel, cap)
+    torch.cuda.synchronize()
+    ms_build = ctx.profile_read()["voxel_map"][1]
+    ctx.profile(False)
+    n_vox = vm.info()[1]
+
+    def frame():
+        a = voxel_downsample(scan, 0.5 * voxel)
+        s1 = scan[a].contiguous()
+        b = voxel_downsample(s1, 1.5 * voxel)
+        src = s1[b].contiguous()
+        return icp_register(vm, src, sc.pose_init, None, tau, sigma, 100, 1e-4), src.shape[0]
+    frame()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        (pose, res), n_src = frame()
+    ms_frame = (time.perf_counter() - t0) * 1e3 / steps
+    err_t = float(np.abs(pose[:, 3] - sc.pose_gt[:, 3]).max())
+    # the whole sweep as the source
+    icp_register(vm, scan, sc.pose_init, None, tau, sigma, 100, 1e-4)
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(max(2, steps // 4)):
+        dpose, dres = icp_register(vm, scan, sc.pose_init, None, tau, sigma, 100, 1e-4)
+    ms_dense = (time.perf_counter() - t0) * 1e3 / max(2, steps // 4)
+    calls, icp_ms = ctx.profile_read()["icp"]
+    ctx.profile(False)
+    vm.close()
+    ms_iter = icp_ms / max(calls, 1) / max(dres["iterations"], 1)
+    log(f"[bench] registration: map build {ms_build:.3f} ms ({sc.map_points.shape[0]} points, {n_vox} voxels); "
+        f"frame {ms_frame:.3f} ms ({n_src} source points, {res['iterations']} steps, |dt| {err_t:.3f} m); "
+        f"whole sweep {ms_dense:.3f} ms ({scan.shape[0]} points, {dres['iterations']} steps, "
+        f"{ms_iter:.3f} ms per step)")
+    return {"map_points": int(sc.map_points.shape[0]), "voxels": int(n_vox), "voxel": voxel,
+            "max_per_voxel": cap, "map_build_ms": ms_build,
+            "frame": {"ms": ms_frame, "scan_points": int(scan.shape[0]), "source_points": int(n_src),
+                      "iterations": res["iterations"], "converged": res["converged"],
+                      "translation_error_m": err_t},
+            "whole_sweep": {"ms": ms_dense, "source_points": int(scan.shape[0]), "iterations": dres["iterations"],
+                            "ms_per_iteration": ms_iter,
+                            "queries_per_sec": scan.shape[0] / (ms_iter * 1e-3)}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -440,6 +501,8 @@ def main():
     expansion = time_expansion(sets, gw, cams, vset, cfg, win, args.steps)
     # submap fusion (eq. 14) on two street submaps
     distillation = time_distillation(args.steps)
+    # frame-to-map registration (eq. 10-12) on a street LiDAR sweep
+    registration = time_registration(args.steps)
 
     E, B, P = st["n_evaluated"], st["n_blended"], st["n_pairs"]
     dom = max(stage_ms, key=stage_ms.get)
@@ -487,6 +550,7 @@ def main():
         "mapping_loss": loss_stage,
         "expansion": expansion,
         "distillation": distillation,
+        "registration": registration,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

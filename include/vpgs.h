@@ -519,7 +519,7 @@ typedef struct {
  * Gauss-Newton steps H dx = -g (FP64 Cholesky on the device) with
  * T <- Exp(dx) T (SE(3) exponential), until |dx| < eps or max_iterations, or a
  * degenerate system.  The pose stays on the device between steps; the host
- * checks the stop flag every four steps.  Synchronous: returns the final
+ * checks the stop flag every eight steps.  Synchronous: returns the final
  * pose (pose_out, host 3x4 float64) and, if result is non-NULL, the
  * counters. */
 int vpgs_icp_register(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* src, int64_t n,

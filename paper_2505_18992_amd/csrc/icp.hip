@@ -15,7 +15,8 @@
 // its points (atomicMin); a point is kept iff it is that minimum, and the
 // kept indices are compacted in index order.
 //
-// Registration: one thread per source point transforms it (FP32, fixed
+// Registration: a group of lanes per source point (32 for a few thousand
+// points, down to one for hundreds of thousands) transforms it (FP32, fixed
 // order, no contraction), searches the 27 voxels around it for the nearest
 // stored point (squared distance in FP32, ties to the lower index), keeps it
 // if d^2 < tau^2, and adds its Geman-McClure-weighted Gauss-Newton terms
@@ -30,6 +31,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "runtime.h"
 
@@ -40,7 +42,7 @@ constexpr uint64_t kEmpty = ~0ull;
 constexpr int kVoxBias = 1 << 20;
 constexpr int kIcpBlock = 256;
 constexpr int kTerms = 29;  // 21 of H (upper triangle, row-major), 6 of g, count, sum rho
-constexpr int kItersPerCheck = 4;
+constexpr int kItersPerCheck = 8;
 
 struct MapView {
   const float4* pts;       // sorted points (x, y, z, index bits)
@@ -188,33 +190,51 @@ struct IcpState {
   float pad2;
 };
 
-// Nearest stored point of q among the 27 voxels around it: (index, d^2),
-// index -1 and d^2 = +inf when no voxel has points.
-__device__ __forceinline__ void nearest(const MapView& M, float qx, float qy, float qz, int32_t& bi, float& bd,
-                                        float4& bm) {
+// Nearest stored point of q among the 27 voxels around it, searched by a
+// group of G lanes (lane l takes voxels l, l + G, ..., and each voxel's
+// <= max_per_voxel points in order) and reduced across the group by the
+// total order (d^2, index).  Every lane of the group returns the result: d^2
+// (+inf if no voxel has points), the original index (-1) and the sorted
+// position.  Few queries use wide groups (latency), many use narrow ones.
+template <int G>
+__device__ __forceinline__ void group_nearest(const MapView& M, float qx, float qy, float qz, int lane, float& bd,
+                                              int32_t& bi, uint32_t& bp) {
 #pragma clang fp contract(off)
-  const int cx = voxel_coord(qx, M.voxel), cy = voxel_coord(qy, M.voxel), cz = voxel_coord(qz, M.voxel);
-  bi = -1;
   bd = __builtin_inff();
-  bm = make_float4(0.f, 0.f, 0.f, 0.f);
-  for (int a = -1; a <= 1; ++a)
-    for (int b = -1; b <= 1; ++b)
-      for (int c = -1; c <= 1; ++c) {
-        const int s = find_slot(M.keys, M.mask, pack_key(cx + a, cy + b, cz + c));
-        if (s < 0) continue;
-        const uint2 run = M.vals[s];
-        for (uint32_t j = 0; j < run.y; ++j) {
-          const float4 m = M.pts[run.x + j];
-          const float dx = qx - m.x, dy = qy - m.y, dz = qz - m.z;
-          const float d2 = (dx * dx + dy * dy) + dz * dz;
-          const int32_t id = (int32_t)__float_as_uint(m.w);
-          if (d2 < bd || (d2 == bd && id < bi)) {
-            bd = d2;
-            bi = id;
-            bm = m;
-          }
+  bi = -1;
+  bp = 0;
+  const int vx = voxel_coord(qx, M.voxel), vy = voxel_coord(qy, M.voxel), vz = voxel_coord(qz, M.voxel);
+  for (int nb = lane; nb < 27; nb += G) {
+    const int cx = vx + nb / 9 - 1;
+    const int cy = vy + (nb / 3) % 3 - 1;
+    const int cz = vz + nb % 3 - 1;
+    const int s = find_slot(M.keys, M.mask, pack_key(cx, cy, cz));
+    if (s >= 0) {
+      const uint2 run = M.vals[s];
+      for (uint32_t j = 0; j < run.y; ++j) {
+        const float4 m = M.pts[run.x + j];
+        const float dx = qx - m.x, dy = qy - m.y, dz = qz - m.z;
+        const float d2 = (dx * dx + dy * dy) + dz * dz;
+        const int32_t id = (int32_t)__float_as_uint(m.w);
+        if (d2 < bd || (d2 == bd && id < bi)) {
+          bd = d2;
+          bi = id;
+          bp = run.x + j;
         }
       }
+    }
+  }
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) {
+    const float od = __shfl_xor(bd, off, G);
+    const int32_t oi = __shfl_xor(bi, off, G);
+    const uint32_t op = __shfl_xor(bp, off, G);
+    // an empty lane carries (+inf, -1): it loses to any point
+    const bool take = od < bd || (od == bd && oi >= 0 && (bi < 0 || oi < bi));
+    bd = take ? od : bd;
+    bi = take ? oi : bi;
+    bp = take ? op : bp;
+  }
 }
 
 __device__ __forceinline__ float3 transform(const Pose32& P, float x, float y, float z) {
@@ -226,18 +246,22 @@ __device__ __forceinline__ float3 transform(const Pose32& P, float x, float y, f
   return q;
 }
 
+template <int G>
 __global__ void __launch_bounds__(kIcpBlock) correspond_kernel(MapView M, const float* __restrict__ src, uint32_t n,
                                                                Pose32 P, float tau2, int32_t* __restrict__ nn,
                                                                float* __restrict__ d2out) {
-  const uint32_t i = blockIdx.x * kIcpBlock + threadIdx.x;
+  const uint32_t i = blockIdx.x * (kIcpBlock / G) + threadIdx.x / G;  // uniform over the group
+  const int lane = threadIdx.x % G;
   if (i >= n) return;
   const float3 q = transform(P, src[3 * (size_t)i], src[3 * (size_t)i + 1], src[3 * (size_t)i + 2]);
-  int32_t bi;
   float bd;
-  float4 bm;
-  nearest(M, q.x, q.y, q.z, bi, bd, bm);
-  if (nn) nn[i] = bd < tau2 ? bi : -1;
-  if (d2out) d2out[i] = bd;
+  int32_t bi;
+  uint32_t bp;
+  group_nearest<G>(M, q.x, q.y, q.z, lane, bd, bi, bp);
+  if (lane == 0) {
+    if (nn) nn[i] = bd < tau2 ? bi : -1;
+    if (d2out) d2out[i] = bd;
+  }
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -246,28 +270,34 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-// Gauss-Newton terms of the accepted correspondences, summed per workgroup
-// into partials[blockIdx.x][kTerms].  With st non-NULL the pose is read from
-// it and the pass is skipped once the registration has stopped.
+// Gauss-Newton terms of the accepted correspondences.  Each lane group
+// takes queries group, group + total groups, ... and its lane 0 accumulates
+// their terms; the workgroup sum goes to partials[blockIdx.x][kTerms].
+// With st non-NULL the pose is read from it and the pass is skipped once the
+// registration has stopped.
+template <int G>
 __global__ void __launch_bounds__(kIcpBlock) linearize_kernel(MapView M, const float* __restrict__ src, uint32_t n,
                                                               Pose32 P, const IcpState* __restrict__ st, float tau2,
                                                               float kappa, float* __restrict__ partials) {
+#pragma clang fp contract(off)
   __shared__ float red[kIcpBlock / 64][kTerms];
   if (st != nullptr) {
     if (st->done) return;  // uniform over the grid
     P = st->p32;
   }
-  const uint32_t i = blockIdx.x * kIcpBlock + threadIdx.x;
+  const int lane = threadIdx.x % G;
   float t[kTerms];
 #pragma unroll
   for (int k = 0; k < kTerms; ++k) t[k] = 0.f;
-  if (i < n) {
+  const uint32_t stride = gridDim.x * (kIcpBlock / G);
+  for (uint32_t i = blockIdx.x * (kIcpBlock / G) + threadIdx.x / G; i < n; i += stride) {
     const float3 q = transform(P, src[3 * (size_t)i], src[3 * (size_t)i + 1], src[3 * (size_t)i + 2]);
-    int32_t bi;
     float bd;
-    float4 m;
-    nearest(M, q.x, q.y, q.z, bi, bd, m);
-    if (bd < tau2) {
+    int32_t bi;
+    uint32_t bp;
+    group_nearest<G>(M, q.x, q.y, q.z, lane, bd, bi, bp);
+    if (lane == 0 && bd < tau2) {
+      const float4 m = M.pts[bp];
       const float r[3] = {q.x - m.x, q.y - m.y, q.z - m.z};
       const float e2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
       const float den = kappa + e2;
@@ -279,11 +309,11 @@ __global__ void __launch_bounds__(kIcpBlock) linearize_kernel(MapView M, const f
 #pragma unroll
       for (int a = 0; a < 6; ++a)
 #pragma unroll
-        for (int b = a; b < 6; ++b) t[k++] = w * (J[0][a] * J[0][b] + J[1][a] * J[1][b] + J[2][a] * J[2][b]);
+        for (int b = a; b < 6; ++b) t[k++] += w * ((J[0][a] * J[0][b] + J[1][a] * J[1][b]) + J[2][a] * J[2][b]);
 #pragma unroll
-      for (int a = 0; a < 6; ++a) t[21 + a] = w * (J[0][a] * r[0] + J[1][a] * r[1] + J[2][a] * r[2]);
-      t[27] = 1.f;
-      t[28] = 0.5f * e2 / den;
+      for (int a = 0; a < 6; ++a) t[21 + a] += w * ((J[0][a] * r[0] + J[1][a] * r[1]) + J[2][a] * r[2]);
+      t[27] += 1.f;
+      t[28] += 0.5f * e2 / den;
     }
   }
 #pragma unroll
@@ -415,6 +445,32 @@ __global__ void solve_kernel(const float* __restrict__ partials, uint32_t nblock
 }
 
 inline uint32_t blocks_of(uint32_t n, uint32_t b) { return (n + b - 1) / b; }
+
+// Lanes per query: enough lane groups to fill the chip (about 512 k lanes)
+// when the queries are few, one lane per query when they are many.
+inline int group_lanes(uint32_t n) {
+  if (n <= 16384) return 32;
+  if (n <= 65536) return 8;
+  if (n <= 262144) return 4;
+  return 1;
+}
+
+// Workgroups of a linearisation pass: one lane group per query up to a cap
+// that bounds the partial sums the step adds up.
+constexpr uint32_t kMaxLinBlocks = 512;
+inline uint32_t linearize_blocks(uint32_t n) {
+  return std::max<uint32_t>(1, std::min(blocks_of(n, kIcpBlock / group_lanes(n)), kMaxLinBlocks));
+}
+
+template <class F>
+void with_group(uint32_t n, F&& f) {
+  switch (group_lanes(n)) {
+    case 32: f(std::integral_constant<int, 32>()); break;
+    case 8: f(std::integral_constant<int, 8>()); break;
+    case 4: f(std::integral_constant<int, 4>()); break;
+    default: f(std::integral_constant<int, 1>()); break;
+  }
+}
 
 uint32_t pow2_at_least(uint64_t x) {
   uint64_t c = 1;
@@ -638,8 +694,11 @@ int vpgs_icp_correspond(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* s
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(hipSetDevice(ctx->device));
   StageTimer timer(ctx, ST_ICP, st);
-  hipLaunchKernelGGL(correspond_kernel, dim3(blocks_of((uint32_t)n, kIcpBlock)), dim3(kIcpBlock), 0, st,
-                     view_of(map), src, (uint32_t)n, pose32_of(pose), tau * tau, nn, d2);
+  with_group((uint32_t)n, [&](auto g) {
+    constexpr int G = decltype(g)::value;
+    hipLaunchKernelGGL(correspond_kernel<G>, dim3(blocks_of((uint32_t)n, kIcpBlock / G)), dim3(kIcpBlock), 0, st,
+                       view_of(map), src, (uint32_t)n, pose32_of(pose), tau * tau, nn, d2);
+  });
   HIP_TRY(hipGetLastError());
   return VPGS_OK;
 }
@@ -656,12 +715,15 @@ int vpgs_icp_linearize(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* sr
     return fail(ctx, VPGS_EINVAL, "tau and sigma must be positive");
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(hipSetDevice(ctx->device));
-  const uint32_t nb = std::max<uint32_t>(1, blocks_of((uint32_t)n, kIcpBlock));
+  const uint32_t nb = linearize_blocks((uint32_t)n);
   if ((rc = ensure(ctx, ctx->icp_ws, (size_t)nb * kTerms * 4 + 512))) return rc;
   float* partials = static_cast<float*>(ctx->icp_ws.p);
   StageTimer timer(ctx, ST_ICP, st);
-  hipLaunchKernelGGL(linearize_kernel, dim3(nb), dim3(kIcpBlock), 0, st, view_of(map), src, (uint32_t)n,
-                     pose32_of(pose), (const IcpState*)nullptr, tau * tau, sigma / 3.0f, partials);
+  with_group((uint32_t)n, [&](auto g) {
+    constexpr int G = decltype(g)::value;
+    hipLaunchKernelGGL(linearize_kernel<G>, dim3(nb), dim3(kIcpBlock), 0, st, view_of(map), src, (uint32_t)n,
+                       pose32_of(pose), (const IcpState*)nullptr, tau * tau, sigma / 3.0f, partials);
+  });
   hipLaunchKernelGGL(reduce_terms_kernel, dim3(1), dim3(64), 0, st, partials, nb, terms);
   HIP_TRY(hipGetLastError());
   return VPGS_OK;
@@ -687,7 +749,7 @@ int vpgs_icp_register(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* src
   double init[12];
   if (pred_pose) compose(prev_pose, pred_pose, init);
   else std::memcpy(init, prev_pose, sizeof(init));
-  const uint32_t nb = std::max<uint32_t>(1, blocks_of((uint32_t)n, kIcpBlock));
+  const uint32_t nb = linearize_blocks((uint32_t)n);
   const size_t state_off = ((size_t)nb * kTerms * 4 + 255) / 256 * 256;
   if ((rc = ensure(ctx, ctx->icp_ws, state_off + sizeof(IcpState)))) return rc;
   float* partials = static_cast<float*>(ctx->icp_ws.p);
@@ -706,8 +768,11 @@ int vpgs_icp_register(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* src
   for (int it = 0; it < opts->max_iterations; it += kItersPerCheck) {
     const int k = std::min(kItersPerCheck, opts->max_iterations - it);
     for (int q = 0; q < k; ++q) {
-      hipLaunchKernelGGL(linearize_kernel, dim3(nb), dim3(kIcpBlock), 0, st, mv, src, (uint32_t)n, ignored,
-                         (const IcpState*)dst, tau * tau, sigma / 3.0f, partials);
+      with_group((uint32_t)n, [&](auto g) {
+        constexpr int G = decltype(g)::value;
+        hipLaunchKernelGGL(linearize_kernel<G>, dim3(nb), dim3(kIcpBlock), 0, st, mv, src, (uint32_t)n, ignored,
+                           (const IcpState*)dst, tau * tau, sigma / 3.0f, partials);
+      });
       hipLaunchKernelGGL(solve_kernel, dim3(1), dim3(64), 0, st, partials, nb, dst, opts->eps,
                          opts->max_iterations);
     }

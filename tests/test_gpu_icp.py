@@ -80,6 +80,26 @@ def test_map_and_correspondences_bit_exact(street):
     gm.close()
 
 
+def test_lane_group_widths_agree(street):
+    # few queries search a voxel per lane, many search all 27 in one lane:
+    # 20 k queries (8 lanes each) against the oracle; 131 k (4 lanes) and
+    # 392 k (1 lane) against the same queries taken 10 k at a time (32 lanes)
+    from paper_2505_18992_amd import VoxelMap, icp_correspond
+    sc, vm = street
+    print("case lane-group widths", flush=True)
+    gm = VoxelMap(_dev(sc.map_points), VOXEL, CAP)
+    rng = np.random.default_rng(5)
+    src = sc.scan[rng.choice(sc.scan.shape[0], 20000, replace=False)]
+    nn, d2 = icp_correspond(gm, _dev(src), sc.pose_init, TAU)
+    enn, ed2 = icp.correspond(vm, icp.transform32(src, sc.pose_init), TAU)
+    assert np.array_equal(nn.cpu().numpy(), enn) and np.array_equal(d2.cpu().numpy(), ed2)
+    for big in (sc.scan, np.concatenate([sc.scan, sc.scan + 0.01, sc.scan - 0.02])):
+        nn, d2 = icp_correspond(gm, _dev(big), sc.pose_init, TAU)
+        parts = [icp_correspond(gm, _dev(big[k:k + 10000]), sc.pose_init, TAU) for k in range(0, len(big), 10000)]
+        assert torch.equal(nn, torch.cat([p[0] for p in parts])) and torch.equal(d2, torch.cat([p[1] for p in parts]))
+    gm.close()
+
+
 def test_cap_and_empty_map():
     from paper_2505_18992_amd import VoxelMap, icp_correspond
     m = np.array([[0.1, 0.1, 0.1], [0.5, 0.5, 0.5], [0.9, 0.2, 0.3]], np.float32)
