@@ -49,11 +49,11 @@ SORT_BYTES_PER_PAIR_PASS = 20.0  # 32-bit keys and values: histogram read 4 B, s
 # those the traffic is reported as null until it is measured again.
 MEASURED_TRAFFIC = {
     ("composite_backward", 32, 8, 0): {
-        "sources_sha256": "1768689087d12b1bef222375b0505bc6f15b3856c90cd6b97191d21433194723",
-        "fetch_bytes": 1109690287, "write_bytes": 613763904},
+        "sources_sha256": "e7bc65a6eae4a6ef9fe083051e9cb92c0eecb882ffb7443d5c1c377978c78fc2",
+        "fetch_bytes": 1110107229, "write_bytes": 613763904},
     ("composite_forward", 32, 8, 0): {
-        "sources_sha256": "1768689087d12b1bef222375b0505bc6f15b3856c90cd6b97191d21433194723",
-        "fetch_bytes": 943196428, "write_bytes": 197190039},
+        "sources_sha256": "e7bc65a6eae4a6ef9fe083051e9cb92c0eecb882ffb7443d5c1c377978c78fc2",
+        "fetch_bytes": 1086265177, "write_bytes": 192990117},
 }
 TRAFFIC_SOURCES = ("paper_2505_18992_amd/csrc/composite.hip", "paper_2505_18992_amd/csrc/internal.h")
 
@@ -398,6 +398,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-one-view", action="store_true",
                     help="skip the one-view-per-launch comparison (profiling runs: it launches the same kernels)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mapping-loss, expansion, distillation and registration measurements "
+                         "(profiling runs of the step alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -494,15 +497,17 @@ def main():
         log(f"[bench] one view per launch: {ms_per_view_launch:.3f} ms for {nv} views; "
             f"eager window {ms_eager_window:.3f} ms")
 
-    # the mapping loss of eq. 7-8 on the same views (rendered frames against
-    # perturbed copies of themselves), timed on its own
-    loss_stage = time_mapping_loss(win, cams, args.steps)
-    # the submap-expansion statistics of Section III-A on the same workload
-    expansion = time_expansion(sets, gw, cams, vset, cfg, win, args.steps)
-    # submap fusion (eq. 14) on two street submaps
-    distillation = time_distillation(args.steps)
-    # frame-to-map registration (eq. 10-12) on a street LiDAR sweep
-    registration = time_registration(args.steps)
+    loss_stage = expansion = distillation = registration = None
+    if not args.no_extras:
+        # the mapping loss of eq. 7-8 on the same views (rendered frames
+        # against perturbed copies of themselves), timed on its own
+        loss_stage = time_mapping_loss(win, cams, args.steps)
+        # the submap-expansion statistics of Section III-A on the same workload
+        expansion = time_expansion(sets, gw, cams, vset, cfg, win, args.steps)
+        # submap fusion (eq. 14) on two street submaps
+        distillation = time_distillation(args.steps)
+        # frame-to-map registration (eq. 10-12) on a street LiDAR sweep
+        registration = time_registration(args.steps)
 
     E, B, P = st["n_evaluated"], st["n_blended"], st["n_pairs"]
     dom = max(stage_ms, key=stage_ms.get)

@@ -330,17 +330,43 @@ __global__ void __launch_bounds__(kIcpBlock) linearize_kernel(MapView M, const f
   }
 }
 
-// FP64 sums of the workgroup partials (fixed order: deterministic).
+// FP64 sums of the workgroup partials by one workgroup of kIcpBlock
+// threads: thread t adds the rows t, t + kIcpBlock, ... (each row one
+// contiguous run of kTerms floats), then the threads are summed by wavefront
+// shuffles and across the wavefronts in LDS.  The order is fixed, so the
+// sums are deterministic.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
 __device__ void sum_partials(const float* __restrict__ partials, uint32_t nblocks, double* tot) {
+  __shared__ double wred[kIcpBlock / 64][kTerms];
+  double acc[kTerms];
+#pragma unroll
+  for (int k = 0; k < kTerms; ++k) acc[k] = 0.0;
+  for (uint32_t b = threadIdx.x; b < nblocks; b += kIcpBlock) {
+    const float* row = partials + (size_t)b * kTerms;
+#pragma unroll
+    for (int k = 0; k < kTerms; ++k) acc[k] += (double)row[k];
+  }
+#pragma unroll
+  for (int k = 0; k < kTerms; ++k) {
+    const double v = wave_sum_f64(acc[k]);
+    if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6][k] = v;
+  }
+  __syncthreads();
   if (threadIdx.x < kTerms) {
     double s = 0.0;
-    for (uint32_t b = 0; b < nblocks; ++b) s += (double)partials[(size_t)b * kTerms + threadIdx.x];
+#pragma unroll
+    for (int w = 0; w < kIcpBlock / 64; ++w) s += wred[w][threadIdx.x];
     tot[threadIdx.x] = s;
   }
   __syncthreads();
 }
 
-__global__ void reduce_terms_kernel(const float* __restrict__ partials, uint32_t nblocks, double* __restrict__ out) {
+__global__ void __launch_bounds__(kIcpBlock) reduce_terms_kernel(const float* __restrict__ partials, uint32_t nblocks, double* __restrict__ out) {
   __shared__ double tot[kTerms];
   sum_partials(partials, nblocks, tot);
   if (threadIdx.x < kTerms) out[threadIdx.x] = tot[threadIdx.x];
@@ -378,7 +404,7 @@ __device__ void round_pose(const double T[12], Pose32& p) {
 }
 
 // One Gauss-Newton step from the summed terms (single workgroup).
-__global__ void solve_kernel(const float* __restrict__ partials, uint32_t nblocks, IcpState* __restrict__ st,
+__global__ void __launch_bounds__(kIcpBlock) solve_kernel(const float* __restrict__ partials, uint32_t nblocks, IcpState* __restrict__ st,
                              double eps, int32_t max_iter) {
   __shared__ double tot[kTerms];
   if (st->done) return;
@@ -724,7 +750,7 @@ int vpgs_icp_linearize(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* sr
     hipLaunchKernelGGL(linearize_kernel<G>, dim3(nb), dim3(kIcpBlock), 0, st, view_of(map), src, (uint32_t)n,
                        pose32_of(pose), (const IcpState*)nullptr, tau * tau, sigma / 3.0f, partials);
   });
-  hipLaunchKernelGGL(reduce_terms_kernel, dim3(1), dim3(64), 0, st, partials, nb, terms);
+  hipLaunchKernelGGL(reduce_terms_kernel, dim3(1), dim3(kIcpBlock), 0, st, partials, nb, terms);
   HIP_TRY(hipGetLastError());
   return VPGS_OK;
 }
@@ -773,7 +799,7 @@ int vpgs_icp_register(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* src
         hipLaunchKernelGGL(linearize_kernel<G>, dim3(nb), dim3(kIcpBlock), 0, st, mv, src, (uint32_t)n, ignored,
                            (const IcpState*)dst, tau * tau, sigma / 3.0f, partials);
       });
-      hipLaunchKernelGGL(solve_kernel, dim3(1), dim3(64), 0, st, partials, nb, dst, opts->eps,
+      hipLaunchKernelGGL(solve_kernel, dim3(1), dim3(kIcpBlock), 0, st, partials, nb, dst, opts->eps,
                          opts->max_iterations);
     }
     HIP_TRY(hipGetLastError());
