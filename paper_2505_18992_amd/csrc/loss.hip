@@ -18,8 +18,9 @@
 // stencil kernels per view: the first filters the five statistics and
 // writes S's partials (and block sums of the loss terms), the second
 // filters the partials and writes the gradient planes.  Both stage a
-// 32x16-pixel tile plus a 5-pixel halo in LDS and filter it separably.  One
-// launch of each covers up to 16 views.
+// 32x16-pixel tile plus a 5-pixel halo in LDS and filter it separably, each
+// thread filtering a run of adjacent outputs from registers (4 along a row,
+// 2 down a column).  One launch of each covers up to 16 views.
 #include <algorithm>
 #include <cmath>
 
@@ -32,6 +33,9 @@ constexpr int kTileW = 32, kTileH = 16;
 constexpr int kRad = 5, kTaps = 2 * kRad + 1;
 constexpr int kHaloW = kTileW + 2 * kRad, kHaloH = kTileH + 2 * kRad;  // 42 x 26
 constexpr int kLossBlock = 256;
+constexpr int kHRun = 4;  // horizontal outputs per thread (kHaloH * kTileW / kHRun <= kLossBlock)
+constexpr int kVRun = 2;  // vertical outputs per thread (kTileW * kTileH / kVRun == kLossBlock)
+static_assert(kHaloH * (kTileW / kHRun) <= kLossBlock && kTileW * kTileH / kVRun == kLossBlock, "filter runs");
 constexpr float kC1 = 0.0001f, kC2 = 0.0009f;
 constexpr int kSumSlots = 64;   // block sums are spread over slots per view
 constexpr int kSums = 4;        // sum S, sum |X - Y|, sum valid |D - T|, valid count
@@ -108,37 +112,54 @@ __global__ void __launch_bounds__(kLossBlock) ssim_stats_kernel(LossBatch batch)
   load_halo(a.x + c * HW, a.W, a.H, x0, y0, sx);
   load_halo(a.y + c * HW, a.W, a.H, x0, y0, sy);
   __syncthreads();
-  for (int k = threadIdx.x; k < kHaloH * kTileW; k += kLossBlock) {
-    const int r = k / kTileW, j = k - r * kTileW;
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+  if (threadIdx.x < kHaloH * (kTileW / kHRun)) {  // kHRun adjacent outputs per thread
+    const int r = threadIdx.x / (kTileW / kHRun), j0 = (threadIdx.x % (kTileW / kHRun)) * kHRun;
+    float xv[kHRun + 2 * kRad], yv[kHRun + 2 * kRad];
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t) {
-      const float g = kGauss[t], xv = sx[r][j + t], yv = sy[r][j + t];
-      s0 = fmaf(g, xv, s0);
-      s1 = fmaf(g, yv, s1);
-      s2 = fmaf(g, xv * xv, s2);
-      s3 = fmaf(g, yv * yv, s3);
-      s4 = fmaf(g, xv * yv, s4);
+    for (int t = 0; t < kHRun + 2 * kRad; ++t) { xv[t] = sx[r][j0 + t]; yv[t] = sy[r][j0 + t]; }
+#pragma unroll
+    for (int o = 0; o < kHRun; ++o) {
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+#pragma unroll
+      for (int t = 0; t < kTaps; ++t) {
+        const float g = kGauss[t], x = xv[o + t], y = yv[o + t];
+        s0 = fmaf(g, x, s0);
+        s1 = fmaf(g, y, s1);
+        s2 = fmaf(g, x * x, s2);
+        s3 = fmaf(g, y * y, s3);
+        s4 = fmaf(g, x * y, s4);
+      }
+      hs[0][r][j0 + o] = s0; hs[1][r][j0 + o] = s1; hs[2][r][j0 + o] = s2; hs[3][r][j0 + o] = s3;
+      hs[4][r][j0 + o] = s4;
     }
-    hs[0][r][j] = s0; hs[1][r][j] = s1; hs[2][r][j] = s2; hs[3][r][j] = s3; hs[4][r][j] = s4;
   }
   __syncthreads();
   float ssum = 0.f, l1sum = 0.f;
   float* P = a.P + (size_t)c * 3 * HW;
-  for (int k = threadIdx.x; k < kTileH * kTileW; k += kLossBlock) {
-    const int i = k / kTileW, j = k - i * kTileW;
+  // kVRun vertically adjacent outputs per thread (kTileW x kTileH / kVRun threads)
+  const int vj = threadIdx.x % kTileW, vi0 = (threadIdx.x / kTileW) * kVRun;
+  float vm[5][kVRun];
+  {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      float col[kVRun + 2 * kRad];
+#pragma unroll
+      for (int t = 0; t < kVRun + 2 * kRad; ++t) col[t] = hs[q][vi0 + t][vj];
+#pragma unroll
+      for (int o = 0; o < kVRun; ++o) {
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) acc = fmaf(kGauss[t], col[o + t], acc);
+        vm[q][o] = acc;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < kVRun; ++o) {
+    const int i = vi0 + o, j = vj;
     const int px = x0 + j, py = y0 + i;
     if (px >= a.W || py >= a.H) continue;
-    float m1 = 0.f, m2 = 0.f, e11 = 0.f, e22 = 0.f, e12 = 0.f;
-#pragma unroll
-    for (int t = 0; t < kTaps; ++t) {
-      const float g = kGauss[t];
-      m1 = fmaf(g, hs[0][i + t][j], m1);
-      m2 = fmaf(g, hs[1][i + t][j], m2);
-      e11 = fmaf(g, hs[2][i + t][j], e11);
-      e22 = fmaf(g, hs[3][i + t][j], e22);
-      e12 = fmaf(g, hs[4][i + t][j], e12);
-    }
+    const float m1 = vm[0][o], m2 = vm[1][o], e11 = vm[2][o], e22 = vm[3][o], e12 = vm[4][o];
     const float A1 = 2.f * m1 * m2 + kC1, A2 = 2.f * (e12 - m1 * m2) + kC2;
     const float B1 = m1 * m1 + m2 * m2 + kC1, B2 = (e11 - m1 * m1) + (e22 - m2 * m2) + kC2;
     const float rB1 = 1.0f / B1, rB2 = 1.0f / B2;
@@ -206,32 +227,45 @@ __global__ void __launch_bounds__(kLossBlock) ssim_grad_kernel(LossBatch batch, 
     s_nvalid = (float)nv;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < kHaloH * kTileW; k += kLossBlock) {
-    const int r = k / kTileW, j = k - r * kTileW;
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+  if (threadIdx.x < kHaloH * (kTileW / kHRun)) {
+    const int r = threadIdx.x / (kTileW / kHRun), j0 = (threadIdx.x % (kTileW / kHRun)) * kHRun;
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t) {
-      const float g = kGauss[t];
-      s0 = fmaf(g, sp[0][r][j + t], s0);
-      s1 = fmaf(g, sp[1][r][j + t], s1);
-      s2 = fmaf(g, sp[2][r][j + t], s2);
+    for (int q = 0; q < 3; ++q) {
+      float row[kHRun + 2 * kRad];
+#pragma unroll
+      for (int t = 0; t < kHRun + 2 * kRad; ++t) row[t] = sp[q][r][j0 + t];
+#pragma unroll
+      for (int o = 0; o < kHRun; ++o) {
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) acc = fmaf(kGauss[t], row[o + t], acc);
+        hs[q][r][j0 + o] = acc;
+      }
     }
-    hs[0][r][j] = s0; hs[1][r][j] = s1; hs[2][r][j] = s2;
   }
   __syncthreads();
   const float nvalid = c == 0 ? s_nvalid : 0.f;
-  for (int k = threadIdx.x; k < kTileH * kTileW; k += kLossBlock) {
-    const int i = k / kTileW, j = k - i * kTileW;
+  const int vj = threadIdx.x % kTileW, vi0 = (threadIdx.x / kTileW) * kVRun;
+  float vq[3][kVRun];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    float col[kVRun + 2 * kRad];
+#pragma unroll
+    for (int t = 0; t < kVRun + 2 * kRad; ++t) col[t] = hs[q][vi0 + t][vj];
+#pragma unroll
+    for (int o = 0; o < kVRun; ++o) {
+      float acc = 0.f;
+#pragma unroll
+      for (int t = 0; t < kTaps; ++t) acc = fmaf(kGauss[t], col[o + t], acc);
+      vq[q][o] = acc;
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < kVRun; ++o) {
+    const int i = vi0 + o, j = vj;
     const int px = x0 + j, py = y0 + i;
     if (px >= a.W || py >= a.H) continue;
-    float q1 = 0.f, q2 = 0.f, q3 = 0.f;
-#pragma unroll
-    for (int t = 0; t < kTaps; ++t) {
-      const float g = kGauss[t];
-      q1 = fmaf(g, hs[0][i + t][j], q1);
-      q2 = fmaf(g, hs[1][i + t][j], q2);
-      q3 = fmaf(g, hs[2][i + t][j], q3);
-    }
+    const float q1 = vq[0][o], q2 = vq[1][o], q3 = vq[2][o];
     const size_t pix = (size_t)py * a.W + px;
     const float xv = a.x[c * HW + pix], yv = a.y[c * HW + pix];
     a.gx[c * HW + pix] = w_ssim * (q1 + 2.f * xv * q2 + yv * q3) + w_l1 * sgnf(xv - yv);
