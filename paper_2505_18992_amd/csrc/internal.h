@@ -110,6 +110,7 @@ struct ProjBuffers {
   float4* rec;      // [R * kRecSlots]
   uint32_t* count;  // [R] tiles overlapped, 0 = culled
   uint32_t* zkey;   // [R] depth key of records with count != 0
+  uint2* rect;      // [R] tile rectangle of records with count != 0 (as in slot 3)
 };
 __host__ __device__ __forceinline__ size_t rec_slot(uint32_t r, int k) { return (size_t)r * kRecSlots + k; }
 
@@ -117,8 +118,10 @@ __host__ __device__ __forceinline__ size_t rec_slot(uint32_t r, int k) { return 
 
 hipError_t launch_project(const CallTables* d_tab, const CallTables& h_tab, ProjBuffers pb, int tile_w,
                           int tile_h, hipStream_t s);
-// Blocks of the per-Gaussian launches (the pose partial buffer holds
-// n_views * project_blocks * 6 floats).
+// Blocks of the per-Gaussian launches.  The projection backward leaves one
+// 6-float pose partial per (view, block, wavefront): the pose partial buffer
+// holds n_views * project_blocks * kPosePartialsPerBlock * 6 floats.
+constexpr int kPosePartialsPerBlock = 4;
 uint32_t project_blocks(const CallTables& h);
 // Reads each visible record's row of acc and leaves it zero.
 hipError_t launch_project_backward(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
@@ -142,14 +145,15 @@ hipError_t launch_compact_visible(const uint32_t* count, const uint32_t* zkey, u
                                   uint32_t* vals, uint32_t* total, void* ws, hipStream_t s);
 
 // Depth order of the compacted visible records: stable sort by FP32 depth
-// bits, their tile counts gathered in that order (by the last sort pass) and
-// the exclusive scan of those (pair offsets; the total goes to
-// *pair_off_total).
+// bits, their tile rectangles and counts gathered in that order (by the last
+// sort pass) and the exclusive scan of the counts (pair offsets; the total
+// goes to *pair_off_total).
 struct DepthOrder {
   uint32_t* keys;
   uint32_t* vals;
   uint32_t* keys_alt;
   uint32_t* vals_alt;
+  uint2* rects;
   uint32_t* counts;
   uint32_t* pair_off;
   uint32_t* pair_off_total;
@@ -159,9 +163,10 @@ struct DepthOrder {
 hipError_t launch_depth_order(const CallTables& h_tab, const ProjBuffers pb, const uint32_t* n_visible, DepthOrder d,
                               void* sort_ws, hipStream_t s);
 
-// One (tile id, record) pair per overlapped tile, in depth order.
-hipError_t launch_emit(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
-                       const uint32_t* sorted_rec, const uint32_t* pair_off, const uint32_t* n_visible,
+// One (tile id, record) pair per overlapped tile, in depth order (records
+// and their rectangles in that order, as the depth order leaves them).
+hipError_t launch_emit(const CallTables* d_tab, const CallTables& h_tab, const uint32_t* sorted_rec,
+                       const uint2* sorted_rect, const uint32_t* pair_off, const uint32_t* n_visible,
                        Counters* cnt, uint32_t* keys, uint32_t* vals, uint32_t capacity, hipStream_t s);
 
 // Stable LSD radix sort of (tile id, record) pairs over key bits [0, key_bits).

@@ -11,6 +11,7 @@ namespace vpgs {
 namespace {
 
 constexpr int kProjBlock = 256;
+static_assert(kProjBlock / 64 == kPosePartialsPerBlock, "one pose partial per wavefront");
 
 // Set index of a thread block (sets own contiguous block ranges).
 __device__ __forceinline__ int set_of_block(const CallTables* tab, uint32_t blk) {
@@ -158,6 +159,7 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(const CallTables* _
         out[2] = make_float4(c0, c1, c2, 0.0f);
         out[3] = make_float4(hx, hy, __uint_as_float(rect.x), __uint_as_float(rect.y));
         pb.zkey[rec] = __float_as_uint(p.z);
+        pb.rect[rec] = rect;
       }
     }
     pb.count[rec] = count;
@@ -168,24 +170,9 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(const CallTables* _
 // backward
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ float block_sum(float v, float* red) {
-  // wave reduction, then across the waves of the block through LDS
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  float r = 0.f;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < kProjBlock / 64; ++w) r += red[w];
-  return r;  // valid on thread 0
-}
-
 __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const CallTables* __restrict__ tab, ProjBuffers pb,
                                                                       float* __restrict__ acc,
                                                                       float* __restrict__ pose_partial) {
-  __shared__ float red[kProjBlock / 64];
   const int s = set_of_block(tab, blockIdx.x);
   const SetDesc& S = tab->sets[s];
   const int64_t i = (int64_t)(blockIdx.x - S.block_base) * kProjBlock + threadIdx.x;
@@ -318,10 +305,16 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
       }
     }
     if (pose_partial != nullptr) {
+      // wavefront sums (no barrier); the pose reduction adds the wavefronts
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const float r = block_sum(pose[k], red);
-        if (threadIdx.x == 0) pose_partial[((size_t)v * gridDim.x + blockIdx.x) * 6 + k] = r;
+      for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) pose[k] += __shfl_xor(pose[k], off, 64);
+      if (lane == 0) {
+        float* dst = pose_partial + (((size_t)v * gridDim.x + blockIdx.x) * kPosePartialsPerBlock + wave) * 6;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) dst[k] = pose[k];
       }
     }
   }
@@ -370,26 +363,50 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
   }
 }
 
-__global__ void pose_reduce_kernel(const CallTables* __restrict__ tab, const float* __restrict__ partial,
-                                   int total_blocks, float* __restrict__ d_pose) {
-  // one block per view; sums the partials of the blocks of the view's set
-  __shared__ float red[256];
+// One workgroup per view: the sum of the wavefront partials of the blocks of
+// the view's set, four rows (of 6 floats) per thread in flight.
+__global__ void __launch_bounds__(256) pose_reduce_kernel(const CallTables* __restrict__ tab,
+                                                          const float* __restrict__ partial, int total_blocks,
+                                                          float* __restrict__ d_pose) {
+  __shared__ float red[4][6];
   const int v = blockIdx.x;
   const SetDesc& S = tab->sets[tab->views[v].set];
-  const int b0 = (int)S.block_base;
-  const int nb = (int)((S.n + kProjBlock - 1) / kProjBlock);
-  for (int k = 0; k < 6; ++k) {
-    float s = 0.f;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partial[((size_t)v * total_blocks + b0 + b) * 6 + k];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) d_pose[6 * v + k] = red[0];
-    __syncthreads();
+  const size_t first = ((size_t)v * total_blocks + S.block_base) * kPosePartialsPerBlock;
+  const uint32_t rows = (uint32_t)((S.n + kProjBlock - 1) / kProjBlock) * kPosePartialsPerBlock;
+  const float2* p = reinterpret_cast<const float2*>(partial + first * 6);  // 3 float2 per row
+  float s[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  uint32_t r = threadIdx.x;
+  for (; r + 3 * 256 < rows; r += 4 * 256) {
+    float2 a[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a[u][c] = p[3 * (size_t)(r + u * 256) + c];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        s[2 * c] += a[u][c].x;
+        s[2 * c + 1] += a[u][c].y;
+      }
   }
+  for (; r < rows; r += 256)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float2 a = p[3 * (size_t)r + c];
+      s[2 * c] += a.x;
+      s[2 * c + 1] += a.y;
+    }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s[k] += __shfl_xor(s[k], off, 64);
+    if (lane == 0) red[wave][k] = s[k];
+  }
+  __syncthreads();
+  const int k = threadIdx.x;
+  if (k < 6) d_pose[6 * v + k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
 }
 
 int ilog2(int x) {

@@ -91,7 +91,7 @@ void free_buf(DevBuf& b) {
 namespace vpgs {
 
 void destroy_saved(vpgs_saved* s) {
-  DevBuf* bufs[] = {&s->tab, &s->rec, &s->count, &s->zkey, &s->scan_ws,
+  DevBuf* bufs[] = {&s->tab, &s->rec, &s->count, &s->zkey, &s->rect, &s->drect, &s->scan_ws,
                     &s->keys, &s->vals, &s->keys_alt, &s->vals_alt, &s->sort_ws, &s->ranges, &s->tfinal,
                     &s->ncontrib, &s->counters, &s->acc, &s->pose_partial, &s->dk, &s->dk_alt, &s->dv,
                     &s->dv_alt, &s->dcount, &s->dpoff, &s->key64, &s->order};
@@ -227,6 +227,7 @@ ProjBuffers proj_of(vpgs_saved* s) {
   pb.rec = static_cast<float4*>(s->rec.p);
   pb.zkey = static_cast<uint32_t*>(s->zkey.p);
   pb.count = static_cast<uint32_t*>(s->count.p);
+  pb.rect = static_cast<uint2*>(s->rect.p);
   return pb;
 }
 
@@ -288,6 +289,7 @@ int prepare_front(vpgs_ctx* ctx, vpgs_saved* sv) {
     return rc;
   if ((rc = ensure(ctx, sv->tab, sizeof(CallTables))) || (rc = ensure(ctx, sv->rec, R * kRecSlots * 16)) ||
       (rc = ensure(ctx, sv->count, R * 4)) || (rc = ensure(ctx, sv->zkey, R * 4)) ||
+      (rc = ensure(ctx, sv->rect, R * 8)) || (rc = ensure(ctx, sv->drect, R * 8)) ||
       (rc = ensure(ctx, sv->scan_ws, scan_workspace_bytes((uint32_t)R))) ||
       (rc = ensure(ctx, sv->ranges, (size_t)T.n_tiles * 8)) || (rc = ensure(ctx, sv->order, (size_t)T.n_tiles * 4)) ||
       (rc = ensure(ctx, sv->tfinal, pixels * 4)) ||
@@ -317,7 +319,8 @@ int ensure_backward(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
   const void* old_acc = sv->acc.p;
   int rc;
   if ((rc = ensure(ctx, sv->acc, R * kNumAcc * sizeof(float))) ||
-      (rc = ensure(ctx, sv->pose_partial, (size_t)T.n_views * std::max<uint32_t>(pblocks, 1u) * 6 * sizeof(float))))
+      (rc = ensure(ctx, sv->pose_partial,
+                   (size_t)T.n_views * std::max<uint32_t>(pblocks, 1u) * kPosePartialsPerBlock * 6 * sizeof(float))))
     return rc;
   if (sv->acc.p != old_acc) HIP_TRY(launch_fill_f32(static_cast<float*>(sv->acc.p), 0.0f, sv->acc.cap / 4, st));
   return VPGS_OK;
@@ -386,6 +389,7 @@ int enqueue_front(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
     d.vals = static_cast<uint32_t*>(sv->dv.p);
     d.keys_alt = static_cast<uint32_t*>(sv->dk_alt.p);
     d.vals_alt = static_cast<uint32_t*>(sv->dv_alt.p);
+    d.rects = static_cast<uint2*>(sv->drect.p);
     d.counts = static_cast<uint32_t*>(sv->dcount.p);
     d.pair_off = static_cast<uint32_t*>(sv->dpoff.p);
     d.pair_off_total = &cnt->pairs;
@@ -409,8 +413,8 @@ int enqueue_back(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
   {
     StageTimer t(ctx, ST_EMIT, st);
     const uint32_t* sorted_rec = static_cast<const uint32_t*>(sv->depth_in_alt ? sv->dv_alt.p : sv->dv.p);
-    HIP_TRY(launch_emit(d_tab, T, pb, sorted_rec, static_cast<const uint32_t*>(sv->dpoff.p), &cnt->visible, cnt, keys,
-                        vals, cap, st));
+    HIP_TRY(launch_emit(d_tab, T, sorted_rec, static_cast<const uint2*>(sv->drect.p),
+                        static_cast<const uint32_t*>(sv->dpoff.p), &cnt->visible, cnt, keys, vals, cap, st));
   }
   {
     StageTimer t(ctx, ST_SORT, st);

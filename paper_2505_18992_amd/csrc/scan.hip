@@ -58,11 +58,16 @@ __global__ void __launch_bounds__(kScanBlock) scan_reduce_kernel(const uint32_t*
   __shared__ uint32_t lds[kScanBlock / 64];
   const uint32_t n = scan_length(n_alloc, n_dev);
   const size_t base = (size_t)blockIdx.x * kScanTile;
+  // every item is loaded before any is summed, so the loads are in flight
+  // together (positions past the end read an allocated value and add 0)
+  uint32_t x[kScanItems];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) x[k] = in[min(base + (size_t)k * kScanBlock + threadIdx.x, (size_t)n_alloc - 1)];
   uint32_t s = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const size_t idx = base + (size_t)k * kScanBlock + threadIdx.x;
-    if (idx < n) s += scan_value(in[idx], flags);
+    s += idx < n ? scan_value(x[k], flags) : 0u;
   }
   uint32_t tot;
   block_excl_scan(s, lds, &tot);
@@ -112,11 +117,13 @@ __global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t* _
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)wave * kWaveItems + lane;
   uint32_t v[kWaveRounds];
+#pragma unroll
+  for (int k = 0; k < kWaveRounds; ++k) v[k] = in[min(base + (size_t)k * 64, (size_t)n_alloc - 1)];
   uint32_t s = 0;
 #pragma unroll
   for (int k = 0; k < kWaveRounds; ++k) {
     const size_t idx = base + (size_t)k * 64;
-    v[k] = idx < n ? scan_value(in[idx], flags) : 0u;
+    v[k] = idx < n ? scan_value(v[k], flags) : 0u;
     s += v[k];
   }
   uint32_t tot;
@@ -145,12 +152,22 @@ __global__ void __launch_bounds__(kScanBlock) compact_down_kernel(const uint32_t
   __shared__ uint32_t lds[kScanBlock / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)wave * kWaveItems + lane;
+  // counts and depth keys of every round are loaded up front, so the loads
+  // are in flight together (positions past the end read allocated values
+  // that are not used)
+  uint32_t c[kWaveRounds], z[kWaveRounds];
+#pragma unroll
+  for (int k = 0; k < kWaveRounds; ++k) {
+    const size_t ci = min(base + (size_t)k * 64, (size_t)n - 1);
+    c[k] = count[ci];
+    z[k] = zkey[ci];
+  }
   uint32_t flags = 0;  // bit k: this lane's value of round k is visible
   uint32_t s = 0;
 #pragma unroll
   for (int k = 0; k < kWaveRounds; ++k) {
     const size_t idx = base + (size_t)k * 64;
-    const bool vis = idx < n && count[idx] != 0u;
+    const bool vis = idx < n && c[k] != 0u;
     flags |= (vis ? 1u : 0u) << k;
     s += __popcll(__ballot(vis));
   }
@@ -165,7 +182,7 @@ __global__ void __launch_bounds__(kScanBlock) compact_down_kernel(const uint32_t
       const size_t idx = base + (size_t)k * 64;
       const uint32_t pos =
           run + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-      keys[pos] = zkey[idx];
+      keys[pos] = z[k];
       vals[pos] = (uint32_t)idx;
     }
     run += __popcll(m);

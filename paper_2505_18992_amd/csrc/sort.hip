@@ -28,24 +28,24 @@ constexpr int kWaves = kSortBlock / 64;
 constexpr int kRounds = 16;                              // 64-key rounds per wave
 constexpr uint32_t kSortTile = kSortBlock * kRounds;     // 4096 keys per workgroup
 constexpr int kRadix = 256;
+static_assert(kRadix == kSortBlock, "one digit per thread in the histogram and offset kernels");
 
 __device__ __forceinline__ uint32_t clamped(const uint32_t* n, uint32_t capacity) {
   const uint32_t v = *n;
   return v < capacity ? v : capacity;
 }
 
-__device__ __forceinline__ int view_of_record(const CallTables* tab, uint32_t rec) {
-  int lo = 0, hi = tab->n_views - 1;
-  while (lo < hi) {  // last view whose rec_base <= rec
-    const int mid = (lo + hi + 1) >> 1;
-    if (tab->views[mid].rec_base <= rec) lo = mid; else hi = mid - 1;
-  }
-  return lo;
+// Tiles of an inclusive tile rectangle (x0 | x1 << 16, y0 | y1 << 16).
+__device__ __forceinline__ uint32_t rect_count(uint2 r) {
+  return ((r.x >> 16) - (r.x & 0xffffu) + 1u) * ((r.y >> 16) - (r.y & 0xffffu) + 1u);
 }
 
 // ---------------------------------------------------------------------------
 // pair emission in depth order
 // ---------------------------------------------------------------------------
+// One thread per visible record in depth order; a record's pairs are its
+// tiles in row-major order.  Small rectangles are written by their own lane,
+// larger ones by the whole wavefront, lanes over tiles.
 __device__ __forceinline__ void emit_range(uint32_t k0, uint32_t k1, uint32_t stride, uint32_t off, uint32_t rec,
                                            uint32_t tile0, uint32_t w, uint32_t tiles_x, uint32_t capacity,
                                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
@@ -60,8 +60,9 @@ __device__ __forceinline__ void emit_range(uint32_t k0, uint32_t k1, uint32_t st
 
 constexpr uint32_t kSmallFootprint = 8;  // records with more tiles are emitted by the whole wavefront
 
-__global__ void __launch_bounds__(256) emit_kernel(const CallTables* __restrict__ tab, const float4* __restrict__ recs,
+__global__ void __launch_bounds__(256) emit_kernel(const CallTables* __restrict__ tab,
                                                    const uint32_t* __restrict__ sorted_rec,
+                                                   const uint2* __restrict__ sorted_rect,
                                                    const uint32_t* __restrict__ pair_off,
                                                    const uint32_t* __restrict__ n_visible, Counters* __restrict__ cnt,
                                                    uint32_t n_records, uint32_t capacity, uint32_t* __restrict__ keys,
@@ -73,14 +74,22 @@ __global__ void __launch_bounds__(256) emit_kernel(const CallTables* __restrict_
   if (i < nv) {
     rec = sorted_rec[i];
     off = pair_off[i];
-    const ViewDesc& V = tab->views[view_of_record(tab, rec)];
-    const float4 x = recs[rec_slot(rec, 3)];
-    const uint32_t rx = __float_as_uint(x.z), ry = __float_as_uint(x.w);
+    const uint2 rr = sorted_rect[i];
+    // the record's view: the last whose first record is <= rec (the table
+    // reads are the same for every lane)
+    uint32_t tile_base = tab->views[0].tile_base;
+    tiles_x = (uint32_t)tab->views[0].tiles_x;
+    for (int v = 1; v < tab->n_views; ++v) {
+      const uint32_t rb = tab->views[v].rec_base, tb = tab->views[v].tile_base, tx = (uint32_t)tab->views[v].tiles_x;
+      const bool in = rec >= rb;
+      tile_base = in ? tb : tile_base;
+      tiles_x = in ? tx : tiles_x;
+    }
+    const uint32_t rx = rr.x, ry = rr.y;
     const uint32_t tx0 = rx & 0xffffu, tx1 = rx >> 16, ty0 = ry & 0xffffu, ty1 = ry >> 16;
-    tiles_x = (uint32_t)V.tiles_x;
     w = tx1 - tx0 + 1u;
     c = w * (ty1 - ty0 + 1u);  // the record's count
-    tile0 = V.tile_base + ty0 * tiles_x + tx0;
+    tile0 = tile_base + ty0 * tiles_x + tx0;
     if (off + c > capacity || off + c < off) cnt->overflow = 1u;
   }
   if (c <= kSmallFootprint) emit_range(0, c, 1, off, rec, tile0, w, tiles_x, capacity, keys, vals);
@@ -120,20 +129,22 @@ __global__ void __launch_bounds__(kSortBlock) radix_hist_kernel(const K* __restr
                                                                 uint32_t capacity, int shift, uint32_t* __restrict__ hist) {
   __shared__ uint32_t wcnt[kWaves][kRadix];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int d = threadIdx.x; d < kWaves * kRadix; d += kSortBlock) (&wcnt[0][0])[d] = 0;
-  __syncthreads();
   const uint32_t n = clamped(n_ptr, capacity);
+  if (blockIdx.x * kSortTile >= n) return;  // a tile past the end (its row entries are not read)
+  for (int d = threadIdx.x; d < kWaves * kRadix; d += kSortBlock) (&wcnt[0][0])[d] = 0;
   const uint32_t base = blockIdx.x * kSortTile + wave * (kSortTile / kWaves);
-  if (blockIdx.x * kSortTile < n) {
-    for (int r = 0; r < kRounds; ++r) {
-      const uint32_t idx = base + r * 64 + lane;
-      const bool ok = idx < n;
-      const uint32_t d = ok ? (uint32_t)(keys[idx] >> shift) & 0xffu : 0u;
-      const uint64_t active = __ballot(ok);
-      if (active == 0) break;
-      const uint64_t peers = match_digit(d, active);
-      if (ok && (peers & lanemask_lt()) == 0) wcnt[wave][d] += (uint32_t)__popcll(peers);
-    }
+  // every round's digit is loaded before any is counted, so the loads are in
+  // flight together; positions past the end read the last key and are left
+  // out of the counts
+  uint32_t dig[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) dig[r] = (uint32_t)(keys[min(base + r * 64 + lane, n - 1)] >> shift) & 0xffu;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const bool ok = base + r * 64 + lane < n;
+    const uint64_t peers = match_digit(dig[r], __ballot(ok));
+    if (ok && (peers & lanemask_lt()) == 0) wcnt[wave][dig[r]] += (uint32_t)__popcll(peers);
   }
   __syncthreads();
   const int d = threadIdx.x;
@@ -143,8 +154,9 @@ __global__ void __launch_bounds__(kSortBlock) radix_hist_kernel(const K* __restr
   hist[(size_t)d * gridDim.x + blockIdx.x] = s;
 }
 
-// Exclusive scan of one value per thread over the 256-thread workgroup.
-__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* wsum) {
+// Exclusive scan of one value per thread over the 256-thread workgroup;
+// *total receives the workgroup sum.
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* wsum, uint32_t* total = nullptr) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t incl = v;
 #pragma unroll
@@ -154,34 +166,51 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* wsu
   }
   if (lane == 63) wsum[wave] = incl;
   __syncthreads();
-  uint32_t wb = 0;
-  for (int w = 0; w < wave; ++w) wb += wsum[w];
+  uint32_t wb = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    wb += w < wave ? wsum[w] : 0u;
+    all += wsum[w];
+  }
   __syncthreads();
+  if (total) *total = all;
   return wb + incl - v;
 }
 
-// One workgroup per digit d: exclusive scan of hist[d][0, blocks) in place
-// of hist_scan and the row total in row_total[d].  Thread t owns a
-// contiguous run of the row.
+// One workgroup per digit d: exclusive scan of hist[d][0, used) into
+// hist_scan and the row total into row_total[d], where used is the number of
+// tiles that hold keys (the rest of the grid has no keys and writes nothing).
+// The row is read in coalesced chunks of 256, eight chunks in flight.
+constexpr int kScanChunks = 8;
 __global__ void __launch_bounds__(kSortBlock) radix_offsets_kernel(const uint32_t* __restrict__ hist, uint32_t blocks,
+                                                                   const uint32_t* __restrict__ n_ptr,
+                                                                   uint32_t capacity,
                                                                    uint32_t* __restrict__ hist_scan,
                                                                    uint32_t* __restrict__ row_total) {
   __shared__ uint32_t wsum[kWaves];
   const uint32_t d = blockIdx.x;
-  const uint32_t per = (blocks + kSortBlock - 1) / kSortBlock;
-  const uint32_t b0 = threadIdx.x * per;
-  const uint32_t b1 = min(b0 + per, blocks);
+  const uint32_t used = min(blocks, (clamped(n_ptr, capacity) + kSortTile - 1) / kSortTile);
   const uint32_t* row = hist + (size_t)d * blocks;
   uint32_t* out = hist_scan + (size_t)d * blocks;
-  uint32_t sum = 0;
-  for (uint32_t b = b0; b < b1; ++b) sum += row[b];
-  uint32_t run = block_excl_scan256(sum, wsum);
-  for (uint32_t b = b0; b < b1; ++b) {
-    const uint32_t c = row[b];
-    out[b] = run;
-    run += c;
+  uint32_t carry = 0;
+  for (uint32_t c0 = 0; c0 < used; c0 += kSortBlock * kScanChunks) {
+    uint32_t v[kScanChunks];
+#pragma unroll
+    for (int j = 0; j < kScanChunks; ++j) {
+      const uint32_t b = c0 + j * kSortBlock + threadIdx.x;
+      const uint32_t x = row[min(b, used - 1)];
+      v[j] = b < used ? x : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kScanChunks; ++j) {
+      const uint32_t b = c0 + j * kSortBlock + threadIdx.x;
+      uint32_t total;
+      const uint32_t excl = block_excl_scan256(v[j], wsum, &total);
+      if (b < used) out[b] = carry + excl;
+      carry += total;
+    }
   }
-  if (threadIdx.x == kSortBlock - 1) row_total[d] = run;
+  if (threadIdx.x == 0) row_total[d] = carry;
 }
 
 template <class K>
@@ -192,7 +221,10 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
                                                                    int shift, const uint32_t* __restrict__ hist_scan,
                                                                    const uint32_t* __restrict__ row_total,
                                                                    const uint32_t* __restrict__ gather_src,
-                                                                   uint32_t* __restrict__ gather_dst) {
+                                                                   uint32_t* __restrict__ gather_dst,
+                                                                   const uint2* __restrict__ rect_src,
+                                                                   uint2* __restrict__ rect_dst,
+                                                                   uint32_t* __restrict__ count_dst) {
   __shared__ uint32_t wcnt[kWaves][kRadix];   // per-wave digit counts, then per-wave prefixes
   __shared__ uint32_t dstart[kRadix];         // block-local first position of each digit
   __shared__ uint32_t gbase[kRadix];          // global first position of each digit for this block
@@ -202,6 +234,9 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
   const uint32_t n = clamped(n_ptr, capacity);
   if (blockIdx.x * kSortTile >= n) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // this thread's digit: its total and this tile's row offset (read early)
+  const uint32_t my_total = row_total[threadIdx.x];
+  const uint32_t my_row_off = hist_scan[(size_t)threadIdx.x * gridDim.x + blockIdx.x];
   for (int d = threadIdx.x; d < kWaves * kRadix; d += kSortBlock) (&wcnt[0][0])[d] = 0;
   __syncthreads();
 
@@ -209,12 +244,18 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
   K k[kRounds];
   uint32_t v[kRounds];
   uint32_t loc[kRounds];
+  // all rounds are loaded before any is ranked (positions past the end read
+  // the last pair and take no part in the ranking)
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t ci = min(base + r * 64 + lane, n - 1);
+    k[r] = keys_in[ci];
+    v[r] = vals_in[ci];
+  }
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t idx = base + r * 64 + lane;
     const bool ok = idx < n;
-    k[r] = ok ? keys_in[idx] : (K)0;
-    v[r] = ok ? vals_in[idx] : 0u;
     const uint32_t d = (uint32_t)(k[r] >> shift) & 0xffu;
     const uint64_t active = __ballot(ok);
     const uint64_t peers = match_digit(d, active);
@@ -246,8 +287,8 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
     dstart[d] = wb + incl - run;
     __syncthreads();
     // global base of digit d: the totals of the smaller digits
-    const uint32_t digit_base = block_excl_scan256(row_total[d], wsum);
-    gbase[d] = digit_base + hist_scan[(size_t)d * gridDim.x + blockIdx.x];
+    const uint32_t digit_base = block_excl_scan256(my_total, wsum);
+    gbase[d] = digit_base + my_row_off;
   }
   __syncthreads();
 #pragma unroll
@@ -262,6 +303,40 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
   }
   __syncthreads();
   const uint32_t tile_n = min(kSortTile, n - blockIdx.x * kSortTile);
+  if (tile_n == kSortTile) {
+    // a full tile: straight-line code, so the gathers are in flight together
+    uint32_t gpos[kRounds], gval[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const uint32_t p = r * kSortBlock + threadIdx.x;
+      const K key = skeys[p];
+      const uint32_t d = (uint32_t)(key >> shift) & 0xffu;
+      const uint32_t g = gbase[d] + (p - dstart[d]);
+      const uint32_t val = svals[p];
+      keys_out[g] = key;
+      vals_out[g] = val;
+      gpos[r] = g;
+      gval[r] = val;
+    }
+    if (gather_dst != nullptr) {
+      uint32_t gv[kRounds];
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) gv[r] = gather_src[gval[r]];
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) gather_dst[gpos[r]] = gv[r];
+    }
+    if (rect_dst != nullptr) {
+      uint2 rv[kRounds];
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) rv[r] = rect_src[gval[r]];
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) {
+        rect_dst[gpos[r]] = rv[r];
+        count_dst[gpos[r]] = rect_count(rv[r]);
+      }
+    }
+    return;
+  }
   for (uint32_t p = threadIdx.x; p < tile_n; p += kSortBlock) {
     const K key = skeys[p];
     const uint32_t d = (uint32_t)(key >> shift) & 0xffu;
@@ -270,6 +345,11 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
     keys_out[g] = key;
     vals_out[g] = val;
     if (gather_dst != nullptr) gather_dst[g] = gather_src[val];
+    if (rect_dst != nullptr) {
+      const uint2 rv = rect_src[val];
+      rect_dst[g] = rv;
+      count_dst[g] = rect_count(rv);
+    }
   }
 }
 
@@ -283,10 +363,13 @@ size_t radix_ws_bytes(uint32_t capacity) {
 
 // gather_src/gather_dst (may be NULL): the last pass also writes
 // gather_dst[i] = gather_src[value i] for every sorted position i.
+// rect_src/rect_dst/count_dst (may be NULL): the last pass also writes
+// rect_dst[i] = rect_src[value i] and count_dst[i] = its number of tiles.
 template <class K>
 hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, uint32_t capacity, int key_bits,
                       const uint32_t* n_ptr, void* ws, int* result_in_alt, hipStream_t s,
-                      const uint32_t* gather_src = nullptr, uint32_t* gather_dst = nullptr) {
+                      const uint32_t* gather_src = nullptr, uint32_t* gather_dst = nullptr,
+                      const uint2* rect_src = nullptr, uint2* rect_dst = nullptr, uint32_t* count_dst = nullptr) {
   *result_in_alt = 0;
   if (capacity == 0) return hipSuccess;
   const uint32_t blocks = div_up(capacity, kSortTile);
@@ -302,12 +385,14 @@ hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, 
     hipLaunchKernelGGL(radix_hist_kernel<K>, dim3(blocks), dim3(kSortBlock), 0, s, kin, n_ptr, capacity, shift, hist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(radix_offsets_kernel, dim3(kRadix), dim3(kSortBlock), 0, s, hist, blocks, hist_scan, row_total);
+    hipLaunchKernelGGL(radix_offsets_kernel, dim3(kRadix), dim3(kSortBlock), 0, s, hist, blocks, n_ptr, capacity,
+                       hist_scan, row_total);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(radix_scatter_kernel<K>, dim3(blocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout, n_ptr,
                        capacity, shift, hist_scan, row_total, last ? gather_src : nullptr,
-                       last ? gather_dst : nullptr);
+                       last ? gather_dst : nullptr, last ? rect_src : nullptr, last ? rect_dst : nullptr,
+                       last ? count_dst : nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     K* tk = kin; kin = kout; kout = tk;
@@ -326,10 +411,13 @@ __global__ void ranges_kernel(const uint32_t* __restrict__ tiles, const uint32_t
   const uint32_t n = clamped(n_ptr, capacity);
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
+  // the three loads are independent, so they are in flight together
   const uint32_t t = tiles[k];
+  const uint32_t prev = tiles[k > 0 ? k - 1 : k];
+  const uint32_t next = tiles[k + 1 < n ? k + 1 : k];
   if (t >= n_tiles) return;
-  if (k == 0 || tiles[k - 1] != t) ranges[t].x = k;
-  if (k == n - 1 || tiles[k + 1] != t) ranges[t].y = k + 1;
+  if (k == 0 || prev != t) ranges[t].x = k;
+  if (k == n - 1 || next != t) ranges[t].y = k + 1;
 }
 
 __global__ void key64_kernel(const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ rec_of,
@@ -404,19 +492,19 @@ hipError_t launch_depth_order(const CallTables& h, const ProjBuffers pb, const u
   const uint32_t R = h.n_records;
   if (R == 0) return launch_fill_u32(d.pair_off_total, 0u, 1, s);
   int alt = 0;
-  hipError_t e = radix_sort<uint32_t>(d.keys, d.vals, d.keys_alt, d.vals_alt, R, 32, n_visible, ws, &alt, s, pb.count,
-                                      d.counts);
+  hipError_t e = radix_sort<uint32_t>(d.keys, d.vals, d.keys_alt, d.vals_alt, R, 32, n_visible, ws, &alt, s, nullptr,
+                                      nullptr, pb.rect, d.rects, d.counts);
   if (e != hipSuccess) return e;
   *d.sorted_in_alt = alt;
   return launch_scan(d.counts, d.pair_off, R, d.pair_off_total, d.scan_ws, s, false, n_visible);
 }
 
-hipError_t launch_emit(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb, const uint32_t* sorted_rec,
-                       const uint32_t* pair_off, const uint32_t* n_visible, Counters* cnt, uint32_t* keys,
-                       uint32_t* vals, uint32_t capacity, hipStream_t s) {
+hipError_t launch_emit(const CallTables* d_tab, const CallTables& h, const uint32_t* sorted_rec,
+                       const uint2* sorted_rect, const uint32_t* pair_off, const uint32_t* n_visible, Counters* cnt,
+                       uint32_t* keys, uint32_t* vals, uint32_t capacity, hipStream_t s) {
   if (h.n_records == 0) return hipSuccess;
-  hipLaunchKernelGGL(emit_kernel, dim3(div_up(h.n_records, 256)), dim3(256), 0, s, d_tab, pb.rec,
-                     sorted_rec, pair_off, n_visible, cnt, h.n_records, capacity, keys, vals);
+  hipLaunchKernelGGL(emit_kernel, dim3(div_up(h.n_records, 256)), dim3(256), 0, s, d_tab, sorted_rec, sorted_rect,
+                     pair_off, n_visible, cnt, h.n_records, capacity, keys, vals);
   return hipGetLastError();
 }
 

@@ -90,6 +90,47 @@ def test_c1_binning_bit_exact(tile):
     assert np.array_equal(ranges, er)
 
 
+@pytest.mark.parametrize("tile", [(32, 8), (16, 16)])
+def test_c4_binning_bit_exact(tile):
+    """The benchmark's binning: 8 keyframes at 1200x680 of the 1M-Gaussian
+    corridor in one call (8 M records, about 12 M pairs), every key, value
+    and tile range against the oracle's binning of each view, concatenated
+    in view order (views own consecutive record and tile ranges)."""
+    from paper_2505_18992_amd import _lib
+    sc = scenes.make_c4(sizes=(1200, 680))
+    print(f"case c4-1200 binning tile={tile}", flush=True)
+    _, outs, saved = _render(sc, tile=tile)
+    st = saved.stats()
+    P = st["n_pairs"]
+    proj = np_(saved.export(_lib.BUF_PROJ)).reshape(-1, 12)
+    ext = np_(saved.export(_lib.BUF_EXTENT)).reshape(-1, 2)
+    count = np_(saved.export(_lib.BUF_COUNT, torch.int32)).view(np.uint32)
+    keys = np_(saved.export(_lib.BUF_KEYS, torch.int64)).view(np.uint64)[:P]
+    vals = np_(saved.export(_lib.BUF_VALUES, torch.int32)).view(np.uint32)[:P]
+    ranges = np_(saved.export(_lib.BUF_RANGES, torch.int32)).view(np.uint32).reshape(-1, 2)
+    saved.close()
+    assert st["overflow"] == 0
+    n = sc.sets[0].means.shape[0]
+    tw, th = tile
+    rec = tb = pos = 0
+    ek, ev, er = [], [], []
+    for cam in sc.cameras:
+        s = slice(rec, rec + n)
+        ok = count[s] > 0
+        k, v, r = oracle.binning(ok, proj[s, 0], proj[s, 1], np.where(ok, ext[s, 0], 0), np.where(ok, ext[s, 1], 0),
+                                 proj[s, 2].view(np.uint32), cam.width, cam.height, tw, th, tile_base=tb,
+                                 index_base=rec, cap=4 * int(count[s].sum()) + 1)
+        ek.append(k); ev.append(v)
+        er.append(np.where(r[:, 1:2] > 0, r + np.uint32(pos), 0).astype(np.uint32))
+        rec += n
+        tb += r.shape[0]
+        pos += len(k)
+    assert P == pos and ranges.shape[0] == tb
+    assert np.array_equal(keys, np.concatenate(ek))
+    assert np.array_equal(vals, np.concatenate(ev))
+    assert np.array_equal(ranges, np.concatenate(er))
+
+
 def test_c1_forward_parity():
     sc = scenes.make_c1()
     g, cam = sc.sets[0], sc.cameras[0]
