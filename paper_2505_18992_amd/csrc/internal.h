@@ -116,8 +116,10 @@ __host__ __device__ __forceinline__ size_t rec_slot(uint32_t r, int k) { return 
 
 // ---- launch helpers (defined in the .hip files) --------------------------------
 
+// The projection also resets the per-forward state: the counters and the
+// tile ranges (every tile empty) before any later kernel of the forward.
 hipError_t launch_project(const CallTables* d_tab, const CallTables& h_tab, ProjBuffers pb, int tile_w,
-                          int tile_h, hipStream_t s);
+                          int tile_h, Counters* cnt, uint2* ranges, hipStream_t s);
 // Blocks of the per-Gaussian launches.  The projection backward leaves one
 // 6-float pose partial per (view, block, wavefront): the pose partial buffer
 // holds n_views * project_blocks * kPosePartialsPerBlock * 6 floats.
@@ -184,6 +186,8 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                              int key_bits, const uint32_t* n_dev, void* ws, int* result_in_alt, hipStream_t s,
                              const uint32_t* gather_src, uint32_t* gather_dst);
 
+// Per-tile [start, end) of the sorted pairs; ranges must hold zeros on entry
+// (empty tiles are not written).
 hipError_t launch_ranges(const uint32_t* tiles, const Counters* cnt, uint32_t capacity, uint2* ranges,
                          uint32_t n_tiles, hipStream_t s);
 // The compositing order of the tiles: order[i] is the tile the i-th

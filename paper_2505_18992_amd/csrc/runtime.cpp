@@ -369,12 +369,9 @@ int enqueue_front(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
   Counters* cnt = static_cast<Counters*>(sv->counters.p);
   const ProjBuffers pb = proj_of(sv);
   {
-    StageTimer t(ctx, ST_FILL, st);
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, sizeof(Counters) / 4, st));
-  }
-  {
+    // (the projection also zeroes the counters and the tile ranges)
     StageTimer t(ctx, ST_PROJECT, st);
-    HIP_TRY(launch_project(d_tab, T, pb, sv->tile_w, sv->tile_h, st));
+    HIP_TRY(launch_project(d_tab, T, pb, sv->tile_w, sv->tile_h, cnt, static_cast<uint2*>(sv->ranges.p), st));
   }
   {
     // visible records (count != 0), compacted in record order with their depth keys
@@ -446,7 +443,7 @@ int enqueue_backward(vpgs_ctx* ctx, vpgs_saved* sv, float* d_pose, hipStream_t s
   const ProjBuffers pb = proj_of(sv);
   float* acc = static_cast<float*>(sv->acc.p);
   const uint32_t* svals = static_cast<const uint32_t*>(sv->result_in_alt ? sv->vals_alt.p : sv->vals.p);
-  {
+  if (sv->persistent_blocks) {
     StageTimer t(ctx, ST_FILL, st);
     HIP_TRY(launch_fill_u32(&cnt->queue_bwd, 0u, 1, st));
   }

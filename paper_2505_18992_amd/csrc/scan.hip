@@ -58,6 +58,10 @@ __global__ void __launch_bounds__(kScanBlock) scan_reduce_kernel(const uint32_t*
   __shared__ uint32_t lds[kScanBlock / 64];
   const uint32_t n = scan_length(n_alloc, n_dev);
   const size_t base = (size_t)blockIdx.x * kScanTile;
+  if (base >= n) {  // a tile past the end (the length may come from the device)
+    if (threadIdx.x == 0) sums[blockIdx.x] = 0u;
+    return;
+  }
   // every item is loaded before any is summed, so the loads are in flight
   // together (positions past the end read an allocated value and add 0)
   uint32_t x[kScanItems];
@@ -115,6 +119,11 @@ __global__ void __launch_bounds__(kScanBlock) scan_down_kernel(const uint32_t* _
   __shared__ uint32_t lds[kScanBlock / 64];
   const uint32_t n = scan_length(n_alloc, n_dev);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if ((size_t)blockIdx.x * kScanTile >= n) {  // a tile past the end: nothing to write but the grand total
+    if (total != nullptr && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+      *total = block_offsets ? block_offsets[blockIdx.x] : 0u;
+    return;
+  }
   const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)wave * kWaveItems + lane;
   uint32_t v[kWaveRounds];
 #pragma unroll

@@ -44,32 +44,35 @@ __device__ __forceinline__ uint32_t rect_count(uint2 r) {
 // pair emission in depth order
 // ---------------------------------------------------------------------------
 // One thread per visible record in depth order; a record's pairs are its
-// tiles in row-major order.  Small rectangles are written by their own lane,
-// larger ones by the whole wavefront, lanes over tiles.
-__device__ __forceinline__ void emit_range(uint32_t k0, uint32_t k1, uint32_t stride, uint32_t off, uint32_t rec,
-                                           uint32_t tile0, uint32_t w, uint32_t tiles_x, uint32_t capacity,
-                                           uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  for (uint32_t k = k0; k < k1; k += stride) {
-    const uint32_t p = off + k;
-    if (p < capacity) {
-      keys[p] = tile0 + (k / w) * tiles_x + (k % w);
-      vals[p] = rec;
-    }
-  }
+// tiles in row-major order.  The 64 records of a wavefront own one
+// contiguous run of the pair list.  When the run fits the wavefront's LDS
+// stage, the pairs are built there (small rectangles by their own lane,
+// larger ones by the whole wavefront, lanes over tiles) and the run is then
+// copied out 64 consecutive pairs at a time; otherwise they are written to
+// the pair list directly in the same way.
+template <class Out>
+__device__ __forceinline__ void emit_range(uint32_t k0, uint32_t k1, uint32_t stride, uint32_t pos, uint32_t rec,
+                                           uint32_t tile0, uint32_t w, uint32_t tiles_x, Out out) {
+  for (uint32_t k = k0; k < k1; k += stride) out(pos + k, tile0 + (k / w) * tiles_x + (k % w), rec);
 }
 
 constexpr uint32_t kSmallFootprint = 8;  // records with more tiles are emitted by the whole wavefront
+constexpr int kEmitBlock = 256;
+constexpr uint32_t kEmitStage = 512;     // staged pairs per wavefront
 
-__global__ void __launch_bounds__(256) emit_kernel(const CallTables* __restrict__ tab,
-                                                   const uint32_t* __restrict__ sorted_rec,
-                                                   const uint2* __restrict__ sorted_rect,
-                                                   const uint32_t* __restrict__ pair_off,
-                                                   const uint32_t* __restrict__ n_visible, Counters* __restrict__ cnt,
-                                                   uint32_t n_records, uint32_t capacity, uint32_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ vals) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kEmitBlock) emit_kernel(const CallTables* __restrict__ tab,
+                                                          const uint32_t* __restrict__ sorted_rec,
+                                                          const uint2* __restrict__ sorted_rect,
+                                                          const uint32_t* __restrict__ pair_off,
+                                                          const uint32_t* __restrict__ n_visible,
+                                                          Counters* __restrict__ cnt, uint32_t n_records,
+                                                          uint32_t capacity, uint32_t* __restrict__ keys,
+                                                          uint32_t* __restrict__ vals) {
+  __shared__ uint32_t stage_key[kEmitBlock / 64][kEmitStage], stage_val[kEmitBlock / 64][kEmitStage];
   const uint32_t nv = clamped(n_visible, n_records);
-  const int lane = threadIdx.x & 63;
+  if (blockIdx.x * kEmitBlock >= nv) return;
+  const uint32_t i = blockIdx.x * kEmitBlock + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t rec = 0, c = 0, off = 0, tile0 = 0, w = 1, tiles_x = 1;
   if (i < nv) {
     rec = sorted_rec[i];
@@ -85,22 +88,51 @@ __global__ void __launch_bounds__(256) emit_kernel(const CallTables* __restrict_
       tile_base = in ? tb : tile_base;
       tiles_x = in ? tx : tiles_x;
     }
-    const uint32_t rx = rr.x, ry = rr.y;
-    const uint32_t tx0 = rx & 0xffffu, tx1 = rx >> 16, ty0 = ry & 0xffffu, ty1 = ry >> 16;
+    const uint32_t tx0 = rr.x & 0xffffu, tx1 = rr.x >> 16, ty0 = rr.y & 0xffffu, ty1 = rr.y >> 16;
     w = tx1 - tx0 + 1u;
     c = w * (ty1 - ty0 + 1u);  // the record's count
     tile0 = tile_base + ty0 * tiles_x + tx0;
     if (off + c > capacity || off + c < off) cnt->overflow = 1u;
   }
-  if (c <= kSmallFootprint) emit_range(0, c, 1, off, rec, tile0, w, tiles_x, capacity, keys, vals);
-  // large footprints: the wavefront emits them one at a time, lanes over tiles
+  // the wavefront's run: active lanes are a prefix of the wavefront
+  const uint64_t active = __ballot(i < nv);
+  if (active == 0ull) return;  // the whole wavefront is past the end (no barrier follows)
+  const int last = 63 - __clzll((long long)active);
+  const uint32_t begin = __shfl(off, 0, 64), end = __shfl(off + c, last, 64);
+  const bool staged = end >= begin && end - begin <= kEmitStage && end <= capacity;  // the same in every lane
+  uint32_t* sk = stage_key[wave];
+  uint32_t* sv = stage_val[wave];
+  auto to_stage = [&](uint32_t p, uint32_t key, uint32_t val) {
+    sk[p - begin] = key;
+    sv[p - begin] = val;
+  };
+  auto to_list = [&](uint32_t p, uint32_t key, uint32_t val) {
+    if (p < capacity) {
+      keys[p] = key;
+      vals[p] = val;
+    }
+  };
+  if (c <= kSmallFootprint) {
+    if (staged) emit_range(0, c, 1, off, rec, tile0, w, tiles_x, to_stage);
+    else emit_range(0, c, 1, off, rec, tile0, w, tiles_x, to_list);
+  }
   uint64_t big = __ballot(c > kSmallFootprint);
   while (big != 0ull) {
     const int src = __ffsll((unsigned long long)big) - 1;
     big &= big - 1ull;
     const uint32_t bc = __shfl(c, src, 64), boff = __shfl(off, src, 64), brec = __shfl(rec, src, 64);
     const uint32_t bt0 = __shfl(tile0, src, 64), bw = __shfl(w, src, 64), btx = __shfl(tiles_x, src, 64);
-    emit_range((uint32_t)lane, bc, 64, boff, brec, bt0, bw, btx, capacity, keys, vals);
+    if (staged) emit_range((uint32_t)lane, bc, 64, boff, brec, bt0, bw, btx, to_stage);
+    else emit_range((uint32_t)lane, bc, 64, boff, brec, bt0, bw, btx, to_list);
+  }
+  if (staged) {
+    // LDS accesses of a wavefront complete in order: the reads see every
+    // lane's writes above
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t q = (uint32_t)lane; q < end - begin; q += 64) {
+      keys[begin + q] = sk[q];
+      vals[begin + q] = sv[q];
+    }
   }
 }
 
@@ -126,32 +158,27 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 
 template <class K>
 __global__ void __launch_bounds__(kSortBlock) radix_hist_kernel(const K* __restrict__ keys, const uint32_t* __restrict__ n_ptr,
-                                                                uint32_t capacity, int shift, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t wcnt[kWaves][kRadix];
+                                                                uint32_t capacity, int shift, uint32_t mask,
+                                                                uint32_t* __restrict__ hist) {
+  __shared__ uint32_t cnt[kRadix];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t n = clamped(n_ptr, capacity);
   if (blockIdx.x * kSortTile >= n) return;  // a tile past the end (its row entries are not read)
-  for (int d = threadIdx.x; d < kWaves * kRadix; d += kSortBlock) (&wcnt[0][0])[d] = 0;
+  cnt[threadIdx.x] = 0u;
   const uint32_t base = blockIdx.x * kSortTile + wave * (kSortTile / kWaves);
   // every round's digit is loaded before any is counted, so the loads are in
-  // flight together; positions past the end read the last key and are left
-  // out of the counts
+  // flight together; positions past the end read the last key and are not
+  // counted
   uint32_t dig[kRounds];
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) dig[r] = (uint32_t)(keys[min(base + r * 64 + lane, n - 1)] >> shift) & 0xffu;
+  for (int r = 0; r < kRounds; ++r) dig[r] = (uint32_t)(keys[min(base + r * 64 + lane, n - 1)] >> shift) & mask;
   __syncthreads();
+  // LDS atomic increments: integer counts, so the order does not matter
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
-    const bool ok = base + r * 64 + lane < n;
-    const uint64_t peers = match_digit(dig[r], __ballot(ok));
-    if (ok && (peers & lanemask_lt()) == 0) wcnt[wave][dig[r]] += (uint32_t)__popcll(peers);
-  }
+  for (int r = 0; r < kRounds; ++r)
+    if (base + r * 64 + lane < n) atomicAdd(&cnt[dig[r]], 1u);
   __syncthreads();
-  const int d = threadIdx.x;
-  uint32_t s = 0;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) s += wcnt[w][d];
-  hist[(size_t)d * gridDim.x + blockIdx.x] = s;
+  hist[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
 }
 
 // Exclusive scan of one value per thread over the 256-thread workgroup;
@@ -218,7 +245,8 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
                                                                    const uint32_t* __restrict__ vals_in,
                                                                    K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
                                                                    const uint32_t* __restrict__ n_ptr, uint32_t capacity,
-                                                                   int shift, const uint32_t* __restrict__ hist_scan,
+                                                                   int shift, uint32_t mask,
+                                                                   const uint32_t* __restrict__ hist_scan,
                                                                    const uint32_t* __restrict__ row_total,
                                                                    const uint32_t* __restrict__ gather_src,
                                                                    uint32_t* __restrict__ gather_dst,
@@ -256,7 +284,7 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t idx = base + r * 64 + lane;
     const bool ok = idx < n;
-    const uint32_t d = (uint32_t)(k[r] >> shift) & 0xffu;
+    const uint32_t d = (uint32_t)(k[r] >> shift) & mask;
     const uint64_t active = __ballot(ok);
     const uint64_t peers = match_digit(d, active);
     const uint32_t before = wcnt[wave][d];
@@ -295,7 +323,7 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t idx = base + r * 64 + lane;
     if (idx < n) {
-      const uint32_t d = (uint32_t)(k[r] >> shift) & 0xffu;
+      const uint32_t d = (uint32_t)(k[r] >> shift) & mask;
       const uint32_t pos = dstart[d] + wcnt[wave][d] + loc[r];
       skeys[pos] = k[r];
       svals[pos] = v[r];
@@ -310,7 +338,7 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
     for (int r = 0; r < kRounds; ++r) {
       const uint32_t p = r * kSortBlock + threadIdx.x;
       const K key = skeys[p];
-      const uint32_t d = (uint32_t)(key >> shift) & 0xffu;
+      const uint32_t d = (uint32_t)(key >> shift) & mask;
       const uint32_t g = gbase[d] + (p - dstart[d]);
       const uint32_t val = svals[p];
       keys_out[g] = key;
@@ -339,7 +367,7 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
   }
   for (uint32_t p = threadIdx.x; p < tile_n; p += kSortBlock) {
     const K key = skeys[p];
-    const uint32_t d = (uint32_t)(key >> shift) & 0xffu;
+    const uint32_t d = (uint32_t)(key >> shift) & mask;
     const uint32_t g = gbase[d] + (p - dstart[d]);
     const uint32_t val = svals[p];
     keys_out[g] = key;
@@ -380,9 +408,15 @@ hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, 
   K* kin = keys; uint32_t* vin = vals;
   K* kout = keys_alt; uint32_t* vout = vals_alt;
   int alt = 0;
-  for (int shift = 0; shift < key_bits; shift += 8) {
-    const bool last = shift + 8 >= key_bits;
-    hipLaunchKernelGGL(radix_hist_kernel<K>, dim3(blocks), dim3(kSortBlock), 0, s, kin, n_ptr, capacity, shift, hist);
+  // passes of at most 8 bits, the narrower digits first (the first pass
+  // scatters into the most runs per tile, so its runs are made longer)
+  const int passes = (key_bits + 7) / 8;
+  for (int pass = 0, shift = 0; pass < passes; ++pass) {
+    const int bits = key_bits / passes + (pass >= passes - key_bits % passes ? 1 : 0);
+    const uint32_t mask = (1u << bits) - 1u;
+    const bool last = pass == passes - 1;
+    hipLaunchKernelGGL(radix_hist_kernel<K>, dim3(blocks), dim3(kSortBlock), 0, s, kin, n_ptr, capacity, shift, mask,
+                       hist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(radix_offsets_kernel, dim3(kRadix), dim3(kSortBlock), 0, s, hist, blocks, n_ptr, capacity,
@@ -390,7 +424,7 @@ hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, 
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(radix_scatter_kernel<K>, dim3(blocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout, n_ptr,
-                       capacity, shift, hist_scan, row_total, last ? gather_src : nullptr,
+                       capacity, shift, mask, hist_scan, row_total, last ? gather_src : nullptr,
                        last ? gather_dst : nullptr, last ? rect_src : nullptr, last ? rect_dst : nullptr,
                        last ? count_dst : nullptr);
     e = hipGetLastError();
@@ -398,6 +432,7 @@ hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, 
     K* tk = kin; kin = kout; kout = tk;
     uint32_t* tv = vin; vin = vout; vout = tv;
     alt ^= 1;
+    shift += bits;
   }
   *result_in_alt = alt;
   return hipSuccess;
@@ -503,8 +538,8 @@ hipError_t launch_emit(const CallTables* d_tab, const CallTables& h, const uint3
                        const uint2* sorted_rect, const uint32_t* pair_off, const uint32_t* n_visible, Counters* cnt,
                        uint32_t* keys, uint32_t* vals, uint32_t capacity, hipStream_t s) {
   if (h.n_records == 0) return hipSuccess;
-  hipLaunchKernelGGL(emit_kernel, dim3(div_up(h.n_records, 256)), dim3(256), 0, s, d_tab, sorted_rec, sorted_rect,
-                     pair_off, n_visible, cnt, h.n_records, capacity, keys, vals);
+  hipLaunchKernelGGL(emit_kernel, dim3(div_up(h.n_records, kEmitBlock)), dim3(kEmitBlock), 0, s, d_tab, sorted_rec,
+                     sorted_rect, pair_off, n_visible, cnt, h.n_records, capacity, keys, vals);
   return hipGetLastError();
 }
 
@@ -522,8 +557,7 @@ hipError_t launch_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint3
 
 hipError_t launch_ranges(const uint32_t* tiles, const Counters* cnt, uint32_t capacity, uint2* ranges,
                          uint32_t n_tiles, hipStream_t s) {
-  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * (size_t)n_tiles, s);
-  if (e != hipSuccess || capacity == 0) return e;
+  if (capacity == 0) return hipSuccess;  // (the projection left every range empty)
   hipLaunchKernelGGL(ranges_kernel, dim3(div_up(capacity, 256)), dim3(256), 0, s, tiles, &cnt->pairs, capacity, ranges,
                      n_tiles);
   return hipGetLastError();
