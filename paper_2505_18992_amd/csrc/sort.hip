@@ -173,10 +173,20 @@ __global__ void __launch_bounds__(kSortBlock) radix_hist_kernel(const K* __restr
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) dig[r] = (uint32_t)(keys[min(base + r * 64 + lane, n - 1)] >> shift) & mask;
   __syncthreads();
-  // LDS atomic increments: integer counts, so the order does not matter
+  // LDS atomic increments (integer counts: the order does not matter); a
+  // round whose keys share one digit (the high byte of nearby depths) adds
+  // its count once instead of serialising 64 increments of one address
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r)
-    if (base + r * 64 + lane < n) atomicAdd(&cnt[dig[r]], 1u);
+  for (int r = 0; r < kRounds; ++r) {
+    const bool ok = base + r * 64 + lane < n;
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(dig[r]);
+    const uint64_t act = __ballot(ok);
+    if (__ballot(ok && dig[r] == d0) == act) {
+      if (lane == 0 && act != 0ull) atomicAdd(&cnt[d0], (uint32_t)__popcll(act));
+    } else if (ok) {
+      atomicAdd(&cnt[dig[r]], 1u);
+    }
+  }
   __syncthreads();
   hist[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
 }
@@ -441,18 +451,31 @@ hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, 
 // ---------------------------------------------------------------------------
 // ranges and key export
 // ---------------------------------------------------------------------------
+// Four sorted keys per thread (one 16-byte load when it lies within the
+// buffer) and their two neighbours.
 __global__ void ranges_kernel(const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ n_ptr,
                               uint32_t capacity, uint2* __restrict__ ranges, uint32_t n_tiles) {
   const uint32_t n = clamped(n_ptr, capacity);
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  // the three loads are independent, so they are in flight together
-  const uint32_t t = tiles[k];
-  const uint32_t prev = tiles[k > 0 ? k - 1 : k];
-  const uint32_t next = tiles[k + 1 < n ? k + 1 : k];
-  if (t >= n_tiles) return;
-  if (k == 0 || prev != t) ranges[t].x = k;
-  if (k == n - 1 || next != t) ranges[t].y = k + 1;
+  const uint32_t k0 = (blockIdx.x * blockDim.x + threadIdx.x) * 4u;
+  if (k0 >= n) return;
+  uint32_t t[4];
+  if (k0 + 4u <= capacity) {
+    const uint4 q = *reinterpret_cast<const uint4*>(tiles + k0);
+    t[0] = q.x; t[1] = q.y; t[2] = q.z; t[3] = q.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) t[j] = k0 + j < n ? tiles[k0 + j] : 0u;
+  }
+  const uint32_t prev = k0 > 0 ? tiles[k0 - 1] : 0u;
+  const uint32_t next = k0 + 4u < n ? tiles[k0 + 4u] : 0u;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t k = k0 + j;
+    if (k >= n || t[j] >= n_tiles) continue;
+    const uint32_t before = j > 0 ? t[j - 1] : prev, after = j < 3 ? t[j + 1] : next;
+    if (k == 0 || before != t[j]) ranges[t[j]].x = k;
+    if (k == n - 1 || after != t[j]) ranges[t[j]].y = k + 1;
+  }
 }
 
 __global__ void key64_kernel(const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ rec_of,
@@ -558,7 +581,7 @@ hipError_t launch_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint3
 hipError_t launch_ranges(const uint32_t* tiles, const Counters* cnt, uint32_t capacity, uint2* ranges,
                          uint32_t n_tiles, hipStream_t s) {
   if (capacity == 0) return hipSuccess;  // (the projection left every range empty)
-  hipLaunchKernelGGL(ranges_kernel, dim3(div_up(capacity, 256)), dim3(256), 0, s, tiles, &cnt->pairs, capacity, ranges,
+  hipLaunchKernelGGL(ranges_kernel, dim3(div_up(capacity, 1024)), dim3(256), 0, s, tiles, &cnt->pairs, capacity, ranges,
                      n_tiles);
   return hipGetLastError();
 }
