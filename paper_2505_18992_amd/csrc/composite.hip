@@ -11,10 +11,12 @@
 // shows every pixel done.
 //
 // The backward walks the same slice in reverse from the last blended entry,
-// recovers the transmittance by division and recomputes alpha with the
-// forward's exact instruction sequence (nothing per (pixel, Gaussian) is
-// stored).  Per-Gaussian gradients are reduced across the wavefront before
-// one set of atomic adds per (wavefront, Gaussian).
+// in the forward's batches, recovers the transmittance by division and
+// recomputes alpha with the forward's exact instruction sequence (nothing per
+// (pixel, Gaussian) is stored; per (wavefront, batch) the forward leaves the
+// bits of the entries that reach the wavefront's quadrant, so the backward
+// does not test them again).  Per-Gaussian gradients are reduced across the
+// wavefront before one set of atomic adds per (wavefront, Gaussian).
 #include "internal.h"
 
 namespace vpgs {
@@ -117,36 +119,69 @@ struct Quadrant {
 };
 
 // Compacts the staged entries [0, n) that reach the wavefront's quadrant
-// into list[] -- in staging order, or in reverse order if DESC --
-// pads it with the sentinel index BS to a multiple of kGroup and returns the
-// number of hits (the same in every lane).  Lane l tests entries l, l + 64,
-// ...; a ballot and a lane-prefix count give each hit its slot.  All lanes
-// of the wavefront must be active; the list is read after the next
-// workgroup barrier.
-template <int BS, bool DESC, int TW, int TH>
+// into list[], in staging order, pads it with the sentinel index BS to a
+// multiple of kGroup and returns the number of hits (the same in every
+// lane); lane 0 also stores the batch's hit bits (one 64-bit word per 64
+// entries) in mask_out, from which the backward rebuilds the list.  Lane l
+// tests entries l, l + 64, ...; a ballot and a lane-prefix count give each
+// hit its slot.  All lanes of the wavefront must be active; the list is read
+// after the next workgroup barrier.
+template <int BS, int TW, int TH>
 __device__ __forceinline__ int wave_hits(const float4* A, const float4* E, int n, const Quadrant<TW, TH>& q,
-                                         uint16_t* list) {
+                                         uint16_t* list, uint64_t* mask_out) {
   const int lane = threadIdx.x & 63;
   int count = 0;
 #pragma unroll
   for (int k = 0; k < BS / 64; ++k) {
-    const int e = DESC ? n - 1 - (k * 64 + lane) : k * 64 + lane;
-    const bool hit = (DESC ? e >= 0 : e < n) && q.reaches(A[e], E[e]);
+    const int e = k * 64 + lane;
+    const bool hit = e < n && q.reaches(A[e], E[e]);
     const uint64_t m = __ballot(hit);
     const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
     if (hit) list[count + below] = (uint16_t)e;
+    if (lane == 0) mask_out[k] = m;
     count += __popcll(m);
   }
   if (lane < ((count + kGroup - 1) & ~(kGroup - 1)) - count) list[count + lane] = (uint16_t)BS;
   return count;
 }
 
+// The backward's list of a batch from the forward's masks: the entries
+// below n whose bit is set, in descending order.  All lanes of the
+// wavefront must be active.
+template <int BS>
+__device__ __forceinline__ int mask_hits_desc(const uint64_t* mask, int n, uint16_t* list) {
+  const int lane = threadIdx.x & 63;
+  int count = 0;
+#pragma unroll
+  for (int k = BS / 64 - 1; k >= 0; --k) {
+    const int lo = k * 64;
+    uint64_t m = mask[k];
+    if (n <= lo) m = 0ull;
+    else if (n < lo + 64) m &= (1ull << (n - lo)) - 1ull;
+    const int above = __popcll((m >> lane) >> 1);  // set bits of the higher lanes
+    if ((m >> lane) & 1ull) list[count + above] = (uint16_t)(lo + lane);
+    count += __popcll(m);
+  }
+  return count;
+}
+
+// The per-wavefront hit masks of every (tile, batch) that the forward
+// composites: BS/64 words of 64 bits per wavefront.  The batches of a tile
+// take consecutive slots from first_slot = start / BS + tile (start = the
+// tile's first pair): the slots of consecutive tiles do not overlap, and
+// every slot is below capacity / BS + n_tiles.
+template <int BS>
+__device__ __forceinline__ size_t batch_mask_index(uint32_t start, uint32_t tile, int batch, int wave) {
+  const size_t slot = (size_t)(start / BS) + tile + (size_t)batch;
+  return (slot * (BS / 64) + wave) * (BS / 64);
+}
+
 template <int TW, int TH>
 __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab, const float4* __restrict__ recs,
                                              const uint2* __restrict__ ranges,
                                              const uint32_t* __restrict__ vals, float* __restrict__ T_final,
-                                             uint32_t* __restrict__ n_contrib, uint32_t tile, FwdShared<TW, TH>& sh,
-                                             uint32_t& ne, uint32_t& nb) {
+                                             uint32_t* __restrict__ n_contrib, uint64_t* __restrict__ masks,
+                                             uint32_t tile, FwdShared<TW, TH>& sh, uint32_t& ne, uint32_t& nb) {
   constexpr int BS = TW * TH;
   const ViewDesc& V = tab->views[view_of_tile(tab, tile)];
   const uint32_t lt = tile - V.tile_base;
@@ -182,7 +217,9 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
       const float4* r = recs + rec_slot(vals[nidx], 0);
       pA = r[0]; pR = r[1]; pC = r[2];
     }
-    const int nhit = wave_hits<BS, false>(sh.A, sh.E, (int)min((uint32_t)BS, rg.y - start), q, hits);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint64_t* wm = masks + batch_mask_index<BS>(rg.x, tile, (int)((start - rg.x) / BS), wave);
+    const int nhit = wave_hits<BS>(sh.A, sh.E, (int)min((uint32_t)BS, rg.y - start), q, hits, wm);
     __syncthreads();
     const uint32_t base = start - rg.x + 1u;
     for (int g = 0; g < nhit && __ballot(!done) != 0ull; g += kGroup) {
@@ -253,7 +290,8 @@ template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
     const CallTables* __restrict__ tab, const float4* __restrict__ recs, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals, float* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
-    const uint32_t* __restrict__ order, Counters* __restrict__ cnt, uint32_t* __restrict__ queue, uint32_t n_tiles) {
+    uint64_t* __restrict__ masks, const uint32_t* __restrict__ order, Counters* __restrict__ cnt,
+    uint32_t* __restrict__ queue, uint32_t n_tiles) {
   __shared__ FwdShared<TW, TH> sh;
   __shared__ uint32_t slot;
   uint32_t ne = 0, nb = 0;
@@ -264,11 +302,11 @@ __global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
   }
   if (queue == nullptr) {
     const uint32_t tile = order[blockIdx.x];
-    if (tile < n_tiles) forward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, tile, sh, ne, nb);
+    if (tile < n_tiles) forward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, masks, tile, sh, ne, nb);
   } else {
     for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot)) {
       const uint32_t tile = order[t];
-      if (tile < n_tiles) forward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, tile, sh, ne, nb);
+      if (tile < n_tiles) forward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, masks, tile, sh, ne, nb);
     }
   }
   flush_counts(ne, nb, cnt);
@@ -343,7 +381,8 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
                                               const uint2* __restrict__ ranges,
                                               const uint32_t* __restrict__ vals, const float* __restrict__ T_final,
                                               const uint32_t* __restrict__ n_contrib, float* __restrict__ acc,
-                                              uint32_t tile, BwdShared<TW, TH>& sh) {
+                                              const uint64_t* __restrict__ masks, uint32_t tile,
+                                              BwdShared<TW, TH>& sh) {
   constexpr int BS = TW * TH;
   const ViewDesc& V = tab->views[view_of_tile(tab, tile)];
   const uint32_t lt = tile - V.tile_base;
@@ -372,6 +411,7 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
   uint32_t wave_last = last;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, off, 64));
+  wave_last = __builtin_amdgcn_readfirstlane(wave_last);  // the same in every lane
   if (lane == 0) sh.maxlast[threadIdx.x >> 6] = wave_last;
   __syncthreads();
   uint32_t max_last = 0;
@@ -379,8 +419,11 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
   for (int w = 0; w < BS / 64; ++w) max_last = max(max_last, sh.maxlast[w]);
 
   float S = 0.f;  // sum over blended entries behind the current one of alpha T f
-  for (int end = (int)max_last; end > 0; end -= BS) {
-    const int begin = end - BS > 0 ? end - BS : 0;
+  // the forward's batches, last first (their hit masks are the forward's)
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int b = (int)((max_last + BS - 1) / BS) - 1; b >= 0; --b) {
+    const int begin = b * BS;
+    const int end = min(begin + BS, (int)max_last);
     __syncthreads();
     {
       const int j = begin + (int)threadIdx.x;
@@ -397,8 +440,9 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
     }
     __syncthreads();
     // entries of this wavefront: those before its own last blended one
-    uint16_t* hits = sh.hits[threadIdx.x >> 6];
-    const int nhit = wave_hits<BS, true>(sh.A, sh.E, min(end, (int)wave_last) - begin, q, hits);
+    uint16_t* hits = sh.hits[wave];
+    const int nhit =
+        mask_hits_desc<BS>(masks + batch_mask_index<BS>(rg.x, tile, b, wave), min(end, (int)wave_last) - begin, hits);
     __syncthreads();
     for (int i = 0; i < nhit; ++i) {
       const int sl = hits[i];
@@ -445,7 +489,8 @@ __global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
     const CallTables* __restrict__ tab, const float4* __restrict__ recs, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals,
     const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib, float* __restrict__ acc,
-    const uint32_t* __restrict__ order, uint32_t* __restrict__ queue, uint32_t n_tiles) {
+    const uint64_t* __restrict__ masks, const uint32_t* __restrict__ order, uint32_t* __restrict__ queue,
+    uint32_t n_tiles) {
   __shared__ BwdShared<TW, TH> sh;
   __shared__ uint32_t slot;
   if (threadIdx.x == 0) {  // the sentinel slot (read after the first staging barrier)
@@ -454,11 +499,11 @@ __global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
   }
   if (queue == nullptr) {
     const uint32_t tile = order[blockIdx.x];
-    if (tile < n_tiles) backward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, acc, tile, sh);
+    if (tile < n_tiles) backward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, acc, masks, tile, sh);
   } else {
     for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot)) {
       const uint32_t tile = order[t];
-      if (tile < n_tiles) backward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, acc, tile, sh);
+      if (tile < n_tiles) backward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, acc, masks, tile, sh);
     }
   }
 }
@@ -466,20 +511,21 @@ __global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
 template <int TW, int TH>
 hipError_t launch_fwd_t(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb, const uint2* ranges,
                         const uint32_t* vals, const uint32_t* order, float* T_final, uint32_t* n_contrib,
-                        Counters* cnt, uint32_t* queue, uint32_t blocks, hipStream_t s) {
+                        uint64_t* masks, Counters* cnt, uint32_t* queue, uint32_t blocks, hipStream_t s) {
   const uint32_t grid = queue ? blocks : h.n_tiles;
   hipLaunchKernelGGL((composite_forward_kernel<TW, TH>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.rec,
-                     ranges, vals, T_final, n_contrib, order, cnt, queue, h.n_tiles);
+                     ranges, vals, T_final, n_contrib, masks, order, cnt, queue, h.n_tiles);
   return hipGetLastError();
 }
 
 template <int TW, int TH>
 hipError_t launch_bwd_t(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb, const uint2* ranges,
                         const uint32_t* vals, const uint32_t* order, const float* T_final,
-                        const uint32_t* n_contrib, float* acc, uint32_t* queue, uint32_t blocks, hipStream_t s) {
+                        const uint32_t* n_contrib, const uint64_t* masks, float* acc, uint32_t* queue,
+                        uint32_t blocks, hipStream_t s) {
   const uint32_t grid = queue ? blocks : h.n_tiles;
   hipLaunchKernelGGL((composite_backward_kernel<TW, TH>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.rec,
-                     ranges, vals, T_final, n_contrib, acc, order, queue, h.n_tiles);
+                     ranges, vals, T_final, n_contrib, acc, masks, order, queue, h.n_tiles);
   return hipGetLastError();
 }
 
@@ -489,14 +535,19 @@ bool tile_shape_supported(int tw, int th) {
   return (tw == 16 && th == 16) || (tw == 16 && th == 8) || (tw == 8 && th == 8) || (tw == 32 && th == 8);
 }
 
+size_t hit_mask_bytes(uint32_t capacity, uint32_t n_tiles, int tile_w, int tile_h) {
+  const size_t bs = (size_t)tile_w * tile_h, words = (bs / 64) * (bs / 64);
+  return ((size_t)capacity / bs + n_tiles + 1) * words * sizeof(uint64_t);
+}
+
 hipError_t launch_composite_forward(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb,
                                     const uint2* ranges, const uint32_t* vals, const uint32_t* order,
-                                    float* T_final, uint32_t* n_contrib, Counters* cnt, int tile_w, int tile_h,
-                                    uint32_t* queue, uint32_t blocks, hipStream_t s) {
+                                    float* T_final, uint32_t* n_contrib, uint64_t* masks, Counters* cnt, int tile_w,
+                                    int tile_h, uint32_t* queue, uint32_t blocks, hipStream_t s) {
   if (h.n_tiles == 0) return hipSuccess;
 #define VPGS_FWD(TW, TH) \
   if (tile_w == TW && tile_h == TH) \
-    return launch_fwd_t<TW, TH>(d_tab, h, pb, ranges, vals, order, T_final, n_contrib, cnt, queue, blocks, s);
+    return launch_fwd_t<TW, TH>(d_tab, h, pb, ranges, vals, order, T_final, n_contrib, masks, cnt, queue, blocks, s);
   VPGS_FWD(16, 16) VPGS_FWD(16, 8) VPGS_FWD(8, 8) VPGS_FWD(32, 8)
 #undef VPGS_FWD
   return hipErrorInvalidValue;
@@ -504,12 +555,14 @@ hipError_t launch_composite_forward(const CallTables* d_tab, const CallTables& h
 
 hipError_t launch_composite_backward(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb,
                                      const uint2* ranges, const uint32_t* vals, const uint32_t* order,
-                                     const float* T_final, const uint32_t* n_contrib, float* acc, int tile_w,
-                                     int tile_h, uint32_t* queue, uint32_t blocks, hipStream_t s) {
+                                     const float* T_final, const uint32_t* n_contrib, const uint64_t* masks,
+                                     float* acc, int tile_w, int tile_h, uint32_t* queue, uint32_t blocks,
+                                     hipStream_t s) {
   if (h.n_tiles == 0) return hipSuccess;
 #define VPGS_BWD(TW, TH) \
   if (tile_w == TW && tile_h == TH) \
-    return launch_bwd_t<TW, TH>(d_tab, h, pb, ranges, vals, order, T_final, n_contrib, acc, queue, blocks, s);
+    return launch_bwd_t<TW, TH>(d_tab, h, pb, ranges, vals, order, T_final, n_contrib, masks, acc, queue, blocks, \
+                                s);
   VPGS_BWD(16, 16) VPGS_BWD(16, 8) VPGS_BWD(8, 8) VPGS_BWD(32, 8)
 #undef VPGS_BWD
   return hipErrorInvalidValue;

@@ -91,7 +91,7 @@ void free_buf(DevBuf& b) {
 namespace vpgs {
 
 void destroy_saved(vpgs_saved* s) {
-  DevBuf* bufs[] = {&s->tab, &s->rec, &s->count, &s->zkey, &s->rect, &s->drect, &s->scan_ws,
+  DevBuf* bufs[] = {&s->tab, &s->rec, &s->count, &s->zkey, &s->rect, &s->drect, &s->hitmask, &s->scan_ws,
                     &s->keys, &s->vals, &s->keys_alt, &s->vals_alt, &s->sort_ws, &s->ranges, &s->tfinal,
                     &s->ncontrib, &s->counters, &s->acc, &s->pose_partial, &s->dk, &s->dk_alt, &s->dv,
                     &s->dv_alt, &s->dcount, &s->dpoff, &s->key64, &s->order};
@@ -303,7 +303,8 @@ int ensure_pairs(vpgs_ctx* ctx, vpgs_saved* sv, uint32_t cap) {
   if ((rc = ensure(ctx, sv->keys, (size_t)cap * 4)) || (rc = ensure(ctx, sv->keys_alt, (size_t)cap * 4)) ||
       (rc = ensure(ctx, sv->vals, (size_t)cap * 4)) || (rc = ensure(ctx, sv->vals_alt, (size_t)cap * 4)) ||
       (rc = ensure(ctx, sv->sort_ws,
-                   sort_workspace_bytes(std::max<uint32_t>(cap, sv->h_tab->n_records)))))
+                   sort_workspace_bytes(std::max<uint32_t>(cap, sv->h_tab->n_records)))) ||
+      (rc = ensure(ctx, sv->hitmask, hit_mask_bytes(cap, sv->h_tab->n_tiles, sv->tile_w, sv->tile_h))))
     return rc;
   sv->capacity = cap;
   return VPGS_OK;
@@ -429,7 +430,8 @@ int enqueue_back(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
   {
     StageTimer t(ctx, ST_FWD, st);
     HIP_TRY(launch_composite_forward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
-                                     static_cast<const uint32_t*>(sv->order.p), static_cast<float*>(sv->tfinal.p), static_cast<uint32_t*>(sv->ncontrib.p), cnt,
+                                     static_cast<const uint32_t*>(sv->order.p), static_cast<float*>(sv->tfinal.p),
+                                     static_cast<uint32_t*>(sv->ncontrib.p), static_cast<uint64_t*>(sv->hitmask.p), cnt,
                                      sv->tile_w, sv->tile_h, sv->persistent_blocks ? &cnt->queue_fwd : nullptr,
                                      sv->persistent_blocks, st));
   }
@@ -451,7 +453,8 @@ int enqueue_backward(vpgs_ctx* ctx, vpgs_saved* sv, float* d_pose, hipStream_t s
     StageTimer t(ctx, ST_BWD, st);
     HIP_TRY(launch_composite_backward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
                                       static_cast<const uint32_t*>(sv->order.p), static_cast<const float*>(sv->tfinal.p),
-                                      static_cast<const uint32_t*>(sv->ncontrib.p), acc, sv->tile_w, sv->tile_h,
+                                      static_cast<const uint32_t*>(sv->ncontrib.p),
+                                      static_cast<const uint64_t*>(sv->hitmask.p), acc, sv->tile_w, sv->tile_h,
                                       sv->persistent_blocks ? &cnt->queue_bwd : nullptr, sv->persistent_blocks, st));
   }
   float* partial = d_pose ? static_cast<float*>(sv->pose_partial.p) : nullptr;

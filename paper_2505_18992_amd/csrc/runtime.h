@@ -30,7 +30,7 @@ struct vpgs_saved {
   // event so an in-flight upload is never overwritten
   vpgs::CallTables* h_tab = nullptr;
   hipEvent_t tab_uploaded = nullptr;
-  vpgs::DevBuf tab, rec, count, zkey, rect, drect, scan_ws, keys, vals, keys_alt, vals_alt, sort_ws, ranges,
+  vpgs::DevBuf tab, rec, count, zkey, rect, drect, hitmask, scan_ws, keys, vals, keys_alt, vals_alt, sort_ws, ranges,
       tfinal, ncontrib, counters, acc, pose_partial, dk, dk_alt, dv, dv_alt, dcount, dpoff, key64, order;
   int result_in_alt = 0;
   int depth_in_alt = 0;
