@@ -94,23 +94,25 @@ struct Quadrant {
   // f(d) = a dx^2 + b dx dy + c dy^2 (a = -E.x, b = -E.y, c = -E.z, d = mean
   // - pixel centre), a positive-definite form, so alpha >= 1/255 somewhere
   // in the quadrant iff E.w - min f >= log2(1/255) over the rectangle of
-  // pixel centres.  The minimum is 0 if d = 0 lies inside, else it is on an
-  // edge, where f is a 1-D quadratic minimised at its clamped vertex.  The
-  // margin covers the float32 rounding of f here and in the per-pixel
-  // evaluation (a few ulps of the largest |term| over the rectangle), so
-  // every pixel whose float32 alpha passes the cutoff is kept: the test only
-  // removes work.
+  // pixel centres.  f decreases along the segment from any point of the
+  // rectangle to the mean, and that segment leaves the rectangle through an
+  // edge facing the mean, so the minimum lies on the facing vertical edge
+  // (x the mean's x clamped to the rectangle) or the facing horizontal one;
+  // along each, f is a 1-D quadratic minimised at its clamped vertex (with
+  // the mean inside, both give f = 0).  The margin covers the float32
+  // rounding of f here and in the per-pixel evaluation (a few ulps of the
+  // largest |term| over the rectangle), so every pixel whose float32 alpha
+  // passes the cutoff is kept: the test only removes work.
   __device__ __forceinline__ bool reaches(const float4 A, const float4 E) const {
     const float a = -E.x, b = -E.y, c = -E.z;
     const float dx0 = A.x - x1, dx1 = A.x - x0, dy0 = A.y - y1, dy1 = A.y - y0;
     const float ra = __builtin_amdgcn_rcpf(2.0f * a), rc = __builtin_amdgcn_rcpf(2.0f * c);
     auto f = [&](float dx, float dy) { return fmaf(fmaf(b, dy, a * dx), dx, c * dy * dy); };
-    const float e0 = f(dx0, fminf(fmaxf(-b * dx0 * rc, dy0), dy1));
-    const float e1 = f(dx1, fminf(fmaxf(-b * dx1 * rc, dy0), dy1));
-    const float e2 = f(fminf(fmaxf(-b * dy0 * ra, dx0), dx1), dy0);
-    const float e3 = f(fminf(fmaxf(-b * dy1 * ra, dx0), dx1), dy1);
-    const bool inside = dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f;
-    const float fmin = inside ? 0.0f : fminf(fminf(e0, e1), fminf(e2, e3));
+    const float dxe = fminf(fmaxf(0.0f, dx0), dx1);  // mean - nearest x of the rectangle
+    const float dye = fminf(fmaxf(0.0f, dy0), dy1);
+    const float ev = f(dxe, fminf(fmaxf(-b * dxe * rc, dy0), dy1));
+    const float eh = f(fminf(fmaxf(-b * dye * ra, dx0), dx1), dye);
+    const float fmin = fminf(ev, eh);
     const float mx = fmaxf(dx0 * dx0, dx1 * dx1), my = fmaxf(dy0 * dy0, dy1 * dy1);
     const float fabs_max = fmaf(a, mx, fmaf(fabsf(b), sqrtf(mx * my), c * my));
     const float margin = fmaf(16.0f * 1.1920929e-7f, fabs_max + fabsf(E.w), 1e-6f);
