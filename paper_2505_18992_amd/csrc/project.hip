@@ -202,42 +202,18 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
   const float o_acc = track ? fmaxf(S.opacities[ii], 0.0f) : 0.0f;
   float a_grad = 0.f, a_ren = 0.f, a_op = 0.f, a_seen = 0.f;
 
-  // The loads run ahead of the views: the tile counts two views ahead and
-  // the accumulated gradient row of the next view are in flight while the
-  // current view is processed.
-  const int n_sv = S.view_count;
-  auto rec_of = [&](int vi) { return tab->views[tab->set_views[S.view_first + vi]].rec_base + (uint32_t)ii; };
-  uint32_t cnt_cur = n_sv > 0 ? pb.count[rec_of(0)] : 0u;
-  uint32_t cnt_next = n_sv > 1 ? pb.count[rec_of(1)] : 0u;
-  float row[kNumAcc];
-#pragma unroll
-  for (int k = 0; k < kNumAcc; ++k) row[k] = 0.0f;
-  if (live && cnt_cur != 0) {
-    const float* g = acc + (size_t)rec_of(0) * kNumAcc;
-#pragma unroll
-    for (int k = 0; k < kNumAcc; ++k) row[k] = g[k];
-  }
-  for (int vi = 0; vi < n_sv; ++vi) {
-    const uint32_t cnt_after = vi + 2 < n_sv ? pb.count[rec_of(vi + 2)] : 0u;
-    float next_row[kNumAcc];
-#pragma unroll
-    for (int k = 0; k < kNumAcc; ++k) next_row[k] = 0.0f;
-    if (live && vi + 1 < n_sv && cnt_next != 0) {
-      const float* g = acc + (size_t)rec_of(vi + 1) * kNumAcc;
-#pragma unroll
-      for (int k = 0; k < kNumAcc; ++k) next_row[k] = g[k];
-    }
+  for (int vi = 0; vi < S.view_count; ++vi) {
     const int v = tab->set_views[S.view_first + vi];
     const ViewDesc& V = tab->views[v];
     const uint32_t rec = V.rec_base + (uint32_t)ii;
     float pose[6] = {0, 0, 0, 0, 0, 0};
-    if (live && cnt_cur != 0) {
-      // the record's accumulated gradient (read ahead); its row is left zero
-      // for the next backward (rows of culled records are never touched)
-      const float m0 = row[0], m1 = row[1], m2 = row[2], m3 = row[3], m4 = row[4], go = row[5];
-      const float gz_direct = row[9];
-      const float gc0 = row[6], gc1 = row[7], gc2 = row[8];
+    if (live && pb.count[rec] != 0) {
+      // read the record's accumulated gradient and leave its row zero for
+      // the next backward (rows of culled records are never touched)
       float* g = acc + (size_t)rec * kNumAcc;
+      const float m0 = g[0], m1 = g[1], m2 = g[2], m3 = g[3], m4 = g[4], go = g[5];
+      const float gz_direct = g[9];
+      const float gc0 = g[6], gc1 = g[7], gc2 = g[8];
 #pragma unroll
       for (int k = 0; k < kNumAcc; ++k) g[k] = 0.0f;
       dop += go;
@@ -347,10 +323,6 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
         for (int k = 0; k < 6; ++k) dst[k] = pose[k];
       }
     }
-#pragma unroll
-    for (int k = 0; k < kNumAcc; ++k) row[k] = next_row[k];
-    cnt_cur = cnt_next;
-    cnt_next = cnt_after;
   }
   if (!live) return;
   // Sg = M M^T with M = R_q diag(s):  dM = 2 dSg M
