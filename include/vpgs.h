@@ -62,6 +62,7 @@ extern "C" {
 #define VPGS_MAX_VIEWS 64       /* views per call */
 #define VPGS_MAX_SETS 64        /* distinct Gaussian sets per call */
 #define VPGS_MAX_DIM 8192       /* image width and height limit */
+#define VPGS_MAX_RECORDS 107374182  /* (view, Gaussian) records per call: sum over views of their set's size */
 
 typedef struct vpgs_ctx vpgs_ctx;
 typedef struct vpgs_saved vpgs_saved;
@@ -155,7 +156,9 @@ int vpgs_version(void);
  * into out[v] (host array of device planes).  If `saved` is non-NULL a
  * saved-state handle for vpgs_render_backward is returned; it must be
  * released with vpgs_saved_release.  The Gaussian and camera buffers must not
- * change between the forward and its backward. */
+ * change between the forward and its backward.  VPGS_EINVAL if the views hold
+ * more than VPGS_MAX_RECORDS records in all (the backward addresses each
+ * record's 40-byte gradient row with a 32-bit byte offset). */
 int vpgs_render_forward(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, int n_views,
                         const int32_t* view_set, const vpgs_camera* cams, const vpgs_images* out,
                         const vpgs_render_opts* opts, vpgs_saved** saved, void* stream);

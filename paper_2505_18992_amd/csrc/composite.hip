@@ -370,10 +370,12 @@ __device__ __forceinline__ bool scatter_writer(int lane) {
   return (lane & 3) == 0 && (((lane >> 2) & 1) == 0 || ((lane >> 3) & 3) == 0);
 }
 
+static_assert((uint64_t)VPGS_MAX_RECORDS * kNumAcc * sizeof(float) < (1ull << 32),
+              "accumulator rows addressed by 32-bit byte offsets");
+
 template <int TW, int TH>
 struct BwdShared {
-  float4 A[TW * TH + 1], E[TW * TH + 1], C[TW * TH + 1];  // C = (r, g, b, 1 / opacity)
-  uint32_t rec[TW * TH];
+  float4 A[TW * TH + 1], E[TW * TH + 1], C[TW * TH + 1];  // C = (r, g, b, bits of the accumulator row offset)
   uint16_t hits[(TW * TH) / 64][TW * TH + kGroup];  // per wavefront, descending
   uint32_t maxlast[(TW * TH) / 64];
 };
@@ -434,11 +436,13 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
         const float4* r = recs + rec_slot(rec, 0);
         const float4 A = r[0];
         const float4 c = r[2];
-        sh.rec[threadIdx.x] = rec;
         sh.A[threadIdx.x] = A;
         sh.E[threadIdx.x] = stage_exponent(A, r[1]);
-        sh.C[threadIdx.x] = make_float4(c.x, c.y, c.z, 1.0f / A.w);
-        }
+        // the record's accumulator row as a byte offset (below 2^32: the
+        // host bounds the records by VPGS_MAX_RECORDS), carried in the
+        // colour's free lane
+        sh.C[threadIdx.x] = make_float4(c.x, c.y, c.z, __uint_as_float(rec * (uint32_t)(kNumAcc * sizeof(float))));
+      }
     }
     __syncthreads();
     // entries of this wavefront: those before its own last blended one
@@ -446,12 +450,12 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
     const int nhit =
         mask_hits_desc<BS>(masks + batch_mask_index<BS>(rg.x, tile, b, wave), min(end, (int)wave_last) - begin, hits);
     __syncthreads();
+    const int last_in_batch = (int)last - begin;  // this pixel's entries are the slots below it
     for (int i = 0; i < nhit; ++i) {
       const int sl = hits[i];
-      const int j = begin + sl;
       const float4 A = sh.A[sl];
       const Falloff f = falloff(A, sh.E[sl], pxc, pyc);
-      const bool valid = (uint32_t)j < last && f.alpha >= kAlphaMin;
+      const bool valid = sl < last_in_batch && f.alpha >= kAlphaMin;
       if (__ballot(valid) == 0ull) continue;
       const float4 c = sh.C[sl];
       const float r1m = __builtin_amdgcn_rcpf(1.0f - f.alpha);
@@ -462,7 +466,8 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
       S = fmaf(w, fj, S);
       T = Tj;
       // s = dL/dalpha * alpha where alpha is not clamped (0 where it is):
-      // dL/dsigma = -s and dL/do = s / o.  The conic terms are accumulated
+      // dL/dsigma = -s and dL/do = s / o (the sum of s is accumulated; the
+      // projection backward divides by o).  The conic terms are accumulated
       // as moments of s over the pixel offsets d = mean - pixel centre,
       //   (sum s dx, sum s dy, sum s dx^2, sum s dx dy, sum s dy^2),
       // which the projection backward turns into dL/du, dL/dv = -Q (M0, M1)
@@ -475,13 +480,15 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
       g[2] = sx * f.dx;
       g[3] = sx * f.dy;
       g[4] = sy * f.dy;
-      g[5] = sg * c.w;
+      g[5] = sg;
       g[6] = w * gC0;
       g[7] = w * gC1;
       g[8] = w * gC2;
       g[9] = w * gD;
       const float mine = wave_reduce_scatter10(g, lane);
-      if (writer) unsafeAtomicAdd(acc + (size_t)sh.rec[sl] * kNumAcc + slot_id, mine);
+      if (writer)
+        unsafeAtomicAdd(reinterpret_cast<float*>(reinterpret_cast<char*>(acc) + (__float_as_uint(c.w) + 4u * slot_id)),
+                        mine);
     }
   }
 }

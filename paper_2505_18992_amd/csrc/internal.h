@@ -22,7 +22,7 @@ constexpr float kDefaultNear = 0.2f;
 // compositor.  With s = dL/dalpha * alpha per pixel (0 where alpha is
 // clamped) and d = (u, v) - pixel centre they hold
 //   sum s dx, sum s dy, sum s dx^2, sum s dx dy, sum s dy^2,   (conic moments)
-//   dL/dopacity, dL/d(r, g, b), dL/dz.
+//   sum s (= o dL/dopacity), dL/d(r, g, b), dL/dz.
 constexpr int kNumAcc = 10;
 
 // One view of a render call, as the kernels see it.

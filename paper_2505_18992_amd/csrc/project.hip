@@ -199,7 +199,8 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
   // expansion accumulators: screen-space gradient norm and rendered views,
   // opacity and views whose frustum holds the centre
   const bool track = S.accum != nullptr;
-  const float o_acc = track ? fmaxf(S.opacities[ii], 0.0f) : 0.0f;
+  const float o_par = S.opacities[ii];
+  const float o_acc = track ? fmaxf(o_par, 0.0f) : 0.0f;
   float a_grad = 0.f, a_ren = 0.f, a_op = 0.f, a_seen = 0.f;
 
   for (int vi = 0; vi < S.view_count; ++vi) {
@@ -216,7 +217,7 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
       const float gc0 = g[6], gc1 = g[7], gc2 = g[8];
 #pragma unroll
       for (int k = 0; k < kNumAcc; ++k) g[k] = 0.0f;
-      dop += go;
+      dop += go / o_par;  // the row holds the sum of s = o dL/do (o > 1/255 for a visible record)
       dcol[0] += gc0; dcol[1] += gc1; dcol[2] += gc2;
 
       const SpecPoint p = spec_point(V, mx, my, mz);

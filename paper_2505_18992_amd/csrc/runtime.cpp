@@ -191,7 +191,9 @@ int build_tables(vpgs_ctx* ctx, CallTables& T, int n_sets, const vpgs_gaussians*
     tiles += (uint64_t)V.tiles_x * V.tiles_y;
     pix += (uint64_t)c.width * c.height;
   }
-  if (rec >= 0xffffffffull) return fail(ctx, VPGS_EINVAL, "too many (view, Gaussian) records: %llu", (unsigned long long)rec);
+  if (rec > VPGS_MAX_RECORDS)
+    return fail(ctx, VPGS_EINVAL, "too many (view, Gaussian) records: %llu (at most %d)", (unsigned long long)rec,
+                VPGS_MAX_RECORDS);
   if (pix >= 0xffffffffull) return fail(ctx, VPGS_EINVAL, "too many pixels");
   T.n_records = (uint32_t)rec;
   T.n_tiles = (uint32_t)tiles;
