@@ -37,8 +37,6 @@ __device__ __forceinline__ int view_of_tile(const CallTables* tab, uint32_t tile
 // i.e. o exp(-sigma) with the constant factors and the opacity folded in.
 // Forward and backward stage and evaluate it with the same instructions, so
 // the backward recomputes bit-identical alpha values.
-constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
-constexpr float kNegLog2e = -1.44269504088896340736f;
 __device__ __forceinline__ float4 stage_exponent(const float4 A, const float4 B) {
   return make_float4(B.x * kNegHalfLog2e, B.y * kNegLog2e, B.z * kNegHalfLog2e, __log2f(A.w));
 }
@@ -68,6 +66,7 @@ constexpr float kNegInf = -__builtin_inff();
 template <int TW, int TH>
 struct FwdShared {
   float4 A[TW * TH + 1], E[TW * TH + 1], C[TW * TH + 1];
+  float2 V[TW * TH];  // the quadrant test's vertex factors (ra, rc) of the record
   uint16_t hits[(TW * TH) / 64][TW * TH + kGroup];  // per wavefront: staged entries that reach its quadrant
 };
 
@@ -103,10 +102,10 @@ struct Quadrant {
   // rounding of f here and in the per-pixel evaluation (a few ulps of the
   // largest |term| over the rectangle), so every pixel whose float32 alpha
   // passes the cutoff is kept: the test only removes work.
-  __device__ __forceinline__ bool reaches(const float4 A, const float4 E) const {
+  __device__ __forceinline__ bool reaches(const float4 A, const float4 E, const float2 V) const {
     const float a = -E.x, b = -E.y, c = -E.z;
     const float dx0 = A.x - x1, dx1 = A.x - x0, dy0 = A.y - y1, dy1 = A.y - y0;
-    const float ra = __builtin_amdgcn_rcpf(2.0f * a), rc = __builtin_amdgcn_rcpf(2.0f * c);
+    const float ra = V.x, rc = V.y;  // 1 / (2a), 1 / (2c), from the projection
     auto f = [&](float dx, float dy) { return fmaf(fmaf(b, dy, a * dx), dx, c * dy * dy); };
     const float dxe = fminf(fmaxf(0.0f, dx0), dx1);  // mean - nearest x of the rectangle
     const float dye = fminf(fmaxf(0.0f, dy0), dy1);
@@ -114,7 +113,8 @@ struct Quadrant {
     const float eh = f(fminf(fmaxf(-b * dye * ra, dx0), dx1), dye);
     const float fmin = fminf(ev, eh);
     const float mx = fmaxf(dx0 * dx0, dx1 * dx1), my = fmaxf(dy0 * dy0, dy1 * dy1);
-    const float fabs_max = fmaf(a, mx, fmaf(fabsf(b), sqrtf(mx * my), c * my));
+    // |b dx dy| <= |b| sqrt(mx my) <= |b| (mx + my) / 2
+    const float fabs_max = fmaf(a, mx, fmaf(fabsf(b), 0.5f * (mx + my), c * my));
     const float margin = fmaf(16.0f * 1.1920929e-7f, fabs_max + fabsf(E.w), 1e-6f);
     return E.w - fmin >= kLog2AlphaMin - margin;
   }
@@ -129,14 +129,14 @@ struct Quadrant {
 // hit its slot.  All lanes of the wavefront must be active; the list is read
 // after the next workgroup barrier.
 template <int BS, int TW, int TH>
-__device__ __forceinline__ int wave_hits(const float4* A, const float4* E, int n, const Quadrant<TW, TH>& q,
-                                         uint16_t* list, uint64_t* mask_out) {
+__device__ __forceinline__ int wave_hits(const float4* A, const float4* E, const float2* V, int n,
+                                         const Quadrant<TW, TH>& q, uint16_t* list, uint64_t* mask_out) {
   const int lane = threadIdx.x & 63;
   int count = 0;
 #pragma unroll
   for (int k = 0; k < BS / 64; ++k) {
     const int e = k * 64 + lane;
-    const bool hit = e < n && q.reaches(A[e], E[e]);
+    const bool hit = e < n && q.reaches(A[e], E[e], V[e]);
     const uint64_t m = __ballot(hit);
     const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
     if (hit) list[count + below] = (uint16_t)e;
@@ -202,9 +202,10 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
   // batch i + 1 is loaded into registers while batch i is tested and
   // composited, so a long list does not wait on each batch's loads
   float4 pA = make_float4(0.f, 0.f, 0.f, 0.f), pR = pA, pC = pA;
+  float2 pV = make_float2(0.f, 0.f);
   if (rg.x + threadIdx.x < rg.y) {
     const float4* r = recs + rec_slot(vals[rg.x + threadIdx.x], 0);
-    pA = r[0]; pR = r[1]; pC = r[2];
+    pA = r[0]; pR = r[1]; pC = r[2]; pV = reinterpret_cast<const float2*>(r + 3)[1];
   }
   for (uint32_t start = rg.x; start < rg.y; start += BS) {
     if (__syncthreads_count(done) == BS) break;
@@ -212,16 +213,17 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
       sh.A[threadIdx.x] = pA;
       sh.E[threadIdx.x] = stage_exponent(pA, pR);
       sh.C[threadIdx.x] = pC;
+      sh.V[threadIdx.x] = pV;
     }
     __syncthreads();
     const uint32_t nidx = start + BS + threadIdx.x;
     if (nidx < rg.y) {
       const float4* r = recs + rec_slot(vals[nidx], 0);
-      pA = r[0]; pR = r[1]; pC = r[2];
+      pA = r[0]; pR = r[1]; pC = r[2]; pV = reinterpret_cast<const float2*>(r + 3)[1];
     }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint64_t* wm = masks + batch_mask_index<BS>(rg.x, tile, (int)((start - rg.x) / BS), wave);
-    const int nhit = wave_hits<BS>(sh.A, sh.E, (int)min((uint32_t)BS, rg.y - start), q, hits, wm);
+    const int nhit = wave_hits<BS>(sh.A, sh.E, sh.V, (int)min((uint32_t)BS, rg.y - start), q, hits, wm);
     __syncthreads();
     const uint32_t base = start - rg.x + 1u;
     for (int g = 0; g < nhit && __ballot(!done) != 0ull; g += kGroup) {
@@ -288,8 +290,10 @@ __device__ __forceinline__ uint32_t next_tile(uint32_t* queue, uint32_t* slot) {
 // One workgroup per tile (grid = tiles), or, when queue is non-NULL, a
 // persistent grid whose workgroups take tiles from the queue until it runs
 // past the last tile.
+// (the second bound keeps the forward within 64 VGPRs: eight wavefronts per
+// SIMD)
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH) composite_forward_kernel(
+__global__ void __launch_bounds__(TW * TH, 8) composite_forward_kernel(
     const CallTables* __restrict__ tab, const float4* __restrict__ recs, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals, float* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
     uint64_t* __restrict__ masks, const uint32_t* __restrict__ order, Counters* __restrict__ cnt,

@@ -101,16 +101,20 @@ static_assert(sizeof(Counters) <= 4096, "the counters are read back through a 4 
 //   [0] (u, v, z, opacity)
 //   [1] (Qa, Qb, Qc, 0)            conic
 //   [2] (r, g, b, 0)
-//   [3] (hx, hy, bits(rect.x), bits(rect.y))  box half extents and the
-//       inclusive tile rectangle (x0 | x1 << 16, y0 | y1 << 16)
-// count and the depth key (IEEE bits of the FP32 z, written with the
-// record) are separate arrays, read contiguously by the scans.
+//   [3] (hx, hy, ra, rc)           box half extents; ra, rc = the
+//       reciprocals of 2a and 2c of the compositor's quadrant test (a, c =
+//       -Qa, -Qc times kNegHalfLog2e)
+// count, the depth key (IEEE bits of the FP32 z) and the inclusive tile
+// rectangle (x0 | x1 << 16, y0 | y1 << 16) are separate arrays, read
+// contiguously by the scans.
+constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
+constexpr float kNegLog2e = -1.44269504088896340736f;
 constexpr int kRecSlots = 4;
 struct ProjBuffers {
   float4* rec;      // [R * kRecSlots]
   uint32_t* count;  // [R] tiles overlapped, 0 = culled
   uint32_t* zkey;   // [R] depth key of records with count != 0
-  uint2* rect;      // [R] tile rectangle of records with count != 0 (as in slot 3)
+  uint2* rect;      // [R] tile rectangle of records with count != 0
 };
 __host__ __device__ __forceinline__ size_t rec_slot(uint32_t r, int k) { return (size_t)r * kRecSlots + k; }
 

@@ -163,7 +163,11 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(const CallTables* _
         out[0] = make_float4(p.u, p.v, p.z, o);
         out[1] = make_float4(Qa, Qb, Qc, 0.0f);
         out[2] = make_float4(c0, c1, c2, 0.0f);
-        out[3] = make_float4(hx, hy, __uint_as_float(rect.x), __uint_as_float(rect.y));
+        // the quadrant test's vertex factors, as the compositor would form
+        // them from the staged conic
+        const float ra = __builtin_amdgcn_rcpf(2.0f * -(Qa * kNegHalfLog2e));
+        const float rc = __builtin_amdgcn_rcpf(2.0f * -(Qc * kNegHalfLog2e));
+        out[3] = make_float4(hx, hy, ra, rc);
         pb.zkey[rec] = __float_as_uint(p.z);
         pb.rect[rec] = rect;
       }
