@@ -24,17 +24,42 @@ __device__ __forceinline__ int set_of_block(const CallTables* tab, uint32_t blk)
 // Camera-space mean and projected centre in FP32 with a fixed operation
 // order and no contraction: these values decide visibility, the sort order
 // and the tile rectangle, so they are reproducible bit for bit.
-struct SpecPoint { float x, y, z, u, v; };
+struct SpecPoint { float x, y, z, tx, ty, u, v; };
 __device__ __forceinline__ SpecPoint spec_point(const ViewDesc& V, float mx, float my, float mz) {
 #pragma clang fp contract(off)
   SpecPoint p;
   p.x = ((V.R[0] * mx + V.R[1] * my) + V.R[2] * mz) + V.t[0];
   p.y = ((V.R[3] * mx + V.R[4] * my) + V.R[5] * mz) + V.t[1];
   p.z = ((V.R[6] * mx + V.R[7] * my) + V.R[8] * mz) + V.t[2];
-  const float tx = p.x / p.z, ty = p.y / p.z;
-  p.u = V.fx * tx + V.cx;
-  p.v = V.fy * ty + V.cy;
+  p.tx = p.x / p.z;
+  p.ty = p.y / p.z;
+  p.u = V.fx * p.tx + V.cx;
+  p.v = V.fy * p.ty + V.cy;
   return p;
+}
+
+// EWA screen-space covariance [[a, b], [b, c]] (with the low-pass dilation)
+// and the rows of the projection Jacobian at the guarded centre; 1/z and the
+// reciprocal of the determinant come from the hardware reciprocal (the
+// forward and the backward form them the same way; the exactly rounded
+// centre of SpecPoint is only needed for u and v).
+struct ScreenCov { float tx, ty, txc, tyc, iz, J00, J02, J11, J12, a, b, c, idet; };
+__device__ __forceinline__ ScreenCov screen_cov(const ViewDesc& V, const SpecPoint& p, const float Sc[9]) {
+  ScreenCov s;
+  s.iz = __builtin_amdgcn_rcpf(p.z);
+  s.tx = p.x * s.iz;
+  s.ty = p.y * s.iz;
+  s.txc = fminf(fmaxf(s.tx, V.glx), V.ghx);
+  s.tyc = fminf(fmaxf(s.ty, V.gly), V.ghy);
+  s.J00 = V.fx * s.iz;
+  s.J02 = -(V.fx * s.txc) * s.iz;
+  s.J11 = V.fy * s.iz;
+  s.J12 = -(V.fy * s.tyc) * s.iz;
+  s.a = s.J00 * s.J00 * Sc[0] + 2.f * s.J00 * s.J02 * Sc[2] + s.J02 * s.J02 * Sc[8] + kDilate;
+  s.b = s.J00 * s.J11 * Sc[1] + s.J00 * s.J12 * Sc[2] + s.J02 * s.J11 * Sc[5] + s.J02 * s.J12 * Sc[8];
+  s.c = s.J11 * s.J11 * Sc[4] + 2.f * s.J11 * s.J12 * Sc[5] + s.J12 * s.J12 * Sc[8] + kDilate;
+  s.idet = __builtin_amdgcn_rcpf(s.a * s.c - s.b * s.b);
+  return s;
 }
 
 // Pixel box of the padded opacity-aware ellipse, in FP32 with a fixed
@@ -136,18 +161,11 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(const CallTables* _
     bool ok = q.ok && opaque && (p.z > V.near_z);
     float Sc[9];
     cam_cov(V.R, Sg, Sc);
-    const float txc = fminf(fmaxf(p.x / p.z, V.glx), V.ghx);
-    const float tyc = fminf(fmaxf(p.y / p.z, V.gly), V.ghy);
-    const float J00 = V.fx / p.z, J02 = -(V.fx * txc) / p.z;
-    const float J11 = V.fy / p.z, J12 = -(V.fy * tyc) / p.z;
-    const float a = J00 * J00 * Sc[0] + 2.f * J00 * J02 * Sc[2] + J02 * J02 * Sc[8] + kDilate;
-    const float b = J00 * J11 * Sc[1] + J00 * J12 * Sc[2] + J02 * J11 * Sc[5] + J02 * J12 * Sc[8];
-    const float c = J11 * J11 * Sc[4] + 2.f * J11 * J12 * Sc[5] + J12 * J12 * Sc[8] + kDilate;
-    const float det = a * c - b * b;
-    ok = ok && det > 0.0f;
-    const float idet = 1.0f / det;
-    const float Qa = c * idet, Qb = -b * idet, Qc = a * idet;
-    const float hx = sqrtf(kq * a), hy = sqrtf(kq * c);
+    const ScreenCov sc2 = screen_cov(V, p, Sc);
+    const float a = sc2.a, b = sc2.b, c = sc2.c;
+    ok = ok && a * c - b * b > 0.0f;
+    const float Qa = c * sc2.idet, Qb = -b * sc2.idet, Qc = a * sc2.idet;
+    const float hx = __builtin_amdgcn_sqrtf(kq * a), hy = __builtin_amdgcn_sqrtf(kq * c);
     ok = ok && isfinite(p.u) && isfinite(p.v) && isfinite(Qa) && isfinite(Qb) && isfinite(Qc) &&
          isfinite(hx) && isfinite(hy);
     uint32_t count = 0;
@@ -204,6 +222,7 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
   // opacity and views whose frustum holds the centre
   const bool track = S.accum != nullptr;
   const float o_par = S.opacities[ii];
+  const float inv_o = 1.0f / o_par;
   const float o_acc = track ? fmaxf(o_par, 0.0f) : 0.0f;
   float a_grad = 0.f, a_ren = 0.f, a_op = 0.f, a_seen = 0.f;
 
@@ -221,23 +240,17 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
       const float gc0 = g[6], gc1 = g[7], gc2 = g[8];
 #pragma unroll
       for (int k = 0; k < kNumAcc; ++k) g[k] = 0.0f;
-      dop += go / o_par;  // the row holds the sum of s = o dL/do (o > 1/255 for a visible record)
+      dop += go * inv_o;  // the row holds the sum of s = o dL/do (o > 1/255 for a visible record)
       dcol[0] += gc0; dcol[1] += gc1; dcol[2] += gc2;
 
       const SpecPoint p = spec_point(V, mx, my, mz);
       float Sc[9];
       cam_cov(V.R, Sg, Sc);
-      const float tx = p.x / p.z, ty = p.y / p.z;
-      const float txc = fminf(fmaxf(tx, V.glx), V.ghx);
-      const float tyc = fminf(fmaxf(ty, V.gly), V.ghy);
-      const float iz = 1.0f / p.z;
-      const float J00 = V.fx * iz, J02 = -(V.fx * txc) * iz;
-      const float J11 = V.fy * iz, J12 = -(V.fy * tyc) * iz;
-      const float a = J00 * J00 * Sc[0] + 2.f * J00 * J02 * Sc[2] + J02 * J02 * Sc[8] + kDilate;
-      const float b = J00 * J11 * Sc[1] + J00 * J12 * Sc[2] + J02 * J11 * Sc[5] + J02 * J12 * Sc[8];
-      const float c = J11 * J11 * Sc[4] + 2.f * J11 * J12 * Sc[5] + J12 * J12 * Sc[8] + kDilate;
-      const float idet = 1.0f / (a * c - b * b);
-      const float Qa = c * idet, Qb = -b * idet, Qc = a * idet;
+      const ScreenCov sc2 = screen_cov(V, p, Sc);
+      const float tx = sc2.tx, ty = sc2.ty, txc = sc2.txc, tyc = sc2.tyc, iz = sc2.iz;
+      const float J00 = sc2.J00, J02 = sc2.J02, J11 = sc2.J11, J12 = sc2.J12;
+      const float a = sc2.a, b = sc2.b, c = sc2.c;
+      const float Qa = c * sc2.idet, Qb = -b * sc2.idet, Qc = a * sc2.idet;
       // the row holds moments of s = dL/dalpha * alpha over the pixel offsets
       // d = (u, v) - pixel centre; dL/dsigma = -s with
       // sigma = (Qa dx^2 + 2 Qb dx dy + Qc dy^2) / 2
