@@ -145,13 +145,21 @@ def test_c1_forward_parity():
     assert abs(st["n_blended"] - int(ref["n_blend"].sum())) <= int(ref["n_blend"][mask].sum()) + 0
 
 
-def test_c1_backward_parity():
-    from paper_2505_18992_amd import render_backward
+@pytest.fixture(scope="module")
+def c1_backward_ref():
     sc = scenes.make_c1()
-    g, cam = sc.sets[0], sc.cameras[0]
-    print("case c1 backward", flush=True)
-    ref, mask, (w, G, S) = oracle_reference(g, cam, sc.weights[0])
-    _, outs, saved = _render(sc)
+    _, _, (w, G, S) = oracle_reference(sc.sets[0], sc.cameras[0], sc.weights[0])
+    return sc, w, G, S
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (16, 8), (32, 8)])
+def test_c1_backward_parity(tile, c1_backward_ref):
+    # every tile shape: 1, 2 or 4 wavefronts per tile and 1, 2 or 4 words of
+    # forward hit bits per wavefront and batch
+    from paper_2505_18992_amd import render_backward
+    sc, w, G, S = c1_backward_ref
+    print(f"case c1 backward tile={tile}", flush=True)
+    _, outs, saved = _render(sc, tile=tile)
     grads, d_pose = render_backward(saved, [to_dev(w)])
     saved.close()
     got = dict(zip(["means", "log_scales", "quats", "opacities", "colors"], [np_(t) for t in grads[0]]))
