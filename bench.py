@@ -325,6 +325,58 @@ def time_distillation(steps, m=4):
                             "frac": gbs / HBM_PEAK_GBS}}
 
 
+def time_decode(steps):
+    """The voxel-anchor decode of eq. 1-5 at the anchor workload (50 k
+    anchors, k = 10, decoder width 64: 500 k neural Gaussians) inside one
+    mapping iteration of the anchor representation: decode, render of one
+    1200x680 view, render backward, decode backward."""
+    import numpy as np
+    import torch
+    import scenes
+    from paper_2505_18992_amd import decode_backward, decode_forward, get_context, render, render_backward
+    ctx = get_context(0)
+    sc = scenes.make_c3()
+    a, d = sc.anchors, sc.decoder
+    cam = sc.cameras[0]
+    R, t = cam.world_to_cam[:, :3].astype(np.float64), cam.world_to_cam[:, 3].astype(np.float64)
+    centre = (-R.T @ t).astype(np.float32)  # the camera centre, a constant of the decode
+    anchors = tuple(torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (a.xyz, a.feat, a.scale, a.offsets))
+    mlp = tuple([torch.from_numpy(x).cuda() for x in lst] for lst in (d.W1, d.b1, d.W2, d.b2))
+    wts = [tuple(torch.from_numpy(x).cuda() for x in sc.weights[0])]
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    dec = decode_forward(anchors, mlp, centre)
+    up = [torch.randn(t.shape, generator=gen, device="cuda") for t in dec]
+
+    def iteration():
+        g = decode_forward(anchors, mlp, centre)
+        outs, saved = render([g], [cam], tile=(32, 8))
+        grads, _ = render_backward(saved, wts)
+        saved.close()
+        decode_backward(anchors, mlp, centre, grads[0])
+    for _ in range(3):
+        iteration()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        iteration()
+    torch.cuda.synchronize()
+    ms_iter = (time.perf_counter() - t0) * 1e3 / steps
+    ms_f = _stage_ms(ctx, "decode_forward", lambda: decode_forward(anchors, mlp, centre), steps)
+    ms_b = _stage_ms(ctx, "decode_backward", lambda: decode_backward(anchors, mlp, centre, up), steps)
+    m, k, width = a.xyz.shape[0], a.k, d.W1[0].shape[0]
+    # two matrix products per head: [36 -> width] and [width -> k, 3k, 7k]
+    flop_f = 2.0 * m * (3 * 36 * width + width * 11 * k)
+    flop_b = 2.0 * flop_f  # input and weight gradients of both layers
+    byts_f = m * (12 + 128 + 12 + 12 * k) + m * k * 56  # anchors read, Gaussians written
+    log(f"[bench] decode (50k anchors, k={k}): forward {ms_f:.4f} ms, backward {ms_b:.4f} ms; "
+        f"anchor mapping iteration {ms_iter:.3f} ms")
+    return {"anchors": m, "k": k, "width": width, "gaussians": m * k,
+            "forward": {"ms": ms_f, "flop": flop_f, "achieved_TFLOPs": flop_f / (ms_f * 1e-3) / 1e12,
+                        "bytes": byts_f, "achieved_GBs": byts_f / (ms_f * 1e-3) / 1e9},
+            "backward": {"ms": ms_b, "flop": flop_b, "achieved_TFLOPs": flop_b / (ms_b * 1e-3) / 1e12},
+            "iteration_ms": ms_iter, "iteration": "decode, render 1200x680, render backward, decode backward"}
+
+
 def time_registration(steps, voxel=1.0, cap=20, tau=3.0, sigma=1.0):
     """Frame-to-map registration (eq. 10-12) on the street LiDAR case: the
     voxel map of 1.5 M map points, then per frame the double downsampling of
@@ -497,7 +549,7 @@ def main():
         log(f"[bench] one view per launch: {ms_per_view_launch:.3f} ms for {nv} views; "
             f"eager window {ms_eager_window:.3f} ms")
 
-    loss_stage = expansion = distillation = registration = None
+    loss_stage = expansion = distillation = registration = anchor_decode = None
     if not args.no_extras:
         # the mapping loss of eq. 7-8 on the same views (rendered frames
         # against perturbed copies of themselves), timed on its own
@@ -508,6 +560,8 @@ def main():
         distillation = time_distillation(args.steps)
         # frame-to-map registration (eq. 10-12) on a street LiDAR sweep
         registration = time_registration(args.steps)
+        # the voxel-anchor decode (eq. 1-5) and its backward
+        anchor_decode = time_decode(args.steps)
 
     E, B, P = st["n_evaluated"], st["n_blended"], st["n_pairs"]
     dom = max(stage_ms, key=stage_ms.get)
@@ -556,6 +610,7 @@ def main():
         "expansion": expansion,
         "distillation": distillation,
         "registration": registration,
+        "decode": anchor_decode,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
