@@ -1,20 +1,27 @@
 // decode.hip -- neural Gaussians from voxel anchors (Section III-A, eq. 1-5)
 // and the backward of that decode.
 //
-// Forward, one thread per anchor: the 36-vector [feature, view direction,
-// distance] (eq. 3) goes through three LINEAR-ReLU-LINEAR heads (eq. 2); the
-// k Gaussians of the anchor get mean = anchor + offset * scaling (eq. 1),
+// Forward: the 36-vector [feature, view direction, distance] of an anchor
+// (eq. 3) goes through three LINEAR-ReLU-LINEAR heads (eq. 2); the k
+// Gaussians of the anchor get mean = anchor + offset * scaling (eq. 1),
 // opacity = tanh, colour = sigmoid (eq. 4), log-scale = log sigmoid + log of
-// the anchor scaling (eq. 5) and a normalised quaternion.  Weight indices are
-// uniform across the wavefront, so the weights stream through scalar loads
-// and every lane keeps its hidden layer in a private column of LDS.
+// the anchor scaling (eq. 5) and a normalised quaternion.
 //
-// Backward: one thread per anchor chains the upstream Gaussian gradients
-// through the activations and both layers (feature, scaling and offset
-// gradients are written directly) and stores the per-anchor layer inputs and
-// output gradients; the weight gradients are then split-K reductions
-// (sum over anchors of outer products) written as per-chunk partials and
-// summed in a fixed order, so they are deterministic.
+// The heads are small dense products over a batch of anchors, so they run on
+// the matrix cores: one wavefront takes 16 anchors (the M rows of a
+// 16x16x4 FP32 MFMA tile) end to end, with its input rows, hidden layer and
+// head outputs in a private slice of LDS, and streams the weights (a few tens
+// of KB, L2-resident) as the B operands.  The activations then run one lane
+// per (anchor, Gaussian) output so that the stores are contiguous.
+//
+// Backward: the same wavefront recomputes its forward, chains the upstream
+// Gaussian gradients through the activations and both layers with the same
+// tiles (feature, scaling and offset gradients are written directly), and
+// stores each layer's input and output gradient.  The weight gradients are
+// sums over anchors of outer products: one launch forms all six of them
+// (W2 and W1 of each head, the bias as an extra all-ones column) per chunk of
+// anchors on the matrix cores, and a second sums the chunks in a fixed order,
+// so they are deterministic.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -25,7 +32,18 @@ namespace vpgs {
 namespace {
 
 constexpr int kIn = 36;
-constexpr int kDecBlock = 64;  // one wavefront per block: LDS holds (width + 7k) floats per thread
+constexpr int kRows = 16;      // anchors per wavefront: the rows of every tile
+constexpr int kHP = kIn + 1;   // LDS pitch of the input rows
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// D += A B for a 16x4 A and a 4x16 B.  Lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and holds D[4 (l / 16) + i][l % 16] in element i.  The
+// contraction index that a (lane group, step) pair stands for is free as long
+// as A and B agree on it.
+__device__ __forceinline__ f32x4 mma(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
 
 struct DecArgs {
   int64_t m;
@@ -63,245 +81,480 @@ struct DecArgs {
 __device__ __forceinline__ float sigmoidf_(float y) { return 1.0f / (1.0f + expf(-y)); }
 __device__ __forceinline__ float log_sigmoidf_(float y) { return -(fmaxf(-y, 0.0f) + log1pf(expf(-fabsf(y)))); }
 
-// h = [feat (32), direction (3), distance (1)] of anchor a (eq. 3)
-__device__ __forceinline__ void anchor_input(const DecArgs& A, int64_t a, float h[kIn]) {
-#pragma unroll
-  for (int i = 0; i < 32; ++i) h[i] = A.feat[a * 32 + i];
-  const float dx = A.xyz[3 * a] - A.cx, dy = A.xyz[3 * a + 1] - A.cy, dz = A.xyz[3 * a + 2] - A.cz;
-  const float delta = sqrtf(dx * dx + dy * dy + dz * dz);
-  const float inv = 1.0f / delta;
-  h[32] = dx * inv;
-  h[33] = dy * inv;
-  h[34] = dz * inv;
-  h[35] = delta;
-}
+__host__ __device__ constexpr int head_outs(int h, int k) { return (h == 0 ? 1 : h == 1 ? 3 : 7) * k; }
 
-// Per-thread vectors of the hidden layer live in LDS, column-major over the
-// block (element j of thread t at [j * kDecBlock + t]), so loops over the
-// hidden units need no unrolling.
-__device__ __forceinline__ void hidden_layer(const float* __restrict__ W1, const float* __restrict__ b1, int width,
-                                             const float h[kIn], float* hid) {
-  for (int j = 0; j < width; ++j) {
-    float acc = b1[j];
+// Rows of h = [feat (32), direction (3), distance (1)] (eq. 3) for the
+// wavefront's anchors a0 .. a0 + nv - 1; rows past nv are zero.
+__device__ __forceinline__ void load_inputs(const DecArgs& A, int64_t a0, int nv, int lane, float* Hs) {
 #pragma unroll
-    for (int i = 0; i < kIn; ++i) acc = fmaf(W1[j * kIn + i], h[i], acc);
-    hid[j * kDecBlock] = fmaxf(acc, 0.0f);
+  for (int e = lane; e < kRows * 32; e += 64) {
+    const int r = e >> 5, i = e & 31;
+    Hs[r * kHP + i] = r < nv ? A.feat[(a0 + r) * 32 + i] : 0.0f;
+  }
+  if (lane < kRows) {
+    float d[4] = {0.f, 0.f, 0.f, 0.f};
+    if (lane < nv) {
+      const int64_t a = a0 + lane;
+      const float dx = A.xyz[3 * a] - A.cx, dy = A.xyz[3 * a + 1] - A.cy, dz = A.xyz[3 * a + 2] - A.cz;
+      const float delta = sqrtf(dx * dx + dy * dy + dz * dz);
+      const float inv = 1.0f / delta;
+      d[0] = dx * inv;
+      d[1] = dy * inv;
+      d[2] = dz * inv;
+      d[3] = delta;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Hs[lane * kHP + 32 + j] = d[j];
   }
 }
 
-__device__ __forceinline__ float head_out(const float* __restrict__ W2, const float* __restrict__ b2, int width, int row,
-                                          const float* hid) {
-  float acc = b2[row];
-  const float* w = W2 + (size_t)row * width;
-#pragma unroll 4
-  for (int j = 0; j < width; ++j) acc = fmaf(w[j], hid[j * kDecBlock], acc);
-  return acc;
-}
-
-__global__ void __launch_bounds__(kDecBlock) decode_forward_kernel(DecArgs A) {
-  extern __shared__ float lds[];
-  float* hid = lds + threadIdx.x;
-  const int64_t a = (int64_t)blockIdx.x * kDecBlock + threadIdx.x;
-  if (a >= A.m) return;
-  const int k = A.k, width = A.width;
-  float h[kIn];
-  anchor_input(A, a, h);
-  const float l0 = A.scale[3 * a], l1 = A.scale[3 * a + 1], l2 = A.scale[3 * a + 2];
-  const float x0 = A.xyz[3 * a], x1 = A.xyz[3 * a + 1], x2 = A.xyz[3 * a + 2];
-  for (int m = 0; m < k; ++m) {  // eq. 1
-    const int64_t g = a * k + m;
-    A.means[3 * g] = x0 + A.offsets[3 * g] * l0;
-    A.means[3 * g + 1] = x1 + A.offsets[3 * g + 1] * l1;
-    A.means[3 * g + 2] = x2 + A.offsets[3 * g + 2] * l2;
-  }
-  hidden_layer(A.W1[0], A.b1[0], width, h, hid);
-  for (int m = 0; m < k; ++m) A.opac[a * k + m] = tanhf(head_out(A.W2[0], A.b2[0], width, m, hid));
-  hidden_layer(A.W1[1], A.b1[1], width, h, hid);
-  for (int r = 0; r < 3 * k; ++r) A.colors[a * 3 * k + r] = sigmoidf_(head_out(A.W2[1], A.b2[1], width, r, hid));
-  hidden_layer(A.W1[2], A.b1[2], width, h, hid);
-  const float ll[3] = {logf(l0), logf(l1), logf(l2)};
-  for (int m = 0; m < k; ++m) {
-    float y[7];
+// hid[r][j] = relu(b1[j] + sum_i W1[j][i] h[r][i]) for the KW column tiles
+// of the hidden layer (columns past the width come out zero).  ha holds the
+// A operand: lane group g covers inputs 9g .. 9g + 8.
+template <int KW>
+__device__ __forceinline__ void hidden_tiles(const float* __restrict__ W1, const float* __restrict__ b1, int W,
+                                             const float ha[9], float* hid, int lane) {
+  constexpr int HP = 16 * KW + 1;
+  const int lo = lane & 15, grp = lane >> 4;
 #pragma unroll
-    for (int j = 0; j < 7; ++j) y[j] = head_out(A.W2[2], A.b2[2], width, 7 * m + j, hid);
-    const int64_t g = a * k + m;
+  for (int ct = 0; ct < KW; ++ct) {
+    const int j = 16 * ct + lo;
+    const bool jv = j < W;
+    float b[9];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) A.log_scales[3 * g + j] = log_sigmoidf_(y[j]) + ll[j];
-    const float n = fmaxf(sqrtf(y[3] * y[3] + y[4] * y[4] + y[5] * y[5] + y[6] * y[6]), 1e-12f);
-    const float in = 1.0f / n;
+    for (int ks = 0; ks < 9; ++ks) b[ks] = jv ? W1[j * kIn + 9 * grp + ks] : 0.0f;
+    f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int j = 0; j < 4; ++j) A.quats[4 * g + j] = y[3 + j] * in;
+    for (int ks = 0; ks < 9; ++ks) c = mma(ha[ks], b[ks], c);
+    const float bias = jv ? b1[j] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) hid[(4 * grp + i) * HP + j] = fmaxf(c[i] + bias, 0.0f);
   }
 }
 
-// dhid = W2^T dy, dpre = dhid on active units, dh += W1^T dpre; stores the
-// hidden layer and dpre for the weight gradients.
-__device__ __forceinline__ void head_backward(const DecArgs& A, int head, int64_t a, int n_out, const float* hid,
-                                              const float* dyl, float dh[kIn]) {
-  const int width = A.width;
-  float* hs = A.ws_hid[head] + a * width;
-  float* ds = A.ws_dpre[head] + a * width;
-  const float* W1 = A.W1[head];
-  const float* W2 = A.W2[head];
-  for (int j = 0; j < width; ++j) {
-    float dhid = 0.0f;
-#pragma unroll 4
-    for (int o = 0; o < n_out; ++o) dhid = fmaf(W2[(size_t)o * width + j], dyl[o * kDecBlock], dhid);
-    const float hv = hid[j * kDecBlock];
-    const float dp = hv > 0.0f ? dhid : 0.0f;
-    hs[j] = hv;
-    ds[j] = dp;
+// y[r][o] = b2[o] + sum_j W2[o][j] hid[r][j] for o < outs, 16 outputs per
+// tile; lane group g covers hidden units g KS .. g KS + KS - 1.
+template <int KW>
+__device__ __forceinline__ void out_tiles(const float* __restrict__ W2, const float* __restrict__ b2, int W, int outs,
+                                          const float* hid, float* ys, int yp, int lane) {
+  constexpr int HP = 16 * KW + 1, KS = 4 * KW;
+  const int lo = lane & 15, grp = lane >> 4;
+  float ha[KS];
 #pragma unroll
-    for (int i = 0; i < kIn; ++i) dh[i] = fmaf(W1[j * kIn + i], dp, dh[i]);
-  }
-}
-
-__global__ void __launch_bounds__(kDecBlock) decode_backward_kernel(DecArgs A) {
-  extern __shared__ float lds[];
-  float* hid = lds + threadIdx.x;
-  float* dyl = lds + (size_t)A.width * kDecBlock + threadIdx.x;
-  const int64_t a = (int64_t)blockIdx.x * kDecBlock + threadIdx.x;
-  if (a >= A.m) return;
-  const int k = A.k, width = A.width;
-  float h[kIn], dh[kIn];
-  anchor_input(A, a, h);
+  for (int ks = 0; ks < KS; ++ks) ha[ks] = hid[lo * HP + KS * grp + ks];
+  for (int o0 = 0; o0 < outs; o0 += 16) {
+    const int o = o0 + lo;
+    const bool ov = o < outs;
+    float b[KS];
 #pragma unroll
-  for (int i = 0; i < kIn; ++i) {
-    A.ws_h[a * kIn + i] = h[i];
-    dh[i] = 0.0f;
-  }
-  const float l[3] = {A.scale[3 * a], A.scale[3 * a + 1], A.scale[3 * a + 2]};
-  float dl[3] = {0.f, 0.f, 0.f};
-  // eq. 1: mean = anchor + offset * l
-  for (int m = 0; m < k; ++m) {
-    const int64_t g = a * k + m;
+    for (int ks = 0; ks < KS; ++ks) {
+      const int j = KS * grp + ks;
+      b[ks] = (ov && j < W) ? W2[(size_t)o * W + j] : 0.0f;
+    }
+    f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float gm = A.g_means[3 * g + c];
-      A.d_offsets[3 * g + c] = gm * l[c];
-      dl[c] = fmaf(gm, A.offsets[3 * g + c], dl[c]);
+    for (int ks = 0; ks < KS; ++ks) c = mma(ha[ks], b[ks], c);
+    if (ov) {
+      const float bias = b2[o];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ys[(4 * grp + i) * yp + o] = c[i] + bias;
     }
   }
-  // opacity head: tanh
-  hidden_layer(A.W1[0], A.b1[0], width, h, hid);
-  for (int m = 0; m < k; ++m) {
-    const float t = tanhf(head_out(A.W2[0], A.b2[0], width, m, hid));
-    const float dy = A.g_opac[a * k + m] * (1.0f - t * t);
-    A.ws_dy[0][a * k + m] = dy;
-    dyl[m * kDecBlock] = dy;
+}
+
+template <int KW>
+__global__ void __launch_bounds__(64) decode_forward_kernel(DecArgs A) {
+  extern __shared__ float lds[];
+  constexpr int HP = 16 * KW + 1;
+  const int lane = threadIdx.x;
+  const int k = A.k, W = A.width, yp = 7 * k + 1;
+  float* Hs = lds;
+  float* hid = Hs + kRows * kHP;
+  float* ys = hid + kRows * HP;
+  const int64_t a0 = (int64_t)blockIdx.x * kRows;
+  const int nv = (int)std::min<int64_t>(A.m - a0, kRows);
+  load_inputs(A, a0, nv, lane, Hs);
+  const int n3 = nv * 3 * k;
+  for (int e = lane; e < n3; e += 64) {  // eq. 1
+    const int r = e / (3 * k), c = e % 3;
+    const int64_t a = a0 + r, g = a0 * 3 * k + e;
+    A.means[g] = A.xyz[3 * a + c] + A.offsets[g] * A.scale[3 * a + c];
   }
-  head_backward(A, 0, a, k, hid, dyl, dh);
-  // colour head: sigmoid (eq. 4)
-  hidden_layer(A.W1[1], A.b1[1], width, h, hid);
-  for (int r = 0; r < 3 * k; ++r) {
-    const float s = sigmoidf_(head_out(A.W2[1], A.b2[1], width, r, hid));
-    const float dy = A.g_colors[a * 3 * k + r] * s * (1.0f - s);
-    A.ws_dy[1][a * 3 * k + r] = dy;
-    dyl[r * kDecBlock] = dy;
-  }
-  head_backward(A, 1, a, 3 * k, hid, dyl, dh);
-  // covariance head: [scale (eq. 5) | quaternion]
-  hidden_layer(A.W1[2], A.b1[2], width, h, hid);
-  for (int m = 0; m < k; ++m) {
-    const int64_t g = a * k + m;
-    float y[7], dy[7];
+  __syncthreads();
+  float ha[9];
 #pragma unroll
-    for (int j = 0; j < 7; ++j) y[j] = head_out(A.W2[2], A.b2[2], width, 7 * m + j, hid);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const float gl = A.g_ls[3 * g + j];
-      dy[j] = gl * (1.0f - sigmoidf_(y[j]));  // d log_sigmoid(y) / dy
-      dl[j] += gl / l[j];                      // d log l / dl
-    }
-    const float nr = sqrtf(y[3] * y[3] + y[4] * y[4] + y[5] * y[5] + y[6] * y[6]);
-    const float gq[4] = {A.g_quats[4 * g], A.g_quats[4 * g + 1], A.g_quats[4 * g + 2], A.g_quats[4 * g + 3]};
-    if (nr > 1e-12f) {
-      const float in = 1.0f / nr;
-      const float q0 = y[3] * in, q1 = y[4] * in, q2 = y[5] * in, q3 = y[6] * in;
-      const float dot = q0 * gq[0] + q1 * gq[1] + q2 * gq[2] + q3 * gq[3];
-      dy[3] = (gq[0] - q0 * dot) * in;
-      dy[4] = (gq[1] - q1 * dot) * in;
-      dy[5] = (gq[2] - q2 * dot) * in;
-      dy[6] = (gq[3] - q3 * dot) * in;
+  for (int ks = 0; ks < 9; ++ks) ha[ks] = Hs[(lane & 15) * kHP + 9 * (lane >> 4) + ks];
+  for (int h = 0; h < 3; ++h) {
+    const int outs = head_outs(h, k);
+    hidden_tiles<KW>(A.W1[h], A.b1[h], W, ha, hid, lane);
+    __syncthreads();
+    out_tiles<KW>(A.W2[h], A.b2[h], W, outs, hid, ys, yp, lane);
+    __syncthreads();
+    if (h == 0) {
+      for (int e = lane; e < nv * k; e += 64) {
+        const int r = e / k;
+        A.opac[a0 * k + e] = tanhf(ys[r * yp + e - r * k]);
+      }
+    } else if (h == 1) {
+      for (int e = lane; e < nv * 3 * k; e += 64) {  // eq. 4
+        const int r = e / (3 * k);
+        A.colors[a0 * 3 * k + e] = sigmoidf_(ys[r * yp + e - r * 3 * k]);
+      }
     } else {
+      for (int e = lane; e < nv * k; e += 64) {
+        const int r = e / k;
+        const float* y = ys + r * yp + 7 * (e - r * k);
+        const int64_t a = a0 + r, g = a0 * k + e;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) dy[3 + j] = gq[j] * 1e12f;
+        for (int j = 0; j < 3; ++j) A.log_scales[3 * g + j] = log_sigmoidf_(y[j]) + logf(A.scale[3 * a + j]);  // eq. 5
+        const float n = fmaxf(sqrtf(y[3] * y[3] + y[4] * y[4] + y[5] * y[5] + y[6] * y[6]), 1e-12f);
+        const float in = 1.0f / n;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) A.quats[4 * g + j] = y[3 + j] * in;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// dhid[r][j] = sum_o dy[r][o] W2[o][j]; dpre = dhid where the hidden unit is
+// active.  Writes dpre to LDS and the hidden layer and dpre of the valid rows
+// to the workspace.  Lane group g covers outputs o0 + 4g .. o0 + 4g + 3.
+template <int KW>
+__device__ __forceinline__ void hid_grad_tiles(const float* __restrict__ W2, int W, int outs, const float* dys, int yp,
+                                               const float* hid, float* dpre, float* ws_hid, float* ws_dpre,
+                                               int64_t a0, int nv, int lane) {
+  constexpr int HP = 16 * KW + 1;
+  const int lo = lane & 15, grp = lane >> 4;
+  f32x4 acc[KW];
+#pragma unroll
+  for (int ct = 0; ct < KW; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int o0 = 0; o0 < outs; o0 += 16) {
+    float a[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int o = o0 + 4 * grp + s;
+      a[s] = o < outs ? dys[lo * yp + o] : 0.0f;
     }
 #pragma unroll
-    for (int j = 0; j < 7; ++j) {
-      A.ws_dy[2][a * 7 * k + 7 * m + j] = dy[j];
-      dyl[(7 * m + j) * kDecBlock] = dy[j];
+    for (int ct = 0; ct < KW; ++ct) {
+      const int j = 16 * ct + lo;
+      float b[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int o = o0 + 4 * grp + s;
+        b[s] = (o < outs && j < W) ? W2[(size_t)o * W + j] : 0.0f;
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[ct] = mma(a[s], b[s], acc[ct]);
     }
   }
-  head_backward(A, 2, a, 7 * k, hid, dyl, dh);
 #pragma unroll
-  for (int i = 0; i < 32; ++i) A.d_feat[a * 32 + i] = dh[i];
+  for (int ct = 0; ct < KW; ++ct) {
+    const int j = 16 * ct + lo;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) A.d_scale[3 * a + c] = dl[c];
+    for (int i = 0; i < 4; ++i) {
+      const int r = 4 * grp + i;
+      const float hv = hid[r * HP + j];
+      const float dp = hv > 0.0f ? acc[ct][i] : 0.0f;
+      dpre[r * HP + j] = dp;
+      if (r < nv && j < W) {
+        ws_hid[(a0 + r) * W + j] = hv;
+        ws_dpre[(a0 + r) * W + j] = dp;
+      }
+    }
+  }
+}
+
+// dh[r][c] += sum_j dpre[r][j] W1[j][c] for the 32 feature inputs (the
+// direction and distance inputs have no parameters upstream).
+template <int KW>
+__device__ __forceinline__ void input_grad_tiles(const float* __restrict__ W1, int W, const float* dpre, f32x4 dh[2],
+                                                 int lane) {
+  constexpr int HP = 16 * KW + 1, KS = 4 * KW;
+  const int lo = lane & 15, grp = lane >> 4;
+  float a[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) a[ks] = dpre[lo * HP + KS * grp + ks];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    const int c = 16 * ct + lo;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int j = KS * grp + ks;
+      dh[ct] = mma(a[ks], j < W ? W1[j * kIn + c] : 0.0f, dh[ct]);
+    }
+  }
+}
+
+template <int KW>
+__global__ void __launch_bounds__(64) decode_backward_kernel(DecArgs A) {
+  extern __shared__ float lds[];
+  constexpr int HP = 16 * KW + 1;
+  const int lane = threadIdx.x, lo = lane & 15, grp = lane >> 4;
+  const int k = A.k, W = A.width, yp = 7 * k + 1;
+  float* Hs = lds;
+  float* hid = Hs + kRows * kHP;
+  float* dpre = hid + kRows * HP;
+  float* ys = dpre + kRows * HP;
+  const int64_t a0 = (int64_t)blockIdx.x * kRows;
+  const int nv = (int)std::min<int64_t>(A.m - a0, kRows);
+  load_inputs(A, a0, nv, lane, Hs);
+  // eq. 1: mean = anchor + offset * l
+  const int n3 = nv * 3 * k;
+  for (int e = lane; e < n3; e += 64) {
+    const int r = e / (3 * k), c = e % 3;
+    const int64_t g = a0 * 3 * k + e;
+    A.d_offsets[g] = A.g_means[g] * A.scale[3 * (a0 + r) + c];
+  }
+  // scaling: through the means and through eq. 5's log l
+  if (lane < 3 * nv) {
+    const int r = lane / 3, c = lane - 3 * r;
+    const int64_t a = a0 + r;
+    const float l = A.scale[3 * a + c];
+    float s = 0.0f;
+    for (int m = 0; m < k; ++m) s = fmaf(A.g_means[3 * (a * k + m) + c], A.offsets[3 * (a * k + m) + c], s);
+    for (int m = 0; m < k; ++m) s += A.g_ls[3 * (a * k + m) + c] / l;
+    A.d_scale[3 * a + c] = s;
+  }
+  __syncthreads();
+  for (int e = lane; e < nv * kIn; e += 64) {
+    const int r = e / kIn;
+    A.ws_h[a0 * kIn + e] = Hs[r * kHP + e - r * kIn];
+  }
+  float ha[9];
+#pragma unroll
+  for (int ks = 0; ks < 9; ++ks) ha[ks] = Hs[lo * kHP + 9 * grp + ks];
+  f32x4 dh[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+  for (int h = 0; h < 3; ++h) {
+    const int outs = head_outs(h, k);
+    hidden_tiles<KW>(A.W1[h], A.b1[h], W, ha, hid, lane);
+    __syncthreads();
+    out_tiles<KW>(A.W2[h], A.b2[h], W, outs, hid, ys, yp, lane);
+    __syncthreads();
+    // gradient at the head outputs, in place of the outputs
+    float* wdy = A.ws_dy[h] + a0 * outs;
+    if (h == 0) {  // tanh
+      for (int e = lane; e < nv * k; e += 64) {
+        const int r = e / k, o = e - r * k;
+        const float t = tanhf(ys[r * yp + o]);
+        const float dy = A.g_opac[a0 * k + e] * (1.0f - t * t);
+        ys[r * yp + o] = dy;
+        wdy[e] = dy;
+      }
+    } else if (h == 1) {  // sigmoid (eq. 4)
+      for (int e = lane; e < nv * 3 * k; e += 64) {
+        const int r = e / (3 * k), o = e - r * 3 * k;
+        const float s = sigmoidf_(ys[r * yp + o]);
+        const float dy = A.g_colors[a0 * 3 * k + e] * s * (1.0f - s);
+        ys[r * yp + o] = dy;
+        wdy[e] = dy;
+      }
+    } else {  // [scale (eq. 5) | quaternion]
+      for (int e = lane; e < nv * k; e += 64) {
+        const int r = e / k;
+        float* y = ys + r * yp + 7 * (e - r * k);
+        const int64_t g = a0 * k + e;
+        float dy[7];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) dy[j] = A.g_ls[3 * g + j] * (1.0f - sigmoidf_(y[j]));  // d log_sigmoid(y) / dy
+        const float nr = sqrtf(y[3] * y[3] + y[4] * y[4] + y[5] * y[5] + y[6] * y[6]);
+        const float gq[4] = {A.g_quats[4 * g], A.g_quats[4 * g + 1], A.g_quats[4 * g + 2], A.g_quats[4 * g + 3]};
+        if (nr > 1e-12f) {
+          const float in = 1.0f / nr;
+          const float q0 = y[3] * in, q1 = y[4] * in, q2 = y[5] * in, q3 = y[6] * in;
+          const float dot = q0 * gq[0] + q1 * gq[1] + q2 * gq[2] + q3 * gq[3];
+          dy[3] = (gq[0] - q0 * dot) * in;
+          dy[4] = (gq[1] - q1 * dot) * in;
+          dy[5] = (gq[2] - q2 * dot) * in;
+          dy[6] = (gq[3] - q3 * dot) * in;
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) dy[3 + j] = gq[j] * 1e12f;
+        }
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+          y[j] = dy[j];
+          wdy[7 * e + j] = dy[j];
+        }
+      }
+    }
+    __syncthreads();
+    hid_grad_tiles<KW>(A.W2[h], W, outs, ys, yp, hid, dpre, A.ws_hid[h], A.ws_dpre[h], a0, nv, lane);
+    __syncthreads();
+    input_grad_tiles<KW>(A.W1[h], W, dpre, dh, lane);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = 4 * grp + i;
+      if (r < nv) A.d_feat[(a0 + r) * 32 + 16 * ct + lo] = dh[ct][i];
+    }
 }
 
 // ---------------------------------------------------------------------------
-// split-K products: partial[chunk][p][q] = sum_{a in chunk} X[a][p] Y[a][q],
-// partial[chunk][P*Q + p] = sum_{a in chunk} X[a][p]
+// Weight gradients: for each of the six products, part[chunk][p][q] =
+// sum over the chunk's anchors a of X[a][p] Y'[a][q], where Y' is Y with a
+// trailing all-ones column (q = Q gives the bias gradient sum_a X[a][p]).
+// One block per (chunk, product); wavefront w owns the p tiles w and w + 4
+// and every q tile, so no two wavefronts share an output.
 // ---------------------------------------------------------------------------
-constexpr int kChunk = 1024;
-constexpr int kTile = 16;
-constexpr int kStep = 64;
+constexpr int kNumProd = 6;
+constexpr int kMaxPT = 2;  // P <= 128: 8 tiles over 4 wavefronts
+constexpr int kMaxQT = 9;  // Q + 1 <= 129
+constexpr int kOuterBlock = 256;
 
-__global__ void __launch_bounds__(256) outer_partial_kernel(const float* __restrict__ X, int P,
-                                                            const float* __restrict__ Y, int Q, int64_t M,
-                                                            float* __restrict__ partial) {
-  __shared__ float xs[kStep][kTile];
-  __shared__ float ys[kStep][kTile];
-  const int tp = threadIdx.x / kTile, tq = threadIdx.x % kTile;
-  const int p = blockIdx.y * kTile + tp, q = blockIdx.z * kTile + tq;
-  const int64_t a0 = (int64_t)blockIdx.x * kChunk;
-  const int64_t a1 = a0 + kChunk < M ? a0 + kChunk : M;
-  float acc = 0.f, bias = 0.f;
-  for (int64_t base = a0; base < a1; base += kStep) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < kStep * kTile; e += 256) {
-      const int r = e / kTile, c = e % kTile;
-      const int64_t a = base + r;
-      const int pp = blockIdx.y * kTile + c, qq = blockIdx.z * kTile + c;
-      xs[r][c] = (a < a1 && pp < P) ? X[a * P + pp] : 0.0f;
-      ys[r][c] = (a < a1 && qq < Q) ? Y[a * Q + qq] : 0.0f;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int r = 0; r < kStep; ++r) {
-      acc = fmaf(xs[r][tp], ys[r][tq], acc);
-      bias += xs[r][tp];
-    }
-  }
-  const size_t per = (size_t)P * Q + P;
-  if (p < P && q < Q) partial[blockIdx.x * per + (size_t)p * Q + q] = acc;
-  if (p < P && blockIdx.z == 0 && tq == 0) partial[blockIdx.x * per + (size_t)P * Q + p] = bias;
+struct OuterJob {
+  const float* X;
+  const float* Y;
+  int P, Q;
+  int64_t off;  // offset of this product in a chunk's partial row
+};
+
+struct OuterArgs {
+  OuterJob job[kNumProd];
+  int64_t M;
+  int64_t chunk;
+  int64_t per;  // floats per chunk: sum of P (Q + 1)
+  float* part;
+};
+
+__device__ __forceinline__ OuterJob pick_job(const OuterArgs& O, int j) {
+  OuterJob J = O.job[0];
+#pragma unroll
+  for (int t = 1; t < kNumProd; ++t)
+    if (j == t) J = O.job[t];
+  return J;
 }
 
-__global__ void reduce_partial_kernel(const float* __restrict__ partial, int chunks, int P, int Q,
-                                      float* __restrict__ dW, float* __restrict__ db) {
-  const size_t per = (size_t)P * Q + P;
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= per) return;
-  float s = 0.f;
-  for (int c = 0; c < chunks; ++c) s += partial[(size_t)c * per + e];
-  if (e < (size_t)P * Q) dW[e] = s;
-  else db[e - (size_t)P * Q] = s;
+__global__ void __launch_bounds__(kOuterBlock) outer_mfma_kernel(OuterArgs O) {
+  const OuterJob J = pick_job(O, blockIdx.y);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lo = lane & 15, grp = lane >> 4;
+  const int npt = (J.P + 15) >> 4, nqt = (J.Q + 16) >> 4;
+  if (w >= npt) return;
+  const int64_t c0 = (int64_t)blockIdx.x * O.chunk;
+  const int64_t c1 = std::min<int64_t>(c0 + O.chunk, O.M);
+  f32x4 acc[kMaxPT][kMaxQT];
+#pragma unroll
+  for (int pt = 0; pt < kMaxPT; ++pt)
+#pragma unroll
+    for (int qt = 0; qt < kMaxQT; ++qt) acc[pt][qt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t a = c0; a < c1; a += 4) {
+    const int64_t ar = a + grp;
+    const bool av = ar < c1;
+    float xa[kMaxPT], yb[kMaxQT];
+#pragma unroll
+    for (int pt = 0; pt < kMaxPT; ++pt) {
+      const int p = 16 * (w + 4 * pt) + lo;
+      xa[pt] = (av && p < J.P) ? J.X[ar * J.P + p] : 0.0f;
+    }
+#pragma unroll
+    for (int qt = 0; qt < kMaxQT; ++qt) {
+      const int q = 16 * qt + lo;
+      yb[qt] = !av ? 0.0f : q < J.Q ? J.Y[ar * J.Q + q] : (q == J.Q ? 1.0f : 0.0f);
+    }
+#pragma unroll
+    for (int pt = 0; pt < kMaxPT; ++pt)
+      if (w + 4 * pt < npt)
+#pragma unroll
+        for (int qt = 0; qt < kMaxQT; ++qt)
+          if (qt < nqt) acc[pt][qt] = mma(xa[pt], yb[qt], acc[pt][qt]);
+  }
+  float* out = O.part + (int64_t)blockIdx.x * O.per + J.off;
+  const int q1 = J.Q + 1;
+#pragma unroll
+  for (int pt = 0; pt < kMaxPT; ++pt) {
+    if (w + 4 * pt >= npt) break;
+#pragma unroll
+    for (int qt = 0; qt < kMaxQT; ++qt) {
+      const int q = 16 * qt + lo;
+      if (qt >= nqt || q >= q1) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int p = 16 * (w + 4 * pt) + 4 * grp + i;
+        if (p < J.P) out[(int64_t)p * q1 + q] = acc[pt][qt][i];
+      }
+    }
+  }
+}
+
+struct ReduceArgs {
+  float* dW[kNumProd];
+  float* db[kNumProd];
+  int Q[kNumProd];
+  int64_t off[kNumProd + 1];
+  int64_t per;
+  int chunks;
+  const float* part;
+};
+
+// Sums the chunks in a fixed order (four interleaved partial sums).
+__global__ void __launch_bounds__(256) reduce_outer_kernel(ReduceArgs R) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= R.per) return;
+  int j = 0;
+#pragma unroll
+  for (int t = 1; t < kNumProd; ++t) j += e >= R.off[t];
+  int Q = R.Q[0];
+  int64_t off = R.off[0];
+  float* dW = R.dW[0];
+  float* db = R.db[0];
+#pragma unroll
+  for (int t = 1; t < kNumProd; ++t)
+    if (j == t) {
+      Q = R.Q[t];
+      off = R.off[t];
+      dW = R.dW[t];
+      db = R.db[t];
+    }
+  float s[4] = {0.f, 0.f, 0.f, 0.f};
+  const float* p = R.part + e;
+  int c = 0;
+  for (; c + 4 <= R.chunks; c += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s[u] += p[(int64_t)(c + u) * R.per];
+  }
+  for (; c < R.chunks; ++c) s[0] += p[(int64_t)c * R.per];
+  const float v = (s[0] + s[1]) + (s[2] + s[3]);
+  const int64_t loc = e - off;
+  const int64_t row = loc / (Q + 1);
+  const int q = (int)(loc - row * (Q + 1));
+  if (q < Q) dW[row * Q + q] = v;
+  else db[row] = v;
+}
+
+size_t dec_lds_bytes(bool backward, int kw, int k) {
+  const size_t hp = 16 * (size_t)kw + 1, yp = 7 * (size_t)k + 1;
+  return (size_t)kRows * (kHP + (backward ? 2 : 1) * hp + yp) * sizeof(float);
+}
+
+template <int KW>
+void launch_kw(bool backward, const DecArgs& A, unsigned blocks, size_t lds, hipStream_t s) {
+  if (backward) hipLaunchKernelGGL(decode_backward_kernel<KW>, dim3(blocks), dim3(64), lds, s, A);
+  else hipLaunchKernelGGL(decode_forward_kernel<KW>, dim3(blocks), dim3(64), lds, s, A);
 }
 
 hipError_t launch_dec_any(bool backward, const DecArgs& A, hipStream_t s) {
-  const unsigned blocks = (unsigned)((A.m + kDecBlock - 1) / kDecBlock);
+  const unsigned blocks = (unsigned)((A.m + kRows - 1) / kRows);
   if (blocks == 0) return hipSuccess;
-  if (backward) {
-    const size_t lds = (size_t)(A.width + 7 * A.k) * kDecBlock * sizeof(float);
-    hipLaunchKernelGGL(decode_backward_kernel, dim3(blocks), dim3(kDecBlock), lds, s, A);
-  } else {
-    const size_t lds = (size_t)A.width * kDecBlock * sizeof(float);
-    hipLaunchKernelGGL(decode_forward_kernel, dim3(blocks), dim3(kDecBlock), lds, s, A);
+  const int kw = (A.width + 15) / 16;
+  const size_t lds = dec_lds_bytes(backward, kw, A.k);
+  switch (kw) {
+    case 1: launch_kw<1>(backward, A, blocks, lds, s); break;
+    case 2: launch_kw<2>(backward, A, blocks, lds, s); break;
+    case 3: launch_kw<3>(backward, A, blocks, lds, s); break;
+    case 4: launch_kw<4>(backward, A, blocks, lds, s); break;
+    case 5: launch_kw<5>(backward, A, blocks, lds, s); break;
+    case 6: launch_kw<6>(backward, A, blocks, lds, s); break;
+    case 7: launch_kw<7>(backward, A, blocks, lds, s); break;
+    case 8: launch_kw<8>(backward, A, blocks, lds, s); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
+
 
 bool finite3(const float* c) { return std::isfinite(c[0]) && std::isfinite(c[1]) && std::isfinite(c[2]); }
 
@@ -376,13 +629,29 @@ int vpgs_decode_backward(vpgs_ctx* ctx, const vpgs_anchors* an, const vpgs_mlp* 
   const int outs[3] = {k, 3 * k, 7 * k};
   // workspace: h, hidden x3, dpre x3, dy x3
   const size_t ws_floats = (size_t)M * (kIn + 6 * (size_t)width + 11 * (size_t)k);
-  const int chunks = (int)std::max<int64_t>((M + kChunk - 1) / kChunk, 1);
-  size_t part_floats = 0;
-  for (int h = 0; h < 3; ++h) {
-    part_floats = std::max(part_floats, (size_t)chunks * ((size_t)outs[h] * width + outs[h]));
-    part_floats = std::max(part_floats, (size_t)chunks * ((size_t)width * kIn + width));
+  // chunks of at least 256 anchors, at most 512 chunks
+  const int64_t chunk = std::max<int64_t>(256, ((M + 511) / 512 + 15) / 16 * 16);
+  const int chunks = (int)std::max<int64_t>((M + chunk - 1) / chunk, 1);
+  OuterArgs O;
+  ReduceArgs R;
+  std::memset(&O, 0, sizeof(O));
+  std::memset(&R, 0, sizeof(R));
+  int64_t per = 0;
+  for (int j = 0; j < kNumProd; ++j) {
+    const int h = j / 2;
+    // even j: dW2[h] = DY^T HID (+ db2); odd j: dW1[h] = DPRE^T H (+ db1)
+    const int P = j % 2 == 0 ? outs[h] : width, Q = j % 2 == 0 ? width : kIn;
+    O.job[j].P = P;
+    O.job[j].Q = Q;
+    O.job[j].off = per;
+    R.Q[j] = Q;
+    R.off[j] = per;
+    R.dW[j] = j % 2 == 0 ? dm->W2[h] : dm->W1[h];
+    R.db[j] = j % 2 == 0 ? dm->b2[h] : dm->b1[h];
+    per += (int64_t)P * (Q + 1);
   }
-  if ((rc = ensure(ctx, ctx->dec_ws, ws_floats * 4)) || (rc = ensure(ctx, ctx->dec_partial, part_floats * 4)))
+  R.off[kNumProd] = per;
+  if ((rc = ensure(ctx, ctx->dec_ws, ws_floats * 4)) || (rc = ensure(ctx, ctx->dec_partial, (size_t)chunks * per * 4)))
     return rc;
   DecArgs A = make_args(an, mlp, cam_center);
   A.g_means = up->means; A.g_ls = up->log_scales; A.g_quats = up->quats; A.g_opac = up->opacities;
@@ -394,30 +663,32 @@ int vpgs_decode_backward(vpgs_ctx* ctx, const vpgs_anchors* an, const vpgs_mlp* 
   for (int h = 0; h < 3; ++h) { A.ws_dpre[h] = w; w += (size_t)M * width; }
   for (int h = 0; h < 3; ++h) { A.ws_dy[h] = w; w += (size_t)M * outs[h]; }
   StageTimer t(ctx, ST_DEC_BWD, st);
-  HIP_TRY(launch_dec_any(true, A, st));
-  float* part = static_cast<float*>(ctx->dec_partial.p);
-  for (int h = 0; h < 3; ++h) {
-    // dW2[h] = DY^T HID, db2 = column sums of DY; dW1[h] = DPRE^T H, db1 = column sums of DPRE
-    const float* X[2] = {A.ws_dy[h], A.ws_dpre[h]};
-    const float* Y[2] = {A.ws_hid[h], A.ws_h};
-    const int P[2] = {outs[h], width}, Q[2] = {width, kIn};
-    float* dW[2] = {dm->W2[h], dm->W1[h]};
-    float* db[2] = {dm->b2[h], dm->b1[h]};
-    for (int g = 0; g < 2; ++g) {
-      if (M > 0) {
-        dim3 grid(chunks, (P[g] + kTile - 1) / kTile, (Q[g] + kTile - 1) / kTile);
-        hipLaunchKernelGGL(outer_partial_kernel, grid, dim3(256), 0, st, X[g], P[g], Y[g], Q[g], M, part);
-        HIP_TRY(hipGetLastError());
-        const size_t per = (size_t)P[g] * Q[g] + P[g];
-        hipLaunchKernelGGL(reduce_partial_kernel, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, st, part,
-                           chunks, P[g], Q[g], dW[g], db[g]);
-        HIP_TRY(hipGetLastError());
-      } else {
-        HIP_TRY(launch_fill_f32(dW[g], 0.f, (size_t)P[g] * Q[g], st));
-        HIP_TRY(launch_fill_f32(db[g], 0.f, (size_t)P[g], st));
-      }
+  if (M == 0) {
+    for (int j = 0; j < kNumProd; ++j) {
+      const int P = O.job[j].P, Q = O.job[j].Q;
+      HIP_TRY(launch_fill_f32(R.dW[j], 0.f, (size_t)P * Q, st));
+      HIP_TRY(launch_fill_f32(R.db[j], 0.f, (size_t)P, st));
     }
+    return VPGS_OK;
   }
+  HIP_TRY(launch_dec_any(true, A, st));
+  for (int h = 0; h < 3; ++h) {
+    O.job[2 * h].X = A.ws_dy[h];
+    O.job[2 * h].Y = A.ws_hid[h];
+    O.job[2 * h + 1].X = A.ws_dpre[h];
+    O.job[2 * h + 1].Y = A.ws_h;
+  }
+  O.M = M;
+  O.chunk = chunk;
+  O.per = per;
+  O.part = static_cast<float*>(ctx->dec_partial.p);
+  hipLaunchKernelGGL(outer_mfma_kernel, dim3(chunks, kNumProd), dim3(kOuterBlock), 0, st, O);
+  HIP_TRY(hipGetLastError());
+  R.per = per;
+  R.chunks = chunks;
+  R.part = O.part;
+  hipLaunchKernelGGL(reduce_outer_kernel, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, st, R);
+  HIP_TRY(hipGetLastError());
   return VPGS_OK;
 }
 
