@@ -8,20 +8,20 @@
 // the anchor scaling (eq. 5) and a normalised quaternion.
 //
 // The heads are small dense products over a batch of anchors, so they run on
-// the matrix cores: one wavefront takes 16 anchors (the M rows of a
-// 16x16x4 FP32 MFMA tile) end to end, with its input rows, hidden layer and
-// head outputs in a private slice of LDS, and streams the weights (a few tens
-// of KB, L2-resident) as the B operands.  The activations then run one lane
-// per (anchor, Gaussian) output so that the stores are contiguous.
+// the matrix cores: a wavefront takes 16 anchors (the M rows of a 16x16x4
+// FP32 MFMA tile) end to end, with its input rows, hidden layer and head
+// outputs in a private slice of LDS; the block's four wavefronts share one
+// head's weights, staged in LDS, as the B operands.  The activations then run
+// one lane per (anchor, Gaussian) output so that the stores are contiguous.
 //
-// Backward: the same wavefront recomputes its forward, chains the upstream
+// Backward: the same blocks recompute the forward, chain the upstream
 // Gaussian gradients through the activations and both layers with the same
-// tiles (feature, scaling and offset gradients are written directly), and
-// stores each layer's input and output gradient.  The weight gradients are
-// sums over anchors of outer products: one launch forms all six of them
-// (W2 and W1 of each head, the bias as an extra all-ones column) per chunk of
-// anchors on the matrix cores, and a second sums the chunks in a fixed order,
-// so they are deterministic.
+// tiles (feature, scaling and offset gradients are written directly), and,
+// holding every layer's input and output gradient for their 64 anchors in
+// LDS, form their share of the six weight-gradient products (W2 and W1 of
+// each head, the bias as an extra all-ones column) on the matrix cores as one
+// partial row per block.  The rows are summed in a fixed order in two levels,
+// so the weight gradients are deterministic.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -34,6 +34,9 @@ namespace {
 constexpr int kIn = 36;
 constexpr int kRows = 16;      // anchors per wavefront: the rows of every tile
 constexpr int kHP = kIn + 1;   // LDS pitch of the input rows
+constexpr int kW1P = kIn + 1;  // LDS pitch of the first-layer weight rows
+constexpr int kDecWaves = 4;   // wavefronts per block: they share the staged weights
+constexpr int kDecThreads = 64 * kDecWaves;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -72,10 +75,13 @@ struct DecArgs {
   float* d_feat;
   float* d_scale;
   float* d_offsets;
-  float* ws_h;       // [m, 36]
-  float* ws_hid[3];  // [m, width] post-ReLU hidden layer
-  float* ws_dpre[3]; // [m, width] gradient at the hidden pre-activation
-  float* ws_dy[3];   // [m, out_h] gradient at the head outputs
+  // per-block weight-gradient partials: the block with blockIdx.x = b (anchors
+  // from (block0 + b) 64) writes the row at part + b part_per, product j (W2
+  // of head j / 2 for even j, W1 for odd j) at part_off[j] within it
+  int64_t block0;
+  float* part;
+  int64_t part_per;
+  int64_t part_off[6];
 };
 
 __device__ __forceinline__ float sigmoidf_(float y) { return 1.0f / (1.0f + expf(-y)); }
@@ -83,9 +89,30 @@ __device__ __forceinline__ float log_sigmoidf_(float y) { return -(fmaxf(-y, 0.0
 
 __host__ __device__ constexpr int head_outs(int h, int k) { return (h == 0 ? 1 : h == 1 ? 3 : 7) * k; }
 
+// Runs store(e, load(e)) over the elements e < n of a wavefront, U per
+// lane at a time with the U loads issued before any store (the outputs
+// may not alias the inputs, but the compiler cannot know that).
+template <int U = 4, class Load, class Store>
+__device__ __forceinline__ void blocked(int n, int lane, Load load, Store store) {
+  for (int base = 0; base < n; base += 64 * U) {
+    decltype(load(0)) v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + lane + 64 * u;
+      if (e < n) v[u] = load(e);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + lane + 64 * u;
+      if (e < n) store(e, v[u]);
+    }
+  }
+}
+
 // Rows of h = [feat (32), direction (3), distance (1)] (eq. 3) for the
-// wavefront's anchors a0 .. a0 + nv - 1; rows past nv are zero.
-__device__ __forceinline__ void load_inputs(const DecArgs& A, int64_t a0, int nv, int lane, float* Hs) {
+// wavefront's anchors a0 .. a0 + nv - 1 (rows past nv are zero), and the log
+// of their scalings (eq. 5).
+__device__ __forceinline__ void load_inputs(const DecArgs& A, int64_t a0, int nv, int lane, float* Hs, float* logl) {
 #pragma unroll
   for (int e = lane; e < kRows * 32; e += 64) {
     const int r = e >> 5, i = e & 31;
@@ -106,27 +133,65 @@ __device__ __forceinline__ void load_inputs(const DecArgs& A, int64_t a0, int nv
 #pragma unroll
     for (int j = 0; j < 4; ++j) Hs[lane * kHP + 32 + j] = d[j];
   }
+  if (lane < 3 * kRows) logl[lane] = lane < 3 * nv ? logf(A.scale[a0 * 3 + lane]) : 0.0f;
+}
+
+// The parameters of head h in LDS, shared by the block's wavefronts: W1 as
+// [width][kW1P], W2 as [outs][width + 1], then b1 and b2.  Synchronises
+// before (the previous head's may still be in use) and after.
+struct HeadLds {
+  float* w1;
+  float* w2;
+  float* b1;
+  float* b2;
+};
+
+__device__ __forceinline__ HeadLds head_lds(float* lds, int W, int k) {
+  HeadLds p;
+  p.w1 = lds;
+  p.w2 = p.w1 + W * kW1P;
+  p.b1 = p.w2 + 7 * k * (W + 1);
+  p.b2 = p.b1 + W;
+  return p;
+}
+
+__host__ __device__ constexpr int head_lds_floats(int W, int k) { return W * kW1P + 7 * k * (W + 1) + W + 7 * k; }
+
+__device__ __forceinline__ void stage_weights(const DecArgs& A, int h, const HeadLds& p) {
+  const int W = A.width, outs = head_outs(h, A.k);
+  const float* __restrict__ W1 = A.W1[h];
+  const float* __restrict__ W2 = A.W2[h];
+  __syncthreads();
+  for (int e = threadIdx.x; e < W * kIn; e += kDecThreads) {
+    const int j = e / kIn;
+    p.w1[j * kW1P + e - j * kIn] = W1[e];
+  }
+  for (int o = threadIdx.x / 64; o < outs; o += kDecWaves)
+    for (int j = threadIdx.x & 63; j < W; j += 64) p.w2[o * (W + 1) + j] = W2[(size_t)o * W + j];
+  for (int j = threadIdx.x; j < W; j += kDecThreads) p.b1[j] = A.b1[h][j];
+  for (int o = threadIdx.x; o < outs; o += kDecThreads) p.b2[o] = A.b2[h][o];
+  __syncthreads();
 }
 
 // hid[r][j] = relu(b1[j] + sum_i W1[j][i] h[r][i]) for the KW column tiles
 // of the hidden layer (columns past the width come out zero).  ha holds the
 // A operand: lane group g covers inputs 9g .. 9g + 8.
 template <int KW>
-__device__ __forceinline__ void hidden_tiles(const float* __restrict__ W1, const float* __restrict__ b1, int W,
-                                             const float ha[9], float* hid, int lane) {
+__device__ __forceinline__ void hidden_tiles(const float* w1s, const float* b1, int W, const float ha[9],
+                                             float* hid, int lane) {
   constexpr int HP = 16 * KW + 1;
   const int lo = lane & 15, grp = lane >> 4;
 #pragma unroll
   for (int ct = 0; ct < KW; ++ct) {
     const int j = 16 * ct + lo;
     const bool jv = j < W;
+    const float bias = jv ? b1[j] : 0.0f;
     float b[9];
 #pragma unroll
-    for (int ks = 0; ks < 9; ++ks) b[ks] = jv ? W1[j * kIn + 9 * grp + ks] : 0.0f;
+    for (int ks = 0; ks < 9; ++ks) b[ks] = jv ? w1s[j * kW1P + 9 * grp + ks] : 0.0f;
     f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < 9; ++ks) c = mma(ha[ks], b[ks], c);
-    const float bias = jv ? b1[j] : 0.0f;
 #pragma unroll
     for (int i = 0; i < 4; ++i) hid[(4 * grp + i) * HP + j] = fmaxf(c[i] + bias, 0.0f);
   }
@@ -135,7 +200,7 @@ __device__ __forceinline__ void hidden_tiles(const float* __restrict__ W1, const
 // y[r][o] = b2[o] + sum_j W2[o][j] hid[r][j] for o < outs, 16 outputs per
 // tile; lane group g covers hidden units g KS .. g KS + KS - 1.
 template <int KW>
-__device__ __forceinline__ void out_tiles(const float* __restrict__ W2, const float* __restrict__ b2, int W, int outs,
+__device__ __forceinline__ void out_tiles(const float* w2s, const float* b2, int W, int outs,
                                           const float* hid, float* ys, int yp, int lane) {
   constexpr int HP = 16 * KW + 1, KS = 4 * KW;
   const int lo = lane & 15, grp = lane >> 4;
@@ -145,50 +210,60 @@ __device__ __forceinline__ void out_tiles(const float* __restrict__ W2, const fl
   for (int o0 = 0; o0 < outs; o0 += 16) {
     const int o = o0 + lo;
     const bool ov = o < outs;
+    const float bias = ov ? b2[o] : 0.0f;
     float b[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int j = KS * grp + ks;
-      b[ks] = (ov && j < W) ? W2[(size_t)o * W + j] : 0.0f;
+      b[ks] = (ov && j < W) ? w2s[o * (W + 1) + j] : 0.0f;
     }
     f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) c = mma(ha[ks], b[ks], c);
     if (ov) {
-      const float bias = b2[o];
 #pragma unroll
       for (int i = 0; i < 4; ++i) ys[(4 * grp + i) * yp + o] = c[i] + bias;
     }
   }
 }
 
+struct MeanIn {
+  float off, x, l;
+};
+
 template <int KW>
-__global__ void __launch_bounds__(64) decode_forward_kernel(DecArgs A) {
+__global__ void __launch_bounds__(kDecThreads) decode_forward_kernel(DecArgs A) {
   extern __shared__ float lds[];
   constexpr int HP = 16 * KW + 1;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int k = A.k, W = A.width, yp = 7 * k + 1;
-  float* Hs = lds;
+  const HeadLds P = head_lds(lds, W, k);
+  float* Hs = lds + head_lds_floats(W, k) + wave * (kRows * (kHP + HP + yp) + 3 * kRows);
   float* hid = Hs + kRows * kHP;
   float* ys = hid + kRows * HP;
-  const int64_t a0 = (int64_t)blockIdx.x * kRows;
-  const int nv = (int)std::min<int64_t>(A.m - a0, kRows);
-  load_inputs(A, a0, nv, lane, Hs);
-  const int n3 = nv * 3 * k;
-  for (int e = lane; e < n3; e += 64) {  // eq. 1
-    const int r = e / (3 * k), c = e % 3;
-    const int64_t a = a0 + r, g = a0 * 3 * k + e;
-    A.means[g] = A.xyz[3 * a + c] + A.offsets[g] * A.scale[3 * a + c];
-  }
+  float* logl = ys + kRows * yp;
+  const int64_t a0 = ((int64_t)blockIdx.x * kDecWaves + wave) * kRows;
+  const int nv = (int)std::max<int64_t>(std::min<int64_t>(A.m - a0, kRows), 0);
+  load_inputs(A, a0, nv, lane, Hs, logl);
+  const int k3 = 3 * k;
+  blocked<8>(  // eq. 1
+      nv * k3, lane,
+      [&](int e) {
+        const int64_t a = a0 + e / k3;
+        const int c = e % 3;
+        return MeanIn{A.offsets[a0 * k3 + e], A.xyz[3 * a + c], A.scale[3 * a + c]};
+      },
+      [&](int e, MeanIn v) { A.means[a0 * k3 + e] = v.x + v.off * v.l; });
   __syncthreads();
   float ha[9];
 #pragma unroll
   for (int ks = 0; ks < 9; ++ks) ha[ks] = Hs[(lane & 15) * kHP + 9 * (lane >> 4) + ks];
   for (int h = 0; h < 3; ++h) {
     const int outs = head_outs(h, k);
-    hidden_tiles<KW>(A.W1[h], A.b1[h], W, ha, hid, lane);
+    stage_weights(A, h, P);
+    hidden_tiles<KW>(P.w1, P.b1, W, ha, hid, lane);
     __syncthreads();
-    out_tiles<KW>(A.W2[h], A.b2[h], W, outs, hid, ys, yp, lane);
+    out_tiles<KW>(P.w2, P.b2, W, outs, hid, ys, yp, lane);
     __syncthreads();
     if (h == 0) {
       for (int e = lane; e < nv * k; e += 64) {
@@ -196,34 +271,32 @@ __global__ void __launch_bounds__(64) decode_forward_kernel(DecArgs A) {
         A.opac[a0 * k + e] = tanhf(ys[r * yp + e - r * k]);
       }
     } else if (h == 1) {
-      for (int e = lane; e < nv * 3 * k; e += 64) {  // eq. 4
-        const int r = e / (3 * k);
-        A.colors[a0 * 3 * k + e] = sigmoidf_(ys[r * yp + e - r * 3 * k]);
+      for (int e = lane; e < nv * k3; e += 64) {  // eq. 4
+        const int r = e / k3;
+        A.colors[a0 * k3 + e] = sigmoidf_(ys[r * yp + e - r * k3]);
       }
     } else {
       for (int e = lane; e < nv * k; e += 64) {
         const int r = e / k;
         const float* y = ys + r * yp + 7 * (e - r * k);
-        const int64_t a = a0 + r, g = a0 * k + e;
+        const int64_t g = a0 * k + e;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) A.log_scales[3 * g + j] = log_sigmoidf_(y[j]) + logf(A.scale[3 * a + j]);  // eq. 5
+        for (int j = 0; j < 3; ++j) A.log_scales[3 * g + j] = log_sigmoidf_(y[j]) + logl[3 * r + j];  // eq. 5
         const float n = fmaxf(sqrtf(y[3] * y[3] + y[4] * y[4] + y[5] * y[5] + y[6] * y[6]), 1e-12f);
         const float in = 1.0f / n;
 #pragma unroll
         for (int j = 0; j < 4; ++j) A.quats[4 * g + j] = y[3 + j] * in;
       }
     }
-    __syncthreads();
   }
 }
 
 // dhid[r][j] = sum_o dy[r][o] W2[o][j]; dpre = dhid where the hidden unit is
-// active.  Writes dpre to LDS and the hidden layer and dpre of the valid rows
-// to the workspace.  Lane group g covers outputs o0 + 4g .. o0 + 4g + 3.
+// active, written over the hidden layer (each lane reads and writes only its
+// own elements).  Lane group g covers outputs o0 + 4g .. o0 + 4g + 3.
 template <int KW>
-__device__ __forceinline__ void hid_grad_tiles(const float* __restrict__ W2, int W, int outs, const float* dys, int yp,
-                                               const float* hid, float* dpre, float* ws_hid, float* ws_dpre,
-                                               int64_t a0, int nv, int lane) {
+__device__ __forceinline__ void hid_grad_tiles(const float* w2s, int W, int outs, const float* dys, int yp,
+                                               float* hid, int lane) {
   constexpr int HP = 16 * KW + 1;
   const int lo = lane & 15, grp = lane >> 4;
   f32x4 acc[KW];
@@ -239,14 +312,11 @@ __device__ __forceinline__ void hid_grad_tiles(const float* __restrict__ W2, int
 #pragma unroll
     for (int ct = 0; ct < KW; ++ct) {
       const int j = 16 * ct + lo;
-      float b[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int o = o0 + 4 * grp + s;
-        b[s] = (o < outs && j < W) ? W2[(size_t)o * W + j] : 0.0f;
+        acc[ct] = mma(a[s], (o < outs && j < W) ? w2s[o * (W + 1) + j] : 0.0f, acc[ct]);
       }
-#pragma unroll
-      for (int s = 0; s < 4; ++s) acc[ct] = mma(a[s], b[s], acc[ct]);
     }
   }
 #pragma unroll
@@ -255,13 +325,7 @@ __device__ __forceinline__ void hid_grad_tiles(const float* __restrict__ W2, int
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = 4 * grp + i;
-      const float hv = hid[r * HP + j];
-      const float dp = hv > 0.0f ? acc[ct][i] : 0.0f;
-      dpre[r * HP + j] = dp;
-      if (r < nv && j < W) {
-        ws_hid[(a0 + r) * W + j] = hv;
-        ws_dpre[(a0 + r) * W + j] = dp;
-      }
+      hid[r * HP + j] = hid[r * HP + j] > 0.0f ? acc[ct][i] : 0.0f;
     }
   }
 }
@@ -269,8 +333,7 @@ __device__ __forceinline__ void hid_grad_tiles(const float* __restrict__ W2, int
 // dh[r][c] += sum_j dpre[r][j] W1[j][c] for the 32 feature inputs (the
 // direction and distance inputs have no parameters upstream).
 template <int KW>
-__device__ __forceinline__ void input_grad_tiles(const float* __restrict__ W1, int W, const float* dpre, f32x4 dh[2],
-                                                 int lane) {
+__device__ __forceinline__ void input_grad_tiles(const float* w1s, int W, const float* dpre, f32x4 dh[2], int lane) {
   constexpr int HP = 16 * KW + 1, KS = 4 * KW;
   const int lo = lane & 15, grp = lane >> 4;
   float a[KS];
@@ -282,31 +345,74 @@ __device__ __forceinline__ void input_grad_tiles(const float* __restrict__ W1, i
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int j = KS * grp + ks;
-      dh[ct] = mma(a[ks], j < W ? W1[j * kIn + c] : 0.0f, dh[ct]);
+      dh[ct] = mma(a[ks], j < W ? w1s[j * kW1P + c] : 0.0f, dh[ct]);
     }
   }
 }
 
+// part[p][q] += sum over the block's anchors a of X[a][p] Y'[a][q], where Y'
+// is Y with a trailing all-ones column (q = Q gives the bias gradient).  Row
+// a of X and Y lives in the LDS region of wavefront a / 16, at row a % 16;
+// anchors past nvb (the block's valid count) contribute nothing.  Tiles of
+// 16x16 go round-robin over the wavefronts; each sums the 64 anchors in 16
+// MFMA steps (lane group g takes anchor 4s + g of step s).
+__device__ __forceinline__ void wgrad_tiles(const float* region0, int region_floats, int xoff, int xp, int P,
+                                            int yoff, int ypitch, int Q, int nvb, float* __restrict__ out, int wave,
+                                            int lane) {
+  const int lo = lane & 15, grp = lane >> 4;
+  const int nqt = (Q + 16) >> 4, nt = ((P + 15) >> 4) * nqt;
+  for (int t = wave; t < nt; t += kDecWaves) {
+    const int pt = t / nqt, qt = t - pt * nqt;
+    const int p = 16 * pt + lo, q = 16 * qt + lo;
+    f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int a = 4 * s + grp;
+      const float* reg = region0 + (a >> 4) * region_floats;
+      const int r = a & 15;
+      const float x = (a < nvb && p < P) ? reg[xoff + r * xp + p] : 0.0f;
+      const float y = q < Q ? reg[yoff + r * ypitch + q] : (q == Q ? 1.0f : 0.0f);
+      c = mma(x, y, c);
+    }
+    if (q <= Q) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pp = 16 * pt + 4 * grp + i;
+        if (pp < P) out[pp * (Q + 1) + q] = c[i];
+      }
+    }
+  }
+}
+
+struct ScaleGradIn {
+  float gl[3], gq[4];
+};
+
 template <int KW>
-__global__ void __launch_bounds__(64) decode_backward_kernel(DecArgs A) {
+__global__ void __launch_bounds__(kDecThreads) decode_backward_kernel(DecArgs A) {
   extern __shared__ float lds[];
   constexpr int HP = 16 * KW + 1;
-  const int lane = threadIdx.x, lo = lane & 15, grp = lane >> 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lo = lane & 15, grp = lane >> 4;
   const int k = A.k, W = A.width, yp = 7 * k + 1;
-  float* Hs = lds;
-  float* hid = Hs + kRows * kHP;
-  float* dpre = hid + kRows * HP;
-  float* ys = dpre + kRows * HP;
-  const int64_t a0 = (int64_t)blockIdx.x * kRows;
-  const int nv = (int)std::min<int64_t>(A.m - a0, kRows);
-  load_inputs(A, a0, nv, lane, Hs);
+  const HeadLds P = head_lds(lds, W, k);
+  float* region0 = lds + head_lds_floats(W, k);
+  const int region_floats = kRows * (kHP + HP + yp) + 3 * kRows;
+  const int hid_off = kRows * kHP, ys_off = hid_off + kRows * HP;
+  float* Hs = region0 + wave * region_floats;
+  float* hid = Hs + hid_off;  // the hidden layer, then the gradient at its pre-activation
+  float* ys = Hs + ys_off;    // the head outputs, then the gradient at them
+  float* logl = ys + kRows * yp;
+  const int64_t b0 = (A.block0 + blockIdx.x) * kDecWaves * kRows;
+  const int nvb = (int)std::min<int64_t>(A.m - b0, kDecWaves * kRows);
+  const int64_t a0 = b0 + wave * kRows;
+  const int nv = std::max(std::min(nvb - wave * kRows, kRows), 0);
+  float* part = A.part + (int64_t)blockIdx.x * A.part_per;
+  load_inputs(A, a0, nv, lane, Hs, logl);
+  const int k3 = 3 * k;
   // eq. 1: mean = anchor + offset * l
-  const int n3 = nv * 3 * k;
-  for (int e = lane; e < n3; e += 64) {
-    const int r = e / (3 * k), c = e % 3;
-    const int64_t g = a0 * 3 * k + e;
-    A.d_offsets[g] = A.g_means[g] * A.scale[3 * (a0 + r) + c];
-  }
+  blocked<8>(
+      nv * k3, lane, [&](int e) { return float2{A.g_means[a0 * k3 + e], A.scale[3 * (a0 + e / k3) + e % 3]}; },
+      [&](int e, float2 v) { A.d_offsets[a0 * k3 + e] = v.x * v.y; });
   // scaling: through the means and through eq. 5's log l
   if (lane < 3 * nv) {
     const int r = lane / 3, c = lane - 3 * r;
@@ -318,72 +424,76 @@ __global__ void __launch_bounds__(64) decode_backward_kernel(DecArgs A) {
     A.d_scale[3 * a + c] = s;
   }
   __syncthreads();
-  for (int e = lane; e < nv * kIn; e += 64) {
-    const int r = e / kIn;
-    A.ws_h[a0 * kIn + e] = Hs[r * kHP + e - r * kIn];
-  }
   float ha[9];
 #pragma unroll
   for (int ks = 0; ks < 9; ++ks) ha[ks] = Hs[lo * kHP + 9 * grp + ks];
   f32x4 dh[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
   for (int h = 0; h < 3; ++h) {
     const int outs = head_outs(h, k);
-    hidden_tiles<KW>(A.W1[h], A.b1[h], W, ha, hid, lane);
+    stage_weights(A, h, P);
+    hidden_tiles<KW>(P.w1, P.b1, W, ha, hid, lane);
     __syncthreads();
-    out_tiles<KW>(A.W2[h], A.b2[h], W, outs, hid, ys, yp, lane);
+    out_tiles<KW>(P.w2, P.b2, W, outs, hid, ys, yp, lane);
     __syncthreads();
     // gradient at the head outputs, in place of the outputs
-    float* wdy = A.ws_dy[h] + a0 * outs;
     if (h == 0) {  // tanh
-      for (int e = lane; e < nv * k; e += 64) {
-        const int r = e / k, o = e - r * k;
-        const float t = tanhf(ys[r * yp + o]);
-        const float dy = A.g_opac[a0 * k + e] * (1.0f - t * t);
-        ys[r * yp + o] = dy;
-        wdy[e] = dy;
-      }
+      blocked(
+          nv * k, lane, [&](int e) { return A.g_opac[a0 * k + e]; },
+          [&](int e, float go) {
+            const int r = e / k;
+            float* y = ys + r * yp + e - r * k;
+            const float t = tanhf(*y);
+            *y = go * (1.0f - t * t);
+          });
     } else if (h == 1) {  // sigmoid (eq. 4)
-      for (int e = lane; e < nv * 3 * k; e += 64) {
-        const int r = e / (3 * k), o = e - r * 3 * k;
-        const float s = sigmoidf_(ys[r * yp + o]);
-        const float dy = A.g_colors[a0 * 3 * k + e] * s * (1.0f - s);
-        ys[r * yp + o] = dy;
-        wdy[e] = dy;
-      }
+      blocked<8>(
+          nv * k3, lane, [&](int e) { return A.g_colors[a0 * k3 + e]; },
+          [&](int e, float gc) {
+            const int r = e / k3;
+            float* y = ys + r * yp + e - r * k3;
+            const float s = sigmoidf_(*y);
+            *y = gc * s * (1.0f - s);
+          });
     } else {  // [scale (eq. 5) | quaternion]
-      for (int e = lane; e < nv * k; e += 64) {
-        const int r = e / k;
-        float* y = ys + r * yp + 7 * (e - r * k);
-        const int64_t g = a0 * k + e;
-        float dy[7];
+      blocked(
+          nv * k, lane,
+          [&](int e) {
+            const int64_t g = a0 * k + e;
+            return ScaleGradIn{{A.g_ls[3 * g], A.g_ls[3 * g + 1], A.g_ls[3 * g + 2]},
+                               {A.g_quats[4 * g], A.g_quats[4 * g + 1], A.g_quats[4 * g + 2], A.g_quats[4 * g + 3]}};
+          },
+          [&](int e, const ScaleGradIn& v) {
+            const int r = e / k;
+            float* y = ys + r * yp + 7 * (e - r * k);
+            float dy[7];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) dy[j] = A.g_ls[3 * g + j] * (1.0f - sigmoidf_(y[j]));  // d log_sigmoid(y) / dy
-        const float nr = sqrtf(y[3] * y[3] + y[4] * y[4] + y[5] * y[5] + y[6] * y[6]);
-        const float gq[4] = {A.g_quats[4 * g], A.g_quats[4 * g + 1], A.g_quats[4 * g + 2], A.g_quats[4 * g + 3]};
-        if (nr > 1e-12f) {
-          const float in = 1.0f / nr;
-          const float q0 = y[3] * in, q1 = y[4] * in, q2 = y[5] * in, q3 = y[6] * in;
-          const float dot = q0 * gq[0] + q1 * gq[1] + q2 * gq[2] + q3 * gq[3];
-          dy[3] = (gq[0] - q0 * dot) * in;
-          dy[4] = (gq[1] - q1 * dot) * in;
-          dy[5] = (gq[2] - q2 * dot) * in;
-          dy[6] = (gq[3] - q3 * dot) * in;
-        } else {
+            for (int j = 0; j < 3; ++j) dy[j] = v.gl[j] * (1.0f - sigmoidf_(y[j]));  // d log_sigmoid(y) / dy
+            const float nr = sqrtf(y[3] * y[3] + y[4] * y[4] + y[5] * y[5] + y[6] * y[6]);
+            if (nr > 1e-12f) {
+              const float in = 1.0f / nr;
+              const float q0 = y[3] * in, q1 = y[4] * in, q2 = y[5] * in, q3 = y[6] * in;
+              const float dot = q0 * v.gq[0] + q1 * v.gq[1] + q2 * v.gq[2] + q3 * v.gq[3];
+              dy[3] = (v.gq[0] - q0 * dot) * in;
+              dy[4] = (v.gq[1] - q1 * dot) * in;
+              dy[5] = (v.gq[2] - q2 * dot) * in;
+              dy[6] = (v.gq[3] - q3 * dot) * in;
+            } else {
 #pragma unroll
-          for (int j = 0; j < 4; ++j) dy[3 + j] = gq[j] * 1e12f;
-        }
+              for (int j = 0; j < 4; ++j) dy[3 + j] = v.gq[j] * 1e12f;
+            }
 #pragma unroll
-        for (int j = 0; j < 7; ++j) {
-          y[j] = dy[j];
-          wdy[7 * e + j] = dy[j];
-        }
-      }
+            for (int j = 0; j < 7; ++j) y[j] = dy[j];
+          });
     }
     __syncthreads();
-    hid_grad_tiles<KW>(A.W2[h], W, outs, ys, yp, hid, dpre, A.ws_hid[h], A.ws_dpre[h], a0, nv, lane);
+    // dW2 = DY^T HID, db2 = column sums of DY
+    wgrad_tiles(region0, region_floats, ys_off, yp, outs, hid_off, HP, W, nvb, part + A.part_off[2 * h], wave, lane);
     __syncthreads();
-    input_grad_tiles<KW>(A.W1[h], W, dpre, dh, lane);
+    hid_grad_tiles<KW>(P.w2, W, outs, ys, yp, hid, lane);
     __syncthreads();
+    input_grad_tiles<KW>(P.w1, W, hid, dh, lane);
+    // dW1 = DPRE^T H, db1 = column sums of DPRE
+    wgrad_tiles(region0, region_floats, hid_off, HP, W, 0, kHP, kIn, nvb, part + A.part_off[2 * h + 1], wave, lane);
   }
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct)
@@ -394,91 +504,29 @@ __global__ void __launch_bounds__(64) decode_backward_kernel(DecArgs A) {
     }
 }
 
-// ---------------------------------------------------------------------------
-// Weight gradients: for each of the six products, part[chunk][p][q] =
-// sum over the chunk's anchors a of X[a][p] Y'[a][q], where Y' is Y with a
-// trailing all-ones column (q = Q gives the bias gradient sum_a X[a][p]).
-// One block per (chunk, product); wavefront w owns the p tiles w and w + 4
-// and every q tile, so no two wavefronts share an output.
-// ---------------------------------------------------------------------------
+// dst[g][e] (+)= sum of src[r][e] over the rows r of group g (group rows
+// each, eight interleaved partial sums): the first level of the fixed-order
+// sum of the block partials.  Adds to dst when accumulate is set.
+__global__ void __launch_bounds__(256) sum_rows_kernel(const float* __restrict__ src, int rows, int64_t per,
+                                                       int group, int accumulate, float* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= per) return;
+  const int r0 = blockIdx.y * group, r1 = std::min(r0 + group, rows);
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int r = r0;
+  for (; r + 8 <= r1; r += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += src[(int64_t)(r + u) * per + e];
+  }
+  for (; r < r1; ++r) s[0] += src[(int64_t)r * per + e];
+  const float v = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  float* d = dst + (int64_t)blockIdx.y * per + e;
+  *d = accumulate ? *d + v : v;
+}
+
 constexpr int kNumProd = 6;
-constexpr int kMaxPT = 2;  // P <= 128: 8 tiles over 4 wavefronts
-constexpr int kMaxQT = 9;  // Q + 1 <= 129
-constexpr int kOuterBlock = 256;
-
-struct OuterJob {
-  const float* X;
-  const float* Y;
-  int P, Q;
-  int64_t off;  // offset of this product in a chunk's partial row
-};
-
-struct OuterArgs {
-  OuterJob job[kNumProd];
-  int64_t M;
-  int64_t chunk;
-  int64_t per;  // floats per chunk: sum of P (Q + 1)
-  float* part;
-};
-
-__device__ __forceinline__ OuterJob pick_job(const OuterArgs& O, int j) {
-  OuterJob J = O.job[0];
-#pragma unroll
-  for (int t = 1; t < kNumProd; ++t)
-    if (j == t) J = O.job[t];
-  return J;
-}
-
-__global__ void __launch_bounds__(kOuterBlock) outer_mfma_kernel(OuterArgs O) {
-  const OuterJob J = pick_job(O, blockIdx.y);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lo = lane & 15, grp = lane >> 4;
-  const int npt = (J.P + 15) >> 4, nqt = (J.Q + 16) >> 4;
-  if (w >= npt) return;
-  const int64_t c0 = (int64_t)blockIdx.x * O.chunk;
-  const int64_t c1 = std::min<int64_t>(c0 + O.chunk, O.M);
-  f32x4 acc[kMaxPT][kMaxQT];
-#pragma unroll
-  for (int pt = 0; pt < kMaxPT; ++pt)
-#pragma unroll
-    for (int qt = 0; qt < kMaxQT; ++qt) acc[pt][qt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t a = c0; a < c1; a += 4) {
-    const int64_t ar = a + grp;
-    const bool av = ar < c1;
-    float xa[kMaxPT], yb[kMaxQT];
-#pragma unroll
-    for (int pt = 0; pt < kMaxPT; ++pt) {
-      const int p = 16 * (w + 4 * pt) + lo;
-      xa[pt] = (av && p < J.P) ? J.X[ar * J.P + p] : 0.0f;
-    }
-#pragma unroll
-    for (int qt = 0; qt < kMaxQT; ++qt) {
-      const int q = 16 * qt + lo;
-      yb[qt] = !av ? 0.0f : q < J.Q ? J.Y[ar * J.Q + q] : (q == J.Q ? 1.0f : 0.0f);
-    }
-#pragma unroll
-    for (int pt = 0; pt < kMaxPT; ++pt)
-      if (w + 4 * pt < npt)
-#pragma unroll
-        for (int qt = 0; qt < kMaxQT; ++qt)
-          if (qt < nqt) acc[pt][qt] = mma(xa[pt], yb[qt], acc[pt][qt]);
-  }
-  float* out = O.part + (int64_t)blockIdx.x * O.per + J.off;
-  const int q1 = J.Q + 1;
-#pragma unroll
-  for (int pt = 0; pt < kMaxPT; ++pt) {
-    if (w + 4 * pt >= npt) break;
-#pragma unroll
-    for (int qt = 0; qt < kMaxQT; ++qt) {
-      const int q = 16 * qt + lo;
-      if (qt >= nqt || q >= q1) continue;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int p = 16 * (w + 4 * pt) + 4 * grp + i;
-        if (p < J.P) out[(int64_t)p * q1 + q] = acc[pt][qt][i];
-      }
-    }
-  }
-}
+constexpr int kGroupRows = 32;   // block partials per first-level group
+constexpr int kSliceRows = 2048;  // blocks per backward launch (64 group rows)
 
 struct ReduceArgs {
   float* dW[kNumProd];
@@ -490,7 +538,8 @@ struct ReduceArgs {
   const float* part;
 };
 
-// Sums the chunks in a fixed order (four interleaved partial sums).
+// Sums the group rows in a fixed order (four interleaved partial sums) into
+// the weight and bias gradients.
 __global__ void __launch_bounds__(256) reduce_outer_kernel(ReduceArgs R) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= R.per) return;
@@ -525,36 +574,40 @@ __global__ void __launch_bounds__(256) reduce_outer_kernel(ReduceArgs R) {
   else db[row] = v;
 }
 
-size_t dec_lds_bytes(bool backward, int kw, int k) {
-  const size_t hp = 16 * (size_t)kw + 1, yp = 7 * (size_t)k + 1;
-  return (size_t)kRows * (kHP + (backward ? 2 : 1) * hp + yp) * sizeof(float);
+size_t dec_lds_bytes(int W, int k) {
+  const size_t hp = 16 * (size_t)((W + 15) / 16) + 1, yp = 7 * (size_t)k + 1;
+  return ((size_t)head_lds_floats(W, k) + kDecWaves * (kRows * (kHP + hp + yp) + 3 * kRows)) * sizeof(float);
 }
 
 template <int KW>
-void launch_kw(bool backward, const DecArgs& A, unsigned blocks, size_t lds, hipStream_t s) {
-  if (backward) hipLaunchKernelGGL(decode_backward_kernel<KW>, dim3(blocks), dim3(64), lds, s, A);
-  else hipLaunchKernelGGL(decode_forward_kernel<KW>, dim3(blocks), dim3(64), lds, s, A);
-}
-
-hipError_t launch_dec_any(bool backward, const DecArgs& A, hipStream_t s) {
-  const unsigned blocks = (unsigned)((A.m + kRows - 1) / kRows);
-  if (blocks == 0) return hipSuccess;
-  const int kw = (A.width + 15) / 16;
-  const size_t lds = dec_lds_bytes(backward, kw, A.k);
-  switch (kw) {
-    case 1: launch_kw<1>(backward, A, blocks, lds, s); break;
-    case 2: launch_kw<2>(backward, A, blocks, lds, s); break;
-    case 3: launch_kw<3>(backward, A, blocks, lds, s); break;
-    case 4: launch_kw<4>(backward, A, blocks, lds, s); break;
-    case 5: launch_kw<5>(backward, A, blocks, lds, s); break;
-    case 6: launch_kw<6>(backward, A, blocks, lds, s); break;
-    case 7: launch_kw<7>(backward, A, blocks, lds, s); break;
-    case 8: launch_kw<8>(backward, A, blocks, lds, s); break;
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_kw(bool backward, const DecArgs& A, unsigned blocks, size_t lds, hipStream_t s) {
+  const void* f = backward ? reinterpret_cast<const void*>(&decode_backward_kernel<KW>)
+                           : reinterpret_cast<const void*>(&decode_forward_kernel<KW>);
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (backward) hipLaunchKernelGGL(decode_backward_kernel<KW>, dim3(blocks), dim3(kDecThreads), lds, s, A);
+  else hipLaunchKernelGGL(decode_forward_kernel<KW>, dim3(blocks), dim3(kDecThreads), lds, s, A);
   return hipGetLastError();
 }
 
+// LDS per block: the staged parameters of one head and, per wavefront, its
+// input rows, hidden layer, head outputs and log scalings; at most about
+// 146 KB (width 128, k = 16).
+hipError_t launch_dec_any(bool backward, const DecArgs& A, hipStream_t s, unsigned blocks) {
+  if (blocks == 0) return hipSuccess;
+  const size_t lds = dec_lds_bytes(A.width, A.k);
+  switch ((A.width + 15) / 16) {
+    case 1: return launch_kw<1>(backward, A, blocks, lds, s);
+    case 2: return launch_kw<2>(backward, A, blocks, lds, s);
+    case 3: return launch_kw<3>(backward, A, blocks, lds, s);
+    case 4: return launch_kw<4>(backward, A, blocks, lds, s);
+    case 5: return launch_kw<5>(backward, A, blocks, lds, s);
+    case 6: return launch_kw<6>(backward, A, blocks, lds, s);
+    case 7: return launch_kw<7>(backward, A, blocks, lds, s);
+    case 8: return launch_kw<8>(backward, A, blocks, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 bool finite3(const float* c) { return std::isfinite(c[0]) && std::isfinite(c[1]) && std::isfinite(c[2]); }
 
@@ -606,7 +659,7 @@ int vpgs_decode_forward(vpgs_ctx* ctx, const vpgs_anchors* an, const vpgs_mlp* m
   A.means = out->means; A.log_scales = out->log_scales; A.quats = out->quats; A.opac = out->opacities;
   A.colors = out->colors;
   StageTimer t(ctx, ST_DEC_FWD, st);
-  HIP_TRY(launch_dec_any(false, A, st));
+  HIP_TRY(launch_dec_any(false, A, st, (unsigned)((an->m + kRows * kDecWaves - 1) / (kRows * kDecWaves))));
   return VPGS_OK;
 }
 
@@ -627,23 +680,18 @@ int vpgs_decode_backward(vpgs_ctx* ctx, const vpgs_anchors* an, const vpgs_mlp* 
   const int64_t M = an->m;
   const int k = an->k, width = mlp->width;
   const int outs[3] = {k, 3 * k, 7 * k};
-  // workspace: h, hidden x3, dpre x3, dy x3
-  const size_t ws_floats = (size_t)M * (kIn + 6 * (size_t)width + 11 * (size_t)k);
-  // chunks of at least 256 anchors, at most 512 chunks
-  const int64_t chunk = std::max<int64_t>(256, ((M + 511) / 512 + 15) / 16 * 16);
-  const int chunks = (int)std::max<int64_t>((M + chunk - 1) / chunk, 1);
-  OuterArgs O;
+  DecArgs A = make_args(an, mlp, cam_center);
+  A.g_means = up->means; A.g_ls = up->log_scales; A.g_quats = up->quats; A.g_opac = up->opacities;
+  A.g_colors = up->colors;
+  A.d_feat = d_feat; A.d_scale = d_scale; A.d_offsets = d_offsets;
   ReduceArgs R;
-  std::memset(&O, 0, sizeof(O));
   std::memset(&R, 0, sizeof(R));
   int64_t per = 0;
   for (int j = 0; j < kNumProd; ++j) {
     const int h = j / 2;
     // even j: dW2[h] = DY^T HID (+ db2); odd j: dW1[h] = DPRE^T H (+ db1)
     const int P = j % 2 == 0 ? outs[h] : width, Q = j % 2 == 0 ? width : kIn;
-    O.job[j].P = P;
-    O.job[j].Q = Q;
-    O.job[j].off = per;
+    A.part_off[j] = per;
     R.Q[j] = Q;
     R.off[j] = per;
     R.dW[j] = j % 2 == 0 ? dm->W2[h] : dm->W1[h];
@@ -651,43 +699,39 @@ int vpgs_decode_backward(vpgs_ctx* ctx, const vpgs_anchors* an, const vpgs_mlp* 
     per += (int64_t)P * (Q + 1);
   }
   R.off[kNumProd] = per;
-  if ((rc = ensure(ctx, ctx->dec_ws, ws_floats * 4)) || (rc = ensure(ctx, ctx->dec_partial, (size_t)chunks * per * 4)))
-    return rc;
-  DecArgs A = make_args(an, mlp, cam_center);
-  A.g_means = up->means; A.g_ls = up->log_scales; A.g_quats = up->quats; A.g_opac = up->opacities;
-  A.g_colors = up->colors;
-  A.d_feat = d_feat; A.d_scale = d_scale; A.d_offsets = d_offsets;
-  float* w = static_cast<float*>(ctx->dec_ws.p);
-  A.ws_h = w; w += (size_t)M * kIn;
-  for (int h = 0; h < 3; ++h) { A.ws_hid[h] = w; w += (size_t)M * width; }
-  for (int h = 0; h < 3; ++h) { A.ws_dpre[h] = w; w += (size_t)M * width; }
-  for (int h = 0; h < 3; ++h) { A.ws_dy[h] = w; w += (size_t)M * outs[h]; }
+  A.part_per = per;
   StageTimer t(ctx, ST_DEC_BWD, st);
   if (M == 0) {
     for (int j = 0; j < kNumProd; ++j) {
-      const int P = O.job[j].P, Q = O.job[j].Q;
-      HIP_TRY(launch_fill_f32(R.dW[j], 0.f, (size_t)P * Q, st));
-      HIP_TRY(launch_fill_f32(R.db[j], 0.f, (size_t)P, st));
+      const int64_t n = R.off[j + 1] - R.off[j];
+      HIP_TRY(launch_fill_f32(R.dW[j], 0.f, (size_t)(n / (R.Q[j] + 1) * R.Q[j]), st));
+      HIP_TRY(launch_fill_f32(R.db[j], 0.f, (size_t)(n / (R.Q[j] + 1)), st));
     }
     return VPGS_OK;
   }
-  HIP_TRY(launch_dec_any(true, A, st));
-  for (int h = 0; h < 3; ++h) {
-    O.job[2 * h].X = A.ws_dy[h];
-    O.job[2 * h].Y = A.ws_hid[h];
-    O.job[2 * h + 1].X = A.ws_dpre[h];
-    O.job[2 * h + 1].Y = A.ws_h;
+  // One partial row per block of the per-anchor kernel.  The blocks run in
+  // slices of at most kSliceRows; each slice's rows are summed in groups of
+  // kGroupRows into the group rows (added to the earlier slices' sums), and
+  // the group rows are summed last, all in a fixed order.
+  const int64_t rows = (M + kRows * kDecWaves - 1) / (kRows * kDecWaves);
+  const int slice = (int)std::min<int64_t>(rows, kSliceRows);
+  const int groups = (slice + kGroupRows - 1) / kGroupRows;
+  if ((rc = ensure(ctx, ctx->dec_partial, (size_t)(slice + groups) * per * 4))) return rc;
+  A.part = static_cast<float*>(ctx->dec_partial.p);
+  float* gsum = A.part + (int64_t)slice * per;
+  const unsigned eblocks = (unsigned)((per + 255) / 256);
+  for (int64_t b = 0; b < rows; b += slice) {
+    const int n = (int)std::min<int64_t>(slice, rows - b);
+    A.block0 = b;
+    HIP_TRY(launch_dec_any(true, A, st, (unsigned)n));
+    hipLaunchKernelGGL(sum_rows_kernel, dim3(eblocks, (n + kGroupRows - 1) / kGroupRows), dim3(256), 0, st, A.part,
+                       n, per, kGroupRows, b > 0 ? 1 : 0, gsum);
+    HIP_TRY(hipGetLastError());
   }
-  O.M = M;
-  O.chunk = chunk;
-  O.per = per;
-  O.part = static_cast<float*>(ctx->dec_partial.p);
-  hipLaunchKernelGGL(outer_mfma_kernel, dim3(chunks, kNumProd), dim3(kOuterBlock), 0, st, O);
-  HIP_TRY(hipGetLastError());
   R.per = per;
-  R.chunks = chunks;
-  R.part = O.part;
-  hipLaunchKernelGGL(reduce_outer_kernel, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, st, R);
+  R.chunks = groups;
+  R.part = gsum;
+  hipLaunchKernelGGL(reduce_outer_kernel, dim3(eblocks), dim3(256), 0, st, R);
   HIP_TRY(hipGetLastError());
   return VPGS_OK;
 }

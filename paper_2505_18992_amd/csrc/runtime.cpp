@@ -550,7 +550,6 @@ int vpgs_destroy(vpgs_ctx* ctx) {
   for (auto& p : ctx->pending) { ctx->ev_free.push_back(p.a); ctx->ev_free.push_back(p.b); }
   for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
   for (vpgs_saved* s : ctx->pool) destroy_saved(s);
-  free_buf(ctx->dec_ws);
   free_buf(ctx->dec_partial);
   free_buf(ctx->loss_ws);
   free_buf(ctx->loss_sums);

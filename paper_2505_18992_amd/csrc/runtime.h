@@ -48,7 +48,7 @@ struct vpgs_ctx {
   std::vector<vpgs_saved*> pool;
   void* h_pinned = nullptr;  // small pinned buffer for counter readback
   // decode workspace
-  vpgs::DevBuf dec_ws, dec_partial;
+  vpgs::DevBuf dec_partial;
   // mapping-loss workspace: SSIM partials of one view, block sums
   vpgs::DevBuf loss_ws, loss_sums;
   // expansion sampling: candidate masks not given by the caller, block counts and offsets
