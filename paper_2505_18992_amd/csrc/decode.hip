@@ -87,7 +87,25 @@ struct DecArgs {
 __device__ __forceinline__ float sigmoidf_(float y) { return 1.0f / (1.0f + expf(-y)); }
 __device__ __forceinline__ float log_sigmoidf_(float y) { return -(fmaxf(-y, 0.0f) + log1pf(expf(-fabsf(y)))); }
 
+// Block barrier for data in LDS only.  The kernels' global stores are never
+// read back within a launch, so unlike __syncthreads() it does not wait for
+// them to complete.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __host__ __device__ constexpr int head_outs(int h, int k) { return (h == 0 ? 1 : h == 1 ? 3 : 7) * k; }
+__host__ __device__ constexpr int pad16(int n) { return (n + 15) & ~15; }
+// LDS pitch of a wavefront's head outputs: the widest head padded to whole
+// tiles, plus one
+__host__ __device__ constexpr int out_pitch(int k) { return pad16(7 * k) + 1; }
+
+// floor(e / d) for 0 <= e < 2^20 and d <= 48 given inv = 1 / d in FP32:
+// (e + 1/2) / d lies at least 1 / (2 d) from an integer and the product errs
+// by under 1e-5, so the truncation is exact
+__device__ __forceinline__ int quot(int e, float inv) { return (int)(((float)e + 0.5f) * inv); }
 
 // Runs store(e, load(e)) over the elements e < n of a wavefront, U per
 // lane at a time with the U loads issued before any store (the outputs
@@ -136,9 +154,11 @@ __device__ __forceinline__ void load_inputs(const DecArgs& A, int64_t a0, int nv
   if (lane < 3 * kRows) logl[lane] = lane < 3 * nv ? logf(A.scale[a0 * 3 + lane]) : 0.0f;
 }
 
-// The parameters of head h in LDS, shared by the block's wavefronts: W1 as
-// [width][kW1P], W2 as [outs][width + 1], then b1 and b2.  Synchronises
-// before (the previous head's may still be in use) and after.
+// The parameters of head h in LDS, shared by the block's wavefronts, padded
+// with zeros to whole tiles (so the tile loops need no bounds tests): W1 as
+// [wp][kW1P], W2 as [pad16(outs)][wp + 1], then b1 [wp] and b2 [pad16(outs)],
+// wp = pad16(width).  Synchronises before (the previous head's may still be in
+// use) and after.
 struct HeadLds {
   float* w1;
   float* w2;
@@ -147,48 +167,51 @@ struct HeadLds {
 };
 
 __device__ __forceinline__ HeadLds head_lds(float* lds, int W, int k) {
+  const int wp = pad16(W);
   HeadLds p;
   p.w1 = lds;
-  p.w2 = p.w1 + W * kW1P;
-  p.b1 = p.w2 + 7 * k * (W + 1);
-  p.b2 = p.b1 + W;
+  p.w2 = p.w1 + wp * kW1P;
+  p.b1 = p.w2 + pad16(7 * k) * (wp + 1);
+  p.b2 = p.b1 + wp;
   return p;
 }
 
-__host__ __device__ constexpr int head_lds_floats(int W, int k) { return W * kW1P + 7 * k * (W + 1) + W + 7 * k; }
+__host__ __device__ constexpr int head_lds_floats(int W, int k) {
+  return pad16(W) * kW1P + pad16(7 * k) * (pad16(W) + 1) + pad16(W) + pad16(7 * k);
+}
 
 __device__ __forceinline__ void stage_weights(const DecArgs& A, int h, const HeadLds& p) {
   const int W = A.width, outs = head_outs(h, A.k);
   const float* __restrict__ W1 = A.W1[h];
   const float* __restrict__ W2 = A.W2[h];
-  __syncthreads();
-  for (int e = threadIdx.x; e < W * kIn; e += kDecThreads) {
+  const int wp = pad16(W), op = pad16(outs);
+  lds_barrier();
+  for (int e = threadIdx.x; e < wp * kIn; e += kDecThreads) {
     const int j = e / kIn;
-    p.w1[j * kW1P + e - j * kIn] = W1[e];
+    p.w1[j * kW1P + e - j * kIn] = e < W * kIn ? W1[e] : 0.0f;
   }
-  for (int o = threadIdx.x / 64; o < outs; o += kDecWaves)
-    for (int j = threadIdx.x & 63; j < W; j += 64) p.w2[o * (W + 1) + j] = W2[(size_t)o * W + j];
-  for (int j = threadIdx.x; j < W; j += kDecThreads) p.b1[j] = A.b1[h][j];
-  for (int o = threadIdx.x; o < outs; o += kDecThreads) p.b2[o] = A.b2[h][o];
-  __syncthreads();
+  for (int o = threadIdx.x / 64; o < op; o += kDecWaves)
+    for (int j = threadIdx.x & 63; j < wp; j += 64) p.w2[o * (wp + 1) + j] = (o < outs && j < W) ? W2[o * W + j] : 0.0f;
+  for (int j = threadIdx.x; j < wp; j += kDecThreads) p.b1[j] = j < W ? A.b1[h][j] : 0.0f;
+  for (int o = threadIdx.x; o < op; o += kDecThreads) p.b2[o] = o < outs ? A.b2[h][o] : 0.0f;
+  lds_barrier();
 }
 
 // hid[r][j] = relu(b1[j] + sum_i W1[j][i] h[r][i]) for the KW column tiles
 // of the hidden layer (columns past the width come out zero).  ha holds the
 // A operand: lane group g covers inputs 9g .. 9g + 8.
 template <int KW>
-__device__ __forceinline__ void hidden_tiles(const float* w1s, const float* b1, int W, const float ha[9],
-                                             float* hid, int lane) {
+__device__ __forceinline__ void hidden_tiles(const float* w1s, const float* b1, const float ha[9], float* hid,
+                                             int lane) {
   constexpr int HP = 16 * KW + 1;
   const int lo = lane & 15, grp = lane >> 4;
 #pragma unroll
   for (int ct = 0; ct < KW; ++ct) {
     const int j = 16 * ct + lo;
-    const bool jv = j < W;
-    const float bias = jv ? b1[j] : 0.0f;
+    const float bias = b1[j];
     float b[9];
 #pragma unroll
-    for (int ks = 0; ks < 9; ++ks) b[ks] = jv ? w1s[j * kW1P + 9 * grp + ks] : 0.0f;
+    for (int ks = 0; ks < 9; ++ks) b[ks] = w1s[j * kW1P + 9 * grp + ks];
     f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < 9; ++ks) c = mma(ha[ks], b[ks], c);
@@ -197,11 +220,12 @@ __device__ __forceinline__ void hidden_tiles(const float* w1s, const float* b1, 
   }
 }
 
-// y[r][o] = b2[o] + sum_j W2[o][j] hid[r][j] for o < outs, 16 outputs per
-// tile; lane group g covers hidden units g KS .. g KS + KS - 1.
+// y[r][o] = b2[o] + sum_j W2[o][j] hid[r][j] for the pad16(outs) outputs
+// (the padding comes out zero), 16 per tile; lane group g covers hidden units
+// g KS .. g KS + KS - 1.
 template <int KW>
-__device__ __forceinline__ void out_tiles(const float* w2s, const float* b2, int W, int outs,
-                                          const float* hid, float* ys, int yp, int lane) {
+__device__ __forceinline__ void out_tiles(const float* w2s, const float* b2, int outs, const float* hid, float* ys,
+                                          int yp, int lane) {
   constexpr int HP = 16 * KW + 1, KS = 4 * KW;
   const int lo = lane & 15, grp = lane >> 4;
   float ha[KS];
@@ -209,21 +233,15 @@ __device__ __forceinline__ void out_tiles(const float* w2s, const float* b2, int
   for (int ks = 0; ks < KS; ++ks) ha[ks] = hid[lo * HP + KS * grp + ks];
   for (int o0 = 0; o0 < outs; o0 += 16) {
     const int o = o0 + lo;
-    const bool ov = o < outs;
-    const float bias = ov ? b2[o] : 0.0f;
+    const float bias = b2[o];
     float b[KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int j = KS * grp + ks;
-      b[ks] = (ov && j < W) ? w2s[o * (W + 1) + j] : 0.0f;
-    }
+    for (int ks = 0; ks < KS; ++ks) b[ks] = w2s[o * HP + KS * grp + ks];
     f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) c = mma(ha[ks], b[ks], c);
-    if (ov) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) ys[(4 * grp + i) * yp + o] = c[i] + bias;
-    }
+    for (int i = 0; i < 4; ++i) ys[(4 * grp + i) * yp + o] = c[i] + bias;
   }
 }
 
@@ -236,7 +254,8 @@ __global__ void __launch_bounds__(kDecThreads) decode_forward_kernel(DecArgs A) 
   extern __shared__ float lds[];
   constexpr int HP = 16 * KW + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int k = A.k, W = A.width, yp = 7 * k + 1;
+  const int k = A.k, W = A.width, yp = out_pitch(k);
+  const float inv_k = 1.0f / k, inv_k3 = 1.0f / (3 * k);
   const HeadLds P = head_lds(lds, W, k);
   float* Hs = lds + head_lds_floats(W, k) + wave * (kRows * (kHP + HP + yp) + 3 * kRows);
   float* hid = Hs + kRows * kHP;
@@ -249,35 +268,35 @@ __global__ void __launch_bounds__(kDecThreads) decode_forward_kernel(DecArgs A) 
   blocked<8>(  // eq. 1
       nv * k3, lane,
       [&](int e) {
-        const int64_t a = a0 + e / k3;
+        const int64_t a = a0 + quot(e, inv_k3);
         const int c = e % 3;
         return MeanIn{A.offsets[a0 * k3 + e], A.xyz[3 * a + c], A.scale[3 * a + c]};
       },
       [&](int e, MeanIn v) { A.means[a0 * k3 + e] = v.x + v.off * v.l; });
-  __syncthreads();
+  lds_barrier();
   float ha[9];
 #pragma unroll
   for (int ks = 0; ks < 9; ++ks) ha[ks] = Hs[(lane & 15) * kHP + 9 * (lane >> 4) + ks];
   for (int h = 0; h < 3; ++h) {
     const int outs = head_outs(h, k);
     stage_weights(A, h, P);
-    hidden_tiles<KW>(P.w1, P.b1, W, ha, hid, lane);
-    __syncthreads();
-    out_tiles<KW>(P.w2, P.b2, W, outs, hid, ys, yp, lane);
-    __syncthreads();
+    hidden_tiles<KW>(P.w1, P.b1, ha, hid, lane);
+    lds_barrier();
+    out_tiles<KW>(P.w2, P.b2, outs, hid, ys, yp, lane);
+    lds_barrier();
     if (h == 0) {
       for (int e = lane; e < nv * k; e += 64) {
-        const int r = e / k;
+        const int r = quot(e, inv_k);
         A.opac[a0 * k + e] = tanhf(ys[r * yp + e - r * k]);
       }
     } else if (h == 1) {
       for (int e = lane; e < nv * k3; e += 64) {  // eq. 4
-        const int r = e / k3;
+        const int r = quot(e, inv_k3);
         A.colors[a0 * k3 + e] = sigmoidf_(ys[r * yp + e - r * k3]);
       }
     } else {
       for (int e = lane; e < nv * k; e += 64) {
-        const int r = e / k;
+        const int r = quot(e, inv_k);
         const float* y = ys + r * yp + 7 * (e - r * k);
         const int64_t g = a0 * k + e;
 #pragma unroll
@@ -293,10 +312,11 @@ __global__ void __launch_bounds__(kDecThreads) decode_forward_kernel(DecArgs A) 
 
 // dhid[r][j] = sum_o dy[r][o] W2[o][j]; dpre = dhid where the hidden unit is
 // active, written over the hidden layer (each lane reads and writes only its
-// own elements).  Lane group g covers outputs o0 + 4g .. o0 + 4g + 3.
+// own elements).  Lane group g covers outputs o0 + 4g .. o0 + 4g + 3; the
+// padded outputs hold zero gradients against zero weights.
 template <int KW>
-__device__ __forceinline__ void hid_grad_tiles(const float* w2s, int W, int outs, const float* dys, int yp,
-                                               float* hid, int lane) {
+__device__ __forceinline__ void hid_grad_tiles(const float* w2s, int outs, const float* dys, int yp, float* hid,
+                                               int lane) {
   constexpr int HP = 16 * KW + 1;
   const int lo = lane & 15, grp = lane >> 4;
   f32x4 acc[KW];
@@ -305,18 +325,12 @@ __device__ __forceinline__ void hid_grad_tiles(const float* w2s, int W, int outs
   for (int o0 = 0; o0 < outs; o0 += 16) {
     float a[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int o = o0 + 4 * grp + s;
-      a[s] = o < outs ? dys[lo * yp + o] : 0.0f;
-    }
+    for (int s = 0; s < 4; ++s) a[s] = dys[lo * yp + o0 + 4 * grp + s];
 #pragma unroll
     for (int ct = 0; ct < KW; ++ct) {
       const int j = 16 * ct + lo;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int o = o0 + 4 * grp + s;
-        acc[ct] = mma(a[s], (o < outs && j < W) ? w2s[o * (W + 1) + j] : 0.0f, acc[ct]);
-      }
+      for (int s = 0; s < 4; ++s) acc[ct] = mma(a[s], w2s[(o0 + 4 * grp + s) * HP + j], acc[ct]);
     }
   }
 #pragma unroll
@@ -333,7 +347,7 @@ __device__ __forceinline__ void hid_grad_tiles(const float* w2s, int W, int outs
 // dh[r][c] += sum_j dpre[r][j] W1[j][c] for the 32 feature inputs (the
 // direction and distance inputs have no parameters upstream).
 template <int KW>
-__device__ __forceinline__ void input_grad_tiles(const float* w1s, int W, const float* dpre, f32x4 dh[2], int lane) {
+__device__ __forceinline__ void input_grad_tiles(const float* w1s, const float* dpre, f32x4 dh[2], int lane) {
   constexpr int HP = 16 * KW + 1, KS = 4 * KW;
   const int lo = lane & 15, grp = lane >> 4;
   float a[KS];
@@ -345,7 +359,7 @@ __device__ __forceinline__ void input_grad_tiles(const float* w1s, int W, const 
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int j = KS * grp + ks;
-      dh[ct] = mma(a[ks], j < W ? w1s[j * kW1P + c] : 0.0f, dh[ct]);
+      dh[ct] = mma(a[ks], w1s[j * kW1P + c], dh[ct]);
     }
   }
 }
@@ -354,8 +368,8 @@ __device__ __forceinline__ void input_grad_tiles(const float* w1s, int W, const 
 // is Y with a trailing all-ones column (q = Q gives the bias gradient).  Row
 // a of X and Y lives in the LDS region of wavefront a / 16, at row a % 16;
 // anchors past nvb (the block's valid count) contribute nothing.  Tiles of
-// 16x16 go round-robin over the wavefronts; each sums the 64 anchors in 16
-// MFMA steps (lane group g takes anchor 4s + g of step s).
+// 16x16 go round-robin over the wavefronts; each sums the block's anchors in
+// 4 MFMA steps per wavefront (lane group g takes anchor 4s + g of step s).
 __device__ __forceinline__ void wgrad_tiles(const float* region0, int region_floats, int xoff, int xp, int P,
                                             int yoff, int ypitch, int Q, int nvb, float* __restrict__ out, int wave,
                                             int lane) {
@@ -366,7 +380,7 @@ __device__ __forceinline__ void wgrad_tiles(const float* region0, int region_flo
     const int p = 16 * pt + lo, q = 16 * qt + lo;
     f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
+    for (int s = 0; s < 4 * kDecWaves; ++s) {
       const int a = 4 * s + grp;
       const float* reg = region0 + (a >> 4) * region_floats;
       const int r = a & 15;
@@ -393,7 +407,8 @@ __global__ void __launch_bounds__(kDecThreads) decode_backward_kernel(DecArgs A)
   extern __shared__ float lds[];
   constexpr int HP = 16 * KW + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lo = lane & 15, grp = lane >> 4;
-  const int k = A.k, W = A.width, yp = 7 * k + 1;
+  const int k = A.k, W = A.width, yp = out_pitch(k);
+  const float inv_k = 1.0f / k, inv_k3 = 1.0f / (3 * k);
   const HeadLds P = head_lds(lds, W, k);
   float* region0 = lds + head_lds_floats(W, k);
   const int region_floats = kRows * (kHP + HP + yp) + 3 * kRows;
@@ -411,7 +426,7 @@ __global__ void __launch_bounds__(kDecThreads) decode_backward_kernel(DecArgs A)
   const int k3 = 3 * k;
   // eq. 1: mean = anchor + offset * l
   blocked<8>(
-      nv * k3, lane, [&](int e) { return float2{A.g_means[a0 * k3 + e], A.scale[3 * (a0 + e / k3) + e % 3]}; },
+      nv * k3, lane, [&](int e) { return float2{A.g_means[a0 * k3 + e], A.scale[3 * (a0 + quot(e, inv_k3)) + e % 3]}; },
       [&](int e, float2 v) { A.d_offsets[a0 * k3 + e] = v.x * v.y; });
   // scaling: through the means and through eq. 5's log l
   if (lane < 3 * nv) {
@@ -423,7 +438,7 @@ __global__ void __launch_bounds__(kDecThreads) decode_backward_kernel(DecArgs A)
     for (int m = 0; m < k; ++m) s += A.g_ls[3 * (a * k + m) + c] / l;
     A.d_scale[3 * a + c] = s;
   }
-  __syncthreads();
+  lds_barrier();
   float ha[9];
 #pragma unroll
   for (int ks = 0; ks < 9; ++ks) ha[ks] = Hs[lo * kHP + 9 * grp + ks];
@@ -431,16 +446,16 @@ __global__ void __launch_bounds__(kDecThreads) decode_backward_kernel(DecArgs A)
   for (int h = 0; h < 3; ++h) {
     const int outs = head_outs(h, k);
     stage_weights(A, h, P);
-    hidden_tiles<KW>(P.w1, P.b1, W, ha, hid, lane);
-    __syncthreads();
-    out_tiles<KW>(P.w2, P.b2, W, outs, hid, ys, yp, lane);
-    __syncthreads();
+    hidden_tiles<KW>(P.w1, P.b1, ha, hid, lane);
+    lds_barrier();
+    out_tiles<KW>(P.w2, P.b2, outs, hid, ys, yp, lane);
+    lds_barrier();
     // gradient at the head outputs, in place of the outputs
     if (h == 0) {  // tanh
       blocked(
           nv * k, lane, [&](int e) { return A.g_opac[a0 * k + e]; },
           [&](int e, float go) {
-            const int r = e / k;
+            const int r = quot(e, inv_k);
             float* y = ys + r * yp + e - r * k;
             const float t = tanhf(*y);
             *y = go * (1.0f - t * t);
@@ -449,7 +464,7 @@ __global__ void __launch_bounds__(kDecThreads) decode_backward_kernel(DecArgs A)
       blocked<8>(
           nv * k3, lane, [&](int e) { return A.g_colors[a0 * k3 + e]; },
           [&](int e, float gc) {
-            const int r = e / k3;
+            const int r = quot(e, inv_k3);
             float* y = ys + r * yp + e - r * k3;
             const float s = sigmoidf_(*y);
             *y = gc * s * (1.0f - s);
@@ -463,7 +478,7 @@ __global__ void __launch_bounds__(kDecThreads) decode_backward_kernel(DecArgs A)
                                {A.g_quats[4 * g], A.g_quats[4 * g + 1], A.g_quats[4 * g + 2], A.g_quats[4 * g + 3]}};
           },
           [&](int e, const ScaleGradIn& v) {
-            const int r = e / k;
+            const int r = quot(e, inv_k);
             float* y = ys + r * yp + 7 * (e - r * k);
             float dy[7];
 #pragma unroll
@@ -485,13 +500,13 @@ __global__ void __launch_bounds__(kDecThreads) decode_backward_kernel(DecArgs A)
             for (int j = 0; j < 7; ++j) y[j] = dy[j];
           });
     }
-    __syncthreads();
+    lds_barrier();
     // dW2 = DY^T HID, db2 = column sums of DY
     wgrad_tiles(region0, region_floats, ys_off, yp, outs, hid_off, HP, W, nvb, part + A.part_off[2 * h], wave, lane);
-    __syncthreads();
-    hid_grad_tiles<KW>(P.w2, W, outs, ys, yp, hid, lane);
-    __syncthreads();
-    input_grad_tiles<KW>(P.w1, W, hid, dh, lane);
+    lds_barrier();
+    hid_grad_tiles<KW>(P.w2, outs, ys, yp, hid, lane);
+    lds_barrier();
+    input_grad_tiles<KW>(P.w1, hid, dh, lane);
     // dW1 = DPRE^T H, db1 = column sums of DPRE
     wgrad_tiles(region0, region_floats, hid_off, HP, W, 0, kHP, kIn, nvb, part + A.part_off[2 * h + 1], wave, lane);
   }
@@ -575,7 +590,7 @@ __global__ void __launch_bounds__(256) reduce_outer_kernel(ReduceArgs R) {
 }
 
 size_t dec_lds_bytes(int W, int k) {
-  const size_t hp = 16 * (size_t)((W + 15) / 16) + 1, yp = 7 * (size_t)k + 1;
+  const size_t hp = (size_t)pad16(W) + 1, yp = (size_t)out_pitch(k);
   return ((size_t)head_lds_floats(W, k) + kDecWaves * (kRows * (kHP + hp + yp) + 3 * kRows)) * sizeof(float);
 }
 
