@@ -84,8 +84,21 @@ struct DecArgs {
   int64_t part_off[6];
 };
 
-__device__ __forceinline__ float sigmoidf_(float y) { return 1.0f / (1.0f + expf(-y)); }
-__device__ __forceinline__ float log_sigmoidf_(float y) { return -(fmaxf(-y, 0.0f) + log1pf(expf(-fabsf(y)))); }
+// Activations on the hardware exp2, log2 and reciprocal (each about 1 ulp;
+// rounding x log2 e adds about 1e-7 |x| relative error to e^x).
+constexpr float kLog2e = 1.44269504088896341f;
+constexpr float kLn2 = 0.693147180559945309f;
+__device__ __forceinline__ float exp_hw(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
+__device__ __forceinline__ float sigmoidf_(float y) { return __builtin_amdgcn_rcpf(1.0f + exp_hw(-y)); }
+// log sigmoid(y) = -(max(-y, 0) + log(1 + e^-|y|))
+__device__ __forceinline__ float log_sigmoidf_(float y) {
+  return -(fmaxf(-y, 0.0f) + __builtin_amdgcn_logf(1.0f + exp_hw(-fabsf(y))) * kLn2);
+}
+// tanh(y) = sign(y) (1 - e) / (1 + e) with e = e^(-2|y|)
+__device__ __forceinline__ float tanh_hw(float y) {
+  const float e = exp_hw(-2.0f * fabsf(y));
+  return copysignf((1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e), y);
+}
 
 // Block barrier for data in LDS only.  The kernels' global stores are never
 // read back within a launch, so unlike __syncthreads() it does not wait for
@@ -287,7 +300,7 @@ __global__ void __launch_bounds__(kDecThreads) decode_forward_kernel(DecArgs A) 
     if (h == 0) {
       for (int e = lane; e < nv * k; e += 64) {
         const int r = quot(e, inv_k);
-        A.opac[a0 * k + e] = tanhf(ys[r * yp + e - r * k]);
+        A.opac[a0 * k + e] = tanh_hw(ys[r * yp + e - r * k]);
       }
     } else if (h == 1) {
       for (int e = lane; e < nv * k3; e += 64) {  // eq. 4
@@ -367,26 +380,38 @@ __device__ __forceinline__ void input_grad_tiles(const float* w1s, const float* 
 // part[p][q] += sum over the block's anchors a of X[a][p] Y'[a][q], where Y'
 // is Y with a trailing all-ones column (q = Q gives the bias gradient).  Row
 // a of X and Y lives in the LDS region of wavefront a / 16, at row a % 16;
-// anchors past nvb (the block's valid count) contribute nothing.  Tiles of
-// 16x16 go round-robin over the wavefronts; each sums the block's anchors in
-// 4 MFMA steps per wavefront (lane group g takes anchor 4s + g of step s).
+// anchors past nvb (the block's valid count) contribute nothing.  The 16x16
+// tiles, in row-major order, are split into contiguous runs, one per
+// wavefront, which keeps its A operand (16 rows of X) in registers while the
+// run stays in one tile row; a tile sums the block's anchors in 4 MFMA steps
+// per wavefront (lane group g takes anchor 4s + g of step s).
 __device__ __forceinline__ void wgrad_tiles(const float* region0, int region_floats, int xoff, int xp, int P,
                                             int yoff, int ypitch, int Q, int nvb, float* __restrict__ out, int wave,
                                             int lane) {
   const int lo = lane & 15, grp = lane >> 4;
   const int nqt = (Q + 16) >> 4, nt = ((P + 15) >> 4) * nqt;
-  for (int t = wave; t < nt; t += kDecWaves) {
+  const int t1 = (wave + 1) * nt / kDecWaves;
+  int row = -1;
+  float x[4 * kDecWaves];
+  for (int t = wave * nt / kDecWaves; t < t1; ++t) {
     const int pt = t / nqt, qt = t - pt * nqt;
     const int p = 16 * pt + lo, q = 16 * qt + lo;
+    if (pt != row) {
+      row = pt;
+#pragma unroll
+      for (int s = 0; s < 4 * kDecWaves; ++s) {
+        const int a = 4 * s + grp;
+        x[s] = (a < nvb && p < P) ? region0[(a >> 4) * region_floats + xoff + (a & 15) * xp + p] : 0.0f;
+      }
+    }
+    const bool qv = q < Q;
+    const float one = q == Q ? 1.0f : 0.0f;
     f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < 4 * kDecWaves; ++s) {
       const int a = 4 * s + grp;
-      const float* reg = region0 + (a >> 4) * region_floats;
-      const int r = a & 15;
-      const float x = (a < nvb && p < P) ? reg[xoff + r * xp + p] : 0.0f;
-      const float y = q < Q ? reg[yoff + r * ypitch + q] : (q == Q ? 1.0f : 0.0f);
-      c = mma(x, y, c);
+      const float y = qv ? region0[(a >> 4) * region_floats + yoff + (a & 15) * ypitch + q] : one;
+      c = mma(x[s], y, c);
     }
     if (q <= Q) {
 #pragma unroll
@@ -457,7 +482,7 @@ __global__ void __launch_bounds__(kDecThreads) decode_backward_kernel(DecArgs A)
           [&](int e, float go) {
             const int r = quot(e, inv_k);
             float* y = ys + r * yp + e - r * k;
-            const float t = tanhf(*y);
+            const float t = tanh_hw(*y);
             *y = go * (1.0f - t * t);
           });
     } else if (h == 1) {  // sigmoid (eq. 4)
