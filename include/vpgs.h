@@ -308,7 +308,12 @@ int vpgs_decode_forward(vpgs_ctx* ctx, const vpgs_anchors* anchors, const vpgs_m
 
 /* Gradients of sum(upstream . decoded) with respect to feat, scale, offsets
  * and every weight and bias (all written in full; the camera is constant).
- * `upstream` uses the vpgs_gauss_grads layout as input. */
+ * `upstream` uses the vpgs_gauss_grads layout as input.  The weight gradients
+ * are sums over anchors taken in a fixed order, so repeated calls agree bit
+ * for bit; their partial sums live in a context-owned device buffer of up to
+ * 2112 rows of sum_h out_h (width + 1) + 3 width 37 floats (one row per 64
+ * anchors, 57 KB at width 64 and k = 10), grown on demand (VPGS_ENOMEM if it
+ * cannot be). */
 int vpgs_decode_backward(vpgs_ctx* ctx, const vpgs_anchors* anchors, const vpgs_mlp* mlp,
                          const float* cam_center, const vpgs_gauss_grads* upstream, float* d_feat,
                          float* d_scale, float* d_offsets, const vpgs_mlp_grads* d_mlp, void* stream);
