@@ -574,7 +574,7 @@ struct ReduceArgs {
   int Q[kNumProd];
   int64_t off[kNumProd + 1];
   int64_t per;
-  int chunks;
+  int rows;  // group rows to sum
   const float* part;
 };
 
@@ -601,11 +601,11 @@ __global__ void __launch_bounds__(256) reduce_outer_kernel(ReduceArgs R) {
   float s[4] = {0.f, 0.f, 0.f, 0.f};
   const float* p = R.part + e;
   int c = 0;
-  for (; c + 4 <= R.chunks; c += 4) {
+  for (; c + 4 <= R.rows; c += 4) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) s[u] += p[(int64_t)(c + u) * R.per];
   }
-  for (; c < R.chunks; ++c) s[0] += p[(int64_t)c * R.per];
+  for (; c < R.rows; ++c) s[0] += p[(int64_t)c * R.per];
   const float v = (s[0] + s[1]) + (s[2] + s[3]);
   const int64_t loc = e - off;
   const int64_t row = loc / (Q + 1);
@@ -769,7 +769,7 @@ int vpgs_decode_backward(vpgs_ctx* ctx, const vpgs_anchors* an, const vpgs_mlp* 
     HIP_TRY(hipGetLastError());
   }
   R.per = per;
-  R.chunks = groups;
+  R.rows = groups;
   R.part = gsum;
   hipLaunchKernelGGL(reduce_outer_kernel, dim3(eblocks), dim3(256), 0, st, R);
   HIP_TRY(hipGetLastError());
