@@ -114,20 +114,28 @@ __global__ void __launch_bounds__(kLossBlock) ssim_stats_kernel(LossBatch batch)
   __syncthreads();
   if (threadIdx.x < kHaloH * (kTileW / kHRun)) {  // kHRun adjacent outputs per thread
     const int r = threadIdx.x / (kTileW / kHRun), j0 = (threadIdx.x % (kTileW / kHRun)) * kHRun;
-    float xv[kHRun + 2 * kRad], yv[kHRun + 2 * kRad];
+    // the run's samples and their products, each formed once (not once per tap)
+    float xv[kHRun + 2 * kRad], yv[kHRun + 2 * kRad], xx[kHRun + 2 * kRad], yy[kHRun + 2 * kRad],
+        xy[kHRun + 2 * kRad];
 #pragma unroll
-    for (int t = 0; t < kHRun + 2 * kRad; ++t) { xv[t] = sx[r][j0 + t]; yv[t] = sy[r][j0 + t]; }
+    for (int t = 0; t < kHRun + 2 * kRad; ++t) {
+      xv[t] = sx[r][j0 + t];
+      yv[t] = sy[r][j0 + t];
+      xx[t] = xv[t] * xv[t];
+      yy[t] = yv[t] * yv[t];
+      xy[t] = xv[t] * yv[t];
+    }
 #pragma unroll
     for (int o = 0; o < kHRun; ++o) {
       float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
 #pragma unroll
       for (int t = 0; t < kTaps; ++t) {
-        const float g = kGauss[t], x = xv[o + t], y = yv[o + t];
-        s0 = fmaf(g, x, s0);
-        s1 = fmaf(g, y, s1);
-        s2 = fmaf(g, x * x, s2);
-        s3 = fmaf(g, y * y, s3);
-        s4 = fmaf(g, x * y, s4);
+        const float g = kGauss[t];
+        s0 = fmaf(g, xv[o + t], s0);
+        s1 = fmaf(g, yv[o + t], s1);
+        s2 = fmaf(g, xx[o + t], s2);
+        s3 = fmaf(g, yy[o + t], s3);
+        s4 = fmaf(g, xy[o + t], s4);
       }
       hs[0][r][j0 + o] = s0; hs[1][r][j0 + o] = s1; hs[2][r][j0 + o] = s2; hs[3][r][j0 + o] = s3;
       hs[4][r][j0 + o] = s4;
