@@ -46,7 +46,7 @@ def _untie(up, a, d, cam):
     return out, int(flags.sum())
 
 
-@pytest.mark.parametrize("m,k,width", [(3000, 10, 64), (1000, 10, 32), (777, 3, 50), (1, 16, 128)])
+@pytest.mark.parametrize("m,k,width", [(3000, 10, 64), (1000, 10, 32), (777, 3, 50), (1, 16, 128), (500, 1, 8)])
 def test_decode_forward_parity(m, k, width):
     from paper_2505_18992_amd import decode_forward
     print(f"case decode forward m={m} k={k} width={width}", flush=True)
@@ -62,7 +62,8 @@ def test_decode_forward_parity(m, k, width):
 
 # 140 000 anchors: more blocks of 64 than one launch of the backward takes,
 # so the weight gradients add the partial sums of several launches
-@pytest.mark.parametrize("m,k,width", [(3000, 10, 64), (1000, 10, 32), (777, 3, 50), (1, 16, 128), (140_000, 10, 64)])
+@pytest.mark.parametrize("m,k,width", [(3000, 10, 64), (1000, 10, 32), (777, 3, 50), (1, 16, 128), (500, 1, 8),
+                                       (140_000, 10, 64)])
 def test_decode_backward_parity(m, k, width):
     from paper_2505_18992_amd import decode_backward
     print(f"case decode backward m={m} k={k} width={width}", flush=True)
@@ -87,6 +88,23 @@ def test_decode_backward_parity(m, k, width):
         assert nrm <= 1e-5, (name, nrm)
         # per element against the tensor's largest magnitude (sums of many signed terms)
         assert np.max(np.abs(g - e)) <= 1e-4 * np.abs(e).max() + 1e-7, (name, np.max(np.abs(g - e)))
+
+
+def test_decode_empty():
+    """No anchors: nothing is decoded and every weight and bias gradient comes
+    back zero."""
+    from paper_2505_18992_amd import decode_backward, decode_forward
+    print("case decode empty", flush=True)
+    a, d, cam = _case(11, 4, 10, 64)
+    anchors, mlp = _dev_inputs(a, d)
+    empty = tuple(t[:0] for t in anchors)
+    outs = decode_forward(empty, mlp, cam)
+    assert all(o.shape[0] == 0 for o in outs)
+    d_feat, d_scale, d_off, grads = decode_backward(empty, mlp, cam, [torch.zeros_like(o) for o in outs])
+    assert d_feat.shape[0] == 0 and d_scale.shape[0] == 0 and d_off.shape[0] == 0
+    for lst in grads:
+        for g in lst:
+            assert g.numel() > 0 and int(torch.count_nonzero(g)) == 0
 
 
 def test_decode_autograd_matches_backward():
