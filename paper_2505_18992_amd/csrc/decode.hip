@@ -250,9 +250,14 @@ __device__ __forceinline__ void out_tiles(const float* w2s, const float* b2, int
     float b[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) b[ks] = w2s[o * HP + KS * grp + ks];
-    f32x4 c = {0.f, 0.f, 0.f, 0.f};
+    // two interleaved accumulators halve the dependent MFMA chain
+    f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) c = mma(ha[ks], b[ks], c);
+    for (int ks = 0; ks < KS; ks += 2) {
+      c0 = mma(ha[ks], b[ks], c0);
+      c1 = mma(ha[ks + 1], b[ks + 1], c1);
+    }
+    const f32x4 c = c0 + c1;
 #pragma unroll
     for (int i = 0; i < 4; ++i) ys[(4 * grp + i) * yp + o] = c[i] + bias;
   }
@@ -406,13 +411,18 @@ __device__ __forceinline__ void wgrad_tiles(const float* region0, int region_flo
     }
     const bool qv = q < Q;
     const float one = q == Q ? 1.0f : 0.0f;
-    f32x4 c = {0.f, 0.f, 0.f, 0.f};
+    // two interleaved accumulators (even and odd steps) halve the dependent
+    // MFMA chain
+    f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < 4 * kDecWaves; ++s) {
-      const int a = 4 * s + grp;
-      const float y = qv ? region0[(a >> 4) * region_floats + yoff + (a & 15) * ypitch + q] : one;
-      c = mma(x[s], y, c);
+    for (int s = 0; s < 4 * kDecWaves; s += 2) {
+      const int a = 4 * s + grp, b = a + 4;
+      const float y0 = qv ? region0[(a >> 4) * region_floats + yoff + (a & 15) * ypitch + q] : one;
+      const float y1 = qv ? region0[(b >> 4) * region_floats + yoff + (b & 15) * ypitch + q] : one;
+      c0 = mma(x[s], y0, c0);
+      c1 = mma(x[s + 1], y1, c1);
     }
+    const f32x4 c = c0 + c1;
     if (q <= Q) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
