@@ -116,3 +116,43 @@ def test_decode_backward_matches_central_differences():
     for j in range(3):
         check(P["W1"][j], G["W1"][j]); check(P["b1"][j], G["b1"][j])
         check(P["W2"][j], G["W2"][j]); check(P["b2"][j], G["b2"][j])
+
+
+def test_relu_clamps_negative_preactivations():
+    """The hidden layers of eq. 2 are ReLU: a unit fed -delta (negative for
+    every anchor) contributes nothing and receives no gradient, and a unit
+    fed delta - c is max(delta - c, 0), zero exactly on the anchors nearer
+    than c.  Expected values are evaluated here in NumPy from eq. 3."""
+    a, d, xc = _small(6, m=12, k=3, width=8)
+    k = d.k
+    W1 = [np.zeros_like(w) for w in d.W1]
+    b1 = [np.zeros_like(b) for b in d.b1]
+    W2 = _zero_w2(d)
+    b2 = [np.zeros_like(b) for b in d.b2]
+    diff = a.xyz.astype(np.float64) - xc
+    delta = np.linalg.norm(diff, axis=1)
+    c = float(np.float32(np.median(delta)))  # the bias array is float32
+    assert (delta < c).sum() >= 3 and (delta > c).sum() >= 3
+    # opacity head: hidden 0 = relu(-delta) = 0, hidden 1 = relu(delta - c)
+    W1[0][0, 35] = -1.0
+    W1[0][1, 35] = 1.0
+    b1[0][1] = -c
+    W2[0][:, 0] = 1.0
+    W2[0][:, 1] = 0.5
+    b2[0][:] = 0.25
+    out = dec.decode_forward(a.xyz, a.feat, a.scale, a.offsets, W1, b1, W2, b2, xc)
+    y = 0.25 + 0.5 * np.maximum(delta - c, 0.0)
+    np.testing.assert_allclose(out[3].numpy().reshape(-1, k), np.tanh(y)[:, None].repeat(k, 1), rtol=1e-14)
+    # gradients of sum(g * opacity): unit 0 is dead, unit 1 lives on delta > c
+    rng = np.random.default_rng(12)
+    n = a.m * k
+    g_o = rng.normal(size=n)
+    up = [np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((n, 4)), g_o, np.zeros((n, 3))]
+    G = dec.decode_backward(a.xyz, a.feat, a.scale, a.offsets, W1, b1, W2, b2, xc, up)
+    dy = (g_o.reshape(-1, k) * (1.0 - np.tanh(y)[:, None] ** 2))    # d loss / d head output [m, k]
+    live = delta > c
+    assert np.all(G["W1"][0][0] == 0.0) and G["b1"][0][0] == 0.0 and np.all(G["W2"][0][:, 0] == 0.0)
+    np.testing.assert_allclose(G["W2"][0][:, 1], (dy * np.maximum(delta - c, 0.0)[:, None]).sum(0), rtol=1e-12)
+    np.testing.assert_allclose(G["b1"][0][1], 0.5 * dy[live].sum(), rtol=1e-12)
+    np.testing.assert_allclose(G["W1"][0][1, 35], 0.5 * (dy[live] * delta[live, None]).sum(), rtol=1e-12)
+    np.testing.assert_allclose(G["b2"][0], dy.sum(0), rtol=1e-12)
