@@ -5,7 +5,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 and shares no code with it.
 
 * ``render``, ``grad``, ``project``, ``binning``: ctypes wrappers over the
-  FP64 C++ reference in ``oracle.cpp`` (see its header for the definition).
+  FP64 C++ reference in ``oracle.cpp`` (see its header for the definition);
+  ``render`` and ``grad`` also run its float32 evaluation (``fp32=True``).
 * ``decode``: the anchor -> neural-Gaussian decoder of Section III-A
   (eq. 1-5) in plain PyTorch CPU float64 with autograd (``decode.py``).
 * ``loss``: the mapping loss of eq. 7-9 (``loss.py``).
@@ -22,7 +23,7 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB = None
+_LIBS = {}
 
 _D = ctypes.POINTER(ctypes.c_double)
 _F = ctypes.POINTER(ctypes.c_float)
@@ -32,10 +33,11 @@ _U32 = ctypes.POINTER(ctypes.c_uint32)
 _U64 = ctypes.POINTER(ctypes.c_uint64)
 
 
-def lib():
-    global _LIB
-    if _LIB is None:
-        path = os.path.join(HERE, "liboracle.so")
+def lib(fp32: bool = False):
+    """The FP64 reference, or with fp32=True the same definition evaluated in
+    float32 (every step rounded to float32)."""
+    if fp32 not in _LIBS:
+        path = os.path.join(HERE, "liboracle32.so" if fp32 else "liboracle.so")
         if not os.path.exists(path):
             from . import build as _b
             _b.build()
@@ -52,8 +54,8 @@ def lib():
                                      ctypes.c_uint32, ctypes.c_uint32, i64, _U64, _U32, _U32]
         L.oracle_binning.restype = i64
         L.oracle_num_threads.restype = c_int
-        _LIB = L
-    return _LIB
+        _LIBS[fp32] = L
+    return _LIBS[fp32]
 
 
 def num_threads() -> int:
@@ -98,23 +100,26 @@ def project(g, cam):
     return out
 
 
-def render(g, cam, brute_force: bool = False, margins=(1e-4, 1e-4, 1e-4)):
-    """FP64 forward render of one view.  Returns rgb[3,H,W], depth, alpha,
-    T_final, n_blend, n_eval and the near-tie pixel flags."""
+def render(g, cam, brute_force: bool = False, margins=(1e-4, 1e-4, 1e-4), fp32: bool = False):
+    """FP64 forward render of one view (fp32=True: evaluated in float32).
+    Returns rgb[3,H,W], depth, alpha, T_final, n_blend, n_eval and the
+    near-tie pixel flags."""
     W, H = cam.width, cam.height
     intr, w2c = _cam_arrays(cam)
     m, l, q, o, c = _gauss_arrays(g)
     rgb = np.zeros((3, H, W)); depth = np.zeros((H, W)); alpha = np.zeros((H, W)); T = np.zeros((H, W))
     nb = np.zeros((H, W), np.int32); ne = np.zeros((H, W), np.int32); fl = np.zeros((H, W), np.uint8)
-    lib().oracle_render(W, H, _p(intr, _D), _p(w2c, _D), g.n, _p(m, _D), _p(l, _D), _p(q, _D), _p(o, _D),
+    lib(fp32).oracle_render(W, H, _p(intr, _D), _p(w2c, _D), g.n, _p(m, _D), _p(l, _D), _p(q, _D), _p(o, _D),
                         _p(c, _D), int(brute_force), float(margins[0]), float(margins[1]), float(margins[2]),
                         _p(rgb, _D), _p(depth, _D), _p(alpha, _D), _p(T, _D), _p(nb, _I32), _p(ne, _I32),
                         _p(fl, _U8))
     return dict(rgb=rgb, depth=depth, alpha=alpha, T_final=T, n_blend=nb, n_eval=ne, flags=fl.astype(bool))
 
 
-def grad(g, cam, g_rgb, g_depth, g_alpha, skip: Optional[np.ndarray] = None, quantities: bool = False):
-    """FP64 gradient of sum(g_rgb*RGB + g_depth*D + g_alpha*A).
+def grad(g, cam, g_rgb, g_depth, g_alpha, skip: Optional[np.ndarray] = None, quantities: bool = False,
+         fp32: bool = False):
+    """FP64 gradient of sum(g_rgb*RGB + g_depth*D + g_alpha*A) (fp32=True: the
+    same definition evaluated in float32, its scales and bounds too).
 
     Returns (grads, scales): dicts with means, log_scales, quats, opacities,
     colors and pose (rho, phi) -- the gradient and its summation error scale.
@@ -136,7 +141,7 @@ def grad(g, cam, g_rgb, g_depth, g_alpha, skip: Optional[np.ndarray] = None, qua
     qg = np.zeros((n, 10)) if quantities else None
     qs = np.zeros((n, 10)) if quantities else None
     qb = np.zeros((n, 10)) if quantities else None
-    lib().oracle_grad(W, H, _p(intr, _D), _p(w2c, _D), n, _p(m, _D), _p(l, _D), _p(q, _D), _p(o, _D),
+    lib(fp32).oracle_grad(W, H, _p(intr, _D), _p(w2c, _D), n, _p(m, _D), _p(l, _D), _p(q, _D), _p(o, _D),
                       _p(c, _D), _p(gr, _D), _p(gd, _D), _p(ga, _D),
                       None if sk is None else _p(sk, _U8),
                       *[_p(a, _D) for a in outs], *[_p(a, _D) for a in scl],

@@ -46,44 +46,53 @@
 #include <omp.h>
 #endif
 
+// The scalar every step is evaluated in.  The reference build is FP64; an
+// FP32 build of the same source (ORACLE_REAL=float, with single-precision
+// literals) measures how far a float32 evaluation of the definition moves
+// each result, and is the like-for-like CPU timing of the method.
+#ifndef ORACLE_REAL
+#define ORACLE_REAL double
+#endif
+typedef ORACLE_REAL real;
+
 namespace {
 
-// FP32 literals of the method, promoted to double so that both sides test
-// against the same real numbers.
-const double kAlphaMin = (double)(1.0f / 255.0f);
-const double kAlphaMax = (double)0.99f;
-const double kTmin = (double)1e-4f;
-const double kDilate = (double)0.3f;
-const double kGuardLo = (double)0.15f;   // guard margin beyond the image, in image widths
-const double kGuardHi = (double)1.15f;
+// FP32 literals of the method, held in the evaluation scalar so that both
+// sides test against the same real numbers.
+const real kAlphaMin = (real)(1.0f / 255.0f);
+const real kAlphaMax = (real)0.99f;
+const real kTmin = (real)1e-4f;
+const real kDilate = (real)0.3f;
+const real kGuardLo = (real)0.15f;   // guard margin beyond the image, in image widths
+const real kGuardHi = (real)1.15f;
 
 // ---------------------------------------------------------------------------
 // forward-mode dual numbers
 // ---------------------------------------------------------------------------
 template <int N>
 struct Dual {
-  double v;
-  double d[N];
+  real v;
+  real d[N];
   Dual() : v(0) { std::memset(d, 0, sizeof(d)); }
-  Dual(double x) : v(x) { std::memset(d, 0, sizeof(d)); }  // NOLINT: implicit constant
+  Dual(real x) : v(x) { std::memset(d, 0, sizeof(d)); }  // NOLINT: implicit constant
 };
 template <int N> inline Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) { Dual<N> r(a.v + b.v); for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i]; return r; }
 template <int N> inline Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) { Dual<N> r(a.v - b.v); for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i]; return r; }
 template <int N> inline Dual<N> operator-(const Dual<N>& a) { Dual<N> r(-a.v); for (int i = 0; i < N; ++i) r.d[i] = -a.d[i]; return r; }
 template <int N> inline Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) { Dual<N> r(a.v * b.v); for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i]; return r; }
 template <int N> inline Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) { Dual<N> r(a.v / b.v); for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] * b.v - a.v * b.d[i]) / (b.v * b.v); return r; }
-template <int N> inline Dual<N> operator+(const Dual<N>& a, double b) { return a + Dual<N>(b); }
-template <int N> inline Dual<N> operator+(double a, const Dual<N>& b) { return Dual<N>(a) + b; }
-template <int N> inline Dual<N> operator-(const Dual<N>& a, double b) { return a - Dual<N>(b); }
-template <int N> inline Dual<N> operator-(double a, const Dual<N>& b) { return Dual<N>(a) - b; }
-template <int N> inline Dual<N> operator*(const Dual<N>& a, double b) { return a * Dual<N>(b); }
-template <int N> inline Dual<N> operator*(double a, const Dual<N>& b) { return Dual<N>(a) * b; }
-template <int N> inline Dual<N> operator/(const Dual<N>& a, double b) { return a / Dual<N>(b); }
-template <int N> inline Dual<N> operator/(double a, const Dual<N>& b) { return Dual<N>(a) / b; }
-template <int N> inline Dual<N> exp(const Dual<N>& a) { double e = std::exp(a.v); Dual<N> r(e); for (int i = 0; i < N; ++i) r.d[i] = e * a.d[i]; return r; }
-template <int N> inline Dual<N> sqrt(const Dual<N>& a) { double s = std::sqrt(a.v); Dual<N> r(s); for (int i = 0; i < N; ++i) r.d[i] = a.d[i] / (2.0 * s); return r; }
-template <int N> inline double val(const Dual<N>& a) { return a.v; }
-inline double val(double a) { return a; }
+template <int N> inline Dual<N> operator+(const Dual<N>& a, real b) { return a + Dual<N>(b); }
+template <int N> inline Dual<N> operator+(real a, const Dual<N>& b) { return Dual<N>(a) + b; }
+template <int N> inline Dual<N> operator-(const Dual<N>& a, real b) { return a - Dual<N>(b); }
+template <int N> inline Dual<N> operator-(real a, const Dual<N>& b) { return Dual<N>(a) - b; }
+template <int N> inline Dual<N> operator*(const Dual<N>& a, real b) { return a * Dual<N>(b); }
+template <int N> inline Dual<N> operator*(real a, const Dual<N>& b) { return Dual<N>(a) * b; }
+template <int N> inline Dual<N> operator/(const Dual<N>& a, real b) { return a / Dual<N>(b); }
+template <int N> inline Dual<N> operator/(real a, const Dual<N>& b) { return Dual<N>(a) / b; }
+template <int N> inline Dual<N> exp(const Dual<N>& a) { real e = std::exp(a.v); Dual<N> r(e); for (int i = 0; i < N; ++i) r.d[i] = e * a.d[i]; return r; }
+template <int N> inline Dual<N> sqrt(const Dual<N>& a) { real s = std::sqrt(a.v); Dual<N> r(s); for (int i = 0; i < N; ++i) r.d[i] = a.d[i] / (2.0 * s); return r; }
+template <int N> inline real val(const Dual<N>& a) { return a.v; }
+inline real val(real a) { return a; }
 using std::exp;
 using std::sqrt;
 
@@ -92,8 +101,8 @@ using std::sqrt;
 // ---------------------------------------------------------------------------
 struct Cam {
   int W, H;
-  double fx, fy, cx, cy, nearp;
-  double R[9], t[3];
+  real fx, fy, cx, cy, nearp;
+  real R[9], t[3];
   float fR[9], ft[3], ffx, ffy, fcx, fcy, fnear;  // the same values as float
 };
 
@@ -116,7 +125,7 @@ Cam make_cam(int W, int H, const double* intr, const double* w2c) {
 // binning keys depend on.  Exp-free, fixed operation order, no contraction
 // (this file is compiled with -ffp-contract=off).
 struct Spec32 { float x, y, z, u, v; };
-Spec32 spec32(const Cam& c, const double* mu) {
+Spec32 spec32(const Cam& c, const real* mu) {
   const float mx = (float)mu[0], my = (float)mu[1], mz = (float)mu[2];
   Spec32 s;
   s.x = ((c.fR[0] * mx + c.fR[1] * my) + c.fR[2] * mz) + c.ft[0];
@@ -177,8 +186,8 @@ bool project_math(const S mu[3], const S ls[3], const S q[4], const S R[9], cons
     }
   // F4 Jacobian of the pinhole map with the guard clamp
   S tx = p[0] / p[2], ty = p[1] / p[2];
-  const double lx = (-kGuardLo * cam.W - cam.cx) / cam.fx, hx = (kGuardHi * cam.W - cam.cx) / cam.fx;
-  const double ly = (-kGuardLo * cam.H - cam.cy) / cam.fy, hy = (kGuardHi * cam.H - cam.cy) / cam.fy;
+  const real lx = (-kGuardLo * cam.W - cam.cx) / cam.fx, hx = (kGuardHi * cam.W - cam.cx) / cam.fx;
+  const real ly = (-kGuardLo * cam.H - cam.cy) / cam.fy, hy = (kGuardHi * cam.H - cam.cy) / cam.fy;
   S txc = tx, tyc = ty;
   if (val(tx) < lx) txc = S(lx);
   if (val(tx) > hx) txc = S(hx);
@@ -219,8 +228,8 @@ bool project_math(const S mu[3], const S ls[3], const S q[4], const S R[9], cons
 // Primal per-Gaussian record in FP64 plus the FP32 values that decide integers.
 struct Prim {
   int valid;
-  double u, v, z, Qa, Qb, Qc, a, b, c, o, col[3];
-  double hx, hy;
+  real u, v, z, Qa, Qb, Qc, a, b, c, o, col[3];
+  real hx, hy;
   int x0, x1, y0, y1;
   uint32_t zbits;
   float u32, v32, z32;
@@ -228,13 +237,13 @@ struct Prim {
 };
 
 bool finite_all(const Prim& p) {
-  const double xs[] = {p.u, p.v, p.z, p.Qa, p.Qb, p.Qc, p.a, p.b, p.c};
-  for (double x : xs) if (!std::isfinite(x)) return false;
+  const real xs[] = {p.u, p.v, p.z, p.Qa, p.Qb, p.Qc, p.a, p.b, p.c};
+  for (real x : xs) if (!std::isfinite(x)) return false;
   return true;
 }
 
-Prim project_one(const Cam& cam, const double* mu, const double* ls, const double* q, double o,
-                 const double* col, int use_box) {
+Prim project_one(const Cam& cam, const real* mu, const real* ls, const real* q, real o,
+                 const real* col, int use_box) {
   Prim pr;
   std::memset(&pr, 0, sizeof(pr));
   const Spec32 s32 = spec32(cam, mu);
@@ -245,29 +254,29 @@ Prim project_one(const Cam& cam, const double* mu, const double* ls, const doubl
   // visibility is decided in FP32 (F3) and on the float opacity (F9)
   if (!(s32.z > cam.fnear)) return pr;
   if (!((float)o > 1.0f / 255.0f)) return pr;
-  Proj<double> P;
-  if (!project_math<double>(mu, ls, q, cam.R, cam.t, cam, P)) return pr;
+  Proj<real> P;
+  if (!project_math<real>(mu, ls, q, cam.R, cam.t, cam, P)) return pr;
   pr.u = P.u; pr.v = P.v; pr.z = P.z; pr.Qa = P.Qa; pr.Qb = P.Qb; pr.Qc = P.Qc;
   pr.a = P.a; pr.b = P.b; pr.c = P.c;
   if (!finite_all(pr)) return pr;
   {
-    const double tx = (cam.R[0] * mu[0] + cam.R[1] * mu[1] + cam.R[2] * mu[2] + cam.t[0]) / P.z;
-    const double ty = (cam.R[3] * mu[0] + cam.R[4] * mu[1] + cam.R[5] * mu[2] + cam.t[1]) / P.z;
-    const double lims[4] = {(-kGuardLo * cam.W - cam.cx) / cam.fx, (kGuardHi * cam.W - cam.cx) / cam.fx,
+    const real tx = (cam.R[0] * mu[0] + cam.R[1] * mu[1] + cam.R[2] * mu[2] + cam.t[0]) / P.z;
+    const real ty = (cam.R[3] * mu[0] + cam.R[4] * mu[1] + cam.R[5] * mu[2] + cam.t[1]) / P.z;
+    const real lims[4] = {(-kGuardLo * cam.W - cam.cx) / cam.fx, (kGuardHi * cam.W - cam.cx) / cam.fx,
                             (-kGuardLo * cam.H - cam.cy) / cam.fy, (kGuardHi * cam.H - cam.cy) / cam.fy};
-    const double vals[4] = {tx, tx, ty, ty};
+    const real vals[4] = {tx, tx, ty, ty};
     for (int i = 0; i < 4; ++i)
       if (std::fabs(vals[i] - lims[i]) <= 1e-6 * std::max(1.0, std::fabs(lims[i]))) pr.near_guard = 1;
   }
   // F9 opacity-aware box, padded by one pixel, pixel centres at +0.5
-  const double kq = 2.0 * std::log(o / kAlphaMin);
+  const real kq = 2.0 * std::log(o / kAlphaMin);
   pr.hx = std::sqrt(kq * P.a);
   pr.hy = std::sqrt(kq * P.c);
   if (use_box) {
-    const double lo_x = std::ceil(P.u - pr.hx - 1.5), hi_x = std::floor(P.u + pr.hx + 0.5);
-    const double lo_y = std::ceil(P.v - pr.hy - 1.5), hi_y = std::floor(P.v + pr.hy + 0.5);
-    const double x0 = std::max(lo_x, 0.0), x1 = std::min(hi_x, (double)(cam.W - 1));
-    const double y0 = std::max(lo_y, 0.0), y1 = std::min(hi_y, (double)(cam.H - 1));
+    const real lo_x = std::ceil(P.u - pr.hx - 1.5), hi_x = std::floor(P.u + pr.hx + 0.5);
+    const real lo_y = std::ceil(P.v - pr.hy - 1.5), hi_y = std::floor(P.v + pr.hy + 0.5);
+    const real x0 = std::max(lo_x, 0.0), x1 = std::min(hi_x, (real)(cam.W - 1));
+    const real y0 = std::max(lo_y, 0.0), y1 = std::min(hi_y, (real)(cam.H - 1));
     if (!(x0 <= x1 && y0 <= y1)) return pr;
     pr.x0 = (int)x0; pr.x1 = (int)x1; pr.y0 = (int)y0; pr.y1 = (int)y1;
   } else {
@@ -279,7 +288,17 @@ Prim project_one(const Cam& cam, const double* mu, const double* ls, const doubl
 
 struct Inputs {
   int64_t n;
-  const double *means, *ls, *quats, *opac, *cols;
+  const real *means, *ls, *quats, *opac, *cols;
+};
+
+// The caller's FP64 arrays in the evaluation scalar.
+struct InputCopy {
+  std::vector<real> m, l, q, o, c;
+  Inputs in;
+  InputCopy(int64_t n, const double* means, const double* ls, const double* quats, const double* opac,
+            const double* cols)
+      : m(means, means + 3 * n), l(ls, ls + 3 * n), q(quats, quats + 4 * n), o(opac, opac + n),
+        c(cols, cols + 3 * n), in{n, m.data(), l.data(), q.data(), o.data(), c.data()} {}
 };
 
 std::vector<Prim> project_all(const Cam& cam, const Inputs& in, int use_box) {
@@ -328,47 +347,47 @@ inline void pixel_candidates(const Buckets& b, const std::vector<Prim>& pr, int 
   }
 }
 
-struct Margins { double alpha, clamp, trans; };
+struct Margins { real alpha, clamp, trans; };
 
 // F11 primal composite of one pixel over its ordered candidates.
 struct PixOut {
-  double C[3], D, T;
+  real C[3], D, T;
   int nb, ne;
   int flag;
   int32_t last;  // candidate position of the last blended Gaussian, -1 if none
 };
 
 PixOut composite_pixel(const std::vector<Prim>& pr, const std::vector<int32_t>& cand, int px, int py,
-                       const Margins& m, std::vector<int32_t>* blended, std::vector<double>* bl_alpha,
-                       std::vector<double>* bl_T) {
+                       const Margins& m, std::vector<int32_t>* blended, std::vector<real>* bl_alpha,
+                       std::vector<real>* bl_T) {
   PixOut r;
   r.C[0] = r.C[1] = r.C[2] = 0.0; r.D = 0.0; r.T = 1.0; r.nb = 0; r.ne = 0; r.flag = 0; r.last = -1;
-  const double cxp = px + 0.5, cyp = py + 0.5;
+  const real cxp = px + 0.5, cyp = py + 0.5;
   // A float32 evaluation carries the projected centre to within a few units
   // in the last place of |u|, |v|; that moves sigma by |d sigma/d u| du and
   // alpha by the same relative amount.  The flag margins add this term, and
   // the transmittance margin accumulates the relative errors of (1 - alpha).
-  const double ulp_pos = std::ldexp(1.0, -22);
-  double T = 1.0, eT = 0.0;
+  const real ulp_pos = std::ldexp(1.0, -22);
+  real T = 1.0, eT = 0.0;
   for (size_t k = 0; k < cand.size(); ++k) {
     const Prim& p = pr[cand[k]];
     if (p.near_guard) r.flag = 1;
-    const double dx = p.u - cxp, dy = p.v - cyp;
-    const double sigma = 0.5 * (p.Qa * dx * dx + p.Qc * dy * dy) + p.Qb * dx * dy;
-    const double raw = p.o * std::exp(-sigma);
-    const double drel = std::fabs(p.Qa * dx + p.Qb * dy) * std::fabs(p.u) * ulp_pos +
+    const real dx = p.u - cxp, dy = p.v - cyp;
+    const real sigma = 0.5 * (p.Qa * dx * dx + p.Qc * dy * dy) + p.Qb * dx * dy;
+    const real raw = p.o * std::exp(-sigma);
+    const real drel = std::fabs(p.Qa * dx + p.Qb * dy) * std::fabs(p.u) * ulp_pos +
                         std::fabs(p.Qb * dx + p.Qc * dy) * std::fabs(p.v) * ulp_pos +
                         (1.0 + sigma) * 16.0 * std::ldexp(1.0, -24);  // exp and conic rounding
     if (std::fabs(raw - kAlphaMax) <= m.clamp + raw * drel) r.flag = 1;
-    const double alpha = std::min(kAlphaMax, raw);
+    const real alpha = std::min(kAlphaMax, raw);
     r.ne++;
     if (std::fabs(alpha - kAlphaMin) <= (m.alpha + drel) * kAlphaMin) r.flag = 1;
     if (alpha < kAlphaMin) continue;
-    const double Tn = T * (1.0 - alpha);
+    const real Tn = T * (1.0 - alpha);
     eT += alpha * drel / (1.0 - alpha);
     if (std::fabs(Tn - kTmin) <= (m.trans + eT) * kTmin) r.flag = 1;
     if (Tn < kTmin) break;
-    const double w = alpha * T;
+    const real w = alpha * T;
     for (int ch = 0; ch < 3; ++ch) r.C[ch] += w * p.col[ch];
     r.D += w * p.z;
     if (blended) { blended->push_back(cand[k]); bl_alpha->push_back(alpha); bl_T->push_back(T); }
@@ -387,13 +406,13 @@ enum { QU = 0, QV, QA, QB, QC, QO, QR, QG, QBL, QZ, NQ };
 // pixel: the blended sequence is fixed by the primal pass, a 10-component dual
 // runs the F11 recurrence over the suffix starting at k.
 void pixel_quantity_grads(const std::vector<Prim>& pr, const std::vector<int32_t>& bl,
-                          const std::vector<double>& bl_T, size_t k, int px, int py,
+                          const std::vector<real>& bl_T, size_t k, int px, int py,
                           Dual<NQ> out[5] /* R, G, B, D, A */, Dual<NQ>* alpha_k) {
   typedef Dual<NQ> D;
-  const double cxp = px + 0.5, cyp = py + 0.5;
+  const real cxp = px + 0.5, cyp = py + 0.5;
   const Prim& g = pr[bl[k]];
   D q[NQ];
-  const double qv[NQ] = {g.u, g.v, g.Qa, g.Qb, g.Qc, g.o, g.col[0], g.col[1], g.col[2], g.z};
+  const real qv[NQ] = {g.u, g.v, g.Qa, g.Qb, g.Qc, g.o, g.col[0], g.col[1], g.col[2], g.z};
   for (int i = 0; i < NQ; ++i) { q[i] = D(qv[i]); q[i].d[i] = 1.0; }
   D C[3] = {D(0.0), D(0.0), D(0.0)};
   D Dp(0.0);
@@ -409,8 +428,8 @@ void pixel_quantity_grads(const std::vector<Prim>& pr, const std::vector<int32_t
       if (alpha_k) *alpha_k = alpha;
       cc[0] = q[QR]; cc[1] = q[QG]; cc[2] = q[QBL]; z = q[QZ];
     } else {
-      const double dx = p.u - cxp, dy = p.v - cyp;
-      const double sigma = 0.5 * (p.Qa * dx * dx + p.Qc * dy * dy) + p.Qb * dx * dy;
+      const real dx = p.u - cxp, dy = p.v - cyp;
+      const real sigma = 0.5 * (p.Qa * dx * dx + p.Qc * dy * dy) + p.Qb * dx * dy;
       alpha = D(std::min(kAlphaMax, p.o * std::exp(-sigma)));
       cc[0] = D(p.col[0]); cc[1] = D(p.col[1]); cc[2] = D(p.col[2]); z = D(p.z);
     }
@@ -434,7 +453,8 @@ int oracle_project(int W, int H, const double* intr, const double* w2c, int64_t 
                    const double* means, const double* ls, const double* quats, const double* opac,
                    const double* cols, double* out_f64, float* out_f32, uint8_t* valid, int32_t* box) {
   const Cam cam = make_cam(W, H, intr, w2c);
-  const Inputs in{n, means, ls, quats, opac, cols};
+  const InputCopy copy(n, means, ls, quats, opac, cols);
+  const Inputs& in = copy.in;
   std::vector<Prim> pr = project_all(cam, in, 1);
   for (int64_t i = 0; i < n; ++i) {
     const Prim& p = pr[i];
@@ -457,10 +477,11 @@ int oracle_render(int W, int H, const double* intr, const double* w2c, int64_t n
                   double* rgb, double* depth, double* alpha, double* T_final, int32_t* n_blend,
                   int32_t* n_eval, uint8_t* flags) {
   const Cam cam = make_cam(W, H, intr, w2c);
-  const Inputs in{n, means, ls, quats, opac, cols};
+  const InputCopy copy(n, means, ls, quats, opac, cols);
+  const Inputs& in = copy.in;
   std::vector<Prim> pr = project_all(cam, in, brute_force ? 0 : 1);
   Buckets b = make_buckets(cam, pr);
-  const Margins m{m_alpha, m_clamp, m_trans};
+  const Margins m{(real)m_alpha, (real)m_clamp, (real)m_trans};
   const size_t HW = (size_t)W * H;
 #pragma omp parallel
   {
@@ -500,24 +521,26 @@ int oracle_grad(int W, int H, const double* intr, const double* w2c, int64_t n,
                 double* b_ls, double* b_quats, double* b_opac, double* b_cols, double* b_pose,
                 double* q_scale, double* q_bound) {
   const Cam cam = make_cam(W, H, intr, w2c);
-  const Inputs in{n, means, ls, quats, opac, cols};
+  const InputCopy copy(n, means, ls, quats, opac, cols);
+  const Inputs& in = copy.in;
   std::vector<Prim> pr = project_all(cam, in, 1);
   Buckets b = make_buckets(cam, pr);
   const Margins m{0.0, 0.0, 0.0};
   const size_t HW = (size_t)W * H;
-  std::vector<double> G((size_t)n * NQ, 0.0), Gabs((size_t)n * NQ, 0.0), Gfp((size_t)n * NQ, 0.0);
-  const double ulp_pos = std::ldexp(1.0, -22);
+  std::vector<real> G((size_t)n * NQ, 0.0), Gabs((size_t)n * NQ, 0.0), Gfp((size_t)n * NQ, 0.0);
+  const real ulp_pos = std::ldexp(1.0, -22);
 #pragma omp parallel
   {
     std::vector<int32_t> cand, bl;
-    std::vector<double> bla, blT, fbar, drel, eTb;
+    std::vector<real> bla, blT, fbar, drel, eTb;
     Dual<NQ> outs[5], alpha_k;
 #pragma omp for schedule(dynamic, 1)
     for (int py = 0; py < H; ++py)
       for (int px = 0; px < W; ++px) {
         const size_t pi = (size_t)py * W + px;
         if (skip && skip[pi]) continue;
-        const double gw[5] = {g_rgb[pi], g_rgb[HW + pi], g_rgb[2 * HW + pi], g_depth[pi], g_alpha[pi]};
+        const real gw[5] = {(real)g_rgb[pi], (real)g_rgb[HW + pi], (real)g_rgb[2 * HW + pi], (real)g_depth[pi],
+                            (real)g_alpha[pi]};
         if (gw[0] == 0 && gw[1] == 0 && gw[2] == 0 && gw[3] == 0 && gw[4] == 0) continue;
         pixel_candidates(b, pr, px, py, cand);
         bl.clear(); bla.clear(); blT.clear();
@@ -534,28 +557,28 @@ int oracle_grad(int W, int H, const double* intr, const double* w2c, int64_t n,
         // error it leaves in the transmittance of everything behind it
         drel.assign(bl.size(), 0.0);
         eTb.assign(bl.size(), 0.0);
-        double eT = 0.0;
+        real eT = 0.0;
         for (size_t j = 0; j < bl.size(); ++j) {
           const Prim& p = pr[bl[j]];
-          const double dx = p.u - (px + 0.5), dy = p.v - (py + 0.5);
-          const double sigma = 0.5 * (p.Qa * dx * dx + p.Qc * dy * dy) + p.Qb * dx * dy;
+          const real dx = p.u - (px + 0.5), dy = p.v - (py + 0.5);
+          const real sigma = 0.5 * (p.Qa * dx * dx + p.Qc * dy * dy) + p.Qb * dx * dy;
           drel[j] = std::fabs(p.Qa * dx + p.Qb * dy) * std::fabs(p.u) * ulp_pos +
                     std::fabs(p.Qb * dx + p.Qc * dy) * std::fabs(p.v) * ulp_pos +
                     (1.0 + sigma) * 16.0 * std::ldexp(1.0, -24);  // exp and conic rounding
           eTb[j] = eT;
           eT += bla[j] * drel[j] / (1.0 - bla[j]) + 2.0 * std::ldexp(1.0, -24);
         }
-        double behind = 0.0;  // sum over blended j > k of alpha_j T_j fbar_j
+        real behind = 0.0;  // sum over blended j > k of alpha_j T_j fbar_j
         for (size_t kk = bl.size(); kk-- > 0;) {
           const size_t k = kk;
           pixel_quantity_grads(pr, bl, blT, k, px, py, outs, &alpha_k);
           const int32_t gi = bl[k];
-          const double mag = blT[k] * fbar[k] + behind / (1.0 - bla[k]);
+          const real mag = blT[k] * fbar[k] + behind / (1.0 - bla[k]);
           for (int qn = 0; qn < NQ; ++qn) {
-            double acc = 0.0;
+            real acc = 0.0;
             for (int o = 0; o < 5; ++o) acc += gw[o] * outs[o].d[qn];
-            const double scale = qn <= QO ? mag * std::fabs(alpha_k.d[qn]) : std::fabs(acc);
-            const double fp = qn <= QO ? scale * (eT + drel[k]) : scale * (eTb[k] + drel[k]);
+            const real scale = qn <= QO ? mag * std::fabs(alpha_k.d[qn]) : std::fabs(acc);
+            const real fp = qn <= QO ? scale * (eT + drel[k]) : scale * (eTb[k] + drel[k]);
 #pragma omp atomic
             G[(size_t)gi * NQ + qn] += acc;
 #pragma omp atomic
@@ -573,10 +596,10 @@ int oracle_grad(int W, int H, const double* intr, const double* w2c, int64_t n,
     for (size_t i = 0; i < G.size(); ++i) { q_scale[i] = Gabs[i]; q_bound[i] = Gfp[i]; }
   // chain through the projection: 14 parameter duals + 6 pose duals
   typedef Dual<20> D20;
-  double pose[6] = {0, 0, 0, 0, 0, 0}, spose[6] = {0, 0, 0, 0, 0, 0}, bpose[6] = {0, 0, 0, 0, 0, 0};
+  real pose[6] = {0, 0, 0, 0, 0, 0}, spose[6] = {0, 0, 0, 0, 0, 0}, bpose[6] = {0, 0, 0, 0, 0, 0};
 #pragma omp parallel
   {
-    double lpose[6] = {0, 0, 0, 0, 0, 0}, lspose[6] = {0, 0, 0, 0, 0, 0}, lbpose[6] = {0, 0, 0, 0, 0, 0};
+    real lpose[6] = {0, 0, 0, 0, 0, 0}, lspose[6] = {0, 0, 0, 0, 0, 0}, lbpose[6] = {0, 0, 0, 0, 0, 0};
 #pragma omp for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
       double* dm = d_means + 3 * i; double* dl = d_ls + 3 * i; double* dq = d_quats + 4 * i;
@@ -591,9 +614,9 @@ int oracle_grad(int W, int H, const double* intr, const double* w2c, int64_t n,
       for (int k = 0; k < 3; ++k) bm[k] = bl_[k] = bc[k] = 0.0;
       for (int k = 0; k < 4; ++k) bq[k] = 0.0;
       b_opac[i] = 0.0;
-      const double* Gi = &G[(size_t)i * NQ];
-      const double* Ai = &Gabs[(size_t)i * NQ];
-      const double* Fi = &Gfp[(size_t)i * NQ];
+      const real* Gi = &G[(size_t)i * NQ];
+      const real* Ai = &Gabs[(size_t)i * NQ];
+      const real* Fi = &Gfp[(size_t)i * NQ];
       bool any = false;
       for (int qn = 0; qn < NQ; ++qn) any = any || Ai[qn] != 0.0;
       if (!any) continue;
@@ -609,15 +632,15 @@ int oracle_grad(int W, int H, const double* intr, const double* w2c, int64_t n,
         t[r].d[14 + r] = 1.0;
       }
       // [e_k]x rows: e_x -> (0,0,0; 0,0,-1; 0,1,0) etc.
-      const double E[3][9] = {{0, 0, 0, 0, 0, -1, 0, 1, 0}, {0, 0, 1, 0, 0, 0, -1, 0, 0}, {0, -1, 0, 1, 0, 0, 0, 0, 0}};
+      const real E[3][9] = {{0, 0, 0, 0, 0, -1, 0, 1, 0}, {0, 0, 1, 0, 0, 0, -1, 0, 0}, {0, -1, 0, 1, 0, 0, 0, 0, 0}};
       for (int kk = 0; kk < 3; ++kk)
         for (int r = 0; r < 3; ++r) {
           for (int c = 0; c < 3; ++c) {
-            double acc = 0.0;
+            real acc = 0.0;
             for (int mm = 0; mm < 3; ++mm) acc += E[kk][3 * r + mm] * cam.R[3 * mm + c];
             R[3 * r + c].d[17 + kk] = acc;
           }
-          double acc = 0.0;
+          real acc = 0.0;
           for (int mm = 0; mm < 3; ++mm) acc += E[kk][3 * r + mm] * cam.t[mm];
           t[r].d[17 + kk] += acc;
         }
@@ -627,9 +650,9 @@ int oracle_grad(int W, int H, const double* intr, const double* w2c, int64_t n,
       qd[QU] = P.u; qd[QV] = P.v; qd[QA] = P.Qa; qd[QB] = P.Qb; qd[QC] = P.Qc; qd[QZ] = P.z;
       qd[QO] = D20(opac[i]); qd[QO].d[10] = 1.0;
       for (int k = 0; k < 3; ++k) { qd[QR + k] = D20(cols[3 * i + k]); qd[QR + k].d[11 + k] = 1.0; }
-      double dv[20], sv[20], bv[20];
+      real dv[20], sv[20], bv[20];
       for (int j = 0; j < 20; ++j) {
-        double acc = 0.0, sacc = 0.0, bacc = 0.0;
+        real acc = 0.0, sacc = 0.0, bacc = 0.0;
         for (int qn = 0; qn < NQ; ++qn) {
           acc += Gi[qn] * qd[qn].d[j];
           sacc += Ai[qn] * std::fabs(qd[qn].d[j]);

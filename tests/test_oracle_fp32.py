@@ -1,0 +1,104 @@
+"""The oracle's definition evaluated in float32, against its FP64 reference
+(CPU only).
+
+The FP32 build of the oracle is the same source with every step rounded to
+float32 (single-precision literals, no double intermediates).  It measures
+how far an FP32 evaluation of the renderer moves each result, which is what
+the GPU gates must allow for:
+
+* images: norm-wise within 1e-5 of FP64 on pixels away from a cutoff;
+* the near-tie mask: the pixels where the float32 evaluation blends a
+  different number of Gaussians than FP64 (it took the other side of a
+  cutoff) are the pixels the mask flags;
+* gradients: per element within 1e-4 S + B, where S is the summation error
+  scale and B the oracle's first-order bound on how far float32 rounding of
+  the projected centres and of the transmittance of long stacks moves the
+  element.  On the street frames the FP32 forward alone moves colour
+  gradients by about three times 1e-4 S, and B covers that move.
+
+Workloads: C1 in full; C2 with its gradient on three 128 x 128 crops; and
+192 x 96 windows (a shifted principal point) of a C4 corridor keyframe and
+of a C5 street frame around its vanishing point, where pixels blend about
+200 Gaussians.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from gpu_util import GRAD_TOL, IMAGE_RTOL, MARGINS, masked_weights
+
+
+def _window(cam, x0, y0, w, h):
+    c = cam.copy()
+    c.width, c.height = w, h
+    c.cx, c.cy = cam.cx - x0, cam.cy - y0
+    return c
+
+
+def _crops(cam, seed, n=3, size=128):
+    rng = np.random.default_rng(seed)
+    keep = np.zeros((cam.height, cam.width), bool)
+    for _ in range(n):
+        x0 = rng.integers(0, max(1, cam.width - size))
+        y0 = rng.integers(0, max(1, cam.height - size))
+        keep[y0:y0 + size, x0:x0 + size] = True
+    return keep
+
+
+def _case(name):
+    if name == "c1":
+        sc = scenes.make_c1()
+        return sc.sets[0], sc.cameras[0], sc.weights[0], None
+    if name == "c2":
+        sc = scenes.make_c2()
+        return sc.sets[0], sc.cameras[0], sc.weights[0], _crops(sc.cameras[0], 205)
+    if name == "c4-window":
+        sc = scenes.make_c4(sizes=(1200, 680), weights=False)
+        cam = _window(sc.cameras[0], 504, 292, 192, 96)
+        return sc.sets[0], cam, scenes.upstream_weights(406, [cam])[0], None
+    sc = scenes.make_c5(weights=False)
+    cam = _window(sc.cameras[9], 448, 240, 192, 96)
+    return sc.sets[sc.view_set[9]], cam, scenes.upstream_weights(509, [cam])[0], None
+
+
+@pytest.fixture(scope="module", params=["c1", "c2", "c4-window", "c5-window"])
+def evaluated(request):
+    g, cam, w, crop = _case(request.param)
+    r64 = oracle.render(g, cam, margins=MARGINS)
+    r32 = oracle.render(g, cam, fp32=True)
+    wm = [x.astype(np.float64) for x in masked_weights(w, r64["flags"])]
+    if crop is not None:
+        wm = [x * crop for x in wm]
+    G, S = oracle.grad(g, cam, *wm)
+    G32, _ = oracle.grad(g, cam, *wm, fp32=True)
+    return request.param, r64, r32, G, S, G32
+
+
+def test_fp32_images_within_the_image_gate(evaluated):
+    name, r64, r32, *_ = evaluated
+    keep = ~r64["flags"]
+    assert r64["n_blend"].sum() > 0
+    for plane in ("rgb", "depth", "alpha"):
+        a, b = r32[plane], r64[plane]
+        m = np.broadcast_to(keep, b.shape)
+        err = np.linalg.norm((a - b)[m]) / np.linalg.norm(b[m])
+        assert err <= IMAGE_RTOL / 2, (name, plane, err)
+
+
+def test_fp32_branch_changes_are_flagged(evaluated):
+    """Where float32 blends another number of Gaussians than FP64, a cutoff
+    decided the other way: the near-tie mask must hold that pixel."""
+    name, r64, r32, *_ = evaluated
+    differs = r32["n_blend"] != r64["n_blend"]
+    assert not np.any(differs & ~r64["flags"]), (name, int(differs.sum()), int((differs & ~r64["flags"]).sum()))
+
+
+def test_fp32_gradients_within_scale_plus_bound(evaluated):
+    name, _, _, G, S, G32 = evaluated
+    for k in ("means", "log_scales", "quats", "opacities", "colors", "pose"):
+        s, b = S[k], S[k + "_fp32"]
+        floor = 1e-7 * s.max()
+        err = np.abs(G32[k] - G[k])
+        frac = float(np.max(err / (GRAD_TOL * (s + floor) + b + 1e-300)))
+        assert frac <= 1.0, (name, k, frac)
