@@ -236,7 +236,12 @@ int vpgs_window_create(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, in
 int vpgs_window_set_cameras(vpgs_window* win, const vpgs_camera* cams);
 /* parts = 1: forward of every view; 2: backward (uses the upstream planes
  * as they are when it runs, so a loss gradient can be computed between the
- * two); 3: both.  Each part is one graph launch on `stream`. */
+ * two); 3: both.  Each part is one graph launch on `stream`.  The forward
+ * ends by raising a sticky flag in mapped host memory if its pair list
+ * overflowed; every later run (and part) then returns VPGS_ECAPACITY without
+ * launching anything, so an overflow is never silent even when nothing
+ * synchronises: the outputs of the run that overflowed are invalid, and the
+ * window must be recreated with a larger pair_capacity. */
 #define VPGS_WINDOW_FORWARD 1
 #define VPGS_WINDOW_BACKWARD 2
 int vpgs_window_run(vpgs_window* win, int parts, void* stream);

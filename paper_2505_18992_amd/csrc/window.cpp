@@ -28,11 +28,22 @@ struct vpgs_window {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph[2] = {nullptr, nullptr};       // forward, backward
   hipGraphExec_t exec[2] = {nullptr, nullptr};
+  // Sticky pair-list overflow flag in mapped pinned host memory, set by the
+  // last kernel of every forward run: a later run reports VPGS_ECAPACITY
+  // without synchronising.
+  uint32_t* h_overflow = nullptr;
+  uint32_t* d_overflow = nullptr;  // the device address of the same word
 };
 
 namespace {
 
 const int kShapes[][2] = {{16, 16}, {16, 8}, {8, 8}, {32, 8}};
+
+// Raises the window's sticky host flag when the forward's pair list
+// overflowed (the pairs the scan asked for exceed the capacity).
+__global__ void publish_overflow_kernel(const Counters* cnt, uint32_t capacity, uint32_t* flag) {
+  if (threadIdx.x == 0 && (cnt->overflow || cnt->pairs > capacity)) *(volatile uint32_t*)flag = 1u;
+}
 
 const vpgs_densify_accum* accum_of(vpgs_window* w) {
   if (w->accum.empty()) return nullptr;
@@ -60,6 +71,12 @@ int enqueue_part(vpgs_window* w, int part, hipStream_t st) {
   int rc;
   if (part == 1) {
     if ((rc = enqueue_front(w->ctx, w->sv, st)) || (rc = enqueue_back(w->ctx, w->sv, st))) return rc;
+    if (w->d_overflow) {
+      vpgs_ctx* ctx = w->ctx;
+      hipLaunchKernelGGL(publish_overflow_kernel, dim3(1), dim3(64), 0, st,
+                         static_cast<const Counters*>(w->sv->counters.p), w->sv->capacity, w->d_overflow);
+      HIP_TRY(hipGetLastError());
+    }
     return VPGS_OK;
   }
   return enqueue_backward(w->ctx, w->sv, w->d_pose, st);
@@ -139,6 +156,7 @@ void release(vpgs_window* w) {
   }
   if (w->cap_stream) (void)hipStreamDestroy(w->cap_stream);
   if (w->sv) destroy_saved(w->sv);
+  if (w->h_overflow) (void)hipHostFree(w->h_overflow);
   delete w;
 }
 
@@ -216,6 +234,17 @@ int vpgs_window_create(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, in
   o.pair_capacity = w->sv->capacity;
   w->cfg = o;
   HIP_TRY(hipStreamSynchronize(st));
+  {
+    hipError_t e = hipHostMalloc((void**)&w->h_overflow, sizeof(uint32_t), hipHostMallocMapped);
+    if (e == hipSuccess) {
+      *(volatile uint32_t*)w->h_overflow = 0u;
+      e = hipHostGetDevicePointer((void**)&w->d_overflow, w->h_overflow, 0);
+    }
+    if (e != hipSuccess) {
+      release(w);
+      return fail(ctx, VPGS_ENOMEM, "pinned overflow flag: %s", hipGetErrorString(e));
+    }
+  }
   if (o.use_graph) {
     rc = capture(w);
     if (rc) { release(w); return rc; }
@@ -265,6 +294,9 @@ int vpgs_window_run(vpgs_window* w, int parts, void* stream) {
   if (parts < 1 || parts > 3) return fail(ctx, VPGS_EINVAL, "parts must be 1 (forward), 2 (backward) or 3 (both)");
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(hipSetDevice(ctx->device));
+  if (*(volatile uint32_t*)w->h_overflow)
+    return fail(ctx, VPGS_ECAPACITY, "the pair list of an earlier run overflowed its capacity of %u pairs: its "
+                "outputs were invalid; recreate the window with a larger pair_capacity", w->sv->capacity);
   if (w->tables_dirty) {
     // rebuild the tables for the new poses (same shapes, same buffers) and upload
     HIP_TRY(hipEventSynchronize(w->sv->tab_uploaded));

@@ -1,12 +1,12 @@
-"""GPU parity of the anchor decode (Section III-A, eq. 1-5) and of
-decode -> render -> backward -> decode-backward against the FP64 oracle."""
+"""GPU parity of the anchor decode (Section III-A, eq. 1-5) against the FP64
+oracle (its autograd Function and the chain through the render are in
+test_gpu_autograd.py)."""
 import numpy as np
 import pytest
 import torch
 
-import oracle
 import scenes
-from gpu_util import MARGINS, assert_grads, masked_weights, np_, to_dev
+from gpu_util import np_, to_dev
 from oracle import decode as odec
 
 pytestmark = pytest.mark.gpu
@@ -105,57 +105,3 @@ def test_decode_empty():
     for lst in grads:
         for g in lst:
             assert g.numel() > 0 and int(torch.count_nonzero(g)) == 0
-
-
-def test_decode_autograd_matches_backward():
-    from paper_2505_18992_amd import decode, decode_backward
-    a, d, cam = _case(3, 500, 10, 64)
-    anchors, mlp = _dev_inputs(a, d)
-    feat = anchors[1].clone().requires_grad_(True)
-    W = [[t.clone().requires_grad_(True) for t in lst] for lst in mlp]
-    outs = decode((anchors[0], feat, anchors[2], anchors[3]), W, cam)
-    rng = np.random.default_rng(1)
-    ws = [torch.from_numpy(rng.standard_normal(tuple(o.shape)).astype(np.float32)).cuda() for o in outs]
-    loss = sum((o * w).sum() for o, w in zip(outs, ws))
-    loss.backward()
-    d_feat, _, _, (dW1, _, dW2, _) = decode_backward(anchors, mlp, cam, ws)
-    assert torch.allclose(feat.grad, d_feat, rtol=1e-6, atol=1e-7)
-    assert torch.allclose(W[0][2].grad, dW1[2], rtol=1e-6, atol=1e-7)
-    assert torch.allclose(W[2][1].grad, dW2[1], rtol=1e-6, atol=1e-7)
-
-
-def test_decode_render_backward_end_to_end():
-    """decode -> render -> backward -> decode backward (the mapping step of
-    the anchor representation) against the oracle's FP64 chain."""
-    from paper_2505_18992_amd import decode_backward, decode_forward, render, render_backward
-    sc = scenes.make_c3(m=4000, img=(320, 180))
-    a, d, cam = sc.anchors, sc.decoder, sc.cameras[0]
-    R = cam.world_to_cam[:, :3].astype(np.float64)
-    centre = (-R.T @ cam.world_to_cam[:, 3].astype(np.float64)).astype(np.float32)
-    print("case c3-4k end-to-end", flush=True)
-    anchors, mlp = _dev_inputs(a, d)
-    gs = decode_forward(anchors, mlp, centre)
-    outs, saved = render([gs], [cam])
-    # oracle chain on its own FP64 decode
-    o_out = [t.numpy() for t in odec.decode_forward(a.xyz, a.feat, a.scale, a.offsets, d.W1, d.b1, d.W2, d.b2,
-                                                    centre.astype(np.float64))]
-    og = scenes.GaussianSet(*o_out)
-    ref = oracle.render(og, cam, margins=MARGINS)
-    mask = ref["flags"]
-    w = masked_weights(sc.weights[0], mask)
-    G, S = oracle.grad(og, cam, *[x.astype(np.float64) for x in w])
-    grads, _ = render_backward(saved, [to_dev(w)], want_pose=False)
-    saved.close()
-    got = dict(zip(["means", "log_scales", "quats", "opacities", "colors"], [np_(t) for t in grads[0]]))
-    # the decoded Gaussians differ from the oracle's by FP32 rounding, so the
-    # render-level gradients are compared at the render gate
-    assert_grads(got, G, S, keys=["means", "log_scales", "quats", "opacities", "colors"], tol=2e-4)
-    up_gpu, _ = _untie([np_(t) for t in grads[0]], a, d, centre)
-    up_ora, _ = _untie([G[k] for k in ("means", "log_scales", "quats", "opacities", "colors")], a, d, centre)
-    d_feat, d_scale, d_off, (dW1, db1, dW2, db2) = decode_backward(anchors, mlp, centre, to_dev(up_gpu))
-    GD = odec.decode_backward(a.xyz, a.feat, a.scale, a.offsets, d.W1, d.b1, d.W2, d.b2, centre.astype(np.float64),
-                              [x.astype(np.float64) for x in up_ora])
-    for name, g, e in (("feat", d_feat, GD["feat"]), ("W2[2]", dW2[2], GD["W2"][2]), ("W1[0]", dW1[0], GD["W1"][0])):
-        g = np_(g).astype(np.float64)
-        nrm = np.linalg.norm(g - e) / max(np.linalg.norm(e), 1e-30)
-        assert nrm <= 1e-3, (name, nrm)

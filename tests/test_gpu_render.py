@@ -14,7 +14,8 @@ import torch
 
 import oracle
 import scenes
-from gpu_util import (MARGINS, assert_grads, assert_images, masked_weights, np_, oracle_reference, to_dev)
+from gpu_util import (MARGINS, assert_grads, assert_images, assert_mask_fraction, masked_weights, np_,
+                      oracle_reference, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -140,7 +141,8 @@ def test_c1_forward_parity():
     saved.close()
     ref, mask, _ = oracle_reference(g, cam)
     errs = assert_images(outs[0], ref, mask)
-    print("c1 image errors", errs, "masked", int(mask.sum()), flush=True)
+    frac = assert_mask_fraction(mask, "c1")
+    print("c1 image errors", errs, f"masked {frac:.3%}", flush=True)
     # blends agree exactly on unmasked pixels
     assert abs(st["n_blended"] - int(ref["n_blend"].sum())) <= int(ref["n_blend"][mask].sum()) + 0
 

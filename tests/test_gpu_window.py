@@ -140,3 +140,29 @@ def test_window_multiple_sets():
     outs, grads, d_pose = _eager(sets, sc.cameras, sc.view_set, gw, (16, 16))
     _check(win, outs, grads, d_pose)
     win.close()
+
+
+def test_window_overflow_on_a_later_run_stops_the_next_one():
+    """The pair list is sized once, at creation; when the inputs change so
+    that it no longer fits (here an optimiser step that grows every scale by
+    e^1.5, read in place), the run that overflows raises the window's flag,
+    and the next run fails with VPGS_ECAPACITY instead of rendering
+    truncated lists."""
+    from paper_2505_18992_amd import RenderWindow
+    from paper_2505_18992_amd._lib import VpgsError
+    sc, sets, gw = _scene()
+    print("case window overflow on a later run", flush=True)
+    win = RenderWindow(sets, sc.cameras, sc.view_set, tile=(16, 16), persistent=0)
+    cap = win.config()["pair_capacity"]
+    win.run()
+    st = win.stats()
+    assert st["overflow"] == 0
+    with torch.no_grad():
+        sets[0][1].add_(1.5)
+    win.run()
+    st = win.stats()
+    assert st["overflow"] == 1 and st["pair_capacity"] == cap, st
+    with pytest.raises(VpgsError) as e:
+        win.run()
+    assert e.value.status == -4  # VPGS_ECAPACITY
+    win.close()
