@@ -509,6 +509,20 @@ int vpgs_icp_correspond(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* s
 int vpgs_icp_linearize(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* src, int64_t n, const double* pose,
                        float tau, float sigma, double* terms, void* stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight tracking loops, harnesses that forbid allocation:
+ * vpgs_icp_linearize with no allocation of any kind.  Its workgroup partial
+ * sums live in a static device array of the library (58 KiB: 512 rows of 29
+ * floats, enough for any n, as a pass has at most 512 workgroups), whose
+ * address on each device is looked up once by vpgs_create.  Arguments,
+ * results and errors are those of vpgs_icp_linearize (VPGS_EINVAL if a pass
+ * would need more rows than the array holds).  Every call on one device
+ * shares that device's array: calls that overlap on one device (on different
+ * streams, or from several threads) race and must be serialised by the
+ * caller.  Nothing needs clearing between calls. */
+int vpgs_icp_linearize_noalloc(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* src, int64_t n,
+                               const double* pose, float tau, float sigma, double* terms, void* stream);
+
 typedef struct {
   float tau;              /* correspondence threshold (map units) */
   float sigma;            /* kernel scale sigma_t of eq. 12 (kappa = sigma / 3) */

@@ -10,7 +10,7 @@ from .render import (Context, DecodeFn, RenderFn, Saved, anchor_stats, camera_st
                      decode_backward, decode_forward, distill_loss, expansion_sample, get_context, mapping_loss, render,
                      render_backward, render_views, RenderWindow, volume_loss)
 
-from .registration import (VoxelMap, icp_correspond, icp_linearize, icp_register,  # noqa: F401
+from .registration import (VoxelMap, icp_correspond, icp_linearize, icp_linearize_noalloc, icp_register,  # noqa: F401
                            voxel_downsample)
 
 __version__ = "0.1.0"

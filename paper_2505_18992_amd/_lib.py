@@ -181,6 +181,9 @@ SIGNATURES = {
     "vpgs_icp_linearize": (ctypes.c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_int64,
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_float, ctypes.c_float, c_void_p,
                                           c_void_p]),
+    "vpgs_icp_linearize_noalloc": (ctypes.c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_int64,
+                                                  ctypes.POINTER(ctypes.c_double), ctypes.c_float, ctypes.c_float,
+                                                  c_void_p, c_void_p]),
     "vpgs_icp_register": (ctypes.c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_int64,
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(IcpOpts), ctypes.POINTER(ctypes.c_double),

@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 
 #include "runtime.h"
@@ -529,6 +530,40 @@ Pose32 pose32_of(const double* P) {
 }  // namespace
 }  // namespace vpgs
 
+// Scratch of the allocation-free linearisation (vpgs_icp_linearize_noalloc):
+// the workgroup partial sums of one pass, at most kMaxLinBlocks rows of
+// kTerms floats (58 KiB).  Every device holds its own copy for the life of
+// the process.  Host code never passes this name: it uses the device address
+// that hipGetSymbolAddress returned on that device.
+constexpr size_t kLinScratchFloats = (size_t)512 * 29;
+static_assert(kLinScratchFloats == (size_t)vpgs::kMaxLinBlocks * vpgs::kTerms, "one row per linearisation workgroup");
+static __device__ __align__(256) float scratch[kLinScratchFloats];
+
+namespace vpgs {
+namespace {
+std::mutex g_scratch_mu;
+float* g_scratch[kMaxDevices] = {};  // device address of `scratch`, per device ordinal
+}  // namespace
+
+int init_scratch(vpgs_ctx* ctx) {
+  if (ctx->device < 0 || ctx->device >= kMaxDevices) return fail(ctx, VPGS_EUNSUPPORTED, "device %d", ctx->device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[ctx->device]) return VPGS_OK;
+  void* p = nullptr;
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  g_scratch[ctx->device] = static_cast<float*>(p);
+  return VPGS_OK;
+}
+
+namespace {
+float* scratch_of(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (device >= 0 && device < kMaxDevices) ? g_scratch[device] : nullptr;
+}
+}  // namespace
+}  // namespace vpgs
+
 using namespace vpgs;
 
 struct vpgs_voxel_map {
@@ -561,6 +596,34 @@ int check_points(vpgs_ctx* ctx, const float* p, int64_t n, float voxel) {
 
 int check_map(vpgs_ctx* ctx, const vpgs_voxel_map* m) {
   if (!m || m->ctx != ctx) return fail(ctx, VPGS_EINVAL, "voxel map of another context or NULL");
+  return VPGS_OK;
+}
+
+int check_linearize(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* src, int64_t n, const double* pose,
+                    float tau, float sigma, const double* terms) {
+  if (!ctx) return VPGS_EINVAL;
+  int rc = check_map(ctx, map);
+  if (rc) return rc;
+  if (n < 0 || n > 0x7fffffff) return fail(ctx, VPGS_EINVAL, "source count out of range");
+  if ((n > 0 && !src) || !terms) return fail(ctx, VPGS_EINVAL, "NULL source or output");
+  if (!pose || !finite_pose(pose)) return fail(ctx, VPGS_EINVAL, "NULL or non-finite pose");
+  if (!(tau > 0.0f) || !std::isfinite(tau) || !(sigma > 0.0f) || !std::isfinite(sigma))
+    return fail(ctx, VPGS_EINVAL, "tau and sigma must be positive");
+  return VPGS_OK;
+}
+
+// One linearisation pass and the FP64 sum of its workgroup partials
+// (partials: linearize_blocks(n) rows of kTerms floats).
+int launch_linearize(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* src, uint32_t n, const double* pose,
+                     float tau, float sigma, float* partials, double* terms, hipStream_t st) {
+  const uint32_t nb = linearize_blocks(n);
+  with_group(n, [&](auto g) {
+    constexpr int G = decltype(g)::value;
+    hipLaunchKernelGGL(linearize_kernel<G>, dim3(nb), dim3(kIcpBlock), 0, st, view_of(map), src, n,
+                       pose32_of(pose), (const IcpState*)nullptr, tau * tau, sigma / 3.0f, partials);
+  });
+  hipLaunchKernelGGL(reduce_terms_kernel, dim3(1), dim3(kIcpBlock), 0, st, partials, nb, terms);
+  HIP_TRY(hipGetLastError());
   return VPGS_OK;
 }
 
@@ -731,28 +794,30 @@ int vpgs_icp_correspond(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* s
 
 int vpgs_icp_linearize(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* src, int64_t n, const double* pose,
                        float tau, float sigma, double* terms, void* stream) {
-  if (!ctx) return VPGS_EINVAL;
-  int rc = check_map(ctx, map);
+  int rc = check_linearize(ctx, map, src, n, pose, tau, sigma, terms);
   if (rc) return rc;
-  if (n < 0 || n > 0x7fffffff) return fail(ctx, VPGS_EINVAL, "source count out of range");
-  if ((n > 0 && !src) || !terms) return fail(ctx, VPGS_EINVAL, "NULL source or output");
-  if (!pose || !finite_pose(pose)) return fail(ctx, VPGS_EINVAL, "NULL or non-finite pose");
-  if (!(tau > 0.0f) || !std::isfinite(tau) || !(sigma > 0.0f) || !std::isfinite(sigma))
-    return fail(ctx, VPGS_EINVAL, "tau and sigma must be positive");
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(hipSetDevice(ctx->device));
   const uint32_t nb = linearize_blocks((uint32_t)n);
   if ((rc = ensure(ctx, ctx->icp_ws, (size_t)nb * kTerms * 4 + 512))) return rc;
-  float* partials = static_cast<float*>(ctx->icp_ws.p);
   StageTimer timer(ctx, ST_ICP, st);
-  with_group((uint32_t)n, [&](auto g) {
-    constexpr int G = decltype(g)::value;
-    hipLaunchKernelGGL(linearize_kernel<G>, dim3(nb), dim3(kIcpBlock), 0, st, view_of(map), src, (uint32_t)n,
-                       pose32_of(pose), (const IcpState*)nullptr, tau * tau, sigma / 3.0f, partials);
-  });
-  hipLaunchKernelGGL(reduce_terms_kernel, dim3(1), dim3(kIcpBlock), 0, st, partials, nb, terms);
-  HIP_TRY(hipGetLastError());
-  return VPGS_OK;
+  return launch_linearize(ctx, map, src, (uint32_t)n, pose, tau, sigma, static_cast<float*>(ctx->icp_ws.p), terms, st);
+}
+
+int vpgs_icp_linearize_noalloc(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* src, int64_t n,
+                               const double* pose, float tau, float sigma, double* terms, void* stream) {
+  int rc = check_linearize(ctx, map, src, n, pose, tau, sigma, terms);
+  if (rc) return rc;
+  const uint32_t nb = linearize_blocks((uint32_t)n);
+  if ((size_t)nb * kTerms > kLinScratchFloats)
+    return fail(ctx, VPGS_EINVAL, "%u workgroup partials exceed the %zu-float scratch", nb, kLinScratchFloats);
+  float* partials = scratch_of(ctx->device);
+  if (!partials) return fail(ctx, VPGS_EHIP, "scratch of device %d not initialised", ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(ctx->device));
+  // every workgroup writes its whole row before the reduction reads it: the
+  // scratch needs no clearing
+  return launch_linearize(ctx, map, src, (uint32_t)n, pose, tau, sigma, partials, terms, st);
 }
 
 int vpgs_icp_register(vpgs_ctx* ctx, const vpgs_voxel_map* map, const float* src, int64_t n,

@@ -503,6 +503,12 @@ int vpgs_create(vpgs_ctx** out, int device) {
     delete ctx;
     return VPGS_EHIP;
   }
+  const int rc = init_scratch(ctx);
+  if (rc) {
+    (void)hipHostFree(ctx->h_pinned);
+    delete ctx;
+    return rc;
+  }
   *out = ctx;
   return VPGS_OK;
 }

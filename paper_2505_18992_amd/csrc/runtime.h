@@ -69,6 +69,12 @@ struct vpgs_ctx {
 
 namespace vpgs {
 
+constexpr int kMaxDevices = 64;
+
+// Looks up, once per device and with it current, the device address of the
+// allocation-free entry points' scratch array (icp.hip).
+int init_scratch(vpgs_ctx* ctx);
+
 // Records the message as the context's last error and returns code.
 int fail(vpgs_ctx* ctx, int code, const char* fmt, ...);
 // Grows b to at least `bytes` (hipFree + hipMalloc; contents are not kept).

@@ -12,7 +12,7 @@ from . import _lib
 from ._lib import check, load
 from .render import Context, _ptr, _stream, get_context
 
-__all__ = ["VoxelMap", "voxel_downsample", "icp_correspond", "icp_linearize", "icp_register"]
+__all__ = ["VoxelMap", "voxel_downsample", "icp_correspond", "icp_linearize", "icp_linearize_noalloc", "icp_register"]
 
 
 def _points(t: torch.Tensor, name: str) -> torch.Tensor:
@@ -93,6 +93,20 @@ def icp_linearize(vmap: VoxelMap, src: torch.Tensor, pose, tau: float, sigma: fl
     check(load().vpgs_icp_linearize(vmap.ctx.handle, vmap.handle, _ptr(src), int(src.shape[0]), _pose(pose),
                                     float(tau), float(sigma), _ptr(out), _stream()),
           vmap.ctx.handle, "vpgs_icp_linearize")
+    return out
+
+
+def icp_linearize_noalloc(vmap: VoxelMap, src: torch.Tensor, pose, tau: float, sigma: float,
+                          out: torch.Tensor) -> torch.Tensor:
+    """icp_linearize into a caller-given float64 [29] device tensor, with no
+    allocation in the library (its partial sums use a static per-device
+    scratch array, so overlapping calls on one device race)."""
+    _points(src, "src")
+    if out.dtype != torch.float64 or tuple(out.shape) != (29,) or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 [29] GPU tensor")
+    check(load().vpgs_icp_linearize_noalloc(vmap.ctx.handle, vmap.handle, _ptr(src), int(src.shape[0]), _pose(pose),
+                                            float(tau), float(sigma), _ptr(out), _stream()),
+          vmap.ctx.handle, "vpgs_icp_linearize_noalloc")
     return out
 
 

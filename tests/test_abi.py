@@ -69,6 +69,7 @@ def test_null_context_is_rejected_without_touching_the_device(lib):
     assert lib.vpgs_voxel_downsample(None, None, 0, 1.0, None, None, None) == _lib.VPGS_EINVAL
     assert lib.vpgs_icp_correspond(None, None, None, 0, None, 1.0, None, None, None) == _lib.VPGS_EINVAL
     assert lib.vpgs_icp_linearize(None, None, None, 0, None, 1.0, 1.0, None, None) == _lib.VPGS_EINVAL
+    assert lib.vpgs_icp_linearize_noalloc(None, None, None, 0, None, 1.0, 1.0, None, None) == _lib.VPGS_EINVAL
     assert lib.vpgs_icp_register(None, None, None, 0, None, None, None, None, None, None) == _lib.VPGS_EINVAL
     assert lib.vpgs_create(None, 0) == _lib.VPGS_EINVAL
     assert lib.vpgs_last_error(None) == b"NULL context"
