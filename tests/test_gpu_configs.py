@@ -118,6 +118,10 @@ def test_c5_street_view():
     got = dict(zip(["means", "log_scales", "quats", "opacities", "colors"], [np_(t) for t in grads[s]]))
     got["pose"] = np_(d_pose)[v]
     print("grad report", assert_grads(got, G, S), flush=True)
+    # the oracle's own float32 evaluation against FP64 on the same crops: how
+    # much of the gate an FP32 forward of the definition uses by itself
+    G32, _ = oracle.grad(g, cam, *[x.astype(np.float64) for x in w[v]], fp32=True)
+    print("oracle fp32 report", assert_grads({k: G32[k] for k in got}, G, S), flush=True)
 
 
 def test_c3_decode_full_size():
