@@ -205,7 +205,7 @@ def time_expansion(sets, gw, cams, vset, cfg, win, steps, k=10, n_samples=4096):
     from paper_2505_18992_amd import RenderWindow, anchor_stats, expansion_sample, get_context
     ctx = get_context(0)
     ewin = RenderWindow(sets, cams, vset, tile=(cfg["tile_w"], cfg["tile_h"]), persistent=cfg["persistent"],
-                        use_graph=False, pair_capacity=cfg["pair_capacity"])
+                        use_graph=False, pair_capacity=cfg["pair_capacity"], lds_batch=cfg["lds_batch"])
     for v in range(len(cams)):
         for dst, src in zip(ewin.grad_out[v], gw[v]):
             dst.copy_(src)
@@ -444,9 +444,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c4-1200")
-    ap.add_argument("--tile", default="32x8", help="WxH, or auto for the window's search over shapes")
-    ap.add_argument("--persistent", type=int, default=0,
+    ap.add_argument("--tile", default="auto", help="WxH, or auto for the window's search over shapes")
+    ap.add_argument("--persistent", type=int, default=-1,
                     help="persistent compositing workgroups: 0 one per tile, -1 search")
+    ap.add_argument("--lds-batch", type=int, default=0, help="entries per compositing batch, 0 search")
+    ap.add_argument("--tune-cache", default=os.path.join(os.environ.get("TMPDIR", "/tmp"), "vpgs_tune.json"),
+                    help="JSON tuning cache of the window's search ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-one-view", action="store_true",
                     help="skip the one-view-per-launch comparison (profiling runs: it launches the same kernels)")
@@ -477,10 +480,12 @@ def main():
 
     # the mapping-window launch: all views bound, tuned, captured in HIP graphs
     t0 = time.perf_counter()
-    win = RenderWindow(sets, cams, vset, tile=tile, persistent=args.persistent, use_graph=True)
+    win = RenderWindow(sets, cams, vset, tile=tile, persistent=args.persistent, use_graph=True,
+                       lds_batch=args.lds_batch, tune_cache=args.tune_cache or None)
     cfg = win.config()
-    log(f"[bench] window ready in {time.perf_counter() - t0:.1f} s: tile {cfg['tile_w']}x{cfg['tile_h']}, "
-        f"persistent {cfg['persistent']}, pair capacity {cfg['pair_capacity']}")
+    t_tune = time.perf_counter() - t0
+    log(f"[bench] window ready in {t_tune:.1f} s: tile {cfg['tile_w']}x{cfg['tile_h']}, "
+        f"persistent {cfg['persistent']}, lds batch {cfg['lds_batch']}, pair capacity {cfg['pair_capacity']}")
     for v in range(nv):
         for dst, src in zip(win.grad_out[v], gw[v]):
             dst.copy_(src)
@@ -503,7 +508,7 @@ def main():
     # per-stage HIP-event timing: the same configuration launched without the
     # graph (events recorded on the launch stream around every stage)
     twin = RenderWindow(sets, cams, vset, tile=(cfg["tile_w"], cfg["tile_h"]), persistent=cfg["persistent"],
-                        use_graph=False, pair_capacity=cfg["pair_capacity"])
+                        use_graph=False, pair_capacity=cfg["pair_capacity"], lds_batch=cfg["lds_batch"])
     for v in range(nv):
         for dst, src in zip(twin.grad_out[v], gw[v]):
             dst.copy_(src)
@@ -530,12 +535,14 @@ def main():
     def one_view_pass():
         for v in range(nv):
             outs, saved = render([sets[vset[v]]], [cams[v]], [0], tile=(cfg["tile_w"], cfg["tile_h"]),
-                                 pair_capacity=per_view_caps[v])
+                                 pair_capacity=per_view_caps[v], lds_batch=cfg["lds_batch"],
+                                 grid_ctas=cfg["persistent"])
             render_backward(saved, [gw[v]])
             saved.close()
     if not args.no_one_view:
         for v in range(nv):
-            outs, saved = render([sets[vset[v]]], [cams[v]], [0], tile=(cfg["tile_w"], cfg["tile_h"]))
+            outs, saved = render([sets[vset[v]]], [cams[v]], [0], tile=(cfg["tile_w"], cfg["tile_h"]),
+                                 lds_batch=cfg["lds_batch"], grid_ctas=cfg["persistent"])
             per_view_caps.append(int(saved.stats()["n_pairs"] * 1.25) + 4096)
             saved.close()
         one_view_pass()
@@ -601,7 +608,8 @@ def main():
                    "launch": "one HIP graph per forward and per backward over all views"},
         "blends_per_sec": B / (ms_step * 1e-3),
         "counts": {"pairs": P, "evaluated": E, "blended": B},
-        "window": {k: cfg[k] for k in ("tile_w", "tile_h", "persistent", "pair_capacity")},
+        "window": dict({k: cfg[k] for k in ("tile_w", "tile_h", "persistent", "lds_batch", "pair_capacity")},
+                       tune_seconds=t_tune, tune_cache=args.tune_cache or None),
         "one_view_per_launch": None if ms_per_view_launch is None else
         {"ms_for_all_views": ms_per_view_launch, "views_per_sec": nv / (ms_per_view_launch * 1e-3),
          "batched_speedup": ms_per_view_launch / ms_step},

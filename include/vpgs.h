@@ -35,7 +35,9 @@
  *   - Calls are asynchronous on the given HIP stream (hipStream_t passed as
  *     void*; NULL = the default stream) unless stated otherwise.
  *   - Ownership: the caller owns every input and output buffer.  The library
- *     owns its workspace and the saved-state handles (until released).
+ *     owns its workspace (allocated through the caller's callbacks when
+ *     vpgs_create was given them) and the saved-state handles (until
+ *     released).
  *   - Errors: every entry point returns a status code; no exception crosses
  *     the ABI.  Arguments are validated on the host before any launch: an
  *     invalid argument returns VPGS_EINVAL and enqueues nothing.
@@ -111,15 +113,29 @@ typedef struct {
 } vpgs_gauss_buffers;
 typedef vpgs_gauss_buffers vpgs_gauss_grads;
 
-/* Render options.  Zero fields take defaults (16x16 tiles, automatic pair
- * capacity).  tile_w x tile_h must be one of the compiled shapes
- * 16x16, 16x8, 8x8, 32x8 (else VPGS_EUNSUPPORTED).  pair_capacity = 0 sizes the
- * pair list exactly (one host synchronisation per forward); > 0 fixes it (no
- * synchronisation; an overflow is reported as VPGS_ECAPACITY by
- * vpgs_saved_stats and the outputs of that call are invalid). */
+/* Render options.  Zero fields take defaults (16x16 tiles, one LDS batch per
+ * tile's pixel count, one compositing workgroup per tile, automatic pair
+ * capacity).
+ *   tile_w x tile_h  one of the compiled shapes 16x16, 16x8, 8x8, 32x8.
+ *   lds_batch        Gaussian entries staged in LDS per compositing batch:
+ *                    half, once or twice the tile's pixel count, a multiple
+ *                    of 64 (16x16 and 32x8: 128, 256, 512; 16x8: 64, 128,
+ *                    256; 8x8: 64, 128).  Any other value: VPGS_EUNSUPPORTED.
+ *   grid_ctas        0: one compositing workgroup per tile; > 0 (at most
+ *                    65536): that many persistent workgroups taking tiles
+ *                    from a queue, longest list first.
+ *   pair_capacity    0 sizes the pair list exactly (one host synchronisation
+ *                    per forward); > 0 fixes it (no synchronisation; an
+ *                    overflow is reported as VPGS_ECAPACITY by
+ *                    vpgs_saved_stats and the outputs of that call are
+ *                    invalid).
+ * The images do not depend on any of these (the forward is bit-identical
+ * across them); the backward's gradients differ only in the order of their
+ * floating-point atomic sums. */
 typedef struct {
   int32_t tile_w, tile_h;
-  int32_t reserved0, reserved1;
+  int32_t lds_batch;
+  int32_t grid_ctas;
   int64_t pair_capacity;
 } vpgs_render_opts;
 
@@ -135,14 +151,22 @@ typedef struct {
   int64_t n_pixels;
   int32_t overflow;    /* 1 if the pair list overflowed */
   int32_t tile_w, tile_h;
-  int32_t reserved;
+  int32_t lds_batch;   /* entries staged per compositing batch */
 } vpgs_stats;
 
 /* ---- context ------------------------------------------------------------- */
 
-/* Create a context on HIP device `device`.  The context owns a grow-only
- * workspace; it is freed by vpgs_destroy. */
-int vpgs_create(vpgs_ctx** out, int device);
+/* Create a context on HIP device `device`.  The context keeps a grow-only
+ * device workspace (the forward's records, pair lists, sort buffers, hit
+ * masks and gradient accumulators, and the scratch of the other calls),
+ * released by vpgs_destroy.  With alloc and free_ given (both or neither,
+ * else VPGS_EINVAL), every workspace block comes from alloc(bytes, user) --
+ * device memory, 256-byte aligned, NULL if it cannot -- and goes back
+ * through free_(ptr, user), e.g. a framework's caching allocator; the library
+ * synchronises the device before handing a block back, so a caller may
+ * recycle it at once.  With neither, it uses hipMalloc / hipFree. */
+int vpgs_create(vpgs_ctx** out, int device, void* (*alloc)(size_t bytes, void* user),
+                void (*free_)(void* ptr, void* user), void* user);
 int vpgs_destroy(vpgs_ctx* ctx);
 const char* vpgs_status_string(int status);
 /* Text of the last error on this context (valid until the next call). */
@@ -207,12 +231,25 @@ int vpgs_saved_release(vpgs_ctx* ctx, vpgs_saved* saved);
 
 /* A window binds every buffer of a repeated multi-view forward+backward (the
  * keyframes of a mapping window, or the views of several submaps) once, picks
- * the tile shape and compositing mode with a timed search on the actual
- * inputs, and captures the launch sequence of all views in two HIP graphs:
+ * the tile shape, LDS batch and compositing grid with a timed search on the
+ * actual inputs, and captures the launch sequence of all views in two HIP
+ * graphs:
  * the forward (projection, binning, sort, ranges, forward compositing) and
  * the backward (backward compositing, projection backward, pose reduction).
  * A run is one graph launch per part; the pair list has a fixed capacity (no
- * host synchronisation), and an overflow is reported by vpgs_window_stats. */
+ * host synchronisation), and an overflow is reported by vpgs_window_stats.
+ *
+ * The search times every candidate over tune_reps runs of the whole forward
+ * and backward on the bound inputs: first each tile shape with each
+ * compositing grid (one workgroup per tile, or 2, 4 or 8 persistent
+ * workgroups per compute unit) at one batch per tile's pixel count, then the
+ * other LDS batch sizes of the best shape and grid.  Fields given in opts
+ * are not searched.  With tune_cache set, a result stored under the same
+ * key -- the device (architecture name and compute units), the number of
+ * views and their sizes, and ceil(log2) of the (view, Gaussian) record count
+ * -- is taken without searching, and a new search result is written to the
+ * file (a JSON object of entries; other keys are kept).  A cache that cannot
+ * be read or parsed is ignored; one that cannot be written is reported. */
 typedef struct {
   int32_t tile_w, tile_h;   /* 0 = chosen by the search */
   int32_t persistent;       /* -1 = chosen by the search; 0 = one workgroup per tile;
@@ -220,7 +257,8 @@ typedef struct {
   int32_t use_graph;        /* 1 = capture in a HIP graph (default); 0 = launch eagerly */
   int64_t pair_capacity;    /* 0 = pairs measured at creation plus 25% headroom */
   int32_t tune_reps;        /* timed runs per candidate in the search (0 = 3) */
-  int32_t reserved;
+  int32_t lds_batch;        /* 0 = chosen by the search; else as in vpgs_render_opts */
+  const char* tune_cache;   /* host path of a JSON tuning cache, or NULL for none */
 } vpgs_window_opts;
 
 /* Inputs and outputs as in vpgs_render_forward / vpgs_render_backward, all

@@ -53,21 +53,21 @@ class GaussBuffers(ctypes.Structure):
 
 
 class RenderOpts(ctypes.Structure):
-    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("reserved1", ctypes.c_int32), ("pair_capacity", ctypes.c_int64)]
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("lds_batch", ctypes.c_int32),
+                ("grid_ctas", ctypes.c_int32), ("pair_capacity", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("n_records", ctypes.c_int64), ("n_visible", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
                 ("n_evaluated", ctypes.c_int64), ("n_blended", ctypes.c_int64), ("pair_capacity", ctypes.c_int64),
                 ("n_tiles", ctypes.c_int64), ("n_pixels", ctypes.c_int64), ("overflow", ctypes.c_int32),
-                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("lds_batch", ctypes.c_int32)]
 
 
 class WindowOpts(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("pair_capacity", ctypes.c_int64), ("tune_reps", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("lds_batch", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
 
 
 class Anchors(ctypes.Structure):
@@ -118,7 +118,7 @@ class IcpResult(ctypes.Structure):
 
 # every entry point of include/vpgs.h, with its ctypes signature
 SIGNATURES = {
-    "vpgs_create": (ctypes.c_int, [ctypes.POINTER(c_void_p), ctypes.c_int]),
+    "vpgs_create": (ctypes.c_int, [ctypes.POINTER(c_void_p), ctypes.c_int, c_void_p, c_void_p, c_void_p]),
     "vpgs_destroy": (ctypes.c_int, [c_void_p]),
     "vpgs_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "vpgs_last_error": (ctypes.c_char_p, [c_void_p]),
@@ -207,6 +207,11 @@ def load():
             fn.argtypes = args
         _LIB = L
     return _LIB
+
+
+# vpgs_create's workspace allocator callbacks
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class VpgsError(RuntimeError):

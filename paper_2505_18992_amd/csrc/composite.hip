@@ -17,6 +17,9 @@
 // bits of the entries that reach the wavefront's quadrant, so the backward
 // does not test them again).  Per-Gaussian gradients are reduced across the
 // wavefront before one set of atomic adds per (wavefront, Gaussian).
+//
+// A batch holds NB entries: half, once or twice the tile's pixel count (a
+// multiple of 64), so each thread stages at most two entries per batch.
 #include "internal.h"
 
 namespace vpgs {
@@ -55,7 +58,7 @@ __device__ __forceinline__ Falloff falloff(const float4 A, const float4 E, float
 }
 
 // Hit lists are padded to a multiple of kGroup entries with a sentinel slot
-// (index BS, staged once per workgroup) whose exponent is -inf, so alpha is 0
+// (index NB, staged once per workgroup) whose exponent is -inf, so alpha is 0
 // there and nothing is blended; the per-pixel loops then run whole groups
 // without per-entry bounds tests, and the forward checks for early
 // termination between groups.
@@ -63,11 +66,11 @@ constexpr int kGroup = 8;
 constexpr float kLog2AlphaMin = -7.99435343685885793769f;  // log2(1/255)
 constexpr float kNegInf = -__builtin_inff();
 
-template <int TW, int TH>
+template <int TW, int TH, int NB>
 struct FwdShared {
-  float4 A[TW * TH + 1], E[TW * TH + 1], C[TW * TH + 1];
-  float2 V[TW * TH];  // the quadrant test's vertex factors (ra, rc) of the record
-  uint16_t hits[(TW * TH) / 64][TW * TH + kGroup];  // per wavefront: staged entries that reach its quadrant
+  float4 A[NB + 1], E[NB + 1], C[NB + 1];
+  float2 V[NB];  // the quadrant test's vertex factors (ra, rc) of the record
+  uint16_t hits[(TW * TH) / 64][NB + kGroup];  // per wavefront: staged entries that reach its quadrant
 };
 
 // Each wavefront owns an 8x8 quadrant of its tile (lane -> (lane % 8,
@@ -121,20 +124,20 @@ struct Quadrant {
 };
 
 // Compacts the staged entries [0, n) that reach the wavefront's quadrant
-// into list[], in staging order, pads it with the sentinel index BS to a
+// into list[], in staging order, pads it with the sentinel index NB to a
 // multiple of kGroup and returns the number of hits (the same in every
 // lane); lane 0 also stores the batch's hit bits (one 64-bit word per 64
 // entries) in mask_out, from which the backward rebuilds the list.  Lane l
 // tests entries l, l + 64, ...; a ballot and a lane-prefix count give each
 // hit its slot.  All lanes of the wavefront must be active; the list is read
 // after the next workgroup barrier.
-template <int BS, int TW, int TH>
+template <int NB, int TW, int TH>
 __device__ __forceinline__ int wave_hits(const float4* A, const float4* E, const float2* V, int n,
                                          const Quadrant<TW, TH>& q, uint16_t* list, uint64_t* mask_out) {
   const int lane = threadIdx.x & 63;
   int count = 0;
 #pragma unroll
-  for (int k = 0; k < BS / 64; ++k) {
+  for (int k = 0; k < NB / 64; ++k) {
     const int e = k * 64 + lane;
     const bool hit = e < n && q.reaches(A[e], E[e], V[e]);
     const uint64_t m = __ballot(hit);
@@ -143,19 +146,19 @@ __device__ __forceinline__ int wave_hits(const float4* A, const float4* E, const
     if (lane == 0) mask_out[k] = m;
     count += __popcll(m);
   }
-  if (lane < ((count + kGroup - 1) & ~(kGroup - 1)) - count) list[count + lane] = (uint16_t)BS;
+  if (lane < ((count + kGroup - 1) & ~(kGroup - 1)) - count) list[count + lane] = (uint16_t)NB;
   return count;
 }
 
 // The backward's list of a batch from the forward's masks: the entries
 // below n whose bit is set, in descending order.  All lanes of the
 // wavefront must be active.
-template <int BS>
+template <int NB>
 __device__ __forceinline__ int mask_hits_desc(const uint64_t* mask, int n, uint16_t* list) {
   const int lane = threadIdx.x & 63;
   int count = 0;
 #pragma unroll
-  for (int k = BS / 64 - 1; k >= 0; --k) {
+  for (int k = NB / 64 - 1; k >= 0; --k) {
     const int lo = k * 64;
     uint64_t m = mask[k];
     if (n <= lo) m = 0ull;
@@ -168,23 +171,26 @@ __device__ __forceinline__ int mask_hits_desc(const uint64_t* mask, int n, uint1
 }
 
 // The per-wavefront hit masks of every (tile, batch) that the forward
-// composites: BS/64 words of 64 bits per wavefront.  The batches of a tile
-// take consecutive slots from first_slot = start / BS + tile (start = the
-// tile's first pair): the slots of consecutive tiles do not overlap, and
-// every slot is below capacity / BS + n_tiles.
-template <int BS>
+// composites: NB/64 words of 64 bits per wavefront (WV wavefronts per
+// tile).  The batches of a tile take consecutive slots from first_slot =
+// start / NB + tile (start = the tile's first pair): the slots of
+// consecutive tiles do not overlap, and every slot is below capacity / NB +
+// n_tiles.
+template <int NB, int WV>
 __device__ __forceinline__ size_t batch_mask_index(uint32_t start, uint32_t tile, int batch, int wave) {
-  const size_t slot = (size_t)(start / BS) + tile + (size_t)batch;
-  return (slot * (BS / 64) + wave) * (BS / 64);
+  const size_t slot = (size_t)(start / NB) + tile + (size_t)batch;
+  return (slot * WV + wave) * (NB / 64);
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int NB>
 __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab, const float4* __restrict__ recs,
                                              const uint2* __restrict__ ranges,
                                              const uint32_t* __restrict__ vals, float* __restrict__ T_final,
                                              uint32_t* __restrict__ n_contrib, uint64_t* __restrict__ masks,
-                                             uint32_t tile, FwdShared<TW, TH>& sh, uint32_t& ne, uint32_t& nb) {
-  constexpr int BS = TW * TH;
+                                             uint32_t tile, FwdShared<TW, TH, NB>& sh, uint32_t& ne, uint32_t& nb) {
+  constexpr int BS = TW * TH;     // threads: one per pixel
+  constexpr int WV = BS / 64;     // wavefronts per tile
+  constexpr int PER = NB > BS ? NB / BS : 1;  // entries each thread stages
   const ViewDesc& V = tab->views[view_of_tile(tab, tile)];
   const uint32_t lt = tile - V.tile_base;
   const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
@@ -201,29 +207,43 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
 
   // batch i + 1 is loaded into registers while batch i is tested and
   // composited, so a long list does not wait on each batch's loads
-  float4 pA = make_float4(0.f, 0.f, 0.f, 0.f), pR = pA, pC = pA;
-  float2 pV = make_float2(0.f, 0.f);
-  if (rg.x + threadIdx.x < rg.y) {
-    const float4* r = recs + rec_slot(vals[rg.x + threadIdx.x], 0);
-    pA = r[0]; pR = r[1]; pC = r[2]; pV = reinterpret_cast<const float2*>(r + 3)[1];
+  float4 pA[PER], pR[PER], pC[PER];
+  float2 pV[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    pA[k] = pR[k] = pC[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    pV[k] = make_float2(0.f, 0.f);
+    const uint32_t e = (uint32_t)(k * BS) + threadIdx.x;
+    if (e < (uint32_t)NB && rg.x + e < rg.y) {
+      const float4* r = recs + rec_slot(vals[rg.x + e], 0);
+      pA[k] = r[0]; pR[k] = r[1]; pC[k] = r[2]; pV[k] = reinterpret_cast<const float2*>(r + 3)[1];
+    }
   }
-  for (uint32_t start = rg.x; start < rg.y; start += BS) {
+  for (uint32_t start = rg.x; start < rg.y; start += NB) {
     if (__syncthreads_count(done) == BS) break;
-    if (start + threadIdx.x < rg.y) {
-      sh.A[threadIdx.x] = pA;
-      sh.E[threadIdx.x] = stage_exponent(pA, pR);
-      sh.C[threadIdx.x] = pC;
-      sh.V[threadIdx.x] = pV;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const uint32_t e = (uint32_t)(k * BS) + threadIdx.x;
+      if (e < (uint32_t)NB && start + e < rg.y) {
+        sh.A[e] = pA[k];
+        sh.E[e] = stage_exponent(pA[k], pR[k]);
+        sh.C[e] = pC[k];
+        sh.V[e] = pV[k];
+      }
     }
     __syncthreads();
-    const uint32_t nidx = start + BS + threadIdx.x;
-    if (nidx < rg.y) {
-      const float4* r = recs + rec_slot(vals[nidx], 0);
-      pA = r[0]; pR = r[1]; pC = r[2]; pV = reinterpret_cast<const float2*>(r + 3)[1];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const uint32_t e = (uint32_t)(k * BS) + threadIdx.x;
+      const uint32_t nidx = start + NB + e;
+      if (e < (uint32_t)NB && nidx < rg.y) {
+        const float4* r = recs + rec_slot(vals[nidx], 0);
+        pA[k] = r[0]; pR[k] = r[1]; pC[k] = r[2]; pV[k] = reinterpret_cast<const float2*>(r + 3)[1];
+      }
     }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    uint64_t* wm = masks + batch_mask_index<BS>(rg.x, tile, (int)((start - rg.x) / BS), wave);
-    const int nhit = wave_hits<BS>(sh.A, sh.E, sh.V, (int)min((uint32_t)BS, rg.y - start), q, hits, wm);
+    uint64_t* wm = masks + batch_mask_index<NB, WV>(rg.x, tile, (int)((start - rg.x) / NB), wave);
+    const int nhit = wave_hits<NB>(sh.A, sh.E, sh.V, (int)min((uint32_t)NB, rg.y - start), q, hits, wm);
     __syncthreads();
     const uint32_t base = start - rg.x + 1u;
     for (int g = 0; g < nhit && __ballot(!done) != 0ull; g += kGroup) {
@@ -292,27 +312,29 @@ __device__ __forceinline__ uint32_t next_tile(uint32_t* queue, uint32_t* slot) {
 // past the last tile.
 // (the second bound keeps the forward within 64 VGPRs: eight wavefronts per
 // SIMD)
-template <int TW, int TH>
+template <int TW, int TH, int NB>
 __global__ void __launch_bounds__(TW * TH, 8) composite_forward_kernel(
     const CallTables* __restrict__ tab, const float4* __restrict__ recs, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals, float* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
     uint64_t* __restrict__ masks, const uint32_t* __restrict__ order, Counters* __restrict__ cnt,
     uint32_t* __restrict__ queue, uint32_t n_tiles) {
-  __shared__ FwdShared<TW, TH> sh;
+  __shared__ FwdShared<TW, TH, NB> sh;
   __shared__ uint32_t slot;
   uint32_t ne = 0, nb = 0;
   if (threadIdx.x == 0) {  // the sentinel slot (read after the first staging barrier)
-    sh.A[TW * TH] = make_float4(0.f, 0.f, 0.f, 0.f);
-    sh.E[TW * TH] = make_float4(0.f, 0.f, 0.f, kNegInf);
-    sh.C[TW * TH] = make_float4(0.f, 0.f, 0.f, 0.f);
+    sh.A[NB] = make_float4(0.f, 0.f, 0.f, 0.f);
+    sh.E[NB] = make_float4(0.f, 0.f, 0.f, kNegInf);
+    sh.C[NB] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   if (queue == nullptr) {
     const uint32_t tile = order[blockIdx.x];
-    if (tile < n_tiles) forward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, masks, tile, sh, ne, nb);
+    if (tile < n_tiles)
+      forward_tile<TW, TH, NB>(tab, recs, ranges, vals, T_final, n_contrib, masks, tile, sh, ne, nb);
   } else {
     for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot)) {
       const uint32_t tile = order[t];
-      if (tile < n_tiles) forward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, masks, tile, sh, ne, nb);
+      if (tile < n_tiles)
+        forward_tile<TW, TH, NB>(tab, recs, ranges, vals, T_final, n_contrib, masks, tile, sh, ne, nb);
     }
   }
   flush_counts(ne, nb, cnt);
@@ -377,21 +399,22 @@ __device__ __forceinline__ bool scatter_writer(int lane) {
 static_assert((uint64_t)VPGS_MAX_RECORDS * kNumAcc * sizeof(float) < (1ull << 32),
               "accumulator rows addressed by 32-bit byte offsets");
 
-template <int TW, int TH>
+template <int TW, int TH, int NB>
 struct BwdShared {
-  float4 A[TW * TH + 1], E[TW * TH + 1], C[TW * TH + 1];  // C = (r, g, b, bits of the accumulator row offset)
-  uint16_t hits[(TW * TH) / 64][TW * TH + kGroup];  // per wavefront, descending
+  float4 A[NB + 1], E[NB + 1], C[NB + 1];  // C = (r, g, b, bits of the accumulator row offset)
+  uint16_t hits[(TW * TH) / 64][NB + kGroup];  // per wavefront, descending
   uint32_t maxlast[(TW * TH) / 64];
 };
 
-template <int TW, int TH>
+template <int TW, int TH, int NB>
 __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab, const float4* __restrict__ recs,
                                               const uint2* __restrict__ ranges,
                                               const uint32_t* __restrict__ vals, const float* __restrict__ T_final,
                                               const uint32_t* __restrict__ n_contrib, float* __restrict__ acc,
                                               const uint64_t* __restrict__ masks, uint32_t tile,
-                                              BwdShared<TW, TH>& sh) {
-  constexpr int BS = TW * TH;
+                                              BwdShared<TW, TH, NB>& sh) {
+  constexpr int BS = TW * TH;  // threads: one per pixel
+  constexpr int WV = BS / 64;
   const ViewDesc& V = tab->views[view_of_tile(tab, tile)];
   const uint32_t lt = tile - V.tile_base;
   const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
@@ -424,35 +447,36 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
   __syncthreads();
   uint32_t max_last = 0;
 #pragma unroll
-  for (int w = 0; w < BS / 64; ++w) max_last = max(max_last, sh.maxlast[w]);
+  for (int w = 0; w < WV; ++w) max_last = max(max_last, sh.maxlast[w]);
 
   float S = 0.f;  // sum over blended entries behind the current one of alpha T f
   // the forward's batches, last first (their hit masks are the forward's)
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (int b = (int)((max_last + BS - 1) / BS) - 1; b >= 0; --b) {
-    const int begin = b * BS;
-    const int end = min(begin + BS, (int)max_last);
+  for (int b = (int)((max_last + NB - 1) / NB) - 1; b >= 0; --b) {
+    const int begin = b * NB;
+    const int end = min(begin + NB, (int)max_last);
     __syncthreads();
-    {
-      const int j = begin + (int)threadIdx.x;
+#pragma unroll
+    for (int e = (int)threadIdx.x; e < NB; e += BS) {
+      const int j = begin + e;
       if (j < end) {
         const uint32_t rec = vals[rg.x + (uint32_t)j];
         const float4* r = recs + rec_slot(rec, 0);
         const float4 A = r[0];
         const float4 c = r[2];
-        sh.A[threadIdx.x] = A;
-        sh.E[threadIdx.x] = stage_exponent(A, r[1]);
+        sh.A[e] = A;
+        sh.E[e] = stage_exponent(A, r[1]);
         // the record's accumulator row as a byte offset (below 2^32: the
         // host bounds the records by VPGS_MAX_RECORDS), carried in the
         // colour's free lane
-        sh.C[threadIdx.x] = make_float4(c.x, c.y, c.z, __uint_as_float(rec * (uint32_t)(kNumAcc * sizeof(float))));
+        sh.C[e] = make_float4(c.x, c.y, c.z, __uint_as_float(rec * (uint32_t)(kNumAcc * sizeof(float))));
       }
     }
     __syncthreads();
     // entries of this wavefront: those before its own last blended one
     uint16_t* hits = sh.hits[wave];
-    const int nhit =
-        mask_hits_desc<BS>(masks + batch_mask_index<BS>(rg.x, tile, b, wave), min(end, (int)wave_last) - begin, hits);
+    const int nhit = mask_hits_desc<NB>(masks + batch_mask_index<NB, WV>(rg.x, tile, b, wave),
+                                        min(end, (int)wave_last) - begin, hits);
     __syncthreads();
     const int last_in_batch = (int)last - begin;  // this pixel's entries are the slots below it
     for (int i = 0; i < nhit; ++i) {
@@ -497,47 +521,49 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
   }
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int NB>
 __global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
     const CallTables* __restrict__ tab, const float4* __restrict__ recs, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals,
     const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib, float* __restrict__ acc,
     const uint64_t* __restrict__ masks, const uint32_t* __restrict__ order, uint32_t* __restrict__ queue,
     uint32_t n_tiles) {
-  __shared__ BwdShared<TW, TH> sh;
+  __shared__ BwdShared<TW, TH, NB> sh;
   __shared__ uint32_t slot;
   if (threadIdx.x == 0) {  // the sentinel slot (read after the first staging barrier)
-    sh.A[TW * TH] = make_float4(0.f, 0.f, 0.f, 0.f);
-    sh.E[TW * TH] = make_float4(0.f, 0.f, 0.f, kNegInf);
+    sh.A[NB] = make_float4(0.f, 0.f, 0.f, 0.f);
+    sh.E[NB] = make_float4(0.f, 0.f, 0.f, kNegInf);
   }
   if (queue == nullptr) {
     const uint32_t tile = order[blockIdx.x];
-    if (tile < n_tiles) backward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, acc, masks, tile, sh);
+    if (tile < n_tiles)
+      backward_tile<TW, TH, NB>(tab, recs, ranges, vals, T_final, n_contrib, acc, masks, tile, sh);
   } else {
     for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot)) {
       const uint32_t tile = order[t];
-      if (tile < n_tiles) backward_tile<TW, TH>(tab, recs, ranges, vals, T_final, n_contrib, acc, masks, tile, sh);
+      if (tile < n_tiles)
+        backward_tile<TW, TH, NB>(tab, recs, ranges, vals, T_final, n_contrib, acc, masks, tile, sh);
     }
   }
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int NB>
 hipError_t launch_fwd_t(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb, const uint2* ranges,
                         const uint32_t* vals, const uint32_t* order, float* T_final, uint32_t* n_contrib,
                         uint64_t* masks, Counters* cnt, uint32_t* queue, uint32_t blocks, hipStream_t s) {
   const uint32_t grid = queue ? blocks : h.n_tiles;
-  hipLaunchKernelGGL((composite_forward_kernel<TW, TH>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.rec,
+  hipLaunchKernelGGL((composite_forward_kernel<TW, TH, NB>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.rec,
                      ranges, vals, T_final, n_contrib, masks, order, cnt, queue, h.n_tiles);
   return hipGetLastError();
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int NB>
 hipError_t launch_bwd_t(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb, const uint2* ranges,
                         const uint32_t* vals, const uint32_t* order, const float* T_final,
                         const uint32_t* n_contrib, const uint64_t* masks, float* acc, uint32_t* queue,
                         uint32_t blocks, hipStream_t s) {
   const uint32_t grid = queue ? blocks : h.n_tiles;
-  hipLaunchKernelGGL((composite_backward_kernel<TW, TH>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.rec,
+  hipLaunchKernelGGL((composite_backward_kernel<TW, TH, NB>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.rec,
                      ranges, vals, T_final, n_contrib, acc, masks, order, queue, h.n_tiles);
   return hipGetLastError();
 }
@@ -548,20 +574,32 @@ bool tile_shape_supported(int tw, int th) {
   return (tw == 16 && th == 16) || (tw == 16 && th == 8) || (tw == 8 && th == 8) || (tw == 32 && th == 8);
 }
 
-size_t hit_mask_bytes(uint32_t capacity, uint32_t n_tiles, int tile_w, int tile_h) {
-  const size_t bs = (size_t)tile_w * tile_h, words = (bs / 64) * (bs / 64);
-  return ((size_t)capacity / bs + n_tiles + 1) * words * sizeof(uint64_t);
+bool lds_batch_supported(int tw, int th, int nb) {
+  const int px = tw * th;
+  return tile_shape_supported(tw, th) && nb % 64 == 0 && (2 * nb == px || nb == px || nb == 2 * px);
 }
+
+size_t hit_mask_bytes(uint32_t capacity, uint32_t n_tiles, int tile_w, int tile_h, int lds_batch) {
+  const size_t nb = (size_t)lds_batch, words = ((size_t)tile_w * tile_h / 64) * (nb / 64);
+  return ((size_t)capacity / nb + n_tiles + 1) * words * sizeof(uint64_t);
+}
+
+// The built (tile shape, batch) instances: batches of half, once and twice
+// the tile's pixels where that is a multiple of 64.
+#define VPGS_SHAPES(X)                                                             \
+  X(16, 16, 128) X(16, 16, 256) X(16, 16, 512) X(16, 8, 64) X(16, 8, 128) X(16, 8, 256) \
+  X(8, 8, 64) X(8, 8, 128) X(32, 8, 128) X(32, 8, 256) X(32, 8, 512)
 
 hipError_t launch_composite_forward(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb,
                                     const uint2* ranges, const uint32_t* vals, const uint32_t* order,
                                     float* T_final, uint32_t* n_contrib, uint64_t* masks, Counters* cnt, int tile_w,
-                                    int tile_h, uint32_t* queue, uint32_t blocks, hipStream_t s) {
+                                    int tile_h, int lds_batch, uint32_t* queue, uint32_t blocks, hipStream_t s) {
   if (h.n_tiles == 0) return hipSuccess;
-#define VPGS_FWD(TW, TH) \
-  if (tile_w == TW && tile_h == TH) \
-    return launch_fwd_t<TW, TH>(d_tab, h, pb, ranges, vals, order, T_final, n_contrib, masks, cnt, queue, blocks, s);
-  VPGS_FWD(16, 16) VPGS_FWD(16, 8) VPGS_FWD(8, 8) VPGS_FWD(32, 8)
+#define VPGS_FWD(TW, TH, NB) \
+  if (tile_w == TW && tile_h == TH && lds_batch == NB) \
+    return launch_fwd_t<TW, TH, NB>(d_tab, h, pb, ranges, vals, order, T_final, n_contrib, masks, cnt, queue, \
+                                    blocks, s);
+  VPGS_SHAPES(VPGS_FWD)
 #undef VPGS_FWD
   return hipErrorInvalidValue;
 }
@@ -569,16 +607,18 @@ hipError_t launch_composite_forward(const CallTables* d_tab, const CallTables& h
 hipError_t launch_composite_backward(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb,
                                      const uint2* ranges, const uint32_t* vals, const uint32_t* order,
                                      const float* T_final, const uint32_t* n_contrib, const uint64_t* masks,
-                                     float* acc, int tile_w, int tile_h, uint32_t* queue, uint32_t blocks,
-                                     hipStream_t s) {
+                                     float* acc, int tile_w, int tile_h, int lds_batch, uint32_t* queue,
+                                     uint32_t blocks, hipStream_t s) {
   if (h.n_tiles == 0) return hipSuccess;
-#define VPGS_BWD(TW, TH) \
-  if (tile_w == TW && tile_h == TH) \
-    return launch_bwd_t<TW, TH>(d_tab, h, pb, ranges, vals, order, T_final, n_contrib, masks, acc, queue, blocks, \
-                                s);
-  VPGS_BWD(16, 16) VPGS_BWD(16, 8) VPGS_BWD(8, 8) VPGS_BWD(32, 8)
+#define VPGS_BWD(TW, TH, NB) \
+  if (tile_w == TW && tile_h == TH && lds_batch == NB) \
+    return launch_bwd_t<TW, TH, NB>(d_tab, h, pb, ranges, vals, order, T_final, n_contrib, masks, acc, queue, \
+                                    blocks, s);
+  VPGS_SHAPES(VPGS_BWD)
 #undef VPGS_BWD
   return hipErrorInvalidValue;
 }
+
+#undef VPGS_SHAPES
 
 }  // namespace vpgs

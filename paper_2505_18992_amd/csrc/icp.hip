@@ -649,7 +649,7 @@ int vpgs_voxel_map_create(vpgs_ctx* ctx, const float* points, int64_t n, float v
   const uint32_t cap = pow2_at_least(std::max<uint64_t>(2 * (uint64_t)n, 64));
   m->mask = cap - 1;
   auto cleanup = [&](int code) {
-    free_buf(m->pts); free_buf(m->keys); free_buf(m->vals); free_buf(m->nvox);
+    free_buf(m->ctx, m->pts); free_buf(m->ctx, m->keys); free_buf(m->ctx, m->vals); free_buf(m->ctx, m->nvox);
     delete m;
     return code;
   };
@@ -730,7 +730,7 @@ int vpgs_voxel_map_info(vpgs_voxel_map* m, int64_t* n_points, int64_t* n_voxels,
 int vpgs_voxel_map_destroy(vpgs_voxel_map* m) {
   if (!m) return VPGS_EINVAL;
   (void)hipSetDevice(m->ctx->device);
-  free_buf(m->pts); free_buf(m->keys); free_buf(m->vals); free_buf(m->nvox);
+  free_buf(m->ctx, m->pts); free_buf(m->ctx, m->keys); free_buf(m->ctx, m->vals); free_buf(m->ctx, m->nvox);
   delete m;
   return VPGS_OK;
 }

@@ -208,19 +208,24 @@ hipError_t launch_key64(const uint32_t* tiles, const uint32_t* recs, const ProjB
 // Compositing: one workgroup per tile, or (queue != NULL) `blocks`
 // persistent workgroups taking tiles from the zeroed counter *queue; the
 // i-th workgroup or ticket takes tile order[i].
-// The forward leaves per (tile, batch, wavefront) the bits of the batch
-// entries that reach the wavefront's quadrant in masks (hit_mask_bytes of
-// them for the pair capacity and tile shape); the backward reads them.
-size_t hit_mask_bytes(uint32_t capacity, uint32_t n_tiles, int tile_w, int tile_h);
+// Each tile's list is staged in LDS in batches of lds_batch entries (half,
+// once or twice the tile's pixel count, a multiple of 64:
+// lds_batch_supported).  The forward leaves per (tile, batch, wavefront) the
+// bits of the batch entries that reach the wavefront's quadrant in masks
+// (hit_mask_bytes of them for the pair capacity, tile shape and batch); the
+// backward reads them.
+bool lds_batch_supported(int tw, int th, int lds_batch);
+size_t hit_mask_bytes(uint32_t capacity, uint32_t n_tiles, int tile_w, int tile_h, int lds_batch);
 hipError_t launch_composite_forward(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
                                     const uint2* ranges, const uint32_t* vals, const uint32_t* order,
                                     float* T_final, uint32_t* n_contrib, uint64_t* masks, Counters* cnt,
-                                    int tile_w, int tile_h, uint32_t* queue, uint32_t blocks, hipStream_t s);
+                                    int tile_w, int tile_h, int lds_batch, uint32_t* queue, uint32_t blocks,
+                                    hipStream_t s);
 hipError_t launch_composite_backward(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
                                      const uint2* ranges, const uint32_t* vals, const uint32_t* order,
                                      const float* T_final, const uint32_t* n_contrib, const uint64_t* masks,
-                                     float* acc, int tile_w, int tile_h, uint32_t* queue, uint32_t blocks,
-                                     hipStream_t s);
+                                     float* acc, int tile_w, int tile_h, int lds_batch, uint32_t* queue,
+                                     uint32_t blocks, hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float value, size_t n, hipStream_t s);

@@ -61,27 +61,65 @@ StageTimer::~StageTimer() {
   ctx->pending.push_back({stage, a, b});
 }
 
+namespace {
+
+// Device memory through the caller's callbacks when it gave them (a caching
+// allocator that recycles blocks needs the device idle before a block comes
+// back: the library synchronises the device first), else hipMalloc/hipFree.
+int alloc_device(vpgs_ctx* ctx, size_t bytes, void** p) {
+  *p = nullptr;
+  if (ctx->alloc) {
+    *p = ctx->alloc(bytes, ctx->alloc_user);
+    if (!*p) return fail(ctx, VPGS_ENOMEM, "allocator callback returned NULL for %zu bytes", bytes);
+    if (reinterpret_cast<uintptr_t>(*p) & 255u) {
+      ctx->free_(*p, ctx->alloc_user);
+      *p = nullptr;
+      return fail(ctx, VPGS_EINVAL, "allocator callback returned a block that is not 256-byte aligned");
+    }
+    return VPGS_OK;
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(ctx, VPGS_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  return VPGS_OK;
+}
+
+int release_device(vpgs_ctx* ctx, void* p) {
+  if (!p) return VPGS_OK;
+  if (ctx->free_) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->free_(p, ctx->alloc_user);
+    return VPGS_OK;
+  }
+  hipError_t e = hipFree(p);
+  if (e != hipSuccess) return fail(ctx, VPGS_EHIP, "hipFree: %s", hipGetErrorString(e));
+  return VPGS_OK;
+}
+
+}  // namespace
+
 int ensure(vpgs_ctx* ctx, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.cap >= bytes) return VPGS_OK;
   if (b.p) {
-    hipError_t e = hipFree(b.p);
+    void* old = b.p;
     b.p = nullptr;
     b.cap = 0;
-    if (e != hipSuccess) return fail(ctx, VPGS_EHIP, "hipFree: %s", hipGetErrorString(e));
+    const int rc = release_device(ctx, old);
+    if (rc) return rc;
   }
   const size_t want = bytes + bytes / 4;
-  hipError_t e = hipMalloc(&b.p, want);
-  if (e != hipSuccess) {
-    b.p = nullptr;
-    return fail(ctx, VPGS_ENOMEM, "hipMalloc(%zu): %s", want, hipGetErrorString(e));
-  }
+  const int rc = alloc_device(ctx, want, &b.p);
+  if (rc) return rc;
   b.cap = want;
   return VPGS_OK;
 }
 
-void free_buf(DevBuf& b) {
-  if (b.p) (void)hipFree(b.p);
+void free_buf(vpgs_ctx* ctx, DevBuf& b) {
+  if (b.p) (void)release_device(ctx, b.p);
   b.p = nullptr;
   b.cap = 0;
 }
@@ -95,7 +133,7 @@ void destroy_saved(vpgs_saved* s) {
                     &s->keys, &s->vals, &s->keys_alt, &s->vals_alt, &s->sort_ws, &s->ranges, &s->tfinal,
                     &s->ncontrib, &s->counters, &s->acc, &s->pose_partial, &s->dk, &s->dk_alt, &s->dv,
                     &s->dv_alt, &s->dcount, &s->dpoff, &s->key64, &s->order};
-  for (DevBuf* b : bufs) free_buf(*b);
+  for (DevBuf* b : bufs) free_buf(s->ctx, *b);
   if (s->tab_uploaded) (void)hipEventDestroy(s->tab_uploaded);
   if (s->h_tab) (void)hipHostFree(s->h_tab);
   delete s;
@@ -104,6 +142,7 @@ void destroy_saved(vpgs_saved* s) {
 int new_saved(vpgs_ctx* ctx, vpgs_saved** out) {
   vpgs_saved* s = new (std::nothrow) vpgs_saved();
   if (!s) return fail(ctx, VPGS_ENOMEM, "out of host memory");
+  s->ctx = ctx;
   hipError_t e = hipHostMalloc((void**)&s->h_tab, sizeof(CallTables), hipHostMallocDefault);
   if (e != hipSuccess) {
     delete s;
@@ -258,6 +297,10 @@ int validate_forward(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, int 
   if (opts) {
     const int tw = opts->tile_w ? opts->tile_w : 16, th = opts->tile_h ? opts->tile_h : 16;
     if (!tile_shape_supported(tw, th)) return fail(ctx, VPGS_EUNSUPPORTED, "tile shape %dx%d not built", tw, th);
+    if (opts->lds_batch != 0 && !lds_batch_supported(tw, th, opts->lds_batch))
+      return fail(ctx, VPGS_EUNSUPPORTED, "LDS batch of %d entries not built for %dx%d tiles", opts->lds_batch, tw, th);
+    if (opts->grid_ctas < 0 || opts->grid_ctas > kMaxGridCtas)
+      return fail(ctx, VPGS_EINVAL, "grid_ctas %d out of range [0, %d]", opts->grid_ctas, kMaxGridCtas);
     if (opts->pair_capacity < 0 || opts->pair_capacity > 0x7fffffffLL)
       return fail(ctx, VPGS_EINVAL, "pair_capacity %lld out of range", (long long)opts->pair_capacity);
   }
@@ -306,7 +349,7 @@ int ensure_pairs(vpgs_ctx* ctx, vpgs_saved* sv, uint32_t cap) {
       (rc = ensure(ctx, sv->vals, (size_t)cap * 4)) || (rc = ensure(ctx, sv->vals_alt, (size_t)cap * 4)) ||
       (rc = ensure(ctx, sv->sort_ws,
                    sort_workspace_bytes(std::max<uint32_t>(cap, sv->h_tab->n_records)))) ||
-      (rc = ensure(ctx, sv->hitmask, hit_mask_bytes(cap, sv->h_tab->n_tiles, sv->tile_w, sv->tile_h))))
+      (rc = ensure(ctx, sv->hitmask, hit_mask_bytes(cap, sv->h_tab->n_tiles, sv->tile_w, sv->tile_h, sv->lds_batch))))
     return rc;
   sv->capacity = cap;
   return VPGS_OK;
@@ -434,8 +477,8 @@ int enqueue_back(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
     HIP_TRY(launch_composite_forward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
                                      static_cast<const uint32_t*>(sv->order.p), static_cast<float*>(sv->tfinal.p),
                                      static_cast<uint32_t*>(sv->ncontrib.p), static_cast<uint64_t*>(sv->hitmask.p), cnt,
-                                     sv->tile_w, sv->tile_h, sv->persistent_blocks ? &cnt->queue_fwd : nullptr,
-                                     sv->persistent_blocks, st));
+                                     sv->tile_w, sv->tile_h, sv->lds_batch,
+                                     sv->persistent_blocks ? &cnt->queue_fwd : nullptr, sv->persistent_blocks, st));
   }
   return VPGS_OK;
 }
@@ -457,7 +500,8 @@ int enqueue_backward(vpgs_ctx* ctx, vpgs_saved* sv, float* d_pose, hipStream_t s
                                       static_cast<const uint32_t*>(sv->order.p), static_cast<const float*>(sv->tfinal.p),
                                       static_cast<const uint32_t*>(sv->ncontrib.p),
                                       static_cast<const uint64_t*>(sv->hitmask.p), acc, sv->tile_w, sv->tile_h,
-                                      sv->persistent_blocks ? &cnt->queue_bwd : nullptr, sv->persistent_blocks, st));
+                                      sv->lds_batch, sv->persistent_blocks ? &cnt->queue_bwd : nullptr,
+                                      sv->persistent_blocks, st));
   }
   float* partial = d_pose ? static_cast<float*>(sv->pose_partial.p) : nullptr;
   {
@@ -491,14 +535,19 @@ const char* vpgs_status_string(int status) {
 
 const char* vpgs_last_error(const vpgs_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "NULL context"; }
 
-int vpgs_create(vpgs_ctx** out, int device) {
+int vpgs_create(vpgs_ctx** out, int device, void* (*alloc)(size_t, void*), void (*free_)(void*, void*),
+                void* user) {
   if (!out) return VPGS_EINVAL;
   *out = nullptr;
+  if ((alloc == nullptr) != (free_ == nullptr)) return VPGS_EINVAL;  // both callbacks or neither
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return VPGS_EINVAL;
   vpgs_ctx* ctx = new (std::nothrow) vpgs_ctx();
   if (!ctx) return VPGS_ENOMEM;
   ctx->device = device;
+  ctx->alloc = alloc;
+  ctx->free_ = free_;
+  ctx->alloc_user = user;
   if (hipSetDevice(device) != hipSuccess || hipHostMalloc(&ctx->h_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
     delete ctx;
     return VPGS_EHIP;
@@ -556,14 +605,14 @@ int vpgs_destroy(vpgs_ctx* ctx) {
   for (auto& p : ctx->pending) { ctx->ev_free.push_back(p.a); ctx->ev_free.push_back(p.b); }
   for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
   for (vpgs_saved* s : ctx->pool) destroy_saved(s);
-  free_buf(ctx->dec_partial);
-  free_buf(ctx->loss_ws);
-  free_buf(ctx->loss_sums);
-  free_buf(ctx->expand_mask);
-  free_buf(ctx->expand_blocks);
-  free_buf(ctx->distill_ws);
-  free_buf(ctx->icp_build);
-  free_buf(ctx->icp_ws);
+  free_buf(ctx, ctx->dec_partial);
+  free_buf(ctx, ctx->loss_ws);
+  free_buf(ctx, ctx->loss_sums);
+  free_buf(ctx, ctx->expand_mask);
+  free_buf(ctx, ctx->expand_blocks);
+  free_buf(ctx, ctx->distill_ws);
+  free_buf(ctx, ctx->icp_build);
+  free_buf(ctx, ctx->icp_ws);
   if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
   delete ctx;
   return VPGS_OK;
@@ -595,7 +644,8 @@ int vpgs_render_forward(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, i
   if (rc) return rc;
   sv->tile_w = tw;
   sv->tile_h = th;
-  sv->persistent_blocks = 0;
+  sv->lds_batch = (opts && opts->lds_batch) ? opts->lds_batch : tw * th;
+  sv->persistent_blocks = opts ? (uint32_t)opts->grid_ctas : 0u;
   if ((rc = prepare_front(ctx, sv)) || (rc = upload_tables(ctx, sv, st)) || (rc = enqueue_front(ctx, sv, st)))
     return rc;
   uint32_t cap;
@@ -665,6 +715,7 @@ int vpgs_saved_stats(vpgs_ctx* ctx, const vpgs_saved* saved, vpgs_stats* out, vo
   out->overflow = hc->overflow || hc->pairs > saved->capacity;
   out->tile_w = saved->tile_w;
   out->tile_h = saved->tile_h;
+  out->lds_batch = saved->lds_batch;
   out->n_visible = hc->visible;
   return out->overflow ? fail(ctx, VPGS_ECAPACITY, "pair list overflow: %u pairs, capacity %u", hc->pairs,
                               saved->capacity)

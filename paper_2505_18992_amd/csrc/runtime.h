@@ -26,6 +26,7 @@ extern const char* const kStageNames[VPGS_NUM_STAGES];
 }  // namespace vpgs
 
 struct vpgs_saved {
+  vpgs_ctx* ctx = nullptr;  // whose allocator holds the buffers
   // host and device call tables; the host copy is pinned and guarded by an
   // event so an in-flight upload is never overwritten
   vpgs::CallTables* h_tab = nullptr;
@@ -35,6 +36,7 @@ struct vpgs_saved {
   int result_in_alt = 0;
   int depth_in_alt = 0;
   int tile_w = 16, tile_h = 16;
+  int lds_batch = 256;  // entries staged per compositing batch
   int key_bits = 16;  // tile-id bits sorted
   uint32_t persistent_blocks = 0;  // 0: one compositing workgroup per tile
   uint32_t capacity = 0;
@@ -44,6 +46,11 @@ struct vpgs_saved {
 
 struct vpgs_ctx {
   int device = 0;
+  // device workspace allocator: the caller's callbacks, or hipMalloc/hipFree
+  // when none were given
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free_)(void*, void*) = nullptr;
+  void* alloc_user = nullptr;
   std::string last_error;
   std::vector<vpgs_saved*> pool;
   void* h_pinned = nullptr;  // small pinned buffer for counter readback
@@ -70,6 +77,7 @@ struct vpgs_ctx {
 namespace vpgs {
 
 constexpr int kMaxDevices = 64;
+constexpr int kMaxGridCtas = 65536;  // persistent compositing workgroups at most
 
 // Looks up, once per device and with it current, the device address of the
 // allocation-free entry points' scratch array (icp.hip).
@@ -77,9 +85,11 @@ int init_scratch(vpgs_ctx* ctx);
 
 // Records the message as the context's last error and returns code.
 int fail(vpgs_ctx* ctx, int code, const char* fmt, ...);
-// Grows b to at least `bytes` (hipFree + hipMalloc; contents are not kept).
+// Grows b to at least `bytes` through the context's allocator (the old
+// buffer is released first; contents are not kept).
 int ensure(vpgs_ctx* ctx, DevBuf& b, size_t bytes);
-void free_buf(DevBuf& b);
+// Releases b through the context's allocator.
+void free_buf(vpgs_ctx* ctx, DevBuf& b);
 
 // Forward/backward pipeline of one call, shared by the eager entry points
 // and the captured window.  The host call tables must be built first.

@@ -3,8 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "runtime.h"
@@ -33,6 +38,7 @@ struct vpgs_window {
   // without synchronising.
   uint32_t* h_overflow = nullptr;
   uint32_t* d_overflow = nullptr;  // the device address of the same word
+  bool tuned_from_cache = false;
 };
 
 namespace {
@@ -51,7 +57,7 @@ const vpgs_densify_accum* accum_of(vpgs_window* w) {
   return &w->acc_desc;
 }
 
-int configure(vpgs_window* w, int tw, int th) {
+int configure(vpgs_window* w, int tw, int th, int nb) {
   vpgs_ctx* ctx = w->ctx;
   vpgs_saved* sv = w->sv;
   HIP_TRY(hipEventSynchronize(sv->tab_uploaded));
@@ -63,6 +69,7 @@ int configure(vpgs_window* w, int tw, int th) {
   if (rc) return rc;
   sv->tile_w = tw;
   sv->tile_h = th;
+  sv->lds_batch = nb;
   return prepare_front(ctx, sv);
 }
 
@@ -149,6 +156,109 @@ int capture(vpgs_window* w) {
   return VPGS_OK;
 }
 
+// ---- tuning cache ------------------------------------------------------
+// A JSON object {"entries": [{"key": "...", "tile_w": .., "tile_h": ..,
+// "persistent": .., "lds_batch": .., "ms": ..}, ...]}, one entry per key.
+
+struct TuneEntry {
+  std::string key;
+  int tile_w = 0, tile_h = 0, persistent = 0, lds_batch = 0;
+  double ms = 0.0;
+};
+
+std::string tune_key(vpgs_window* w) {
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDeviceProperties(&prop, w->ctx->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  }
+  for (char& c : arch)
+    if (c == '"' || c == '\\') c = '_';
+  uint64_t records = 0;
+  for (int32_t s : w->view_set) records += (uint64_t)w->sets[s].n;
+  std::ostringstream k;
+  k << arch << "/" << cus << "cu/" << w->cams.size() << "views/";
+  for (size_t v = 0; v < w->cams.size(); ++v) k << (v ? "," : "") << w->cams[v].width << "x" << w->cams[v].height;
+  k << "/records2^" << (records > 1 ? (int)std::ceil(std::log2((double)records)) : 0);
+  return k.str();
+}
+
+// The text of a "name": value field inside one entry, or "" if absent.
+std::string field(const std::string& obj, const char* name) {
+  const std::string tag = std::string("\"") + name + "\"";
+  size_t p = obj.find(tag);
+  if (p == std::string::npos) return "";
+  p = obj.find(':', p + tag.size());
+  if (p == std::string::npos) return "";
+  ++p;
+  while (p < obj.size() && (obj[p] == ' ' || obj[p] == '\t' || obj[p] == '\n')) ++p;
+  if (p < obj.size() && obj[p] == '"') {
+    const size_t q = obj.find('"', p + 1);
+    return q == std::string::npos ? "" : obj.substr(p + 1, q - p - 1);
+  }
+  size_t q = p;
+  while (q < obj.size() && obj[q] != ',' && obj[q] != '}') ++q;
+  return obj.substr(p, q - p);
+}
+
+std::vector<TuneEntry> read_cache(const char* path) {
+  std::vector<TuneEntry> out;
+  std::ifstream f(path);
+  if (!f) return out;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string text = ss.str();
+  size_t p = text.find('[');
+  while (p != std::string::npos) {
+    const size_t a = text.find('{', p);
+    if (a == std::string::npos) break;
+    const size_t b = text.find('}', a);
+    if (b == std::string::npos) break;
+    const std::string obj = text.substr(a, b - a + 1);
+    TuneEntry e;
+    e.key = field(obj, "key");
+    const std::string tw = field(obj, "tile_w"), th = field(obj, "tile_h"), pe = field(obj, "persistent"),
+                      nb = field(obj, "lds_batch"), ms = field(obj, "ms");
+    if (!e.key.empty() && !tw.empty() && !th.empty() && !pe.empty() && !nb.empty()) {
+      e.tile_w = std::atoi(tw.c_str());
+      e.tile_h = std::atoi(th.c_str());
+      e.persistent = std::atoi(pe.c_str());
+      e.lds_batch = std::atoi(nb.c_str());
+      e.ms = ms.empty() ? 0.0 : std::atof(ms.c_str());
+      out.push_back(e);
+    }
+    p = b + 1;
+  }
+  return out;
+}
+
+int write_cache(vpgs_ctx* ctx, const char* path, const TuneEntry& e) {
+  std::vector<TuneEntry> all = read_cache(path);
+  bool found = false;
+  for (TuneEntry& x : all)
+    if (x.key == e.key) { x = e; found = true; }
+  if (!found) all.push_back(e);
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    if (!f) return fail(ctx, VPGS_EINVAL, "tuning cache %s: cannot write", path);
+    f << "{\"entries\": [\n";
+    for (size_t i = 0; i < all.size(); ++i) {
+      char ms[32];
+      std::snprintf(ms, sizeof(ms), "%.4f", all[i].ms);
+      f << "  {\"key\": \"" << all[i].key << "\", \"tile_w\": " << all[i].tile_w << ", \"tile_h\": " << all[i].tile_h
+        << ", \"persistent\": " << all[i].persistent << ", \"lds_batch\": " << all[i].lds_batch << ", \"ms\": " << ms
+        << "}" << (i + 1 < all.size() ? "," : "") << "\n";
+    }
+    f << "]}\n";
+    if (!f) return fail(ctx, VPGS_EINVAL, "tuning cache %s: write failed", path);
+  }
+  if (std::rename(tmp.c_str(), path) != 0) return fail(ctx, VPGS_EINVAL, "tuning cache %s: cannot replace", path);
+  return VPGS_OK;
+}
+
 void release(vpgs_window* w) {
   for (int i = 0; i < 2; ++i) {
     if (w->exec[i]) (void)hipGraphExecDestroy(w->exec[i]);
@@ -176,6 +286,7 @@ int vpgs_window_create(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, in
   o.use_graph = 1;
   if (opts) o = *opts;
   if (o.tune_reps <= 0) o.tune_reps = 3;
+  if (o.lds_batch < 0) return fail(ctx, VPGS_EINVAL, "lds_batch must be >= 0");
   if ((o.tile_w != 0 || o.tile_h != 0) && !tile_shape_supported(o.tile_w, o.tile_h))
     return fail(ctx, VPGS_EUNSUPPORTED, "tile shape %dx%d not built", o.tile_w, o.tile_h);
   if (o.pair_capacity < 0 || o.pair_capacity > 0x7fffffffLL) return fail(ctx, VPGS_EINVAL, "pair_capacity out of range");
@@ -204,34 +315,85 @@ int vpgs_window_create(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, in
 
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+  const bool fixed_nb = o.lds_batch > 0;
+  if (fixed_nb && o.tile_w && !lds_batch_supported(o.tile_w, o.tile_h, o.lds_batch))
+    { release(w); return fail(ctx, VPGS_EUNSUPPORTED, "LDS batch of %d entries not built", o.lds_batch); }
+  if (o.persistent > kMaxGridCtas) { release(w); return fail(ctx, VPGS_EINVAL, "persistent grid out of range"); }
+
+  int best_tw = 0, best_th = 0, best_mode = 0, best_nb = 0;
+  float best_ms = 1e30f;
+  bool from_cache = false;
+  std::string key;
+  if (o.tune_cache) {
+    key = tune_key(w);
+    for (const TuneEntry& e : read_cache(o.tune_cache)) {
+      const bool fits = e.key == key && tile_shape_supported(e.tile_w, e.tile_h) &&
+                        lds_batch_supported(e.tile_w, e.tile_h, e.lds_batch) && e.persistent >= 0 &&
+                        e.persistent <= kMaxGridCtas && (!o.tile_w || (o.tile_w == e.tile_w && o.tile_h == e.tile_h)) &&
+                        (o.persistent < 0 || o.persistent == e.persistent) && (!fixed_nb || o.lds_batch == e.lds_batch);
+      if (fits) {
+        best_tw = e.tile_w; best_th = e.tile_h; best_mode = e.persistent; best_nb = e.lds_batch;
+        best_ms = (float)e.ms;
+        from_cache = true;
+      }
+    }
+  }
+
   // candidates of the search
   std::vector<std::pair<int, int>> shapes;
   if (o.tile_w && o.tile_h) shapes.push_back({o.tile_w, o.tile_h});
   else for (auto& s : kShapes) shapes.push_back({s[0], s[1]});
   std::vector<int> modes;
   if (o.persistent >= 0) modes.push_back(o.persistent);
-  else { modes.push_back(0); modes.push_back(4 * cus); modes.push_back(8 * cus); }
+  else { modes.push_back(0); modes.push_back(2 * cus); modes.push_back(4 * cus); modes.push_back(8 * cus); }
 
-  float best_ms = 1e30f;
-  int best_tw = shapes[0].first, best_th = shapes[0].second, best_mode = modes[0];
-  const bool search = shapes.size() * modes.size() > 1;
-  for (auto& sh : shapes) {
-    if ((rc = configure(w, sh.first, sh.second)) || (rc = size_pairs(w, st, o.pair_capacity))) { release(w); return rc; }
-    if (!search) break;
-    for (int m : modes) {
-      w->sv->persistent_blocks = (uint32_t)m;
-      float ms = 0.f;
-      rc = time_config(w, st, o.tune_reps, &ms);
-      if (rc) { release(w); return rc; }
-      if (ms < best_ms) { best_ms = ms; best_tw = sh.first; best_th = sh.second; best_mode = m; }
+  if (!from_cache) {
+    const bool search = shapes.size() * modes.size() > 1 || !fixed_nb;
+    best_tw = shapes[0].first; best_th = shapes[0].second; best_mode = modes[0];
+    best_nb = fixed_nb ? o.lds_batch : best_tw * best_th;
+    // stage 1: shape x grid at one batch per tile's pixels (or the given batch)
+    for (auto& sh : shapes) {
+      const int nb = fixed_nb ? o.lds_batch : sh.first * sh.second;
+      if (!lds_batch_supported(sh.first, sh.second, nb)) continue;
+      if ((rc = configure(w, sh.first, sh.second, nb)) || (rc = size_pairs(w, st, o.pair_capacity))) { release(w); return rc; }
+      if (!search) break;
+      for (int m : modes) {
+        w->sv->persistent_blocks = (uint32_t)m;
+        float ms = 0.f;
+        rc = time_config(w, st, o.tune_reps, &ms);
+        if (rc) { release(w); return rc; }
+        if (ms < best_ms) { best_ms = ms; best_tw = sh.first; best_th = sh.second; best_mode = m; best_nb = nb; }
+      }
+    }
+    // stage 2: the other batch sizes of the best shape and grid
+    if (search && !fixed_nb) {
+      const int px = best_tw * best_th;
+      for (int nb : {px / 2, 2 * px}) {
+        if (!lds_batch_supported(best_tw, best_th, nb)) continue;
+        if ((rc = configure(w, best_tw, best_th, nb)) || (rc = size_pairs(w, st, o.pair_capacity))) { release(w); return rc; }
+        w->sv->persistent_blocks = (uint32_t)best_mode;
+        float ms = 0.f;
+        rc = time_config(w, st, o.tune_reps, &ms);
+        if (rc) { release(w); return rc; }
+        if (ms < best_ms) { best_ms = ms; best_nb = nb; }
+      }
     }
   }
   o.tile_w = best_tw;
   o.tile_h = best_th;
   o.persistent = best_mode;
-  if ((rc = configure(w, best_tw, best_th)) || (rc = size_pairs(w, st, o.pair_capacity))) { release(w); return rc; }
+  o.lds_batch = best_nb;
+  if ((rc = configure(w, best_tw, best_th, best_nb)) || (rc = size_pairs(w, st, o.pair_capacity))) { release(w); return rc; }
   w->sv->persistent_blocks = (uint32_t)best_mode;
+  if (o.tune_cache && !from_cache && best_ms < 1e30f) {
+    TuneEntry e;
+    e.key = key;
+    e.tile_w = best_tw; e.tile_h = best_th; e.persistent = best_mode; e.lds_batch = best_nb; e.ms = best_ms;
+    if ((rc = write_cache(ctx, o.tune_cache, e))) { release(w); return rc; }
+  }
+  w->tuned_from_cache = from_cache;
   o.pair_capacity = w->sv->capacity;
+  o.tune_cache = nullptr;  // the caller's path is not kept
   w->cfg = o;
   HIP_TRY(hipStreamSynchronize(st));
   {

@@ -12,6 +12,7 @@ step of the computation runs in ``libvpgs.so``.
 from __future__ import annotations
 
 import ctypes
+import sys
 import threading
 from typing import List, Optional, Sequence
 
@@ -25,13 +26,47 @@ __all__ = ["Context", "get_context", "render", "render_backward", "Saved", "Rend
            "mapping_loss", "volume_loss"]
 
 
-class Context:
-    """One library context per device (the library requires one per stream user)."""
+class _TorchWorkspace:
+    """The library's device workspace through torch's caching allocator: a
+    block is a uint8 tensor held until the library hands it back (the
+    library synchronises the device first)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int):
+        self.device = torch.device("cuda", device)
+        self.blocks = {}
+        # late-bound, so a test can swap the allocation policy of a live context
+        self.alloc_cb = _lib.ALLOC_FN(lambda n, u: self._alloc(n, u))
+        self.free_cb = _lib.FREE_FN(lambda p, u: self._free(p, u))
+
+    def _alloc(self, nbytes, _user):
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        except Exception:  # out of memory: the library reports VPGS_ENOMEM
+            return None
+        self.blocks[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _free(self, ptr, _user):
+        self.blocks.pop(ptr, None)
+
+    def bytes_held(self) -> int:
+        return sum(t.numel() for t in self.blocks.values())
+
+
+class Context:
+    """One library context per device (the library requires one per stream
+    user).  Its workspace comes from torch's caching allocator unless
+    ``torch_workspace`` is False (then the library calls hipMalloc)."""
+
+    def __init__(self, device: int = 0, torch_workspace: bool = True):
         L = load()
         h = ctypes.c_void_p()
-        st = L.vpgs_create(ctypes.byref(h), int(device))
+        self.workspace = _TorchWorkspace(device) if torch_workspace else None
+        if self.workspace is not None:
+            st = L.vpgs_create(ctypes.byref(h), int(device), ctypes.cast(self.workspace.alloc_cb, ctypes.c_void_p),
+                               ctypes.cast(self.workspace.free_cb, ctypes.c_void_p), None)
+        else:
+            st = L.vpgs_create(ctypes.byref(h), int(device), None, None, None)
         if st != 0:
             raise _lib.VpgsError(st, f"vpgs_create(device={device}) failed: {L.vpgs_status_string(st).decode()}")
         self.handle = h
@@ -59,7 +94,8 @@ class Context:
 
     def __del__(self):
         try:
-            self.close()
+            if not sys.is_finalizing():  # the allocator callbacks need a live interpreter
+                self.close()
         except Exception:
             pass
 
@@ -168,10 +204,14 @@ def _set_struct(s) -> _lib.Gaussians:
 
 
 def render(sets: Sequence[Sequence[torch.Tensor]], cameras: Sequence, view_set: Optional[Sequence[int]] = None,
-           tile=(16, 16), pair_capacity: int = 0, keep: bool = True, ctx: Optional[Context] = None):
+           tile=(16, 16), pair_capacity: int = 0, keep: bool = True, ctx: Optional[Context] = None,
+           lds_batch: int = 0, grid_ctas: int = 0):
     """Forward render.  ``sets`` is a list of (means, log_scales, quats,
     opacities, colors) tuples; view v renders sets[view_set[v]] with
-    cameras[v].  Returns (list of (rgb[3,H,W], depth[H,W], alpha[H,W]), Saved or None)."""
+    cameras[v].  lds_batch: entries staged per compositing batch (0 = the
+    tile's pixel count); grid_ctas: persistent compositing workgroups (0 =
+    one per tile).  Returns (list of (rgb[3,H,W], depth[H,W], alpha[H,W]),
+    Saved or None)."""
     ctx = ctx or get_context()
     L = load()
     nv = len(cameras)
@@ -191,6 +231,8 @@ def render(sets: Sequence[Sequence[torch.Tensor]], cameras: Sequence, view_set: 
         outs.append((rgb, depth, alpha))
     opts = _lib.RenderOpts()
     opts.tile_w, opts.tile_h = tile
+    opts.lds_batch = int(lds_batch)
+    opts.grid_ctas = int(grid_ctas)
     opts.pair_capacity = int(pair_capacity)
     h = ctypes.c_void_p()
     st = L.vpgs_render_forward(ctx.handle, len(sets), gs, nv, vs, cams, ims, ctypes.byref(opts),
@@ -328,7 +370,8 @@ class RenderWindow:
     between runs."""
 
     def __init__(self, sets, cameras, view_set=None, tile=None, persistent: int = -1, use_graph: bool = True,
-                 pair_capacity: int = 0, tune_reps: int = 3, ctx: Optional[Context] = None):
+                 pair_capacity: int = 0, tune_reps: int = 3, ctx: Optional[Context] = None, lds_batch: int = 0,
+                 tune_cache: Optional[str] = None):
         self.ctx = ctx or get_context()
         L = load()
         nv = len(cameras)
@@ -358,6 +401,8 @@ class RenderWindow:
         o.use_graph = int(use_graph)
         o.pair_capacity = int(pair_capacity)
         o.tune_reps = int(tune_reps)
+        o.lds_batch = int(lds_batch)
+        o.tune_cache = None if tune_cache is None else str(tune_cache).encode()
         h = ctypes.c_void_p()
         check(L.vpgs_window_create(self.ctx.handle, len(self.sets), gs, nv, vs, cams, ims, gis, gb,
                                    _ptr(self.d_pose), ctypes.byref(o), ctypes.byref(h), _stream()),
@@ -395,7 +440,7 @@ class RenderWindow:
     def config(self) -> dict:
         o = _lib.WindowOpts()
         check(load().vpgs_window_config(self.handle, ctypes.byref(o)), self.ctx.handle, "vpgs_window_config")
-        return {f: getattr(o, f) for f, _ in _lib.WindowOpts._fields_}
+        return {f: getattr(o, f) for f, _ in _lib.WindowOpts._fields_ if f != "tune_cache"}
 
     def close(self):
         if getattr(self, "handle", None):

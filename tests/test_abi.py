@@ -71,7 +71,7 @@ def test_null_context_is_rejected_without_touching_the_device(lib):
     assert lib.vpgs_icp_linearize(None, None, None, 0, None, 1.0, 1.0, None, None) == _lib.VPGS_EINVAL
     assert lib.vpgs_icp_linearize_noalloc(None, None, None, 0, None, 1.0, 1.0, None, None) == _lib.VPGS_EINVAL
     assert lib.vpgs_icp_register(None, None, None, 0, None, None, None, None, None, None) == _lib.VPGS_EINVAL
-    assert lib.vpgs_create(None, 0) == _lib.VPGS_EINVAL
+    assert lib.vpgs_create(None, 0, None, None, None) == _lib.VPGS_EINVAL
     assert lib.vpgs_last_error(None) == b"NULL context"
 
 
@@ -82,6 +82,9 @@ def test_structure_layouts_match_the_header():
     assert ctypes.sizeof(_lib.Camera) == 4 * 7 + 4 * 12
     assert _lib.Gaussians.means.offset == 8 and ctypes.sizeof(_lib.Gaussians) == 48
     assert ctypes.sizeof(_lib.RenderOpts) == 24 and _lib.RenderOpts.pair_capacity.offset == 16
+    assert _lib.RenderOpts.lds_batch.offset == 8 and _lib.RenderOpts.grid_ctas.offset == 12
+    assert ctypes.sizeof(_lib.WindowOpts) == 40 and _lib.WindowOpts.lds_batch.offset == 28
+    assert _lib.WindowOpts.tune_cache.offset == 32
     assert _lib.Anchors.xyz.offset == 16
     assert _lib.Mlp.W1.offset == 8 and ctypes.sizeof(_lib.Mlp) == 8 + 12 * 8
     assert ctypes.sizeof(_lib.Stats) == 8 * 8 + 4 * 4

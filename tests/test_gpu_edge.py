@@ -113,6 +113,13 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(VpgsError) as e:
         render([t], [cam], tile=(12, 12))
     assert e.value.status == _lib.VPGS_EUNSUPPORTED
+    for nb in (96, 1024, 32):  # not a multiple of 64, or not half/once/twice 256 pixels
+        with pytest.raises(VpgsError) as e:
+            render([t], [cam], tile=(16, 16), lds_batch=nb)
+        assert e.value.status == _lib.VPGS_EUNSUPPORTED
+    with pytest.raises(VpgsError) as e:
+        render([t], [cam], grid_ctas=-1)
+    assert e.value.status == _lib.VPGS_EINVAL
     with pytest.raises(VpgsError):
         render([t], [cam], view_set=[1])
     # misaligned quaternions
@@ -177,3 +184,49 @@ def test_multiple_sets_in_one_call():
     g, cam = sc.sets[sc.view_set[v]], sc.cameras[v]
     ref, mask, _ = oracle_reference(g, cam)
     assert_images(outs[v], ref, mask)
+
+
+def test_workspace_comes_from_the_torch_allocator():
+    """The default context hands the library torch's caching allocator
+    (vpgs_create's callbacks): the workspace of a render is held as torch
+    blocks, and a context on hipMalloc renders the same images bit for bit."""
+    from paper_2505_18992_amd import render
+    from paper_2505_18992_amd.render import Context
+    sc = scenes.make_c1()
+    print("case torch-backed workspace", flush=True)
+    ctx = Context(0)
+    outs, saved = render([to_dev(sc.sets[0].arrays())], sc.cameras, ctx=ctx)
+    saved.close()
+    held = ctx.workspace.bytes_held()
+    assert held > 0 and all(t.is_cuda for t in ctx.workspace.blocks.values())
+    hip_ctx = Context(0, torch_workspace=False)
+    assert hip_ctx.workspace is None
+    outs2, saved2 = render([to_dev(sc.sets[0].arrays())], sc.cameras, ctx=hip_ctx)
+    saved2.close()
+    for a, b in zip(outs[0], outs2[0]):
+        assert torch.equal(a, b)
+    ctx.close()
+    assert ctx.workspace.bytes_held() == 0  # every block was handed back
+    hip_ctx.close()
+
+
+def test_workspace_allocator_failure_is_reported():
+    """An allocator callback that returns NULL makes the call fail with
+    VPGS_ENOMEM and nothing enqueued; the context stays usable once the
+    allocator succeeds again."""
+    from paper_2505_18992_amd import render
+    from paper_2505_18992_amd._lib import VpgsError
+    from paper_2505_18992_amd.render import Context
+    sc = scenes.make_c1(n=100)
+    print("case allocator failure", flush=True)
+    ctx = Context(0)
+    real = ctx.workspace._alloc
+    ctx.workspace._alloc = lambda n, u: None
+    with pytest.raises(VpgsError) as e:
+        render([to_dev(sc.sets[0].arrays())], sc.cameras, ctx=ctx)
+    assert e.value.status == -2  # VPGS_ENOMEM
+    ctx.workspace._alloc = real
+    outs, saved = render([to_dev(sc.sets[0].arrays())], sc.cameras, ctx=ctx)
+    saved.close()
+    assert torch.count_nonzero(outs[0][2]) > 0
+    ctx.close()

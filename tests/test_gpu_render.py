@@ -28,12 +28,12 @@ def _need_gpu():
     _lib.load()
 
 
-def _render(sc, tile=(16, 16), views=None, cap=0):
+def _render(sc, tile=(16, 16), views=None, cap=0, lds_batch=0, grid_ctas=0):
     from paper_2505_18992_amd import render
     sets = [to_dev(g.arrays()) for g in sc.sets]
     cams = sc.cameras if views is None else [sc.cameras[v] for v in views]
     vset = sc.view_set if views is None else [sc.view_set[v] for v in views]
-    outs, saved = render(sets, cams, vset, tile=tile, pair_capacity=cap)
+    outs, saved = render(sets, cams, vset, tile=tile, pair_capacity=cap, lds_batch=lds_batch, grid_ctas=grid_ctas)
     torch.cuda.synchronize()
     return sets, outs, saved
 
@@ -168,6 +168,47 @@ def test_c1_backward_parity(tile, c1_backward_ref):
     got["pose"] = np_(d_pose)[0]
     rep = assert_grads(got, G, S)
     print("c1 grad errors", rep, flush=True)
+
+
+# every built (tile shape, LDS batch) pair: batches of half, once and twice
+# the tile's pixels (multiples of 64), so a batch's hit masks take one to
+# eight words per wavefront and a thread stages zero to two entries
+BATCHES = [((16, 16), 128), ((16, 16), 512), ((16, 8), 64), ((16, 8), 256), ((8, 8), 128), ((32, 8), 128),
+           ((32, 8), 512)]
+
+
+@pytest.mark.parametrize("tile,nb", BATCHES)
+def test_c1_backward_parity_per_lds_batch(tile, nb, c1_backward_ref):
+    from paper_2505_18992_amd import render_backward
+    sc, w, G, S = c1_backward_ref
+    print(f"case c1 backward tile={tile} lds_batch={nb}", flush=True)
+    _, outs, saved = _render(sc, tile=tile, lds_batch=nb)
+    assert saved.stats()["lds_batch"] == nb
+    grads, d_pose = render_backward(saved, [to_dev(w)])
+    saved.close()
+    got = dict(zip(["means", "log_scales", "quats", "opacities", "colors"], [np_(t) for t in grads[0]]))
+    got["pose"] = np_(d_pose)[0]
+    print("c1 grad errors", assert_grads(got, G, S), flush=True)
+
+
+@pytest.mark.parametrize("tile,nb,grid", [((16, 16), 512, 0), ((32, 8), 128, 512), ((16, 8), 64, 1024),
+                                          ((8, 8), 128, 256)])
+def test_forward_is_batch_and_grid_invariant(tile, nb, grid):
+    """The forward is bit-identical for every LDS batch and compositing grid
+    (a 200x150 view of the room scene: lists longer than one batch)."""
+    sc = scenes.make_c2(n=50_000)
+    sc.cameras[0] = sc.cameras[0].copy()
+    cam = sc.cameras[0]
+    cam.width, cam.height, cam.cx, cam.cy = 200, 150, 100.0, 75.0
+    cam.fx = cam.fy = 164.0
+    print(f"case forward invariance tile={tile} lds_batch={nb} grid={grid}", flush=True)
+    _, a, s1 = _render(sc)
+    _, b, s2 = _render(sc, tile=tile, lds_batch=nb, grid_ctas=grid)
+    st = s2.stats()
+    s1.close(); s2.close()
+    assert st["n_pairs"] > 20 * nb  # several batches per tile on average
+    for x, y in zip(a[0], b[0]):
+        assert torch.equal(x, y)
 
 
 @pytest.mark.parametrize("tile", [(8, 8), (16, 8), (32, 8)])

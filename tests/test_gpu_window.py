@@ -166,3 +166,42 @@ def test_window_overflow_on_a_later_run_stops_the_next_one():
         win.run()
     assert e.value.status == -4  # VPGS_ECAPACITY
     win.close()
+
+
+def test_window_tuning_cache(tmp_path):
+    """The search result is stored in the JSON tuning cache under the
+    workload's key, and a second window on the same workload takes it from
+    the cache (no search) and renders the same images."""
+    import json
+    from paper_2505_18992_amd import RenderWindow
+    sc, sets, gw = _scene()
+    path = tmp_path / "tune.json"
+    print("case window tuning cache", flush=True)
+    win = RenderWindow(sets, sc.cameras, sc.view_set, tune_reps=1, tune_cache=str(path))
+    cfg = win.config()
+    entries = json.loads(path.read_text())["entries"]
+    assert len(entries) == 1
+    e = entries[0]
+    assert (e["tile_w"], e["tile_h"], e["persistent"], e["lds_batch"]) == \
+        (cfg["tile_w"], cfg["tile_h"], cfg["persistent"], cfg["lds_batch"])
+    assert f"{len(sc.cameras)}views" in e["key"] and e["ms"] > 0
+    assert cfg["lds_batch"] in (cfg["tile_w"] * cfg["tile_h"] // 2, cfg["tile_w"] * cfg["tile_h"],
+                                2 * cfg["tile_w"] * cfg["tile_h"])
+    # an unrelated entry is kept; a second window uses the stored result
+    data = json.loads(path.read_text())
+    data["entries"].append({"key": "other", "tile_w": 8, "tile_h": 8, "persistent": 0, "lds_batch": 64, "ms": 1.0})
+    path.write_text(json.dumps(data))
+    win2 = RenderWindow(sets, sc.cameras, sc.view_set, tune_reps=1, tune_cache=str(path))
+    assert win2.config() == cfg
+    assert len(json.loads(path.read_text())["entries"]) == 2
+    for w in (win, win2):
+        for v in range(len(sc.cameras)):
+            for dst, src in zip(w.grad_out[v], gw[v]):
+                dst.copy_(src)
+        w.run()
+    torch.cuda.synchronize()
+    for v in range(len(sc.cameras)):
+        for a, b in zip(win.outputs[v], win2.outputs[v]):
+            assert torch.equal(a, b)
+    win.close()
+    win2.close()
