@@ -34,27 +34,37 @@ import numpy as np  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
-# Algorithmic work per unit (see the design notes for the derivation).
-FWD_FLOP_PER_EVAL = 16.0     # falloff: offset, quadratic form, exp, opacity, clamp, cutoff test
-FWD_FLOP_PER_BLEND = 12.0    # transmittance update and four fused accumulations
-BWD_FLOP_PER_EVAL = 16.0     # the same falloff, recomputed
-BWD_FLOP_PER_BLEND = 40.0    # transmittance recovery, alpha gradient, 10 per-Gaussian partials
+# Algorithmic work per unit (the derivation is in the design notes).
+# Compositing, per (pixel, Gaussian) evaluation and per blend:
+FWD_FLOP_PER_EVAL = 15.0     # offset, quadratic form, opacity, clamp, cutoff test (+ one exp)
+FWD_FLOP_PER_BLEND = 12.0    # transmittance update and the four accumulations
+BWD_FLOP_PER_BLEND = 60.0    # recomputed falloff, transmittance recovery, dL/dalpha, the 10 per-Gaussian
+                             # partials and their share of the wavefront reduction (+ one exp, one reciprocal)
+# HBM bytes: per pair staged (record line 48 B read once per tile, value 4 B),
+# per pixel (5 planes + T_final + n_contrib), per visible record's gradient row
+PAIR_STAGE_BYTES = 52.0
+FWD_PIXEL_BYTES = 28.0
+BWD_PIXEL_BYTES = 28.0       # 5 upstream planes, T_final, n_contrib read
+ACC_ROW_BYTES = 40.0
+# LDS bytes delivered to lanes per wavefront step (one wavefront of 64
+# lanes taking one hit-list entry): the entry's index, position/opacity,
+# pre-scaled conic and colour (forward); index, position and conic, plus
+# colour and row offset on active steps (backward); and per staged entry its
+# 56 B written once and 40 B read by each wavefront's quadrant test.
+FWD_LDS_PER_STEP = 64 * (2 + 16 + 16 + 16)
+BWD_LDS_PER_STEP = 64 * (2 + 16 + 16)
+BWD_LDS_PER_ACTIVE = 64 * 16
+LDS_PER_STAGED = 56.0
+LDS_PER_STAGED_TEST = 40.0
 SORT_BYTES_PER_PAIR_PASS = 20.0  # 32-bit keys and values: histogram read 4 B, scatter read 8 B + write 8 B
 
 # HBM bytes per launch of the compositing kernels from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE passes over the default workload and configuration
-# (profiles/render_c4-1200_hbm_traffic.md), scaled by what the same counters
+# WRITE_SIZE passes over the default workload and configuration (the
+# profiles directory holds the summary), scaled by what the same counters
 # read for a 256 MiB device copy (FETCH_SIZE x 2, WRITE_SIZE x 1).  They hold
 # only for the kernel sources they were taken with; after any change to
 # those the traffic is reported as null until it is measured again.
-MEASURED_TRAFFIC = {
-    ("composite_backward", 32, 8, 0): {
-        "sources_sha256": "593696e699f1f25895f14f4c36b7210a803107380ebe2392539d32df6fc68cf8",
-        "fetch_bytes": 1122117976, "write_bytes": 613763904},
-    ("composite_forward", 32, 8, 0): {
-        "sources_sha256": "593696e699f1f25895f14f4c36b7210a803107380ebe2392539d32df6fc68cf8",
-        "fetch_bytes": 1090667174, "write_bytes": 199058507},
-}
+MEASURED_TRAFFIC = {}
 TRAFFIC_SOURCES = ("paper_2505_18992_amd/csrc/composite.hip", "paper_2505_18992_amd/csrc/internal.h")
 
 
@@ -68,7 +78,7 @@ def sources_sha256():
 
 
 def measured_traffic(kernel, cfg):
-    rec = MEASURED_TRAFFIC.get((kernel, cfg["tile_w"], cfg["tile_h"], cfg["persistent"]))
+    rec = MEASURED_TRAFFIC.get((kernel, cfg["tile_w"], cfg["tile_h"], cfg["persistent"], cfg["lds_batch"]))
     if rec is None or rec["sources_sha256"] != sources_sha256():
         return None
     return rec["fetch_bytes"] + rec["write_bytes"]
@@ -103,40 +113,66 @@ def workload(name):
 CPU_CROPS = 8  # seeded 128x128 gradient crops per view in the CPU baseline
 
 
-def cpu_baseline(sc):
-    """Time the FP64 oracle on every view of the workload: the full forward
-    image, and the gradient over eight seeded 128x128 crops scaled to the
-    whole view (about 10-15 s of host work at 16 threads)."""
+def cpu_baseline(sc, fp32=False, views=None, crops=CPU_CROPS):
+    """Time the oracle (FP64, or its FP32 build) on views of the workload
+    (all by default): the full forward image, and the gradient over seeded
+    128x128 crops scaled to the whole view."""
     import oracle
     rng = np.random.default_rng(7)
     t_total, blends, crop_px_total, t_fwd_total, t_grad_total = 0.0, 0.0, 0, 0.0, 0.0
-    for v, cam in enumerate(sc.cameras):
+    views = list(range(len(sc.cameras))) if views is None else list(views)
+    for v in views:
+        cam = sc.cameras[v]
         g = sc.sets[sc.view_set[v]]
         W, H = cam.width, cam.height
         t0 = time.perf_counter()
-        ref = oracle.render(g, cam)
+        ref = oracle.render(g, cam, fp32=fp32)
         t_fwd = time.perf_counter() - t0
         skip = np.ones((H, W), np.uint8)
         cw, ch = min(128, W), min(128, H)
-        for _ in range(CPU_CROPS):
+        for _ in range(crops):
             x0 = int(rng.integers(0, W - cw + 1)); y0 = int(rng.integers(0, H - ch + 1))
             skip[y0:y0 + ch, x0:x0 + cw] = 0
         crop_px = int((skip == 0).sum())
         gr, gd, ga = (w.astype(np.float64) for w in sc.weights[v])
         t0 = time.perf_counter()
-        oracle.grad(g, cam, gr, gd, ga, skip=skip)
+        oracle.grad(g, cam, gr, gd, ga, skip=skip, fp32=fp32)
         t_grad = time.perf_counter() - t0
         t_total += t_fwd + t_grad * (W * H) / crop_px
         blends += float(ref["n_blend"].sum())
         crop_px_total += crop_px
         t_fwd_total += t_fwd
         t_grad_total += t_grad
-    nv = len(sc.cameras)
+    nv = len(views)
+    prec = "FP32" if fp32 else "FP64"
     return {"value": nv / t_total, "unit": "views/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"all {nv} views of the workload: FP64 forward on each full view ({t_fwd_total:.1f} s) and the "
-                      f"gradient on {CPU_CROPS} seeded 128x128 crops per view ({crop_px_total} px, {t_grad_total:.1f} s), "
+            "precision": prec,
+            "sample": f"{nv} view(s) of the workload: {prec} forward on each full view ({t_fwd_total:.1f} s) and the "
+                      f"gradient on {crops} seeded 128x128 crops per view ({crop_px_total} px, {t_grad_total:.1f} s), "
                       f"scaled by pixel count",
             "blends_per_sec": blends / t_total, "seconds_measured": t_fwd_total + t_grad_total}
+
+
+def cpu_oracle_configs(names):
+    """The oracle (FP64 and FP32 builds) on a bounded sample of each other
+    workload: C1 and C2 (one view each), one view of each resolution of the
+    mixed corridor, one street view."""
+    out = {}
+    for name in names:
+        sc, _ = workload(name)
+        if name == "c4-mixed":
+            first = {}
+            for v, c in enumerate(sc.cameras):
+                first.setdefault((c.width, c.height), v)
+            views = sorted(first.values())
+        elif name == "c5":
+            views = [9]
+        else:
+            views = [0]
+        out[name] = {"fp64": cpu_baseline(sc, views=views), "fp32": cpu_baseline(sc, fp32=True, views=views)}
+        log(f"[bench] CPU oracle {name}: FP64 {out[name]['fp64']['value']:.3f} views/s, "
+            f"FP32 {out[name]['fp32']['value']:.3f} views/s")
+    return out
 
 
 LOSS_BYTES_PER_PIXEL = 52.0  # rendered colour+depth and target colour+depth read (32 B), 3+1+1 gradient planes written
@@ -438,6 +474,173 @@ def time_registration(steps, voxel=1.0, cap=20, tau=3.0, sigma=1.0):
                             "queries_per_sec": scan.shape[0] / (ms_iter * 1e-3)}}
 
 
+def stage_rooflines(st, stage_ms, n_gauss, nv, peaks):
+    """Per stage of the step: algorithmic HBM bytes, FP32 FLOP, LDS bytes
+    delivered to lanes and transcendental operations, from the counters of
+    the timed pass, and t_roof = the largest of bytes / 8 TB/s, FLOP / 157.3
+    TFLOP/s, LDS bytes / the measured broadcast LDS rate and transcendentals
+    / the measured exp2 rate."""
+    R, V, P = st["n_records"], st["n_visible"], st["n_pairs"]
+    E, B, px, T = st["n_evaluated"], st["n_blended"], st["n_pixels"], st["n_tiles"]
+    fs, bs, ba = st["n_fwd_steps"], st["n_bwd_steps"], st["n_bwd_active"]
+    waves_per_tile = st["tile_w"] * st["tile_h"] // 64
+    sort_passes = math.ceil(math.ceil(math.log2(max(T, 2))) / 8)
+    work = {
+        "project": {"hbm_bytes": 56.0 * n_gauss + 76.0 * V + 4.0 * R},
+        "scan": {"hbm_bytes": 12.0 * R + 8.0 * V},
+        "depth_order": {"hbm_bytes": (4 * 20.0 + 20.0 + 12.0) * V},
+        "emit": {"hbm_bytes": 16.0 * V + 8.0 * P},
+        "sort": {"hbm_bytes": SORT_BYTES_PER_PAIR_PASS * sort_passes * P},
+        "ranges": {"hbm_bytes": 4.0 * P + 8.0 * T},
+        "composite_forward": {"hbm_bytes": PAIR_STAGE_BYTES * P + FWD_PIXEL_BYTES * px,
+                              "flop": FWD_FLOP_PER_EVAL * E + FWD_FLOP_PER_BLEND * B,
+                              "lds_bytes": FWD_LDS_PER_STEP * fs + (LDS_PER_STAGED + LDS_PER_STAGED_TEST *
+                                                                    waves_per_tile) * P,
+                              "trans": float(E)},
+        "composite_backward": {"hbm_bytes": PAIR_STAGE_BYTES * P + BWD_PIXEL_BYTES * px + ACC_ROW_BYTES * V,
+                               "flop": BWD_FLOP_PER_BLEND * B,
+                               "lds_bytes": BWD_LDS_PER_STEP * bs + BWD_LDS_PER_ACTIVE * ba + LDS_PER_STAGED * P,
+                               "trans": 2.0 * B},
+        "project_backward": {"hbm_bytes": 112.0 * n_gauss + 80.0 * V},
+        "pose_reduce": {"hbm_bytes": 0.0},
+    }
+    out = {}
+    for name, ms in stage_ms.items():
+        if name not in work:
+            continue
+        w = dict(hbm_bytes=0.0, flop=0.0, lds_bytes=0.0, trans=0.0)
+        w.update(work[name])
+        t = {"hbm": w["hbm_bytes"] / (HBM_PEAK_GBS * 1e9), "alu": w["flop"] / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
+             "lds": w["lds_bytes"] / (peaks["lds_broadcast_GBs"] * 1e9), "trans": w["trans"] / (peaks["exp2_Tps"] * 1e12)}
+        bound = max(t, key=t.get)
+        t_roof = t[bound] * 1e3
+        row = dict(w, ms=ms, bound=bound, t_roof_ms=t_roof, frac=t_roof / ms if ms > 0 else None,
+                   hbm_GBs=w["hbm_bytes"] / (ms * 1e-3) / 1e9, lds_GBs=w["lds_bytes"] / (ms * 1e-3) / 1e9)
+        out[name] = row
+    return out
+
+
+def measure_workload(sc, args, ctx, tile, steps, warmup, one_view=True):
+    """One workload on the GPU: a searched, graph-captured window over all
+    its views (the timed step), the per-stage HIP-event times of the same
+    configuration launched without the graph, and the same views one per
+    launch."""
+    import torch
+    from paper_2505_18992_amd import RenderWindow, render, render_backward
+    dev = torch.device("cuda:0")
+    sets = [tuple(torch.from_numpy(a).to(dev) for a in g.arrays()) for g in sc.sets]
+    gw = [tuple(torch.from_numpy(w).to(dev) for w in ws) for ws in sc.weights]
+    cams, vset = sc.cameras, sc.view_set
+    nv = len(cams)
+    # the mapping-window launch: all views bound, tuned, captured in HIP graphs
+    t0 = time.perf_counter()
+    win = RenderWindow(sets, cams, vset, tile=tile, persistent=args.persistent, use_graph=True,
+                       lds_batch=args.lds_batch, tune_cache=args.tune_cache or None)
+    cfg = win.config()
+    t_tune = time.perf_counter() - t0
+    log(f"[bench] window ready in {t_tune:.1f} s: tile {cfg['tile_w']}x{cfg['tile_h']}, "
+        f"persistent {cfg['persistent']}, lds batch {cfg['lds_batch']}, pair capacity {cfg['pair_capacity']}")
+    for v in range(nv):
+        for dst, src in zip(win.grad_out[v], gw[v]):
+            dst.copy_(src)
+    for _ in range(warmup):
+        win.run()
+    torch.cuda.synchronize()
+
+    # timed region: K whole steps (forward + backward of every view)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        win.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / steps
+    st = win.stats()
+    if st["overflow"]:
+        raise SystemExit("pair capacity overflow in the timed pass")
+    log(f"[bench] {steps} steps: {ms_step:.3f} ms/step")
+
+    # per-stage HIP-event timing: the same configuration launched without the
+    # graph (events recorded on the launch stream around every stage)
+    twin = RenderWindow(sets, cams, vset, tile=(cfg["tile_w"], cfg["tile_h"]), persistent=cfg["persistent"],
+                        use_graph=False, pair_capacity=cfg["pair_capacity"], lds_batch=cfg["lds_batch"])
+    for v in range(nv):
+        for dst, src in zip(twin.grad_out[v], gw[v]):
+            dst.copy_(src)
+    twin.run()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        twin.run()
+    torch.cuda.synchronize()
+    ms_eager_window = (time.perf_counter() - t0) * 1e3 / steps
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    twin.close()
+    stage_ms = {k: v[1] / max(v[0], 1) for k, v in prof.items() if v[0] > 0}
+    # fills run in both halves: per step, not per launch sequence
+    if "fill" in prof:
+        stage_ms["fill"] = prof["fill"][1] / steps
+    log("[bench] stage ms/step: " + ", ".join(f"{k}={v:.3f}" for k, v in sorted(stage_ms.items(), key=lambda x: -x[1])))
+
+    # one view per launch: the same kernels, each view its own forward+backward call
+    ms_per_view_launch = None
+    per_view_caps = []
+
+    def one_view_pass():
+        for v in range(nv):
+            outs, saved = render([sets[vset[v]]], [cams[v]], [0], tile=(cfg["tile_w"], cfg["tile_h"]),
+                                 pair_capacity=per_view_caps[v], lds_batch=cfg["lds_batch"],
+                                 grid_ctas=cfg["persistent"])
+            render_backward(saved, [gw[v]])
+            saved.close()
+    if one_view:
+        for v in range(nv):
+            outs, saved = render([sets[vset[v]]], [cams[v]], [0], tile=(cfg["tile_w"], cfg["tile_h"]),
+                                 lds_batch=cfg["lds_batch"], grid_ctas=cfg["persistent"])
+            per_view_caps.append(int(saved.stats()["n_pairs"] * 1.25) + 4096)
+            saved.close()
+        one_view_pass()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = max(2, steps // 4)
+        for _ in range(reps):
+            one_view_pass()
+        torch.cuda.synchronize()
+        ms_per_view_launch = (time.perf_counter() - t0) * 1e3 / reps
+        log(f"[bench] one view per launch: {ms_per_view_launch:.3f} ms for {nv} views; "
+            f"eager window {ms_eager_window:.3f} ms")
+    return {"win": win, "cfg": cfg, "stats": st, "stage_ms": stage_ms, "ms_step": ms_step, "sets": sets, "gw": gw,
+            "n_gauss": sum(g.n for g in sc.sets), "ms_per_view_launch": ms_per_view_launch, "tune_seconds": t_tune,
+            "ms_eager_window": ms_eager_window}
+
+
+def config_line(name, sc, desc, m, peaks):
+    """The summary of one workload measured in the same run."""
+    st, ms, nv = m["stats"], m["ms_step"], len(sc.cameras)
+    table = stage_rooflines(st, m["stage_ms"], m["n_gauss"], nv, peaks)
+    dom = max(m["stage_ms"], key=m["stage_ms"].get)
+    row = table.get(dom, {})
+    t_roof = sum(r["t_roof_ms"] for r in table.values())
+    out = {"workload": desc, "views": nv, "gaussians": m["n_gauss"],
+           "resolutions": sorted({f"{c.width}x{c.height}" for c in sc.cameras}),
+           "ms_per_step": ms, "views_per_sec": nv / (ms * 1e-3), "blends_per_sec": st["n_blended"] / (ms * 1e-3),
+           "counts": {"pairs": st["n_pairs"], "evaluated": st["n_evaluated"], "blended": st["n_blended"]},
+           "window": {k: m["cfg"][k] for k in ("tile_w", "tile_h", "persistent", "lds_batch")},
+           "dominant_kernel": dom, "dominant_ms": m["stage_ms"].get(dom),
+           "dominant_frac": (row["flop"] / (row["ms"] * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS
+                             if row.get("flop") else row["hbm_bytes"] / (row["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS)
+           if row else None,
+           "step_roofline_frac": t_roof / ms}
+    if m["ms_per_view_launch"] is not None:
+        out["one_view_per_launch"] = {"ms_for_all_views": m["ms_per_view_launch"],
+                                      "views_per_sec": nv / (m["ms_per_view_launch"] * 1e-3),
+                                      "batched_speedup": m["ms_per_view_launch"] / ms}
+    log(f"[bench] {name}: {ms:.3f} ms/step, {out['views_per_sec']:.0f} views/s, "
+        f"{out['blends_per_sec'] / 1e9:.1f} G blends/s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -456,6 +659,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mapping-loss, expansion, distillation and registration measurements "
                          "(profiling runs of the step alone)")
+    ap.add_argument("--configs", default="c1,c2,c4-mixed,c5",
+                    help="other workloads measured in the same run (comma list, '' for none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -463,98 +668,19 @@ def main():
         return 2
 
     import torch
-    from paper_2505_18992_amd import RenderWindow, _lib, get_context, render, render_backward
+    from paper_2505_18992_amd import _lib, get_context
 
     _lib.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    log(f"[bench] building workload {args.workload}")
-    sc, desc = workload(args.workload)
-    sets = [tuple(torch.from_numpy(a).to(dev) for a in g.arrays()) for g in sc.sets]
-    gw = [tuple(torch.from_numpy(w).to(dev) for w in ws) for ws in sc.weights]
-    cams, vset = sc.cameras, sc.view_set
-    nv = len(cams)
-    n_gauss = sum(g.n for g in sc.sets)
     ctx = get_context(0)
     tile = None if args.tile == "auto" else tuple(int(x) for x in args.tile.split("x"))
-
-    # the mapping-window launch: all views bound, tuned, captured in HIP graphs
-    t0 = time.perf_counter()
-    win = RenderWindow(sets, cams, vset, tile=tile, persistent=args.persistent, use_graph=True,
-                       lds_batch=args.lds_batch, tune_cache=args.tune_cache or None)
-    cfg = win.config()
-    t_tune = time.perf_counter() - t0
-    log(f"[bench] window ready in {t_tune:.1f} s: tile {cfg['tile_w']}x{cfg['tile_h']}, "
-        f"persistent {cfg['persistent']}, lds batch {cfg['lds_batch']}, pair capacity {cfg['pair_capacity']}")
-    for v in range(nv):
-        for dst, src in zip(win.grad_out[v], gw[v]):
-            dst.copy_(src)
-    for _ in range(args.warmup):
-        win.run()
-    torch.cuda.synchronize()
-
-    # timed region: K whole steps (forward + backward of every view)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        win.run()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    st = win.stats()
-    if st["overflow"]:
-        raise SystemExit("pair capacity overflow in the timed pass")
-    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step")
-
-    # per-stage HIP-event timing: the same configuration launched without the
-    # graph (events recorded on the launch stream around every stage)
-    twin = RenderWindow(sets, cams, vset, tile=(cfg["tile_w"], cfg["tile_h"]), persistent=cfg["persistent"],
-                        use_graph=False, pair_capacity=cfg["pair_capacity"], lds_batch=cfg["lds_batch"])
-    for v in range(nv):
-        for dst, src in zip(twin.grad_out[v], gw[v]):
-            dst.copy_(src)
-    twin.run()
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        twin.run()
-    torch.cuda.synchronize()
-    ms_eager_window = (time.perf_counter() - t0) * 1e3 / args.steps
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    twin.close()
-    stage_ms = {k: v[1] / max(v[0], 1) for k, v in prof.items() if v[0] > 0}
-    # fills run in both halves: per step, not per launch sequence
-    if "fill" in prof:
-        stage_ms["fill"] = prof["fill"][1] / args.steps
-    log("[bench] stage ms/step: " + ", ".join(f"{k}={v:.3f}" for k, v in sorted(stage_ms.items(), key=lambda x: -x[1])))
-
-    # one view per launch: the same kernels, each view its own forward+backward call
-    ms_per_view_launch = None
-    per_view_caps = []
-    def one_view_pass():
-        for v in range(nv):
-            outs, saved = render([sets[vset[v]]], [cams[v]], [0], tile=(cfg["tile_w"], cfg["tile_h"]),
-                                 pair_capacity=per_view_caps[v], lds_batch=cfg["lds_batch"],
-                                 grid_ctas=cfg["persistent"])
-            render_backward(saved, [gw[v]])
-            saved.close()
-    if not args.no_one_view:
-        for v in range(nv):
-            outs, saved = render([sets[vset[v]]], [cams[v]], [0], tile=(cfg["tile_w"], cfg["tile_h"]),
-                                 lds_batch=cfg["lds_batch"], grid_ctas=cfg["persistent"])
-            per_view_caps.append(int(saved.stats()["n_pairs"] * 1.25) + 4096)
-            saved.close()
-        one_view_pass()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        reps = max(2, args.steps // 4)
-        for _ in range(reps):
-            one_view_pass()
-        torch.cuda.synchronize()
-        ms_per_view_launch = (time.perf_counter() - t0) * 1e3 / reps
-        log(f"[bench] one view per launch: {ms_per_view_launch:.3f} ms for {nv} views; "
-            f"eager window {ms_eager_window:.3f} ms")
+    log(f"[bench] building workload {args.workload}")
+    sc, desc = workload(args.workload)
+    m = measure_workload(sc, args, ctx, tile, args.steps, args.warmup, one_view=not args.no_one_view)
+    win, cfg, st, stage_ms, ms_step = m["win"], m["cfg"], m["stats"], m["stage_ms"], m["ms_step"]
+    sets, gw, cams, vset, nv, n_gauss = m["sets"], m["gw"], sc.cameras, sc.view_set, len(sc.cameras), m["n_gauss"]
+    ms_per_view_launch, t_tune = m["ms_per_view_launch"], m["tune_seconds"]
 
     loss_stage = expansion = distillation = registration = anchor_decode = None
     if not args.no_extras:
@@ -571,23 +697,44 @@ def main():
         anchor_decode = time_decode(args.steps)
 
     E, B, P = st["n_evaluated"], st["n_blended"], st["n_pairs"]
+    peaks = ctx.measure_peaks()
+    log("[bench] measured peaks: " + ", ".join(f"{k}={v:.1f}" for k, v in peaks.items()))
+    table = stage_rooflines(st, stage_ms, n_gauss, nv, peaks)
     dom = max(stage_ms, key=stage_ms.get)
-    t_dom = stage_ms[dom] * 1e-3
-    if dom == "composite_forward":
-        work = FWD_FLOP_PER_EVAL * E + FWD_FLOP_PER_BLEND * B
-        roof = {"bound": "alu", "achieved": work / t_dom / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s"}
-    elif dom == "composite_backward":
-        work = BWD_FLOP_PER_EVAL * E + BWD_FLOP_PER_BLEND * B
-        roof = {"bound": "alu", "achieved": work / t_dom / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    row = table[dom]
+    if dom in ("composite_forward", "composite_backward"):
+        roof = {"bound": "alu", "achieved": row["flop"] / (row["ms"] * 1e-3) / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
     else:
-        passes = math.ceil(math.ceil(math.log2(max(st["n_tiles"], 2))) / 8)
-        work = SORT_BYTES_PER_PAIR_PASS * passes * P
-        roof = {"bound": "hbm", "achieved": work / t_dom / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        roof = {"bound": "hbm", "achieved": row["hbm_bytes"] / (row["ms"] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic(dom, cfg)
     roof["kernel"] = dom
-    roof["kernel_ms"] = stage_ms[dom]
-    roof["work_per_launch"] = work
+    roof["kernel_ms"] = row["ms"]
+    roof["work_per_launch"] = row["flop"] if roof["unit"] == "TFLOP/s" else row["hbm_bytes"]
+    roof["work_unit"] = ("FLOP: 60 per blend" if dom == "composite_backward" else
+                         "FLOP: 15 per evaluation + 12 per blend" if dom == "composite_forward" else "HBM bytes")
+    roof["frac_of_measured_fp32"] = (roof["achieved"] / peaks["fp32_fma_TFLOPs"]
+                                     if roof["unit"] == "TFLOP/s" else None)
+    t_roof = sum(r["t_roof_ms"] for r in table.values())
+    step_roofline = {"t_roof_ms": t_roof, "t_measured_ms": ms_step, "frac": t_roof / ms_step,
+                     "stage_sum_ms": sum(r["ms"] for r in table.values()), "stages": table,
+                     "peaks_used": {"hbm_GBs": HBM_PEAK_GBS, "fp32_TFLOPs": FP32_VECTOR_PEAK_TFLOPS,
+                                    "lds_broadcast_GBs": peaks["lds_broadcast_GBs"], "exp2_Tps": peaks["exp2_Tps"]}}
+    log(f"[bench] step roofline: sum of per-stage t_roof {t_roof:.3f} ms of {ms_step:.3f} ms measured "
+        f"({t_roof / ms_step:.1%})")
+
+    # the other workloads, each a searched window over all its views
+    others = {}
+    for name in [c for c in args.configs.split(",") if c and c != args.workload]:
+        log(f"[bench] building workload {name}")
+        osc, odesc = workload(name)
+        om = measure_workload(osc, args, ctx, None, max(5, args.steps // 2), 2, one_view=True)
+        om["win"].close()
+        others[name] = config_line(name, osc, odesc, om, peaks)
+        del om, osc
+        torch.cuda.empty_cache()
 
     views_per_s = nv / (ms_step * 1e-3)
     out = {
@@ -620,10 +767,15 @@ def main():
         "registration": registration,
         "decode": anchor_decode,
         "roofline": roof,
+        "step_roofline": step_roofline,
+        "measured_peaks": peaks,
+        "other_configs": others,
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(sc)
+        out["cpu_baseline_fp32"] = cpu_baseline(sc, fp32=True)
+        out["cpu_oracle_configs"] = cpu_oracle_configs([c for c in args.configs.split(",") if c])
     print(json.dumps(out), flush=True)
     return 0
 

@@ -152,6 +152,12 @@ typedef struct {
   int32_t overflow;    /* 1 if the pair list overflowed */
   int32_t tile_w, tile_h;
   int32_t lds_batch;   /* entries staged per compositing batch */
+  /* compositing work in wavefront steps: one step is one wavefront (64
+   * pixels) taking one Gaussian of its hit list.  The backward counts add up
+   * over the backward calls of a forward. */
+  int64_t n_fwd_steps;   /* forward steps */
+  int64_t n_bwd_steps;   /* backward steps */
+  int64_t n_bwd_active;  /* backward steps in which some pixel takes a gradient */
 } vpgs_stats;
 
 /* ---- context ------------------------------------------------------------- */
@@ -306,6 +312,21 @@ int vpgs_window_destroy(vpgs_window* win);
 #define VPGS_NUM_STAGES 20
 int vpgs_profile_enable(vpgs_ctx* ctx, int on);
 int vpgs_profile_read(vpgs_ctx* ctx, int stage, const char** name, int64_t* calls, double* total_ms);
+
+/* Microbenchmarks of the device rates the kernels of this library are held
+ * against (diagnostics; synchronous on `stream`).  Writes out (host, 5
+ * doubles):
+ *   [0] LDS read bandwidth, a distinct 16-byte address per lane (GB/s of
+ *       data delivered to lanes)
+ *   [1] LDS read bandwidth, one 16-byte address per wavefront (a broadcast,
+ *       the compositors' pattern; GB/s delivered to lanes)
+ *   [2] FP32 fused-multiply-add rate, 2 FLOP each (TFLOP/s; the library is
+ *       built without packed FP32 instructions)
+ *   [3] exp2 rate (T/s)
+ *   [4] HBM copy bandwidth (GB/s of bytes read plus written)
+ * Eight workgroups of 256 lanes per compute unit; the copy uses a 512 MiB
+ * workspace buffer of the context. */
+int vpgs_measure_peaks(vpgs_ctx* ctx, double* out, void* stream);
 
 /* ---- anchor decoder (Section III-A, eq. 1-5) ------------------------------- */
 

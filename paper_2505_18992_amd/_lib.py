@@ -61,7 +61,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("n_records", ctypes.c_int64), ("n_visible", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
                 ("n_evaluated", ctypes.c_int64), ("n_blended", ctypes.c_int64), ("pair_capacity", ctypes.c_int64),
                 ("n_tiles", ctypes.c_int64), ("n_pixels", ctypes.c_int64), ("overflow", ctypes.c_int32),
-                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("lds_batch", ctypes.c_int32)]
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("lds_batch", ctypes.c_int32),
+                ("n_fwd_steps", ctypes.c_int64), ("n_bwd_steps", ctypes.c_int64), ("n_bwd_active", ctypes.c_int64)]
 
 
 class WindowOpts(ctypes.Structure):
@@ -184,6 +185,7 @@ SIGNATURES = {
     "vpgs_icp_linearize_noalloc": (ctypes.c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_int64,
                                                   ctypes.POINTER(ctypes.c_double), ctypes.c_float, ctypes.c_float,
                                                   c_void_p, c_void_p]),
+    "vpgs_measure_peaks": (ctypes.c_int, [c_void_p, ctypes.POINTER(ctypes.c_double), c_void_p]),
     "vpgs_icp_register": (ctypes.c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_int64,
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(IcpOpts), ctypes.POINTER(ctypes.c_double),

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libvpgs.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["project.hip", "scan.hip", "sort.hip", "composite.hip", "decode.hip", "loss.hip", "densify.hip", "distill.hip", "icp.hip", "runtime.cpp",
+SOURCES = ["project.hip", "scan.hip", "sort.hip", "composite.hip", "decode.hip", "loss.hip", "densify.hip", "distill.hip", "icp.hip", "peaks.hip", "runtime.cpp",
            "window.cpp"]
 ARCH = "gfx950"
 

@@ -187,7 +187,8 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
                                              const uint2* __restrict__ ranges,
                                              const uint32_t* __restrict__ vals, float* __restrict__ T_final,
                                              uint32_t* __restrict__ n_contrib, uint64_t* __restrict__ masks,
-                                             uint32_t tile, FwdShared<TW, TH, NB>& sh, uint32_t& ne, uint32_t& nb) {
+                                             uint32_t tile, FwdShared<TW, TH, NB>& sh, uint32_t& ne, uint32_t& nb,
+                                             uint32_t& nsteps) {
   constexpr int BS = TW * TH;     // threads: one per pixel
   constexpr int WV = BS / 64;     // wavefronts per tile
   constexpr int PER = NB > BS ? NB / BS : 1;  // entries each thread stages
@@ -246,7 +247,8 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
     const int nhit = wave_hits<NB>(sh.A, sh.E, sh.V, (int)min((uint32_t)NB, rg.y - start), q, hits, wm);
     __syncthreads();
     const uint32_t base = start - rg.x + 1u;
-    for (int g = 0; g < nhit && __ballot(!done) != 0ull; g += kGroup) {
+    int g = 0;
+    for (; g < nhit && __ballot(!done) != 0ull; g += kGroup) {
 #pragma unroll
       for (int u = 0; u < kGroup; ++u) {
         const int j = hits[g + u];
@@ -269,6 +271,7 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
         done = done || stop;
       }
     }
+    nsteps += (uint32_t)min(g, nhit);  // the same in every lane of the wavefront
   }
   if (inside) {
     const size_t HW = (size_t)V.W * V.H;
@@ -283,18 +286,45 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
   }
 }
 
-// Evaluation and blend counters: wave sums, one atomic per wave.
-__device__ __forceinline__ void flush_counts(uint32_t ne, uint32_t nb, Counters* cnt) {
+// Work counters: wave sums added in LDS (wg[], zeroed by thread 0 before
+// the first barrier of the kernel), then one global atomic per counter and
+// workgroup, spread over kCountSlots slots.  The step counts are the same in
+// every lane of a wavefront (lane 0's is added).
+__device__ __forceinline__ void flush_counts(uint32_t ne, uint32_t nb, uint32_t nsteps, unsigned long long* wg,
+                                             Counters* cnt) {
   unsigned long long e = ne, b = nb;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     e += __shfl_xor(e, off, 64);
     b += __shfl_xor(b, off, 64);
   }
+  __syncthreads();
   if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&wg[0], e);
+    atomicAdd(&wg[1], b);
+    atomicAdd(&wg[2], (unsigned long long)nsteps);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
     const int slot = (int)(blockIdx.x % kCountSlots);
-    atomicAdd(&cnt->evaluated[slot], e);
-    atomicAdd(&cnt->blended[slot], b);
+    atomicAdd(&cnt->evaluated[slot], wg[0]);
+    atomicAdd(&cnt->blended[slot], wg[1]);
+    atomicAdd(&cnt->fwd_hits[slot], wg[2]);
+  }
+}
+
+__device__ __forceinline__ void flush_backward_counts(uint32_t nsteps, uint32_t nactive, unsigned long long* wg,
+                                                      Counters* cnt) {
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&wg[0], (unsigned long long)nsteps);
+    atomicAdd(&wg[1], (unsigned long long)nactive);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int slot = (int)(blockIdx.x % kCountSlots);
+    atomicAdd(&cnt->bwd_hits[slot], wg[0]);
+    atomicAdd(&cnt->bwd_active[slot], wg[1]);
   }
 }
 
@@ -320,24 +350,26 @@ __global__ void __launch_bounds__(TW * TH, 8) composite_forward_kernel(
     uint32_t* __restrict__ queue, uint32_t n_tiles) {
   __shared__ FwdShared<TW, TH, NB> sh;
   __shared__ uint32_t slot;
-  uint32_t ne = 0, nb = 0;
-  if (threadIdx.x == 0) {  // the sentinel slot (read after the first staging barrier)
+  __shared__ unsigned long long wg[3];
+  uint32_t ne = 0, nb = 0, nsteps = 0;
+  if (threadIdx.x == 0) {  // the sentinel slot (read after the first staging barrier) and the counters
     sh.A[NB] = make_float4(0.f, 0.f, 0.f, 0.f);
     sh.E[NB] = make_float4(0.f, 0.f, 0.f, kNegInf);
     sh.C[NB] = make_float4(0.f, 0.f, 0.f, 0.f);
+    wg[0] = wg[1] = wg[2] = 0ull;
   }
   if (queue == nullptr) {
     const uint32_t tile = order[blockIdx.x];
     if (tile < n_tiles)
-      forward_tile<TW, TH, NB>(tab, recs, ranges, vals, T_final, n_contrib, masks, tile, sh, ne, nb);
+      forward_tile<TW, TH, NB>(tab, recs, ranges, vals, T_final, n_contrib, masks, tile, sh, ne, nb, nsteps);
   } else {
     for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot)) {
       const uint32_t tile = order[t];
       if (tile < n_tiles)
-        forward_tile<TW, TH, NB>(tab, recs, ranges, vals, T_final, n_contrib, masks, tile, sh, ne, nb);
+        forward_tile<TW, TH, NB>(tab, recs, ranges, vals, T_final, n_contrib, masks, tile, sh, ne, nb, nsteps);
     }
   }
-  flush_counts(ne, nb, cnt);
+  flush_counts(ne, nb, nsteps, wg, cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -412,7 +444,7 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
                                               const uint32_t* __restrict__ vals, const float* __restrict__ T_final,
                                               const uint32_t* __restrict__ n_contrib, float* __restrict__ acc,
                                               const uint64_t* __restrict__ masks, uint32_t tile,
-                                              BwdShared<TW, TH, NB>& sh) {
+                                              BwdShared<TW, TH, NB>& sh, uint32_t& nsteps, uint32_t& nactive) {
   constexpr int BS = TW * TH;  // threads: one per pixel
   constexpr int WV = BS / 64;
   const ViewDesc& V = tab->views[view_of_tile(tab, tile)];
@@ -479,12 +511,14 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
                                         min(end, (int)wave_last) - begin, hits);
     __syncthreads();
     const int last_in_batch = (int)last - begin;  // this pixel's entries are the slots below it
+    nsteps += (uint32_t)nhit;
     for (int i = 0; i < nhit; ++i) {
       const int sl = hits[i];
       const float4 A = sh.A[sl];
       const Falloff f = falloff(A, sh.E[sl], pxc, pyc);
       const bool valid = sl < last_in_batch && f.alpha >= kAlphaMin;
       if (__ballot(valid) == 0ull) continue;
+      ++nactive;
       const float4 c = sh.C[sl];
       const float r1m = __builtin_amdgcn_rcpf(1.0f - f.alpha);
       const float Tj = valid ? T * r1m : T;
@@ -527,24 +561,29 @@ __global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
     const uint32_t* __restrict__ vals,
     const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib, float* __restrict__ acc,
     const uint64_t* __restrict__ masks, const uint32_t* __restrict__ order, uint32_t* __restrict__ queue,
-    uint32_t n_tiles) {
+    Counters* __restrict__ cnt, uint32_t n_tiles) {
   __shared__ BwdShared<TW, TH, NB> sh;
   __shared__ uint32_t slot;
-  if (threadIdx.x == 0) {  // the sentinel slot (read after the first staging barrier)
+  __shared__ unsigned long long wg[2];
+  uint32_t nsteps = 0, nactive = 0;
+  if (threadIdx.x == 0) {  // the sentinel slot (read after the first staging barrier) and the counters
     sh.A[NB] = make_float4(0.f, 0.f, 0.f, 0.f);
     sh.E[NB] = make_float4(0.f, 0.f, 0.f, kNegInf);
+    wg[0] = wg[1] = 0ull;
   }
   if (queue == nullptr) {
     const uint32_t tile = order[blockIdx.x];
     if (tile < n_tiles)
-      backward_tile<TW, TH, NB>(tab, recs, ranges, vals, T_final, n_contrib, acc, masks, tile, sh);
+      backward_tile<TW, TH, NB>(tab, recs, ranges, vals, T_final, n_contrib, acc, masks, tile, sh, nsteps, nactive);
   } else {
     for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot)) {
       const uint32_t tile = order[t];
       if (tile < n_tiles)
-        backward_tile<TW, TH, NB>(tab, recs, ranges, vals, T_final, n_contrib, acc, masks, tile, sh);
+        backward_tile<TW, TH, NB>(tab, recs, ranges, vals, T_final, n_contrib, acc, masks, tile, sh, nsteps,
+                                  nactive);
     }
   }
+  flush_backward_counts(nsteps, nactive, wg, cnt);
 }
 
 template <int TW, int TH, int NB>
@@ -560,11 +599,11 @@ hipError_t launch_fwd_t(const CallTables* d_tab, const CallTables& h, const Proj
 template <int TW, int TH, int NB>
 hipError_t launch_bwd_t(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb, const uint2* ranges,
                         const uint32_t* vals, const uint32_t* order, const float* T_final,
-                        const uint32_t* n_contrib, const uint64_t* masks, float* acc, uint32_t* queue,
-                        uint32_t blocks, hipStream_t s) {
+                        const uint32_t* n_contrib, const uint64_t* masks, float* acc, Counters* cnt,
+                        uint32_t* queue, uint32_t blocks, hipStream_t s) {
   const uint32_t grid = queue ? blocks : h.n_tiles;
   hipLaunchKernelGGL((composite_backward_kernel<TW, TH, NB>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.rec,
-                     ranges, vals, T_final, n_contrib, acc, masks, order, queue, h.n_tiles);
+                     ranges, vals, T_final, n_contrib, acc, masks, order, queue, cnt, h.n_tiles);
   return hipGetLastError();
 }
 
@@ -607,13 +646,13 @@ hipError_t launch_composite_forward(const CallTables* d_tab, const CallTables& h
 hipError_t launch_composite_backward(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb,
                                      const uint2* ranges, const uint32_t* vals, const uint32_t* order,
                                      const float* T_final, const uint32_t* n_contrib, const uint64_t* masks,
-                                     float* acc, int tile_w, int tile_h, int lds_batch, uint32_t* queue,
-                                     uint32_t blocks, hipStream_t s) {
+                                     float* acc, Counters* cnt, int tile_w, int tile_h, int lds_batch,
+                                     uint32_t* queue, uint32_t blocks, hipStream_t s) {
   if (h.n_tiles == 0) return hipSuccess;
 #define VPGS_BWD(TW, TH, NB) \
   if (tile_w == TW && tile_h == TH && lds_batch == NB) \
-    return launch_bwd_t<TW, TH, NB>(d_tab, h, pb, ranges, vals, order, T_final, n_contrib, masks, acc, queue, \
-                                    blocks, s);
+    return launch_bwd_t<TW, TH, NB>(d_tab, h, pb, ranges, vals, order, T_final, n_contrib, masks, acc, cnt, \
+                                    queue, blocks, s);
   VPGS_SHAPES(VPGS_BWD)
 #undef VPGS_BWD
   return hipErrorInvalidValue;

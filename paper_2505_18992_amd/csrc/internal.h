@@ -84,6 +84,9 @@ constexpr int kOrderBuckets = 66;
 struct Counters {
   unsigned long long evaluated[kCountSlots];
   unsigned long long blended[kCountSlots];
+  unsigned long long fwd_hits[kCountSlots];    // (wavefront, hit-list entry) steps of the forward
+  unsigned long long bwd_hits[kCountSlots];    // and of the backward (added over backward calls)
+  unsigned long long bwd_active[kCountSlots];  // backward steps in which some lane contributes
   uint32_t pairs;      // pairs requested by the scan
   uint32_t overflow;   // 1 if pairs > capacity
   uint32_t visible;
@@ -224,8 +227,8 @@ hipError_t launch_composite_forward(const CallTables* d_tab, const CallTables& h
 hipError_t launch_composite_backward(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
                                      const uint2* ranges, const uint32_t* vals, const uint32_t* order,
                                      const float* T_final, const uint32_t* n_contrib, const uint64_t* masks,
-                                     float* acc, int tile_w, int tile_h, int lds_batch, uint32_t* queue,
-                                     uint32_t blocks, hipStream_t s);
+                                     float* acc, Counters* cnt, int tile_w, int tile_h, int lds_batch,
+                                     uint32_t* queue, uint32_t blocks, hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float value, size_t n, hipStream_t s);

@@ -80,14 +80,35 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
   return r;  // every thread
 }
 
-// Loads the tile's halo window of plane `src` ([H,W]) into lds[kHaloH][kHaloW],
-// zero outside the image.
-__device__ __forceinline__ void load_halo(const float* __restrict__ src, int W, int H, int x0, int y0,
-                                          float (*lds)[kHaloW]) {
-  for (int k = threadIdx.x; k < kHaloH * kHaloW; k += kLossBlock) {
-    const int r = k / kHaloW, c = k - r * kHaloW;
+// Loads the tile's halo window of NP planes (src[q], each [H,W]) into
+// lds[q][kHaloH][kHaloW], zero outside the image.  Every load of the thread
+// is issued before the first LDS write (out-of-image slots read the plane's
+// first element and are replaced by zero), so a thread waits for its global
+// loads once, not once per element.
+constexpr int kHaloPer = (kHaloH * kHaloW + kLossBlock - 1) / kLossBlock;
+template <int NP>
+__device__ __forceinline__ void load_halos(const float* const* src, int W, int H, int x0, int y0,
+                                           float (*lds)[kHaloH][kHaloW]) {
+  float v[NP][kHaloPer];
+  bool in[kHaloPer];
+  int slot[kHaloPer];
+#pragma unroll
+  for (int u = 0; u < kHaloPer; ++u) {
+    const int k = (int)threadIdx.x + u * kLossBlock;
+    const int r = k / kHaloW, c = k - r * kHaloW;  // constant divisor
     const int gy = y0 - kRad + r, gx = x0 - kRad + c;
-    lds[r][c] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? src[(size_t)gy * W + gx] : 0.0f;
+    in[u] = k < kHaloH * kHaloW && gx >= 0 && gx < W && gy >= 0 && gy < H;
+    slot[u] = k;
+    const size_t off = in[u] ? (size_t)gy * W + gx : 0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) v[q][u] = src[q][off];
+  }
+#pragma unroll
+  for (int u = 0; u < kHaloPer; ++u) {
+    if (slot[u] >= kHaloH * kHaloW) continue;
+    const int r = slot[u] / kHaloW, c = slot[u] - r * kHaloW;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) lds[q][r][c] = in[u] ? v[q][u] : 0.0f;
   }
 }
 
@@ -101,16 +122,20 @@ __device__ __forceinline__ void load_halo(const float* __restrict__ src, int W, 
 //   dS/de12 = 2 A1 / (B1 B2)
 // (only B1 >= C1 and B2 >= C2 are divided by; A2 may vanish).
 __global__ void __launch_bounds__(kLossBlock) ssim_stats_kernel(LossBatch batch) {
-  __shared__ float sx[kHaloH][kHaloW], sy[kHaloH][kHaloW];
+  __shared__ float sxy[2][kHaloH][kHaloW];  // x, y
   __shared__ float hs[5][kHaloH][kTileW];  // horizontal sums of x, y, x^2, y^2, xy
   __shared__ float red[kLossBlock / 64];
+  float (*sx)[kHaloW] = sxy[0];
+  float (*sy)[kHaloW] = sxy[1];
   const ViewArgs& a = batch.v[blockIdx.z / 3];
   if ((int)blockIdx.x >= a.tiles_x || (int)blockIdx.y >= a.tiles_y) return;
   const int c = blockIdx.z % 3;
   const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
   const size_t HW = (size_t)a.W * a.H;
-  load_halo(a.x + c * HW, a.W, a.H, x0, y0, sx);
-  load_halo(a.y + c * HW, a.W, a.H, x0, y0, sy);
+  {
+    const float* planes[2] = {a.x + c * HW, a.y + c * HW};
+    load_halos<2>(planes, a.W, a.H, x0, y0, sxy);
+  }
   __syncthreads();
   if (threadIdx.x < kHaloH * (kTileW / kHRun)) {  // kHRun adjacent outputs per thread
     const int r = threadIdx.x / (kTileW / kHRun), j0 = (threadIdx.x % (kTileW / kHRun)) * kHRun;
@@ -227,8 +252,10 @@ __global__ void __launch_bounds__(kLossBlock) ssim_grad_kernel(LossBatch batch, 
   const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
   const size_t HW = (size_t)a.W * a.H;
   const float* P = a.P + (size_t)c * 3 * HW;
-#pragma unroll
-  for (int q = 0; q < 3; ++q) load_halo(P + q * HW, a.W, a.H, x0, y0, sp[q]);
+  {
+    const float* planes[3] = {P, P + HW, P + 2 * HW};
+    load_halos<3>(planes, a.W, a.H, x0, y0, sp);
+  }
   if (c == 0 && threadIdx.x == 0) {  // valid target-depth pixels of the view (first kernel's sums)
     double nv = 0.0;
     for (int k = 0; k < kSumSlots; ++k) nv += a.sums[3 * kSumSlots + k];

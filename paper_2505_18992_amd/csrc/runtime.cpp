@@ -499,8 +499,8 @@ int enqueue_backward(vpgs_ctx* ctx, vpgs_saved* sv, float* d_pose, hipStream_t s
     HIP_TRY(launch_composite_backward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
                                       static_cast<const uint32_t*>(sv->order.p), static_cast<const float*>(sv->tfinal.p),
                                       static_cast<const uint32_t*>(sv->ncontrib.p),
-                                      static_cast<const uint64_t*>(sv->hitmask.p), acc, sv->tile_w, sv->tile_h,
-                                      sv->lds_batch, sv->persistent_blocks ? &cnt->queue_bwd : nullptr,
+                                      static_cast<const uint64_t*>(sv->hitmask.p), acc, cnt, sv->tile_w,
+                                      sv->tile_h, sv->lds_batch, sv->persistent_blocks ? &cnt->queue_bwd : nullptr,
                                       sv->persistent_blocks, st));
   }
   float* partial = d_pose ? static_cast<float*>(sv->pose_partial.p) : nullptr;
@@ -613,6 +613,7 @@ int vpgs_destroy(vpgs_ctx* ctx) {
   free_buf(ctx, ctx->distill_ws);
   free_buf(ctx, ctx->icp_build);
   free_buf(ctx, ctx->icp_ws);
+  free_buf(ctx, ctx->peak_ws);
   if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
   delete ctx;
   return VPGS_OK;
@@ -702,13 +703,19 @@ int vpgs_saved_stats(vpgs_ctx* ctx, const vpgs_saved* saved, vpgs_stats* out, vo
   const CallTables& T = *saved->h_tab;
   out->n_records = T.n_records;
   out->n_pairs = hc->pairs;
-  unsigned long long ev = 0, bl = 0;
+  unsigned long long ev = 0, bl = 0, fh = 0, bh = 0, ba = 0;
   for (int k = 0; k < kCountSlots; ++k) {
     ev += hc->evaluated[k];
     bl += hc->blended[k];
+    fh += hc->fwd_hits[k];
+    bh += hc->bwd_hits[k];
+    ba += hc->bwd_active[k];
   }
   out->n_evaluated = (int64_t)ev;
   out->n_blended = (int64_t)bl;
+  out->n_fwd_steps = (int64_t)fh;
+  out->n_bwd_steps = (int64_t)bh;
+  out->n_bwd_active = (int64_t)ba;
   out->pair_capacity = saved->capacity;
   out->n_tiles = T.n_tiles;
   out->n_pixels = saved->n_pixels;

@@ -65,6 +65,8 @@ struct vpgs_ctx {
   // registration: temporaries of voxel-map builds and downsampling; the
   // per-iteration partial sums and state
   vpgs::DevBuf icp_build, icp_ws;
+  // device-rate microbenchmarks: source and destination of the copy
+  vpgs::DevBuf peak_ws;
   // stage timing
   bool profiling = false;
   std::vector<hipEvent_t> ev_free;

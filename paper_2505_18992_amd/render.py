@@ -92,6 +92,15 @@ class Context:
             out[name.value.decode()] = (calls.value, ms.value)
         return out
 
+    def measure_peaks(self) -> dict:
+        """Measured device rates (vpgs_measure_peaks): LDS read GB/s with
+        distinct and with broadcast addresses, FP32 FMA TFLOP/s, exp2 T/s and
+        HBM copy GB/s."""
+        out = (ctypes.c_double * 5)()
+        check(load().vpgs_measure_peaks(self.handle, out, _stream()), self.handle, "vpgs_measure_peaks")
+        return {"lds_GBs": out[0], "lds_broadcast_GBs": out[1], "fp32_fma_TFLOPs": out[2], "exp2_Tps": out[3],
+                "hbm_copy_GBs": out[4]}
+
     def __del__(self):
         try:
             if not sys.is_finalizing():  # the allocator callbacks need a live interpreter

@@ -87,4 +87,4 @@ def test_structure_layouts_match_the_header():
     assert _lib.WindowOpts.tune_cache.offset == 32
     assert _lib.Anchors.xyz.offset == 16
     assert _lib.Mlp.W1.offset == 8 and ctypes.sizeof(_lib.Mlp) == 8 + 12 * 8
-    assert ctypes.sizeof(_lib.Stats) == 8 * 8 + 4 * 4
+    assert ctypes.sizeof(_lib.Stats) == 8 * 8 + 4 * 4 + 3 * 8
