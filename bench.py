@@ -535,7 +535,7 @@ def measure_workload(sc, args, ctx, tile, steps, warmup, one_view=True):
     # the mapping-window launch: all views bound, tuned, captured in HIP graphs
     t0 = time.perf_counter()
     win = RenderWindow(sets, cams, vset, tile=tile, persistent=args.persistent, use_graph=True,
-                       lds_batch=args.lds_batch, tune_cache=args.tune_cache or None)
+                       lds_batch=args.lds_batch, tune_cache=args.tune_cache or None, count=False)
     cfg = win.config()
     t_tune = time.perf_counter() - t0
     log(f"[bench] window ready in {t_tune:.1f} s: tile {cfg['tile_w']}x{cfg['tile_h']}, "
@@ -558,11 +558,25 @@ def measure_workload(sc, args, ctx, tile, steps, warmup, one_view=True):
     if st["overflow"]:
         raise SystemExit("pair capacity overflow in the timed pass")
     log(f"[bench] {steps} steps: {ms_step:.3f} ms/step")
+    # the timed pass does not count its evaluations and blends (that is
+    # instrumentation): one eager pass of the same configuration with the
+    # counters on gives them (the render is deterministic)
+    cwin = RenderWindow(sets, cams, vset, tile=(cfg["tile_w"], cfg["tile_h"]), persistent=cfg["persistent"],
+                        use_graph=False, pair_capacity=cfg["pair_capacity"], lds_batch=cfg["lds_batch"], count=True)
+    for v in range(nv):
+        for dst, src in zip(cwin.grad_out[v], gw[v]):
+            dst.copy_(src)
+    cwin.run()
+    cst = cwin.stats()
+    cwin.close()
+    for k in ("n_evaluated", "n_blended", "n_fwd_steps"):
+        st[k] = cst[k]
+    assert cst["n_pairs"] == st["n_pairs"] and cst["n_bwd_steps"] == st["n_bwd_steps"]
 
     # per-stage HIP-event timing: the same configuration launched without the
     # graph (events recorded on the launch stream around every stage)
     twin = RenderWindow(sets, cams, vset, tile=(cfg["tile_w"], cfg["tile_h"]), persistent=cfg["persistent"],
-                        use_graph=False, pair_capacity=cfg["pair_capacity"], lds_batch=cfg["lds_batch"])
+                        use_graph=False, pair_capacity=cfg["pair_capacity"], lds_batch=cfg["lds_batch"], count=False)
     for v in range(nv):
         for dst, src in zip(twin.grad_out[v], gw[v]):
             dst.copy_(src)
@@ -591,7 +605,7 @@ def measure_workload(sc, args, ctx, tile, steps, warmup, one_view=True):
         for v in range(nv):
             outs, saved = render([sets[vset[v]]], [cams[v]], [0], tile=(cfg["tile_w"], cfg["tile_h"]),
                                  pair_capacity=per_view_caps[v], lds_batch=cfg["lds_batch"],
-                                 grid_ctas=cfg["persistent"])
+                                 grid_ctas=cfg["persistent"], count=False)
             render_backward(saved, [gw[v]])
             saved.close()
     if one_view:

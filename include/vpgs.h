@@ -129,6 +129,11 @@ typedef vpgs_gauss_buffers vpgs_gauss_grads;
  *                    overflow is reported as VPGS_ECAPACITY by
  *                    vpgs_saved_stats and the outputs of that call are
  *                    invalid).
+ *   skip_counts      1: the forward compositor does not count its (pixel,
+ *                    Gaussian) evaluations and blends (vpgs_stats then
+ *                    reports them as 0); 0 counts them (instrumentation
+ *                    that costs about a seventh of the compositor's
+ *                    per-step instructions).
  * The images do not depend on any of these (the forward is bit-identical
  * across them); the backward's gradients differ only in the order of their
  * floating-point atomic sums. */
@@ -137,6 +142,8 @@ typedef struct {
   int32_t lds_batch;
   int32_t grid_ctas;
   int64_t pair_capacity;
+  int32_t skip_counts;
+  int32_t reserved;
 } vpgs_render_opts;
 
 /* Counters of one forward, filled by vpgs_saved_stats. */
@@ -265,6 +272,8 @@ typedef struct {
   int32_t tune_reps;        /* timed runs per candidate in the search (0 = 3) */
   int32_t lds_batch;        /* 0 = chosen by the search; else as in vpgs_render_opts */
   const char* tune_cache;   /* host path of a JSON tuning cache, or NULL for none */
+  int32_t skip_counts;      /* as in vpgs_render_opts (the search times the window's own setting) */
+  int32_t reserved;
 } vpgs_window_opts;
 
 /* Inputs and outputs as in vpgs_render_forward / vpgs_render_backward, all

@@ -54,7 +54,8 @@ class GaussBuffers(ctypes.Structure):
 
 class RenderOpts(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("lds_batch", ctypes.c_int32),
-                ("grid_ctas", ctypes.c_int32), ("pair_capacity", ctypes.c_int64)]
+                ("grid_ctas", ctypes.c_int32), ("pair_capacity", ctypes.c_int64), ("skip_counts", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -68,7 +69,8 @@ class Stats(ctypes.Structure):
 class WindowOpts(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("pair_capacity", ctypes.c_int64), ("tune_reps", ctypes.c_int32),
-                ("lds_batch", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
+                ("lds_batch", ctypes.c_int32), ("tune_cache", ctypes.c_char_p), ("skip_counts", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Anchors(ctypes.Structure):

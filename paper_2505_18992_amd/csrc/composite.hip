@@ -182,7 +182,7 @@ __device__ __forceinline__ size_t batch_mask_index(uint32_t start, uint32_t tile
   return (slot * WV + wave) * (NB / 64);
 }
 
-template <int TW, int TH, int NB>
+template <int TW, int TH, int NB, bool COUNT>
 __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab, const float4* __restrict__ recs,
                                              const uint2* __restrict__ ranges,
                                              const uint32_t* __restrict__ vals, float* __restrict__ T_final,
@@ -255,7 +255,7 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
         const float4 A = sh.A[j];
         const Falloff f = falloff(A, sh.E[j], pxc, pyc);
         const float4 c = sh.C[j];
-        ne += (g + u < nhit && !done) ? 1u : 0u;
+        if (COUNT) ne += (g + u < nhit && !done) ? 1u : 0u;
         const bool ok = !done && f.alpha >= kAlphaMin;
         const float Tn = T * (1.0f - f.alpha);
         const bool stop = ok && Tn < kTransMin;
@@ -267,7 +267,7 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
         D = fmaf(w, A.z, D);
         T = blend ? Tn : T;
         last = blend ? base + (uint32_t)j : last;
-        nb += blend ? 1u : 0u;
+        if (COUNT) nb += blend ? 1u : 0u;
         done = done || stop;
       }
     }
@@ -286,10 +286,10 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
   }
 }
 
-// Work counters: wave sums added in LDS (wg[], zeroed by thread 0 before
-// the first barrier of the kernel), then one global atomic per counter and
-// workgroup, spread over kCountSlots slots.  The step counts are the same in
-// every lane of a wavefront (lane 0's is added).
+// Work counters: wave sums (the step count is the same in every lane:
+// lane 0's is added) summed in LDS (wg[], zeroed by thread 0 before the
+// first barrier of the kernel), then one global atomic per counter and
+// workgroup, spread over kCountSlots slots.
 __device__ __forceinline__ void flush_counts(uint32_t ne, uint32_t nb, uint32_t nsteps, unsigned long long* wg,
                                              Counters* cnt) {
   unsigned long long e = ne, b = nb;
@@ -342,7 +342,9 @@ __device__ __forceinline__ uint32_t next_tile(uint32_t* queue, uint32_t* slot) {
 // past the last tile.
 // (the second bound keeps the forward within 64 VGPRs: eight wavefronts per
 // SIMD)
-template <int TW, int TH, int NB>
+// COUNT: count the evaluations and blends per pixel (instrumentation:
+// about four of the step's 27 VALU instructions).
+template <int TW, int TH, int NB, bool COUNT>
 __global__ void __launch_bounds__(TW * TH, 8) composite_forward_kernel(
     const CallTables* __restrict__ tab, const float4* __restrict__ recs, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals, float* __restrict__ T_final, uint32_t* __restrict__ n_contrib,
@@ -361,12 +363,12 @@ __global__ void __launch_bounds__(TW * TH, 8) composite_forward_kernel(
   if (queue == nullptr) {
     const uint32_t tile = order[blockIdx.x];
     if (tile < n_tiles)
-      forward_tile<TW, TH, NB>(tab, recs, ranges, vals, T_final, n_contrib, masks, tile, sh, ne, nb, nsteps);
+      forward_tile<TW, TH, NB, COUNT>(tab, recs, ranges, vals, T_final, n_contrib, masks, tile, sh, ne, nb, nsteps);
   } else {
     for (uint32_t t = next_tile(queue, &slot); t < n_tiles; t = next_tile(queue, &slot)) {
       const uint32_t tile = order[t];
       if (tile < n_tiles)
-        forward_tile<TW, TH, NB>(tab, recs, ranges, vals, T_final, n_contrib, masks, tile, sh, ne, nb, nsteps);
+        forward_tile<TW, TH, NB, COUNT>(tab, recs, ranges, vals, T_final, n_contrib, masks, tile, sh, ne, nb, nsteps);
     }
   }
   flush_counts(ne, nb, nsteps, wg, cnt);
@@ -589,10 +591,15 @@ __global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
 template <int TW, int TH, int NB>
 hipError_t launch_fwd_t(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb, const uint2* ranges,
                         const uint32_t* vals, const uint32_t* order, float* T_final, uint32_t* n_contrib,
-                        uint64_t* masks, Counters* cnt, uint32_t* queue, uint32_t blocks, hipStream_t s) {
+                        uint64_t* masks, Counters* cnt, bool count, uint32_t* queue, uint32_t blocks,
+                        hipStream_t s) {
   const uint32_t grid = queue ? blocks : h.n_tiles;
-  hipLaunchKernelGGL((composite_forward_kernel<TW, TH, NB>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.rec,
-                     ranges, vals, T_final, n_contrib, masks, order, cnt, queue, h.n_tiles);
+  if (count)
+    hipLaunchKernelGGL((composite_forward_kernel<TW, TH, NB, true>), dim3(grid), dim3(TW * TH), 0, s, d_tab, pb.rec,
+                       ranges, vals, T_final, n_contrib, masks, order, cnt, queue, h.n_tiles);
+  else
+    hipLaunchKernelGGL((composite_forward_kernel<TW, TH, NB, false>), dim3(grid), dim3(TW * TH), 0, s, d_tab,
+                       pb.rec, ranges, vals, T_final, n_contrib, masks, order, cnt, queue, h.n_tiles);
   return hipGetLastError();
 }
 
@@ -631,13 +638,14 @@ size_t hit_mask_bytes(uint32_t capacity, uint32_t n_tiles, int tile_w, int tile_
 
 hipError_t launch_composite_forward(const CallTables* d_tab, const CallTables& h, const ProjBuffers pb,
                                     const uint2* ranges, const uint32_t* vals, const uint32_t* order,
-                                    float* T_final, uint32_t* n_contrib, uint64_t* masks, Counters* cnt, int tile_w,
-                                    int tile_h, int lds_batch, uint32_t* queue, uint32_t blocks, hipStream_t s) {
+                                    float* T_final, uint32_t* n_contrib, uint64_t* masks, Counters* cnt, bool count,
+                                    int tile_w, int tile_h, int lds_batch, uint32_t* queue, uint32_t blocks,
+                                    hipStream_t s) {
   if (h.n_tiles == 0) return hipSuccess;
 #define VPGS_FWD(TW, TH, NB) \
   if (tile_w == TW && tile_h == TH && lds_batch == NB) \
-    return launch_fwd_t<TW, TH, NB>(d_tab, h, pb, ranges, vals, order, T_final, n_contrib, masks, cnt, queue, \
-                                    blocks, s);
+    return launch_fwd_t<TW, TH, NB>(d_tab, h, pb, ranges, vals, order, T_final, n_contrib, masks, cnt, count, \
+                                    queue, blocks, s);
   VPGS_SHAPES(VPGS_FWD)
 #undef VPGS_FWD
   return hipErrorInvalidValue;

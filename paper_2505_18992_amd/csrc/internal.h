@@ -222,8 +222,8 @@ size_t hit_mask_bytes(uint32_t capacity, uint32_t n_tiles, int tile_w, int tile_
 hipError_t launch_composite_forward(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
                                     const uint2* ranges, const uint32_t* vals, const uint32_t* order,
                                     float* T_final, uint32_t* n_contrib, uint64_t* masks, Counters* cnt,
-                                    int tile_w, int tile_h, int lds_batch, uint32_t* queue, uint32_t blocks,
-                                    hipStream_t s);
+                                    bool count, int tile_w, int tile_h, int lds_batch, uint32_t* queue,
+                                    uint32_t blocks, hipStream_t s);
 hipError_t launch_composite_backward(const CallTables* d_tab, const CallTables& h_tab, const ProjBuffers pb,
                                      const uint2* ranges, const uint32_t* vals, const uint32_t* order,
                                      const float* T_final, const uint32_t* n_contrib, const uint64_t* masks,

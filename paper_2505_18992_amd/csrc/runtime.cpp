@@ -134,8 +134,7 @@ void destroy_saved(vpgs_saved* s) {
                     &s->ncontrib, &s->counters, &s->acc, &s->pose_partial, &s->dk, &s->dk_alt, &s->dv,
                     &s->dv_alt, &s->dcount, &s->dpoff, &s->key64, &s->order};
   for (DevBuf* b : bufs) free_buf(s->ctx, *b);
-  if (s->tab_uploaded) (void)hipEventDestroy(s->tab_uploaded);
-  if (s->h_tab) (void)hipHostFree(s->h_tab);
+  delete s->h_tab;
   delete s;
 }
 
@@ -143,15 +142,10 @@ int new_saved(vpgs_ctx* ctx, vpgs_saved** out) {
   vpgs_saved* s = new (std::nothrow) vpgs_saved();
   if (!s) return fail(ctx, VPGS_ENOMEM, "out of host memory");
   s->ctx = ctx;
-  hipError_t e = hipHostMalloc((void**)&s->h_tab, sizeof(CallTables), hipHostMallocDefault);
-  if (e != hipSuccess) {
+  s->h_tab = new (std::nothrow) CallTables();
+  if (!s->h_tab) {
     delete s;
-    return fail(ctx, VPGS_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
-  }
-  e = hipEventCreateWithFlags(&s->tab_uploaded, hipEventDisableTiming);
-  if (e != hipSuccess) {
-    destroy_saved(s);
-    return fail(ctx, VPGS_EHIP, "hipEventCreate: %s", hipGetErrorString(e));
+    return fail(ctx, VPGS_ENOMEM, "out of host memory");
   }
   std::memset(s->h_tab, 0, sizeof(CallTables));
   *out = s;
@@ -258,8 +252,12 @@ int build_tables(vpgs_ctx* ctx, CallTables& T, int n_sets, const vpgs_gaussians*
 }
 
 int upload_tables(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
-  HIP_TRY(hipMemcpyAsync(sv->tab.p, sv->h_tab, sizeof(CallTables), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipEventRecord(sv->tab_uploaded, st));
+  const int slot = ctx->tab_ring_next;
+  ctx->tab_ring_next = (slot + 1) % vpgs_ctx::kTabRing;
+  HIP_TRY(hipEventSynchronize(ctx->tab_ring_ev[slot]));  // the copy that last read this slot is done
+  std::memcpy(&ctx->tab_ring[slot], sv->h_tab, sizeof(CallTables));
+  HIP_TRY(hipMemcpyAsync(sv->tab.p, &ctx->tab_ring[slot], sizeof(CallTables), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(ctx->tab_ring_ev[slot], st));
   return VPGS_OK;
 }
 
@@ -477,7 +475,7 @@ int enqueue_back(vpgs_ctx* ctx, vpgs_saved* sv, hipStream_t st) {
     HIP_TRY(launch_composite_forward(d_tab, T, pb, static_cast<const uint2*>(sv->ranges.p), svals,
                                      static_cast<const uint32_t*>(sv->order.p), static_cast<float*>(sv->tfinal.p),
                                      static_cast<uint32_t*>(sv->ncontrib.p), static_cast<uint64_t*>(sv->hitmask.p), cnt,
-                                     sv->tile_w, sv->tile_h, sv->lds_batch,
+                                     sv->count_work, sv->tile_w, sv->tile_h, sv->lds_batch,
                                      sv->persistent_blocks ? &cnt->queue_fwd : nullptr, sv->persistent_blocks, st));
   }
   return VPGS_OK;
@@ -552,8 +550,22 @@ int vpgs_create(vpgs_ctx** out, int device, void* (*alloc)(size_t, void*), void 
     delete ctx;
     return VPGS_EHIP;
   }
+  bool ring_ok = hipHostMalloc((void**)&ctx->tab_ring, vpgs_ctx::kTabRing * sizeof(CallTables),
+                               hipHostMallocDefault) == hipSuccess;
+  for (int k = 0; ring_ok && k < vpgs_ctx::kTabRing; ++k)
+    ring_ok = hipEventCreateWithFlags(&ctx->tab_ring_ev[k], hipEventDisableTiming) == hipSuccess;
+  if (!ring_ok) {
+    for (hipEvent_t e : ctx->tab_ring_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (ctx->tab_ring) (void)hipHostFree(ctx->tab_ring);
+    (void)hipHostFree(ctx->h_pinned);
+    delete ctx;
+    return VPGS_EHIP;
+  }
   const int rc = init_scratch(ctx);
   if (rc) {
+    for (hipEvent_t e : ctx->tab_ring_ev) (void)hipEventDestroy(e);
+    (void)hipHostFree(ctx->tab_ring);
     (void)hipHostFree(ctx->h_pinned);
     delete ctx;
     return rc;
@@ -615,6 +627,9 @@ int vpgs_destroy(vpgs_ctx* ctx) {
   free_buf(ctx, ctx->icp_ws);
   free_buf(ctx, ctx->peak_ws);
   if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
+  for (hipEvent_t e : ctx->tab_ring_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->tab_ring) (void)hipHostFree(ctx->tab_ring);
   delete ctx;
   return VPGS_OK;
 }
@@ -640,13 +655,13 @@ int vpgs_render_forward(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, i
     ~Releaser() { if (!keep) s->in_use = false; }
   } rel{sv};
 
-  HIP_TRY(hipEventSynchronize(sv->tab_uploaded));  // the previous upload from h_tab has completed
   rc = build_tables(ctx, *sv->h_tab, n_sets, sets, n_views, view_set, cams, out, tw, th);
   if (rc) return rc;
   sv->tile_w = tw;
   sv->tile_h = th;
   sv->lds_batch = (opts && opts->lds_batch) ? opts->lds_batch : tw * th;
   sv->persistent_blocks = opts ? (uint32_t)opts->grid_ctas : 0u;
+  sv->count_work = !(opts && opts->skip_counts);
   if ((rc = prepare_front(ctx, sv)) || (rc = upload_tables(ctx, sv, st)) || (rc = enqueue_front(ctx, sv, st)))
     return rc;
   uint32_t cap;
@@ -681,7 +696,6 @@ int vpgs_render_backward_accum(vpgs_ctx* ctx, const vpgs_saved* saved_c, const v
   if (!known) return fail(ctx, VPGS_EINVAL, "saved-state handle of another context");
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(hipSetDevice(ctx->device));
-  HIP_TRY(hipEventSynchronize(sv->tab_uploaded));
   int rc = bind_backward(ctx, *sv->h_tab, grad_out, grads);
   if (!rc) rc = bind_accum(ctx, *sv->h_tab, acc);
   if (rc) return rc;

@@ -27,16 +27,16 @@ extern const char* const kStageNames[VPGS_NUM_STAGES];
 
 struct vpgs_saved {
   vpgs_ctx* ctx = nullptr;  // whose allocator holds the buffers
-  // host and device call tables; the host copy is pinned and guarded by an
-  // event so an in-flight upload is never overwritten
+  // host and device call tables (the host copy is uploaded through the
+  // context's ring of pinned staging buffers)
   vpgs::CallTables* h_tab = nullptr;
-  hipEvent_t tab_uploaded = nullptr;
   vpgs::DevBuf tab, rec, count, zkey, rect, drect, hitmask, scan_ws, keys, vals, keys_alt, vals_alt, sort_ws, ranges,
       tfinal, ncontrib, counters, acc, pose_partial, dk, dk_alt, dv, dv_alt, dcount, dpoff, key64, order;
   int result_in_alt = 0;
   int depth_in_alt = 0;
   int tile_w = 16, tile_h = 16;
   int lds_batch = 256;  // entries staged per compositing batch
+  bool count_work = true;  // the forward counts its evaluations and blends
   int key_bits = 16;  // tile-id bits sorted
   uint32_t persistent_blocks = 0;  // 0: one compositing workgroup per tile
   uint32_t capacity = 0;
@@ -45,7 +45,14 @@ struct vpgs_saved {
 };
 
 struct vpgs_ctx {
+  static constexpr int kTabRing = 8;
   int device = 0;
+  // pinned staging buffers of the call-table uploads, each reused only once
+  // the copy that last read it has completed (an event per slot), so the
+  // host runs ahead of the device by up to kTabRing uploads
+  vpgs::CallTables* tab_ring = nullptr;
+  hipEvent_t tab_ring_ev[kTabRing] = {};
+  int tab_ring_next = 0;
   // device workspace allocator: the caller's callbacks, or hipMalloc/hipFree
   // when none were given
   void* (*alloc)(size_t, void*) = nullptr;

@@ -60,7 +60,6 @@ const vpgs_densify_accum* accum_of(vpgs_window* w) {
 int configure(vpgs_window* w, int tw, int th, int nb) {
   vpgs_ctx* ctx = w->ctx;
   vpgs_saved* sv = w->sv;
-  HIP_TRY(hipEventSynchronize(sv->tab_uploaded));
   int rc = build_tables(ctx, *sv->h_tab, (int)w->sets.size(), w->sets.data(), (int)w->view_set.size(),
                         w->view_set.data(), w->cams.data(), w->out.data(), tw, th);
   if (rc) return rc;
@@ -312,6 +311,7 @@ int vpgs_window_create(vpgs_ctx* ctx, int n_sets, const vpgs_gaussians* sets, in
   rc = new_saved(ctx, &w->sv);
   if (rc) { release(w); return rc; }
   w->sv->in_use = true;
+  w->sv->count_work = !o.skip_counts;
 
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
@@ -461,7 +461,6 @@ int vpgs_window_run(vpgs_window* w, int parts, void* stream) {
                 "outputs were invalid; recreate the window with a larger pair_capacity", w->sv->capacity);
   if (w->tables_dirty) {
     // rebuild the tables for the new poses (same shapes, same buffers) and upload
-    HIP_TRY(hipEventSynchronize(w->sv->tab_uploaded));
     int rc = build_tables(ctx, *w->sv->h_tab, (int)w->sets.size(), w->sets.data(), (int)w->view_set.size(),
                           w->view_set.data(), w->cams.data(), w->out.data(), w->cfg.tile_w, w->cfg.tile_h);
     if (!rc) rc = bind_backward(ctx, *w->sv->h_tab, w->grad_out.data(), w->grads.data());

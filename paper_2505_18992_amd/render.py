@@ -214,12 +214,12 @@ def _set_struct(s) -> _lib.Gaussians:
 
 def render(sets: Sequence[Sequence[torch.Tensor]], cameras: Sequence, view_set: Optional[Sequence[int]] = None,
            tile=(16, 16), pair_capacity: int = 0, keep: bool = True, ctx: Optional[Context] = None,
-           lds_batch: int = 0, grid_ctas: int = 0):
+           lds_batch: int = 0, grid_ctas: int = 0, count: bool = True):
     """Forward render.  ``sets`` is a list of (means, log_scales, quats,
     opacities, colors) tuples; view v renders sets[view_set[v]] with
     cameras[v].  lds_batch: entries staged per compositing batch (0 = the
     tile's pixel count); grid_ctas: persistent compositing workgroups (0 =
-    one per tile).  Returns (list of (rgb[3,H,W], depth[H,W], alpha[H,W]),
+    one per tile); count: count evaluations and blends (Saved.stats).  Returns (list of (rgb[3,H,W], depth[H,W], alpha[H,W]),
     Saved or None)."""
     ctx = ctx or get_context()
     L = load()
@@ -243,6 +243,7 @@ def render(sets: Sequence[Sequence[torch.Tensor]], cameras: Sequence, view_set: 
     opts.lds_batch = int(lds_batch)
     opts.grid_ctas = int(grid_ctas)
     opts.pair_capacity = int(pair_capacity)
+    opts.skip_counts = 0 if count else 1
     h = ctypes.c_void_p()
     st = L.vpgs_render_forward(ctx.handle, len(sets), gs, nv, vs, cams, ims, ctypes.byref(opts),
                                ctypes.byref(h) if keep else None, _stream())
@@ -380,7 +381,7 @@ class RenderWindow:
 
     def __init__(self, sets, cameras, view_set=None, tile=None, persistent: int = -1, use_graph: bool = True,
                  pair_capacity: int = 0, tune_reps: int = 3, ctx: Optional[Context] = None, lds_batch: int = 0,
-                 tune_cache: Optional[str] = None):
+                 tune_cache: Optional[str] = None, count: bool = True):
         self.ctx = ctx or get_context()
         L = load()
         nv = len(cameras)
@@ -412,6 +413,7 @@ class RenderWindow:
         o.tune_reps = int(tune_reps)
         o.lds_batch = int(lds_batch)
         o.tune_cache = None if tune_cache is None else str(tune_cache).encode()
+        o.skip_counts = 0 if count else 1
         h = ctypes.c_void_p()
         check(L.vpgs_window_create(self.ctx.handle, len(self.sets), gs, nv, vs, cams, ims, gis, gb,
                                    _ptr(self.d_pose), ctypes.byref(o), ctypes.byref(h), _stream()),
@@ -449,7 +451,7 @@ class RenderWindow:
     def config(self) -> dict:
         o = _lib.WindowOpts()
         check(load().vpgs_window_config(self.handle, ctypes.byref(o)), self.ctx.handle, "vpgs_window_config")
-        return {f: getattr(o, f) for f, _ in _lib.WindowOpts._fields_ if f != "tune_cache"}
+        return {f: getattr(o, f) for f, _ in _lib.WindowOpts._fields_ if f not in ("tune_cache", "reserved")}
 
     def close(self):
         if getattr(self, "handle", None):

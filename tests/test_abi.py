@@ -81,10 +81,11 @@ def test_structure_layouts_match_the_header():
     from paper_2505_18992_amd import _lib
     assert ctypes.sizeof(_lib.Camera) == 4 * 7 + 4 * 12
     assert _lib.Gaussians.means.offset == 8 and ctypes.sizeof(_lib.Gaussians) == 48
-    assert ctypes.sizeof(_lib.RenderOpts) == 24 and _lib.RenderOpts.pair_capacity.offset == 16
+    assert ctypes.sizeof(_lib.RenderOpts) == 32 and _lib.RenderOpts.pair_capacity.offset == 16
+    assert _lib.RenderOpts.skip_counts.offset == 24
     assert _lib.RenderOpts.lds_batch.offset == 8 and _lib.RenderOpts.grid_ctas.offset == 12
-    assert ctypes.sizeof(_lib.WindowOpts) == 40 and _lib.WindowOpts.lds_batch.offset == 28
-    assert _lib.WindowOpts.tune_cache.offset == 32
+    assert ctypes.sizeof(_lib.WindowOpts) == 48 and _lib.WindowOpts.lds_batch.offset == 28
+    assert _lib.WindowOpts.tune_cache.offset == 32 and _lib.WindowOpts.skip_counts.offset == 40
     assert _lib.Anchors.xyz.offset == 16
     assert _lib.Mlp.W1.offset == 8 and ctypes.sizeof(_lib.Mlp) == 8 + 12 * 8
     assert ctypes.sizeof(_lib.Stats) == 8 * 8 + 4 * 4 + 3 * 8

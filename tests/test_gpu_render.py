@@ -234,3 +234,26 @@ def test_forward_deterministic():
     assert torch.equal(k1, k2)
     for x, y in zip(a[0], b[0]):
         assert torch.equal(x, y)
+
+
+def test_forward_without_work_counters():
+    """skip_counts: the same images bit for bit, evaluation and blend counts
+    reported as zero, the pair list and backward unchanged."""
+    from paper_2505_18992_amd import render, render_backward
+    sc = scenes.make_c1()
+    print("case c1 forward without counters", flush=True)
+    sets = [to_dev(g.arrays()) for g in sc.sets]
+    outs = []
+    for count in (True, False):
+        o, saved = render(sets, sc.cameras, tile=(32, 8), count=count)
+        st = saved.stats()
+        grads, d_pose = render_backward(saved, [to_dev(sc.weights[0])])
+        saved.close()
+        outs.append((o[0], st, grads[0]))
+    (a, sa, ga), (b, sb, gb) = outs
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    assert sa["n_blended"] > 0 and sb["n_blended"] == 0 and sb["n_evaluated"] == 0
+    assert sa["n_pairs"] == sb["n_pairs"] and sa["n_bwd_steps"] == sb["n_bwd_steps"]
+    for x, y in zip(ga, gb):
+        assert torch.allclose(x, y, rtol=1e-5, atol=1e-6 * float(x.abs().max()))
