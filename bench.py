@@ -64,7 +64,12 @@ SORT_BYTES_PER_PAIR_PASS = 20.0  # 32-bit keys and values: histogram read 4 B, s
 # read for a 256 MiB device copy (FETCH_SIZE x 2, WRITE_SIZE x 1).  They hold
 # only for the kernel sources they were taken with; after any change to
 # those the traffic is reported as null until it is measured again.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    ("composite_backward", 32, 8, 0, 256): {"fetch_bytes": 1120859332.0, "write_bytes": 615417856.0,
+                                            "sources_sha256": "5d6d6329087f31488d659e738131a2ee741a90dc49848adfac5d0d7efda573e1"},
+    ("composite_forward", 32, 8, 0, 256): {"fetch_bytes": 1110456127.0, "write_bytes": 221749248.0,
+                                           "sources_sha256": "5d6d6329087f31488d659e738131a2ee741a90dc49848adfac5d0d7efda573e1"},
+}
 TRAFFIC_SOURCES = ("paper_2505_18992_amd/csrc/composite.hip", "paper_2505_18992_amd/csrc/internal.h")
 
 
@@ -671,8 +676,10 @@ def main():
     ap.add_argument("--no-one-view", action="store_true",
                     help="skip the one-view-per-launch comparison (profiling runs: it launches the same kernels)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the mapping-loss, expansion, distillation and registration measurements "
+                    help="skip the mapping-loss, expansion, distillation, registration and decode measurements "
                          "(profiling runs of the step alone)")
+    ap.add_argument("--extras", default="loss,expansion,distillation,registration,decode",
+                    help="which of the extra measurements to run (comma list)")
     ap.add_argument("--configs", default="c1,c2,c4-mixed,c5",
                     help="other workloads measured in the same run (comma list, '' for none)")
     args = ap.parse_args()
@@ -697,17 +704,22 @@ def main():
     ms_per_view_launch, t_tune = m["ms_per_view_launch"], m["tune_seconds"]
 
     loss_stage = expansion = distillation = registration = anchor_decode = None
-    if not args.no_extras:
-        # the mapping loss of eq. 7-8 on the same views (rendered frames
-        # against perturbed copies of themselves), timed on its own
+    extras = set() if args.no_extras else {e for e in args.extras.split(",") if e}
+    # the mapping loss of eq. 7-8 on the same views (rendered frames
+    # against perturbed copies of themselves), timed on its own
+    if "loss" in extras:
         loss_stage = time_mapping_loss(win, cams, args.steps)
-        # the submap-expansion statistics of Section III-A on the same workload
+    # the submap-expansion statistics of Section III-A on the same workload
+    if "expansion" in extras:
         expansion = time_expansion(sets, gw, cams, vset, cfg, win, args.steps)
-        # submap fusion (eq. 14) on two street submaps
+    # submap fusion (eq. 14) on two street submaps
+    if "distillation" in extras:
         distillation = time_distillation(args.steps)
-        # frame-to-map registration (eq. 10-12) on a street LiDAR sweep
+    # frame-to-map registration (eq. 10-12) on a street LiDAR sweep
+    if "registration" in extras:
         registration = time_registration(args.steps)
-        # the voxel-anchor decode (eq. 1-5) and its backward
+    # the voxel-anchor decode (eq. 1-5) and its backward
+    if "decode" in extras:
         anchor_decode = time_decode(args.steps)
 
     E, B, P = st["n_evaluated"], st["n_blended"], st["n_pairs"]
