@@ -57,21 +57,28 @@ __device__ __forceinline__ Falloff falloff(const float4 A, const float4 E, float
   return f;
 }
 
-// Hit lists are padded to a multiple of kGroup entries with a sentinel slot
-// (index NB, staged once per workgroup) whose exponent is -inf, so alpha is 0
-// there and nothing is blended; the per-pixel loops then run whole groups
-// without per-entry bounds tests, and the forward checks for early
-// termination between groups.
+// Staged entry e lives in slot e + 1 of the LDS arrays; slot 0 is a sentinel
+// (staged once per workgroup) whose exponent is -inf, so alpha is 0 there and
+// nothing is blended.  Hit lists hold LDS byte offsets (16 x slot) into the
+// slot arrays, so a list entry is the address of its Gaussian's data, and are
+// padded with the sentinel's offset 0 to a multiple of kGroup entries; the
+// per-pixel loops then run whole groups without per-entry bounds tests, and
+// the forward checks for early termination between groups.
 constexpr int kGroup = 8;
 constexpr float kLog2AlphaMin = -7.99435343685885793769f;  // log2(1/255)
 constexpr float kNegInf = -__builtin_inff();
 
 template <int TW, int TH, int NB>
 struct FwdShared {
-  float4 A[NB + 1], E[NB + 1], C[NB + 1];
-  float2 V[NB];  // the quadrant test's vertex factors (ra, rc) of the record
-  uint16_t hits[(TW * TH) / 64][NB + kGroup];  // per wavefront: staged entries that reach its quadrant
+  float4 A[NB + 1], E[NB + 1], C[NB + 1];  // by slot
+  float2 V[NB];  // the quadrant test's vertex factors (ra, rc) of the record, by entry
+  uint32_t hits[(TW * TH) / 64][NB + kGroup];  // per wavefront: offsets of the entries that reach its quadrant
 };
+
+// The slot array element at byte offset o (a hit-list entry).
+__device__ __forceinline__ const float4& at_offset(const float4* a, uint32_t o) {
+  return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(a) + o);
+}
 
 // Each wavefront owns an 8x8 quadrant of its tile (lane -> (lane % 8,
 // lane / 8)) and keeps in its hit list only the Gaussians that can reach
@@ -124,37 +131,39 @@ struct Quadrant {
 };
 
 // Compacts the staged entries [0, n) that reach the wavefront's quadrant
-// into list[], in staging order, pads it with the sentinel index NB to a
-// multiple of kGroup and returns the number of hits (the same in every
-// lane); lane 0 also stores the batch's hit bits (one 64-bit word per 64
-// entries) in mask_out, from which the backward rebuilds the list.  Lane l
-// tests entries l, l + 64, ...; a ballot and a lane-prefix count give each
-// hit its slot.  All lanes of the wavefront must be active; the list is read
-// after the next workgroup barrier.
+// into list[] (as slot offsets), in staging order, pads it with the
+// sentinel's offset to a multiple of kGroup and returns the number of hits
+// (the same in every lane); lane 0 also stores the batch's hit bits (one
+// 64-bit word per 64 entries) in mask_out, from which the backward rebuilds
+// the list.  Lane l tests entries l, l + 64, ...; a ballot and a lane-prefix
+// count give each hit its place.  All lanes of the wavefront must be active;
+// the list is read after the next workgroup barrier.
 template <int NB, int TW, int TH>
 __device__ __forceinline__ int wave_hits(const float4* A, const float4* E, const float2* V, int n,
-                                         const Quadrant<TW, TH>& q, uint16_t* list, uint64_t* mask_out) {
+                                         const Quadrant<TW, TH>& q, uint32_t* list, uint64_t* mask_out) {
   const int lane = threadIdx.x & 63;
   int count = 0;
 #pragma unroll
   for (int k = 0; k < NB / 64; ++k) {
     const int e = k * 64 + lane;
-    const bool hit = e < n && q.reaches(A[e], E[e], V[e]);
+    const bool hit = e < n && q.reaches(A[e + 1], E[e + 1], V[e]);
     const uint64_t m = __ballot(hit);
     const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-    if (hit) list[count + below] = (uint16_t)e;
+    if (hit) list[count + below] = (uint32_t)(e + 1) * (uint32_t)sizeof(float4);
     if (lane == 0) mask_out[k] = m;
     count += __popcll(m);
   }
-  if (lane < ((count + kGroup - 1) & ~(kGroup - 1)) - count) list[count + lane] = (uint16_t)NB;
+  if (lane < ((count + kGroup - 1) & ~(kGroup - 1)) - count) list[count + lane] = 0u;
   return count;
 }
 
 // The backward's list of a batch from the forward's masks: the entries
-// below n whose bit is set, in descending order.  All lanes of the
+// below n whose bit is set, in descending order, as slot offsets, padded
+// with the sentinel's offset to a multiple of kBwdGroup.  All lanes of the
 // wavefront must be active.
+constexpr int kBwdGroup = 4;
 template <int NB>
-__device__ __forceinline__ int mask_hits_desc(const uint64_t* mask, int n, uint16_t* list) {
+__device__ __forceinline__ int mask_hits_desc(const uint64_t* mask, int n, uint32_t* list) {
   const int lane = threadIdx.x & 63;
   int count = 0;
 #pragma unroll
@@ -164,9 +173,10 @@ __device__ __forceinline__ int mask_hits_desc(const uint64_t* mask, int n, uint1
     if (n <= lo) m = 0ull;
     else if (n < lo + 64) m &= (1ull << (n - lo)) - 1ull;
     const int above = __popcll((m >> lane) >> 1);  // set bits of the higher lanes
-    if ((m >> lane) & 1ull) list[count + above] = (uint16_t)(lo + lane);
+    if ((m >> lane) & 1ull) list[count + above] = (uint32_t)(lo + lane + 1) * (uint32_t)sizeof(float4);
     count += __popcll(m);
   }
+  if (lane < ((count + kBwdGroup - 1) & ~(kBwdGroup - 1)) - count) list[count + lane] = 0u;
   return count;
 }
 
@@ -200,7 +210,7 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
   const bool inside = px < V.W && py < V.H;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
   const uint2 rg = ranges[tile];
-  uint16_t* hits = sh.hits[threadIdx.x >> 6];
+  uint32_t* hits = sh.hits[threadIdx.x >> 6];
 
   float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
   uint32_t last = 0;
@@ -226,9 +236,9 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
     for (int k = 0; k < PER; ++k) {
       const uint32_t e = (uint32_t)(k * BS) + threadIdx.x;
       if (e < (uint32_t)NB && start + e < rg.y) {
-        sh.A[e] = pA[k];
-        sh.E[e] = stage_exponent(pA[k], pR[k]);
-        sh.C[e] = pC[k];
+        sh.A[e + 1] = pA[k];
+        sh.E[e + 1] = stage_exponent(pA[k], pR[k]);
+        sh.C[e + 1] = pC[k];
         sh.V[e] = pV[k];
       }
     }
@@ -246,31 +256,35 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
     uint64_t* wm = masks + batch_mask_index<NB, WV>(rg.x, tile, (int)((start - rg.x) / NB), wave);
     const int nhit = wave_hits<NB>(sh.A, sh.E, sh.V, (int)min((uint32_t)NB, rg.y - start), q, hits, wm);
     __syncthreads();
-    const uint32_t base = start - rg.x + 1u;
+    uint32_t lb = 0;  // offset of this pixel's last blended entry of the batch (0: none)
     int g = 0;
     for (; g < nhit && __ballot(!done) != 0ull; g += kGroup) {
 #pragma unroll
       for (int u = 0; u < kGroup; ++u) {
-        const int j = hits[g + u];
-        const float4 A = sh.A[j];
-        const Falloff f = falloff(A, sh.E[j], pxc, pyc);
-        const float4 c = sh.C[j];
+        const uint32_t o = hits[g + u];
+        const float4 A = at_offset(sh.A, o);
+        const Falloff f = falloff(A, at_offset(sh.E, o), pxc, pyc);
+        const float4 c = at_offset(sh.C, o);
         if (COUNT) ne += (g + u < nhit && !done) ? 1u : 0u;
         const bool ok = !done && f.alpha >= kAlphaMin;
         const float Tn = T * (1.0f - f.alpha);
-        const bool stop = ok && Tn < kTransMin;
-        const bool blend = ok && !stop;
-        const float w = blend ? f.alpha * T : 0.0f;
-        C0 = fmaf(w, c.x, C0);
-        C1 = fmaf(w, c.y, C1);
-        C2 = fmaf(w, c.z, C2);
-        D = fmaf(w, A.z, D);
-        T = blend ? Tn : T;
-        last = blend ? base + (uint32_t)j : last;
-        if (COUNT) nb += blend ? 1u : 0u;
-        done = done || stop;
+        const bool low = Tn < kTransMin;
+        const bool blend = ok && !low;
+        if (blend) {
+          const float w = f.alpha * T;
+          C0 = fmaf(w, c.x, C0);
+          C1 = fmaf(w, c.y, C1);
+          C2 = fmaf(w, c.z, C2);
+          D = fmaf(w, A.z, D);
+          T = Tn;
+          lb = o;
+          if (COUNT) nb += 1u;
+        }
+        done = done || (ok && low);
       }
     }
+    // the pair index after the blended entry: (start - rg.x) + its entry + 1
+    if (lb != 0u) last = start - rg.x + lb / (uint32_t)sizeof(float4);
     nsteps += (uint32_t)min(g, nhit);  // the same in every lane of the wavefront
   }
   if (inside) {
@@ -355,9 +369,9 @@ __global__ void __launch_bounds__(TW * TH, 8) composite_forward_kernel(
   __shared__ unsigned long long wg[3];
   uint32_t ne = 0, nb = 0, nsteps = 0;
   if (threadIdx.x == 0) {  // the sentinel slot (read after the first staging barrier) and the counters
-    sh.A[NB] = make_float4(0.f, 0.f, 0.f, 0.f);
-    sh.E[NB] = make_float4(0.f, 0.f, 0.f, kNegInf);
-    sh.C[NB] = make_float4(0.f, 0.f, 0.f, 0.f);
+    sh.A[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+    sh.E[0] = make_float4(0.f, 0.f, 0.f, kNegInf);
+    sh.C[0] = make_float4(0.f, 0.f, 0.f, 0.f);
     wg[0] = wg[1] = wg[2] = 0ull;
   }
   if (queue == nullptr) {
@@ -435,8 +449,8 @@ static_assert((uint64_t)VPGS_MAX_RECORDS * kNumAcc * sizeof(float) < (1ull << 32
 
 template <int TW, int TH, int NB>
 struct BwdShared {
-  float4 A[NB + 1], E[NB + 1], C[NB + 1];  // C = (r, g, b, bits of the accumulator row offset)
-  uint16_t hits[(TW * TH) / 64][NB + kGroup];  // per wavefront, descending
+  float4 A[NB + 1], E[NB + 1], C[NB + 1];  // by slot; C = (r, g, b, bits of the accumulator row offset)
+  alignas(16) uint32_t hits[(TW * TH) / 64][NB + kBwdGroup];  // per wavefront, descending
   uint32_t maxlast[(TW * TH) / 64];
 };
 
@@ -498,30 +512,36 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
         const float4* r = recs + rec_slot(rec, 0);
         const float4 A = r[0];
         const float4 c = r[2];
-        sh.A[e] = A;
-        sh.E[e] = stage_exponent(A, r[1]);
+        sh.A[e + 1] = A;
+        sh.E[e + 1] = stage_exponent(A, r[1]);
         // the record's accumulator row as a byte offset (below 2^32: the
         // host bounds the records by VPGS_MAX_RECORDS), carried in the
         // colour's free lane
-        sh.C[e] = make_float4(c.x, c.y, c.z, __uint_as_float(rec * (uint32_t)(kNumAcc * sizeof(float))));
+        sh.C[e + 1] = make_float4(c.x, c.y, c.z, __uint_as_float(rec * (uint32_t)(kNumAcc * sizeof(float))));
       }
     }
     __syncthreads();
     // entries of this wavefront: those before its own last blended one
-    uint16_t* hits = sh.hits[wave];
+    uint32_t* hits = sh.hits[wave];
     const int nhit = mask_hits_desc<NB>(masks + batch_mask_index<NB, WV>(rg.x, tile, b, wave),
                                         min(end, (int)wave_last) - begin, hits);
     __syncthreads();
-    const int last_in_batch = (int)last - begin;  // this pixel's entries are the slots below it
+    // this pixel's entries are those before its last blended one: offsets
+    // below 16 (last - begin + 1); the padding (offset 0) has alpha 0
+    const int lim_slot = min(max((int)last - begin + 1, 0), NB + 1);
+    const uint32_t lim = (uint32_t)lim_slot * (uint32_t)sizeof(float4);
     nsteps += (uint32_t)nhit;
-    for (int i = 0; i < nhit; ++i) {
-      const int sl = hits[i];
-      const float4 A = sh.A[sl];
-      const Falloff f = falloff(A, sh.E[sl], pxc, pyc);
-      const bool valid = sl < last_in_batch && f.alpha >= kAlphaMin;
+    for (int i0 = 0; i0 < nhit; i0 += kBwdGroup) {
+    const uint4 h4 = *reinterpret_cast<const uint4*>(hits + i0);
+#pragma unroll
+    for (int u = 0; u < kBwdGroup; ++u) {
+      const uint32_t o = u == 0 ? h4.x : u == 1 ? h4.y : u == 2 ? h4.z : h4.w;
+      const float4 A = at_offset(sh.A, o);
+      const Falloff f = falloff(A, at_offset(sh.E, o), pxc, pyc);
+      const bool valid = o < lim && f.alpha >= kAlphaMin;
       if (__ballot(valid) == 0ull) continue;
       ++nactive;
-      const float4 c = sh.C[sl];
+      const float4 c = at_offset(sh.C, o);
       const float r1m = __builtin_amdgcn_rcpf(1.0f - f.alpha);
       const float Tj = valid ? T * r1m : T;
       const float fj = fmaf(gC0, c.x, fmaf(gC1, c.y, fmaf(gC2, c.z, fmaf(gD, A.z, gA))));
@@ -554,6 +574,7 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
         unsafeAtomicAdd(reinterpret_cast<float*>(reinterpret_cast<char*>(acc) + (__float_as_uint(c.w) + 4u * slot_id)),
                         mine);
     }
+    }
   }
 }
 
@@ -569,8 +590,9 @@ __global__ void __launch_bounds__(TW * TH) composite_backward_kernel(
   __shared__ unsigned long long wg[2];
   uint32_t nsteps = 0, nactive = 0;
   if (threadIdx.x == 0) {  // the sentinel slot (read after the first staging barrier) and the counters
-    sh.A[NB] = make_float4(0.f, 0.f, 0.f, 0.f);
-    sh.E[NB] = make_float4(0.f, 0.f, 0.f, kNegInf);
+    sh.A[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+    sh.E[0] = make_float4(0.f, 0.f, 0.f, kNegInf);
+    sh.C[0] = make_float4(0.f, 0.f, 0.f, 0.f);
     wg[0] = wg[1] = 0ull;
   }
   if (queue == nullptr) {
