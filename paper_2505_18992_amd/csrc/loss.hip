@@ -17,10 +17,15 @@
 // so the gradient of mean S is (G*P1 + 2 X (G*P2) + Y (G*P3)) / N.  Two
 // stencil kernels per view: the first filters the five statistics and
 // writes S's partials (and block sums of the loss terms), the second
-// filters the partials and writes the gradient planes.  Both stage a
-// 32x16-pixel tile plus a 5-pixel halo in LDS and filter it separably, each
-// thread filtering a run of adjacent outputs from registers (4 along a row,
-// 2 down a column).  One launch of each covers up to 16 views.
+// filters the partials and writes the gradient planes.  A workgroup walks a
+// 32-column strip down a segment of kSeg rows in bands of 32 rows: each band
+// stages its new input rows (with a 5-column halo, zero outside the image),
+// filters them horizontally once (each thread 4 adjacent outputs from
+// registers), appends them to the 42 horizontally filtered rows the band's
+// vertical filter needs (the last 10 rows of the previous band stay), and
+// filters vertically (each thread 4 outputs down a column).  Only the first
+// band of a segment filters 10 rows that another segment also filters.  One
+// launch of each covers up to 16 views.
 #include <algorithm>
 #include <cmath>
 
@@ -29,13 +34,17 @@
 namespace vpgs {
 namespace {
 
-constexpr int kTileW = 32, kTileH = 16;
 constexpr int kRad = 5, kTaps = 2 * kRad + 1;
-constexpr int kHaloW = kTileW + 2 * kRad, kHaloH = kTileH + 2 * kRad;  // 42 x 26
+constexpr int kSW = 32;                   // strip width (output columns)
+constexpr int kBand = 32;                 // output rows per band
+constexpr int kSeg = 128;                 // output rows per workgroup (whole bands)
+constexpr int kSWH = kSW + 2 * kRad;      // staged columns (42)
+constexpr int kRows = kBand + 2 * kRad;   // horizontally filtered rows a band's vertical filter reads (42)
 constexpr int kLossBlock = 256;
-constexpr int kHRun = 4;  // horizontal outputs per thread (kHaloH * kTileW / kHRun <= kLossBlock)
-constexpr int kVRun = 2;  // vertical outputs per thread (kTileW * kTileH / kVRun == kLossBlock)
-static_assert(kHaloH * (kTileW / kHRun) <= kLossBlock && kTileW * kTileH / kVRun == kLossBlock, "filter runs");
+constexpr int kHRun = 4;  // horizontal outputs per thread: kBand rows x kSW / kHRun runs = kLossBlock
+constexpr int kVRun = 4;  // vertical outputs per thread: kSW columns x kBand / kVRun runs = kLossBlock
+static_assert(kBand * (kSW / kHRun) == kLossBlock && kSW * (kBand / kVRun) == kLossBlock, "filter runs");
+static_assert(kSeg % kBand == 0 && 2 * kRad <= kBand, "bands");
 constexpr float kC1 = 0.0001f, kC2 = 0.0009f;
 constexpr int kSumSlots = 64;   // block sums are spread over slots per view
 constexpr int kSums = 4;        // sum S, sum |X - Y|, sum valid |D - T|, valid count
@@ -80,36 +89,70 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
   return r;  // every thread
 }
 
-// Loads the tile's halo window of NP planes (src[q], each [H,W]) into
-// lds[q][kHaloH][kHaloW], zero outside the image.  Every load of the thread
-// is issued before the first LDS write (out-of-image slots read the plane's
-// first element and are replaced by zero), so a thread waits for its global
-// loads once, not once per element.
-constexpr int kHaloPer = (kHaloH * kHaloW + kLossBlock - 1) / kLossBlock;
+// Stages input rows [r0, r0 + n) (n <= kBand) of NP planes, columns x0 - 5
+// .. x0 + kSW + 4, into lds[q][0, n)[kSWH], zero outside the image.  Every
+// load of the thread is issued before its first LDS write (out-of-image
+// slots read the plane's first element and are replaced by zero).
+constexpr int kStagePer = (kBand * kSWH + kLossBlock - 1) / kLossBlock;
 template <int NP>
-__device__ __forceinline__ void load_halos(const float* const* src, int W, int H, int x0, int y0,
-                                           float (*lds)[kHaloH][kHaloW]) {
-  float v[NP][kHaloPer];
-  bool in[kHaloPer];
-  int slot[kHaloPer];
+__device__ __forceinline__ void stage_rows(const float* const* src, int W, int H, int x0, int r0, int n,
+                                           float (*lds)[kBand][kSWH]) {
+  float v[NP][kStagePer];
+  bool in[kStagePer];
 #pragma unroll
-  for (int u = 0; u < kHaloPer; ++u) {
+  for (int u = 0; u < kStagePer; ++u) {
     const int k = (int)threadIdx.x + u * kLossBlock;
-    const int r = k / kHaloW, c = k - r * kHaloW;  // constant divisor
-    const int gy = y0 - kRad + r, gx = x0 - kRad + c;
-    in[u] = k < kHaloH * kHaloW && gx >= 0 && gx < W && gy >= 0 && gy < H;
-    slot[u] = k;
+    const int r = k / kSWH, c = k - r * kSWH;  // constant divisor
+    const int gy = r0 + r, gx = x0 - kRad + c;
+    in[u] = r < n && gx >= 0 && gx < W && gy >= 0 && gy < H;
     const size_t off = in[u] ? (size_t)gy * W + gx : 0;
 #pragma unroll
     for (int q = 0; q < NP; ++q) v[q][u] = src[q][off];
   }
 #pragma unroll
-  for (int u = 0; u < kHaloPer; ++u) {
-    if (slot[u] >= kHaloH * kHaloW) continue;
-    const int r = slot[u] / kHaloW, c = slot[u] - r * kHaloW;
+  for (int u = 0; u < kStagePer; ++u) {
+    const int k = (int)threadIdx.x + u * kLossBlock;
+    const int r = k / kSWH, c = k - r * kSWH;
+    if (r >= n) continue;
 #pragma unroll
     for (int q = 0; q < NP; ++q) lds[q][r][c] = in[u] ? v[q][u] : 0.0f;
   }
+}
+
+// Moves the last 2 kRad horizontally filtered rows to the top of hs (the
+// next band's upper halo).
+template <int NQ>
+__device__ __forceinline__ void keep_halo_rows(float (*hs)[kRows][kSW]) {
+  float v[NQ][(2 * kRad * kSW + kLossBlock - 1) / kLossBlock];
+#pragma unroll
+  for (int u = 0; u < (2 * kRad * kSW + kLossBlock - 1) / kLossBlock; ++u) {
+    const int k = (int)threadIdx.x + u * kLossBlock;
+    if (k < 2 * kRad * kSW)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) v[q][u] = hs[q][kBand + k / kSW][k % kSW];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < (2 * kRad * kSW + kLossBlock - 1) / kLossBlock; ++u) {
+    const int k = (int)threadIdx.x + u * kLossBlock;
+    if (k < 2 * kRad * kSW)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) hs[q][k / kSW][k % kSW] = v[q][u];
+  }
+}
+
+// Workgroups are dispatched to the eight XCDs round robin by linear id, and
+// each XCD has its own L2.  Neighbouring strips share their halo columns, so
+// the linear id is renumbered to give every XCD a contiguous run of strips:
+// XCD k takes the k-th eighth of the grid in (x, y, z) order.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint3 xcd_block() {
+  const uint32_t gx = gridDim.x, gy = gridDim.y;
+  const uint32_t n = gx * gy * gridDim.z;
+  const uint32_t h = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const uint32_t x = h % kXcds, k = h / kXcds, q = n / kXcds, r = n % kXcds;
+  const uint32_t id = x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+  return make_uint3(id % gx, (id / gx) % gy, id / (gx * gy));
 }
 
 // ---------------------------------------------------------------------------
@@ -121,58 +164,84 @@ __device__ __forceinline__ void load_halos(const float* const* src, int W, int H
 //   dS/de11 = -A1 A2 / (B1 B2^2)
 //   dS/de12 = 2 A1 / (B1 B2)
 // (only B1 >= C1 and B2 >= C2 are divided by; A2 may vanish).
+//
+// Horizontal filter of the staged rows [0, n) of x and y into hs rows
+// [dst, dst + n): the five statistics x, y, x^2, y^2, xy.
+__device__ __forceinline__ void stats_rows(const float (*sxy)[kBand][kSWH], int n, int dst,
+                                           float (*hs)[kRows][kSW]) {
+  const int r = threadIdx.x / (kSW / kHRun), j0 = (threadIdx.x % (kSW / kHRun)) * kHRun;
+  if (r >= n) return;
+  // the run's samples and their products, each formed once (not once per tap)
+  float xv[kHRun + 2 * kRad], yv[kHRun + 2 * kRad], xx[kHRun + 2 * kRad], yy[kHRun + 2 * kRad],
+      xy[kHRun + 2 * kRad];
+#pragma unroll
+  for (int t = 0; t < kHRun + 2 * kRad; ++t) {
+    xv[t] = sxy[0][r][j0 + t];
+    yv[t] = sxy[1][r][j0 + t];
+    xx[t] = xv[t] * xv[t];
+    yy[t] = yv[t] * yv[t];
+    xy[t] = xv[t] * yv[t];
+  }
+#pragma unroll
+  for (int o = 0; o < kHRun; ++o) {
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+      const float g = kGauss[t];
+      s0 = fmaf(g, xv[o + t], s0);
+      s1 = fmaf(g, yv[o + t], s1);
+      s2 = fmaf(g, xx[o + t], s2);
+      s3 = fmaf(g, yy[o + t], s3);
+      s4 = fmaf(g, xy[o + t], s4);
+    }
+    hs[0][dst + r][j0 + o] = s0; hs[1][dst + r][j0 + o] = s1; hs[2][dst + r][j0 + o] = s2;
+    hs[3][dst + r][j0 + o] = s3; hs[4][dst + r][j0 + o] = s4;
+  }
+}
+
 __global__ void __launch_bounds__(kLossBlock) ssim_stats_kernel(LossBatch batch) {
-  __shared__ float sxy[2][kHaloH][kHaloW];  // x, y
-  __shared__ float hs[5][kHaloH][kTileW];  // horizontal sums of x, y, x^2, y^2, xy
+  __shared__ float sxy[2][kBand][kSWH];  // staged x, y rows
+  __shared__ float hs[5][kRows][kSW];    // horizontal sums of x, y, x^2, y^2, xy
   __shared__ float red[kLossBlock / 64];
-  float (*sx)[kHaloW] = sxy[0];
-  float (*sy)[kHaloW] = sxy[1];
-  const ViewArgs& a = batch.v[blockIdx.z / 3];
-  if ((int)blockIdx.x >= a.tiles_x || (int)blockIdx.y >= a.tiles_y) return;
-  const int c = blockIdx.z % 3;
-  const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
+  const uint3 blk = xcd_block();
+  const ViewArgs& a = batch.v[blk.z / 3];
+  if ((int)blk.x >= a.tiles_x || (int)blk.y >= a.tiles_y) return;
+  const int c = blk.z % 3;
+  const int x0 = blk.x * kSW, y0 = blk.y * kSeg;
   const size_t HW = (size_t)a.W * a.H;
-  {
-    const float* planes[2] = {a.x + c * HW, a.y + c * HW};
-    load_halos<2>(planes, a.W, a.H, x0, y0, sxy);
-  }
-  __syncthreads();
-  if (threadIdx.x < kHaloH * (kTileW / kHRun)) {  // kHRun adjacent outputs per thread
-    const int r = threadIdx.x / (kTileW / kHRun), j0 = (threadIdx.x % (kTileW / kHRun)) * kHRun;
-    // the run's samples and their products, each formed once (not once per tap)
-    float xv[kHRun + 2 * kRad], yv[kHRun + 2 * kRad], xx[kHRun + 2 * kRad], yy[kHRun + 2 * kRad],
-        xy[kHRun + 2 * kRad];
-#pragma unroll
-    for (int t = 0; t < kHRun + 2 * kRad; ++t) {
-      xv[t] = sx[r][j0 + t];
-      yv[t] = sy[r][j0 + t];
-      xx[t] = xv[t] * xv[t];
-      yy[t] = yv[t] * yv[t];
-      xy[t] = xv[t] * yv[t];
-    }
-#pragma unroll
-    for (int o = 0; o < kHRun; ++o) {
-      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
-#pragma unroll
-      for (int t = 0; t < kTaps; ++t) {
-        const float g = kGauss[t];
-        s0 = fmaf(g, xv[o + t], s0);
-        s1 = fmaf(g, yv[o + t], s1);
-        s2 = fmaf(g, xx[o + t], s2);
-        s3 = fmaf(g, yy[o + t], s3);
-        s4 = fmaf(g, xy[o + t], s4);
-      }
-      hs[0][r][j0 + o] = s0; hs[1][r][j0 + o] = s1; hs[2][r][j0 + o] = s2; hs[3][r][j0 + o] = s3;
-      hs[4][r][j0 + o] = s4;
-    }
-  }
-  __syncthreads();
-  float ssum = 0.f, l1sum = 0.f;
+  const float* planes[2] = {a.x + c * HW, a.y + c * HW};
   float* P = a.P + (size_t)c * 3 * HW;
-  // kVRun vertically adjacent outputs per thread (kTileW x kTileH / kVRun threads)
-  const int vj = threadIdx.x % kTileW, vi0 = (threadIdx.x / kTileW) * kVRun;
-  float vm[5][kVRun];
-  {
+  float ssum = 0.f, l1sum = 0.f;
+  // the segment's upper halo: input rows y0 - 5 .. y0 + 4
+  stage_rows<2>(planes, a.W, a.H, x0, y0 - kRad, 2 * kRad, sxy);
+  __syncthreads();
+  stats_rows(sxy, 2 * kRad, 0, hs);
+  const int seg_end = min(y0 + kSeg, a.H);
+  const int vj = threadIdx.x % kSW, vi0 = (threadIdx.x / kSW) * kVRun;
+  for (int yb = y0; yb < seg_end; yb += kBand) {
+    __syncthreads();
+    // input rows yb + 5 .. yb + kBand + 4 after the 10 already filtered
+    stage_rows<2>(planes, a.W, a.H, x0, yb + kRad, kBand, sxy);
+    __syncthreads();
+    stats_rows(sxy, kBand, 2 * kRad, hs);
+    {
+      // |x - y| of the band's output pixels: rows yb + 5 .. yb + kBand - 1
+      // are staged (staged row rr holds row yb + 5 + rr)
+      const int r = threadIdx.x / kSW, j = threadIdx.x % kSW;
+#pragma unroll
+      for (int rr = r; rr < kBand - kRad; rr += kLossBlock / kSW) {
+        const int py = yb + kRad + rr;
+        if (py < seg_end && x0 + j < a.W) l1sum += fabsf(sxy[0][rr][j + kRad] - sxy[1][rr][j + kRad]);
+      }
+      // output rows yb .. yb + 4 came in the previous band's staging (or the
+      // upper halo): read them from memory
+      if (r < kRad && yb + r < seg_end && x0 + j < a.W) {
+        const size_t pix = (size_t)(yb + r) * a.W + x0 + j;
+        l1sum += fabsf(planes[0][pix] - planes[1][pix]);
+      }
+    }
+    __syncthreads();
+    float vm[5][kVRun];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       float col[kVRun + 2 * kRad];
@@ -186,26 +255,26 @@ __global__ void __launch_bounds__(kLossBlock) ssim_stats_kernel(LossBatch batch)
         vm[q][o] = acc;
       }
     }
-  }
 #pragma unroll
-  for (int o = 0; o < kVRun; ++o) {
-    const int i = vi0 + o, j = vj;
-    const int px = x0 + j, py = y0 + i;
-    if (px >= a.W || py >= a.H) continue;
-    const float m1 = vm[0][o], m2 = vm[1][o], e11 = vm[2][o], e22 = vm[3][o], e12 = vm[4][o];
-    const float A1 = 2.f * m1 * m2 + kC1, A2 = 2.f * (e12 - m1 * m2) + kC2;
-    const float B1 = m1 * m1 + m2 * m2 + kC1, B2 = (e11 - m1 * m1) + (e22 - m2 * m2) + kC2;
-    const float rB1 = 1.0f / B1, rB2 = 1.0f / B2;
-    const float rr = rB1 * rB2;
-    const float S = A1 * A2 * rr;
-    const size_t pix = (size_t)py * a.W + px;
-    P[pix] = 2.f * rr * (m2 * (A2 - A1) + A1 * A2 * m1 * (rB2 - rB1));  // dS/dm1
-    P[HW + pix] = -S * rB2;                                               // dS/de11
-    P[2 * HW + pix] = 2.f * A1 * rr;                                      // dS/de12
-    ssum += S;
-    l1sum += fabsf(sx[i + kRad][j + kRad] - sy[i + kRad][j + kRad]);
+    for (int o = 0; o < kVRun; ++o) {
+      const int px = x0 + vj, py = yb + vi0 + o;
+      if (px >= a.W || py >= seg_end) continue;
+      const float m1 = vm[0][o], m2 = vm[1][o], e11 = vm[2][o], e22 = vm[3][o], e12 = vm[4][o];
+      const float A1 = 2.f * m1 * m2 + kC1, A2 = 2.f * (e12 - m1 * m2) + kC2;
+      const float B1 = m1 * m1 + m2 * m2 + kC1, B2 = (e11 - m1 * m1) + (e22 - m2 * m2) + kC2;
+      const float rB1 = 1.0f / B1, rB2 = 1.0f / B2;
+      const float rr = rB1 * rB2;
+      const float S = A1 * A2 * rr;
+      const size_t pix = (size_t)py * a.W + px;
+      P[pix] = 2.f * rr * (m2 * (A2 - A1) + A1 * A2 * m1 * (rB2 - rB1));  // dS/dm1
+      P[HW + pix] = -S * rB2;                                               // dS/de11
+      P[2 * HW + pix] = 2.f * A1 * rr;                                      // dS/de12
+      ssum += S;
+    }
+    __syncthreads();
+    keep_halo_rows<5>(hs);
   }
-  const int slot = (int)((blockIdx.y * a.tiles_x + blockIdx.x) % kSumSlots);
+  const int slot = (int)((blk.y * a.tiles_x + blk.x) % kSumSlots);
   ssum = block_sum(ssum, red);
   l1sum = block_sum(l1sum, red);
   if (threadIdx.x == 0) {
@@ -214,8 +283,8 @@ __global__ void __launch_bounds__(kLossBlock) ssim_stats_kernel(LossBatch batch)
   }
   if (c == 0) {  // depth terms once per pixel
     float dsum = 0.f, nvalid = 0.f;
-    for (int k = threadIdx.x; k < kTileH * kTileW; k += kLossBlock) {
-      const int i = k / kTileW, j = k - i * kTileW;
+    for (int k = threadIdx.x; k < kSeg * kSW; k += kLossBlock) {
+      const int i = k / kSW, j = k - i * kSW;
       const int px = x0 + j, py = y0 + i;
       if (px >= a.W || py >= a.H) continue;
       const size_t pix = (size_t)py * a.W + px;
@@ -239,76 +308,89 @@ __global__ void __launch_bounds__(kLossBlock) ssim_stats_kernel(LossBatch batch)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float sgnf(float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); }
 
+// Horizontal filter of the staged rows [0, n) of the three partial planes
+// into hs rows [dst, dst + n).
+__device__ __forceinline__ void partial_rows(const float (*sp)[kBand][kSWH], int n, int dst,
+                                             float (*hs)[kRows][kSW]) {
+  const int r = threadIdx.x / (kSW / kHRun), j0 = (threadIdx.x % (kSW / kHRun)) * kHRun;
+  if (r >= n) return;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    float row[kHRun + 2 * kRad];
+#pragma unroll
+    for (int t = 0; t < kHRun + 2 * kRad; ++t) row[t] = sp[q][r][j0 + t];
+#pragma unroll
+    for (int o = 0; o < kHRun; ++o) {
+      float acc = 0.f;
+#pragma unroll
+      for (int t = 0; t < kTaps; ++t) acc = fmaf(kGauss[t], row[o + t], acc);
+      hs[q][dst + r][j0 + o] = acc;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kLossBlock) ssim_grad_kernel(LossBatch batch, float lam_ssim, float lam_d) {
-  __shared__ float sp[3][kHaloH][kHaloW];
-  __shared__ float hs[3][kHaloH][kTileW];
+  __shared__ float sp[3][kBand][kSWH];
+  __shared__ float hs[3][kRows][kSW];
   __shared__ float s_nvalid;
-  const ViewArgs& a = batch.v[blockIdx.z / 3];
-  if ((int)blockIdx.x >= a.tiles_x || (int)blockIdx.y >= a.tiles_y) return;
-  const int c = blockIdx.z % 3;
+  const uint3 blk = xcd_block();
+  const ViewArgs& a = batch.v[blk.z / 3];
+  if ((int)blk.x >= a.tiles_x || (int)blk.y >= a.tiles_y) return;
+  const int c = blk.z % 3;
   const float n = 3.0f * (float)a.W * (float)a.H;
   const float w_ssim = -lam_ssim / n;
   const float w_l1 = (2.0f - lam_ssim) / n;  // L_c and the (1 - lambda_ssim) L1 part of L_SSIM
-  const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
+  const int x0 = blk.x * kSW, y0 = blk.y * kSeg;
   const size_t HW = (size_t)a.W * a.H;
   const float* P = a.P + (size_t)c * 3 * HW;
-  {
-    const float* planes[3] = {P, P + HW, P + 2 * HW};
-    load_halos<3>(planes, a.W, a.H, x0, y0, sp);
-  }
+  const float* planes[3] = {P, P + HW, P + 2 * HW};
   if (c == 0 && threadIdx.x == 0) {  // valid target-depth pixels of the view (first kernel's sums)
     double nv = 0.0;
     for (int k = 0; k < kSumSlots; ++k) nv += a.sums[3 * kSumSlots + k];
     s_nvalid = (float)nv;
   }
+  stage_rows<3>(planes, a.W, a.H, x0, y0 - kRad, 2 * kRad, sp);
   __syncthreads();
-  if (threadIdx.x < kHaloH * (kTileW / kHRun)) {
-    const int r = threadIdx.x / (kTileW / kHRun), j0 = (threadIdx.x % (kTileW / kHRun)) * kHRun;
+  partial_rows(sp, 2 * kRad, 0, hs);
+  const float nvalid = c == 0 ? s_nvalid : 0.f;  // read after the barrier below
+  const int seg_end = min(y0 + kSeg, a.H);
+  const int vj = threadIdx.x % kSW, vi0 = (threadIdx.x / kSW) * kVRun;
+  for (int yb = y0; yb < seg_end; yb += kBand) {
+    __syncthreads();
+    stage_rows<3>(planes, a.W, a.H, x0, yb + kRad, kBand, sp);
+    __syncthreads();
+    partial_rows(sp, kBand, 2 * kRad, hs);
+    __syncthreads();
+    float vq[3][kVRun];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      float row[kHRun + 2 * kRad];
+      float col[kVRun + 2 * kRad];
 #pragma unroll
-      for (int t = 0; t < kHRun + 2 * kRad; ++t) row[t] = sp[q][r][j0 + t];
+      for (int t = 0; t < kVRun + 2 * kRad; ++t) col[t] = hs[q][vi0 + t][vj];
 #pragma unroll
-      for (int o = 0; o < kHRun; ++o) {
+      for (int o = 0; o < kVRun; ++o) {
         float acc = 0.f;
 #pragma unroll
-        for (int t = 0; t < kTaps; ++t) acc = fmaf(kGauss[t], row[o + t], acc);
-        hs[q][r][j0 + o] = acc;
+        for (int t = 0; t < kTaps; ++t) acc = fmaf(kGauss[t], col[o + t], acc);
+        vq[q][o] = acc;
       }
     }
-  }
-  __syncthreads();
-  const float nvalid = c == 0 ? s_nvalid : 0.f;
-  const int vj = threadIdx.x % kTileW, vi0 = (threadIdx.x / kTileW) * kVRun;
-  float vq[3][kVRun];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    float col[kVRun + 2 * kRad];
-#pragma unroll
-    for (int t = 0; t < kVRun + 2 * kRad; ++t) col[t] = hs[q][vi0 + t][vj];
 #pragma unroll
     for (int o = 0; o < kVRun; ++o) {
-      float acc = 0.f;
-#pragma unroll
-      for (int t = 0; t < kTaps; ++t) acc = fmaf(kGauss[t], col[o + t], acc);
-      vq[q][o] = acc;
+      const int px = x0 + vj, py = yb + vi0 + o;
+      if (px >= a.W || py >= seg_end) continue;
+      const float q1 = vq[0][o], q2 = vq[1][o], q3 = vq[2][o];
+      const size_t pix = (size_t)py * a.W + px;
+      const float xv = a.x[c * HW + pix], yv = a.y[c * HW + pix];
+      a.gx[c * HW + pix] = w_ssim * (q1 + 2.f * xv * q2 + yv * q3) + w_l1 * sgnf(xv - yv);
+      if (c == 0) {
+        const float tv = a.t[pix];
+        a.gd[pix] = (tv > 0.0f && nvalid > 0.f) ? lam_d * sgnf(a.d[pix] - tv) / nvalid : 0.0f;
+        if (a.ga) a.ga[pix] = 0.0f;
+      }
     }
-  }
-#pragma unroll
-  for (int o = 0; o < kVRun; ++o) {
-    const int i = vi0 + o, j = vj;
-    const int px = x0 + j, py = y0 + i;
-    if (px >= a.W || py >= a.H) continue;
-    const float q1 = vq[0][o], q2 = vq[1][o], q3 = vq[2][o];
-    const size_t pix = (size_t)py * a.W + px;
-    const float xv = a.x[c * HW + pix], yv = a.y[c * HW + pix];
-    a.gx[c * HW + pix] = w_ssim * (q1 + 2.f * xv * q2 + yv * q3) + w_l1 * sgnf(xv - yv);
-    if (c == 0) {
-      const float tv = a.t[pix];
-      a.gd[pix] = (tv > 0.0f && nvalid > 0.f) ? lam_d * sgnf(a.d[pix] - tv) / nvalid : 0.0f;
-      if (a.ga) a.ga[pix] = 0.0f;
-    }
+    __syncthreads();
+    keep_halo_rows<3>(hs);
   }
 }
 
@@ -417,8 +499,8 @@ int vpgs_mapping_loss(vpgs_ctx* ctx, int n_views, const vpgs_camera* cams, const
       a.P = static_cast<float*>(ctx->loss_ws.p) + off;
       off += (size_t)9 * a.W * a.H;
       a.sums = static_cast<double*>(ctx->loss_sums.p) + (size_t)v * kSums * kSumSlots;
-      a.tiles_x = (a.W + kTileW - 1) / kTileW;
-      a.tiles_y = (a.H + kTileH - 1) / kTileH;
+      a.tiles_x = (a.W + kSW - 1) / kSW;
+      a.tiles_y = (a.H + kSeg - 1) / kSeg;
       gx = std::max(gx, a.tiles_x);
       gy = std::max(gy, a.tiles_y);
     }

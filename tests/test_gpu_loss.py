@@ -12,10 +12,14 @@ pytestmark = pytest.mark.gpu
 
 # Terms: the loss is a mean of float32 per-pixel values summed in double.
 TERM_RTOL = 2e-5
-# Gradient: per element |g - g_ref| <= GRAD_TOL * scale + 64 * fp32 + floor,
-# scale and fp32 from oracle_loss.view_grad_bounds (term magnitudes and the
-# float32 rounding amplification of the SSIM statistics).
+# Gradient: per element |g - g_ref| <= GRAD_TOL * scale + B_FACTOR * fp32 +
+# floor, scale and fp32 from oracle_loss.view_grad_bounds (term magnitudes
+# and the float32 rounding amplification of the SSIM statistics).  On these
+# cases every element is within GRAD_TOL * scale alone (the test prints how
+# many fp32 bounds an element needs beyond it: none); the fp32 term covers
+# images whose local variance is small against their mean.
 GRAD_TOL = 1e-5
+B_FACTOR = 4.0
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -67,8 +71,10 @@ def _check_view(x, d, y, t, terms, grads, lam_ssim=0.2, lam_d=1.0):
     # either sign
     kink = np.abs(x.astype(np.float64) - y) < 1e-6
     err = np.abs(gx - gx_ref)
-    bound = GRAD_TOL * scale + 64.0 * fp32 + 1e-12
+    bound = GRAD_TOL * scale + B_FACTOR * fp32 + 1e-12
     bad = (err > bound) & ~kink
+    need = np.maximum(err - GRAD_TOL * scale, 0.0) / (fp32 + 1e-30)
+    print("fp32 bounds needed beyond the scale term", float(need[~kink].max()), flush=True)
     assert not bad.any(), (int(bad.sum()), float((err / bound)[~kink].max()))
     dk = (t > 0) & (np.abs(d.astype(np.float64) - t) < 1e-6)
     assert np.all(np.abs(gd - gd_ref)[~dk] <= 1e-6 * np.abs(gd_ref).max() + 1e-12)
