@@ -198,6 +198,48 @@ __global__ void __launch_bounds__(kProjBlock) project_kernel(const CallTables* _
 // backward
 // ---------------------------------------------------------------------------
 
+// Wavefront reduce-scatter of the six pose terms: each step pairs a lane
+// with the one that differs in one lane-index bit, keeps half of its values
+// and adds the partner's copy of them.
+//   bit 5: p[i] with p[3 + i] by v_permlane32_swap            6 -> 3 values
+//   bit 4: (h0, h1) by v_permlane16_swap, h2 in both            3 -> 2
+//   bit 3: (a, c) by DPP row rotate 8 (lane xor 8)              2 -> 1
+//   bits 0-2: sums over the 8-lane group (DPP).
+// Lane L ends with the wave total of term 3 b5 + (b3 ? 2 : b4) (b = bits of
+// L).  All lanes of the wavefront must be active.
+template <int CTRL>
+__device__ __forceinline__ float pdpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float psum32(float lo, float hi) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float psum16(float lo, float hi) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float pose_reduce_scatter6(const float p[6], int lane) {
+  const bool b3 = (lane >> 3) & 1;
+  const float h0 = psum32(p[0], p[3]), h1 = psum32(p[1], p[4]), h2 = psum32(p[2], p[5]);
+  const float a = psum16(h0, h1);
+  const float c = psum16(h2, h2);
+  float x = (b3 ? c : a) + pdpp<0x128>(b3 ? a : c);  // row_ror:8
+  x += pdpp<0x141>(x);  // row_half_mirror
+  x += pdpp<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += pdpp<0x4E>(x);   // quad_perm [2,3,0,1]
+  return x;
+}
+__device__ __forceinline__ int pose_slot(int lane) {
+  const int b3 = (lane >> 3) & 1, b4 = (lane >> 4) & 1, b5 = (lane >> 5) & 1;
+  return 3 * b5 + (b3 ? 2 : b4);
+}
+// One lane per term: the first of its 8-lane group, and for term 3 b5 + 2
+// (held by the groups with b3 set) only the one with b4 = 0.
+__device__ __forceinline__ bool pose_writer(int lane) {
+  return (lane & 7) == 0 && !(((lane >> 3) & 1) && ((lane >> 4) & 1));
+}
+
 __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const CallTables* __restrict__ tab, ProjBuffers pb,
                                                                       float* __restrict__ acc,
                                                                       float* __restrict__ pose_partial) {
@@ -331,14 +373,10 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
     if (pose_partial != nullptr) {
       // wavefront sums (no barrier); the pose reduction adds the wavefronts
       const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-      for (int k = 0; k < 6; ++k)
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) pose[k] += __shfl_xor(pose[k], off, 64);
-      if (lane == 0) {
+      const float t = pose_reduce_scatter6(pose, lane);
+      if (pose_writer(lane)) {
         float* dst = pose_partial + (((size_t)v * gridDim.x + blockIdx.x) * kPosePartialsPerBlock + wave) * 6;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) dst[k] = pose[k];
+        dst[pose_slot(lane)] = t;
       }
     }
   }
