@@ -8,17 +8,18 @@
 // the anchor scaling (eq. 5) and a normalised quaternion.
 //
 // The heads are small dense products over a batch of anchors, so they run on
-// the matrix cores: a wavefront takes 16 anchors (the M rows of a 16x16x4
-// FP32 MFMA tile) end to end, with its input rows, hidden layer and head
-// outputs in a private slice of LDS; the block's four wavefronts share one
-// head's weights, staged in LDS, as the B operands.  The activations then run
-// one lane per (anchor, Gaussian) output so that the stores are contiguous.
+// the matrix cores: a wavefront takes 16 anchors (one dimension of a 16x16x4
+// FP32 MFMA tile) end to end and the block's four wavefronts share one head's
+// weights, staged in LDS.  The forward computes both products transposed
+// (anchors on the N columns), so the hidden layer never leaves registers and
+// each lane applies the activations to the outputs it holds.
 //
-// Backward: the same blocks recompute the forward, chain the upstream
-// Gaussian gradients through the activations and both layers with the same
-// tiles (feature, scaling and offset gradients are written directly), and,
-// holding every layer's input and output gradient for their 64 anchors in
-// LDS, form their share of the six weight-gradient products (W2 and W1 of
+// Backward: with the anchors on the M rows and each wavefront's input rows,
+// hidden layer and head outputs in a private slice of LDS, the blocks
+// recompute the forward, chain the upstream Gaussian gradients through the
+// activations and both layers with the same tiles (feature, scaling and
+// offset gradients are written directly), and, holding every layer's input
+// and output gradient for their 64 anchors in LDS, form their share of the six weight-gradient products (W2 and W1 of
 // each head, the bias as an extra all-ones column) on the matrix cores as one
 // partial row per block.  The rows are summed in a fixed order in two levels,
 // so the weight gradients are deterministic.
@@ -122,16 +123,15 @@ __device__ __forceinline__ int quot(int e, float inv) { return (int)(((float)e +
 
 // Runs store(e, load(e)) over the elements e < n of a wavefront, U per
 // lane at a time with the U loads issued before any store (the outputs
-// may not alias the inputs, but the compiler cannot know that).
+// may not alias the inputs, but the compiler cannot know that).  Lanes past
+// n load element n - 1 and store nothing, so the loads carry no branch and
+// are all in flight together.
 template <int U = 4, class Load, class Store>
 __device__ __forceinline__ void blocked(int n, int lane, Load load, Store store) {
   for (int base = 0; base < n; base += 64 * U) {
     decltype(load(0)) v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = base + lane + 64 * u;
-      if (e < n) v[u] = load(e);
-    }
+    for (int u = 0; u < U; ++u) v[u] = load(std::min(base + lane + 64 * u, n - 1));
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = base + lane + 64 * u;
@@ -144,16 +144,26 @@ __device__ __forceinline__ void blocked(int n, int lane, Load load, Store store)
 // wavefront's anchors a0 .. a0 + nv - 1 (rows past nv are zero), and the log
 // of their scalings (eq. 5).
 __device__ __forceinline__ void load_inputs(const DecArgs& A, int64_t a0, int nv, int lane, float* Hs, float* logl) {
+  // rows past the anchor count read the last anchor (all loads unconditional)
+  const int64_t last = A.m - 1;
+  float f[kRows / 2];
 #pragma unroll
-  for (int e = lane; e < kRows * 32; e += 64) {
-    const int r = e >> 5, i = e & 31;
-    Hs[r * kHP + i] = r < nv ? A.feat[(a0 + r) * 32 + i] : 0.0f;
+  for (int u = 0; u < kRows / 2; ++u) {
+    const int e = lane + 64 * u, r = e >> 5;
+    f[u] = A.feat[std::min(a0 + r, last) * 32 + (e & 31)];
+  }
+  const int64_t a = std::min(a0 + (lane & (kRows - 1)), last);
+  const float px = A.xyz[3 * a], py = A.xyz[3 * a + 1], pz = A.xyz[3 * a + 2];
+  const float sl = A.scale[std::min(a0 * 3 + std::min(lane, 3 * kRows - 1), 3 * last + 2)];
+#pragma unroll
+  for (int u = 0; u < kRows / 2; ++u) {
+    const int e = lane + 64 * u, r = e >> 5;
+    Hs[r * kHP + (e & 31)] = r < nv ? f[u] : 0.0f;
   }
   if (lane < kRows) {
     float d[4] = {0.f, 0.f, 0.f, 0.f};
     if (lane < nv) {
-      const int64_t a = a0 + lane;
-      const float dx = A.xyz[3 * a] - A.cx, dy = A.xyz[3 * a + 1] - A.cy, dz = A.xyz[3 * a + 2] - A.cz;
+      const float dx = px - A.cx, dy = py - A.cy, dz = pz - A.cz;
       const float delta = sqrtf(dx * dx + dy * dy + dz * dz);
       const float inv = 1.0f / delta;
       d[0] = dx * inv;
@@ -164,7 +174,7 @@ __device__ __forceinline__ void load_inputs(const DecArgs& A, int64_t a0, int nv
 #pragma unroll
     for (int j = 0; j < 4; ++j) Hs[lane * kHP + 32 + j] = d[j];
   }
-  if (lane < 3 * kRows) logl[lane] = lane < 3 * nv ? logf(A.scale[a0 * 3 + lane]) : 0.0f;
+  if (lane < 3 * kRows) logl[lane] = lane < 3 * nv ? logf(sl) : 0.0f;
 }
 
 // The parameters of head h in LDS, shared by the block's wavefronts, padded
@@ -193,21 +203,133 @@ __host__ __device__ constexpr int head_lds_floats(int W, int k) {
   return pad16(W) * kW1P + pad16(7 * k) * (pad16(W) + 1) + pad16(W) + pad16(7 * k);
 }
 
+// The staged parameters form one index space [W1 | W2 | b1 | b2] in their
+// padded layouts; each thread loads kStageU elements of it (padding reads a
+// valid address and is replaced by zero) before it stores any, so a head's
+// parameters arrive in one or two load latencies.  src_of(e) is the source
+// of element e (null for padding), dst_of(e) its LDS destination.
+constexpr int kStageU = 16;
+
+template <class Src, class Dst>
+__device__ __forceinline__ void stage_flat(int n, const float* any, Src src_of, Dst dst_of) {
+  lds_barrier();
+  for (int base = 0; base < n; base += kDecThreads * kStageU) {
+    float v[kStageU];
+#pragma unroll
+    for (int u = 0; u < kStageU; ++u) {
+      const int e = base + (int)threadIdx.x + kDecThreads * u;
+      const float* q = e < n ? src_of(e) : nullptr;
+      const float x = *(q != nullptr ? q : any);
+      v[u] = q != nullptr ? x : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kStageU; ++u) {
+      const int e = base + (int)threadIdx.x + kDecThreads * u;
+      if (e < n) *dst_of(e) = v[u];
+    }
+  }
+  lds_barrier();
+}
+
+// Head h's parameters in the backward's layout (HeadLds).  Synchronises
+// before (the previous head's may still be in use) and after.
+template <int KW>
 __device__ __forceinline__ void stage_weights(const DecArgs& A, int h, const HeadLds& p) {
-  const int W = A.width, outs = head_outs(h, A.k);
+  constexpr int wp = 16 * KW;
+  const int W = A.width, outs = head_outs(h, A.k), op = pad16(outs);
   const float* __restrict__ W1 = A.W1[h];
   const float* __restrict__ W2 = A.W2[h];
-  const int wp = pad16(W), op = pad16(outs);
-  lds_barrier();
-  for (int e = threadIdx.x; e < wp * kIn; e += kDecThreads) {
-    const int j = e / kIn;
-    p.w1[j * kW1P + e - j * kIn] = e < W * kIn ? W1[e] : 0.0f;
+  const float* __restrict__ b1 = A.b1[h];
+  const float* __restrict__ b2 = A.b2[h];
+  const int n1 = wp * kIn, n2 = n1 + op * wp, n3 = n2 + wp, n = n3 + op;
+  stage_flat(
+      n, W1,
+      [&](int e) -> const float* {
+        if (e < n1) return e / kIn < W ? W1 + e : nullptr;
+        if (e < n2) {
+          const int f = e - n1, o = f / wp, j = f - o * wp;
+          return (o < outs && j < W) ? W2 + o * W + j : nullptr;
+        }
+        if (e < n3) return e - n2 < W ? b1 + (e - n2) : nullptr;
+        return e - n3 < outs ? b2 + (e - n3) : nullptr;
+      },
+      [&](int e) -> float* {
+        if (e < n1) {
+          const int j = e / kIn;
+          return p.w1 + j * kW1P + (e - j * kIn);
+        }
+        if (e < n2) {
+          const int f = e - n1, o = f / wp;
+          return p.w2 + o * (wp + 1) + (f - o * wp);
+        }
+        if (e < n3) return p.b1 + (e - n2);
+        return p.b2 + (e - n3);
+      });
+}
+
+// The forward's layout of one head, for the transposed products (hidden
+// units and head outputs on the M rows, anchors on the N columns): W1 as
+// [wp][kIn], W2 as [pad16(outs)][wp + 4] (a pitch of 4 mod 16 words puts
+// the 16-byte reads of 16 rows on distinct banks), b1 [wp], b2
+// [pad16(outs)].  Head 2's rows are permuted so that a lane holds each
+// quaternion whole: row 4m + q is quaternion component q of Gaussian m, row
+// 4k + 3m + c scale axis c of Gaussian m.
+template <int KW>
+struct FwdLds {
+  static constexpr int wp = 16 * KW, P2 = wp + 4;
+  float* w1;
+  float* w2;
+  float* b1;
+  float* b2;
+  __device__ FwdLds(float* lds, int k) {
+    w1 = lds;
+    w2 = w1 + wp * kIn;
+    b1 = w2 + pad16(7 * k) * P2;
+    b2 = b1 + wp;
   }
-  for (int o = threadIdx.x / 64; o < op; o += kDecWaves)
-    for (int j = threadIdx.x & 63; j < wp; j += 64) p.w2[o * (wp + 1) + j] = (o < outs && j < W) ? W2[o * W + j] : 0.0f;
-  for (int j = threadIdx.x; j < wp; j += kDecThreads) p.b1[j] = j < W ? A.b1[h][j] : 0.0f;
-  for (int o = threadIdx.x; o < op; o += kDecThreads) p.b2[o] = o < outs ? A.b2[h][o] : 0.0f;
-  lds_barrier();
+};
+
+__host__ __device__ constexpr int fwd_lds_floats(int KW, int k) {
+  return 16 * KW * kIn + pad16(7 * k) * (16 * KW + 4) + 16 * KW + pad16(7 * k);
+}
+
+// The W2 (and b2) row of head h held at forward row s < 7k.
+__device__ __forceinline__ int fwd_row(int h, int s, int k) {
+  if (h < 2) return s;
+  if (s < 4 * k) return 7 * (s >> 2) + 3 + (s & 3);
+  const int r = s - 4 * k, m = r / 3;
+  return 7 * m + (r - 3 * m);
+}
+
+template <int KW>
+__device__ __forceinline__ void stage_forward(const DecArgs& A, int h, const FwdLds<KW>& p) {
+  constexpr int wp = FwdLds<KW>::wp, P2 = FwdLds<KW>::P2;
+  const int W = A.width, k = A.k, outs = head_outs(h, k), op = pad16(outs);
+  const float* __restrict__ W1 = A.W1[h];
+  const float* __restrict__ W2 = A.W2[h];
+  const float* __restrict__ b1 = A.b1[h];
+  const float* __restrict__ b2 = A.b2[h];
+  const int n1 = wp * kIn, n2 = n1 + op * wp, n3 = n2 + wp, n = n3 + op;
+  stage_flat(
+      n, W1,
+      [&](int e) -> const float* {
+        if (e < n1) return e < W * kIn ? W1 + e : nullptr;
+        if (e < n2) {
+          const int f = e - n1, o = f / wp, j = f - o * wp;
+          return (o < outs && j < W) ? W2 + fwd_row(h, o, k) * W + j : nullptr;
+        }
+        if (e < n3) return e - n2 < W ? b1 + (e - n2) : nullptr;
+        return e - n3 < outs ? b2 + fwd_row(h, e - n3, k) : nullptr;
+      },
+      [&](int e) -> float* {
+        if (e < n1) return p.w1 + e;
+        if (e < n2) {
+          const int f = e - n1, o = f / wp;
+          return p.w2 + o * P2 + (f - o * wp);
+        }
+        if (e < n3) return p.b1 + (e - n2);
+        return p.b2 + (e - n3);
+      });
 }
 
 // hid[r][j] = relu(b1[j] + sum_i W1[j][i] h[r][i]) for the KW column tiles
@@ -267,22 +389,24 @@ struct MeanIn {
   float off, x, l;
 };
 
+// Forward, one wavefront per 16 anchors with everything in registers: the
+// hidden layer is computed transposed, hid^T = W1 h^T (hidden units on the
+// M rows, the anchors on the N columns), which leaves lane (r, g) holding
+// hidden units 16 t + 4 g + i of anchor r: exactly the B operand of the
+// second product y^T = W2 hid^T when its contraction step (t, i) stands for
+// hidden unit 16 t + 4 g + i in lane group g.  Lane (r, g) then holds
+// outputs 16 t + 4 g + i of anchor r, which the activations map and store.
+// Only the staging of each head's parameters synchronises the block.
 template <int KW>
 __global__ void __launch_bounds__(kDecThreads) decode_forward_kernel(DecArgs A) {
   extern __shared__ float lds[];
-  constexpr int HP = 16 * KW + 1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int k = A.k, W = A.width, yp = out_pitch(k);
-  const float inv_k = 1.0f / k, inv_k3 = 1.0f / (3 * k);
-  const HeadLds P = head_lds(lds, W, k);
-  float* Hs = lds + head_lds_floats(W, k) + wave * (kRows * (kHP + HP + yp) + 3 * kRows);
-  float* hid = Hs + kRows * kHP;
-  float* ys = hid + kRows * HP;
-  float* logl = ys + kRows * yp;
+  constexpr int P2 = FwdLds<KW>::P2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lo = lane & 15, grp = lane >> 4;
+  const int k = A.k, k3 = 3 * k;
+  const float inv_k3 = 1.0f / k3;
+  const FwdLds<KW> P(lds, k);
   const int64_t a0 = ((int64_t)blockIdx.x * kDecWaves + wave) * kRows;
   const int nv = (int)std::max<int64_t>(std::min<int64_t>(A.m - a0, kRows), 0);
-  load_inputs(A, a0, nv, lane, Hs, logl);
-  const int k3 = 3 * k;
   blocked<8>(  // eq. 1
       nv * k3, lane,
       [&](int e) {
@@ -291,38 +415,87 @@ __global__ void __launch_bounds__(kDecThreads) decode_forward_kernel(DecArgs A) 
         return MeanIn{A.offsets[a0 * k3 + e], A.xyz[3 * a + c], A.scale[3 * a + c]};
       },
       [&](int e, MeanIn v) { A.means[a0 * k3 + e] = v.x + v.off * v.l; });
-  lds_barrier();
-  float ha[9];
+  // this lane's anchor; lanes past the anchor count read the last anchor and
+  // store nothing
+  const bool row_ok = lo < nv;
+  const int64_t a = std::min<int64_t>(a0 + lo, A.m - 1);
+  // inputs 9 g .. 9 g + 8 of h = [feat (32), direction (3), distance (1)]
+  // (eq. 3): the B operand of the first product
+  float hin[9];
 #pragma unroll
-  for (int ks = 0; ks < 9; ++ks) ha[ks] = Hs[(lane & 15) * kHP + 9 * (lane >> 4) + ks];
+  for (int s = 0; s < 9; ++s) hin[s] = A.feat[a * 32 + std::min(9 * grp + s, 31)];
+  const float px = A.xyz[3 * a], py = A.xyz[3 * a + 1], pz = A.xyz[3 * a + 2];
+  const float l0 = A.scale[3 * a], l1 = A.scale[3 * a + 1], l2 = A.scale[3 * a + 2];
+  if (grp == 3) {
+    const float dx = px - A.cx, dy = py - A.cy, dz = pz - A.cz;
+    const float delta = sqrtf(dx * dx + dy * dy + dz * dz);
+    const float inv = 1.0f / delta;
+    hin[5] = dx * inv;
+    hin[6] = dy * inv;
+    hin[7] = dz * inv;
+    hin[8] = delta;
+  }
+  const float logl[3] = {logf(l0), logf(l1), logf(l2)};  // eq. 5
   for (int h = 0; h < 3; ++h) {
+    stage_forward<KW>(A, h, P);
+    // hid^T = relu(W1 h^T + b1); KW independent accumulation chains
+    f32x4 acc[KW];
+#pragma unroll
+    for (int t = 0; t < KW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 9; ++s)
+#pragma unroll
+      for (int t = 0; t < KW; ++t) acc[t] = mma(P.w1[(16 * t + lo) * kIn + 9 * grp + s], hin[s], acc[t]);
+    float hid[KW][4];
+#pragma unroll
+    for (int t = 0; t < KW; ++t) {
+      const float4 b = *reinterpret_cast<const float4*>(P.b1 + 16 * t + 4 * grp);
+      hid[t][0] = fmaxf(acc[t][0] + b.x, 0.0f);
+      hid[t][1] = fmaxf(acc[t][1] + b.y, 0.0f);
+      hid[t][2] = fmaxf(acc[t][2] + b.z, 0.0f);
+      hid[t][3] = fmaxf(acc[t][3] + b.w, 0.0f);
+    }
     const int outs = head_outs(h, k);
-    stage_weights(A, h, P);
-    hidden_tiles<KW>(P.w1, P.b1, ha, hid, lane);
-    lds_barrier();
-    out_tiles<KW>(P.w2, P.b2, outs, hid, ys, yp, lane);
-    lds_barrier();
-    if (h == 0) {
-      for (int e = lane; e < nv * k; e += 64) {
-        const int r = quot(e, inv_k);
-        A.opac[a0 * k + e] = tanh_hw(ys[r * yp + e - r * k]);
-      }
-    } else if (h == 1) {
-      for (int e = lane; e < nv * k3; e += 64) {  // eq. 4
-        const int r = quot(e, inv_k3);
-        A.colors[a0 * k3 + e] = sigmoidf_(ys[r * yp + e - r * k3]);
-      }
-    } else {
-      for (int e = lane; e < nv * k; e += 64) {
-        const int r = quot(e, inv_k);
-        const float* y = ys + r * yp + 7 * (e - r * k);
-        const int64_t g = a0 * k + e;
+    for (int o0 = 0; o0 < outs; o0 += 16) {
+      // y^T = W2 hid^T + b2 for rows o0 .. o0 + 15; two interleaved
+      // accumulators halve the dependent chain
+      f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int j = 0; j < 3; ++j) A.log_scales[3 * g + j] = log_sigmoidf_(y[j]) + logl[3 * r + j];  // eq. 5
-        const float n = fmaxf(sqrtf(y[3] * y[3] + y[4] * y[4] + y[5] * y[5] + y[6] * y[6]), 1e-12f);
+      for (int t = 0; t < KW; ++t) {
+        const float4 w = *reinterpret_cast<const float4*>(P.w2 + (o0 + lo) * P2 + 16 * t + 4 * grp);
+        c0 = mma(w.x, hid[t][0], c0);
+        c1 = mma(w.y, hid[t][1], c1);
+        c0 = mma(w.z, hid[t][2], c0);
+        c1 = mma(w.w, hid[t][3], c1);
+      }
+      const f32x4 c = c0 + c1;
+      const float4 b = *reinterpret_cast<const float4*>(P.b2 + o0 + 4 * grp);
+      const float y[4] = {c[0] + b.x, c[1] + b.y, c[2] + b.z, c[3] + b.w};
+      const int s0 = o0 + 4 * grp;  // rows s0 .. s0 + 3 of anchor a
+      if (!row_ok) continue;
+      if (h == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (s0 + i < k) A.opac[a * k + s0 + i] = tanh_hw(y[i]);
+      } else if (h == 1) {  // eq. 4
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (s0 + i < k3) A.colors[a * k3 + s0 + i] = sigmoidf_(y[i]);
+      } else if (s0 < 4 * k) {  // the quaternion of Gaussian s0 / 4
+        const float n = fmaxf(sqrtf(y[0] * y[0] + y[1] * y[1] + y[2] * y[2] + y[3] * y[3]), 1e-12f);
         const float in = 1.0f / n;
+        float* q = A.quats + 4 * (a * k + (s0 >> 2));
 #pragma unroll
-        for (int j = 0; j < 4; ++j) A.quats[4 * g + j] = y[3 + j] * in;
+        for (int i = 0; i < 4; ++i) q[i] = y[i] * in;
+      } else {  // scale axis (s - 4k) % 3 of Gaussian (s - 4k) / 3 (eq. 5)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = s0 + i - 4 * k;
+          if (r < k3) {
+            const int c = r % 3;
+            A.log_scales[a * k3 + r] = log_sigmoidf_(y[i]) + (c == 0 ? logl[0] : c == 1 ? logl[1] : logl[2]);
+          }
+        }
       }
     }
   }
@@ -469,8 +642,28 @@ __global__ void __launch_bounds__(kDecThreads) decode_backward_kernel(DecArgs A)
     const int64_t a = a0 + r;
     const float l = A.scale[3 * a + c];
     float s = 0.0f;
-    for (int m = 0; m < k; ++m) s = fmaf(A.g_means[3 * (a * k + m) + c], A.offsets[3 * (a * k + m) + c], s);
-    for (int m = 0; m < k; ++m) s += A.g_ls[3 * (a * k + m) + c] / l;
+    // eight Gaussians' loads in flight at a time (k <= 16); the sum keeps
+    // its order: the mean terms, then the log-scale terms
+    for (int m0 = 0; m0 < k; m0 += 8) {
+      float gm[8], of[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t i = 3 * (a * k + std::min(m0 + u, k - 1)) + c;
+        gm[u] = A.g_means[i];
+        of[u] = A.offsets[i];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (m0 + u < k) s = fmaf(gm[u], of[u], s);
+    }
+    for (int m0 = 0; m0 < k; m0 += 8) {
+      float gl[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) gl[u] = A.g_ls[3 * (a * k + std::min(m0 + u, k - 1)) + c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (m0 + u < k) s += gl[u] / l;
+    }
     A.d_scale[3 * a + c] = s;
   }
   lds_barrier();
@@ -480,7 +673,7 @@ __global__ void __launch_bounds__(kDecThreads) decode_backward_kernel(DecArgs A)
   f32x4 dh[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
   for (int h = 0; h < 3; ++h) {
     const int outs = head_outs(h, k);
-    stage_weights(A, h, P);
+    stage_weights<KW>(A, h, P);
     hidden_tiles<KW>(P.w1, P.b1, ha, hid, lane);
     lds_barrier();
     out_tiles<KW>(P.w2, P.b2, outs, hid, ys, yp, lane);
@@ -630,7 +823,8 @@ size_t dec_lds_bytes(int W, int k) {
 }
 
 template <int KW>
-hipError_t launch_kw(bool backward, const DecArgs& A, unsigned blocks, size_t lds, hipStream_t s) {
+hipError_t launch_kw(bool backward, const DecArgs& A, unsigned blocks, hipStream_t s) {
+  const size_t lds = backward ? dec_lds_bytes(A.width, A.k) : (size_t)fwd_lds_floats(KW, A.k) * sizeof(float);
   const void* f = backward ? reinterpret_cast<const void*>(&decode_backward_kernel<KW>)
                            : reinterpret_cast<const void*>(&decode_forward_kernel<KW>);
   hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -640,21 +834,20 @@ hipError_t launch_kw(bool backward, const DecArgs& A, unsigned blocks, size_t ld
   return hipGetLastError();
 }
 
-// LDS per block: the staged parameters of one head and, per wavefront, its
-// input rows, hidden layer, head outputs and log scalings; at most about
-// 146 KB (width 128, k = 16).
+// LDS per block: the staged parameters of one head (forward: at most about
+// 77 KB, width 128 and k = 16) and, in the backward, per wavefront its input
+// rows, hidden layer, head outputs and log scalings (at most about 146 KB).
 hipError_t launch_dec_any(bool backward, const DecArgs& A, hipStream_t s, unsigned blocks) {
   if (blocks == 0) return hipSuccess;
-  const size_t lds = dec_lds_bytes(A.width, A.k);
   switch ((A.width + 15) / 16) {
-    case 1: return launch_kw<1>(backward, A, blocks, lds, s);
-    case 2: return launch_kw<2>(backward, A, blocks, lds, s);
-    case 3: return launch_kw<3>(backward, A, blocks, lds, s);
-    case 4: return launch_kw<4>(backward, A, blocks, lds, s);
-    case 5: return launch_kw<5>(backward, A, blocks, lds, s);
-    case 6: return launch_kw<6>(backward, A, blocks, lds, s);
-    case 7: return launch_kw<7>(backward, A, blocks, lds, s);
-    case 8: return launch_kw<8>(backward, A, blocks, lds, s);
+    case 1: return launch_kw<1>(backward, A, blocks, s);
+    case 2: return launch_kw<2>(backward, A, blocks, s);
+    case 3: return launch_kw<3>(backward, A, blocks, s);
+    case 4: return launch_kw<4>(backward, A, blocks, s);
+    case 5: return launch_kw<5>(backward, A, blocks, s);
+    case 6: return launch_kw<6>(backward, A, blocks, s);
+    case 7: return launch_kw<7>(backward, A, blocks, s);
+    case 8: return launch_kw<8>(backward, A, blocks, s);
     default: return hipErrorInvalidValue;
   }
 }
