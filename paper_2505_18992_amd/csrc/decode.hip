@@ -574,26 +574,37 @@ __device__ __forceinline__ void wgrad_tiles(const float* region0, int region_flo
   for (int t = wave * nt / kDecWaves; t < t1; ++t) {
     const int pt = t / nqt, qt = t - pt * nqt;
     const int p = 16 * pt + lo, q = 16 * qt + lo;
+    // anchor a = 4 s + g sits in the region of wavefront s / 4, at row
+    // 4 (s % 4) + g; every read is unconditional (columns past the matrix
+    // read its last column), so all are in flight before the first MFMA
     if (pt != row) {
       row = pt;
+      // the masks clear anchors past the count and columns past P (as bit
+      // masks, so the reads stay unconditional)
+      const float* xs = region0 + xoff + grp * xp + std::min(p, P - 1);
+      const uint32_t colm = p < P ? ~0u : 0u;
 #pragma unroll
       for (int s = 0; s < 4 * kDecWaves; ++s) {
-        const int a = 4 * s + grp;
-        x[s] = (a < nvb && p < P) ? region0[(a >> 4) * region_floats + xoff + (a & 15) * xp + p] : 0.0f;
+        const float v = xs[(s >> 2) * region_floats + 4 * (s & 3) * xp];
+        x[s] = __uint_as_float(__float_as_uint(v) & (4 * s + grp < nvb ? colm : 0u));
       }
     }
     const bool qv = q < Q;
     const float one = q == Q ? 1.0f : 0.0f;
+    const float* ysrc = region0 + yoff + grp * ypitch + std::min(q, Q - 1);
+    float y[4 * kDecWaves];
+#pragma unroll
+    for (int s = 0; s < 4 * kDecWaves; ++s) {
+      const float v = ysrc[(s >> 2) * region_floats + 4 * (s & 3) * ypitch];
+      y[s] = qv ? v : one;
+    }
     // two interleaved accumulators (even and odd steps) halve the dependent
     // MFMA chain
     f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < 4 * kDecWaves; s += 2) {
-      const int a = 4 * s + grp, b = a + 4;
-      const float y0 = qv ? region0[(a >> 4) * region_floats + yoff + (a & 15) * ypitch + q] : one;
-      const float y1 = qv ? region0[(b >> 4) * region_floats + yoff + (b & 15) * ypitch + q] : one;
-      c0 = mma(x[s], y0, c0);
-      c1 = mma(x[s + 1], y1, c1);
+      c0 = mma(x[s], y[s], c0);
+      c1 = mma(x[s + 1], y[s + 1], c1);
     }
     const f32x4 c = c0 + c1;
     if (q <= Q) {
