@@ -124,8 +124,10 @@ __device__ __forceinline__ int quot(int e, float inv) { return (int)(((float)e +
 // Runs store(e, load(e)) over the elements e < n of a wavefront, U per
 // lane at a time with the U loads issued before any store (the outputs
 // may not alias the inputs, but the compiler cannot know that).  Lanes past
-// n load element n - 1 and store nothing, so the loads carry no branch and
-// are all in flight together.
+// n take element n - 1 and store the same value to it as its own lane, so
+// nothing depends on e < n and the loads are all in flight together (a
+// store under that condition would let the compiler move each load into
+// it, behind its own wait).  store(e, v) must depend only on e and v.
 template <int U = 4, class Load, class Store>
 __device__ __forceinline__ void blocked(int n, int lane, Load load, Store store) {
   for (int base = 0; base < n; base += 64 * U) {
@@ -133,9 +135,36 @@ __device__ __forceinline__ void blocked(int n, int lane, Load load, Store store)
 #pragma unroll
     for (int u = 0; u < U; ++u) v[u] = load(std::min(base + lane + 64 * u, n - 1));
 #pragma unroll
+    for (int u = 0; u < U; ++u) store(std::min(base + lane + 64 * u, n - 1), v[u]);
+  }
+}
+
+// Replaces the NV values at ptr(e) in LDS by f(load(e), values) for the
+// elements e < n of a wavefront, U per lane at a time: the U global loads
+// and LDS reads are all issued before any arithmetic.  Lanes past n take
+// element n - 1 and write the same values to it as its own lane (as in
+// blocked), so nothing is conditional.  Distinct elements never share LDS
+// values.
+template <int U, int NV, class Load, class Ptr, class F>
+__device__ __forceinline__ void rmw_blocked(int n, int lane, Load load, Ptr ptr, F f) {
+  for (int base = 0; base < n; base += 64 * U) {
+    decltype(load(0)) g[U];
+    float y[U][NV];
+#pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = base + lane + 64 * u;
-      if (e < n) store(e, v[u]);
+      const int e = std::min(base + lane + 64 * u, n - 1);
+      g[u] = load(e);
+      const float* p = ptr(e);
+#pragma unroll
+      for (int j = 0; j < NV; ++j) y[u][j] = p[j];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) f(g[u], y[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      float* p = ptr(std::min(base + lane + 64 * u, n - 1));
+#pragma unroll
+      for (int j = 0; j < NV; ++j) p[j] = y[u][j];
     }
   }
 }
@@ -566,47 +595,61 @@ __device__ __forceinline__ void input_grad_tiles(const float* w1s, const float* 
 __device__ __forceinline__ void wgrad_tiles(const float* region0, int region_floats, int xoff, int xp, int P,
                                             int yoff, int ypitch, int Q, int nvb, float* __restrict__ out, int wave,
                                             int lane) {
+  constexpr int S = 4 * kDecWaves;  // contraction steps: 4 anchors each
   const int lo = lane & 15, grp = lane >> 4;
   const int nqt = (Q + 16) >> 4, nt = ((P + 15) >> 4) * nqt;
-  const int t1 = (wave + 1) * nt / kDecWaves;
-  int row = -1;
-  float x[4 * kDecWaves];
-  for (int t = wave * nt / kDecWaves; t < t1; ++t) {
-    const int pt = t / nqt, qt = t - pt * nqt;
-    const int p = 16 * pt + lo, q = 16 * qt + lo;
-    // anchor a = 4 s + g sits in the region of wavefront s / 4, at row
-    // 4 (s % 4) + g; every read is unconditional (columns past the matrix
-    // read its last column), so all are in flight before the first MFMA
-    if (pt != row) {
-      row = pt;
-      // the masks clear anchors past the count and columns past P (as bit
-      // masks, so the reads stay unconditional)
-      const float* xs = region0 + xoff + grp * xp + std::min(p, P - 1);
-      const uint32_t colm = p < P ? ~0u : 0u;
+  const int t0 = wave * nt / kDecWaves, t1 = (wave + 1) * nt / kDecWaves;
+  if (t0 >= t1) return;
+  // anchor a = 4 s + g sits in the region of wavefront s / 4, at row
+  // 4 (s % 4) + g.  Every read is unconditional (columns past the matrix
+  // read its last column; bit masks clear padding and anchors past the
+  // count), so a tile's reads are in flight together.
+  auto load_x = [&](int pt, float* x) {
+    const int p = 16 * pt + lo;
+    const float* xs = region0 + xoff + grp * xp + std::min(p, P - 1);
+    const uint32_t colm = p < P ? ~0u : 0u;
 #pragma unroll
-      for (int s = 0; s < 4 * kDecWaves; ++s) {
-        const float v = xs[(s >> 2) * region_floats + 4 * (s & 3) * xp];
-        x[s] = __uint_as_float(__float_as_uint(v) & (4 * s + grp < nvb ? colm : 0u));
-      }
+    for (int s = 0; s < S; ++s) {
+      const float v = xs[(s >> 2) * region_floats + 4 * (s & 3) * xp];
+      x[s] = __uint_as_float(__float_as_uint(v) & (4 * s + grp < nvb ? colm : 0u));
     }
+  };
+  auto load_y = [&](int qt, float* y) {
+    const int q = 16 * qt + lo;
     const bool qv = q < Q;
     const float one = q == Q ? 1.0f : 0.0f;
-    const float* ysrc = region0 + yoff + grp * ypitch + std::min(q, Q - 1);
-    float y[4 * kDecWaves];
+    const float* ys = region0 + yoff + grp * ypitch + std::min(q, Q - 1);
 #pragma unroll
-    for (int s = 0; s < 4 * kDecWaves; ++s) {
-      const float v = ysrc[(s >> 2) * region_floats + 4 * (s & 3) * ypitch];
+    for (int s = 0; s < S; ++s) {
+      const float v = ys[(s >> 2) * region_floats + 4 * (s & 3) * ypitch];
       y[s] = qv ? v : one;
     }
+  };
+  int pt = t0 / nqt, qt = t0 - pt * nqt;
+  float x[S], y[S];
+  load_x(pt, x);
+  load_y(qt, y);
+  for (int t = t0; t < t1; ++t) {
+    // the next tile's operands load while this tile's products run
+    int npt = pt, nq = qt + 1;
+    if (nq == nqt) {
+      nq = 0;
+      ++npt;
+    }
+    const bool more = t + 1 < t1, new_row = more && npt != pt;
+    float xn[S], yn[S];
+    if (more) load_y(nq, yn);
+    if (new_row) load_x(npt, xn);
     // two interleaved accumulators (even and odd steps) halve the dependent
     // MFMA chain
     f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < 4 * kDecWaves; s += 2) {
+    for (int s = 0; s < S; s += 2) {
       c0 = mma(x[s], y[s], c0);
       c1 = mma(x[s + 1], y[s + 1], c1);
     }
     const f32x4 c = c0 + c1;
+    const int q = 16 * qt + lo;
     if (q <= Q) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -614,6 +657,16 @@ __device__ __forceinline__ void wgrad_tiles(const float* region0, int region_flo
         if (pp < P) out[pp * (Q + 1) + q] = c[i];
       }
     }
+    if (more) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) y[s] = yn[s];
+    }
+    if (new_row) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) x[s] = xn[s];
+    }
+    pt = npt;
+    qt = nq;
   }
 }
 
@@ -691,34 +744,40 @@ __global__ void __launch_bounds__(kDecThreads) decode_backward_kernel(DecArgs A)
     lds_barrier();
     // gradient at the head outputs, in place of the outputs
     if (h == 0) {  // tanh
-      blocked(
+      rmw_blocked<4, 1>(
           nv * k, lane, [&](int e) { return A.g_opac[a0 * k + e]; },
-          [&](int e, float go) {
+          [&](int e) {
             const int r = quot(e, inv_k);
-            float* y = ys + r * yp + e - r * k;
-            const float t = tanh_hw(*y);
-            *y = go * (1.0f - t * t);
+            return ys + r * yp + e - r * k;
+          },
+          [&](float go, float* y) {
+            const float t = tanh_hw(y[0]);
+            y[0] = go * (1.0f - t * t);
           });
     } else if (h == 1) {  // sigmoid (eq. 4)
-      blocked<8>(
+      rmw_blocked<8, 1>(
           nv * k3, lane, [&](int e) { return A.g_colors[a0 * k3 + e]; },
-          [&](int e, float gc) {
+          [&](int e) {
             const int r = quot(e, inv_k3);
-            float* y = ys + r * yp + e - r * k3;
-            const float s = sigmoidf_(*y);
-            *y = gc * s * (1.0f - s);
+            return ys + r * yp + e - r * k3;
+          },
+          [&](float gc, float* y) {
+            const float s = sigmoidf_(y[0]);
+            y[0] = gc * s * (1.0f - s);
           });
     } else {  // [scale (eq. 5) | quaternion]
-      blocked(
+      rmw_blocked<4, 7>(
           nv * k, lane,
           [&](int e) {
             const int64_t g = a0 * k + e;
             return ScaleGradIn{{A.g_ls[3 * g], A.g_ls[3 * g + 1], A.g_ls[3 * g + 2]},
                                {A.g_quats[4 * g], A.g_quats[4 * g + 1], A.g_quats[4 * g + 2], A.g_quats[4 * g + 3]}};
           },
-          [&](int e, const ScaleGradIn& v) {
+          [&](int e) {
             const int r = quot(e, inv_k);
-            float* y = ys + r * yp + 7 * (e - r * k);
+            return ys + r * yp + 7 * (e - r * k);
+          },
+          [&](const ScaleGradIn& v, float* y) {
             float dy[7];
 #pragma unroll
             for (int j = 0; j < 3; ++j) dy[j] = v.gl[j] * (1.0f - sigmoidf_(y[j]));  // d log_sigmoid(y) / dy
