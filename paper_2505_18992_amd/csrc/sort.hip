@@ -50,10 +50,34 @@ __device__ __forceinline__ uint32_t rect_count(uint2 r) {
 // larger ones by the whole wavefront, lanes over tiles) and the run is then
 // copied out 64 consecutive pairs at a time; otherwise they are written to
 // the pair list directly in the same way.
+//
+// A lane walks its record's tiles with a running (column, tile) pair; the
+// wavefront takes tile k of a large record from its row k / w, computed as
+// ((float)k + 1/2) (1/w): (k + 1/2) / w lies at least 1 / (2w) from an
+// integer and the product errs by under (k + 1/2) / w 2^-23, so the
+// truncation is exact for k < 2^22 (a rectangle holds at most 2^20 tiles:
+// 8192 / 8 on a side).
 template <class Out>
-__device__ __forceinline__ void emit_range(uint32_t k0, uint32_t k1, uint32_t stride, uint32_t pos, uint32_t rec,
-                                           uint32_t tile0, uint32_t w, uint32_t tiles_x, Out out) {
-  for (uint32_t k = k0; k < k1; k += stride) out(pos + k, tile0 + (k / w) * tiles_x + (k % w), rec);
+__device__ __forceinline__ void emit_lane(uint32_t c, uint32_t pos, uint32_t rec, uint32_t tile0, uint32_t w,
+                                          uint32_t tiles_x, Out out) {
+  uint32_t x = 0, t = tile0;
+  for (uint32_t k = 0; k < c; ++k) {
+    out(pos + k, t, rec);
+    ++t;
+    if (++x == w) {
+      x = 0;
+      t += tiles_x - w;
+    }
+  }
+}
+template <class Out>
+__device__ __forceinline__ void emit_wave(uint32_t lane, uint32_t c, uint32_t pos, uint32_t rec, uint32_t tile0,
+                                          uint32_t w, uint32_t tiles_x, Out out) {
+  const float inv_w = 1.0f / (float)w;
+  for (uint32_t k = lane; k < c; k += 64) {
+    const uint32_t row = (uint32_t)(((float)k + 0.5f) * inv_w);
+    out(pos + k, tile0 + row * tiles_x + (k - row * w), rec);
+  }
 }
 
 constexpr uint32_t kSmallFootprint = 8;  // records with more tiles are emitted by the whole wavefront
@@ -113,8 +137,8 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const CallTables* __re
     }
   };
   if (c <= kSmallFootprint) {
-    if (staged) emit_range(0, c, 1, off, rec, tile0, w, tiles_x, to_stage);
-    else emit_range(0, c, 1, off, rec, tile0, w, tiles_x, to_list);
+    if (staged) emit_lane(c, off, rec, tile0, w, tiles_x, to_stage);
+    else emit_lane(c, off, rec, tile0, w, tiles_x, to_list);
   }
   uint64_t big = __ballot(c > kSmallFootprint);
   while (big != 0ull) {
@@ -122,8 +146,8 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const CallTables* __re
     big &= big - 1ull;
     const uint32_t bc = __shfl(c, src, 64), boff = __shfl(off, src, 64), brec = __shfl(rec, src, 64);
     const uint32_t bt0 = __shfl(tile0, src, 64), bw = __shfl(w, src, 64), btx = __shfl(tiles_x, src, 64);
-    if (staged) emit_range((uint32_t)lane, bc, 64, boff, brec, bt0, bw, btx, to_stage);
-    else emit_range((uint32_t)lane, bc, 64, boff, brec, bt0, bw, btx, to_list);
+    if (staged) emit_wave((uint32_t)lane, bc, boff, brec, bt0, bw, btx, to_stage);
+    else emit_wave((uint32_t)lane, bc, boff, brec, bt0, bw, btx, to_list);
   }
   if (staged) {
     // LDS accesses of a wavefront complete in order: the reads see every
