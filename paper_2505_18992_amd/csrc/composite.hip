@@ -570,6 +570,9 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
       g[8] = w * gC2;
       g[9] = w * gD;
       const float mine = wave_reduce_scatter10(g, lane);
+      // an empty statement that consumes the sum here, so its last DPP step
+      // stays fused into one add instead of moving into the writers' branch
+      asm volatile("" ::"v"(mine));
       if (writer)
         unsafeAtomicAdd(reinterpret_cast<float*>(reinterpret_cast<char*>(acc) + (__float_as_uint(c.w) + 4u * slot_id)),
                         mine);
