@@ -542,11 +542,14 @@ __device__ __forceinline__ void backward_tile(const CallTables* __restrict__ tab
       if (__ballot(valid) == 0ull) continue;
       ++nactive;
       const float4 c = at_offset(sh.C, o);
-      const float r1m = __builtin_amdgcn_rcpf(1.0f - f.alpha);
-      const float Tj = valid ? T * r1m : T;
+      // invalid lanes take alpha = 0: then 1 / (1 - alpha) = 1 exactly, so
+      // they keep T and add nothing, with no further selects
+      const float a = valid ? f.alpha : 0.0f;
+      const float r1m = __builtin_amdgcn_rcpf(1.0f - a);
+      const float Tj = T * r1m;
       const float fj = fmaf(gC0, c.x, fmaf(gC1, c.y, fmaf(gC2, c.z, fmaf(gD, A.z, gA))));
       const float dLda = Tj * fj - S * r1m;
-      const float w = valid ? f.alpha * Tj : 0.0f;
+      const float w = a * Tj;
       S = fmaf(w, fj, S);
       T = Tj;
       // s = dL/dalpha * alpha where alpha is not clamped (0 where it is):
