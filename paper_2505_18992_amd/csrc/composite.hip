@@ -72,12 +72,16 @@ template <int TW, int TH, int NB>
 struct FwdShared {
   float4 A[NB + 1], E[NB + 1], C[NB + 1];  // by slot
   float2 V[NB];  // the quadrant test's vertex factors (ra, rc) of the record, by entry
-  uint32_t hits[(TW * TH) / 64][NB + kGroup];  // per wavefront: offsets of the entries that reach its quadrant
+  alignas(16) uint32_t hits[(TW * TH) / 64][NB + kGroup];  // per wavefront: offsets of the entries that reach its quadrant
 };
 
-// The slot array element at byte offset o (a hit-list entry).
+// The slot array element at byte offset o (a hit-list entry), and its
+// first two components.
 __device__ __forceinline__ const float4& at_offset(const float4* a, uint32_t o) {
   return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(a) + o);
+}
+__device__ __forceinline__ float2 at_offset2(const float4* a, uint32_t o) {
+  return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(a) + o);
 }
 
 // Each wavefront owns an 8x8 quadrant of its tile (lane -> (lane % 8,
@@ -259,12 +263,25 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
     uint32_t lb = 0;  // offset of this pixel's last blended entry of the batch (0: none)
     int g = 0;
     for (; g < nhit && __ballot(!done) != 0ull; g += kGroup) {
+      // the group's offsets in two 16-byte reads, so every entry's data
+      // reads can issue without waiting on a list read of its own
+      uint32_t ho[kGroup];
+#pragma unroll
+      for (int u = 0; u < kGroup; u += 4) {
+        const uint4 h4 = *reinterpret_cast<const uint4*>(hits + g + u);
+        ho[u] = h4.x;
+        ho[u + 1] = h4.y;
+        ho[u + 2] = h4.z;
+        ho[u + 3] = h4.w;
+      }
 #pragma unroll
       for (int u = 0; u < kGroup; ++u) {
-        const uint32_t o = hits[g + u];
-        const float4 A = at_offset(sh.A, o);
-        const Falloff f = falloff(A, at_offset(sh.E, o), pxc, pyc);
+        const uint32_t o = ho[u];
+        const float2 P = at_offset2(sh.A, o);
+        const float4 E = at_offset(sh.E, o);
+        const Falloff f = falloff(make_float4(P.x, P.y, 0.f, 0.f), E, pxc, pyc);
         const float4 c = at_offset(sh.C, o);
+        const float Az = at_offset(sh.A, o).z;
         if (COUNT) ne += (g + u < nhit && !done) ? 1u : 0u;
         const bool ok = !done && f.alpha >= kAlphaMin;
         const float Tn = T * (1.0f - f.alpha);
@@ -275,7 +292,7 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
           C0 = fmaf(w, c.x, C0);
           C1 = fmaf(w, c.y, C1);
           C2 = fmaf(w, c.z, C2);
-          D = fmaf(w, A.z, D);
+          D = fmaf(w, Az, D);
           T = Tn;
           lb = o;
           if (COUNT) nb += 1u;
