@@ -282,17 +282,30 @@ __global__ void __launch_bounds__(kLossBlock) ssim_stats_kernel(LossBatch batch)
     atomicAdd(&a.sums[1 * kSumSlots + slot], (double)l1sum);
   }
   if (c == 0) {  // depth terms once per pixel
+    // eight pixels' loads in flight per thread (out-of-range pixels read
+    // pixel 0 and count nothing); the sums keep the pixel order
+    constexpr int kDU = 8;
+    static_assert((kSeg * kSW) % (kLossBlock * kDU) == 0, "whole chunks");
     float dsum = 0.f, nvalid = 0.f;
-    for (int k = threadIdx.x; k < kSeg * kSW; k += kLossBlock) {
-      const int i = k / kSW, j = k - i * kSW;
-      const int px = x0 + j, py = y0 + i;
-      if (px >= a.W || py >= a.H) continue;
-      const size_t pix = (size_t)py * a.W + px;
-      const float tv = a.t[pix];
-      if (tv > 0.0f) {
-        dsum += fabsf(a.d[pix] - tv);
-        nvalid += 1.0f;
+    for (int k0 = threadIdx.x; k0 < kSeg * kSW; k0 += kLossBlock * kDU) {
+      float tv[kDU], dv[kDU];
+      bool ok[kDU];
+#pragma unroll
+      for (int u = 0; u < kDU; ++u) {
+        const int k = k0 + u * kLossBlock;
+        const int i = k / kSW, j = k - i * kSW;
+        const int px = x0 + j, py = y0 + i;
+        ok[u] = px < a.W && py < a.H;
+        const size_t pix = ok[u] ? (size_t)py * a.W + px : 0;
+        tv[u] = a.t[pix];
+        dv[u] = a.d[pix];
       }
+#pragma unroll
+      for (int u = 0; u < kDU; ++u)
+        if (ok[u] && tv[u] > 0.0f) {
+          dsum += fabsf(dv[u] - tv[u]);
+          nvalid += 1.0f;
+        }
     }
     dsum = block_sum(dsum, red);
     nvalid = block_sum(nvalid, red);
@@ -356,6 +369,22 @@ __global__ void __launch_bounds__(kLossBlock) ssim_grad_kernel(LossBatch batch, 
   const int seg_end = min(y0 + kSeg, a.H);
   const int vj = threadIdx.x % kSW, vi0 = (threadIdx.x / kSW) * kVRun;
   for (int yb = y0; yb < seg_end; yb += kBand) {
+    // the inputs of this thread's output pixels, issued before the staging
+    // so their loads overlap it (out-of-range pixels read pixel 0)
+    float ox[kVRun], oy[kVRun], ot[kVRun], od[kVRun];
+#pragma unroll
+    for (int o = 0; o < kVRun; ++o) {
+      const int px = x0 + vj, py = yb + vi0 + o;
+      const size_t pix = (px < a.W && py < seg_end) ? (size_t)py * a.W + px : 0;
+      ox[o] = a.x[c * HW + pix];
+      oy[o] = a.y[c * HW + pix];
+      if (c == 0) {
+        ot[o] = a.t[pix];
+        od[o] = a.d[pix];
+      } else {
+        ot[o] = od[o] = 0.0f;
+      }
+    }
     __syncthreads();
     stage_rows<3>(planes, a.W, a.H, x0, yb + kRad, kBand, sp);
     __syncthreads();
@@ -381,11 +410,11 @@ __global__ void __launch_bounds__(kLossBlock) ssim_grad_kernel(LossBatch batch, 
       if (px >= a.W || py >= seg_end) continue;
       const float q1 = vq[0][o], q2 = vq[1][o], q3 = vq[2][o];
       const size_t pix = (size_t)py * a.W + px;
-      const float xv = a.x[c * HW + pix], yv = a.y[c * HW + pix];
+      const float xv = ox[o], yv = oy[o];
       a.gx[c * HW + pix] = w_ssim * (q1 + 2.f * xv * q2 + yv * q3) + w_l1 * sgnf(xv - yv);
       if (c == 0) {
-        const float tv = a.t[pix];
-        a.gd[pix] = (tv > 0.0f && nvalid > 0.f) ? lam_d * sgnf(a.d[pix] - tv) / nvalid : 0.0f;
+        const float tv = ot[o];
+        a.gd[pix] = (tv > 0.0f && nvalid > 0.f) ? lam_d * sgnf(od[o] - tv) / nvalid : 0.0f;
         if (a.ga) a.ga[pix] = 0.0f;
       }
     }
