@@ -94,29 +94,46 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
 // load of the thread is issued before its first LDS write (out-of-image
 // slots read the plane's first element and are replaced by zero).
 constexpr int kStagePer = (kBand * kSWH + kLossBlock - 1) / kLossBlock;
+// A thread's share of staging rows r0 .. r0 + n - 1 (columns x0 - kRad ..
+// x0 + kSW + kRad - 1) of NP planes: loaded into registers by load(), then
+// written to LDS by store() (zero outside the image), so the loads of the
+// next rows can be issued while the current ones are still in use.
+template <int NP>
+struct StageRegs {
+  float v[NP][kStagePer];
+  bool in[kStagePer];
+  int n;
+  __device__ __forceinline__ void load(const float* const* src, int W, int H, int x0, int r0, int n_) {
+    n = n_;
+#pragma unroll
+    for (int u = 0; u < kStagePer; ++u) {
+      const int k = (int)threadIdx.x + u * kLossBlock;
+      const int r = k / kSWH, c = k - r * kSWH;  // constant divisor
+      const int gy = r0 + r, gx = x0 - kRad + c;
+      in[u] = r < n && gx >= 0 && gx < W && gy >= 0 && gy < H;
+      const size_t off = in[u] ? (size_t)gy * W + gx : 0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) v[q][u] = src[q][off];
+    }
+  }
+  __device__ __forceinline__ void store(float (*lds)[kBand][kSWH]) const {
+#pragma unroll
+    for (int u = 0; u < kStagePer; ++u) {
+      const int k = (int)threadIdx.x + u * kLossBlock;
+      const int r = k / kSWH, c = k - r * kSWH;
+      if (r >= n) continue;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) lds[q][r][c] = in[u] ? v[q][u] : 0.0f;
+    }
+  }
+};
+
 template <int NP>
 __device__ __forceinline__ void stage_rows(const float* const* src, int W, int H, int x0, int r0, int n,
                                            float (*lds)[kBand][kSWH]) {
-  float v[NP][kStagePer];
-  bool in[kStagePer];
-#pragma unroll
-  for (int u = 0; u < kStagePer; ++u) {
-    const int k = (int)threadIdx.x + u * kLossBlock;
-    const int r = k / kSWH, c = k - r * kSWH;  // constant divisor
-    const int gy = r0 + r, gx = x0 - kRad + c;
-    in[u] = r < n && gx >= 0 && gx < W && gy >= 0 && gy < H;
-    const size_t off = in[u] ? (size_t)gy * W + gx : 0;
-#pragma unroll
-    for (int q = 0; q < NP; ++q) v[q][u] = src[q][off];
-  }
-#pragma unroll
-  for (int u = 0; u < kStagePer; ++u) {
-    const int k = (int)threadIdx.x + u * kLossBlock;
-    const int r = k / kSWH, c = k - r * kSWH;
-    if (r >= n) continue;
-#pragma unroll
-    for (int q = 0; q < NP; ++q) lds[q][r][c] = in[u] ? v[q][u] : 0.0f;
-  }
+  StageRegs<NP> st;
+  st.load(src, W, H, x0, r0, n);
+  st.store(lds);
 }
 
 // Moves the last 2 kRad horizontally filtered rows to the top of hs (the
@@ -199,7 +216,9 @@ __device__ __forceinline__ void stats_rows(const float (*sxy)[kBand][kSWH], int 
   }
 }
 
-__global__ void __launch_bounds__(kLossBlock) ssim_stats_kernel(LossBatch batch) {
+// At most 128 VGPRs (four wavefronts per SIMD): the next band's rows held
+// in registers would otherwise cost a wavefront per SIMD.
+__global__ void __launch_bounds__(kLossBlock) __attribute__((amdgpu_waves_per_eu(4))) ssim_stats_kernel(LossBatch batch) {
   __shared__ float sxy[2][kBand][kSWH];  // staged x, y rows
   __shared__ float hs[5][kRows][kSW];    // horizontal sums of x, y, x^2, y^2, xy
   __shared__ float red[kLossBlock / 64];
@@ -212,35 +231,50 @@ __global__ void __launch_bounds__(kLossBlock) ssim_stats_kernel(LossBatch batch)
   const float* planes[2] = {a.x + c * HW, a.y + c * HW};
   float* P = a.P + (size_t)c * 3 * HW;
   float ssum = 0.f, l1sum = 0.f;
-  // the segment's upper halo: input rows y0 - 5 .. y0 + 4
-  stage_rows<2>(planes, a.W, a.H, x0, y0 - kRad, 2 * kRad, sxy);
+  // the segment's upper halo (input rows y0 - 5 .. y0 + 4), with the first
+  // band's rows loaded alongside; each band then loads the next band's rows
+  // while it filters
+  StageRegs<2> nxt;
+  {
+    StageRegs<2> halo;
+    halo.load(planes, a.W, a.H, x0, y0 - kRad, 2 * kRad);
+    nxt.load(planes, a.W, a.H, x0, y0 + kRad, kBand);
+    halo.store(sxy);
+  }
   __syncthreads();
   stats_rows(sxy, 2 * kRad, 0, hs);
   const int seg_end = min(y0 + kSeg, a.H);
   const int vj = threadIdx.x % kSW, vi0 = (threadIdx.x / kSW) * kVRun;
   for (int yb = y0; yb < seg_end; yb += kBand) {
+    const int lr = threadIdx.x / kSW, lj = threadIdx.x % kSW;
+    // output rows yb .. yb + 4 are still staged from the previous band (its
+    // staged rows kBand - 5 ..) or, in the first band, from the upper halo
+    // (staged rows 5 .. 9): their |x - y| terms, before the staging below
+    // overwrites them
+    float lprev = 0.f;
+    const bool lhave = lr < kRad && yb + lr < seg_end && x0 + lj < a.W;
+    if (lhave) {
+      const int rr = (yb == y0 ? kRad : kBand - kRad) + lr;
+      lprev = fabsf(sxy[0][rr][lj + kRad] - sxy[1][rr][lj + kRad]);
+    }
     __syncthreads();
     // input rows yb + 5 .. yb + kBand + 4 after the 10 already filtered
-    stage_rows<2>(planes, a.W, a.H, x0, yb + kRad, kBand, sxy);
+    nxt.store(sxy);
     __syncthreads();
     stats_rows(sxy, kBand, 2 * kRad, hs);
     {
       // |x - y| of the band's output pixels: rows yb + 5 .. yb + kBand - 1
       // are staged (staged row rr holds row yb + 5 + rr)
-      const int r = threadIdx.x / kSW, j = threadIdx.x % kSW;
 #pragma unroll
-      for (int rr = r; rr < kBand - kRad; rr += kLossBlock / kSW) {
+      for (int rr = lr; rr < kBand - kRad; rr += kLossBlock / kSW) {
         const int py = yb + kRad + rr;
-        if (py < seg_end && x0 + j < a.W) l1sum += fabsf(sxy[0][rr][j + kRad] - sxy[1][rr][j + kRad]);
+        if (py < seg_end && x0 + lj < a.W) l1sum += fabsf(sxy[0][rr][lj + kRad] - sxy[1][rr][lj + kRad]);
       }
-      // output rows yb .. yb + 4 came in the previous band's staging (or the
-      // upper halo): read them from memory
-      if (r < kRad && yb + r < seg_end && x0 + j < a.W) {
-        const size_t pix = (size_t)(yb + r) * a.W + x0 + j;
-        l1sum += fabsf(planes[0][pix] - planes[1][pix]);
-      }
+      if (lhave) l1sum += lprev;
     }
     __syncthreads();
+    // the next band's input rows, in flight through this band's vertical filter
+    if (yb + kBand < seg_end) nxt.load(planes, a.W, a.H, x0, yb + kBand + kRad, kBand);
     float vm[5][kVRun];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
