@@ -268,12 +268,25 @@ __global__ void __launch_bounds__(kProjBlock) project_backward_kernel(const Call
   const float o_acc = track ? fmaxf(o_par, 0.0f) : 0.0f;
   float a_grad = 0.f, a_ren = 0.f, a_op = 0.f, a_seen = 0.f;
 
+  uint32_t vis = 0;  // bit u: the record of view (vi & ~7) + u is visible
   for (int vi = 0; vi < S.view_count; ++vi) {
+    if ((vi & 7) == 0) {
+      // the tile counts of the next eight views' records, loaded together
+      uint32_t c8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int vj = min(vi + u, S.view_count - 1);
+        c8[u] = pb.count[tab->views[tab->set_views[S.view_first + vj]].rec_base + (uint32_t)ii];
+      }
+      vis = 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) vis |= (live && vi + u < S.view_count && c8[u] != 0) ? (1u << u) : 0u;
+    }
     const int v = tab->set_views[S.view_first + vi];
     const ViewDesc& V = tab->views[v];
     const uint32_t rec = V.rec_base + (uint32_t)ii;
     float pose[6] = {0, 0, 0, 0, 0, 0};
-    if (live && pb.count[rec] != 0) {
+    if ((vis >> (vi & 7)) & 1u) {
       // read the record's accumulated gradient and leave its row zero for
       // the next backward (rows of culled records are never touched)
       float* g = acc + (size_t)rec * kNumAcc;
