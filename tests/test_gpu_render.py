@@ -91,6 +91,41 @@ def test_c1_binning_bit_exact(tile):
     assert np.array_equal(ranges, er)
 
 
+@pytest.mark.parametrize("tile", [(8, 8), (32, 8)])
+def test_wide_footprint_binning_bit_exact(tile):
+    """Records whose tile rectangles are tens to thousands of tiles (up to the
+    whole 1200x680 view: 150 x 85 tiles of 8x8) are emitted by a whole
+    wavefront, each tile's row from a float reciprocal; keys, values and
+    ranges stay bit-exact against the oracle's binning."""
+    from paper_2505_18992_amd import _lib
+    sc = scenes.make_c1(seed=7, n=400, width=1200, height=680)
+    g, cam = sc.sets[0], sc.cameras[0]
+    rng = np.random.default_rng(17)
+    big = rng.choice(g.n, 80, replace=False)
+    # footprints from about ten pixels to beyond the view (f = 100, z in [2, 6])
+    g.log_scales[big] += rng.uniform(1.0, 5.5, (80, 1)).astype(np.float32)
+    print(f"case wide-footprint binning tile={tile}", flush=True)
+    _, outs, saved = _render(sc, tile=tile)
+    st = saved.stats()
+    P = st["n_pairs"]
+    proj = np_(saved.export(_lib.BUF_PROJ)).reshape(-1, 12)
+    ext = np_(saved.export(_lib.BUF_EXTENT)).reshape(-1, 2)
+    count = np_(saved.export(_lib.BUF_COUNT, torch.int32)).view(np.uint32)
+    keys = np_(saved.export(_lib.BUF_KEYS, torch.int64)).view(np.uint64)[:P]
+    vals = np_(saved.export(_lib.BUF_VALUES, torch.int32)).view(np.uint32)[:P]
+    ranges = np_(saved.export(_lib.BUF_RANGES, torch.int32)).view(np.uint32).reshape(-1, 2)
+    saved.close()
+    ok = count > 0
+    # the case reaches the wide rectangles it is about
+    assert count[big[ok[big]]].max() > 2000 and int((count > 8).sum()) >= 40, (count[big].max(), (count > 8).sum())
+    ek, ev, er = oracle.binning(ok.copy(), proj[:, 0], proj[:, 1], np.where(ok, ext[:, 0], 0),
+                                np.where(ok, ext[:, 1], 0), proj[:, 2].view(np.uint32), cam.width, cam.height, *tile)
+    assert P == len(ek) and st["overflow"] == 0
+    assert np.array_equal(keys, ek)
+    assert np.array_equal(vals, ev)
+    assert np.array_equal(ranges, er)
+
+
 @pytest.mark.parametrize("tile", [(32, 8), (16, 16)])
 def test_c4_binning_bit_exact(tile):
     """The benchmark's binning: 8 keyframes at 1200x680 of the 1M-Gaussian
