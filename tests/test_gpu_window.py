@@ -31,12 +31,13 @@ def _eager(sets, cams, vset, gw, tile):
     return outs, grads, d_pose
 
 
-def _close(a, b, rel=2e-3):
-    """Two FP32 runs differ only in the order of their atomic additions.  A
-    Gaussian that covers ~1e5 pixels sums terms of both signs whose
-    magnitudes exceed the total by ~1e3, so the order can move an element by
-    ~1e-3 of the tensor's largest value (the oracle comparisons bound each
-    run against its summation scale)."""
+def _close(a, b, rel=2e-4):
+    """Two FP32 runs differ only in the order of their atomic additions.  On
+    this scene six eager runs differ by at most 8.3e-7 of a gradient tensor's
+    largest value and 3.9e-7 of the pose gradient's (1e-4 and 1.5e-6 on the
+    1 M-Gaussian, 8-view workload, whose Gaussians cover more pixels): the
+    gates, 2e-4 and 1e-4, leave more than a hundredfold margin (the oracle
+    comparisons bound each run against its summation scale)."""
     scale = float(b.abs().max()) + 1e-12
     return float((a - b).abs().max()) <= rel * scale
 
@@ -49,7 +50,7 @@ def _check(win, outs, grads, d_pose):
         for k, (a, b) in enumerate(zip(win.grads[s], grads[s])):
             assert _close(a, b), (s, k, float((a - b).abs().max()), float(b.abs().max()),
                                   int(torch.argmax((a - b).abs().reshape(-1))))
-    assert _close(win.d_pose, d_pose, 1e-2)
+    assert _close(win.d_pose, d_pose, 1e-4)
 
 
 @pytest.mark.parametrize("use_graph,persistent", [(True, 0), (True, 1024), (False, 0)])
