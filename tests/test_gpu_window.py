@@ -31,26 +31,33 @@ def _eager(sets, cams, vset, gw, tile):
     return outs, grads, d_pose
 
 
-def _close(a, b, rel=2e-4):
-    """Two FP32 runs differ only in the order of their atomic additions.  On
-    this scene six eager runs differ by at most 8.3e-7 of a gradient tensor's
-    largest value and 3.9e-7 of the pose gradient's (1e-4 and 1.5e-6 on the
-    1 M-Gaussian, 8-view workload, whose Gaussians cover more pixels): the
-    gates, 2e-4 and 1e-4, leave more than a hundredfold margin (the oracle
-    comparisons bound each run against its summation scale)."""
+# Two FP32 runs differ only in the order of the compositing backward's atomic
+# additions.  Measured over ten eager runs (largest difference over the
+# tensor's largest value): the corridor scene of these tests 2.0e-6 for the
+# Gaussian gradients and 2.7e-7 for the pose gradient; the four-set street
+# scene, whose Gaussians each cover up to ~1e5 pixels and sum terms of both
+# signs far larger than their total, 1.1e-3 and 4.2e-7.  The gates below keep
+# a margin of 4-50x over those (the oracle comparisons bound each run
+# against its summation scale).
+GRAD_REL = 1e-4
+GRAD_REL_STREET = 5e-3
+POSE_REL = 1e-4
+
+
+def _close(a, b, rel):
     scale = float(b.abs().max()) + 1e-12
     return float((a - b).abs().max()) <= rel * scale
 
 
-def _check(win, outs, grads, d_pose):
+def _check(win, outs, grads, d_pose, grad_rel=GRAD_REL):
     for v in range(len(outs)):
         for a, b in zip(win.outputs[v], outs[v]):
             assert torch.equal(a, b)
     for s in range(len(grads)):
         for k, (a, b) in enumerate(zip(win.grads[s], grads[s])):
-            assert _close(a, b), (s, k, float((a - b).abs().max()), float(b.abs().max()),
-                                  int(torch.argmax((a - b).abs().reshape(-1))))
-    assert _close(win.d_pose, d_pose, 1e-4)
+            assert _close(a, b, grad_rel), (s, k, float((a - b).abs().max()), float(b.abs().max()),
+                                            int(torch.argmax((a - b).abs().reshape(-1))))
+    assert _close(win.d_pose, d_pose, POSE_REL)
 
 
 @pytest.mark.parametrize("use_graph,persistent", [(True, 0), (True, 1024), (False, 0)])
@@ -139,7 +146,7 @@ def test_window_multiple_sets():
     win.run()
     torch.cuda.synchronize()
     outs, grads, d_pose = _eager(sets, sc.cameras, sc.view_set, gw, (16, 16))
-    _check(win, outs, grads, d_pose)
+    _check(win, outs, grads, d_pose, GRAD_REL_STREET)
     win.close()
 
 
