@@ -353,6 +353,22 @@ __global__ void __launch_bounds__(kLossBlock) __attribute__((amdgpu_waves_per_eu
 // ---------------------------------------------------------------------------
 // kernel 2: gradient planes
 // ---------------------------------------------------------------------------
+// Loss terms of one view from the block sums: L_c, L_SSIM, L_d, total.
+__device__ void view_terms(const ViewArgs& a, float lam_ssim, float lam_d, float* __restrict__ terms) {
+  const double* sums = a.sums;
+  double s[kSums] = {0, 0, 0, 0};
+  for (int q = 0; q < kSums; ++q)
+    for (int k = 0; k < kSumSlots; ++k) s[q] += sums[q * kSumSlots + k];
+  const double n = 3.0 * a.W * a.H;
+  const double l1 = s[1] / n, ssim = s[0] / n;
+  const double ld = s[3] > 0 ? s[2] / s[3] : 0.0;
+  const double l_ssim = (1.0 - lam_ssim) * l1 + lam_ssim * (1.0 - ssim);
+  terms[0] = (float)l1;
+  terms[1] = (float)l_ssim;
+  terms[2] = (float)ld;
+  terms[3] = (float)(l1 + l_ssim + lam_d * ld);
+}
+
 __device__ __forceinline__ float sgnf(float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); }
 
 // Horizontal filter of the staged rows [0, n) of the three partial planes
@@ -376,7 +392,8 @@ __device__ __forceinline__ void partial_rows(const float (*sp)[kBand][kSWH], int
   }
 }
 
-__global__ void __launch_bounds__(kLossBlock) ssim_grad_kernel(LossBatch batch, float lam_ssim, float lam_d) {
+__global__ void __launch_bounds__(kLossBlock) ssim_grad_kernel(LossBatch batch, float lam_ssim, float lam_d,
+                                                                 float* __restrict__ terms) {
   __shared__ float sp[3][kBand][kSWH];
   __shared__ float hs[3][kRows][kSW];
   __shared__ float s_nvalid;
@@ -395,6 +412,9 @@ __global__ void __launch_bounds__(kLossBlock) ssim_grad_kernel(LossBatch batch, 
     double nv = 0.0;
     for (int k = 0; k < kSumSlots; ++k) nv += a.sums[3 * kSumSlots + k];
     s_nvalid = (float)nv;
+    // the first block of the view also reduces the first kernel's sums to the
+    // view's loss terms: L_c, L_SSIM, L_d and the total (eq. 7-8)
+    if (blk.x == 0 && blk.y == 0) view_terms(a, lam_ssim, lam_d, terms + 4 * (blk.z / 3));
   }
   stage_rows<3>(planes, a.W, a.H, x0, y0 - kRad, 2 * kRad, sp);
   __syncthreads();
@@ -457,25 +477,6 @@ __global__ void __launch_bounds__(kLossBlock) ssim_grad_kernel(LossBatch batch, 
   }
 }
 
-// Loss terms of one view from the block sums: L_c, L_SSIM, L_d, total.
-__global__ void loss_terms_kernel(LossBatch batch, float lam_ssim, float lam_d, float* __restrict__ terms) {
-  const ViewArgs& a = batch.v[blockIdx.x];
-  const double* sums = a.sums;
-  const int W = a.W, H = a.H;
-  terms += 4 * blockIdx.x;
-  if (threadIdx.x != 0) return;
-  double s[kSums] = {0, 0, 0, 0};
-  for (int q = 0; q < kSums; ++q)
-    for (int k = 0; k < kSumSlots; ++k) s[q] += sums[q * kSumSlots + k];
-  const double n = 3.0 * W * H;
-  const double l1 = s[1] / n, ssim = s[0] / n;
-  const double ld = s[3] > 0 ? s[2] / s[3] : 0.0;
-  const double l_ssim = (1.0 - lam_ssim) * l1 + lam_ssim * (1.0 - ssim);
-  terms[0] = (float)l1;
-  terms[1] = (float)l_ssim;
-  terms[2] = (float)ld;
-  terms[3] = (float)(l1 + l_ssim + lam_d * ld);
-}
 
 // Volume term of eq. 9: loss = lv sum_i prod(exp(l_i)); adds lv prod(exp(l_i))
 // to each of the three log-scale gradients of Gaussian i.
@@ -570,9 +571,7 @@ int vpgs_mapping_loss(vpgs_ctx* ctx, int n_views, const vpgs_camera* cams, const
     const dim3 grid(gx, gy, 3 * nb);
     hipLaunchKernelGGL(ssim_stats_kernel, grid, dim3(kLossBlock), 0, st, batch);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(ssim_grad_kernel, grid, dim3(kLossBlock), 0, st, batch, lam_ssim, lam_d);
-    HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(loss_terms_kernel, dim3(nb), dim3(64), 0, st, batch, lam_ssim, lam_d, terms + 4 * v0);
+    hipLaunchKernelGGL(ssim_grad_kernel, grid, dim3(kLossBlock), 0, st, batch, lam_ssim, lam_d, terms + 4 * v0);
     HIP_TRY(hipGetLastError());
   }
   return VPGS_OK;
