@@ -265,9 +265,13 @@ __global__ void __launch_bounds__(kIcpBlock) correspond_kernel(MapView M, const 
   }
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
+// Wavefront sum of values held only by the first lane of each G-lane group
+// (the other lanes hold zero): the butterfly levels below G would only add
+// zeros, so they are skipped; the result (in lane 0) is the same.
+template <int G>
+__device__ __forceinline__ float wave_sum_groups(float v) {
 #pragma unroll
-  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  for (int d = 32; d >= G; d >>= 1) v += __shfl_xor(v, d, 64);
   return v;
 }
 
@@ -319,7 +323,7 @@ __global__ void __launch_bounds__(kIcpBlock) linearize_kernel(MapView M, const f
   }
 #pragma unroll
   for (int k = 0; k < kTerms; ++k) {
-    const float s = wave_sum(t[k]);
+    const float s = wave_sum_groups<G>(t[k]);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][k] = s;
   }
   __syncthreads();
@@ -331,38 +335,39 @@ __global__ void __launch_bounds__(kIcpBlock) linearize_kernel(MapView M, const f
   }
 }
 
-// FP64 sums of the workgroup partials by one workgroup of kIcpBlock
-// threads: thread t adds the rows t, t + kIcpBlock, ... (each row one
-// contiguous run of kTerms floats), then the threads are summed by wavefront
-// shuffles and across the wavefronts in LDS.  The order is fixed, so the
-// sums are deterministic.
-__device__ __forceinline__ double wave_sum_f64(double v) {
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
-}
+// FP64 sums of the workgroup partials by one workgroup: kSumSplit threads
+// per term each add every kSumSplit-th row in row order (four rows in
+// flight), then one thread per term adds its kSumSplit partial sums in
+// order.  The order is fixed, so the sums are deterministic.
+constexpr int kSumSplit = 8;
+static_assert(kSumSplit * kTerms <= kIcpBlock, "one thread per (term, split)");
 
 __device__ void sum_partials(const float* __restrict__ partials, uint32_t nblocks, double* tot) {
-  __shared__ double wred[kIcpBlock / 64][kTerms];
-  double acc[kTerms];
-#pragma unroll
-  for (int k = 0; k < kTerms; ++k) acc[k] = 0.0;
-  for (uint32_t b = threadIdx.x; b < nblocks; b += kIcpBlock) {
-    const float* row = partials + (size_t)b * kTerms;
-#pragma unroll
-    for (int k = 0; k < kTerms; ++k) acc[k] += (double)row[k];
-  }
-#pragma unroll
-  for (int k = 0; k < kTerms; ++k) {
-    const double v = wave_sum_f64(acc[k]);
-    if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6][k] = v;
+  __shared__ double part[kSumSplit][kTerms];
+  const int t = threadIdx.x;
+  if (t < kSumSplit * kTerms) {
+    const int k = t % kTerms, p = t / kTerms;
+    double acc = 0.0;
+    uint32_t b = (uint32_t)p;
+    for (; b + 3 * kSumSplit < nblocks; b += 4 * kSumSplit) {
+      const float v0 = partials[(size_t)b * kTerms + k];
+      const float v1 = partials[(size_t)(b + kSumSplit) * kTerms + k];
+      const float v2 = partials[(size_t)(b + 2 * kSumSplit) * kTerms + k];
+      const float v3 = partials[(size_t)(b + 3 * kSumSplit) * kTerms + k];
+      acc += (double)v0;
+      acc += (double)v1;
+      acc += (double)v2;
+      acc += (double)v3;
+    }
+    for (; b < nblocks; b += kSumSplit) acc += (double)partials[(size_t)b * kTerms + k];
+    part[p][k] = acc;
   }
   __syncthreads();
-  if (threadIdx.x < kTerms) {
+  if (t < kTerms) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < kIcpBlock / 64; ++w) s += wred[w][threadIdx.x];
-    tot[threadIdx.x] = s;
+    for (int p = 0; p < kSumSplit; ++p) s += part[p][t];
+    tot[t] = s;
   }
   __syncthreads();
 }
@@ -384,9 +389,11 @@ __device__ void exp_se3(const double xi[6], double E[12]) {
   if (th < 1e-8) {
     a = 1.0; b = 0.5; cc = 1.0 / 6.0;
   } else {
-    a = sin(th) / th;
-    b = (1.0 - cos(th)) / (th * th);
-    cc = (th - sin(th)) / (th * th * th);
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    a = sn / th;
+    b = (1.0 - cs) / (th * th);
+    cc = (th - sn) / (th * th * th);
   }
   double V[9];
   for (int k = 0; k < 9; ++k) {
@@ -423,16 +430,17 @@ __global__ void __launch_bounds__(kIcpBlock) solve_kernel(const float* __restric
     }
   for (int a = 0; a < 6; ++a) g[a] = tot[21 + a];
   bool ok = st->count >= 6;
-  double L[36] = {0.0};
+  double L[36] = {0.0}, inv[6];  // inv[j] = 1 / L[j][j]
   for (int j = 0; j < 6 && ok; ++j) {  // Cholesky H = L L^T
     double d = H[6 * j + j];
     for (int q = 0; q < j; ++q) d -= L[6 * j + q] * L[6 * j + q];
     if (!(d > 0.0)) { ok = false; break; }
     L[6 * j + j] = sqrt(d);
+    inv[j] = 1.0 / L[6 * j + j];
     for (int r = j + 1; r < 6; ++r) {
       double s = H[6 * r + j];
       for (int q = 0; q < j; ++q) s -= L[6 * r + q] * L[6 * j + q];
-      L[6 * r + j] = s / L[6 * j + j];
+      L[6 * r + j] = s * inv[j];
     }
   }
   if (!ok) {
@@ -444,12 +452,12 @@ __global__ void __launch_bounds__(kIcpBlock) solve_kernel(const float* __restric
   for (int r = 0; r < 6; ++r) {  // L y = -g
     double s = -g[r];
     for (int q = 0; q < r; ++q) s -= L[6 * r + q] * y[q];
-    y[r] = s / L[6 * r + r];
+    y[r] = s * inv[r];
   }
   for (int r = 5; r >= 0; --r) {  // L^T dx = y
     double s = y[r];
     for (int q = r + 1; q < 6; ++q) s -= L[6 * q + r] * dx[q];
-    dx[r] = s / L[6 * r + r];
+    dx[r] = s * inv[r];
   }
   double E[12], T[12];
   exp_se3(dx, E);
