@@ -197,6 +197,8 @@ struct IcpState {
 // total order (d^2, index).  Every lane of the group returns the result: d^2
 // (+inf if no voxel has points), the original index (-1) and the sorted
 // position.  Few queries use wide groups (latency), many use narrow ones.
+constexpr uint32_t kScan = 4;  // points of a voxel compared per round
+
 template <int G>
 __device__ __forceinline__ void group_nearest(const MapView& M, float qx, float qy, float qz, int lane, float& bd,
                                               int32_t& bi, uint32_t& bp) {
@@ -211,16 +213,27 @@ __device__ __forceinline__ void group_nearest(const MapView& M, float qx, float 
     const int cz = vz + nb % 3 - 1;
     const int s = find_slot(M.keys, M.mask, pack_key(cx, cy, cz));
     if (s >= 0) {
+      // kScan points are loaded together; past the end of the run the last
+      // point is loaded again, and a point already compared never replaces
+      // the best (the comparison is strict in the total order)
       const uint2 run = M.vals[s];
-      for (uint32_t j = 0; j < run.y; ++j) {
-        const float4 m = M.pts[run.x + j];
-        const float dx = qx - m.x, dy = qy - m.y, dz = qz - m.z;
-        const float d2 = (dx * dx + dy * dy) + dz * dz;
-        const int32_t id = (int32_t)__float_as_uint(m.w);
-        if (d2 < bd || (d2 == bd && id < bi)) {
-          bd = d2;
-          bi = id;
-          bp = run.x + j;
+      for (uint32_t j = 0; j < run.y; j += kScan) {
+        float4 m[kScan];
+        uint32_t at[kScan];
+#pragma unroll
+        for (int u = 0; u < kScan; ++u) {
+          at[u] = run.x + min(j + u, run.y - 1);
+          m[u] = M.pts[at[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kScan; ++u) {
+          const float dx = qx - m[u].x, dy = qy - m[u].y, dz = qz - m[u].z;
+          const float d2 = (dx * dx + dy * dy) + dz * dz;
+          const int32_t id = (int32_t)__float_as_uint(m[u].w);
+          const bool take = d2 < bd || (d2 == bd && id < bi);
+          bd = take ? d2 : bd;
+          bi = take ? id : bi;
+          bp = take ? at[u] : bp;
         }
       }
     }
@@ -378,12 +391,14 @@ __global__ void __launch_bounds__(kIcpBlock) reduce_terms_kernel(const float* __
   if (threadIdx.x < kTerms) out[threadIdx.x] = tot[threadIdx.x];
 }
 
-__device__ void exp_se3(const double xi[6], double E[12]) {
+__device__ __forceinline__ void exp_se3(const double xi[6], double E[12]) {
   const double px = xi[3], py = xi[4], pz = xi[5];
   const double th = sqrt(px * px + py * py + pz * pz);
   const double K[9] = {0.0, -pz, py, pz, 0.0, -px, -py, px, 0.0};
   double K2[9];
+#pragma unroll
   for (int r = 0; r < 3; ++r)
+#pragma unroll
     for (int c = 0; c < 3; ++c) K2[3 * r + c] = K[3 * r] * K[c] + K[3 * r + 1] * K[3 + c] + K[3 * r + 2] * K[6 + c];
   double a, b, cc;
   if (th < 1e-8) {
@@ -396,15 +411,17 @@ __device__ void exp_se3(const double xi[6], double E[12]) {
     cc = (th - sn) / (th * th * th);
   }
   double V[9];
+#pragma unroll
   for (int k = 0; k < 9; ++k) {
     const double I = (k % 4 == 0) ? 1.0 : 0.0;
     E[4 * (k / 3) + k % 3] = I + a * K[k] + b * K2[k];
     V[k] = I + b * K[k] + cc * K2[k];
   }
+#pragma unroll
   for (int r = 0; r < 3; ++r) E[4 * r + 3] = V[3 * r] * xi[0] + V[3 * r + 1] * xi[1] + V[3 * r + 2] * xi[2];
 }
 
-__device__ void round_pose(const double T[12], Pose32& p) {
+__device__ __forceinline__ void round_pose(const double T[12], Pose32& p) {
   for (int r = 0; r < 3; ++r) {
     for (int c = 0; c < 3; ++c) p.R[3 * r + c] = (float)T[4 * r + c];
     p.t[r] = (float)T[4 * r + 3];
@@ -415,30 +432,48 @@ __device__ void round_pose(const double T[12], Pose32& p) {
 __global__ void __launch_bounds__(kIcpBlock) solve_kernel(const float* __restrict__ partials, uint32_t nblocks, IcpState* __restrict__ st,
                              double eps, int32_t max_iter) {
   __shared__ double tot[kTerms];
-  if (st->done) return;
+  // the state is read while the partial sums are loaded (they are read even
+  // after the registration has stopped, and then not used)
+  const int32_t done = st->done;
+  double T0[12];
+  int32_t iters = 0;
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < 12; ++q) T0[q] = st->T[q];
+    iters = st->iterations;
+  }
   sum_partials(partials, nblocks, tot);
-  if (threadIdx.x != 0) return;
+  if (done || threadIdx.x != 0) return;
   st->count = (int32_t)tot[27];
   st->rho = (float)tot[28];
+  // Every loop below has constant bounds and is unrolled, so that the
+  // matrices stay in registers (indexed arrays would live in scratch memory,
+  // one memory round trip per dependent access).
   double H[36], g[6];
   int k = 0;
+#pragma unroll
   for (int a = 0; a < 6; ++a)
+#pragma unroll
     for (int b = a; b < 6; ++b) {
       H[6 * a + b] = tot[k];
       H[6 * b + a] = tot[k];
       ++k;
     }
+#pragma unroll
   for (int a = 0; a < 6; ++a) g[a] = tot[21 + a];
   bool ok = st->count >= 6;
-  double L[36] = {0.0}, inv[6];  // inv[j] = 1 / L[j][j]
-  for (int j = 0; j < 6 && ok; ++j) {  // Cholesky H = L L^T
+  double L[36], inv[6];  // inv[j] = 1 / L[j][j]; only the lower triangle is used
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {  // Cholesky H = L L^T (not used once a pivot is not positive)
     double d = H[6 * j + j];
+#pragma unroll
     for (int q = 0; q < j; ++q) d -= L[6 * j + q] * L[6 * j + q];
-    if (!(d > 0.0)) { ok = false; break; }
+    ok = ok && d > 0.0;
     L[6 * j + j] = sqrt(d);
     inv[j] = 1.0 / L[6 * j + j];
+#pragma unroll
     for (int r = j + 1; r < 6; ++r) {
       double s = H[6 * r + j];
+#pragma unroll
       for (int q = 0; q < j; ++q) s -= L[6 * r + q] * L[6 * j + q];
       L[6 * r + j] = s * inv[j];
     }
@@ -449,13 +484,17 @@ __global__ void __launch_bounds__(kIcpBlock) solve_kernel(const float* __restric
     return;
   }
   double y[6], dx[6];
+#pragma unroll
   for (int r = 0; r < 6; ++r) {  // L y = -g
     double s = -g[r];
+#pragma unroll
     for (int q = 0; q < r; ++q) s -= L[6 * r + q] * y[q];
     y[r] = s * inv[r];
   }
+#pragma unroll
   for (int r = 5; r >= 0; --r) {  // L^T dx = y
     double s = y[r];
+#pragma unroll
     for (int q = r + 1; q < 6; ++q) s -= L[6 * q + r] * dx[q];
     dx[r] = s * inv[r];
   }
@@ -463,18 +502,18 @@ __global__ void __launch_bounds__(kIcpBlock) solve_kernel(const float* __restric
   exp_se3(dx, E);
   for (int r = 0; r < 3; ++r) {
     for (int c = 0; c < 3; ++c)
-      T[4 * r + c] = E[4 * r] * st->T[c] + E[4 * r + 1] * st->T[4 + c] + E[4 * r + 2] * st->T[8 + c];
-    T[4 * r + 3] = E[4 * r] * st->T[3] + E[4 * r + 1] * st->T[7] + E[4 * r + 2] * st->T[11] + E[4 * r + 3];
+      T[4 * r + c] = E[4 * r] * T0[c] + E[4 * r + 1] * T0[4 + c] + E[4 * r + 2] * T0[8 + c];
+    T[4 * r + 3] = E[4 * r] * T0[3] + E[4 * r + 1] * T0[7] + E[4 * r + 2] * T0[11] + E[4 * r + 3];
   }
   for (int q = 0; q < 12; ++q) st->T[q] = T[q];
   round_pose(T, st->p32);
-  st->iterations += 1;
+  st->iterations = ++iters;
   double nrm = 0.0;
   for (int q = 0; q < 6; ++q) nrm += dx[q] * dx[q];
   if (sqrt(nrm) < eps) {
     st->converged = 1;
     st->done = 1;
-  } else if (st->iterations >= max_iter) {
+  } else if (iters >= max_iter) {
     st->done = 1;
   }
 }
