@@ -100,6 +100,38 @@ def test_lane_group_widths_agree(street):
     gm.close()
 
 
+def test_correspondence_ties_bit_exact():
+    # dyadic map and query coordinates make many squared distances exactly
+    # equal: the nearest point is then the lowest index, within a voxel's
+    # run (runs of 3, 5, 7 and 20 points, the last capped) and across
+    # neighbouring voxels; duplicated points (higher indices) never win
+    from paper_2505_18992_amd import VoxelMap, icp_correspond
+    print("case correspondence ties", flush=True)
+    g = np.arange(0.0, 2.0, 0.25, dtype=np.float32)
+    lattice = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    rng = np.random.default_rng(11)
+    keep = np.concatenate([lattice[:: 7], lattice[3::11], lattice[rng.choice(len(lattice), 60, replace=False)]])
+    pts = np.concatenate([keep, keep[::-1][:40], lattice[lattice[:, 0] >= 1.5]])  # duplicates come later
+    q = np.arange(-0.75, 2.75, 0.125, dtype=np.float32)
+    qs = np.stack(np.meshgrid(q, q, q, indexing="ij"), -1).reshape(-1, 3)
+    for cap in (3, 5, 7, 20):
+        vm = icp.VoxelMap(pts, VOXEL, cap)
+        gm = VoxelMap(_dev(pts), VOXEL, cap)
+        assert gm.info() == (pts.shape[0], len(vm.cells))
+        nn, d2 = icp_correspond(gm, _dev(qs), np.eye(3, 4), TAU)
+        enn, ed2 = icp.correspond(vm, icp.transform32(qs, np.eye(3, 4)), TAU)
+        assert np.array_equal(nn.cpu().numpy(), enn), f"cap {cap}"
+        assert np.array_equal(d2.cpu().numpy().view(np.uint32), ed2.view(np.uint32)), f"cap {cap}"
+        # fewer queries (a voxel per lane) and the same queries many times
+        # over (four lanes per query) give the same answers
+        ns, ds = icp_correspond(gm, _dev(qs[:9000]), np.eye(3, 4), TAU)
+        assert np.array_equal(ns.cpu().numpy(), enn[:9000]) and np.array_equal(ds.cpu().numpy(), ed2[:9000])
+        big = np.tile(qs, (7, 1))
+        nb, db = icp_correspond(gm, _dev(big), np.eye(3, 4), TAU)
+        assert np.array_equal(nb.cpu().numpy(), np.tile(enn, 7)) and np.array_equal(db.cpu().numpy(), np.tile(ed2, 7))
+        gm.close()
+
+
 def test_cap_and_empty_map():
     from paper_2505_18992_amd import VoxelMap, icp_correspond
     m = np.array([[0.1, 0.1, 0.1], [0.5, 0.5, 0.5], [0.9, 0.2, 0.3]], np.float32)
