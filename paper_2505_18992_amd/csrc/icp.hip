@@ -90,12 +90,18 @@ __device__ __forceinline__ int find_slot(const uint64_t* __restrict__ keys, uint
   return -1;
 }
 
-// Slot of key k, inserting it if absent (-1 if the table is full).
+// Slot of key k, inserting it if absent (-1 if the table is full).  A slot's
+// key never changes once set, so a plain read that finds a key is final; only
+// a slot read as empty (possibly a stale read) is claimed by compare-and-swap.
+// Points of one voxel mostly find their key already there and do not queue on
+// its slot's atomics.
 __device__ __forceinline__ int insert_slot(uint64_t* __restrict__ keys, uint32_t mask, uint64_t k) {
   uint32_t s = hash_slot(k, mask);
   for (uint32_t step = 0; step <= mask; ++step) {
-    const uint64_t old = atomicCAS((unsigned long long*)&keys[s], (unsigned long long)kEmpty, (unsigned long long)k);
-    if (old == kEmpty || old == k) return (int)s;
+    uint64_t cur = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == kEmpty)
+      cur = atomicCAS((unsigned long long*)&keys[s], (unsigned long long)kEmpty, (unsigned long long)k);
+    if (cur == kEmpty || cur == k) return (int)s;
     s = (s + 1) & mask;
   }
   return -1;
@@ -154,12 +160,24 @@ __global__ void map_insert_kernel(const float4* __restrict__ pts, const uint32_t
 
 // ---- downsampling ------------------------------------------------------------------
 
-__global__ void ds_insert_kernel(const float* __restrict__ p, uint32_t n, float v, uint64_t* __restrict__ keys,
-                                 uint32_t* __restrict__ first, uint32_t mask) {
+// A scan arrives in sweep order, so neighbouring points mostly share a
+// voxel: of a run of lanes with one key only the first (the smallest index
+// of the run) inserts it and offers its index, and the others, which could
+// not win, add no atomics to the same slot.  Runs of one key that are not
+// adjacent each insert, which the table and atomicMin resolve.
+__global__ void __launch_bounds__(256) ds_insert_kernel(const float* __restrict__ p, uint32_t n, float v,
+                                                        uint64_t* __restrict__ keys, uint32_t* __restrict__ first,
+                                                        uint32_t mask) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int s = insert_slot(keys, mask, key_of(p[3 * (size_t)i], p[3 * (size_t)i + 1], p[3 * (size_t)i + 2], v));
-  if (s >= 0) atomicMin(&first[s], i);
+  const uint32_t ii = min(i, n - 1);  // lanes past the end repeat the last point (the same key)
+  const uint64_t k = key_of(p[3 * (size_t)ii], p[3 * (size_t)ii + 1], p[3 * (size_t)ii + 2], v);
+  const uint32_t klo = (uint32_t)k, khi = (uint32_t)(k >> 32);
+  const uint32_t plo = __shfl_up(klo, 1, 64), phi = __shfl_up(khi, 1, 64);
+  const bool run_start = (threadIdx.x & 63) == 0 || plo != klo || phi != khi;
+  if (i >= n || !run_start) return;
+  const int s = insert_slot(keys, mask, k);
+  // first[s] only decreases, so a value read at or below i already wins
+  if (s >= 0 && __hip_atomic_load(&first[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > i) atomicMin(&first[s], i);
 }
 
 __global__ void ds_flag_kernel(const float* __restrict__ p, uint32_t n, float v, const uint64_t* __restrict__ keys,
