@@ -274,7 +274,13 @@ __global__ void __launch_bounds__(kSortBlock) radix_offsets_kernel(const uint32_
   if (threadIdx.x == 0) row_total[d] = carry;
 }
 
-template <class K>
+// With few workgroups (at most kFusedOffsetsMax), the scatter forms its
+// digit offsets itself from the raw histogram (hist_scan then holds it and
+// row_total is unused): thread d adds row d over the tiles that hold keys,
+// which saves the offsets kernel's launch on small inputs.
+constexpr uint32_t kFusedOffsetsMax = 64;
+
+template <class K, bool FUSED>
 __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __restrict__ keys_in,
                                                                    const uint32_t* __restrict__ vals_in,
                                                                    K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
@@ -297,8 +303,27 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
   if (blockIdx.x * kSortTile >= n) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // this thread's digit: its total and this tile's row offset (read early)
-  const uint32_t my_total = row_total[threadIdx.x];
-  const uint32_t my_row_off = hist_scan[(size_t)threadIdx.x * gridDim.x + blockIdx.x];
+  uint32_t my_total, my_row_off;
+  if constexpr (FUSED) {
+    const uint32_t used = min(gridDim.x, (n + kSortTile - 1) / kSortTile);
+    const uint32_t* row = hist_scan + (size_t)threadIdx.x * gridDim.x;
+    my_total = 0u;
+    my_row_off = 0u;
+    for (uint32_t b0 = 0; b0 < used; b0 += 16) {
+      uint32_t c[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) c[u] = row[min(b0 + u, used - 1)];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const uint32_t b = b0 + u;
+        my_total += b < used ? c[u] : 0u;
+        my_row_off += b < blockIdx.x ? c[u] : 0u;
+      }
+    }
+  } else {
+    my_total = row_total[threadIdx.x];
+    my_row_off = hist_scan[(size_t)threadIdx.x * gridDim.x + blockIdx.x];
+  }
   for (int d = threadIdx.x; d < kWaves * kRadix; d += kSortBlock) (&wcnt[0][0])[d] = 0;
   __syncthreads();
 
@@ -453,14 +478,21 @@ hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, 
                        hist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(radix_offsets_kernel, dim3(kRadix), dim3(kSortBlock), 0, s, hist, blocks, n_ptr, capacity,
-                       hist_scan, row_total);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(radix_scatter_kernel<K>, dim3(blocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout, n_ptr,
-                       capacity, shift, mask, hist_scan, row_total, last ? gather_src : nullptr,
-                       last ? gather_dst : nullptr, last ? rect_src : nullptr, last ? rect_dst : nullptr,
-                       last ? count_dst : nullptr);
+    if (blocks <= kFusedOffsetsMax) {
+      hipLaunchKernelGGL((radix_scatter_kernel<K, true>), dim3(blocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout,
+                         n_ptr, capacity, shift, mask, hist, row_total, last ? gather_src : nullptr,
+                         last ? gather_dst : nullptr, last ? rect_src : nullptr, last ? rect_dst : nullptr,
+                         last ? count_dst : nullptr);
+    } else {
+      hipLaunchKernelGGL(radix_offsets_kernel, dim3(kRadix), dim3(kSortBlock), 0, s, hist, blocks, n_ptr, capacity,
+                         hist_scan, row_total);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((radix_scatter_kernel<K, false>), dim3(blocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout,
+                         n_ptr, capacity, shift, mask, hist_scan, row_total, last ? gather_src : nullptr,
+                         last ? gather_dst : nullptr, last ? rect_src : nullptr, last ? rect_dst : nullptr,
+                         last ? count_dst : nullptr);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     K* tk = kin; kin = kout; kout = tk;
