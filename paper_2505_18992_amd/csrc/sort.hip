@@ -25,8 +25,12 @@ namespace {
 
 constexpr int kSortBlock = 256;
 constexpr int kWaves = kSortBlock / 64;
-constexpr int kRounds = 16;                              // 64-key rounds per wave
-constexpr uint32_t kSortTile = kSortBlock * kRounds;     // 4096 keys per workgroup
+// A workgroup sorts kSortBlock * R keys, R 64-key rounds per wavefront: 16
+// (4096 keys) for large sorts, 4 (1024 keys) for sorts of at most
+// kSmallSortKeys, which then spread over four times the workgroups.
+constexpr int kRoundsLarge = 16, kRoundsSmall = 4;
+constexpr uint32_t kSmallSortKeys = 1u << 20;
+inline int sort_rounds(uint32_t capacity) { return capacity <= kSmallSortKeys ? kRoundsSmall : kRoundsLarge; }
 constexpr int kRadix = 256;
 static_assert(kRadix == kSortBlock, "one digit per thread in the histogram and offset kernels");
 
@@ -180,28 +184,29 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-template <class K>
+template <class K, int R>
 __global__ void __launch_bounds__(kSortBlock) radix_hist_kernel(const K* __restrict__ keys, const uint32_t* __restrict__ n_ptr,
                                                                 uint32_t capacity, int shift, uint32_t mask,
                                                                 uint32_t* __restrict__ hist) {
+  constexpr uint32_t kTile = kSortBlock * R;
   __shared__ uint32_t cnt[kRadix];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t n = clamped(n_ptr, capacity);
-  if (blockIdx.x * kSortTile >= n) return;  // a tile past the end (its row entries are not read)
+  if (blockIdx.x * kTile >= n) return;  // a tile past the end (its row entries are not read)
   cnt[threadIdx.x] = 0u;
-  const uint32_t base = blockIdx.x * kSortTile + wave * (kSortTile / kWaves);
+  const uint32_t base = blockIdx.x * kTile + wave * (kTile / kWaves);
   // every round's digit is loaded before any is counted, so the loads are in
   // flight together; positions past the end read the last key and are not
   // counted
-  uint32_t dig[kRounds];
+  uint32_t dig[R];
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) dig[r] = (uint32_t)(keys[min(base + r * 64 + lane, n - 1)] >> shift) & mask;
+  for (int r = 0; r < R; ++r) dig[r] = (uint32_t)(keys[min(base + r * 64 + lane, n - 1)] >> shift) & mask;
   __syncthreads();
   // LDS atomic increments (integer counts: the order does not matter); a
   // round whose keys share one digit (the high byte of nearby depths) adds
   // its count once instead of serialising 64 increments of one address
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
+  for (int r = 0; r < R; ++r) {
     const bool ok = base + r * 64 + lane < n;
     const uint32_t d0 = __builtin_amdgcn_readfirstlane(dig[r]);
     const uint64_t act = __ballot(ok);
@@ -244,13 +249,13 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* wsu
 // The row is read in coalesced chunks of 256, eight chunks in flight.
 constexpr int kScanChunks = 8;
 __global__ void __launch_bounds__(kSortBlock) radix_offsets_kernel(const uint32_t* __restrict__ hist, uint32_t blocks,
-                                                                   const uint32_t* __restrict__ n_ptr,
+                                                                   uint32_t tile, const uint32_t* __restrict__ n_ptr,
                                                                    uint32_t capacity,
                                                                    uint32_t* __restrict__ hist_scan,
                                                                    uint32_t* __restrict__ row_total) {
   __shared__ uint32_t wsum[kWaves];
   const uint32_t d = blockIdx.x;
-  const uint32_t used = min(blocks, (clamped(n_ptr, capacity) + kSortTile - 1) / kSortTile);
+  const uint32_t used = min(blocks, (clamped(n_ptr, capacity) + tile - 1) / tile);
   const uint32_t* row = hist + (size_t)d * blocks;
   uint32_t* out = hist_scan + (size_t)d * blocks;
   uint32_t carry = 0;
@@ -280,7 +285,7 @@ __global__ void __launch_bounds__(kSortBlock) radix_offsets_kernel(const uint32_
 // which saves the offsets kernel's launch on small inputs.
 constexpr uint32_t kFusedOffsetsMax = 64;
 
-template <class K, bool FUSED>
+template <class K, int R, bool FUSED>
 __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __restrict__ keys_in,
                                                                    const uint32_t* __restrict__ vals_in,
                                                                    K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
@@ -293,19 +298,20 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
                                                                    const uint2* __restrict__ rect_src,
                                                                    uint2* __restrict__ rect_dst,
                                                                    uint32_t* __restrict__ count_dst) {
+  constexpr uint32_t kTile = kSortBlock * R;
   __shared__ uint32_t wcnt[kWaves][kRadix];   // per-wave digit counts, then per-wave prefixes
   __shared__ uint32_t dstart[kRadix];         // block-local first position of each digit
   __shared__ uint32_t gbase[kRadix];          // global first position of each digit for this block
   __shared__ uint32_t wsum[kWaves];
-  __shared__ K skeys[kSortTile];
-  __shared__ uint32_t svals[kSortTile];
+  __shared__ K skeys[kTile];
+  __shared__ uint32_t svals[kTile];
   const uint32_t n = clamped(n_ptr, capacity);
-  if (blockIdx.x * kSortTile >= n) return;
+  if (blockIdx.x * kTile >= n) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // this thread's digit: its total and this tile's row offset (read early)
   uint32_t my_total, my_row_off;
   if constexpr (FUSED) {
-    const uint32_t used = min(gridDim.x, (n + kSortTile - 1) / kSortTile);
+    const uint32_t used = min(gridDim.x, (n + kTile - 1) / kTile);
     const uint32_t* row = hist_scan + (size_t)threadIdx.x * gridDim.x;
     my_total = 0u;
     my_row_off = 0u;
@@ -327,20 +333,20 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
   for (int d = threadIdx.x; d < kWaves * kRadix; d += kSortBlock) (&wcnt[0][0])[d] = 0;
   __syncthreads();
 
-  const uint32_t base = blockIdx.x * kSortTile + wave * (kSortTile / kWaves);
-  K k[kRounds];
-  uint32_t v[kRounds];
-  uint32_t loc[kRounds];
+  const uint32_t base = blockIdx.x * kTile + wave * (kTile / kWaves);
+  K k[R];
+  uint32_t v[R];
+  uint32_t loc[R];
   // all rounds are loaded before any is ranked (positions past the end read
   // the last pair and take no part in the ranking)
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
+  for (int r = 0; r < R; ++r) {
     const uint32_t ci = min(base + r * 64 + lane, n - 1);
     k[r] = keys_in[ci];
     v[r] = vals_in[ci];
   }
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
+  for (int r = 0; r < R; ++r) {
     const uint32_t idx = base + r * 64 + lane;
     const bool ok = idx < n;
     const uint32_t d = (uint32_t)(k[r] >> shift) & mask;
@@ -379,7 +385,7 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
+  for (int r = 0; r < R; ++r) {
     const uint32_t idx = base + r * 64 + lane;
     if (idx < n) {
       const uint32_t d = (uint32_t)(k[r] >> shift) & mask;
@@ -389,12 +395,12 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
     }
   }
   __syncthreads();
-  const uint32_t tile_n = min(kSortTile, n - blockIdx.x * kSortTile);
-  if (tile_n == kSortTile) {
+  const uint32_t tile_n = min(kTile, n - blockIdx.x * kTile);
+  if (tile_n == kTile) {
     // a full tile: straight-line code, so the gathers are in flight together
-    uint32_t gpos[kRounds], gval[kRounds];
+    uint32_t gpos[R], gval[R];
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
+    for (int r = 0; r < R; ++r) {
       const uint32_t p = r * kSortBlock + threadIdx.x;
       const K key = skeys[p];
       const uint32_t d = (uint32_t)(key >> shift) & mask;
@@ -406,18 +412,18 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
       gval[r] = val;
     }
     if (gather_dst != nullptr) {
-      uint32_t gv[kRounds];
+      uint32_t gv[R];
 #pragma unroll
-      for (int r = 0; r < kRounds; ++r) gv[r] = gather_src[gval[r]];
+      for (int r = 0; r < R; ++r) gv[r] = gather_src[gval[r]];
 #pragma unroll
-      for (int r = 0; r < kRounds; ++r) gather_dst[gpos[r]] = gv[r];
+      for (int r = 0; r < R; ++r) gather_dst[gpos[r]] = gv[r];
     }
     if (rect_dst != nullptr) {
-      uint2 rv[kRounds];
+      uint2 rv[R];
 #pragma unroll
-      for (int r = 0; r < kRounds; ++r) rv[r] = rect_src[gval[r]];
+      for (int r = 0; r < R; ++r) rv[r] = rect_src[gval[r]];
 #pragma unroll
-      for (int r = 0; r < kRounds; ++r) {
+      for (int r = 0; r < R; ++r) {
         rect_dst[gpos[r]] = rv[r];
         count_dst[gpos[r]] = rect_count(rv[r]);
       }
@@ -443,7 +449,7 @@ __global__ void __launch_bounds__(kSortBlock) radix_scatter_kernel(const K* __re
 inline uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
 size_t radix_ws_bytes(uint32_t capacity) {
-  const uint32_t blocks = div_up(capacity > 0 ? capacity : 1, kSortTile);
+  const uint32_t blocks = div_up(capacity > 0 ? capacity : 1, kSortBlock * sort_rounds(capacity));
   const size_t h = ((size_t)blocks * kRadix * sizeof(uint32_t) + 255) / 256 * 256;
   return 2 * h + kRadix * sizeof(uint32_t);
 }
@@ -452,6 +458,33 @@ size_t radix_ws_bytes(uint32_t capacity) {
 // gather_dst[i] = gather_src[value i] for every sorted position i.
 // rect_src/rect_dst/count_dst (may be NULL): the last pass also writes
 // rect_dst[i] = rect_src[value i] and count_dst[i] = its number of tiles.
+// One radix pass with R rounds per wavefront: histogram, digit offsets
+// (fused into the scatter when the workgroups are few) and scatter.
+template <class K, int R>
+hipError_t radix_pass(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, uint32_t blocks, uint32_t capacity,
+                      int shift, uint32_t mask, const uint32_t* n_ptr, uint32_t* hist, uint32_t* hist_scan,
+                      uint32_t* row_total, hipStream_t s, const uint32_t* gather_src, uint32_t* gather_dst,
+                      const uint2* rect_src, uint2* rect_dst, uint32_t* count_dst) {
+  hipLaunchKernelGGL((radix_hist_kernel<K, R>), dim3(blocks), dim3(kSortBlock), 0, s, kin, n_ptr, capacity, shift, mask,
+                     hist);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (blocks <= kFusedOffsetsMax) {
+    hipLaunchKernelGGL((radix_scatter_kernel<K, R, true>), dim3(blocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout,
+                       n_ptr, capacity, shift, mask, hist, row_total, gather_src, gather_dst, rect_src, rect_dst,
+                       count_dst);
+  } else {
+    hipLaunchKernelGGL(radix_offsets_kernel, dim3(kRadix), dim3(kSortBlock), 0, s, hist, blocks,
+                       (uint32_t)(kSortBlock * R), n_ptr, capacity, hist_scan, row_total);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((radix_scatter_kernel<K, R, false>), dim3(blocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout,
+                       n_ptr, capacity, shift, mask, hist_scan, row_total, gather_src, gather_dst, rect_src, rect_dst,
+                       count_dst);
+  }
+  return hipGetLastError();
+}
+
 template <class K>
 hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, uint32_t capacity, int key_bits,
                       const uint32_t* n_ptr, void* ws, int* result_in_alt, hipStream_t s,
@@ -459,7 +492,8 @@ hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, 
                       const uint2* rect_src = nullptr, uint2* rect_dst = nullptr, uint32_t* count_dst = nullptr) {
   *result_in_alt = 0;
   if (capacity == 0) return hipSuccess;
-  const uint32_t blocks = div_up(capacity, kSortTile);
+  const int rounds = sort_rounds(capacity);
+  const uint32_t blocks = div_up(capacity, kSortBlock * rounds);
   const size_t hist_bytes = ((size_t)blocks * kRadix * sizeof(uint32_t) + 255) / 256 * 256;
   uint32_t* hist = static_cast<uint32_t*>(ws);
   uint32_t* hist_scan = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + hist_bytes);
@@ -474,26 +508,11 @@ hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, 
     const int bits = key_bits / passes + (pass >= passes - key_bits % passes ? 1 : 0);
     const uint32_t mask = (1u << bits) - 1u;
     const bool last = pass == passes - 1;
-    hipLaunchKernelGGL(radix_hist_kernel<K>, dim3(blocks), dim3(kSortBlock), 0, s, kin, n_ptr, capacity, shift, mask,
-                       hist);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (blocks <= kFusedOffsetsMax) {
-      hipLaunchKernelGGL((radix_scatter_kernel<K, true>), dim3(blocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout,
-                         n_ptr, capacity, shift, mask, hist, row_total, last ? gather_src : nullptr,
-                         last ? gather_dst : nullptr, last ? rect_src : nullptr, last ? rect_dst : nullptr,
-                         last ? count_dst : nullptr);
-    } else {
-      hipLaunchKernelGGL(radix_offsets_kernel, dim3(kRadix), dim3(kSortBlock), 0, s, hist, blocks, n_ptr, capacity,
-                         hist_scan, row_total);
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((radix_scatter_kernel<K, false>), dim3(blocks), dim3(kSortBlock), 0, s, kin, vin, kout, vout,
-                         n_ptr, capacity, shift, mask, hist_scan, row_total, last ? gather_src : nullptr,
-                         last ? gather_dst : nullptr, last ? rect_src : nullptr, last ? rect_dst : nullptr,
-                         last ? count_dst : nullptr);
-    }
-    e = hipGetLastError();
+    const hipError_t e =
+        (rounds == kRoundsSmall ? radix_pass<K, kRoundsSmall> : radix_pass<K, kRoundsLarge>)(
+            kin, vin, kout, vout, blocks, capacity, shift, mask, n_ptr, hist, hist_scan, row_total, s,
+            last ? gather_src : nullptr, last ? gather_dst : nullptr, last ? rect_src : nullptr,
+            last ? rect_dst : nullptr, last ? count_dst : nullptr);
     if (e != hipSuccess) return e;
     K* tk = kin; kin = kout; kout = tk;
     uint32_t* tv = vin; vin = vout; vout = tv;
