@@ -284,7 +284,8 @@ __device__ __forceinline__ void forward_tile(const CallTables* __restrict__ tab,
         const float Az = at_offset(sh.A, o).z;
         if (COUNT) ne += (g + u < nhit && !done) ? 1u : 0u;
         const bool ok = !done && f.alpha >= kAlphaMin;
-        const float Tn = T * (1.0f - f.alpha);
+        // T (1 - alpha) as T - alpha T in one fused operation (rounded once)
+        const float Tn = fmaf(-f.alpha, T, T);
         const bool low = Tn < kTransMin;
         const bool blend = ok && !low;
         if (blend) {
