@@ -91,10 +91,10 @@ __device__ __forceinline__ int find_slot(const uint64_t* __restrict__ keys, uint
 }
 
 // Slot of key k, inserting it if absent (-1 if the table is full).  A slot's
-// key never changes once set, so a plain read that finds a key is final; only
-// a slot read as empty (possibly a stale read) is claimed by compare-and-swap.
-// Points of one voxel mostly find their key already there and do not queue on
-// its slot's atomics.
+// key never changes once set, so a (relaxed atomic) read that finds a key is
+// final; only a slot read as empty (possibly a stale read) is claimed by
+// compare-and-swap.  Points of one voxel mostly find their key already there
+// and do not queue on its slot's atomics.
 __device__ __forceinline__ int insert_slot(uint64_t* __restrict__ keys, uint32_t mask, uint64_t k) {
   uint32_t s = hash_slot(k, mask);
   for (uint32_t step = 0; step <= mask; ++step) {
