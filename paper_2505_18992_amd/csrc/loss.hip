@@ -183,36 +183,36 @@ __device__ __forceinline__ uint3 xcd_block() {
 // (only B1 >= C1 and B2 >= C2 are divided by; A2 may vanish).
 //
 // Horizontal filter of the staged rows [0, n) of x and y into hs rows
-// [dst, dst + n): the five statistics x, y, x^2, y^2, xy.
+// [dst, dst + n): the four statistics x, y, x^2 + y^2, xy.  Only the sum of
+// the second moments enters SSIM (through sigma_x^2 + sigma_y^2), so the two
+// are filtered as one map.
+constexpr int kStats = 4;
 __device__ __forceinline__ void stats_rows(const float (*sxy)[kBand][kSWH], int n, int dst,
                                            float (*hs)[kRows][kSW]) {
   const int r = threadIdx.x / (kSW / kHRun), j0 = (threadIdx.x % (kSW / kHRun)) * kHRun;
   if (r >= n) return;
   // the run's samples and their products, each formed once (not once per tap)
-  float xv[kHRun + 2 * kRad], yv[kHRun + 2 * kRad], xx[kHRun + 2 * kRad], yy[kHRun + 2 * kRad],
-      xy[kHRun + 2 * kRad];
+  float xv[kHRun + 2 * kRad], yv[kHRun + 2 * kRad], ss[kHRun + 2 * kRad], xy[kHRun + 2 * kRad];
 #pragma unroll
   for (int t = 0; t < kHRun + 2 * kRad; ++t) {
     xv[t] = sxy[0][r][j0 + t];
     yv[t] = sxy[1][r][j0 + t];
-    xx[t] = xv[t] * xv[t];
-    yy[t] = yv[t] * yv[t];
+    ss[t] = xv[t] * xv[t] + yv[t] * yv[t];
     xy[t] = xv[t] * yv[t];
   }
 #pragma unroll
   for (int o = 0; o < kHRun; ++o) {
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
 #pragma unroll
     for (int t = 0; t < kTaps; ++t) {
       const float g = kGauss[t];
       s0 = fmaf(g, xv[o + t], s0);
       s1 = fmaf(g, yv[o + t], s1);
-      s2 = fmaf(g, xx[o + t], s2);
-      s3 = fmaf(g, yy[o + t], s3);
-      s4 = fmaf(g, xy[o + t], s4);
+      s2 = fmaf(g, ss[o + t], s2);
+      s3 = fmaf(g, xy[o + t], s3);
     }
     hs[0][dst + r][j0 + o] = s0; hs[1][dst + r][j0 + o] = s1; hs[2][dst + r][j0 + o] = s2;
-    hs[3][dst + r][j0 + o] = s3; hs[4][dst + r][j0 + o] = s4;
+    hs[3][dst + r][j0 + o] = s3;
   }
 }
 
@@ -220,7 +220,7 @@ __device__ __forceinline__ void stats_rows(const float (*sxy)[kBand][kSWH], int 
 // in registers would otherwise cost a wavefront per SIMD.
 __global__ void __launch_bounds__(kLossBlock) __attribute__((amdgpu_waves_per_eu(4))) ssim_stats_kernel(LossBatch batch) {
   __shared__ float sxy[2][kBand][kSWH];  // staged x, y rows
-  __shared__ float hs[5][kRows][kSW];    // horizontal sums of x, y, x^2, y^2, xy
+  __shared__ float hs[kStats][kRows][kSW];  // horizontal sums of x, y, x^2 + y^2, xy
   __shared__ float red[kLossBlock / 64];
   const uint3 blk = xcd_block();
   const ViewArgs& a = batch.v[blk.z / 3];
@@ -275,9 +275,9 @@ __global__ void __launch_bounds__(kLossBlock) __attribute__((amdgpu_waves_per_eu
     __syncthreads();
     // the next band's input rows, in flight through this band's vertical filter
     if (yb + kBand < seg_end) nxt.load(planes, a.W, a.H, x0, yb + kBand + kRad, kBand);
-    float vm[5][kVRun];
+    float vm[kStats][kVRun];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
+    for (int q = 0; q < kStats; ++q) {
       float col[kVRun + 2 * kRad];
 #pragma unroll
       for (int t = 0; t < kVRun + 2 * kRad; ++t) col[t] = hs[q][vi0 + t][vj];
@@ -293,9 +293,10 @@ __global__ void __launch_bounds__(kLossBlock) __attribute__((amdgpu_waves_per_eu
     for (int o = 0; o < kVRun; ++o) {
       const int px = x0 + vj, py = yb + vi0 + o;
       if (px >= a.W || py >= seg_end) continue;
-      const float m1 = vm[0][o], m2 = vm[1][o], e11 = vm[2][o], e22 = vm[3][o], e12 = vm[4][o];
+      const float m1 = vm[0][o], m2 = vm[1][o], es = vm[2][o], e12 = vm[3][o];  // es = E[x^2] + E[y^2]
       const float A1 = 2.f * m1 * m2 + kC1, A2 = 2.f * (e12 - m1 * m2) + kC2;
-      const float B1 = m1 * m1 + m2 * m2 + kC1, B2 = (e11 - m1 * m1) + (e22 - m2 * m2) + kC2;
+      const float mm = m1 * m1 + m2 * m2;
+      const float B1 = mm + kC1, B2 = (es - mm) + kC2;
       const float rB1 = 1.0f / B1, rB2 = 1.0f / B2;
       const float rr = rB1 * rB2;
       const float S = A1 * A2 * rr;
@@ -306,7 +307,7 @@ __global__ void __launch_bounds__(kLossBlock) __attribute__((amdgpu_waves_per_eu
       ssum += S;
     }
     __syncthreads();
-    keep_halo_rows<5>(hs);
+    keep_halo_rows<kStats>(hs);
   }
   const int slot = (int)((blk.y * a.tiles_x + blk.x) % kSumSlots);
   ssum = block_sum(ssum, red);
