@@ -132,6 +132,31 @@ def test_correspondence_ties_bit_exact():
         gm.close()
 
 
+@pytest.mark.parametrize("n", [1000, 1025, 65536, 65537, 1048577])
+def test_map_sizes_across_sort_paths(n):
+    # the map build sorts n voxel keys: sizes on both sides of the sort's
+    # switches (one workgroup, 64 workgroups with the digit offsets formed in
+    # the scatter, more with the offsets kernel, and above 1 M keys the
+    # larger workgroups); a dense cluster makes long runs of one key and
+    # capped voxels
+    from paper_2505_18992_amd import VoxelMap, icp_correspond
+    print(f"case map size {n}", flush=True)
+    rng = np.random.default_rng(n)
+    k = n // 4
+    pts = np.concatenate([rng.uniform(-30, 30, (n - k, 3)), rng.normal(0, 0.6, (k, 3))]).astype(np.float32)
+    rng.shuffle(pts)
+    vm = icp.VoxelMap(pts, VOXEL, CAP)
+    gm = VoxelMap(_dev(pts), VOXEL, CAP)
+    assert gm.info() == (n, len(vm.cells))
+    q = rng.uniform(-31, 31, (3000, 3)).astype(np.float32)
+    q[:1000] = rng.normal(0, 0.8, (1000, 3))
+    nn, d2 = icp_correspond(gm, _dev(q), np.eye(3, 4), TAU)
+    enn, ed2 = icp.correspond(vm, icp.transform32(q, np.eye(3, 4)), TAU)
+    assert np.array_equal(nn.cpu().numpy(), enn)
+    assert np.array_equal(d2.cpu().numpy().view(np.uint32), ed2.view(np.uint32))
+    gm.close()
+
+
 def test_cap_and_empty_map():
     from paper_2505_18992_amd import VoxelMap, icp_correspond
     m = np.array([[0.1, 0.1, 0.1], [0.5, 0.5, 0.5], [0.9, 0.2, 0.3]], np.float32)
